@@ -1,0 +1,127 @@
+"""Quantum Fisher matrix, force vector and the regularised TDVP / SR solve.
+
+Paper:
+  * eq:qfm            S_kk' = <O_k^* O_k'>^c  (connected: <AB> - <A><B>)
+  * eq:force_vector   F_k   = <E_loc O_k^*>^c
+  * eq:energy_gradient  dE/dtheta_k = 2 Re F_k  (SR step eq:stochastic_reconfiguration)
+  * eq:tdvp_util      [[S]] theta_dot = -[[gamma F]],  gamma in {1, i},
+                      [[.]] = identity (holomorphic nets), Re or Im
+  * Sec. 3.1 "Diagonal shift": S~_kk' = (1 + nu delta_kk') S_kk'.
+
+Readings:
+  * expectation values are plain empirical means (1/N_s) over the samples
+    (eq:Oloc_mean), or sum_n w_n (.) with normalised weights w (the exact
+    enumeration path, where w = p(s));
+  * an optional additive shift eps_abs * I is applied after the relative one;
+  * the solve is a textbook Cholesky factorisation S~ = L L^H (Golub & Van
+    Loan, "Matrix Computations", Alg. 4.2.1, column form) followed by forward
+    and back substitution; a non-positive pivot is reported, never repaired;
+  * the factor 2 of the SR gradient is absorbed into the step size: the
+    solve returns x with [[S~]] x = -[[gamma F]].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _weights(n, weights):
+    if weights is None:
+        return np.full(n, 1.0 / n)
+    w = np.asarray(weights, dtype=np.float64)
+    return w / w.sum()
+
+
+def energy_stats(eloc, weights=None):
+    """Mean and variance of E_loc: (<E>, <|E - <E>|^2>)."""
+    e = np.asarray(eloc, dtype=np.complex128)
+    w = _weights(len(e), weights)
+    mean = np.sum(w * e)
+    var = np.sum(w * np.abs(e - mean) ** 2)
+    return mean, var
+
+
+def fisher_and_force(O, eloc, weights=None):
+    """S (K x K) and F (K) from per-sample log-derivatives O (N_s x K)."""
+    O = np.asarray(O, dtype=np.complex128)
+    e = np.asarray(eloc, dtype=np.complex128)
+    w = _weights(O.shape[0], weights)
+    mean_O = w @ O                                   # <O_k>
+    mean_E = np.sum(w * e)                           # <E_loc>
+    S = (O.conj().T * w[None, :]) @ O - np.outer(mean_O.conj(), mean_O)
+    F = (O.conj().T * w[None, :]) @ e - mean_O.conj() * mean_E
+    return S, F
+
+
+def project(A, mode):
+    if mode == "complex":
+        return A
+    if mode == "real":
+        return A.real.astype(np.complex128)
+    if mode == "imag":
+        return A.imag.astype(np.complex128)
+    raise ValueError(mode)
+
+
+def shifted(S, nu_rel, eps_abs=0.0):
+    """S~ = S + nu_rel * diag(S) + eps_abs * I (the paper's (1 + nu delta) S)."""
+    St = np.array(S, dtype=np.complex128, copy=True)
+    d = np.arange(St.shape[0])
+    St[d, d] = St[d, d] * (1.0 + nu_rel) + eps_abs
+    return St
+
+
+def cholesky(A):
+    """Lower-triangular L with A = L L^H, column by column.
+
+    Returns (L, fail_index, min_pivot); fail_index is -1 on success, else the
+    first column whose pivot A_jj - sum_k |L_jk|^2 is not positive (and L is
+    then only valid in its first fail_index columns)."""
+    A = np.asarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    L = np.zeros_like(A)
+    min_pivot = np.inf
+    for j in range(n):
+        d = A[j, j].real - np.sum(np.abs(L[j, :j]) ** 2)
+        min_pivot = min(min_pivot, d)
+        if not d > 0.0:
+            return L, j, min_pivot
+        L[j, j] = np.sqrt(d)
+        L[j + 1:, j] = (A[j + 1:, j] - L[j + 1:, :j] @ L[j, :j].conj()) / L[j, j]
+    return L, -1, min_pivot
+
+
+def forward_sub(L, b):
+    """Solve L y = b for lower-triangular L."""
+    n = L.shape[0]
+    y = np.zeros(n, dtype=np.complex128)
+    for i in range(n):
+        y[i] = (b[i] - L[i, :i] @ y[:i]) / L[i, i]
+    return y
+
+
+def back_sub_h(L, y):
+    """Solve L^H x = y for lower-triangular L."""
+    n = L.shape[0]
+    x = np.zeros(n, dtype=np.complex128)
+    for i in range(n - 1, -1, -1):
+        x[i] = (y[i] - L[i + 1:, i].conj() @ x[i + 1:]) / L[i, i].conj()
+    return x
+
+
+def sr_solve(O, eloc, *, nu_rel=1e-3, eps_abs=0.0, mode="complex", gamma=1.0,
+             weights=None):
+    """One regularised SR / TDVP solve, following the steps of Algorithm 1
+    after the local energies: S and F, shift, factorisation, two triangular
+    solves.  Returns (x, info) with [[S~]] x = -[[gamma F]]."""
+    S, F = fisher_and_force(O, eloc, weights)
+    mean, var = energy_stats(eloc, weights)
+    Sm = project(S, mode)
+    rhs = -project(gamma * F, mode)
+    St = shifted(Sm, nu_rel, eps_abs)
+    L, fail, min_piv = cholesky(St)
+    info = dict(e_mean=mean, e_var=var, fail_index=fail, min_pivot=min_piv)
+    if fail >= 0:
+        return None, info
+    x = back_sub_h(L, forward_sub(L, rhs))
+    info["residual"] = np.linalg.norm(St @ x - rhs) / max(np.linalg.norm(rhs), 1e-300)
+    return x, info

@@ -1,0 +1,136 @@
+"""Pins of oracle.sr and oracle.ess: exact-energy gradient identity, the
+Fubini-Study (fidelity) form of the Fisher diagonal, LAPACK solves and
+factorisations, limits of the diagonal shift, and the AR(1) autocorrelation."""
+import numpy as np
+import pytest
+
+from oracle import sr, rbm, eloc, ess
+import synth_inputs as si
+
+
+def _exact_energy(p, n, nh, kind="tfim", h=1.0):
+    f = lambda x: rbm.log_psi(p, x, nh)
+    E, prob, el, states = eloc.exact_expectation(f, kind, n, n, 1, True, 1.0, h)
+    return E.real, prob, el, states
+
+
+def test_force_is_half_the_exact_energy_gradient():
+    # eq:energy_gradient: dE/dRe theta_k = 2 Re F_k; holomorphy adds dE/dIm theta_k = 2 Im F_k
+    n, nh = 6, 3
+    p = si.rbm_params(n, nh, std=0.3, seed=21)
+    E, prob, el, states = _exact_energy(p, n, nh)
+    O = rbm.grad_log_psi(p, states, nh)
+    S, F = sr.fisher_and_force(O, el, prob)
+    eps = 1e-6
+    for k in range(len(p)):
+        d = np.zeros_like(p)
+        d[k] = eps
+        gr = (_exact_energy(p + d, n, nh)[0] - _exact_energy(p - d, n, nh)[0]) / (2 * eps)
+        gi = (_exact_energy(p + 1j * d, n, nh)[0] - _exact_energy(p - 1j * d, n, nh)[0]) / (2 * eps)
+        assert abs(gr - 2 * F[k].real) < 1e-7
+        assert abs(gi - 2 * F[k].imag) < 1e-7
+
+
+def test_fisher_diagonal_is_fidelity_curvature():
+    # S is the Fubini-Study metric: 1 - |<psi|psi_eps>|^2/(|psi|^2 |psi_eps|^2) = eps^2 S_kk + O(eps^4)
+    n, nh = 6, 4
+    p = si.rbm_params(n, nh, std=0.4, seed=22)
+    states = eloc.all_states(n)
+    E, prob, el, _ = _exact_energy(p, n, nh)
+    O = rbm.grad_log_psi(p, states, nh)
+    S, _ = sr.fisher_and_force(O, el, prob)
+    eps = 1e-4
+    v0 = np.exp(rbm.log_psi(p, states, nh))
+    def one_minus_fid(v1):
+        # |a|^2 |b|^2 - |<a,b>|^2 = 1/2 sum_ij |a_i b_j - a_j b_i|^2 (Lagrange; no cancellation)
+        cross = v0[:, None] * v1[None, :] - v0[None, :] * v1[:, None]
+        return 0.5 * np.sum(np.abs(cross) ** 2) / (np.vdot(v0, v0).real * np.vdot(v1, v1).real)
+
+    for k in range(0, len(p), 3):
+        d = np.zeros_like(p)
+        d[k] = eps
+        # the eps^3 term is odd in eps: average +eps and -eps
+        curv = (one_minus_fid(np.exp(rbm.log_psi(p + d, states, nh)))
+                + one_minus_fid(np.exp(rbm.log_psi(p - d, states, nh)))) / (2 * eps ** 2)
+        assert abs(curv - S[k, k].real) < 1e-6 * max(1.0, S[k, k].real)
+
+
+def test_S_hermitian_psd_and_rank():
+    n, nh, ns = 8, 8, 40
+    p = si.rbm_params(n, nh, std=0.3, seed=23)
+    bits = si.random_bits(ns, n, seed=1)
+    O = rbm.grad_log_psi(p, bits, nh)
+    el = np.random.default_rng(0).normal(size=ns) + 0j
+    S, F = sr.fisher_and_force(O, el)
+    assert np.allclose(S, S.conj().T, atol=1e-15)
+    lam = np.linalg.eigvalsh(S)
+    assert lam.min() >= -1e-12 * np.abs(lam).max()
+    assert np.linalg.matrix_rank(S, tol=1e-10 * lam.max()) <= ns - 1
+    # the connected correlator equals the covariance of explicitly centred data
+    Oc = O - O.mean(0)
+    assert np.allclose(S, Oc.conj().T @ Oc / ns, atol=1e-14)
+
+
+def test_cholesky_and_solve_match_lapack():
+    rng = np.random.default_rng(4)
+    A = rng.normal(size=(30, 30)) + 1j * rng.normal(size=(30, 30))
+    A = A @ A.conj().T + 30 * np.eye(30)
+    L, fail, piv = sr.cholesky(A)
+    assert fail == -1
+    assert np.allclose(L, np.linalg.cholesky(A), atol=1e-12)
+    b = rng.normal(size=30) + 1j * rng.normal(size=30)
+    x = sr.back_sub_h(L, sr.forward_sub(L, b))
+    assert np.allclose(x, np.linalg.solve(A, b), atol=1e-12)
+
+
+@pytest.mark.parametrize("mode,gamma", [("complex", 1.0), ("complex", 1j), ("real", 1.0)])
+def test_sr_solve_vs_lapack(mode, gamma):
+    n, nh, ns = 6, 6, 200
+    p = si.rbm_params(n, nh, std=0.3, seed=24)
+    bits = si.random_bits(ns, n, seed=2)
+    O = rbm.grad_log_psi(p, bits, nh)
+    el = eloc.local_energy(lambda x: rbm.log_psi(p, x, nh), "tfim", bits, n, 1, True, 1.0, 1.0)
+    x, info = sr.sr_solve(O, el, nu_rel=1e-2, mode=mode, gamma=gamma)
+    S, F = sr.fisher_and_force(O, el)
+    S = sr.project(S, mode)
+    rhs = -sr.project(gamma * F, mode)
+    St = S + 1e-2 * np.diag(np.diag(S))
+    ref = np.linalg.solve(St, rhs)
+    assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref) * max(1.0, np.linalg.cond(St) * 1e-5)
+    assert info["residual"] < 1e-12
+    assert abs(info["e_mean"] - el.mean()) < 1e-12
+
+
+def test_shift_limits_and_not_pd():
+    n, nh, ns = 6, 6, 20
+    p = si.rbm_params(n, nh, std=0.3, seed=25)
+    bits = si.random_bits(ns, n, seed=3)
+    O = rbm.grad_log_psi(p, bits, nh)
+    el = np.random.default_rng(1).normal(size=ns) + 0.1j
+    S, F = sr.fisher_and_force(O, el)
+    # large shift: nu * x -> -F_k / S_kk (diagonal preconditioning)
+    nu = 1e9
+    x, _ = sr.sr_solve(O, el, nu_rel=nu)
+    assert np.allclose(nu * x, -F / np.diag(S).real, rtol=1e-6, atol=1e-9)
+    # nu = 0 with fewer samples than parameters: S is singular -> reported, not repaired
+    x, info = sr.sr_solve(O, el, nu_rel=0.0)
+    assert x is None and info["fail_index"] >= 0
+    # additive shift alone makes it solvable
+    x, info = sr.sr_solve(O, el, nu_rel=0.0, eps_abs=1e-3)
+    assert x is not None and info["residual"] < 1e-10
+
+
+def test_ar1_integrated_autocorrelation_time():
+    rho, T, C = 0.8, 20000, 16
+    rng = np.random.default_rng(5)
+    x = np.zeros((T, C))
+    e = rng.normal(size=(T, C))
+    x[0] = e[0] / np.sqrt(1 - rho ** 2)
+    for t in range(1, T):
+        x[t] = rho * x[t - 1] + e[t]
+    tau, W = ess.tau_int(x)
+    exact = (1 + rho) / (2 * (1 - rho))
+    assert abs(tau - exact) < 0.05 * exact
+    assert abs(ess.batch_means_tau(x) - exact) < 0.15 * exact
+    n_eff, _ = ess.ess(x)
+    assert abs(n_eff - x.size / (2 * exact)) < 0.06 * x.size / (2 * exact)
