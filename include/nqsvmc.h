@@ -1,0 +1,256 @@
+/*
+ * nqsvmc.h - C ABI of libnqsvmc.so: the variational Monte Carlo hot path for
+ * neural quantum states on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Schmitt & Reh, "jVMC: Versatile and performant variational Monte
+ * Carlo leveraging automated differentiation and GPU acceleration" (SciPost
+ * Phys. Codebases).  One stochastic-reconfiguration / TDVP step (the paper's
+ * Algorithm 1) is
+ *     vmc_sample -> vmc_log_psi -> vmc_grad_log_psi -> vmc_local_energy
+ *                -> vmc_sr_solve
+ * and each call below names the passage that defines what it computes.
+ *
+ * Conventions (all calls)
+ *  - Every data pointer is a caller-owned DEVICE pointer unless its name ends
+ *    in _host.  The library never frees caller memory.  Opaque handles are
+ *    created and destroyed by the library.
+ *  - Calls are asynchronous on the context's HIP stream (the one passed to
+ *    vmc_ctx_create, or the null stream).  Outputs are valid after
+ *    vmc_ctx_sync() or an event recorded on that stream.  Calls that return
+ *    results in _host arguments synchronise the stream themselves.
+ *  - Every call returns a status: VMC_OK (0) or a negative VMC_ERR_* code; the
+ *    message of the last failure on a context is vmc_last_error(ctx).  No C++
+ *    exception crosses this boundary.  A handle that failed is left unchanged.
+ *  - Sizes are int64_t.  One context per host thread; calls on one context
+ *    must not overlap.
+ *
+ * Spin configurations (the paper's 0/1 basis of Sec. 4.2): N sites packed in
+ * W = ceil(N/64) little-endian uint64 words per configuration, site i in word
+ * i/64, bit i%64; a set bit is spin up (sigma = 2s - 1 = +1).  Bits >= N in
+ * the last word must be zero.  A batch of B configurations is B*W words,
+ * configuration-major.
+ *
+ * Complex numbers are interleaved (re, im): c128 = 2 doubles, c64 = 2 floats.
+ */
+#ifndef NQSVMC_H
+#define NQSVMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+  VMC_OK = 0,
+  VMC_ERR_INVALID_ARG = -1,  /* bad size, null pointer, inconsistent handles */
+  VMC_ERR_OOM = -2,          /* device allocation failed                      */
+  VMC_ERR_HIP = -3,          /* a HIP runtime call failed                     */
+  VMC_ERR_NOT_PD = -4,       /* shifted S not positive definite (see info)    */
+  VMC_ERR_NONFINITE = -5,    /* NaN/Inf in parameters or results              */
+  VMC_ERR_UNSUPPORTED = -6,  /* valid request this build does not implement   */
+  VMC_ERR_WORKSPACE = -7     /* request exceeds the workspace limit           */
+};
+
+/* compute precision of network evaluations (vmc_model_set_precision) */
+enum vmc_prec { VMC_F64 = 0, VMC_F32 = 1, VMC_BF16 = 2 };
+
+/* element types of parameter / gradient buffers */
+enum vmc_dtype { VMC_DT_F64 = 0, VMC_DT_C128 = 1, VMC_DT_C64 = 2, VMC_DT_F32 = 3 };
+
+/* Metropolis proposals */
+enum { VMC_PROP_FLIP = 0, VMC_PROP_EXCHANGE = 1, VMC_PROP_MADE_MIX = 2 };
+
+/* [[.]] of eq:tdvp_gen / eq:tdvp_util */
+enum { VMC_SR_COMPLEX = 0, VMC_SR_REAL = 1, VMC_SR_IMAG = 2 };
+
+typedef struct vmc_ctx vmc_ctx;
+typedef struct vmc_model vmc_model;
+typedef struct vmc_ham vmc_ham;
+typedef struct vmc_sampler vmc_sampler;
+typedef struct vmc_made vmc_made;
+
+/* ---- context ------------------------------------------------------------ */
+/* Binds a HIP device and stream (hip_stream may be NULL: the null stream).  */
+int vmc_ctx_create(int hip_device, void* hip_stream, vmc_ctx** out);
+int vmc_ctx_destroy(vmc_ctx* ctx);
+int vmc_ctx_sync(vmc_ctx* ctx);
+/* Message of the last failed call on ctx ("" if none).  Valid until the next call. */
+const char* vmc_last_error(vmc_ctx* ctx);
+/* Caps the library-owned device workspace (bytes; 0 = no cap).  Calls that
+ * would need more return VMC_ERR_WORKSPACE. */
+int vmc_ctx_set_workspace_limit(vmc_ctx* ctx, size_t bytes);
+/* Library version string. */
+const char* vmc_version(void);
+
+/* ---- models (the paper's NQS, Sec. 4.2 "Variational wave functions") ---- */
+/* Restricted Boltzmann machine, eq:rbm_ex:
+ *   log psi(s) = sum_i a_i sigma_i + sum_j log cosh(theta_j),
+ *   theta_j = b_j + sum_i W_ji sigma_i.
+ * Flat parameter order: [a (N), b (N_h), W (N_h x N, row-major)], K = N + N_h + N*N_h.
+ * is_complex = 0 keeps all parameters real (imaginary parts forced to 0).  */
+int vmc_model_create_rbm(vmc_ctx* ctx, int n_visible, int n_hidden, int is_complex, vmc_model** out);
+/* Two-layer periodic CNN on an Lx x Ly torus (the paper's convolutional
+ * NQS class, Sec. 4.2 "nets"):
+ *   z1[c,y,x] = b1_c + sum_{dy,dx} W1[c,dy,dx] sigma[(y+dy)%Ly, (x+dx)%Lx]
+ *   z2[c,y,x] = b2_c + sum_{c',dy,dx} W2[c,c',dy,dx] logcosh(z1[c',(y+dy)%Ly,(x+dx)%Lx])
+ *   log psi   = sum_{c,y,x} logcosh(z2[c,y,x])
+ * Flat order: [W1 (C*k*k), b1 (C), W2 (C*C*k*k, [c_out][c_in][dy][dx]), b2 (C)], complex. */
+int vmc_model_create_cnn(vmc_ctx* ctx, int Lx, int Ly, int channels, int kernel, vmc_model** out);
+int vmc_model_num_params(const vmc_model* m, int64_t* K);
+int vmc_model_num_sites(const vmc_model* m, int* N);
+/* Copies K parameters from device memory (dtype C128, C64 or, for real RBMs, F64)
+ * into the model; converted to the model's internal float64 master copy.
+ * Returns VMC_ERR_NONFINITE if any parameter is NaN/Inf (model unchanged). */
+int vmc_model_set_params(vmc_model* m, const void* params_dev, int dtype);
+/* Writes the K parameters as complex128 (dtype C128) or complex64 (C64). */
+int vmc_model_get_params(const vmc_model* m, void* params_dev, int dtype);
+/* Precision of network evaluation: VMC_F64 (default) or VMC_F32 / VMC_BF16
+ * where supported (VMC_ERR_UNSUPPORTED otherwise). */
+int vmc_model_set_precision(vmc_model* m, int prec);
+int vmc_model_destroy(vmc_model* m);
+
+/* ---- Hamiltonians (Sec. 4.2 "Operators", eq:operator_mapping) ---------- */
+/* Bonds: for each site i = y*Lx + x in order, the bond to +x, then (Ly > 1)
+ * the bond to +y; periodic wraps, open boundaries drop wrapping bonds.  A
+ * periodic direction needs length >= 3.
+ * TFIM (Sec. 5): H = -J sum_<ij> Z_i Z_j - h sum_i X_i.                       */
+int vmc_ham_create_tfim(vmc_ctx* ctx, int Lx, int Ly, int periodic, double J, double h, vmc_ham** out);
+/* Heisenberg in Pauli matrices: H = J sum_<ij> (X_i X_j + Y_i Y_j + Z_i Z_j). */
+int vmc_ham_create_heisenberg(vmc_ctx* ctx, int Lx, int Ly, int periodic, double J, vmc_ham** out);
+/* M_max = 1 + N (TFIM) or 1 + n_bonds (Heisenberg). */
+int vmc_ham_max_connected(const vmc_ham* H, int* M_max);
+int vmc_ham_num_bonds(const vmc_ham* H, int* n_bonds);
+/* The paper's get_s_primes (Sec. 4.2): for each configuration the connected
+ * configurations and matrix elements, in the canonical slot order: slot 0 is
+ * the diagonal (always present, element -J*(n_al - n_anti) for TFIM,
+ * +J*(n_al - n_anti) for Heisenberg, one float64 product); then the non-zero
+ * off-diagonal terms in term order (X on sites 0..N-1 with element -h;
+ * exchange on anti-aligned bonds in bond order with element 2J).  Slots at
+ * and beyond count[b] repeat s with element 0.
+ *   sp:  B*M_max*W words;  mel: B*M_max doubles;  count: B int32.
+ * Test export: the hot path (vmc_local_energy) never writes s' to memory.  */
+int vmc_ham_connected(vmc_ham* H, const uint64_t* s, int64_t B, uint64_t* sp, double* mel, int32_t* count);
+int vmc_ham_destroy(vmc_ham* H);
+
+/* ---- hot path ------------------------------------------------------------ */
+/* log psi(s) (the NQS __call__, Sec. 4.2) for B configurations.
+ *   s: B*W words; logpsi: B complex128.  Im log psi is defined modulo 2*pi. */
+int vmc_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double* logpsi);
+
+/* Local energy, eq:Oloc with O = H:
+ *   E_loc(s) = sum_j H_{s s'_j} exp(log psi(s'_j) - log psi(s))
+ * over the connected configurations of vmc_ham_connected (s' never leave the
+ * chip).  logpsi_s is ignored (may be NULL): the kernel evaluates both sides
+ * itself.  eloc: B complex128.  The model's site count must equal the
+ * Hamiltonian's.                                                              */
+int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B,
+                     const double* logpsi_s, double* eloc);
+
+/* Log-derivatives O_k(s) = d log psi(s) / d theta_k (Sec. 2.2; the complex
+ * derivative for holomorphic nets, Sec. 2.3), flat parameter order.
+ *   O: B*K elements, sample-major (row n = sample n), dtype C128 or C64.      */
+int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
+
+/* Metropolis sampler of p(s) = |psi(s)|^2/<psi|psi> (Sec. 2.1, Sec. 4.2
+ * "Sampler"), all chains in sync.
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed & 0xffffffff,
+ * seed >> 32).  Proposal t (counted from 0 over the sampler's life) of chain c
+ * uses x = Philox((c, t & 0xffffffff, t >> 32, 0)):
+ *   flip:      site l = (x0 * N) >> 32, s' = s with bit l flipped;
+ *   exchange:  bond b = (x0 * n_bonds) >> 32, the two spins of bond b swapped
+ *              (aligned pair: identity move, accepted);
+ *   u = ((x1 << 21) | (x2 >> 11)) * 2^-53;
+ *   r = 2 Re(log psi(s') - log psi(s)); accept iff r >= 0 or u < exp(r).
+ * Initial state of chain c: flip - word w = (y0 | y1 << 32) for w even and
+ * (y2 | y3 << 32) for w odd, y = Philox((c, w/2, 0, 2)), masked to N bits;
+ * exchange - sites 0..N/2-1 up, then Fisher-Yates for i = N-1..1 swapping i
+ * with j = (y0 * (i+1)) >> 32, y = Philox((c, i, 1, 2)) (needs N even).
+ * A sweep is sweep_steps proposals (0 = N); therm_sweeps sweeps run before the
+ * first recorded sample of the sampler's life.                                */
+typedef struct {
+  int proposal;      /* VMC_PROP_FLIP | VMC_PROP_EXCHANGE | VMC_PROP_MADE_MIX */
+  int n_chains;      /* > 0 */
+  int sweep_steps;   /* proposals per sweep; 0 means N */
+  int therm_sweeps;  /* thermalisation sweeps before the first sample */
+  double p_global;   /* MADE_MIX: probability of a global proposal */
+  uint64_t seed;
+} vmc_sampler_opts;
+/* The sampler keeps a reference to m (and H for bonds); both must outlive it. */
+int vmc_sampler_create(vmc_ctx* ctx, vmc_model* m, vmc_ham* H, const vmc_sampler_opts* opts, vmc_sampler** out);
+/* Draws ceil(n_samples / n_chains) sweeps' worth of samples, one per chain per
+ * sweep, sample-major: output index k*n_chains + c.  s_out: n_written*W
+ * words; logpsi_out: n_written complex128 (may be NULL).  *n_written and
+ * *accept_rate_host (acceptance of this call's proposals; may be NULL) are
+ * host outputs; the call synchronises the stream.  The buffers must hold the
+ * rounded-up count.                                                          */
+int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, double* logpsi_out,
+               int64_t* n_written, double* accept_rate_host);
+/* Chain state (configurations, step counter, seed) as a host byte blob;
+ * *bytes in: capacity of buf_host (buf_host NULL: query size), out: size.   */
+int vmc_sampler_get_state(vmc_sampler* S, void* buf_host, size_t* bytes);
+int vmc_sampler_set_state(vmc_sampler* S, const void* buf_host, size_t bytes);
+/* Frozen MADE proposal used by VMC_PROP_MADE_MIX (the sampler copies its
+ * parameters; later training of md does not affect the sampler).            */
+int vmc_sampler_set_proposal_made(vmc_sampler* S, const vmc_made* md);
+int vmc_sampler_destroy(vmc_sampler* S);
+
+/* Regularised SR / TDVP solve: eq:qfm, eq:force_vector, eq:tdvp_util and the
+ * diagonal shift of Sec. 3.1:
+ *   S_kk' = <O_k^* O_k'> - <O_k^*><O_k'>,  F_k = <O_k^* E> - <O_k^*><E>,
+ *   S~ = [[S]] + nu_rel * diag([[S]]) + eps_abs * I,
+ *   S~ x = -[[gamma F]]   (Cholesky S~ = L L^H, two triangular solves).
+ * <.> is the sample mean (weights == NULL) or the weighted mean with weights
+ * normalised to sum 1.  The factor 2 of the SR gradient (eq:energy_gradient)
+ * is left to the caller's step size: theta <- theta + tau * x.
+ *   O: N*K sample-major, dtype C64 or C128;  eloc: N complex128;
+ *   weights: N doubles or NULL;  x: K complex128 (written on success).
+ * S is formed on the matrix cores from centred O in float32 (C64 input) or
+ * float64 (C128 input); factorisation and solves are float64.
+ * Returns VMC_ERR_NOT_PD with info->fail_index = first failing column, or
+ * VMC_ERR_UNSUPPORTED for VMC_SR_IMAG (Im S is antisymmetric, not PD).
+ * info_host (may be NULL) is written on return; the call synchronises.       */
+typedef struct {
+  double nu_rel;     /* relative diagonal shift (the paper's nu) */
+  double eps_abs;    /* additive shift */
+  int mode;          /* VMC_SR_COMPLEX | VMC_SR_REAL | VMC_SR_IMAG */
+  double gamma_re, gamma_im;  /* gamma = 1: SR / imaginary time; gamma = i: real time */
+} vmc_sr_opts;
+typedef struct {
+  double e_mean[2];  /* <E_loc> */
+  double e_var;      /* <|E_loc - <E_loc>|^2> */
+  double residual;   /* ||S~ x + [[gamma F]]|| / ||[[gamma F]]|| */
+  double min_pivot;  /* smallest Cholesky pivot (before the square root) */
+  int64_t fail_index;  /* -1, or the column where factorisation failed */
+} vmc_sr_info;
+int vmc_sr_solve(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, const double* weights,
+                 int64_t N, int64_t K, const vmc_sr_opts* opts, double* x, vmc_sr_info* info_host);
+
+/* ---- learned proposal: masked autoregressive network (MADE) ------------- */
+/* q(s) = prod_d p_d^{s_d} (1-p_d)^{1-s_d},  p = sigmoid(W2m relu(W1m sigma' + b1) + b2)
+ * with MADE masks (Germain et al. 2015; hidden degree m(k) = k mod (N-1) + 1,
+ * M1[k,d] = [m(k) >= d+1], M2[d,k] = [d+1 > m(k)]) on input x = s (0/1).
+ * Flat order: [W1 (H x N), b1 (H), W2 (N x H), b2 (N)], float64 on the host side. */
+int vmc_made_create(vmc_ctx* ctx, int n_in, int n_hidden, vmc_made** out);
+int vmc_made_num_params(const vmc_made* md, int64_t* P);
+int vmc_made_set_params(vmc_made* md, const double* params_dev);
+int vmc_made_get_params(const vmc_made* md, double* params_dev);
+/* log q(s) for B configurations (float64 out). */
+int vmc_made_log_q(vmc_made* md, const uint64_t* s, int64_t B, double* logq);
+/* Mean negative log-likelihood gradient over B configurations, flat order. */
+int vmc_made_nll_grad(vmc_made* md, const uint64_t* s, int64_t B, double* grad, double* nll_host);
+/* Adam (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8) on minibatches of
+ * `batch` rows of s for `epochs` passes in order; *nll_host = mean NLL of the
+ * last epoch.                                                                 */
+int vmc_made_train(vmc_made* md, const uint64_t* s, int64_t B, int epochs, int batch, double lr, double* nll_host);
+/* Autoregressive samples: row c uses Philox((c, counter_lo, counter_hi, 1 + 256*(d/4))),
+ * site d up iff x_{d%4} * 2^-32 < p_d.  s_out: B*W words; logq: B doubles.  */
+int vmc_made_sample(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, uint64_t* s_out, double* logq);
+int vmc_made_destroy(vmc_made* md);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NQSVMC_H */

@@ -1,0 +1,241 @@
+// Internal declarations of libnqsvmc: handle structs, error plumbing, device
+// math helpers (complex float64, Philox4x32-10) and kernel launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nqsvmc.h"
+
+// ---------------------------------------------------------------- errors --
+struct vmc_error {
+  int code;
+  std::string msg;
+};
+
+#define VMC_HIP(call)                                                           \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      throw vmc_error{VMC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define VMC_REQUIRE(cond, msg)                                                  \
+  do {                                                                          \
+    if (!(cond)) throw vmc_error{VMC_ERR_INVALID_ARG, msg};                     \
+  } while (0)
+
+// ------------------------------------------------------------- workspace --
+// Grow-only device arena owned by a context.  Buffers carved from it are
+// valid until the next call on the same context.
+struct vmc_arena {
+  void* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+
+struct vmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  size_t ws_limit = 0;
+  vmc_arena ws;
+  // pinned host staging for small readbacks
+  void* pinned = nullptr;
+  size_t pinned_cap = 0;
+};
+
+// Carving: call ws_begin, then ws_take for each buffer (256-byte aligned).
+void ws_reserve(vmc_ctx* ctx, size_t bytes);
+void* ws_take(vmc_ctx* ctx, size_t bytes);
+inline size_t ws_round(size_t b) { return (b + 255) & ~size_t(255); }
+void* pinned_host(vmc_ctx* ctx, size_t bytes);
+
+// ---------------------------------------------------------------- models --
+enum { MODEL_RBM = 0, MODEL_CNN = 1 };
+
+struct vmc_ham;
+
+// Per (model, move set) tables of the RBM ratio identity (see rbm.hip).
+struct rbm_move_tables {
+  int move_kind = -1;  // 0 = site flips, 1 = bond exchanges
+  int n_moves = 0;
+  uint64_t param_version = 0;
+  const vmc_ham* ham = nullptr;
+  double2* T = nullptr;    // [N_h][n_moves] tanh(2 D_jm)
+  double2* D = nullptr;    // [N_h][n_moves] D_jm
+  double2* LC = nullptr;   // [n_moves] sum_j logcosh(2 D_jm)
+  double2* alpha = nullptr;  // [n_moves] visible-bias difference
+};
+
+struct vmc_model {
+  vmc_ctx* ctx = nullptr;
+  int kind = MODEL_RBM;
+  int N = 0;          // sites
+  int W = 1;          // words per configuration
+  int Nh = 0;         // RBM hidden units
+  int is_complex = 1;
+  int Lx = 0, Ly = 0, C = 0, k = 0;  // CNN geometry
+  int64_t K = 0;
+  int prec = VMC_F64;
+  uint64_t version = 1;     // bumped on every set_params
+  double2* params = nullptr;  // K complex float64 master copy (device)
+  double2* Wt = nullptr;      // RBM: W transposed [N][N_h]
+  rbm_move_tables tab[2];     // flip / exchange tables
+};
+
+// ----------------------------------------------------------- Hamiltonians --
+enum { HAM_TFIM = 0, HAM_HEIS = 1 };
+
+struct vmc_ham {
+  vmc_ctx* ctx = nullptr;
+  int kind = HAM_TFIM;
+  int Lx = 0, Ly = 1, periodic = 1;
+  int N = 0, W = 1;
+  double J = 0.0, h = 0.0;
+  int n_bonds = 0;
+  std::vector<int2> bonds_host;
+  int2* bonds = nullptr;  // device copy
+  int M_max = 1;
+};
+
+struct vmc_made;
+
+struct vmc_sampler {
+  vmc_ctx* ctx = nullptr;
+  vmc_model* model = nullptr;
+  vmc_ham* ham = nullptr;
+  vmc_sampler_opts opts{};
+  int N = 0, W = 1;
+  uint64_t t = 0;            // proposals made per chain so far
+  int thermalized = 0;
+  uint64_t* bits = nullptr;  // [n_chains][W] chain configurations (device)
+  unsigned long long* acc = nullptr;  // [n_chains] accepted proposals in the current call
+  // frozen MADE proposal (VMC_PROP_MADE_MIX)
+  int made_hidden = 0;
+  double* made_params = nullptr;  // device, float64 flat MADE parameters
+  float* made_w = nullptr;        // device, float32 masked copies for the kernels
+};
+
+struct vmc_made {
+  vmc_ctx* ctx = nullptr;
+  int N = 0, H = 0, W = 1;
+  int64_t P = 0;
+  double* params = nullptr;  // device float64 master
+  double* adam_m = nullptr;
+  double* adam_v = nullptr;
+  int64_t adam_t = 0;
+};
+
+// ------------------------------------------------------- device helpers --
+namespace dev {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  // Smith's algorithm
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  } else {
+    double r = b.x / b.y, d = b.x * r + b.y;
+    return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+  }
+}
+__device__ __forceinline__ double2 cexp(double2 z) {
+  double e = exp(z.x), s, c;
+  sincos(z.y, &s, &c);
+  return make_double2(e * c, e * s);
+}
+__device__ __forceinline__ double2 clog(double2 z) {
+  return make_double2(log(hypot(z.x, z.y)), atan2(z.y, z.x));
+}
+
+// log cosh z without overflow: with z~ = +-z such that Re z~ >= 0,
+//   log cosh z = z~ - ln 2 + log(1 + e^{-2 z~})   (mod 2 pi i).
+__device__ __forceinline__ double2 clogcosh(double2 z) {
+  if (z.x < 0.0) z = make_double2(-z.x, -z.y);
+  double e = exp(-2.0 * z.x), s, c;
+  sincos(-2.0 * z.y, &s, &c);
+  double er = e * c, ei = e * s;  // e^{-2 z~}
+  // log|1 + w| = 0.5 log1p(2 Re w + |w|^2)
+  double lr = 0.5 * log1p(2.0 * er + er * er + ei * ei);
+  double li = atan2(ei, 1.0 + er);
+  return make_double2(z.x - 0.69314718055994530942 + lr, z.y + li);
+}
+
+// tanh z = (1 - e^{-2z})/(1 + e^{-2z}) for Re z >= 0; odd in z.
+__device__ __forceinline__ double2 ctanh(double2 z) {
+  bool neg = z.x < 0.0;
+  if (neg) z = make_double2(-z.x, -z.y);
+  double e = exp(-2.0 * z.x), s, c;
+  sincos(-2.0 * z.y, &s, &c);
+  double2 w = make_double2(e * c, e * s);
+  double2 r = cdiv(make_double2(1.0 - w.x, -w.y), make_double2(1.0 + w.x, w.y));
+  return neg ? make_double2(-r.x, -r.y) : r;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k.x += 0x9E3779B9u;
+      k.y += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k.x, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k.y,
+                   (uint32_t)p0);
+  }
+  return c;
+}
+__device__ __forceinline__ uint32_t to_index(uint32_t x, uint32_t n) {
+  return (uint32_t)(((uint64_t)x * n) >> 32);
+}
+__device__ __forceinline__ double to_uniform(uint32_t x1, uint32_t x2) {
+  uint64_t m = ((uint64_t)x1 << 21) | (x2 >> 11);
+  return (double)m * 0x1.0p-53;
+}
+
+__device__ __forceinline__ int get_bit(const uint64_t* w, int i) { return (int)((w[i >> 6] >> (i & 63)) & 1ull); }
+
+// Wave-wide (64-lane) reductions.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double2 wave_sum(double2 v) {
+  v.x = wave_sum(v.x);
+  v.y = wave_sum(v.y);
+  return v;
+}
+
+}  // namespace dev
+
+// -------------------------------------------------- cross-file launchers --
+// rbm.hip
+void rbm_theta(vmc_model* m, const uint64_t* s, int64_t B, double2* theta);
+void rbm_ensure_tables(vmc_model* m, const vmc_ham* H, int move_kind);
+void rbm_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* logpsi);
+void rbm_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
+void rbm_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
+// sampler.hip
+void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
+// sr.hip
+void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N,
+                   int64_t K, const vmc_sr_opts* o, double2* x, vmc_sr_info* info);
+// ham
+void ham_connected_impl(vmc_ham* H, const uint64_t* s, int64_t B, uint64_t* sp, double* mel, int32_t* cnt);
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }

@@ -1,0 +1,375 @@
+// RBM network kernels: pre-activations theta = W sigma + b over sample
+// batches, log psi, the fused connected-configuration / local-energy kernel,
+// and the per-sample log-derivatives O_k.
+//
+// Local energies (eq:Oloc) need psi(s')/psi(s) on every connected s'.  For the
+// RBM of eq:rbm_ex a connected configuration differs from s by one flipped spin
+// (TFIM) or one exchanged anti-aligned pair (Heisenberg), i.e. by a "move" m
+// that shifts every pre-activation by theta_j -> theta_j - 2 sigma_m D_jm with
+//   flip of site l:           D_jm = W_jl,          sigma_m = sigma_l,
+//   exchange of bond (i,k):   D_jm = W_ji - W_jk,   sigma_m = sigma_i (= -sigma_k).
+// cosh(theta - 2 sigma D) = cosh(theta) cosh(2D) (1 - sigma tanh(theta) tanh(2D)),
+// so, exactly,
+//   log psi(s') - log psi(s) = -2 sigma_m alpha_m + LC_m + sum_j log(1 - sigma_m t_j T_jm)
+// with t_j = tanh(theta_j(s)), T_jm = tanh(2 D_jm), LC_m = sum_j log cosh(2 D_jm)
+// and alpha_m = a_l (flip) or a_i - a_k (exchange).  T, LC and alpha depend on
+// the parameters only and are tabulated once per parameter version; each
+// connected configuration then costs N_h complex multiply-adds and no
+// transcendental, instead of a fresh N x N_h network evaluation.
+#include "internal.h"
+
+using namespace dev;
+
+namespace {
+
+constexpr int kThetaSamples = 16;  // samples per theta block (4 per thread)
+
+// theta[n][j] = b_j + sum_i Wt[i][j] sigma_i(n); block (64, 4): x = hidden unit,
+// y = group of 4 samples.
+__global__ __launch_bounds__(256) void k_theta(const double2* __restrict__ params, const double2* __restrict__ Wt,
+                                               const uint64_t* __restrict__ s, int64_t B, int N, int W, int Nh,
+                                               double2* __restrict__ theta) {
+  extern __shared__ uint64_t sbits[];  // [kThetaSamples][W]
+  const int64_t n0 = (int64_t)blockIdx.y * kThetaSamples;
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+  for (int e = tid; e < kThetaSamples * W; e += 256) {
+    int64_t n = n0 + e / W;
+    sbits[e] = n < B ? s[n * W + e % W] : 0ull;
+  }
+  __syncthreads();
+  const int j = blockIdx.x * 64 + threadIdx.x;
+  if (j >= Nh) return;
+  const double2 bj = params[N + j];
+  double2 acc[4] = {bj, bj, bj, bj};
+  const int r0 = threadIdx.y * 4;
+  for (int i = 0; i < N; ++i) {
+    const double2 w = Wt[(int64_t)i * Nh + j];
+    const int wd = i >> 6, bt = i & 63;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool up = (sbits[(r0 + q) * W + wd] >> bt) & 1ull;
+      acc[q].x += up ? w.x : -w.x;
+      acc[q].y += up ? w.y : -w.y;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t n = n0 + r0 + q;
+    if (n < B) theta[n * Nh + j] = acc[q];
+  }
+}
+
+// log psi(n) = sum_i a_i sigma_i + sum_j logcosh(theta_j); one wave per sample.
+__global__ __launch_bounds__(64) void k_logpsi(const double2* __restrict__ params, const double2* __restrict__ theta,
+                                               const uint64_t* __restrict__ s, int64_t B, int N, int W, int Nh,
+                                               double2* __restrict__ logpsi) {
+  const int64_t n = blockIdx.x;
+  if (n >= B) return;
+  const int lane = threadIdx.x;
+  double2 acc = make_double2(0.0, 0.0);
+  const uint64_t* sn = s + n * W;
+  for (int i = lane; i < N; i += 64) {
+    const double2 a = params[i];
+    const double sg = get_bit(sn, i) ? 1.0 : -1.0;
+    acc = cadd(acc, cscale(a, sg));
+  }
+  for (int j = lane; j < Nh; j += 64) acc = cadd(acc, clogcosh(theta[n * Nh + j]));
+  acc = wave_sum(acc);
+  if (lane == 0) logpsi[n] = acc;
+}
+
+// Move tables: one wave per move m.
+__global__ __launch_bounds__(64) void k_tables(const double2* __restrict__ params, const int2* __restrict__ bonds,
+                                               int move_kind, int n_moves, int N, int Nh, double2* __restrict__ T,
+                                               double2* __restrict__ D, double2* __restrict__ LC,
+                                               double2* __restrict__ alpha) {
+  const int m = blockIdx.x;
+  if (m >= n_moves) return;
+  const int lane = threadIdx.x;
+  const double2* Wm = params + N + Nh;
+  int i, k = -1;
+  if (move_kind == 0) {
+    i = m;
+  } else {
+    i = bonds[m].x;
+    k = bonds[m].y;
+  }
+  double2 lc = make_double2(0.0, 0.0);
+  for (int j = lane; j < Nh; j += 64) {
+    double2 d = Wm[(int64_t)j * N + i];
+    if (k >= 0) d = csub(d, Wm[(int64_t)j * N + k]);
+    const double2 d2 = cscale(d, 2.0);
+    D[(int64_t)j * n_moves + m] = d;
+    T[(int64_t)j * n_moves + m] = ctanh(d2);
+    lc = cadd(lc, clogcosh(d2));
+  }
+  lc = wave_sum(lc);
+  if (lane == 0) {
+    LC[m] = lc;
+    alpha[m] = k >= 0 ? csub(params[i], params[k]) : params[i];
+  }
+}
+
+// Fused enumeration + evaluation + reduction of E_loc; one wave per sample.
+// LDS: t_j (Nh complex) and the compacted move list (<= n_moves ints).
+__global__ __launch_bounds__(64) void k_eloc(const double2* __restrict__ theta, const uint64_t* __restrict__ s,
+                                             int64_t B, int N, int W, int Nh, int ham_kind, double J, double h,
+                                             const int2* __restrict__ bonds, int n_bonds,
+                                             const double2* __restrict__ T, const double2* __restrict__ LC,
+                                             const double2* __restrict__ alpha, int n_moves,
+                                             double2* __restrict__ eloc) {
+  extern __shared__ double2 lds[];
+  double2* t = lds;                              // [Nh]
+  int* moves = (int*)(lds + Nh);                 // [n_moves]
+  const int64_t n = blockIdx.x;
+  if (n >= B) return;
+  const int lane = threadIdx.x;
+  const uint64_t* sn = s + n * W;
+
+  for (int j = lane; j < Nh; j += 64) t[j] = ctanh(theta[n * Nh + j]);
+
+  // diagonal element: coupling * (n_aligned - n_anti), exact integer count
+  int n_al = 0;
+  for (int b = lane; b < n_bonds; b += 64) {
+    const int2 bd = bonds[b];
+    n_al += get_bit(sn, bd.x) == get_bit(sn, bd.y);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) n_al += __shfl_xor(n_al, o, 64);
+  const int n_anti = n_bonds - n_al;
+  const double diag = ham_kind == HAM_TFIM ? -J * (double)(n_al - n_anti) : J * (double)(n_al - n_anti);
+
+  // compacted list of off-diagonal moves in slot order
+  int n_slots = 0;
+  double mel;
+  if (ham_kind == HAM_TFIM) {
+    mel = -h;
+    if (h != 0.0) {
+      for (int l = lane; l < N; l += 64) moves[l] = l;
+      n_slots = N;
+    }
+  } else {
+    mel = 2.0 * J;
+    if (J != 0.0) {
+      for (int b0 = 0; b0 < n_bonds; b0 += 64) {
+        const int b = b0 + lane;
+        bool anti = false;
+        if (b < n_bonds) {
+          const int2 bd = bonds[b];
+          anti = get_bit(sn, bd.x) != get_bit(sn, bd.y);
+        }
+        const uint64_t mask = __ballot(anti);
+        const int pos = n_slots + __popcll(mask & ((1ull << lane) - 1ull));
+        if (anti) moves[pos] = b;
+        n_slots += __popcll(mask);
+      }
+    }
+  }
+  __syncthreads();
+
+  double2 acc = make_double2(0.0, 0.0);
+  for (int q0 = 0; q0 < n_slots; q0 += 64) {
+    const int q = q0 + lane;
+    if (q < n_slots) {
+      const int m = moves[q];
+      const int site = ham_kind == HAM_TFIM ? m : bonds[m].x;
+      const double sg = get_bit(sn, site) ? 1.0 : -1.0;
+      double2 P = make_double2(1.0, 0.0);
+      int e2 = 0;
+      const double2* Tm = T + m;
+      for (int j0 = 0; j0 < Nh; j0 += 32) {
+        const int j1 = min(Nh, j0 + 32);
+        for (int j = j0; j < j1; ++j) {
+          const double2 tt = cmul(t[j], Tm[(int64_t)j * n_moves]);
+          const double2 f = make_double2(1.0 - sg * tt.x, -sg * tt.y);
+          P = cmul(P, f);
+        }
+        // keep |P| near 1: exact power-of-two rescaling
+        int e;
+        frexp(fmax(fabs(P.x), fabs(P.y)), &e);
+        P.x = ldexp(P.x, -e);
+        P.y = ldexp(P.y, -e);
+        e2 += e;
+      }
+      const double2 a = alpha[m];
+      double2 lr = cadd(cscale(a, -2.0 * sg), LC[m]);
+      const double2 lp = clog(P);
+      lr.x += lp.x + (double)e2 * 0.69314718055994530942;
+      lr.y += lp.y;
+      acc = cadd(acc, cscale(cexp(lr), mel));
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) eloc[n] = make_double2(acc.x + diag, acc.y);
+}
+
+// O_k rows: [sigma (N), t (Nh), t_j sigma_i (Nh x N)]; one block per sample.
+template <typename OutT>
+__global__ __launch_bounds__(256) void k_grad(const double2* __restrict__ theta, const uint64_t* __restrict__ s,
+                                              int64_t B, int N, int W, int Nh, int64_t K, OutT* __restrict__ O) {
+  extern __shared__ double2 tl[];  // [Nh]
+  const int64_t n = blockIdx.x;
+  if (n >= B) return;
+  const int tid = threadIdx.x;
+  const uint64_t* sn = s + n * W;
+  for (int j = tid; j < Nh; j += 256) tl[j] = ctanh(theta[n * Nh + j]);
+  __syncthreads();
+  OutT* row = O + n * K;
+  auto put = [&](int64_t k, double2 v) {
+    if constexpr (sizeof(OutT) == sizeof(double2))
+      row[k] = v;
+    else
+      row[k] = make_float2((float)v.x, (float)v.y);
+  };
+  for (int i = tid; i < N; i += 256) put(i, make_double2(get_bit(sn, i) ? 1.0 : -1.0, 0.0));
+  for (int j = tid; j < Nh; j += 256) put(N + j, tl[j]);
+  const int64_t nw = (int64_t)N * Nh;
+  for (int64_t e = tid; e < nw; e += 256) {
+    const int j = (int)(e / N);
+    const int i = (int)(e - (int64_t)j * N);
+    const double2 v = tl[j];
+    put(N + Nh + e, get_bit(sn, i) ? v : make_double2(-v.x, -v.y));
+  }
+}
+
+// get_s_primes as a test export: one thread per sample.
+__global__ void k_connected(const uint64_t* __restrict__ s, int64_t B, int N, int W, int ham_kind, double J,
+                            double h, const int2* __restrict__ bonds, int n_bonds, int M_max,
+                            uint64_t* __restrict__ sp, double* __restrict__ mel, int32_t* __restrict__ count) {
+  const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (n >= B) return;
+  const uint64_t* sn = s + n * W;
+  int n_al = 0;
+  for (int b = 0; b < n_bonds; ++b) n_al += get_bit(sn, bonds[b].x) == get_bit(sn, bonds[b].y);
+  const int n_anti = n_bonds - n_al;
+  uint64_t* out = sp + n * (int64_t)M_max * W;
+  double* me = mel + n * (int64_t)M_max;
+  auto copy_s = [&](int slot) {
+    for (int w = 0; w < W; ++w) out[(int64_t)slot * W + w] = sn[w];
+  };
+  copy_s(0);
+  me[0] = ham_kind == HAM_TFIM ? -J * (double)(n_al - n_anti) : J * (double)(n_al - n_anti);
+  int c = 1;
+  if (ham_kind == HAM_TFIM) {
+    if (h != 0.0)
+      for (int l = 0; l < N; ++l, ++c) {
+        copy_s(c);
+        out[(int64_t)c * W + (l >> 6)] ^= 1ull << (l & 63);
+        me[c] = -h;
+      }
+  } else if (J != 0.0) {
+    for (int b = 0; b < n_bonds; ++b) {
+      const int i = bonds[b].x, k = bonds[b].y;
+      if (get_bit(sn, i) == get_bit(sn, k)) continue;
+      copy_s(c);
+      out[(int64_t)c * W + (i >> 6)] ^= 1ull << (i & 63);
+      out[(int64_t)c * W + (k >> 6)] ^= 1ull << (k & 63);
+      me[c] = 2.0 * J;
+      ++c;
+    }
+  }
+  count[n] = c;
+  for (int q = c; q < M_max; ++q) {
+    copy_s(q);
+    me[q] = 0.0;
+  }
+}
+
+constexpr int64_t kChunk = 1 << 16;  // samples per theta chunk
+
+}  // namespace
+
+void rbm_theta(vmc_model* m, const uint64_t* s, int64_t B, double2* theta) {
+  dim3 grid(grid_for(m->Nh, 64), grid_for(B, kThetaSamples));
+  k_theta<<<grid, dim3(64, 4), sizeof(uint64_t) * kThetaSamples * m->W, m->ctx->stream>>>(m->params, m->Wt, s, B,
+                                                                                          m->N, m->W, m->Nh, theta);
+  VMC_HIP(hipGetLastError());
+}
+
+void rbm_ensure_tables(vmc_model* m, const vmc_ham* H, int move_kind) {
+  rbm_move_tables& tb = m->tab[move_kind];
+  const int n_moves = move_kind == 0 ? m->N : H->n_bonds;
+  if (tb.T && tb.param_version == m->version && tb.n_moves == n_moves && (move_kind == 0 || tb.ham == H)) return;
+  if (tb.n_moves != n_moves || !tb.T) {
+    VMC_HIP(hipStreamSynchronize(m->ctx->stream));
+    if (tb.T) VMC_HIP(hipFree(tb.T));
+    if (tb.D) VMC_HIP(hipFree(tb.D));
+    if (tb.LC) VMC_HIP(hipFree(tb.LC));
+    if (tb.alpha) VMC_HIP(hipFree(tb.alpha));
+    tb.T = tb.D = tb.LC = tb.alpha = nullptr;
+    size_t tsz = sizeof(double2) * (size_t)m->Nh * std::max(1, n_moves);
+    VMC_HIP(hipMalloc(&tb.T, tsz));
+    VMC_HIP(hipMalloc(&tb.D, tsz));
+    VMC_HIP(hipMalloc(&tb.LC, sizeof(double2) * std::max(1, n_moves)));
+    VMC_HIP(hipMalloc(&tb.alpha, sizeof(double2) * std::max(1, n_moves)));
+  }
+  tb.move_kind = move_kind;
+  tb.n_moves = n_moves;
+  tb.ham = H;
+  if (n_moves > 0) {
+    k_tables<<<n_moves, 64, 0, m->ctx->stream>>>(m->params, H->bonds, move_kind, n_moves, m->N, m->Nh, tb.T, tb.D,
+                                                 tb.LC, tb.alpha);
+    VMC_HIP(hipGetLastError());
+  }
+  tb.param_version = m->version;
+}
+
+void rbm_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* logpsi) {
+  vmc_ctx* ctx = m->ctx;
+  const int64_t chunk = std::min<int64_t>(B, kChunk);
+  ws_reserve(ctx, ws_round(sizeof(double2) * chunk * m->Nh));
+  double2* theta = (double2*)ws_take(ctx, sizeof(double2) * chunk * m->Nh);
+  for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+    const int64_t nb = std::min(chunk, B - b0);
+    rbm_theta(m, s + b0 * m->W, nb, theta);
+    k_logpsi<<<(unsigned)nb, 64, 0, ctx->stream>>>(m->params, theta, s + b0 * m->W, nb, m->N, m->W, m->Nh,
+                                                  logpsi + b0);
+    VMC_HIP(hipGetLastError());
+  }
+}
+
+void rbm_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc) {
+  vmc_ctx* ctx = m->ctx;
+  const int move_kind = H->kind == HAM_TFIM ? 0 : 1;
+  rbm_ensure_tables(m, H, move_kind);
+  const rbm_move_tables& tb = m->tab[move_kind];
+  const int64_t chunk = std::min<int64_t>(B, kChunk);
+  ws_reserve(ctx, ws_round(sizeof(double2) * chunk * m->Nh));
+  double2* theta = (double2*)ws_take(ctx, sizeof(double2) * chunk * m->Nh);
+  const size_t lds = sizeof(double2) * m->Nh + sizeof(int) * std::max(1, tb.n_moves);
+  VMC_REQUIRE(lds <= 64 * 1024, "model too large for the local-energy kernel's LDS budget");
+  for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+    const int64_t nb = std::min(chunk, B - b0);
+    rbm_theta(m, s + b0 * m->W, nb, theta);
+    k_eloc<<<(unsigned)nb, 64, lds, ctx->stream>>>(theta, s + b0 * m->W, nb, m->N, m->W, m->Nh, H->kind, H->J, H->h,
+                                                   H->bonds, H->n_bonds, tb.T, tb.LC, tb.alpha, tb.n_moves,
+                                                   eloc + b0);
+    VMC_HIP(hipGetLastError());
+  }
+}
+
+void rbm_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype) {
+  vmc_ctx* ctx = m->ctx;
+  const int64_t chunk = std::min<int64_t>(B, kChunk);
+  ws_reserve(ctx, ws_round(sizeof(double2) * chunk * m->Nh));
+  double2* theta = (double2*)ws_take(ctx, sizeof(double2) * chunk * m->Nh);
+  const size_t esz = dtype == VMC_DT_C128 ? sizeof(double2) : sizeof(float2);
+  for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+    const int64_t nb = std::min(chunk, B - b0);
+    rbm_theta(m, s + b0 * m->W, nb, theta);
+    void* out = (char*)O + (size_t)b0 * m->K * esz;
+    if (dtype == VMC_DT_C128)
+      k_grad<double2><<<(unsigned)nb, 256, sizeof(double2) * m->Nh, ctx->stream>>>(
+          theta, s + b0 * m->W, nb, m->N, m->W, m->Nh, m->K, (double2*)out);
+    else
+      k_grad<float2><<<(unsigned)nb, 256, sizeof(double2) * m->Nh, ctx->stream>>>(
+          theta, s + b0 * m->W, nb, m->N, m->W, m->Nh, m->K, (float2*)out);
+    VMC_HIP(hipGetLastError());
+  }
+}
+
+void ham_connected_impl(vmc_ham* H, const uint64_t* s, int64_t B, uint64_t* sp, double* mel, int32_t* cnt) {
+  k_connected<<<grid_for(B, 128), 128, 0, H->ctx->stream>>>(s, B, H->N, H->W, H->kind, H->J, H->h, H->bonds,
+                                                             H->n_bonds, H->M_max, sp, mel, cnt);
+  VMC_HIP(hipGetLastError());
+}

@@ -1,0 +1,528 @@
+// Stochastic reconfiguration / TDVP solve (eq:qfm, eq:force_vector,
+// eq:tdvp_util, Sec. 3.1 diagonal shift):
+//   1. sample means <O_k>, <E> and Var E (float64 accumulation);
+//   2. centred, weight-scaled Obar_nk = sqrt(w_n) (O_nk - <O_k>) and the force
+//      F_k = sum_n w_n conj(O_nk - <O_k>) (E_n - <E>) in one pass over O;
+//   3. S = Obar^H Obar (Hermitian, lower triangle computed, mirrored);
+//      [[.]] projection and the shift S~ = S + nu diag(S) + eps I;
+//   4. blocked right-looking Cholesky S~ = L L^H in float64 (lower triangle
+//      overwritten; the upper triangle keeps S~ for the residual);
+//   5. L y = -[[gamma F]], L^H x = y; residual ||S~ x + [[gamma F]]|| / ||[[gamma F]]||.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+using namespace dev;
+
+namespace {
+
+constexpr int kColChunk = 256;  // samples per partial-sum chunk
+constexpr int NB = 32;          // Cholesky / triangular-solve block size
+
+template <typename InT>
+__device__ __forceinline__ double2 load_c(const InT* p, int64_t i) {
+  if constexpr (sizeof(InT) == sizeof(double2)) {
+    return ((const double2*)p)[i];
+  } else {
+    const float2 f = ((const float2*)p)[i];
+    return make_double2(f.x, f.y);
+  }
+}
+
+// sum of weights (or N when w == NULL) and the energy statistics
+__global__ __launch_bounds__(1024) void k_energy_stats(const double2* __restrict__ e, const double* __restrict__ w,
+                                                       int64_t N, double* __restrict__ out /*wsum, mean re, im, var*/) {
+  __shared__ double red[3][16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double sw = 0, sr = 0, si = 0;
+  for (int64_t n = tid; n < N; n += 1024) {
+    const double wn = w ? w[n] : 1.0;
+    sw += wn;
+    sr += wn * e[n].x;
+    si += wn * e[n].y;
+  }
+  sw = wave_sum(sw);
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) {
+    red[0][wv] = sw;
+    red[1][wv] = sr;
+    red[2][wv] = si;
+  }
+  __syncthreads();
+  __shared__ double tot[3];
+  if (tid == 0) {
+    double a = 0, b = 0, c = 0;
+    for (int q = 0; q < 16; ++q) {
+      a += red[0][q];
+      b += red[1][q];
+      c += red[2][q];
+    }
+    tot[0] = a;
+    tot[1] = b / a;
+    tot[2] = c / a;
+  }
+  __syncthreads();
+  const double wsum = tot[0], mr = tot[1], mi = tot[2];
+  double sv = 0;
+  for (int64_t n = tid; n < N; n += 1024) {
+    const double wn = w ? w[n] : 1.0;
+    const double dr = e[n].x - mr, di = e[n].y - mi;
+    sv += wn * (dr * dr + di * di);
+  }
+  sv = wave_sum(sv);
+  __syncthreads();
+  if (lane == 0) red[0][wv] = sv;
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0;
+    for (int q = 0; q < 16; ++q) a += red[0][q];
+    out[0] = wsum;
+    out[1] = mr;
+    out[2] = mi;
+    out[3] = a / wsum;
+  }
+}
+
+// partial[chunk][k] = sum_{n in chunk} w_n O_nk
+template <typename InT>
+__global__ __launch_bounds__(256) void k_col_partial(const InT* __restrict__ O, const double* __restrict__ w, int64_t N,
+                                                     int64_t K, double2* __restrict__ partial) {
+  const int64_t k = blockIdx.x * 256ll + threadIdx.x;
+  if (k >= K) return;
+  const int64_t n0 = (int64_t)blockIdx.y * kColChunk, n1 = min(N, n0 + kColChunk);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t n = n0; n < n1; ++n) {
+    const double wn = w ? w[n] : 1.0;
+    const double2 v = load_c(O, n * K + k);
+    acc.x += wn * v.x;
+    acc.y += wn * v.y;
+  }
+  partial[(int64_t)blockIdx.y * K + k] = acc;
+}
+
+__global__ void k_reduce_partial(const double2* __restrict__ partial, int nchunk, int64_t K,
+                                 const double* __restrict__ stats, double2* __restrict__ out) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int c = 0; c < nchunk; ++c) acc = cadd(acc, partial[(int64_t)c * K + k]);
+  out[k] = cscale(acc, 1.0 / stats[0]);
+}
+
+// Xc[n][k] = sqrt(w_n / wsum) (O_nk - mean_k); Fpartial[chunk][k] = sum w_n conj(O_nk - mean_k) (E_n - Ebar)
+template <typename InT, typename XT>
+__global__ __launch_bounds__(256) void k_center_force(const InT* __restrict__ O, const double* __restrict__ w,
+                                                      const double2* __restrict__ e, int64_t N, int64_t K,
+                                                      const double2* __restrict__ mean,
+                                                      const double* __restrict__ stats, XT* __restrict__ Xc,
+                                                      double2* __restrict__ Fpartial) {
+  const int64_t k = blockIdx.x * 256ll + threadIdx.x;
+  if (k >= K) return;
+  const int64_t n0 = (int64_t)blockIdx.y * kColChunk, n1 = min(N, n0 + kColChunk);
+  const double wsum = stats[0];
+  const double2 eb = make_double2(stats[1], stats[2]);
+  const double2 mk = mean[k];
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t n = n0; n < n1; ++n) {
+    const double wn = (w ? w[n] : 1.0) / wsum;
+    const double2 d = csub(load_c(O, n * K + k), mk);
+    const double sq = sqrt(wn);
+    if constexpr (sizeof(XT) == sizeof(double2))
+      Xc[n * K + k] = make_double2(sq * d.x, sq * d.y);
+    else
+      Xc[n * K + k] = make_float2((float)(sq * d.x), (float)(sq * d.y));
+    const double2 de = csub(e[n], eb);
+    const double2 p = cmul(cconj(d), de);
+    acc.x += wn * p.x;
+    acc.y += wn * p.y;
+  }
+  Fpartial[(int64_t)blockIdx.y * K + k] = acc;
+}
+
+__global__ void k_reduce_plain(const double2* __restrict__ partial, int nchunk, int64_t K, double2* __restrict__ out) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int c = 0; c < nchunk; ++c) acc = cadd(acc, partial[(int64_t)c * K + k]);
+  out[k] = acc;
+}
+
+// S[r][c] = sum_n conj(Xc[n][r]) Xc[n][c] for the 32x32 tile (r >= c block-wise),
+// written to both triangles; projection and shift applied here.
+template <typename XT>
+__global__ __launch_bounds__(256) void k_herk_simple(const XT* __restrict__ X, int64_t N, int64_t K, int mode,
+                                                     double nu, double eps, double2* __restrict__ S,
+                                                     double2* __restrict__ diag) {
+  const int tr = blockIdx.y, tc = blockIdx.x;
+  if (tc > tr) return;
+  __shared__ double2 xa[16][33], xb[16][33];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t r0 = (int64_t)tr * 32, c0 = (int64_t)tc * 32;
+  double2 acc[2][2] = {};
+  for (int64_t n0 = 0; n0 < N; n0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 32; e += 256) {
+      const int nn = e >> 5, cc = e & 31;
+      const int64_t n = n0 + nn;
+      xa[nn][cc] = (n < N && r0 + cc < K) ? load_c(X, n * K + r0 + cc) : make_double2(0.0, 0.0);
+      xb[nn][cc] = (n < N && c0 + cc < K) ? load_c(X, n * K + c0 + cc) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int nn = 0; nn < 16; ++nn) {
+      const double2 a0 = cconj(xa[nn][ty]), a1 = cconj(xa[nn][ty + 16]);
+      const double2 b0 = xb[nn][tx], b1 = xb[nn][tx + 16];
+      acc[0][0] = cadd(acc[0][0], cmul(a0, b0));
+      acc[0][1] = cadd(acc[0][1], cmul(a0, b1));
+      acc[1][0] = cadd(acc[1][0], cmul(a1, b0));
+      acc[1][1] = cadd(acc[1][1], cmul(a1, b1));
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
+      if (r >= K || c >= K || c > r) continue;
+      double2 v = acc[i][j];
+      if (mode == VMC_SR_REAL) v.y = 0.0;
+      if (r == c) {
+        v = make_double2(v.x * (1.0 + nu) + eps, 0.0);
+        diag[r] = v;
+      }
+      S[r * K + c] = v;
+      if (r != c) S[c * K + r] = cconj(v);
+    }
+}
+
+// ---- Cholesky ----------------------------------------------------------
+__global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
+                                                   long long* __restrict__ fail, double* __restrict__ pivmin) {
+  __shared__ double2 a[NB][NB + 1];
+  __shared__ int bad;
+  __shared__ double pmin;
+  if (*fail >= 0) return;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e % NB;
+    a[r][c] = (r < nb && c <= r) ? A[(kb0 + r) * K + kb0 + c] : make_double2(0.0, 0.0);
+  }
+  if (tid == 0) {
+    bad = 0;
+    pmin = INFINITY;
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double d = a[j][j].x;
+    if (tid == 0) {
+      pmin = fmin(pmin, d);
+      if (!(d > 0.0)) {
+        bad = 1;
+        *fail = kb0 + j;
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    const double l = sqrt(d);
+    if (tid > j && tid < nb) a[tid][j] = cscale(a[tid][j], 1.0 / l);
+    __syncthreads();
+    if (tid == 0) a[j][j] = make_double2(l, 0.0);
+    const int m = nb - j - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int r = j + 1 + e / m, c = j + 1 + e % m;
+      if (c <= r) a[r][c] = csub(a[r][c], cmul(a[r][j], cconj(a[c][j])));
+    }
+    __syncthreads();
+  }
+  if (tid == 0) pivmin[kb0 / NB] = pmin;
+  if (bad) return;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e / NB, c = e % NB;
+    if (r < nb && c <= r) A[(kb0 + r) * K + kb0 + c] = a[r][c];
+  }
+}
+
+// rows below the diagonal block: X L_kk^H = A  ->  X
+__global__ __launch_bounds__(64) void k_chol_trsm(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
+                                                  const long long* __restrict__ fail) {
+  __shared__ double2 L[NB][NB + 1];
+  __shared__ double2 X[64][NB + 1];
+  if (*fail >= 0) return;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += 64) {
+    const int r = e / NB, c = e % NB;
+    L[r][c] = (r < nb && c <= r) ? A[(kb0 + r) * K + kb0 + c] : make_double2(0.0, 0.0);
+  }
+  const int64_t row = kb0 + nb + (int64_t)blockIdx.x * 64 + tid;
+  const bool live = row < K;
+  for (int c = 0; c < nb; ++c) X[tid][c] = live ? A[row * K + kb0 + c] : make_double2(0.0, 0.0);
+  __syncthreads();
+  if (!live) return;
+  for (int j = 0; j < nb; ++j) {
+    double2 v = X[tid][j];
+    for (int m = 0; m < j; ++m) v = csub(v, cmul(X[tid][m], cconj(L[j][m])));
+    X[tid][j] = cscale(v, 1.0 / L[j][j].x);
+  }
+  for (int c = 0; c < nb; ++c) A[row * K + kb0 + c] = X[tid][c];
+}
+
+// trailing update A[r][c] -= sum_m L[r][kb0+m] conj(L[c][kb0+m]) on the lower triangle
+__global__ __launch_bounds__(256) void k_chol_update(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
+                                                     const long long* __restrict__ fail) {
+  if (*fail >= 0) return;
+  const int tr = blockIdx.y, tc = blockIdx.x;
+  if (tc > tr) return;
+  const int64_t base = kb0 + nb;
+  const int64_t r0 = base + (int64_t)tr * 32, c0 = base + (int64_t)tc * 32;
+  __shared__ double2 pa[32][NB + 1], pb[32][NB + 1];
+  for (int e = threadIdx.x; e < 32 * NB; e += 256) {
+    const int rr = e / NB, m = e % NB;
+    pa[rr][m] = (r0 + rr < K && m < nb) ? A[(r0 + rr) * K + kb0 + m] : make_double2(0.0, 0.0);
+    pb[rr][m] = (c0 + rr < K && m < nb) ? A[(c0 + rr) * K + kb0 + m] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double2 acc[2][2] = {};
+  for (int m = 0; m < nb; ++m) {
+    const double2 a0 = pa[ty][m], a1 = pa[ty + 16][m];
+    const double2 b0 = cconj(pb[tx][m]), b1 = cconj(pb[tx + 16][m]);
+    acc[0][0] = cadd(acc[0][0], cmul(a0, b0));
+    acc[0][1] = cadd(acc[0][1], cmul(a0, b1));
+    acc[1][0] = cadd(acc[1][0], cmul(a1, b0));
+    acc[1][1] = cadd(acc[1][1], cmul(a1, b1));
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
+      if (r < K && c < K && c <= r) A[r * K + c] = csub(A[r * K + c], acc[i][j]);
+    }
+}
+
+// ---- triangular solves -------------------------------------------------
+// y_kb = L_kk^{-1} b_kb (in place in b)
+__global__ void k_trsv_fwd_diag(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb, double2* __restrict__ b) {
+  __shared__ double2 y[NB];
+  const int tid = threadIdx.x;
+  if (tid < nb) y[tid] = b[kb0 + tid];
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (tid == j) y[j] = cscale(y[j], 1.0 / A[(kb0 + j) * K + kb0 + j].x);
+    __syncthreads();
+    if (tid > j && tid < nb) y[tid] = csub(y[tid], cmul(A[(kb0 + tid) * K + kb0 + j], y[j]));
+    __syncthreads();
+  }
+  if (tid < nb) b[kb0 + tid] = y[tid];
+}
+
+// b[r] -= sum_m L[r][kb0+m] y[kb0+m] for rows r >= kb0 + nb
+__global__ void k_trsv_fwd_update(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb, double2* __restrict__ b) {
+  const int64_t r = kb0 + nb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= K) return;
+  double2 acc = b[r];
+  for (int m = 0; m < nb; ++m) acc = csub(acc, cmul(A[r * K + kb0 + m], b[kb0 + m]));
+  b[r] = acc;
+}
+
+// x_kb = L_kk^{-H} y_kb (in place)
+__global__ void k_trsv_bwd_diag(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb, double2* __restrict__ b) {
+  __shared__ double2 y[NB];
+  const int tid = threadIdx.x;
+  if (tid < nb) y[tid] = b[kb0 + tid];
+  __syncthreads();
+  for (int j = nb - 1; j >= 0; --j) {
+    if (tid == j) y[j] = cscale(y[j], 1.0 / A[(kb0 + j) * K + kb0 + j].x);
+    __syncthreads();
+    // (L^H)[i][j] = conj(L[j][i]) for i < j
+    if (tid < j) y[tid] = csub(y[tid], cmul(cconj(A[(kb0 + j) * K + kb0 + tid]), y[j]));
+    __syncthreads();
+  }
+  if (tid < nb) b[kb0 + tid] = y[tid];
+}
+
+// b[c] -= sum_m conj(L[kb0+m][c]) x[kb0+m] for columns c < kb0
+__global__ void k_trsv_bwd_update(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb, double2* __restrict__ b) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= kb0) return;
+  double2 acc = b[c];
+  for (int m = 0; m < nb; ++m) acc = csub(acc, cmul(cconj(A[(kb0 + m) * K + c]), b[kb0 + m]));
+  b[c] = acc;
+}
+
+// rhs = -[[gamma F]]
+__global__ void k_rhs(const double2* __restrict__ F, int64_t K, double gr, double gi, int mode, double2* __restrict__ rhs) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double2 v = cmul(make_double2(gr, gi), F[k]);
+  if (mode == VMC_SR_REAL) v.y = 0.0;
+  rhs[k] = make_double2(-v.x, -v.y);
+}
+
+// r_k = sum_c S~[k][c] x_c - rhs_k, using the upper triangle (S~ itself) and
+// the saved diagonal; one wave per row.
+__global__ __launch_bounds__(64) void k_resid_upper(const double2* __restrict__ A, int64_t K,
+                                                    const double2* __restrict__ diag, const double2* __restrict__ x,
+                                                    double2* __restrict__ r) {
+  const int64_t k = blockIdx.x;
+  const int lane = threadIdx.x;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t c = k + 1 + lane; c < K; c += 64) acc = cadd(acc, cmul(A[k * K + c], x[c]));
+  acc = wave_sum(acc);
+  if (lane == 0) r[k] = cadd(acc, cmul(diag[k], x[k]));
+}
+
+// r_c += sum_{k<c} conj(S~[k][c]) x_k  (strictly lower part via the upper storage)
+__global__ void k_resid_lower(const double2* __restrict__ A, int64_t K, const double2* __restrict__ x,
+                              const double2* __restrict__ rhs, double2* __restrict__ r) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= K) return;
+  double2 acc = r[c];
+  for (int64_t k = 0; k < c; ++k) acc = cadd(acc, cmul(cconj(A[k * K + c]), x[k]));
+  r[c] = csub(acc, rhs[c]);
+}
+
+__global__ __launch_bounds__(1024) void k_norms(const double2* __restrict__ a, const double2* __restrict__ b, int64_t K,
+                                                double* __restrict__ out) {
+  __shared__ double ra[16], rb[16];
+  double sa = 0, sb = 0;
+  for (int64_t k = threadIdx.x; k < K; k += 1024) {
+    sa += a[k].x * a[k].x + a[k].y * a[k].y;
+    sb += b[k].x * b[k].x + b[k].y * b[k].y;
+  }
+  sa = wave_sum(sa);
+  sb = wave_sum(sb);
+  if ((threadIdx.x & 63) == 0) {
+    ra[threadIdx.x >> 6] = sa;
+    rb[threadIdx.x >> 6] = sb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double x = 0, y = 0;
+    for (int q = 0; q < 16; ++q) {
+      x += ra[q];
+      y += rb[q];
+    }
+    out[0] = x;
+    out[1] = y;
+  }
+}
+
+__global__ void k_init_fail(long long* f) { *f = -1; }
+
+}  // namespace
+
+void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N, int64_t K,
+                   const vmc_sr_opts* o, double2* x, vmc_sr_info* info) {
+  hipStream_t st = ctx->stream;
+  const int nchunk = (int)((N + kColChunk - 1) / kColChunk);
+  const int nblk = (int)((K + NB - 1) / NB);
+  const bool f32 = dtype == VMC_DT_C64;
+  const size_t xsz = (f32 ? sizeof(float2) : sizeof(double2)) * (size_t)N * K;
+  size_t total = ws_round(64) + ws_round(sizeof(double2) * nchunk * K) + ws_round(sizeof(double2) * K) * 6 +
+                 ws_round(xsz) + ws_round(sizeof(double2) * (size_t)K * K) + ws_round(sizeof(double) * nblk) +
+                 ws_round(sizeof(long long)) + ws_round(sizeof(double) * 4);
+  ws_reserve(ctx, total);
+  double* stats = (double*)ws_take(ctx, 64);
+  double2* partial = (double2*)ws_take(ctx, sizeof(double2) * nchunk * K);
+  double2* mean = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* F = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* rhs = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* sol = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* diag = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* res = (double2*)ws_take(ctx, sizeof(double2) * K);
+  void* Xc = ws_take(ctx, xsz);
+  double2* S = (double2*)ws_take(ctx, sizeof(double2) * (size_t)K * K);
+  double* pivmin = (double*)ws_take(ctx, sizeof(double) * nblk);
+  long long* fail = (long long*)ws_take(ctx, sizeof(long long));
+  double* norms = (double*)ws_take(ctx, sizeof(double) * 4);
+
+  k_energy_stats<<<1, 1024, 0, st>>>(eloc, w, N, stats);
+  dim3 cg(grid_for(K, 256), nchunk);
+  if (f32) {
+    k_col_partial<float2><<<cg, 256, 0, st>>>((const float2*)O, w, N, K, partial);
+  } else {
+    k_col_partial<double2><<<cg, 256, 0, st>>>((const double2*)O, w, N, K, partial);
+  }
+  k_reduce_partial<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, stats, mean);
+  if (f32)
+    k_center_force<float2, float2><<<cg, 256, 0, st>>>((const float2*)O, w, eloc, N, K, mean, stats, (float2*)Xc,
+                                                        partial);
+  else
+    k_center_force<double2, double2><<<cg, 256, 0, st>>>((const double2*)O, w, eloc, N, K, mean, stats,
+                                                          (double2*)Xc, partial);
+  k_reduce_plain<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, F);
+  VMC_HIP(hipGetLastError());
+
+  dim3 hg(nblk, nblk);
+  if (f32)
+    k_herk_simple<float2><<<hg, 256, 0, st>>>((const float2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag);
+  else
+    k_herk_simple<double2><<<hg, 256, 0, st>>>((const double2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag);
+  VMC_HIP(hipGetLastError());
+
+  k_init_fail<<<1, 1, 0, st>>>(fail);
+  for (int b = 0; b < nblk; ++b) {
+    const int64_t kb0 = (int64_t)b * NB;
+    const int nb = (int)std::min<int64_t>(NB, K - kb0);
+    k_chol_diag<<<1, 256, 0, st>>>(S, K, kb0, nb, fail, pivmin);
+    const int64_t rest = K - kb0 - nb;
+    if (rest > 0) {
+      k_chol_trsm<<<grid_for(rest, 64), 64, 0, st>>>(S, K, kb0, nb, fail);
+      const int nt = (int)((rest + 31) / 32);
+      k_chol_update<<<dim3(nt, nt), 256, 0, st>>>(S, K, kb0, nb, fail);
+    }
+  }
+  VMC_HIP(hipGetLastError());
+
+  // fail flag and pivots back to the host
+  const size_t hbytes = sizeof(long long) + sizeof(double) * (nblk + 8);
+  char* h = (char*)pinned_host(ctx, hbytes);
+  VMC_HIP(hipMemcpyAsync(h, fail, sizeof(long long), hipMemcpyDeviceToHost, st));
+  VMC_HIP(hipMemcpyAsync(h + sizeof(long long), pivmin, sizeof(double) * nblk, hipMemcpyDeviceToHost, st));
+  VMC_HIP(hipMemcpyAsync(h + sizeof(long long) + sizeof(double) * nblk, stats, sizeof(double) * 4,
+                         hipMemcpyDeviceToHost, st));
+  VMC_HIP(hipStreamSynchronize(st));
+  long long fidx;
+  std::memcpy(&fidx, h, sizeof(fidx));
+  const double* piv = (const double*)(h + sizeof(long long));
+  const double* hs = piv + nblk;
+  info->e_mean[0] = hs[1];
+  info->e_mean[1] = hs[2];
+  info->e_var = hs[3];
+  info->fail_index = fidx;
+  const int nb_done = fidx >= 0 ? (int)(fidx / NB) + 1 : nblk;
+  double pm = INFINITY;
+  for (int b = 0; b < nb_done; ++b) pm = std::min(pm, piv[b]);
+  info->min_pivot = pm;
+  info->residual = NAN;
+  if (fidx >= 0) return;
+
+  k_rhs<<<grid_for(K, 256), 256, 0, st>>>(F, K, o->gamma_re, o->gamma_im, o->mode, rhs);
+  VMC_HIP(hipMemcpyAsync(sol, rhs, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
+  for (int b = 0; b < nblk; ++b) {
+    const int64_t kb0 = (int64_t)b * NB;
+    const int nb = (int)std::min<int64_t>(NB, K - kb0);
+    k_trsv_fwd_diag<<<1, 64, 0, st>>>(S, K, kb0, nb, sol);
+    const int64_t rest = K - kb0 - nb;
+    if (rest > 0) k_trsv_fwd_update<<<grid_for(rest, 256), 256, 0, st>>>(S, K, kb0, nb, sol);
+  }
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int64_t kb0 = (int64_t)b * NB;
+    const int nb = (int)std::min<int64_t>(NB, K - kb0);
+    k_trsv_bwd_diag<<<1, 64, 0, st>>>(S, K, kb0, nb, sol);
+    if (kb0 > 0) k_trsv_bwd_update<<<grid_for(kb0, 256), 256, 0, st>>>(S, K, kb0, nb, sol);
+  }
+  VMC_HIP(hipGetLastError());
+  k_resid_upper<<<(unsigned)K, 64, 0, st>>>(S, K, diag, sol, res);
+  k_resid_lower<<<grid_for(K, 256), 256, 0, st>>>(S, K, sol, rhs, res);
+  k_norms<<<1, 1024, 0, st>>>(res, rhs, K, norms);
+  VMC_HIP(hipMemcpyAsync(x, sol, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
+  VMC_HIP(hipGetLastError());
+  double* hn = (double*)pinned_host(ctx, sizeof(double) * 2);
+  VMC_HIP(hipMemcpyAsync(hn, norms, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+  VMC_HIP(hipStreamSynchronize(st));
+  info->residual = hn[1] > 0 ? std::sqrt(hn[0] / hn[1]) : std::sqrt(hn[0]);
+}

@@ -1,0 +1,82 @@
+"""GPU SR / TDVP solve against the oracle (S, F, shift, Cholesky, solves)."""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import rbm as orbm, eloc as oeloc, sr as osr
+from gpu_common import dev_bits, dev_c128, flush
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2108_03409_amd import nqsvmc as V  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return V.Context(0)
+
+
+def _problem(N, Nh, ns, std, seed, cplx=True):
+    p = si.rbm_params(N, Nh, std=std, is_complex=cplx, seed=seed)
+    bits = si.random_bits(ns, N, seed=seed + 1)
+    O = orbm.grad_log_psi(p, bits, Nh)
+    el = oeloc.local_energy(lambda x: orbm.log_psi(p, x, Nh), "tfim", bits, N, 1, True, 1.0, 1.0)
+    return O, el
+
+
+@pytest.mark.parametrize("N,Nh,ns,mode,gamma,nu,eps,weighted", [
+    (10, 10, 1024, "real", 1.0, 1e-3, 0.0, False),
+    (8, 16, 300, "complex", 1.0, 1e-2, 0.0, False),
+    (8, 16, 300, "complex", 1j, 1e-2, 1e-4, True),
+    (12, 20, 77, "complex", 1.0, 1e-3, 0.0, False),   # fewer samples than parameters
+    (20, 40, 2000, "complex", 1.0, 1e-3, 0.0, False),  # K = 860: many blocks + ragged tail
+])
+def test_sr_solve_fp64_matches_oracle(ctx, N, Nh, ns, mode, gamma, nu, eps, weighted):
+    flush(f"sr fp64 N={N} Nh={Nh} ns={ns} mode={mode}")
+    O, el = _problem(N, Nh, ns, 0.2, seed=N * Nh, cplx=(mode != "real"))
+    w = np.random.default_rng(3).uniform(0.5, 1.5, ns) if weighted else None
+    x_ref, info_ref = osr.sr_solve(O, el, nu_rel=nu, eps_abs=eps, mode=mode, gamma=gamma, weights=w)
+    x, info = V.sr_solve(ctx, dev_c128(O), dev_c128(el), weights=None if w is None else
+                         torch.from_numpy(w).to("cuda:0"), nu_rel=nu, eps_abs=eps,
+                         mode=V.SR_REAL if mode == "real" else V.SR_COMPLEX, gamma=gamma)
+    x = x.cpu().numpy()
+    S, F = osr.fisher_and_force(O, el, w)
+    St = osr.shifted(osr.project(S, mode), nu, eps)
+    kappa = np.linalg.cond(St)
+    err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+    assert err <= max(1e-12, 1e-15 * kappa * 100), (err, kappa)
+    assert info["residual"] < 1e-10
+    assert abs(info["e_mean"] - info_ref["e_mean"]) < 1e-12 * max(1, abs(info_ref["e_mean"]))
+    assert abs(info["e_var"] - info_ref["e_var"]) < 1e-10 * max(1, info_ref["e_var"])
+    assert abs(info["min_pivot"] - info_ref["min_pivot"]) <= 1e-9 * abs(info_ref["min_pivot"])
+
+
+def test_sr_solve_fp32_gram_within_bound(ctx):
+    # S from complex64 O on the float32 path; error bound |dS| <= gamma_N sum |Obar||Obar| (Higham)
+    N, Nh, ns = 16, 32, 4096
+    O, el = _problem(N, Nh, ns, 0.2, seed=5)
+    x_ref, _ = osr.sr_solve(O.astype(np.complex64).astype(np.complex128), el, nu_rel=1e-2)
+    x, info = V.sr_solve(ctx, torch.from_numpy(O.astype(np.complex64)).to("cuda:0"), dev_c128(el), nu_rel=1e-2)
+    x = x.cpu().numpy()
+    S, _ = osr.fisher_and_force(O, el)
+    St = osr.shifted(S, 1e-2)
+    kappa = np.linalg.cond(St)
+    err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+    bound = kappa * 4 * np.sqrt(ns) * 2.0 ** -24
+    assert err <= bound, (err, bound)
+    assert info["residual"] < 1e-10
+
+
+def test_not_pd_reported(ctx):
+    O, el = _problem(12, 20, 50, 0.2, seed=8)
+    x, info = V.sr_solve(ctx, dev_c128(O), dev_c128(el), nu_rel=0.0, raise_on_error=False)
+    assert x is None and info["status"] == "NOT_PD"
+    _, info_ref = osr.sr_solve(O, el, nu_rel=0.0)
+    assert info["fail_index"] >= 0 and info_ref["fail_index"] >= 0
+    with pytest.raises(V.VMCError) as e:
+        V.sr_solve(ctx, dev_c128(O), dev_c128(el), mode=V.SR_IMAG)
+    assert e.value.name == "UNSUPPORTED"
