@@ -1,0 +1,204 @@
+"""Throughput of the NQS-VMC hot path on one MI355X.
+
+One step = one stochastic-reconfiguration step (the paper's Algorithm 1 plus
+the parameter update): Metropolis sampling, log psi, log-derivatives O_k,
+local energies, S / F with the shifted Cholesky solve, theta <- theta + tau x.
+
+Default workload: 1D transverse-field Ising chain L = 64 (periodic, J = h = 1),
+complex RBM alpha = 4 (16 704 parameters, N(0, 0.01)), 16 384 samples per step
+(1024 chains x 16 sweeps of 64 single-spin-flip proposals), S from complex64
+O_k on the matrix path, float64 Cholesky with relative diagonal shift 1e-3.
+
+Prints one JSON line (rank 0): SR steps/s with per-phase times, local
+energies/s, the roofline of the dominant kernel (live HIP-event timing on the
+library's stream) and the FP64 oracle timed on the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth_inputs as si  # noqa: E402
+
+PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TF": 157.3, "fp64_TF": 78.6, "fp64_valu_TF": 78.6, "bf16_mfma_TF": 2500.0}
+METRIC = "local energies/s & SR steps/s vs roofline; ESS/s learned vs local proposal"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="tfim1d_L64_rbm_a4_sr", choices=["tfim1d_L64_rbm_a4_sr"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tau", type=float, default=1e-2)
+    return ap.parse_args()
+
+
+def herk_flops(ns, K):
+    """Complex Hermitian rank-ns update, lower triangle with diagonal: K(K+1)/2 outputs x ns
+    complex multiply-adds x 8 real flops."""
+    return 4.0 * ns * K * (K + 1)
+
+
+def chol_flops(K):
+    """Complex Cholesky: K^3/6 complex multiply-adds x 8 real flops (leading order)."""
+    return 4.0 * K ** 3 / 3.0
+
+
+def eloc_flops(N, Nh, n_slots):
+    """Per local energy: theta = b + sum_i +-W_ji (2 N Nh real flops) and, per non-zero
+    off-diagonal slot, N_h complex multiply, subtract and multiply (14 real flops)."""
+    return 2.0 * N * Nh + 14.0 * Nh * n_slots
+
+
+def cpu_baseline(cfg, p, N, Nh, n_chains, per_chain):
+    """The FP64 oracle on a bounded sample of the same step, scaled to one step."""
+    from oracle import rbm as orbm, eloc as oeloc, metropolis as omet, sr as osr
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    f = lambda b: orbm.log_psi(p, b, Nh)
+    t = {}
+    # sampling: 32 chains x one sweep, scaled to n_chains x per_chain sweeps
+    ch = omet.Chains(f, N, "flip", seed=103, chain_ids=np.arange(32), therm_sweeps=0)
+    t0 = time.perf_counter()
+    s, _ = ch.sample(1)
+    t["sample"] = (time.perf_counter() - t0) * (n_chains * per_chain) / 32
+    bits = si.random_bits(1024, N, seed=7)
+    t0 = time.perf_counter()
+    orbm.log_psi(p, bits, Nh)
+    t["log_psi"] = (time.perf_counter() - t0) * 16
+    t0 = time.perf_counter()
+    O = orbm.grad_log_psi(p, bits, Nh)
+    t["grad"] = (time.perf_counter() - t0) * 16
+    t0 = time.perf_counter()
+    el = oeloc.local_energy(f, "tfim", bits[:32], N, 1, True, 1.0, 1.0)
+    t["eloc"] = (time.perf_counter() - t0) * (n_chains * per_chain) / 32
+    ns = 256
+    el_s = np.resize(el, ns)
+    t0 = time.perf_counter()
+    S, F = osr.fisher_and_force(O[:ns], el_s)
+    t["S_F"] = (time.perf_counter() - t0) * (n_chains * per_chain) / ns
+    Kp = 768
+    A = osr.shifted(S[:Kp, :Kp], 1e-3)
+    del S
+    t0 = time.perf_counter()
+    L, fail, _ = osr.cholesky(A)
+    t["cholesky"] = (time.perf_counter() - t0) * (len(p) / Kp) ** 3
+    t0 = time.perf_counter()
+    osr.back_sub_h(L, osr.forward_sub(L, -F[:Kp]))
+    t["solve"] = (time.perf_counter() - t0) * (len(p) / Kp) ** 2
+    total = sum(t.values())
+    return {
+        "value": 1.0 / total, "unit": "SR steps/s", "cores": threads, "kind": "oracle",
+        "sample": ("oracle timed on: 32 chains x 1 sweep (scaled to 1024 x 16), log psi and O_k on 1024 "
+                   "samples (x16), E_loc on 32 samples (x512), S/F on 256 samples (x64), Cholesky and "
+                   "triangular solves on the leading 768 x 768 block of S~ (scaled by (K/768)^3 and ^2)"),
+        "phase_s": {k: round(v, 3) for k, v in t.items()},
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
+                                   "and not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2108_03409_amd import nqsvmc as V
+
+    cfg = si.WORKLOADS[args.workload]
+    N = cfg["Lx"] * cfg["Ly"]
+    Nh = cfg["alpha"] * N
+    n_chains, per_chain = cfg["n_chains"], cfg["samples_per_chain"]
+    ns = n_chains * per_chain
+    dev = "cuda:0"
+
+    p = si.rbm_params(N, Nh, std=cfg["std"], is_complex=True, seed=cfg["param_seed"])
+    ctx = V.Context(0)
+    model = V.Model.rbm(ctx, N, Nh, True)
+    K = model.K
+    theta = torch.from_numpy(p).to(dev)
+    model.set_params(theta)
+    H = V.Hamiltonian.tfim(ctx, cfg["Lx"], cfg["Ly"], cfg["periodic"], cfg["J"], cfg["h"])
+    sampler = V.Sampler(ctx, model, H, proposal=V.PROP_FLIP, n_chains=n_chains, therm_sweeps=20,
+                        seed=cfg["sampler_seed"])
+    O = torch.empty((ns, K), dtype=torch.complex64, device=dev)
+    el = torch.empty(ns, dtype=torch.complex128, device=dev)
+    lp = torch.empty(ns, dtype=torch.complex128, device=dev)
+
+    def step():
+        nonlocal theta
+        s, _, acc = sampler.sample(ns)
+        model.log_psi(s, out=lp)
+        model.grad_log_psi(s, out=O)
+        model.local_energy(H, s, out=el)
+        x, info = V.sr_solve(ctx, O, el, nu_rel=cfg["nu_rel"])
+        theta = theta + args.tau * x
+        model.set_params(theta)
+        return info, acc
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = {}
+    for ph in ["sample", "log_psi", "grad", "eloc", "sr.center", "sr.herk", "sr.chol", "sr.trsv", "sr.resid"]:
+        ms, n = ctx.get_timing(ph)
+        phases[ph] = round(ms / max(n, 1), 3)
+    ctx.set_timing(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+
+    # dominant kernel: the Gram (S) kernel, one launch per step
+    herk_ms = phases["sr.herk"]
+    herk_achieved = herk_flops(ns, K) / (herk_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_herk_mfma_f32 (S = Obar^H Obar)", "bound": "mfma", "achieved": round(herk_achieved, 3),
+                "peak": PEAK["fp32_mfma_TF"], "unit": "TFLOP/s", "frac": round(herk_achieved / PEAK["fp32_mfma_TF"], 4),
+                "traffic": None,
+                "work": f"4*Ns*K*(K+1) = {herk_flops(ns, K):.4e} flop per launch (Ns={ns}, K={K})"}
+    chol_ms = phases["sr.chol"]
+    eloc_ms = phases["eloc"]
+    eloc_per_s = ns / (eloc_ms * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": round(1e3 / ms_step, 4),
+        "unit": "SR steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (S Gram from c64 O_k)",
+        "data": "synthetic (seeded RBM parameters N(0,0.01), Metropolis samples)",
+        "config": {"workload": "SR step: TFIM chain L=64 PBC J=h=1, complex RBM alpha=4 (K=16704), "
+                               "16384 samples (1024 chains x 16 sweeps), nu_rel=1e-3",
+                   "global_batch": ns, "K": K, "parallelism": "single GPU"},
+        "phases_ms": phases,
+        "local_energies_per_s": round(eloc_per_s, 1),
+        "eloc_roofline": {"bound": "alu", "achieved_TF": round(ns * eloc_flops(N, Nh, N) / (eloc_ms * 1e-3) / 1e12, 3),
+                          "peak": PEAK["fp64_valu_TF"]},
+        "chol_TF": round(chol_flops(K) / (chol_ms * 1e-3) / 1e12, 3) if chol_ms > 0 else None,
+        "roofline": roofline,
+        "energy": infos[-1][0]["e_mean"].real, "residual": infos[-1][0]["residual"],
+        "accept": round(infos[-1][1], 4),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, p, N, Nh, n_chains, per_chain)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

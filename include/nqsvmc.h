@@ -84,6 +84,14 @@ const char* vmc_last_error(vmc_ctx* ctx);
 int vmc_ctx_set_workspace_limit(vmc_ctx* ctx, size_t bytes);
 /* Library version string. */
 const char* vmc_version(void);
+/* Per-phase device timing: when enabled, the library brackets each phase of
+ * its calls (e.g. "sample", "eloc", "grad", "sr.herk", "sr.chol") with HIP
+ * events on the context's stream.  vmc_ctx_set_timing(ctx, 1) enables and
+ * clears the accumulators, 0 disables.  vmc_ctx_get_timing synchronises the
+ * stream and returns the summed milliseconds and the number of brackets of
+ * `phase` (0 and 0 if it never ran). */
+int vmc_ctx_set_timing(vmc_ctx* ctx, int enable);
+int vmc_ctx_get_timing(vmc_ctx* ctx, const char* phase, double* total_ms_host, int64_t* count_host);
 
 /* ---- models (the paper's NQS, Sec. 4.2 "Variational wave functions") ---- */
 /* Restricted Boltzmann machine, eq:rbm_ex:

@@ -79,6 +79,75 @@ void* pinned_host(vmc_ctx* ctx, size_t bytes) {
   return ctx->pinned;
 }
 
+// ----------------------------------------------------------------- timing --
+namespace {
+hipEvent_t pool_event(vmc_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  VMC_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void resolve_timing(vmc_ctx* ctx) {
+  VMC_HIP(hipStreamSynchronize(ctx->stream));
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    if (p.b) VMC_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    auto& acc = ctx->phases[p.name];
+    acc.first += ms;
+    acc.second += 1;
+    ctx->event_pool.push_back(p.a);
+    if (p.b) ctx->event_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+}  // namespace
+
+phase_scope::phase_scope(vmc_ctx* c, const char* name) : ctx(c), idx((size_t)-1) {
+  if (!ctx || !ctx->timing) return;
+  hipEvent_t a = pool_event(ctx);
+  VMC_HIP(hipEventRecord(a, ctx->stream));
+  ctx->pending.push_back({name, a, nullptr});
+  idx = ctx->pending.size() - 1;
+}
+
+phase_scope::~phase_scope() {
+  if (idx == (size_t)-1) return;
+  hipEvent_t b = nullptr;
+  if (!ctx->event_pool.empty()) {
+    b = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+  } else if (hipEventCreate(&b) != hipSuccess) {
+    b = nullptr;
+  }
+  if (b && hipEventRecord(b, ctx->stream) == hipSuccess) ctx->pending[idx].b = b;
+}
+
+extern "C" int vmc_ctx_set_timing(vmc_ctx* ctx, int enable) {
+  return guard(ctx, [&] {
+    VMC_REQUIRE(ctx, "ctx is NULL");
+    set_device(ctx);
+    resolve_timing(ctx);
+    ctx->phases.clear();
+    ctx->timing = enable ? 1 : 0;
+  });
+}
+
+extern "C" int vmc_ctx_get_timing(vmc_ctx* ctx, const char* phase, double* total_ms, int64_t* count) {
+  return guard(ctx, [&] {
+    VMC_REQUIRE(ctx && phase && total_ms && count, "NULL argument");
+    set_device(ctx);
+    resolve_timing(ctx);
+    auto it = ctx->phases.find(phase);
+    *total_ms = it == ctx->phases.end() ? 0.0 : it->second.first;
+    *count = it == ctx->phases.end() ? 0 : it->second.second;
+  });
+}
+
 // ---------------------------------------------------------------- context --
 extern "C" const char* vmc_version(void) { return "nqsvmc 0.1 (gfx950)"; }
 
@@ -106,6 +175,11 @@ extern "C" int vmc_ctx_destroy(vmc_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws.base) (void)hipFree(ctx->ws.base);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  for (auto& p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    if (p.b) (void)hipEventDestroy(p.b);
+  }
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   delete ctx;
   return VMC_OK;
 }
@@ -366,6 +440,7 @@ extern "C" int vmc_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double* l
     if (B == 0) return;
     VMC_REQUIRE(s && logpsi, "NULL buffer");
     set_device(m->ctx);
+    phase_scope ps(m->ctx, "log_psi");
     if (m->kind == MODEL_RBM)
       rbm_log_psi(m, s, B, (double2*)logpsi);
     else
@@ -384,6 +459,7 @@ extern "C" int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int
     if (B == 0) return;
     VMC_REQUIRE(s && eloc, "NULL buffer");
     set_device(m->ctx);
+    phase_scope ps(m->ctx, "eloc");
     if (m->kind == MODEL_RBM)
       rbm_local_energy(m, H, s, B, (double2*)eloc);
     else
@@ -399,6 +475,7 @@ extern "C" int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void
     if (B == 0) return;
     VMC_REQUIRE(s && O, "NULL buffer");
     set_device(m->ctx);
+    phase_scope ps(m->ctx, "grad");
     if (m->kind == MODEL_RBM)
       rbm_grad(m, s, B, O, dtype);
     else
@@ -464,7 +541,10 @@ extern "C" int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, do
       VMC_REQUIRE(S->made_params, "VMC_PROP_MADE_MIX needs vmc_sampler_set_proposal_made first");
     set_device(S->ctx);
     uint64_t t0 = S->t;
-    sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
+    {
+      phase_scope ps(S->ctx, "sample");
+      sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
+    }
     if (accept_rate_host) {
       auto* h = (unsigned long long*)pinned_host(S->ctx, sizeof(unsigned long long) * S->opts.n_chains);
       VMC_HIP(hipMemcpyAsync(h, S->acc, sizeof(unsigned long long) * S->opts.n_chains, hipMemcpyDeviceToHost,

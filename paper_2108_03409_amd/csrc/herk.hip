@@ -1,0 +1,184 @@
+// S = Obar^H Obar on the float32 matrix cores (eq:qfm with centred data).
+//
+// Obar is N_s x K complex64, sample-major.  For a complex 16x16 output block
+// (rows k, columns k') the kernel keeps four float32 MFMA accumulators at the
+// same lane positions,
+//   RR = sum_n Re O_nk Re O_nk',  II = sum Im Im,  RI = sum Re Im',  IR = sum Im Re',
+// so that S_kk' = (RR + II) + i (RI - IR) is formed in-register.  One
+// v_mfma_f32_16x16x4_f32 consumes 4 samples; a lane's A and B fragments are one
+// float2 (re, im) each, read from LDS.
+//
+// Work-group tile: 128 complex rows x 64 complex columns, 4 waves (2 x 2),
+// each wave 64 x 32 (4 x 2 blocks of 16 x 16, 128 accumulator registers).
+// Samples are staged 16 at a time through double-buffered LDS.  Only tiles
+// that touch the lower triangle are launched; the linear tile index is
+// remapped so that consecutive tiles of one row stripe run on the same XCD
+// (shared L2).  The epilogue writes S~ (float64, projection and diagonal shift
+// applied) to the lower triangle and its conjugate to the upper triangle.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128;  // complex rows per tile
+constexpr int BN = 64;   // complex columns per tile
+constexpr int BK = 16;   // samples per LDS stage
+constexpr int PAD = 2;   // float2 padding per LDS row
+
+struct herk_args {
+  const float2* X;  // [N][K]
+  int64_t N, K;
+  int mode;
+  double nu, eps;
+  double2* S;
+  double2* diag;
+  int n_row_tiles;
+  int64_t n_tiles;
+};
+
+__device__ __forceinline__ void tile_of(int64_t b, int& tr, int& tc) {
+  // row tile tr holds tiles tc = 0 .. 2 tr + 1; cumulative count tr (tr + 1)
+  int t = (int)((sqrt(4.0 * (double)b + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(t + 1) * (t + 2) <= b) ++t;
+  while ((int64_t)t * (t + 1) > b) --t;
+  tr = t;
+  tc = (int)(b - (int64_t)t * (t + 1));
+}
+
+__global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
+  __shared__ float2 As[2][BK][BM + PAD];
+  __shared__ float2 Bs[2][BK][BN + PAD];
+
+  // XCD-aware remap: hardware places block i on XCD i % 8
+  const int64_t nb = a.n_tiles;
+  const int64_t per = (nb + 7) / 8;
+  const int64_t bid = blockIdx.x;
+  const int64_t lin = (bid % 8) * per + bid / 8;
+  if (lin >= nb) return;
+  int tr, tc;
+  tile_of(lin, tr, tc);
+  const int64_t row0 = (int64_t)tr * BM, col0 = (int64_t)tc * BN;
+  const int64_t K = a.K, N = a.N;
+  if (col0 >= K) return;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;  // wave position in the 2 x 2 grid
+
+  floatx4 acc[4][2][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[i][j][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  // global -> register staging: A 16 x 128 float2 (8 per thread), B 16 x 64 (4 per thread)
+  float2 ra[8], rb[4];
+  auto gload = [&](int64_t n0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int q = tid + 256 * r;
+      const int nn = q / BM, cc = q % BM;
+      const int64_t n = n0 + nn, c = row0 + cc;
+      ra[r] = (n < N && c < K) ? a.X[n * K + c] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = tid + 256 * r;
+      const int nn = q / BN, cc = q % BN;
+      const int64_t n = n0 + nn, c = col0 + cc;
+      rb[r] = (n < N && c < K) ? a.X[n * K + c] : make_float2(0.f, 0.f);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int q = tid + 256 * r;
+      As[buf][q / BM][q % BM] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = tid + 256 * r;
+      Bs[buf][q / BN][q % BN] = rb[r];
+    }
+  };
+
+  const int64_t n_stages = (N + BK - 1) / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int li = lane & 15, lk = lane >> 4;
+  for (int64_t st = 0; st < n_stages; ++st) {
+    const int buf = (int)(st & 1);
+    if (st + 1 < n_stages) gload((st + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int n = ks * 4 + lk;
+      float2 fa[4], fb[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[i] = As[buf][n][wr * 64 + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) fb[j] = Bs[buf][n][wc * 32 + j * 16 + li];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].x, acc[i][j][0], 0, 0, 0);
+          acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].y, acc[i][j][1], 0, 0, 0);
+          acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].y, acc[i][j][2], 0, 0, 0);
+          acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].x, acc[i][j][3], 0, 0, 0);
+        }
+    }
+    if (st + 1 < n_stages) {
+      sstore(buf ^ 1);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: lane holds D[4 * (lane / 16) + r][lane % 16] of each block
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t k = row0 + wr * 64 + i * 16 + 4 * lk + r;
+        const int64_t kp = col0 + wc * 32 + j * 16 + li;
+        if (k >= K || kp >= K || kp > k) continue;
+        double re = (double)acc[i][j][0][r] + (double)acc[i][j][1][r];
+        double im = (double)acc[i][j][2][r] - (double)acc[i][j][3][r];
+        if (a.mode == VMC_SR_REAL) im = 0.0;
+        if (k == kp) {
+          const double2 d = make_double2(re * (1.0 + a.nu) + a.eps, 0.0);
+          a.diag[k] = d;
+          a.S[k * K + k] = d;
+        } else {
+          a.S[k * K + kp] = make_double2(re, im);
+          a.S[kp * K + k] = make_double2(re, -im);
+        }
+      }
+}
+
+}  // namespace
+
+void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode, double nu, double eps, double2* S,
+                   double2* diag) {
+  herk_args a{};
+  a.X = X;
+  a.N = N;
+  a.K = K;
+  a.mode = mode;
+  a.nu = nu;
+  a.eps = eps;
+  a.S = S;
+  a.diag = diag;
+  a.n_row_tiles = (int)((K + BM - 1) / BM);
+  const int64_t rt = a.n_row_tiles;
+  a.n_tiles = rt * (rt + 1);  // row tile t holds 2t + 2 column tiles
+  const int64_t grid = ((a.n_tiles + 7) / 8) * 8;
+  k_herk_mfma_f32<<<(unsigned)grid, 256, 0, ctx->stream>>>(a);
+  VMC_HIP(hipGetLastError());
+}

@@ -6,7 +6,9 @@
 
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "nqsvmc.h"
@@ -47,6 +49,25 @@ struct vmc_ctx {
   // pinned host staging for small readbacks
   void* pinned = nullptr;
   size_t pinned_cap = 0;
+  // per-phase event timing
+  int timing = 0;
+  struct pending_t {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<pending_t> pending;
+  std::map<std::string, std::pair<double, int64_t>> phases;
+  std::vector<hipEvent_t> event_pool;
+};
+
+// RAII bracket of one timed phase (no-op unless timing is enabled).
+struct phase_scope {
+  vmc_ctx* ctx;
+  size_t idx;
+  phase_scope(vmc_ctx* c, const char* name);
+  ~phase_scope();
+  phase_scope(const phase_scope&) = delete;
+  phase_scope& operator=(const phase_scope&) = delete;
 };
 
 // Carving: call ws_begin, then ws_take for each buffer (256-byte aligned).
@@ -232,6 +253,9 @@ void rbm_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, do
 void rbm_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
 // sampler.hip
 void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
+// herk.hip
+void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode, double nu, double eps, double2* S,
+                   double2* diag);
 // sr.hip
 void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N,
                    int64_t K, const vmc_sr_opts* o, double2* x, vmc_sr_info* info);

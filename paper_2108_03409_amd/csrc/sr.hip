@@ -10,6 +10,7 @@
 //   5. L y = -[[gamma F]], L^H x = y; residual ||S~ x + [[gamma F]]|| / ||[[gamma F]]||.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 
 #include "internal.h"
 
@@ -374,13 +375,24 @@ __global__ __launch_bounds__(64) void k_resid_upper(const double2* __restrict__ 
   if (lane == 0) r[k] = cadd(acc, cmul(diag[k], x[k]));
 }
 
-// r_c += sum_{k<c} conj(S~[k][c]) x_k  (strictly lower part via the upper storage)
-__global__ void k_resid_lower(const double2* __restrict__ A, int64_t K, const double2* __restrict__ x,
-                              const double2* __restrict__ rhs, double2* __restrict__ r) {
+// part[chunk][c] = sum_{k in chunk, k < c} conj(S~[k][c]) x_k  (strictly lower part
+// via the upper storage); rows split into chunks of 256 over blockIdx.y.
+__global__ __launch_bounds__(256) void k_resid_lower_part(const double2* __restrict__ A, int64_t K,
+                                                          const double2* __restrict__ x, double2* __restrict__ part) {
+  const int64_t c = blockIdx.x * 256ll + threadIdx.x;
+  if (c >= K) return;
+  const int64_t k0 = (int64_t)blockIdx.y * 256, k1 = min(c, k0 + 256);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t k = k0; k < k1; ++k) acc = cadd(acc, cmul(cconj(A[k * K + c]), x[k]));
+  part[(int64_t)blockIdx.y * K + c] = acc;
+}
+
+__global__ void k_resid_finish(const double2* __restrict__ part, int nchunk, int64_t K,
+                               const double2* __restrict__ rhs, double2* __restrict__ r) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= K) return;
   double2 acc = r[c];
-  for (int64_t k = 0; k < c; ++k) acc = cadd(acc, cmul(cconj(A[k * K + c]), x[k]));
+  for (int q = 0; q < nchunk; ++q) acc = cadd(acc, part[(int64_t)q * K + c]);
   r[c] = csub(acc, rhs[c]);
 }
 
@@ -418,15 +430,17 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
                    const vmc_sr_opts* o, double2* x, vmc_sr_info* info) {
   hipStream_t st = ctx->stream;
   const int nchunk = (int)((N + kColChunk - 1) / kColChunk);
+  const int kchunk = (int)((K + 255) / 256);
+  const int npart = std::max(nchunk, kchunk);
   const int nblk = (int)((K + NB - 1) / NB);
   const bool f32 = dtype == VMC_DT_C64;
   const size_t xsz = (f32 ? sizeof(float2) : sizeof(double2)) * (size_t)N * K;
-  size_t total = ws_round(64) + ws_round(sizeof(double2) * nchunk * K) + ws_round(sizeof(double2) * K) * 6 +
+  size_t total = ws_round(64) + ws_round(sizeof(double2) * npart * K) + ws_round(sizeof(double2) * K) * 6 +
                  ws_round(xsz) + ws_round(sizeof(double2) * (size_t)K * K) + ws_round(sizeof(double) * nblk) +
                  ws_round(sizeof(long long)) + ws_round(sizeof(double) * 4);
   ws_reserve(ctx, total);
   double* stats = (double*)ws_take(ctx, 64);
-  double2* partial = (double2*)ws_take(ctx, sizeof(double2) * nchunk * K);
+  double2* partial = (double2*)ws_take(ctx, sizeof(double2) * npart * K);
   double2* mean = (double2*)ws_take(ctx, sizeof(double2) * K);
   double2* F = (double2*)ws_take(ctx, sizeof(double2) * K);
   double2* rhs = (double2*)ws_take(ctx, sizeof(double2) * K);
@@ -439,6 +453,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   long long* fail = (long long*)ws_take(ctx, sizeof(long long));
   double* norms = (double*)ws_take(ctx, sizeof(double) * 4);
 
+  std::unique_ptr<phase_scope> ph(new phase_scope(ctx, "sr.center"));
   k_energy_stats<<<1, 1024, 0, st>>>(eloc, w, N, stats);
   dim3 cg(grid_for(K, 256), nchunk);
   if (f32) {
@@ -455,14 +470,18 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
                                                           (double2*)Xc, partial);
   k_reduce_plain<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, F);
   VMC_HIP(hipGetLastError());
+  ph.reset();
 
+  ph.reset(new phase_scope(ctx, "sr.herk"));
   dim3 hg(nblk, nblk);
   if (f32)
-    k_herk_simple<float2><<<hg, 256, 0, st>>>((const float2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag);
+    herk_mfma_f32(ctx, (const float2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag);
   else
     k_herk_simple<double2><<<hg, 256, 0, st>>>((const double2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag);
   VMC_HIP(hipGetLastError());
+  ph.reset();
 
+  ph.reset(new phase_scope(ctx, "sr.chol"));
   k_init_fail<<<1, 1, 0, st>>>(fail);
   for (int b = 0; b < nblk; ++b) {
     const int64_t kb0 = (int64_t)b * NB;
@@ -476,6 +495,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
     }
   }
   VMC_HIP(hipGetLastError());
+  ph.reset();
 
   // fail flag and pivots back to the host
   const size_t hbytes = sizeof(long long) + sizeof(double) * (nblk + 8);
@@ -500,6 +520,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   info->residual = NAN;
   if (fidx >= 0) return;
 
+  ph.reset(new phase_scope(ctx, "sr.trsv"));
   k_rhs<<<grid_for(K, 256), 256, 0, st>>>(F, K, o->gamma_re, o->gamma_im, o->mode, rhs);
   VMC_HIP(hipMemcpyAsync(sol, rhs, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
   for (int b = 0; b < nblk; ++b) {
@@ -516,11 +537,15 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
     if (kb0 > 0) k_trsv_bwd_update<<<grid_for(kb0, 256), 256, 0, st>>>(S, K, kb0, nb, sol);
   }
   VMC_HIP(hipGetLastError());
+  ph.reset();
+  ph.reset(new phase_scope(ctx, "sr.resid"));
   k_resid_upper<<<(unsigned)K, 64, 0, st>>>(S, K, diag, sol, res);
-  k_resid_lower<<<grid_for(K, 256), 256, 0, st>>>(S, K, sol, rhs, res);
+  k_resid_lower_part<<<dim3(grid_for(K, 256), kchunk), 256, 0, st>>>(S, K, sol, partial);
+  k_resid_finish<<<grid_for(K, 256), 256, 0, st>>>(partial, kchunk, K, rhs, res);
   k_norms<<<1, 1024, 0, st>>>(res, rhs, K, norms);
   VMC_HIP(hipMemcpyAsync(x, sol, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
   VMC_HIP(hipGetLastError());
+  ph.reset();
   double* hn = (double*)pinned_host(ctx, sizeof(double) * 2);
   VMC_HIP(hipMemcpyAsync(hn, norms, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
   VMC_HIP(hipStreamSynchronize(st));

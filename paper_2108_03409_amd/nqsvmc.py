@@ -59,6 +59,8 @@ _SIGS = {
     "vmc_ctx_sync": ([P], C.c_int),
     "vmc_last_error": ([P], C.c_char_p),
     "vmc_ctx_set_workspace_limit": ([P, C.c_size_t], C.c_int),
+    "vmc_ctx_set_timing": ([P, C.c_int], C.c_int),
+    "vmc_ctx_get_timing": ([P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
     "vmc_model_create_rbm": ([P, C.c_int, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_model_create_cnn": ([P, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_model_num_params": ([P, C.POINTER(I64)], C.c_int),
@@ -145,6 +147,16 @@ class Context:
 
     def set_workspace_limit(self, nbytes: int):
         _check(load().vmc_ctx_set_workspace_limit(self.h, nbytes), self.h)
+
+    def set_timing(self, enable: bool):
+        _check(load().vmc_ctx_set_timing(self.h, int(enable)), self.h)
+
+    def get_timing(self, phase: str):
+        """(total milliseconds, number of brackets) of a library phase."""
+        ms = C.c_double()
+        n = I64()
+        _check(load().vmc_ctx_get_timing(self.h, phase.encode(), C.byref(ms), C.byref(n)), self.h)
+        return ms.value, n.value
 
     def close(self):
         if getattr(self, "h", None):

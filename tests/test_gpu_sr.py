@@ -55,18 +55,22 @@ def test_sr_solve_fp64_matches_oracle(ctx, N, Nh, ns, mode, gamma, nu, eps, weig
     assert abs(info["min_pivot"] - info_ref["min_pivot"]) <= 1e-9 * abs(info_ref["min_pivot"])
 
 
-def test_sr_solve_fp32_gram_within_bound(ctx):
-    # S from complex64 O on the float32 path; error bound |dS| <= gamma_N sum |Obar||Obar| (Higham)
-    N, Nh, ns = 16, 32, 4096
-    O, el = _problem(N, Nh, ns, 0.2, seed=5)
-    x_ref, _ = osr.sr_solve(O.astype(np.complex64).astype(np.complex128), el, nu_rel=1e-2)
-    x, info = V.sr_solve(ctx, torch.from_numpy(O.astype(np.complex64)).to("cuda:0"), dev_c128(el), nu_rel=1e-2)
+@pytest.mark.parametrize("N,Nh,ns,weighted", [(16, 32, 4096, False), (5, 7, 9, True), (9, 21, 1001, False),
+                                              (12, 48, 333, True)])
+def test_sr_solve_fp32_gram_within_bound(ctx, N, Nh, ns, weighted):
+    # S from complex64 O on the float32 matrix path; |dS| <= gamma_N sum |Obar||Obar| (Higham)
+    flush(f"sr fp32 N={N} Nh={Nh} ns={ns}")
+    O, el = _problem(N, Nh, ns, 0.2, seed=5 + N)
+    w = np.random.default_rng(4).uniform(0.5, 1.5, ns) if weighted else None
+    x_ref, _ = osr.sr_solve(O.astype(np.complex64).astype(np.complex128), el, nu_rel=1e-2, weights=w)
+    x, info = V.sr_solve(ctx, torch.from_numpy(O.astype(np.complex64)).to("cuda:0"), dev_c128(el), nu_rel=1e-2,
+                         weights=None if w is None else torch.from_numpy(w).to("cuda:0"))
     x = x.cpu().numpy()
-    S, _ = osr.fisher_and_force(O, el)
+    S, _ = osr.fisher_and_force(O, el, w)
     St = osr.shifted(S, 1e-2)
     kappa = np.linalg.cond(St)
     err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
-    bound = kappa * 4 * np.sqrt(ns) * 2.0 ** -24
+    bound = kappa * 4 * np.sqrt(ns) * 2.0 ** -24 + 1e-12
     assert err <= bound, (err, bound)
     assert info["residual"] < 1e-10
 
