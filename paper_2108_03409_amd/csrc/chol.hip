@@ -1,0 +1,335 @@
+// Blocked right-looking Cholesky S~ = L L^H in float64 (lower triangle, row-major,
+// in place) and the two triangular solves, block size 64.
+//
+// Per 64-column panel b:
+//   k_chol_diag   one work-group factors the diagonal block in LDS (packed
+//                 lower triangle), writes L_bb, inverts it in place and writes
+//                 L_bb^{-1} (dense 64 x 64) to the Linv buffer;
+//   k_zmfma<0>    panel below: L_rb = A_rb L_bb^{-H}, a complex GEMM on the
+//                 float64 matrix cores (in place, one 64-row block per group);
+//   k_zmfma<1>    trailing update A_rc -= L_rb L_cb^H on the lower 64 x 64
+//                 tiles of the trailing matrix (float64 MFMA).
+// The complex products use four real accumulators per 16x16 block held in the
+// same lanes (RR, II, IR, RI), so re = RR + II and im = IR - RI are formed
+// in-register.  A non-positive pivot sets the fail index; every later kernel
+// then exits at once.  The upper triangle of S~ is never written.
+//
+// Triangular solves: one launch per block; every group recomputes the 64-entry
+// block solution from L_bb^{-1} (a 64 x 64 product) and then updates its share
+// of the remaining right-hand side.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+using namespace dev;
+
+namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int CB = 64;  // block size
+
+__device__ __forceinline__ int pk(int r, int c) { return r * (r + 1) / 2 + c; }  // packed lower index
+
+// Factor and invert the diagonal block at kb0 (nb <= 64 valid rows/cols; the
+// rest is padded with the identity).
+__global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
+                                                   double2* __restrict__ Linv, long long* __restrict__ fail,
+                                                   double* __restrict__ pivmin) {
+  __shared__ double2 L[CB * (CB + 1) / 2];
+  __shared__ double2 v[CB];
+  __shared__ int bad;
+  __shared__ double pmin;
+  if (*fail >= 0) return;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    if (c > r) continue;
+    double2 x;
+    if (r < nb)
+      x = A[(kb0 + r) * K + kb0 + c];
+    else
+      x = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    L[pk(r, c)] = x;
+  }
+  if (tid == 0) {
+    bad = 0;
+    pmin = INFINITY;
+  }
+  __syncthreads();
+  // right-looking factorisation
+  for (int j = 0; j < CB; ++j) {
+    if (tid == 0) {
+      const double d = L[pk(j, j)].x;
+      if (j < nb) {
+        pmin = fmin(pmin, d);
+        if (!(d > 0.0)) {
+          bad = 1;
+          *fail = kb0 + j;
+        }
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    const double l = sqrt(L[pk(j, j)].x);
+    const double il = 1.0 / l;
+    if (tid > j && tid < CB) L[pk(tid, j)] = cscale(L[pk(tid, j)], il);
+    __syncthreads();
+    if (tid == 0) L[pk(j, j)] = make_double2(l, 0.0);
+    const int m = CB - 1 - j;
+    for (int e = tid; e < m * m; e += 256) {
+      const int r = j + 1 + e / m, c = j + 1 + e % m;
+      if (c <= r) L[pk(r, c)] = csub(L[pk(r, c)], cmul(L[pk(r, j)], cconj(L[pk(c, j)])));
+    }
+    __syncthreads();
+  }
+  if (tid == 0) pivmin[kb0 / CB] = pmin;
+  if (bad) return;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    if (c <= r && r < nb) A[(kb0 + r) * K + kb0 + c] = L[pk(r, c)];
+  }
+  __syncthreads();
+  // in-place inverse, columns from the right:
+  //   Linv[j+1:, j] = -(1/l_jj) * Linv[j+1:, j+1:] * L[j+1:, j]
+  for (int j = CB - 1; j >= 0; --j) {
+    const int r = tid;
+    double2 acc = make_double2(0.0, 0.0);
+    if (r > j && r < CB)
+      for (int mm = j + 1; mm <= r; ++mm) acc = cadd(acc, cmul(L[pk(r, mm)], L[pk(mm, j)]));
+    __syncthreads();
+    const double d = 1.0 / L[pk(j, j)].x;
+    if (r > j && r < CB) L[pk(r, j)] = cscale(acc, -d);
+    __syncthreads();
+    if (tid == 0) L[pk(j, j)] = make_double2(d, 0.0);
+    __syncthreads();
+  }
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    Linv[e] = c <= r ? L[pk(r, c)] : make_double2(0.0, 0.0);
+  }
+  (void)v;
+}
+
+struct zargs {
+  double2* S;
+  int64_t K;
+  int64_t kb0;  // panel column start
+  int nb;       // valid panel width
+  int64_t base; // first output row (and column, for the update)
+  int64_t rows; // rows below the panel
+  const double2* Linv;
+  int nt;
+  int64_t ntiles;
+  const long long* fail;
+};
+
+// MODE 0 (panel solve):  S[r][kb0 + c] = sum_m A[r][kb0 + m] conj(Linv[c][m])
+// MODE 1 (trailing):     S[R][C] -= sum_m L[R][kb0 + m] conj(L[C][kb0 + m]),  C <= R
+template <int MODE>
+__global__ __launch_bounds__(256) void k_zmfma(zargs a) {
+  __shared__ double2 Ps[16][CB + 1];
+  __shared__ double2 Qs[16][CB + 1];
+  if (*a.fail >= 0) return;
+  const int64_t K = a.K;
+  int64_t r0, c0;
+  if (MODE == 0) {
+    r0 = a.base + (int64_t)blockIdx.x * CB;
+    c0 = 0;
+  } else {
+    const int64_t per = (a.ntiles + 7) / 8;
+    const int64_t lin = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (lin >= a.ntiles) return;
+    int tr = (int)((sqrt(8.0 * (double)lin + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(tr + 1) * (tr + 2) / 2 <= lin) ++tr;
+    while ((int64_t)tr * (tr + 1) / 2 > lin) --tr;
+    const int tc = (int)(lin - (int64_t)tr * (tr + 1) / 2);
+    r0 = a.base + (int64_t)tr * CB;
+    c0 = a.base + (int64_t)tc * CB;
+  }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+
+  doublex4 acc[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[i][j][q] = doublex4{0.0, 0.0, 0.0, 0.0};
+
+  for (int m0 = 0; m0 < CB; m0 += 16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = tid + 256 * j;
+      const int r = q >> 4, mm = q & 15;
+      const int m = m0 + mm;
+      const int64_t R = r0 + r;
+      Ps[mm][r] = (R < K && m < a.nb) ? a.S[R * K + a.kb0 + m] : make_double2(0.0, 0.0);
+      double2 qv;
+      if (MODE == 0) {
+        qv = a.Linv[r * CB + m];
+      } else {
+        const int64_t C = c0 + r;
+        qv = (C < K && m < a.nb) ? a.S[C * K + a.kb0 + m] : make_double2(0.0, 0.0);
+      }
+      Qs[mm][r] = qv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int m = ks * 4 + lk;
+      double2 fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) fa[i] = Ps[m][wr * 32 + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) fb[j] = Qs[m][wc * 32 + j * 16 + li];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].x, fb[j].x, acc[i][j][0], 0, 0, 0);
+          acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].y, acc[i][j][1], 0, 0, 0);
+          acc[i][j][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].x, acc[i][j][2], 0, 0, 0);
+          acc[i][j][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].x, fb[j].y, acc[i][j][3], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // float64 MFMA accumulators interleave rows: register r of lane l holds
+        // D[l / 16 + 4 r][l % 16] (float32 holds D[4 (l / 16) + r][l % 16])
+        const int row = wr * 32 + i * 16 + lk + 4 * r;
+        const int col = wc * 32 + j * 16 + li;
+        const double re = acc[i][j][0][r] + acc[i][j][1][r];
+        const double im = acc[i][j][2][r] - acc[i][j][3][r];
+        const int64_t R = r0 + row;
+        if (R >= K) continue;
+        if (MODE == 0) {
+          if (col < a.nb) a.S[R * K + a.kb0 + col] = make_double2(re, im);
+        } else {
+          const int64_t C = c0 + col;
+          if (C < K && C <= R) {
+            double2 v = a.S[R * K + C];
+            a.S[R * K + C] = make_double2(v.x - re, v.y - im);
+          }
+        }
+      }
+}
+
+// forward step of block b: y_b = Linv_b rhs_b; rhs[R] -= sum_m L[R][kb0+m] y_b[m] for R >= kb0 + 64
+__global__ __launch_bounds__(256) void k_fwd_step(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
+                                                  const double2* __restrict__ Linv, double2* __restrict__ rhs,
+                                                  double2* __restrict__ y) {
+  __shared__ double2 yb[CB];
+  __shared__ double2 part[4][CB];
+  const int tid = threadIdx.x;
+  {
+    const int r = tid & 63, q = tid >> 6;  // 4 partial sums over m per row
+    double2 acc = make_double2(0.0, 0.0);
+    for (int m = q; m <= r; m += 4)
+      if (m < nb) acc = cadd(acc, cmul(Linv[r * CB + m], rhs[kb0 + m]));
+    part[q][r] = acc;
+  }
+  __syncthreads();
+  if (tid < CB) {
+    const double2 s = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
+    yb[tid] = tid < nb ? s : make_double2(0.0, 0.0);
+    if (blockIdx.x == 0 && tid < nb) y[kb0 + tid] = s;
+  }
+  __syncthreads();
+  const int64_t R = kb0 + CB + (int64_t)blockIdx.x * 256 + tid;
+  if (R >= K) return;
+  const double2* row = A + R * K + kb0;
+  double2 acc = rhs[R];
+  for (int m = 0; m < nb; ++m) acc = csub(acc, cmul(row[m], yb[m]));
+  rhs[R] = acc;
+}
+
+// backward step of block b: x_b = Linv_b^H v_b; v[c] -= sum_m conj(L[kb0+m][c]) x_b[m] for c < kb0
+__global__ __launch_bounds__(256) void k_bwd_step(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
+                                                  const double2* __restrict__ Linv, double2* __restrict__ v,
+                                                  double2* __restrict__ x) {
+  __shared__ double2 xb[CB];
+  __shared__ double2 part[4][CB];
+  const int tid = threadIdx.x;
+  {
+    const int r = tid & 63, q = tid >> 6;
+    double2 acc = make_double2(0.0, 0.0);
+    // (Linv^H)[r][m] = conj(Linv[m][r]), non-zero for m >= r
+    for (int m = r + q; m < nb; m += 4) acc = cadd(acc, cmul(cconj(Linv[m * CB + r]), v[kb0 + m]));
+    part[q][r] = acc;
+  }
+  __syncthreads();
+  if (tid < CB) {
+    const double2 s = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
+    xb[tid] = tid < nb ? s : make_double2(0.0, 0.0);
+    if (blockIdx.x == 0 && tid < nb) x[kb0 + tid] = s;
+  }
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * 256 + tid;
+  if (c >= kb0) return;
+  double2 acc = v[c];
+  for (int m = 0; m < nb; ++m) acc = csub(acc, cmul(cconj(A[(kb0 + m) * K + c]), xb[m]));
+  v[c] = acc;
+}
+
+}  // namespace
+
+size_t chol_linv_bytes(int64_t K) { return sizeof(double2) * (size_t)((K + CB - 1) / CB) * CB * CB; }
+int chol_block() { return CB; }
+
+void chol_factor(vmc_ctx* ctx, double2* S, int64_t K, double2* Linv, long long* fail, double* pivmin) {
+  hipStream_t st = ctx->stream;
+  const int nblk = (int)((K + CB - 1) / CB);
+  for (int b = 0; b < nblk; ++b) {
+    const int64_t kb0 = (int64_t)b * CB;
+    const int nb = (int)std::min<int64_t>(CB, K - kb0);
+    double2* Lb = Linv + (size_t)b * CB * CB;
+    k_chol_diag<<<1, 256, 0, st>>>(S, K, kb0, nb, Lb, fail, pivmin);
+    const int64_t rest = K - kb0 - nb;
+    if (rest <= 0) continue;
+    zargs a{};
+    a.S = S;
+    a.K = K;
+    a.kb0 = kb0;
+    a.nb = nb;
+    a.base = kb0 + nb;
+    a.rows = rest;
+    a.Linv = Lb;
+    a.fail = fail;
+    k_zmfma<0><<<(unsigned)((rest + CB - 1) / CB), 256, 0, st>>>(a);
+    a.nt = (int)((rest + CB - 1) / CB);
+    a.ntiles = (int64_t)a.nt * (a.nt + 1) / 2;
+    k_zmfma<1><<<(unsigned)(((a.ntiles + 7) / 8) * 8), 256, 0, st>>>(a);
+  }
+  VMC_HIP(hipGetLastError());
+}
+
+// rhs is consumed; y and x are K-vectors; x receives the solution
+void chol_solve(vmc_ctx* ctx, const double2* S, int64_t K, const double2* Linv, double2* rhs, double2* y, double2* x) {
+  hipStream_t st = ctx->stream;
+  const int nblk = (int)((K + CB - 1) / CB);
+  for (int b = 0; b < nblk; ++b) {
+    const int64_t kb0 = (int64_t)b * CB;
+    const int nb = (int)std::min<int64_t>(CB, K - kb0);
+    const int64_t rest = std::max<int64_t>(0, K - kb0 - CB);
+    k_fwd_step<<<(unsigned)std::max<int64_t>(1, (rest + 255) / 256), 256, 0, st>>>(S, K, kb0, nb,
+                                                                                   Linv + (size_t)b * CB * CB, rhs, y);
+  }
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int64_t kb0 = (int64_t)b * CB;
+    const int nb = (int)std::min<int64_t>(CB, K - kb0);
+    k_bwd_step<<<(unsigned)std::max<int64_t>(1, (kb0 + 255) / 256), 256, 0, st>>>(S, K, kb0, nb,
+                                                                                  Linv + (size_t)b * CB * CB, y, x);
+  }
+  VMC_HIP(hipGetLastError());
+}

@@ -19,7 +19,6 @@ using namespace dev;
 namespace {
 
 constexpr int kColChunk = 256;  // samples per partial-sum chunk
-constexpr int NB = 32;          // Cholesky / triangular-solve block size
 
 template <typename InT>
 __device__ __forceinline__ double2 load_c(const InT* p, int64_t i) {
@@ -198,161 +197,6 @@ __global__ __launch_bounds__(256) void k_herk_simple(const XT* __restrict__ X, i
     }
 }
 
-// ---- Cholesky ----------------------------------------------------------
-__global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
-                                                   long long* __restrict__ fail, double* __restrict__ pivmin) {
-  __shared__ double2 a[NB][NB + 1];
-  __shared__ int bad;
-  __shared__ double pmin;
-  if (*fail >= 0) return;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    a[r][c] = (r < nb && c <= r) ? A[(kb0 + r) * K + kb0 + c] : make_double2(0.0, 0.0);
-  }
-  if (tid == 0) {
-    bad = 0;
-    pmin = INFINITY;
-  }
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    const double d = a[j][j].x;
-    if (tid == 0) {
-      pmin = fmin(pmin, d);
-      if (!(d > 0.0)) {
-        bad = 1;
-        *fail = kb0 + j;
-      }
-    }
-    __syncthreads();
-    if (bad) break;
-    const double l = sqrt(d);
-    if (tid > j && tid < nb) a[tid][j] = cscale(a[tid][j], 1.0 / l);
-    __syncthreads();
-    if (tid == 0) a[j][j] = make_double2(l, 0.0);
-    const int m = nb - j - 1;
-    for (int e = tid; e < m * m; e += 256) {
-      const int r = j + 1 + e / m, c = j + 1 + e % m;
-      if (c <= r) a[r][c] = csub(a[r][c], cmul(a[r][j], cconj(a[c][j])));
-    }
-    __syncthreads();
-  }
-  if (tid == 0) pivmin[kb0 / NB] = pmin;
-  if (bad) return;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    if (r < nb && c <= r) A[(kb0 + r) * K + kb0 + c] = a[r][c];
-  }
-}
-
-// rows below the diagonal block: X L_kk^H = A  ->  X
-__global__ __launch_bounds__(64) void k_chol_trsm(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
-                                                  const long long* __restrict__ fail) {
-  __shared__ double2 L[NB][NB + 1];
-  __shared__ double2 X[64][NB + 1];
-  if (*fail >= 0) return;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 64) {
-    const int r = e / NB, c = e % NB;
-    L[r][c] = (r < nb && c <= r) ? A[(kb0 + r) * K + kb0 + c] : make_double2(0.0, 0.0);
-  }
-  const int64_t row = kb0 + nb + (int64_t)blockIdx.x * 64 + tid;
-  const bool live = row < K;
-  for (int c = 0; c < nb; ++c) X[tid][c] = live ? A[row * K + kb0 + c] : make_double2(0.0, 0.0);
-  __syncthreads();
-  if (!live) return;
-  for (int j = 0; j < nb; ++j) {
-    double2 v = X[tid][j];
-    for (int m = 0; m < j; ++m) v = csub(v, cmul(X[tid][m], cconj(L[j][m])));
-    X[tid][j] = cscale(v, 1.0 / L[j][j].x);
-  }
-  for (int c = 0; c < nb; ++c) A[row * K + kb0 + c] = X[tid][c];
-}
-
-// trailing update A[r][c] -= sum_m L[r][kb0+m] conj(L[c][kb0+m]) on the lower triangle
-__global__ __launch_bounds__(256) void k_chol_update(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
-                                                     const long long* __restrict__ fail) {
-  if (*fail >= 0) return;
-  const int tr = blockIdx.y, tc = blockIdx.x;
-  if (tc > tr) return;
-  const int64_t base = kb0 + nb;
-  const int64_t r0 = base + (int64_t)tr * 32, c0 = base + (int64_t)tc * 32;
-  __shared__ double2 pa[32][NB + 1], pb[32][NB + 1];
-  for (int e = threadIdx.x; e < 32 * NB; e += 256) {
-    const int rr = e / NB, m = e % NB;
-    pa[rr][m] = (r0 + rr < K && m < nb) ? A[(r0 + rr) * K + kb0 + m] : make_double2(0.0, 0.0);
-    pb[rr][m] = (c0 + rr < K && m < nb) ? A[(c0 + rr) * K + kb0 + m] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double2 acc[2][2] = {};
-  for (int m = 0; m < nb; ++m) {
-    const double2 a0 = pa[ty][m], a1 = pa[ty + 16][m];
-    const double2 b0 = cconj(pb[tx][m]), b1 = cconj(pb[tx + 16][m]);
-    acc[0][0] = cadd(acc[0][0], cmul(a0, b0));
-    acc[0][1] = cadd(acc[0][1], cmul(a0, b1));
-    acc[1][0] = cadd(acc[1][0], cmul(a1, b0));
-    acc[1][1] = cadd(acc[1][1], cmul(a1, b1));
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
-      if (r < K && c < K && c <= r) A[r * K + c] = csub(A[r * K + c], acc[i][j]);
-    }
-}
-
-// ---- triangular solves -------------------------------------------------
-// y_kb = L_kk^{-1} b_kb (in place in b)
-__global__ void k_trsv_fwd_diag(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb, double2* __restrict__ b) {
-  __shared__ double2 y[NB];
-  const int tid = threadIdx.x;
-  if (tid < nb) y[tid] = b[kb0 + tid];
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (tid == j) y[j] = cscale(y[j], 1.0 / A[(kb0 + j) * K + kb0 + j].x);
-    __syncthreads();
-    if (tid > j && tid < nb) y[tid] = csub(y[tid], cmul(A[(kb0 + tid) * K + kb0 + j], y[j]));
-    __syncthreads();
-  }
-  if (tid < nb) b[kb0 + tid] = y[tid];
-}
-
-// b[r] -= sum_m L[r][kb0+m] y[kb0+m] for rows r >= kb0 + nb
-__global__ void k_trsv_fwd_update(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb, double2* __restrict__ b) {
-  const int64_t r = kb0 + nb + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= K) return;
-  double2 acc = b[r];
-  for (int m = 0; m < nb; ++m) acc = csub(acc, cmul(A[r * K + kb0 + m], b[kb0 + m]));
-  b[r] = acc;
-}
-
-// x_kb = L_kk^{-H} y_kb (in place)
-__global__ void k_trsv_bwd_diag(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb, double2* __restrict__ b) {
-  __shared__ double2 y[NB];
-  const int tid = threadIdx.x;
-  if (tid < nb) y[tid] = b[kb0 + tid];
-  __syncthreads();
-  for (int j = nb - 1; j >= 0; --j) {
-    if (tid == j) y[j] = cscale(y[j], 1.0 / A[(kb0 + j) * K + kb0 + j].x);
-    __syncthreads();
-    // (L^H)[i][j] = conj(L[j][i]) for i < j
-    if (tid < j) y[tid] = csub(y[tid], cmul(cconj(A[(kb0 + j) * K + kb0 + tid]), y[j]));
-    __syncthreads();
-  }
-  if (tid < nb) b[kb0 + tid] = y[tid];
-}
-
-// b[c] -= sum_m conj(L[kb0+m][c]) x[kb0+m] for columns c < kb0
-__global__ void k_trsv_bwd_update(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb, double2* __restrict__ b) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= kb0) return;
-  double2 acc = b[c];
-  for (int m = 0; m < nb; ++m) acc = csub(acc, cmul(cconj(A[(kb0 + m) * K + c]), b[kb0 + m]));
-  b[c] = acc;
-}
-
 // rhs = -[[gamma F]]
 __global__ void k_rhs(const double2* __restrict__ F, int64_t K, double gr, double gi, int mode, double2* __restrict__ rhs) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -432,10 +276,12 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   const int nchunk = (int)((N + kColChunk - 1) / kColChunk);
   const int kchunk = (int)((K + 255) / 256);
   const int npart = std::max(nchunk, kchunk);
-  const int nblk = (int)((K + NB - 1) / NB);
+  const int CB = chol_block();
+  const int nblk = (int)((K + CB - 1) / CB);
   const bool f32 = dtype == VMC_DT_C64;
   const size_t xsz = (f32 ? sizeof(float2) : sizeof(double2)) * (size_t)N * K;
-  size_t total = ws_round(64) + ws_round(sizeof(double2) * npart * K) + ws_round(sizeof(double2) * K) * 6 +
+  size_t total = ws_round(64) + ws_round(sizeof(double2) * npart * K) + ws_round(sizeof(double2) * K) * 7 +
+                 ws_round(chol_linv_bytes(K)) +
                  ws_round(xsz) + ws_round(sizeof(double2) * (size_t)K * K) + ws_round(sizeof(double) * nblk) +
                  ws_round(sizeof(long long)) + ws_round(sizeof(double) * 4);
   ws_reserve(ctx, total);
@@ -447,6 +293,8 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   double2* sol = (double2*)ws_take(ctx, sizeof(double2) * K);
   double2* diag = (double2*)ws_take(ctx, sizeof(double2) * K);
   double2* res = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* yv = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* Linv = (double2*)ws_take(ctx, chol_linv_bytes(K));
   void* Xc = ws_take(ctx, xsz);
   double2* S = (double2*)ws_take(ctx, sizeof(double2) * (size_t)K * K);
   double* pivmin = (double*)ws_take(ctx, sizeof(double) * nblk);
@@ -473,7 +321,8 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   ph.reset();
 
   ph.reset(new phase_scope(ctx, "sr.herk"));
-  dim3 hg(nblk, nblk);
+  const unsigned nb32 = (unsigned)((K + 31) / 32);
+  dim3 hg(nb32, nb32);
   if (f32)
     herk_mfma_f32(ctx, (const float2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag);
   else
@@ -483,17 +332,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
 
   ph.reset(new phase_scope(ctx, "sr.chol"));
   k_init_fail<<<1, 1, 0, st>>>(fail);
-  for (int b = 0; b < nblk; ++b) {
-    const int64_t kb0 = (int64_t)b * NB;
-    const int nb = (int)std::min<int64_t>(NB, K - kb0);
-    k_chol_diag<<<1, 256, 0, st>>>(S, K, kb0, nb, fail, pivmin);
-    const int64_t rest = K - kb0 - nb;
-    if (rest > 0) {
-      k_chol_trsm<<<grid_for(rest, 64), 64, 0, st>>>(S, K, kb0, nb, fail);
-      const int nt = (int)((rest + 31) / 32);
-      k_chol_update<<<dim3(nt, nt), 256, 0, st>>>(S, K, kb0, nb, fail);
-    }
-  }
+  chol_factor(ctx, S, K, Linv, fail, pivmin);
   VMC_HIP(hipGetLastError());
   ph.reset();
 
@@ -513,7 +352,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   info->e_mean[1] = hs[2];
   info->e_var = hs[3];
   info->fail_index = fidx;
-  const int nb_done = fidx >= 0 ? (int)(fidx / NB) + 1 : nblk;
+  const int nb_done = fidx >= 0 ? (int)(fidx / CB) + 1 : nblk;
   double pm = INFINITY;
   for (int b = 0; b < nb_done; ++b) pm = std::min(pm, piv[b]);
   info->min_pivot = pm;
@@ -522,20 +361,8 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
 
   ph.reset(new phase_scope(ctx, "sr.trsv"));
   k_rhs<<<grid_for(K, 256), 256, 0, st>>>(F, K, o->gamma_re, o->gamma_im, o->mode, rhs);
-  VMC_HIP(hipMemcpyAsync(sol, rhs, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
-  for (int b = 0; b < nblk; ++b) {
-    const int64_t kb0 = (int64_t)b * NB;
-    const int nb = (int)std::min<int64_t>(NB, K - kb0);
-    k_trsv_fwd_diag<<<1, 64, 0, st>>>(S, K, kb0, nb, sol);
-    const int64_t rest = K - kb0 - nb;
-    if (rest > 0) k_trsv_fwd_update<<<grid_for(rest, 256), 256, 0, st>>>(S, K, kb0, nb, sol);
-  }
-  for (int b = nblk - 1; b >= 0; --b) {
-    const int64_t kb0 = (int64_t)b * NB;
-    const int nb = (int)std::min<int64_t>(NB, K - kb0);
-    k_trsv_bwd_diag<<<1, 64, 0, st>>>(S, K, kb0, nb, sol);
-    if (kb0 > 0) k_trsv_bwd_update<<<grid_for(kb0, 256), 256, 0, st>>>(S, K, kb0, nb, sol);
-  }
+  VMC_HIP(hipMemcpyAsync(res, rhs, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
+  chol_solve(ctx, S, K, Linv, res, yv, sol);
   VMC_HIP(hipGetLastError());
   ph.reset();
   ph.reset(new phase_scope(ctx, "sr.resid"));
