@@ -1,14 +1,18 @@
 // Blocked right-looking Cholesky S~ = L L^H in float64 (lower triangle, row-major,
 // in place) and the two triangular solves, block size 64.
 //
-// Per 64-column panel b:
+// Two levels: 256-column panels, each factored as four 64-column blocks.
+// Per 64-column block b:
 //   k_chol_diag   one work-group factors the diagonal block in LDS (packed
-//                 lower triangle), writes L_bb, inverts it in place and writes
+//                 lower triangle), writes L_bb, inverts it and writes
 //                 L_bb^{-1} (dense 64 x 64) to the Linv buffer;
-//   k_zmfma<0>    panel below: L_rb = A_rb L_bb^{-H}, a complex GEMM on the
+//   k_zmfma<0>    rows below: L_rb = A_rb L_bb^{-H}, a complex GEMM on the
 //                 float64 matrix cores (in place, one 64-row block per group);
-//   k_zmfma<1>    trailing update A_rc -= L_rb L_cb^H on the lower 64 x 64
-//                 tiles of the trailing matrix (float64 MFMA).
+//   k_zmfma<2>    the rest of the panel's columns: A_rc -= L_rb L_cb^H.
+// Per panel p, once its four blocks are done:
+//   k_zmfma<1>    trailing update A_rc -= L_rp L_cp^H (reduction depth 256) on
+//                 the lower 64 x 64 tiles of the trailing matrix, so the
+//                 trailing matrix is read and written once per 256 columns.
 // The complex products use four real accumulators per 16x16 block held in the
 // same lanes (RR, II, IR, RI), so re = RR + II and im = IR - RI are formed
 // in-register.  A non-positive pivot sets the fail index; every later kernel
@@ -34,12 +38,11 @@ constexpr int CB = 64;  // block size
 __device__ __forceinline__ int pk(int r, int c) { return r * (r + 1) / 2 + c; }  // packed lower index
 
 // Factor and invert the diagonal block at kb0 (nb <= 64 valid rows/cols; the
-// rest is padded with the identity).
+// rest is padded with the identity).  LDS holds the packed lower triangle.
 __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
                                                    double2* __restrict__ Linv, long long* __restrict__ fail,
                                                    double* __restrict__ pivmin) {
   __shared__ double2 L[CB * (CB + 1) / 2];
-  __shared__ double2 v[CB];
   __shared__ int bad;
   __shared__ double pmin;
   if (*fail >= 0) return;
@@ -59,7 +62,8 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int6
     pmin = INFINITY;
   }
   __syncthreads();
-  // right-looking factorisation
+  // right-looking factorisation; thread (ty, tx) updates rows ty + 16a, columns tx + 16b
+  const int ty = tid >> 4, tx = tid & 15;
   for (int j = 0; j < CB; ++j) {
     if (tid == 0) {
       const double d = L[pk(j, j)].x;
@@ -78,10 +82,16 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int6
     if (tid > j && tid < CB) L[pk(tid, j)] = cscale(L[pk(tid, j)], il);
     __syncthreads();
     if (tid == 0) L[pk(j, j)] = make_double2(l, 0.0);
-    const int m = CB - 1 - j;
-    for (int e = tid; e < m * m; e += 256) {
-      const int r = j + 1 + e / m, c = j + 1 + e % m;
-      if (c <= r) L[pk(r, c)] = csub(L[pk(r, c)], cmul(L[pk(r, j)], cconj(L[pk(c, j)])));
+#pragma unroll
+    for (int aa = 0; aa < 4; ++aa) {
+      const int r = ty + 16 * aa;
+      if (r <= j) continue;
+      const double2 lr = L[pk(r, j)];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const int c = tx + 16 * bb;
+        if (c > j && c <= r) L[pk(r, c)] = csub(L[pk(r, c)], cmul(lr, cconj(L[pk(c, j)])));
+      }
     }
     __syncthreads();
   }
@@ -92,53 +102,62 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int6
     if (c <= r && r < nb) A[(kb0 + r) * K + kb0 + c] = L[pk(r, c)];
   }
   __syncthreads();
-  // in-place inverse, columns from the right:
-  //   Linv[j+1:, j] = -(1/l_jj) * Linv[j+1:, j+1:] * L[j+1:, j]
-  for (int j = CB - 1; j >= 0; --j) {
-    const int r = tid;
+  // inverse X = L^{-1} by rows: X[r][c] = -(1/L_rr) sum_{m=c}^{r-1} L[r][m] X[m][c];
+  // row r of X overwrites row r of L once computed (rows < r already hold X).
+  // Four threads per column split the sum over m and combine by lane shuffles.
+  const int cc = tid >> 2, qq = tid & 3;
+  if (tid == 0) L[pk(0, 0)] = make_double2(1.0 / L[pk(0, 0)].x, 0.0);
+  __syncthreads();
+  for (int r = 1; r < CB; ++r) {
     double2 acc = make_double2(0.0, 0.0);
-    if (r > j && r < CB)
-      for (int mm = j + 1; mm <= r; ++mm) acc = cadd(acc, cmul(L[pk(r, mm)], L[pk(mm, j)]));
+    if (cc < r)
+      for (int m = cc + qq; m < r; m += 4) acc = cadd(acc, cmul(L[pk(r, m)], L[pk(m, cc)]));
+    acc.x += __shfl_xor(acc.x, 1, 64);
+    acc.y += __shfl_xor(acc.y, 1, 64);
+    acc.x += __shfl_xor(acc.x, 2, 64);
+    acc.y += __shfl_xor(acc.y, 2, 64);
+    const double d = 1.0 / L[pk(r, r)].x;
     __syncthreads();
-    const double d = 1.0 / L[pk(j, j)].x;
-    if (r > j && r < CB) L[pk(r, j)] = cscale(acc, -d);
-    __syncthreads();
-    if (tid == 0) L[pk(j, j)] = make_double2(d, 0.0);
+    if (qq == 0 && cc < r) L[pk(r, cc)] = cscale(acc, -d);
+    if (tid == 0) L[pk(r, r)] = make_double2(d, 0.0);
     __syncthreads();
   }
   for (int e = tid; e < CB * CB; e += 256) {
     const int r = e / CB, c = e % CB;
     Linv[e] = c <= r ? L[pk(r, c)] : make_double2(0.0, 0.0);
   }
-  (void)v;
 }
 
 struct zargs {
   double2* S;
   int64_t K;
-  int64_t kb0;  // panel column start
-  int nb;       // valid panel width
-  int64_t base; // first output row (and column, for the update)
-  int64_t rows; // rows below the panel
+  int64_t kb0;   // first panel column of the reduction
+  int depth;     // valid panel columns (reduction length)
+  int64_t rbase; // first output row
+  int64_t cbase; // first output column
+  int64_t cend;  // one past the last output column (MODE 2)
+  int nct;       // column tiles (MODE 2)
   const double2* Linv;
-  int nt;
   int64_t ntiles;
   const long long* fail;
 };
 
-// MODE 0 (panel solve):  S[r][kb0 + c] = sum_m A[r][kb0 + m] conj(Linv[c][m])
-// MODE 1 (trailing):     S[R][C] -= sum_m L[R][kb0 + m] conj(L[C][kb0 + m]),  C <= R
+// MODE 0 (panel solve):   S[R][kb0 + c] = sum_m S[R][kb0 + m] conj(Linv[c][m]),  R = rbase + 64 b + r
+// MODE 1 (trailing):      S[R][C] -= sum_m S[R][kb0 + m] conj(S[C][kb0 + m]) on lower 64x64 tiles of
+//                         the square region starting at (rbase, rbase), C <= R
+// MODE 2 (inside panel):  as MODE 1 for R >= rbase, cbase <= C < cend, C <= R (rectangular tile grid)
+// The reduction is staged 16 columns at a time through double-buffered LDS.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_zmfma(zargs a) {
-  __shared__ double2 Ps[16][CB + 1];
-  __shared__ double2 Qs[16][CB + 1];
+  __shared__ double2 Ps[2][16][CB + 1];
+  __shared__ double2 Qs[2][16][CB + 1];
   if (*a.fail >= 0) return;
   const int64_t K = a.K;
   int64_t r0, c0;
   if (MODE == 0) {
-    r0 = a.base + (int64_t)blockIdx.x * CB;
+    r0 = a.rbase + (int64_t)blockIdx.x * CB;
     c0 = 0;
-  } else {
+  } else if (MODE == 1) {
     const int64_t per = (a.ntiles + 7) / 8;
     const int64_t lin = (blockIdx.x % 8) * per + blockIdx.x / 8;
     if (lin >= a.ntiles) return;
@@ -146,8 +165,11 @@ __global__ __launch_bounds__(256) void k_zmfma(zargs a) {
     while ((int64_t)(tr + 1) * (tr + 2) / 2 <= lin) ++tr;
     while ((int64_t)tr * (tr + 1) / 2 > lin) --tr;
     const int tc = (int)(lin - (int64_t)tr * (tr + 1) / 2);
-    r0 = a.base + (int64_t)tr * CB;
-    c0 = a.base + (int64_t)tc * CB;
+    r0 = a.rbase + (int64_t)tr * CB;
+    c0 = a.rbase + (int64_t)tc * CB;
+  } else {
+    r0 = a.rbase + (int64_t)(blockIdx.x / a.nct) * CB;
+    c0 = a.cbase + (int64_t)(blockIdx.x % a.nct) * CB;
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -161,32 +183,46 @@ __global__ __launch_bounds__(256) void k_zmfma(zargs a) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[i][j][q] = doublex4{0.0, 0.0, 0.0, 0.0};
 
-  for (int m0 = 0; m0 < CB; m0 += 16) {
+  double2 rp[4], rq[4];
+  auto gload = [&](int m0) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int q = tid + 256 * j;
       const int r = q >> 4, mm = q & 15;
       const int m = m0 + mm;
       const int64_t R = r0 + r;
-      Ps[mm][r] = (R < K && m < a.nb) ? a.S[R * K + a.kb0 + m] : make_double2(0.0, 0.0);
-      double2 qv;
+      rp[j] = (R < K && m < a.depth) ? a.S[R * K + a.kb0 + m] : make_double2(0.0, 0.0);
       if (MODE == 0) {
-        qv = a.Linv[r * CB + m];
+        rq[j] = a.Linv[r * CB + m];
       } else {
         const int64_t C = c0 + r;
-        qv = (C < K && m < a.nb) ? a.S[C * K + a.kb0 + m] : make_double2(0.0, 0.0);
+        rq[j] = (C < K && m < a.depth) ? a.S[C * K + a.kb0 + m] : make_double2(0.0, 0.0);
       }
-      Qs[mm][r] = qv;
     }
-    __syncthreads();
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = tid + 256 * j;
+      Ps[buf][q & 15][q >> 4] = rp[j];
+      Qs[buf][q & 15][q >> 4] = rq[j];
+    }
+  };
+  const int nst = (a.depth + 15) / 16;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) gload((st + 1) * 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int m = ks * 4 + lk;
       double2 fa[2], fb[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) fa[i] = Ps[m][wr * 32 + i * 16 + li];
+      for (int i = 0; i < 2; ++i) fa[i] = Ps[buf][m][wr * 32 + i * 16 + li];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) fb[j] = Qs[m][wc * 32 + j * 16 + li];
+      for (int j = 0; j < 2; ++j) fb[j] = Qs[buf][m][wc * 32 + j * 16 + li];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -197,6 +233,7 @@ __global__ __launch_bounds__(256) void k_zmfma(zargs a) {
           acc[i][j][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].x, fb[j].y, acc[i][j][3], 0, 0, 0);
         }
     }
+    if (st + 1 < nst) sstore(buf ^ 1);
     __syncthreads();
   }
 #pragma unroll
@@ -214,11 +251,11 @@ __global__ __launch_bounds__(256) void k_zmfma(zargs a) {
         const int64_t R = r0 + row;
         if (R >= K) continue;
         if (MODE == 0) {
-          if (col < a.nb) a.S[R * K + a.kb0 + col] = make_double2(re, im);
+          if (col < a.depth) a.S[R * K + a.kb0 + col] = make_double2(re, im);
         } else {
           const int64_t C = c0 + col;
-          if (C < K && C <= R) {
-            double2 v = a.S[R * K + C];
+          if (C < K && C <= R && (MODE == 1 || C < a.cend)) {
+            const double2 v = a.S[R * K + C];
             a.S[R * K + C] = make_double2(v.x - re, v.y - im);
           }
         }
@@ -289,27 +326,44 @@ int chol_block() { return CB; }
 
 void chol_factor(vmc_ctx* ctx, double2* S, int64_t K, double2* Linv, long long* fail, double* pivmin) {
   hipStream_t st = ctx->stream;
-  const int nblk = (int)((K + CB - 1) / CB);
-  for (int b = 0; b < nblk; ++b) {
-    const int64_t kb0 = (int64_t)b * CB;
-    const int nb = (int)std::min<int64_t>(CB, K - kb0);
-    double2* Lb = Linv + (size_t)b * CB * CB;
-    k_chol_diag<<<1, 256, 0, st>>>(S, K, kb0, nb, Lb, fail, pivmin);
-    const int64_t rest = K - kb0 - nb;
-    if (rest <= 0) continue;
-    zargs a{};
-    a.S = S;
-    a.K = K;
-    a.kb0 = kb0;
-    a.nb = nb;
-    a.base = kb0 + nb;
-    a.rows = rest;
-    a.Linv = Lb;
-    a.fail = fail;
-    k_zmfma<0><<<(unsigned)((rest + CB - 1) / CB), 256, 0, st>>>(a);
-    a.nt = (int)((rest + CB - 1) / CB);
-    a.ntiles = (int64_t)a.nt * (a.nt + 1) / 2;
-    k_zmfma<1><<<(unsigned)(((a.ntiles + 7) / 8) * 8), 256, 0, st>>>(a);
+  constexpr int PW = 256;  // panel width of the trailing update
+  for (int64_t p0 = 0; p0 < K; p0 += PW) {
+    const int64_t pend = std::min<int64_t>(K, p0 + PW);
+    for (int64_t c0 = p0; c0 < pend; c0 += CB) {
+      const int nb = (int)std::min<int64_t>(CB, K - c0);
+      double2* Lb = Linv + (size_t)(c0 / CB) * CB * CB;
+      k_chol_diag<<<1, 256, 0, st>>>(S, K, c0, nb, Lb, fail, pivmin);
+      const int64_t rest = K - c0 - nb;
+      if (rest <= 0) continue;
+      zargs a{};
+      a.S = S;
+      a.K = K;
+      a.kb0 = c0;
+      a.depth = nb;
+      a.rbase = c0 + nb;
+      a.Linv = Lb;
+      a.fail = fail;
+      k_zmfma<0><<<(unsigned)((rest + CB - 1) / CB), 256, 0, st>>>(a);
+      if (c0 + nb < pend) {  // remaining columns of this panel
+        a.cbase = c0 + nb;
+        a.cend = pend;
+        a.nct = (int)((pend - a.cbase + CB - 1) / CB);
+        const int64_t nrt = (rest + CB - 1) / CB;
+        k_zmfma<2><<<(unsigned)(nrt * a.nct), 256, 0, st>>>(a);
+      }
+    }
+    if (pend < K) {  // trailing matrix, reduction over the whole panel
+      zargs a{};
+      a.S = S;
+      a.K = K;
+      a.kb0 = p0;
+      a.depth = (int)(pend - p0);
+      a.rbase = pend;
+      a.fail = fail;
+      const int64_t nt = (K - pend + CB - 1) / CB;
+      a.ntiles = nt * (nt + 1) / 2;
+      k_zmfma<1><<<(unsigned)(((a.ntiles + 7) / 8) * 8), 256, 0, st>>>(a);
+    }
   }
   VMC_HIP(hipGetLastError());
 }
