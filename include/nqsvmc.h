@@ -197,9 +197,15 @@ int vmc_sampler_create(vmc_ctx* ctx, vmc_model* m, vmc_ham* H, const vmc_sampler
 int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, double* logpsi_out,
                int64_t* n_written, double* accept_rate_host);
 /* Chain state (configurations, step counter, seed) as a host byte blob;
- * *bytes in: capacity of buf_host (buf_host NULL: query size), out: size.   */
+ * *bytes in: capacity of buf_host (buf_host NULL: query size), out: size.
+ * VMC_ERR_INVALID_ARG before the first vmc_sample (no state yet).  After
+ * set_state the chains continue exactly as the saved sampler would have.    */
 int vmc_sampler_get_state(vmc_sampler* S, void* buf_host, size_t* bytes);
 int vmc_sampler_set_state(vmc_sampler* S, const void* buf_host, size_t bytes);
+/* Acceptance statistics of the last vmc_sample call: overall acceptance, the
+ * acceptance of global (MADE) proposals and their number (MADE_MIX only). */
+int vmc_sampler_get_stats(vmc_sampler* S, double* accept_rate_host, double* global_accept_rate_host,
+                          int64_t* n_global_host);
 /* Frozen MADE proposal used by VMC_PROP_MADE_MIX (the sampler copies its
  * parameters; later training of md does not affect the sampler).            */
 int vmc_sampler_set_proposal_made(vmc_sampler* S, const vmc_made* md);
@@ -254,7 +260,12 @@ int vmc_made_nll_grad(vmc_made* md, const uint64_t* s, int64_t B, double* grad, 
  * last epoch.                                                                 */
 int vmc_made_train(vmc_made* md, const uint64_t* s, int64_t B, int epochs, int batch, double lr, double* nll_host);
 /* Autoregressive samples: row c uses Philox((c, counter_lo, counter_hi, 1 + 256*(d/4))),
- * site d up iff x_{d%4} * 2^-32 < p_d.  s_out: B*W words; logq: B doubles.  */
+ * site d up iff x_{d%4} * 2^-32 < p_d.  s_out: B*W words; logq: B doubles.
+ * In VMC_PROP_MADE_MIX, proposal t of chain c is global iff x3 * 2^-32 < p_global
+ * (x = the proposal's Philox block) and its sample uses (c, t) as (row, counter);
+ * it is accepted iff r >= 0 or u < exp(r),
+ *   r = 2 Re(log psi(s') - log psi(s)) + log q(s) - log q(s').  A local proposal
+ * is the single-spin flip of VMC_PROP_FLIP.                                    */
 int vmc_made_sample(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, uint64_t* s_out, double* logq);
 int vmc_made_destroy(vmc_made* md);
 

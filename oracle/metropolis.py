@@ -87,10 +87,15 @@ def accept(r, u):
 
 class Chains:
     """A set of Metropolis chains (possibly a subset of a larger ensemble,
-    given by ``chain_ids``) that replays the library's random stream."""
+    given by ``chain_ids``) that replays the library's random stream.
+
+    proposal "made_mix" (not in the paper): proposal t is global iff
+    x3 * 2^-32 < p_global, its s' ~ q drawn by oracle.made.sample with (row,
+    counter) = (chain, t), and accepted with the Metropolis-Hastings ratio
+    |psi(s')|^2 q(s) / (|psi(s)|^2 q(s')); otherwise a single-spin flip."""
 
     def __init__(self, logpsi_fn, n_sites, proposal, seed, chain_ids,
-                 bond_list=None, sweep_steps=None, therm_sweeps=20):
+                 bond_list=None, sweep_steps=None, therm_sweeps=20, made=None, p_global=0.0):
         self.f = logpsi_fn
         self.key = philox.seed_key(seed)
         self.proposal = proposal
@@ -98,6 +103,11 @@ class Chains:
         self.bonds = bond_list
         self.sweep = n_sites if sweep_steps is None else sweep_steps
         self.therm = therm_sweeps
+        self.seed = seed
+        self.made = made            # (params, N, H) of the frozen proposal network
+        self.p_global = p_global
+        self.n_global = 0
+        self.acc_global = 0
         self.states = initial_states(len(self.cids), n_sites, self.key,
                                      proposal == "exchange", self.cids)
         self.logpsi = self.f(self.states)
@@ -108,6 +118,8 @@ class Chains:
         self.near_ties = 0
 
     def step(self):
+        if self.proposal == "made_mix":
+            return self._step_mix()
         sp, u = propose(self.proposal, self.states, self.t, self.key, self.cids, self.bonds)
         lp = self.f(sp)
         r = 2.0 * (lp.real - self.logpsi.real)
@@ -118,6 +130,42 @@ class Chains:
         self.logpsi[acc] = lp[acc]
         self.accepted += int(acc.sum())
         self.proposed += len(acc)
+        self.t += 1
+
+    def _step_mix(self):
+        from . import made as omade
+
+        mp, N, H = self.made
+        ctr = np.zeros((len(self.cids), 4), dtype=np.uint32)
+        ctr[:, 0] = self.cids.astype(np.uint32)
+        ctr[:, 1] = np.uint32(self.t & 0xFFFFFFFF)
+        ctr[:, 2] = np.uint32(self.t >> 32)
+        x = philox.philox4x32_10(ctr, self.key)
+        u = philox.to_uniform(x[:, 1], x[:, 2])
+        glob = x[:, 3].astype(np.float64) * 2.0 ** -32 < self.p_global
+        for r in range(len(self.cids)):
+            if glob[r]:
+                sp, lq_new = omade.sample(mp, 1, N, H, self.seed, self.t & 0xFFFFFFFF, self.t >> 32,
+                                          rows=[self.cids[r]])
+                lq_old = omade.log_q(mp, self.states[r][None], N, H)[0]
+                lp_new = self.f(sp)[0]
+                rr = 2.0 * (lp_new.real - self.logpsi[r].real) + lq_old - lq_new[0]
+                self.n_global += 1
+                if rr >= 0.0 or u[r] < np.exp(rr):
+                    self.states[r] = sp[0]
+                    self.logpsi[r] = lp_new
+                    self.accepted += 1
+                    self.acc_global += 1
+            else:
+                sp = self.states[r].copy()
+                sp[philox.to_index(x[r, 0], sp.shape[0])] ^= 1
+                lp_new = self.f(sp[None])[0]
+                rr = 2.0 * (lp_new.real - self.logpsi[r].real)
+                if rr >= 0.0 or u[r] < np.exp(rr):
+                    self.states[r] = sp
+                    self.logpsi[r] = lp_new
+                    self.accepted += 1
+            self.proposed += 1
         self.t += 1
 
     def sample(self, n_per_chain):

@@ -512,7 +512,7 @@ extern "C" int vmc_sampler_create(vmc_ctx* ctx, vmc_model* m, vmc_ham* H, const 
     S->W = m->W;
     try {
       S->bits = (uint64_t*)dmalloc(sizeof(uint64_t) * (size_t)o->n_chains * S->W);
-      S->acc = (unsigned long long*)dmalloc(sizeof(unsigned long long) * o->n_chains);
+      S->acc = (unsigned long long*)dmalloc(sizeof(unsigned long long) * 3 * (size_t)o->n_chains);
     } catch (...) {
       if (S->bits) (void)hipFree(S->bits);
       delete S;
@@ -538,25 +538,31 @@ extern "C" int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, do
     }
     VMC_REQUIRE(s_out, "NULL s_out");
     if (S->opts.proposal == VMC_PROP_MADE_MIX)
-      VMC_REQUIRE(S->made_params, "VMC_PROP_MADE_MIX needs vmc_sampler_set_proposal_made first");
+      VMC_REQUIRE(S->made_buf, "VMC_PROP_MADE_MIX needs vmc_sampler_set_proposal_made first");
     set_device(S->ctx);
     uint64_t t0 = S->t;
     {
       phase_scope ps(S->ctx, "sample");
       sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
     }
-    if (accept_rate_host) {
-      auto* h = (unsigned long long*)pinned_host(S->ctx, sizeof(unsigned long long) * S->opts.n_chains);
-      VMC_HIP(hipMemcpyAsync(h, S->acc, sizeof(unsigned long long) * S->opts.n_chains, hipMemcpyDeviceToHost,
-                             S->ctx->stream));
-      VMC_HIP(hipStreamSynchronize(S->ctx->stream));
-      double tot = 0;
-      for (int c = 0; c < S->opts.n_chains; ++c) tot += (double)h[c];
-      double steps = (double)(S->t - t0) * S->opts.n_chains;
-      *accept_rate_host = steps > 0 ? tot / steps : 0.0;
-    } else {
-      VMC_HIP(hipStreamSynchronize(S->ctx->stream));
-    }
+    const int nc = S->opts.n_chains;
+    const int nrows = S->opts.proposal == VMC_PROP_MADE_MIX ? 3 : 1;
+    auto* h = (unsigned long long*)pinned_host(S->ctx, sizeof(unsigned long long) * nrows * (size_t)nc);
+    VMC_HIP(hipMemcpyAsync(h, S->acc, sizeof(unsigned long long) * nrows * (size_t)nc, hipMemcpyDeviceToHost,
+                           S->ctx->stream));
+    VMC_HIP(hipStreamSynchronize(S->ctx->stream));
+    double tot = 0, tg = 0, ng = 0;
+    for (int c = 0; c < nc; ++c) tot += (double)h[c];
+    if (nrows == 3)
+      for (int c = 0; c < nc; ++c) {
+        tg += (double)h[nc + c];
+        ng += (double)h[2 * nc + c];
+      }
+    const double steps = (double)(S->t - t0) * nc;
+    S->last_accept = steps > 0 ? tot / steps : 0.0;
+    S->last_global_accept = ng > 0 ? tg / ng : 0.0;
+    S->last_n_global = (int64_t)ng;
+    if (accept_rate_host) *accept_rate_host = S->last_accept;
   });
 }
 
@@ -570,6 +576,7 @@ const uint64_t kStateMagic = 0x4e51535653414d31ull;  // "NQSVSAM1"
 extern "C" int vmc_sampler_get_state(vmc_sampler* S, void* buf_host, size_t* bytes) {
   return guard(S ? S->ctx : nullptr, [&] {
     VMC_REQUIRE(S && bytes, "NULL argument");
+    VMC_REQUIRE(S->bits_valid, "the sampler has no chain state yet (call vmc_sample first)");
     size_t need = sizeof(state_header) + sizeof(uint64_t) * (size_t)S->opts.n_chains * S->W;
     if (!buf_host) {
       *bytes = need;
@@ -604,6 +611,17 @@ extern "C" int vmc_sampler_set_state(vmc_sampler* S, const void* buf_host, size_
     S->t = h.t;
     S->thermalized = (int)h.thermalized;
     S->opts.seed = h.seed;
+    S->bits_valid = 1;
+  });
+}
+
+extern "C" int vmc_sampler_get_stats(vmc_sampler* S, double* accept_rate_host, double* global_accept_rate_host,
+                                     int64_t* n_global_host) {
+  return guard(S ? S->ctx : nullptr, [&] {
+    VMC_REQUIRE(S, "NULL sampler");
+    if (accept_rate_host) *accept_rate_host = S->last_accept;
+    if (global_accept_rate_host) *global_accept_rate_host = S->last_global_accept;
+    if (n_global_host) *n_global_host = S->last_n_global;
   });
 }
 
@@ -613,8 +631,7 @@ extern "C" int vmc_sampler_destroy(vmc_sampler* S) {
   (void)hipStreamSynchronize(S->ctx->stream);
   if (S->bits) (void)hipFree(S->bits);
   if (S->acc) (void)hipFree(S->acc);
-  if (S->made_params) (void)hipFree(S->made_params);
-  if (S->made_w) (void)hipFree(S->made_w);
+  if (S->made_buf) (void)hipFree(S->made_buf);
   delete S;
   return VMC_OK;
 }

@@ -1,0 +1,93 @@
+// Real float64 GEMM on the matrix cores with arbitrary strides:
+//   C[m][n] = beta * C[m][n] + sum_k A(m, k) B(k, n),
+//   A(m, k) = A[m * sam + k * sak],  B(k, n) = B[k * sbk + n * sbn].
+// 64 x 64 output tile per 256-thread group (2 x 2 waves of 32 x 32, each
+// 2 x 2 blocks of v_mfma_f64_16x16x4), the reduction staged 16 deep through
+// LDS.  Loads are coalesced along whichever stride of each operand is 1.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_dgemm(dgemm_args g) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][65];
+  const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  doublex4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+  const bool a_k_fast = g.sak == 1;
+  const bool b_n_fast = g.sbn == 1;
+  for (int64_t k0 = 0; k0 < g.K; k0 += 16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = tid + 256 * j;
+      int mm, kk;
+      if (a_k_fast) {
+        mm = q >> 4;
+        kk = q & 15;
+      } else {
+        mm = q & 63;
+        kk = q >> 6;
+      }
+      const int64_t m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : 0.0;
+      int nn, kb;
+      if (b_n_fast) {
+        nn = q & 63;
+        kb = q >> 6;
+      } else {
+        nn = q >> 4;
+        kb = q & 15;
+      }
+      const int64_t n = n0 + nn, kq = k0 + kb;
+      Bs[kb][nn] = (n < g.N && kq < g.K) ? g.B[kq * g.sbk + n * g.sbn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = ks * 4 + lk;
+      double fa[2], fb[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) fa[i] = As[kk][wr * 32 + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) fb[j] = Bs[kk][wc * 32 + j * 16 + li];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // float64 accumulator layout: register r of lane l holds D[l/16 + 4r][l%16]
+        const int64_t m = m0 + wr * 32 + i * 16 + lk + 4 * r;
+        const int64_t n = n0 + wc * 32 + j * 16 + li;
+        if (m < g.M && n < g.N) {
+          double* c = g.C + m * g.ldc + n;
+          *c = (g.beta == 0.0 ? 0.0 : g.beta * *c) + acc[i][j][r];
+        }
+      }
+}
+
+}  // namespace
+
+void dgemm(vmc_ctx* ctx, const dgemm_args& g) {
+  if (g.M <= 0 || g.N <= 0) return;
+  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
+  k_dgemm<<<grid, 256, 0, ctx->stream>>>(g);
+  VMC_HIP(hipGetLastError());
+}

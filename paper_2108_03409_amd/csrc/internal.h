@@ -134,12 +134,15 @@ struct vmc_sampler {
   int N = 0, W = 1;
   uint64_t t = 0;            // proposals made per chain so far
   int thermalized = 0;
+  int bits_valid = 0;         // chain configurations drawn or restored
   uint64_t* bits = nullptr;  // [n_chains][W] chain configurations (device)
-  unsigned long long* acc = nullptr;  // [n_chains] accepted proposals in the current call
-  // frozen MADE proposal (VMC_PROP_MADE_MIX)
-  int made_hidden = 0;
-  double* made_params = nullptr;  // device, float64 flat MADE parameters
-  float* made_w = nullptr;        // device, float32 masked copies for the kernels
+  // [3][n_chains]: accepted proposals, accepted global proposals, global proposals (last call)
+  unsigned long long* acc = nullptr;
+  double last_accept = 0.0, last_global_accept = 0.0;
+  int64_t last_n_global = 0;
+  // frozen MADE proposal (VMC_PROP_MADE_MIX): [W1m^T (N x H) | W2m (N x H) | b1 (H) | b2 (N)]
+  int made_H = 0;
+  double* made_buf = nullptr;
 };
 
 struct vmc_made {
@@ -150,6 +153,9 @@ struct vmc_made {
   double* adam_m = nullptr;
   double* adam_v = nullptr;
   int64_t adam_t = 0;
+  double* W1m = nullptr;   // masked W1 (H x N)
+  double* W1mT = nullptr;  // its transpose (N x H)
+  double* W2m = nullptr;   // masked W2 (N x H)
 };
 
 // ------------------------------------------------------- device helpers --
@@ -253,6 +259,18 @@ void rbm_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, do
 void rbm_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
 // sampler.hip
 void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
+// gemm64.hip: C = beta C + op(A) op(B) in float64 with arbitrary strides
+struct dgemm_args {
+  const double* A;
+  int64_t sam, sak;
+  const double* B;
+  int64_t sbk, sbn;
+  double* C;
+  int64_t ldc;
+  int64_t M, N, K;
+  double beta;
+};
+void dgemm(vmc_ctx* ctx, const dgemm_args& g);
 // herk.hip
 void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode, double nu, double eps, double2* S,
                    double2* diag);

@@ -8,6 +8,13 @@
 // On acceptance theta_j -= 2 sigma_m D_jm and t_j follows the tanh addition
 // rule t' = (t - sigma T) / (1 - sigma t T); theta is rebuilt from the spins
 // at the start of every call and t from theta at every recorded sample.
+//
+// VMC_PROP_MADE_MIX: each proposal is, with probability p_global, an
+// independent sample s' ~ q of the frozen MADE (drawn in-kernel by the same
+// wave, hidden units across lanes) accepted with the Metropolis-Hastings rule
+//   r = 2 Re(log psi(s') - log psi(s)) + log q(s) - log q(s'),
+// and otherwise a single-spin flip.  log q of the current state is cached and
+// recomputed (teacher-forced pass) only after a local move changed the state.
 #include "internal.h"
 
 using namespace dev;
@@ -36,11 +43,73 @@ struct sampler_args {
   uint64_t* s_out;
   double2* logpsi_out;
   unsigned long long* acc;
+  // MADE_MIX
+  const double* mW1T;  // [N][H]
+  const double* mW2;   // [N][H]
+  const double* mb1;   // [H]
+  const double* mb2;   // [N]
+  int mH;
+  double p_global;
+  unsigned long long* acc_global;  // [n_chains] accepted global proposals
+  unsigned long long* n_global;    // [n_chains] global proposals made
 };
 
-template <int Q>
+constexpr int QH_MAX = 16;  // MADE hidden units per lane (H <= 1024)
+
+__device__ __forceinline__ double softplus_d(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
+
+// One autoregressive pass of the MADE over the wave: samples s' into out (when
+// sample == true, using Philox purpose-1 counters of (c, t)) or evaluates the
+// given configuration in out (teacher forcing).  Returns log q (uniform).
+__device__ double made_pass(const sampler_args& a, uint64_t* out, bool sample, uint32_t c, uint64_t t, int lane) {
+  const int N = a.N, H = a.mH;
+  double act[QH_MAX];
+#pragma unroll
+  for (int q = 0; q < QH_MAX; ++q) {
+    const int k = lane + 64 * q;
+    act[q] = k < H ? a.mb1[k] : 0.0;
+  }
+  if (sample) {
+    for (int w = lane; w < a.W; w += 64) out[w] = 0ull;
+    __syncthreads();
+  }
+  double lq = 0.0;
+  uint4 x4 = make_uint4(0, 0, 0, 0);
+  for (int d = 0; d < N; ++d) {
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < QH_MAX; ++q) {
+      const int k = lane + 64 * q;
+      if (k < H) part += a.mW2[(int64_t)d * H + k] * fmax(act[q], 0.0);
+    }
+    double l = wave_sum(part);
+    l = __shfl(l, 0, 64) + a.mb2[d];
+    bool up;
+    if (sample) {
+      if ((d & 3) == 0) x4 = philox(make_uint4(c, (uint32_t)t, (uint32_t)(t >> 32), 1u + 256u * (uint32_t)(d >> 2)), a.key);
+      const uint32_t xr = (d & 3) == 0 ? x4.x : (d & 3) == 1 ? x4.y : (d & 3) == 2 ? x4.z : x4.w;
+      up = (double)xr * 0x1.0p-32 < 1.0 / (1.0 + exp(-l));
+    } else {
+      up = (out[d >> 6] >> (d & 63)) & 1ull;
+    }
+    lq += (up ? l : 0.0) - softplus_d(l);
+    if (up) {
+#pragma unroll
+      for (int q = 0; q < QH_MAX; ++q) {
+        const int k = lane + 64 * q;
+        if (k < H) act[q] += a.mW1T[(int64_t)d * H + k];
+      }
+      if (sample && lane == 0) out[d >> 6] |= 1ull << (d & 63);
+    }
+  }
+  __syncthreads();
+  return lq;
+}
+
+template <int Q, bool MIX>
 __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   __shared__ uint64_t cb[64];  // chain configuration, W <= 64 words
+  __shared__ uint64_t sp[64];  // global proposal (MADE_MIX)
   const int c = blockIdx.x;
   if (c >= a.n_chains) return;
   const int lane = threadIdx.x;
@@ -97,13 +166,70 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
 #pragma unroll
   for (int q = 0; q < Q; ++q) tt[q] = ctanh(th[q]);
 
-  unsigned long long accepted = 0;
+  unsigned long long accepted = 0, acc_g = 0, n_g = 0;
+  double lq_cur = 0.0;
+  bool lq_valid = false;
   const int64_t total = a.therm_steps + a.n_record * a.sweep;
   for (int64_t step = 0; step < total; ++step) {
     const uint64_t t = a.t0 + (uint64_t)step;
     const uint4 x = philox(make_uint4((uint32_t)c, (uint32_t)t, (uint32_t)(t >> 32), 0u), a.key);
     const int m = (int)to_index(x.x, (uint32_t)a.n_moves);
     const double u = to_uniform(x.y, x.z);
+    if (MIX && (double)x.w * 0x1.0p-32 < a.p_global) {
+      // ---- global MADE proposal with exact Metropolis-Hastings acceptance ----
+      ++n_g;
+      if (!lq_valid) {
+        lq_cur = made_pass(a, cb, false, (uint32_t)c, t, lane);
+        lq_valid = true;
+      }
+      const double lq_new = made_pass(a, sp, true, (uint32_t)c, t, lane);
+      double2 thn[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int j = lane + 64 * q;
+        thn[q] = j < Nh ? a.params[N + j] : make_double2(0.0, 0.0);
+      }
+      double dre = 0.0;  // 2 Re(log psi(s') - log psi(s)), lane partial
+      for (int i = 0; i < N; ++i) {
+        const bool up = (sp[i >> 6] >> (i & 63)) & 1ull;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int j = lane + 64 * q;
+          if (j < Nh) {
+            const double2 w = a.Wt[(int64_t)i * Nh + j];
+            thn[q].x += up ? w.x : -w.x;
+            thn[q].y += up ? w.y : -w.y;
+          }
+        }
+      }
+      for (int i = lane; i < N; i += 64) {
+        const double sn = ((sp[i >> 6] >> (i & 63)) & 1ull) ? 1.0 : -1.0;
+        const double so = ((cb[i >> 6] >> (i & 63)) & 1ull) ? 1.0 : -1.0;
+        dre += 2.0 * a.params[i].x * (sn - so);
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int j = lane + 64 * q;
+        if (j < Nh) dre += 2.0 * (clogcosh(thn[q]).x - clogcosh(th[q]).x);
+      }
+      double dr = wave_sum(dre);
+      dr = __shfl(dr, 0, 64);
+      const double r = dr + lq_cur - lq_new;
+      const bool accg = (r >= 0.0) || (u < exp(r));
+      if (accg) {
+        ++accepted;
+        ++acc_g;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          th[q] = thn[q];
+          tt[q] = ctanh(thn[q]);
+        }
+        __syncthreads();
+        for (int w = lane; w < W; w += 64) cb[w] = sp[w];
+        lq_cur = lq_new;
+        __syncthreads();
+      }
+    } else {
     int site = m, site2 = -1;
     bool identity = false;
     if (a.proposal == VMC_PROP_EXCHANGE) {
@@ -152,7 +278,9 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
           if (site2 >= 0) cb[site2 >> 6] ^= 1ull << (site2 & 63);
         }
         __syncthreads();
+        lq_valid = false;
       }
+    }
     }
     // record after every completed sweep of the recording phase
     if (step >= a.therm_steps && ((step - a.therm_steps + 1) % a.sweep) == 0) {
@@ -178,12 +306,21 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
     }
   }
   for (int w = lane; w < W; w += 64) a.bits[(int64_t)c * W + w] = cb[w];
-  if (lane == 0) a.acc[c] = accepted;
+  if (lane == 0) {
+    a.acc[c] = accepted;
+    if (MIX) {
+      a.acc_global[c] = acc_g;
+      a.n_global[c] = n_g;
+    }
+  }
 }
 
 template <int Q>
 void launch(const sampler_args& a, hipStream_t st) {
-  k_metropolis<Q><<<a.n_chains, 64, 0, st>>>(a);
+  if (a.proposal == VMC_PROP_MADE_MIX)
+    k_metropolis<Q, true><<<a.n_chains, 64, 0, st>>>(a);
+  else
+    k_metropolis<Q, false><<<a.n_chains, 64, 0, st>>>(a);
 }
 
 }  // namespace
@@ -192,7 +329,6 @@ void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* 
   vmc_model* m = S->model;
   VMC_REQUIRE(m->kind == MODEL_RBM, "sampler supports RBM models");
   VMC_REQUIRE(m->W <= 64, "sampler supports up to 4096 sites");
-  VMC_REQUIRE(S->opts.proposal != VMC_PROP_MADE_MIX, "MADE proposals are handled by the mixed sampler");
   const int move_kind = S->opts.proposal == VMC_PROP_EXCHANGE ? 1 : 0;
   rbm_ensure_tables(m, S->ham, move_kind);
   const rbm_move_tables& tb = m->tab[move_kind];
@@ -213,13 +349,25 @@ void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* 
   a.bits = S->bits;
   a.key = make_uint2((uint32_t)S->opts.seed, (uint32_t)(S->opts.seed >> 32));
   a.t0 = S->t;
-  a.init = S->t == 0 && !S->thermalized;
+  a.init = !S->bits_valid;
   a.therm_steps = S->thermalized ? 0 : (int64_t)S->opts.therm_sweeps * S->opts.sweep_steps;
   a.n_record = n_per_chain;
   a.sweep = S->opts.sweep_steps;
   a.s_out = s_out;
   a.logpsi_out = logpsi_out;
   a.acc = S->acc;
+  if (S->opts.proposal == VMC_PROP_MADE_MIX) {
+    VMC_REQUIRE(S->made_buf && S->made_H > 0 && S->made_H <= 64 * QH_MAX, "no MADE proposal set");
+    const int64_t nh = (int64_t)m->N * S->made_H;
+    a.mW1T = S->made_buf;
+    a.mW2 = S->made_buf + nh;
+    a.mb1 = S->made_buf + 2 * nh;
+    a.mb2 = S->made_buf + 2 * nh + S->made_H;
+    a.mH = S->made_H;
+    a.p_global = S->opts.p_global;
+    a.acc_global = S->acc + S->opts.n_chains;
+    a.n_global = S->acc + 2 * (int64_t)S->opts.n_chains;
+  }
   const int Q = (m->Nh + 63) / 64;
   hipStream_t st = S->ctx->stream;
   if (Q <= 1)
@@ -237,4 +385,45 @@ void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* 
   VMC_HIP(hipGetLastError());
   S->t += (uint64_t)(a.therm_steps + a.n_record * a.sweep);
   S->thermalized = 1;
+  S->bits_valid = 1;
+}
+
+namespace {
+__global__ void k_copy_made(const double* __restrict__ W1mT, const double* __restrict__ W2m,
+                            const double* __restrict__ params, int N, int H, double* __restrict__ buf) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nh = (int64_t)N * H;
+  if (e < nh) {
+    buf[e] = W1mT[e];
+    buf[nh + e] = W2m[e];
+  }
+  if (e < H) buf[2 * nh + e] = params[nh + e];
+  if (e < N) buf[2 * nh + H + e] = params[2 * nh + H + e];
+}
+}  // namespace
+
+extern "C" int vmc_sampler_set_proposal_made(vmc_sampler* S, const vmc_made* md) {
+  if (!S || !md) return VMC_ERR_INVALID_ARG;
+  try {
+    VMC_REQUIRE(md->ctx == S->ctx, "MADE belongs to another context");
+    VMC_REQUIRE(md->N == S->N, "MADE input size differs from the sampler's site count");
+    VMC_REQUIRE(md->H <= 64 * QH_MAX, "MADE hidden size above 1024");
+    VMC_HIP(hipSetDevice(S->ctx->device));
+    const int64_t nh = (int64_t)md->N * md->H;
+    const size_t bytes = sizeof(double) * (size_t)(2 * nh + md->H + md->N);
+    VMC_HIP(hipStreamSynchronize(S->ctx->stream));
+    if (S->made_buf) VMC_HIP(hipFree(S->made_buf));
+    S->made_buf = nullptr;
+    VMC_HIP(hipMalloc(&S->made_buf, bytes));
+    S->made_H = md->H;
+    const int64_t n = std::max<int64_t>(nh, std::max(md->H, md->N));
+    k_copy_made<<<grid_for(n, 256), 256, 0, S->ctx->stream>>>(md->W1mT, md->W2m, md->params, md->N, md->H,
+                                                               S->made_buf);
+    VMC_HIP(hipGetLastError());
+    S->ctx->err.clear();
+    return VMC_OK;
+  } catch (vmc_error& e) {
+    S->ctx->err = e.msg;
+    return e.code;
+  }
 }

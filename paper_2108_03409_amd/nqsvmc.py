@@ -83,6 +83,7 @@ _SIGS = {
     "vmc_sampler_get_state": ([P, P, C.POINTER(C.c_size_t)], C.c_int),
     "vmc_sampler_set_state": ([P, P, C.c_size_t], C.c_int),
     "vmc_sampler_set_proposal_made": ([P, P], C.c_int),
+    "vmc_sampler_get_stats": ([P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
     "vmc_sampler_destroy": ([P], C.c_int),
     "vmc_sr_solve": ([P, P, C.c_int, P, P, I64, I64, C.POINTER(SROpts), P, C.POINTER(SRInfo)], C.c_int),
     "vmc_made_create": ([P, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
@@ -305,6 +306,15 @@ class Sampler:
         assert nw.value == n
         return s, lp, acc.value
 
+    def set_proposal_made(self, made: "MADE"):
+        _check(load().vmc_sampler_set_proposal_made(self.h, made.h), self.ctx.h)
+
+    def stats(self):
+        """(acceptance, global acceptance, number of global proposals) of the last sample call."""
+        a, g, n = C.c_double(), C.c_double(), I64()
+        _check(load().vmc_sampler_get_stats(self.h, C.byref(a), C.byref(g), C.byref(n)), self.ctx.h)
+        return a.value, g.value, n.value
+
     def get_state(self) -> bytes:
         n = C.c_size_t(0)
         _check(load().vmc_sampler_get_state(self.h, None, C.byref(n)), self.ctx.h)
@@ -319,6 +329,63 @@ class Sampler:
     def close(self):
         if getattr(self, "h", None):
             load().vmc_sampler_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MADE:
+    """Masked autoregressive proposal network (float64 parameters on the device)."""
+
+    def __init__(self, ctx: Context, n_in: int, n_hidden: int):
+        self.ctx, self.N, self.H = ctx, n_in, n_hidden
+        self.W = (n_in + 63) // 64
+        h = P()
+        _check(load().vmc_made_create(ctx.h, n_in, n_hidden, C.byref(h)), ctx.h)
+        self.h = h
+        k = I64()
+        _check(load().vmc_made_num_params(h, C.byref(k)), ctx.h)
+        self.P = k.value
+
+    def set_params(self, p: torch.Tensor):
+        assert p.dtype == torch.float64 and p.numel() == self.P
+        _check(load().vmc_made_set_params(self.h, _ptr(p)), self.ctx.h)
+
+    def get_params(self) -> torch.Tensor:
+        out = torch.empty(self.P, dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        _check(load().vmc_made_get_params(self.h, _ptr(out)), self.ctx.h)
+        return out
+
+    def log_q(self, s: torch.Tensor) -> torch.Tensor:
+        out = torch.empty(s.shape[0], dtype=torch.float64, device=s.device)
+        _check(load().vmc_made_log_q(self.h, _ptr(s), s.shape[0], _ptr(out)), self.ctx.h)
+        return out
+
+    def nll_grad(self, s: torch.Tensor):
+        g = torch.empty(self.P, dtype=torch.float64, device=s.device)
+        nll = C.c_double()
+        _check(load().vmc_made_nll_grad(self.h, _ptr(s), s.shape[0], _ptr(g), C.byref(nll)), self.ctx.h)
+        return nll.value, g
+
+    def train(self, s: torch.Tensor, epochs: int, batch: int, lr: float) -> float:
+        nll = C.c_double()
+        _check(load().vmc_made_train(self.h, _ptr(s), s.shape[0], epochs, batch, lr, C.byref(nll)), self.ctx.h)
+        return nll.value
+
+    def sample(self, B: int, seed: int, counter: int = 0):
+        dev = f"cuda:{self.ctx.device}"
+        s = torch.empty((B, self.W), dtype=torch.int64, device=dev)
+        lq = torch.empty(B, dtype=torch.float64, device=dev)
+        _check(load().vmc_made_sample(self.h, B, seed, counter, _ptr(s), _ptr(lq)), self.ctx.h)
+        return s, lq
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().vmc_made_destroy(self.h)
             self.h = None
 
     def __del__(self):
