@@ -37,7 +37,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tfim1d_L64_rbm_a4_sr", choices=["tfim1d_L64_rbm_a4_sr"])
+    ap.add_argument("--workload", default="tfim1d_L64_rbm_a4_sr",
+                    choices=["tfim1d_L64_rbm_a4_sr", "heis2d_10x10_rbm_a4", "tfim2d_16x16_cnn",
+                             "tfim2d_20x20_rbm_a2_made"])
+    ap.add_argument("--p-global", type=float, default=None, help="MADE mix: global proposal probability")
+    ap.add_argument("--record-sweeps", type=int, default=256, help="MADE mix: recorded sweeps per chain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tau", type=float, default=1e-2)
     return ap.parse_args()
@@ -106,6 +110,134 @@ def cpu_baseline(cfg, p, N, Nh, n_chains, per_chain):
     }
 
 
+def bench_eloc(args, V, torch):
+    """Local energies/s: one step = sample + local energies of every sample."""
+    cfg = si.WORKLOADS[args.workload]
+    dev = "cuda:0"
+    ctx = V.Context(0)
+    Lx, Ly = cfg["Lx"], cfg["Ly"]
+    N = Lx * Ly
+    if cfg["net"] == "rbm":
+        Nh = cfg["alpha"] * N
+        p = si.rbm_params(N, Nh, std=cfg["std"], is_complex=True, seed=cfg["param_seed"])
+        model = V.Model.rbm(ctx, N, Nh, True)
+        # non-zero off-diagonal slots: N flips (TFIM); about N anti-aligned bonds of 2N (Heisenberg, Sz = 0)
+        work = eloc_flops(N, Nh, N)
+    else:
+        p = si.cnn_params(cfg["channels"], cfg["kernel"], std=cfg["std"], seed=cfg["param_seed"])
+        model = V.Model.cnn(ctx, Lx, Ly, cfg["channels"], cfg["kernel"])
+        Nh = None
+        work = None
+    model.set_params(torch.from_numpy(p).to(dev))
+    if cfg["ham"] == "heisenberg":
+        H = V.Hamiltonian.heisenberg(ctx, Lx, Ly, True, cfg["J"])
+    else:
+        H = V.Hamiltonian.tfim(ctx, Lx, Ly, True, cfg["J"], cfg["h"])
+    ns = cfg["n_chains"] * cfg["samples_per_chain"]
+    el = torch.empty(ns, dtype=torch.complex128, device=dev)
+    if cfg["net"] == "rbm":
+        sampler = V.Sampler(ctx, model, H, proposal=V.PROP_EXCHANGE if cfg["proposal"] == "exchange" else V.PROP_FLIP,
+                            n_chains=cfg["n_chains"], therm_sweeps=20, seed=cfg["sampler_seed"])
+        get_samples = lambda: sampler.sample(ns)[0]
+    else:
+        # the CNN path has no sampler yet: uniformly random configurations of the same shape
+        s_fixed = torch.from_numpy(si.pack_bits(si.random_bits(ns, N, seed=cfg["sampler_seed"])).view(np.int64)).to(dev)
+        get_samples = lambda: s_fixed
+
+    def step():
+        s = get_samples()
+        model.local_energy(H, s, out=el)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    eloc_ms = ctx.get_timing("eloc")[0] / args.steps
+    samp_ms = ctx.get_timing("sample")[0] / args.steps
+    ctx.set_timing(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    out = {
+        "metric": METRIC, "value": round(ns / (ms_step * 1e-3), 1), "unit": "local energies/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": args.workload, "samples": ns},
+        "phases_ms": {"sample": round(samp_ms, 3), "eloc": round(eloc_ms, 3)},
+        "eloc_kernel_per_s": round(ns / (eloc_ms * 1e-3), 1),
+        "mean_energy": float(el.real.mean().item()),
+    }
+    if work is not None:
+        out["eloc_roofline"] = {"bound": "alu", "achieved_TF": round(ns * work / (eloc_ms * 1e-3) / 1e12, 3),
+                                "peak": PEAK["fp64_valu_TF"], "work_per_eloc_flop": work}
+    print(json.dumps(out), flush=True)
+
+
+def bench_made(args, V, torch):
+    """Effective samples/s of the energy series: trained MADE mixed with flips
+    against flips alone, on the critical bond-RBM state of a 20 x 20 lattice."""
+    from paper_2108_03409_amd import stats as pstats
+
+    cfg = si.WORKLOADS[args.workload]
+    dev = "cuda:0"
+    Lx, Ly = cfg["Lx"], cfg["Ly"]
+    N = Lx * Ly
+    ctx = V.Context(0)
+    p = si.bond_rbm_params(Lx, Ly, si.W_CRITICAL)
+    Nh = (len(p) - N) // (N + 1)
+    model = V.Model.rbm(ctx, N, Nh, True)
+    model.set_params(torch.from_numpy(p).to(dev))
+    H = V.Hamiltonian.tfim(ctx, Lx, Ly, True, cfg["J"], cfg["h"])
+    nc = cfg["n_chains"]
+    # training data from thermalised local chains
+    t0 = time.perf_counter()
+    src = V.Sampler(ctx, model, H, proposal=V.PROP_FLIP, n_chains=nc, therm_sweeps=200, seed=cfg["sampler_seed"] + 1000)
+    data, _, _ = src.sample(cfg["train_samples"])
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    made = V.MADE(ctx, N, cfg["made_hidden"])
+    made.set_params(torch.from_numpy(si.made_params(N, cfg["made_hidden"], seed=cfg["made_seed"])).to(dev))
+    t0 = time.perf_counter()
+    nll = made.train(data, epochs=20, batch=1024, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    pg = args.p_global if args.p_global is not None else 1.0 / N
+    R = args.record_sweeps
+    res = {}
+    for name, prop in [("local", V.PROP_FLIP), ("mixed", V.PROP_MADE_MIX)]:
+        S = V.Sampler(ctx, model, H, proposal=prop, n_chains=nc, therm_sweeps=100, seed=cfg["sampler_seed"],
+                      p_global=pg)
+        if prop == V.PROP_MADE_MIX:
+            S.set_proposal_made(made)
+        S.sample(nc)                       # thermalisation + one sweep, untimed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, _, acc = S.sample(nc * R)
+        torch.cuda.synchronize()
+        t_s = time.perf_counter() - t0
+        a, ga, ng = S.stats()
+        el = model.local_energy(H, s).real.cpu().numpy().reshape(R, nc)
+        n_eff, tau = pstats.ess(el)
+        res[name] = {"ess": n_eff, "tau_int_sweeps": tau, "sample_s": t_s, "ess_per_s": n_eff / t_s,
+                     "accept": a, "global_accept": ga, "n_global": ng,
+                     "energy": float(el.mean()), "sigma_energy": float(np.sqrt(el.var() / n_eff))}
+    ratio = res["mixed"]["ess_per_s"] / res["local"]["ess_per_s"]
+    out = {
+        "metric": METRIC, "value": round(res["mixed"]["ess_per_s"], 2), "unit": "effective samples/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(res["mixed"]["sample_s"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (bond-RBM at the 2D Ising critical coupling)",
+        "config": {"workload": args.workload, "n_chains": nc, "record_sweeps": R, "p_global": pg,
+                   "made_hidden": cfg["made_hidden"], "train_samples": cfg["train_samples"]},
+        "local": res["local"], "mixed": res["mixed"], "ess_per_s_ratio_mixed_over_local": round(ratio, 3),
+        "train_s": round(t_train, 3), "train_data_s": round(t_data, 3), "final_nll": nll,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -114,6 +246,11 @@ def main():
         sys.exit(2)
     import torch
     from paper_2108_03409_amd import nqsvmc as V
+
+    if args.workload in ("heis2d_10x10_rbm_a4", "tfim2d_16x16_cnn"):
+        return bench_eloc(args, V, torch)
+    if args.workload == "tfim2d_20x20_rbm_a2_made":
+        return bench_made(args, V, torch)
 
     cfg = si.WORKLOADS[args.workload]
     N = cfg["Lx"] * cfg["Ly"]

@@ -162,6 +162,13 @@ int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B,
  *   O: B*K elements, sample-major (row n = sample n), dtype C128 or C64.      */
 int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
 
+/* Reverse-mode product with the log-derivatives (the backward of log psi for
+ * automatic differentiation in the conjugate-Wirtinger convention of
+ * holomorphic maps):  out_k = sum_n g_n conj(O_nk(s_n)).
+ *   g: B complex128 (the incoming cotangent);  out: K complex128.
+ * O is recomputed from the configurations; no activations are stored.        */
+int vmc_log_psi_vjp(vmc_model* m, const uint64_t* s, int64_t B, const double* g, double* out);
+
 /* Metropolis sampler of p(s) = |psi(s)|^2/<psi|psi> (Sec. 2.1, Sec. 4.2
  * "Sampler"), all chains in sync.
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed & 0xffffffff,

@@ -233,11 +233,33 @@ extern "C" int vmc_model_create_rbm(vmc_ctx* ctx, int n_visible, int n_hidden, i
 extern "C" int vmc_model_create_cnn(vmc_ctx* ctx, int Lx, int Ly, int channels, int kernel, vmc_model** out) {
   return guard(ctx, [&] {
     VMC_REQUIRE(ctx && out, "NULL argument");
-    (void)Lx;
-    (void)Ly;
-    (void)channels;
-    (void)kernel;
-    throw vmc_error{VMC_ERR_UNSUPPORTED, "CNN model is not built yet"};
+    VMC_REQUIRE(Lx >= 1 && Ly >= 1 && (int64_t)Lx * Ly <= 4096, "lattice must have 1..4096 sites");
+    VMC_REQUIRE(channels >= 1 && channels <= 64, "channels must be in [1, 64]");
+    VMC_REQUIRE(kernel >= 1 && kernel <= Lx && kernel <= Ly && kernel <= 8, "kernel must be in [1, min(Lx, Ly, 8)]");
+    VMC_REQUIRE(2ull * channels * Lx * Ly * sizeof(double2) + 4096 <= 160 * 1024,
+                "channels * sites too large for the per-sample LDS budget");
+    set_device(ctx);
+    auto* m = new vmc_model;
+    m->ctx = ctx;
+    m->kind = MODEL_CNN;
+    m->Lx = Lx;
+    m->Ly = Ly;
+    m->N = Lx * Ly;
+    m->W = (m->N + 63) / 64;
+    m->C = channels;
+    m->k = kernel;
+    m->is_complex = 1;
+    const int64_t kk = (int64_t)kernel * kernel;
+    m->K = channels * kk + channels + (int64_t)channels * channels * kk + channels;
+    try {
+      m->params = (double2*)dmalloc(sizeof(double2) * m->K);
+      VMC_HIP(hipMemsetAsync(m->params, 0, sizeof(double2) * m->K, ctx->stream));
+    } catch (...) {
+      if (m->params) (void)hipFree(m->params);
+      delete m;
+      throw;
+    }
+    *out = m;
   });
 }
 
@@ -444,7 +466,7 @@ extern "C" int vmc_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double* l
     if (m->kind == MODEL_RBM)
       rbm_log_psi(m, s, B, (double2*)logpsi);
     else
-      throw vmc_error{VMC_ERR_UNSUPPORTED, "model kind"};
+      cnn_log_psi(m, s, B, (double2*)logpsi);
   });
 }
 
@@ -463,7 +485,7 @@ extern "C" int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int
     if (m->kind == MODEL_RBM)
       rbm_local_energy(m, H, s, B, (double2*)eloc);
     else
-      throw vmc_error{VMC_ERR_UNSUPPORTED, "model kind"};
+      cnn_local_energy(m, H, s, B, (double2*)eloc);
   });
 }
 
@@ -479,7 +501,23 @@ extern "C" int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void
     if (m->kind == MODEL_RBM)
       rbm_grad(m, s, B, O, dtype);
     else
-      throw vmc_error{VMC_ERR_UNSUPPORTED, "model kind"};
+      cnn_grad(m, s, B, O, dtype);
+  });
+}
+
+extern "C" int vmc_log_psi_vjp(vmc_model* m, const uint64_t* s, int64_t B, const double* g, double* out) {
+  return guard(m ? m->ctx : nullptr, [&] {
+    VMC_REQUIRE(m, "NULL model");
+    VMC_REQUIRE(B >= 0, "B < 0");
+    VMC_REQUIRE(out, "NULL out");
+    set_device(m->ctx);
+    phase_scope ps(m->ctx, "vjp");
+    if (B == 0) {
+      VMC_HIP(hipMemsetAsync(out, 0, sizeof(double2) * m->K, m->ctx->stream));
+      return;
+    }
+    VMC_REQUIRE(s && g, "NULL buffer");
+    log_psi_vjp_impl(m, s, B, (const double2*)g, (double2*)out);
   });
 }
 

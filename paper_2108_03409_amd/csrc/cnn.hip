@@ -1,0 +1,329 @@
+// Two-layer periodic CNN (C channels, k x k kernels, log-cosh after both
+// layers, sum-pool) on an Lx x Ly torus, float64 path:
+//   z1[c,p] = b1_c + sum_t W1[c,t] sigma[p + t],      a1 = logcosh(z1)
+//   z2[c,p] = b2_c + sum_{c',t} W2[c,c',t] a1[c',p + t],  log psi = sum logcosh(z2)
+// with p + t the periodic shift of position p by tap t = (dy, dx).
+//
+// Kernels (one 256-thread work-group per sample, activations in LDS):
+//   k_cnn_forward  log psi
+//   k_cnn_grad     O_k by the chain rule with recomputation of both layers
+//                  (no activations are stored between calls)
+//   k_cnn_eloc     local energies of the TFIM: for a flip of site s only the
+//                  k x k layer-1 positions p with p + t = s change, and only the
+//                  (2k-1) x (2k-1) layer-2 positions that read them, so each
+//                  connected configuration costs C*C*k^4 complex multiply-adds
+//                  instead of a full evaluation (requires Lx, Ly >= 2k - 1;
+//                  smaller tori re-evaluate layer 2 in full per slot).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+using namespace dev;
+
+namespace {
+
+struct cnn_geom {
+  int Lx, Ly, N, C, k, W;
+  const double2* W1;  // [C][k][k]
+  const double2* b1;  // [C]
+  const double2* W2;  // [C][C][k][k]
+  const double2* b2;  // [C]
+};
+
+__device__ __forceinline__ int shift_pos(const cnn_geom& g, int p, int dy, int dx) {
+  const int y = p / g.Lx, x = p - y * g.Lx;
+  int yy = y + dy, xx = x + dx;
+  yy %= g.Ly;
+  xx %= g.Lx;
+  if (yy < 0) yy += g.Ly;
+  if (xx < 0) xx += g.Lx;
+  return yy * g.Lx + xx;
+}
+
+__device__ __forceinline__ double sig_at(const uint64_t* s, int i) { return ((s[i >> 6] >> (i & 63)) & 1ull) ? 1.0 : -1.0; }
+
+__device__ __forceinline__ double2 z1_at(const cnn_geom& g, const uint64_t* s, int c, int p) {
+  double2 z = g.b1[c];
+  for (int dy = 0; dy < g.k; ++dy)
+    for (int dx = 0; dx < g.k; ++dx) {
+      const double sg = sig_at(s, shift_pos(g, p, dy, dx));
+      const double2 w = g.W1[(c * g.k + dy) * g.k + dx];
+      z.x += sg * w.x;
+      z.y += sg * w.y;
+    }
+  return z;
+}
+
+// layer 1 into a1[c][p] (LDS), layer 2 value at (c, p) from LDS a1
+__device__ __forceinline__ double2 z2_at(const cnn_geom& g, const double2* a1, int c, int p) {
+  double2 z = g.b2[c];
+  const int kk = g.k * g.k;
+  for (int ci = 0; ci < g.C; ++ci)
+    for (int dy = 0; dy < g.k; ++dy)
+      for (int dx = 0; dx < g.k; ++dx) {
+        const double2 w = g.W2[((c * g.C + ci) * g.k + dy) * g.k + dx];
+        z = cadd(z, cmul(w, a1[ci * g.N + shift_pos(g, p, dy, dx)]));
+      }
+  (void)kk;
+  return z;
+}
+
+__device__ double2 block_sum(double2 v, double2* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double2 t = make_double2(0.0, 0.0);
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t = cadd(t, red[q]);
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(256) void k_cnn_forward(cnn_geom g, const uint64_t* __restrict__ s, int64_t B,
+                                                     double2* __restrict__ logpsi) {
+  extern __shared__ double2 sm[];
+  double2* a1 = sm;                 // [C][N]
+  double2* red = sm + g.C * g.N;    // [4]
+  const int64_t b = blockIdx.x;
+  if (b >= B) return;
+  const uint64_t* sb = s + b * g.W;
+  const int CN = g.C * g.N;
+  for (int e = threadIdx.x; e < CN; e += 256) a1[e] = clogcosh(z1_at(g, sb, e / g.N, e % g.N));
+  __syncthreads();
+  double2 acc = make_double2(0.0, 0.0);
+  for (int e = threadIdx.x; e < CN; e += 256) acc = cadd(acc, clogcosh(z2_at(g, a1, e / g.N, e % g.N)));
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) logpsi[b] = acc;
+}
+
+// O_k rows [W1 (C k k), b1 (C), W2 (C C k k), b2 (C)].  LDS: bufA [C][N] (a1, later
+// d log psi / d z1), bufB [C][N] (tanh z2).
+template <typename OutT>
+__global__ __launch_bounds__(256) void k_cnn_grad(cnn_geom g, const uint64_t* __restrict__ s, int64_t B, int64_t K,
+                                                  OutT* __restrict__ O) {
+  extern __shared__ double2 sm[];
+  const int CN = g.C * g.N, kk = g.k * g.k;
+  double2* A = sm;
+  double2* G2 = sm + CN;
+  const int64_t b = blockIdx.x;
+  if (b >= B) return;
+  const uint64_t* sb = s + b * g.W;
+  OutT* row = O + b * K;
+  auto put = [&](int64_t k, double2 v) {
+    if constexpr (sizeof(OutT) == sizeof(double2))
+      row[k] = v;
+    else
+      row[k] = make_float2((float)v.x, (float)v.y);
+  };
+  const int off_b1 = g.C * kk, off_W2 = off_b1 + g.C, off_b2 = off_W2 + g.C * g.C * kk;
+  for (int e = threadIdx.x; e < CN; e += 256) A[e] = clogcosh(z1_at(g, sb, e / g.N, e % g.N));
+  __syncthreads();
+  for (int e = threadIdx.x; e < CN; e += 256) G2[e] = ctanh(z2_at(g, A, e / g.N, e % g.N));
+  __syncthreads();
+  // dW2[c][c'][t] = sum_p g2[c][p] a1[c'][p + t];  db2[c] = sum_p g2[c][p]
+  for (int e = threadIdx.x; e < g.C * g.C * kk; e += 256) {
+    const int c = e / (g.C * kk), r = e % (g.C * kk), ci = r / kk, t = r % kk;
+    const int dy = t / g.k, dx = t % g.k;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int p = 0; p < g.N; ++p) acc = cadd(acc, cmul(G2[c * g.N + p], A[ci * g.N + shift_pos(g, p, dy, dx)]));
+    put(off_W2 + e, acc);
+  }
+  for (int c = threadIdx.x; c < g.C; c += 256) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int p = 0; p < g.N; ++p) acc = cadd(acc, G2[c * g.N + p]);
+    put(off_b2 + c, acc);
+  }
+  __syncthreads();
+  // d log psi / d a1[c'][P] = sum_{c,t} W2[c][c'][t] g2[c][P - t], times tanh(z1) -> A
+  for (int e = threadIdx.x; e < CN; e += 256) {
+    const int ci = e / g.N, P = e % g.N;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int c = 0; c < g.C; ++c)
+      for (int dy = 0; dy < g.k; ++dy)
+        for (int dx = 0; dx < g.k; ++dx)
+          acc = cadd(acc, cmul(g.W2[((c * g.C + ci) * g.k + dy) * g.k + dx], G2[c * g.N + shift_pos(g, P, -dy, -dx)]));
+    A[e] = acc;  // each thread overwrites only its own entries; a1 is no longer read
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < CN; e += 256) A[e] = cmul(A[e], ctanh(z1_at(g, sb, e / g.N, e % g.N)));
+  __syncthreads();
+  // dW1[c][t] = sum_p g1[c][p] sigma[p + t];  db1[c] = sum_p g1[c][p]
+  for (int e = threadIdx.x; e < g.C * kk; e += 256) {
+    const int c = e / kk, t = e % kk, dy = t / g.k, dx = t % g.k;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int p = 0; p < g.N; ++p) acc = cadd(acc, cscale(A[c * g.N + p], sig_at(sb, shift_pos(g, p, dy, dx))));
+    put(e, acc);
+  }
+  for (int c = threadIdx.x; c < g.C; c += 256) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int p = 0; p < g.N; ++p) acc = cadd(acc, A[c * g.N + p]);
+    put(off_b1 + c, acc);
+  }
+}
+
+// TFIM local energies.  LDS: z2 [C][N], lc2 = logcosh(z2) [C][N], da1 [C][k*k]
+// (the changed layer-1 values of the current flip), sigma words, reduction.
+__global__ __launch_bounds__(256) void k_cnn_eloc(cnn_geom g, const uint64_t* __restrict__ s, int64_t B, double J,
+                                                  double h, const int2* __restrict__ bonds, int n_bonds,
+                                                  double2* __restrict__ eloc, double2* __restrict__ a1_scratch) {
+  extern __shared__ double2 sm[];
+  const int CN = g.C * g.N, kk = g.k * g.k;
+  double2* Z2 = sm;
+  double2* LC2 = sm + CN;
+  double2* DA = sm + 2 * CN;         // [C][kk]
+  double2* red = DA + g.C * kk;      // [4]
+  const int64_t b = blockIdx.x;
+  if (b >= B) return;
+  const uint64_t* sb = s + b * g.W;
+  double2* a1 = a1_scratch + b * CN;  // global scratch for the full layer 1 of this sample
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CN; e += 256) a1[e] = clogcosh(z1_at(g, sb, e / g.N, e % g.N));
+  __syncthreads();
+  for (int e = tid; e < CN; e += 256) {
+    const double2 z = z2_at(g, a1, e / g.N, e % g.N);
+    Z2[e] = z;
+    LC2[e] = clogcosh(z);
+  }
+  // diagonal element
+  int n_al = 0;
+  for (int q = tid; q < n_bonds; q += 256) n_al += sig_at(sb, bonds[q].x) == sig_at(sb, bonds[q].y);
+  __syncthreads();
+  double2 tot = block_sum(make_double2((double)n_al, 0.0), red);
+  const int nal = (int)tot.x;
+  const double diag = -J * (double)(nal - (n_bonds - nal));
+  double2 acc = make_double2(0.0, 0.0);
+  const int win = 2 * g.k - 1;
+  const bool incremental = g.Lx >= win && g.Ly >= win;
+  if (h != 0.0) {
+    for (int site = 0; site < g.N; ++site) {
+      const double ds = -2.0 * sig_at(sb, site);
+      const int Ys = site / g.Lx, Xs = site % g.Lx;
+      // changed layer-1 values: positions p = site - (dy, dx)
+      for (int e = tid; e < g.C * kk; e += 256) {
+        const int c = e / kk, t = e % kk, dy = t / g.k, dx = t % g.k;
+        const int p = shift_pos(g, site, -dy, -dx);
+        const double2 z = z1_at(g, sb, c, p);
+        const double2 w = g.W1[(c * g.k + dy) * g.k + dx];
+        const double2 zn = make_double2(z.x + ds * w.x, z.y + ds * w.y);
+        DA[e] = csub(clogcosh(zn), clogcosh(z));
+      }
+      __syncthreads();
+      double2 part = make_double2(0.0, 0.0);
+      if (incremental) {
+        // affected layer-2 outputs: q = site - (ey, ex), 0 <= ey, ex < 2k - 1
+        for (int e = tid; e < g.C * win * win; e += 256) {
+          const int c = e / (win * win), r = e % (win * win), ey = r / win, ex = r % win;
+          double2 dz = make_double2(0.0, 0.0);
+          for (int dy1 = max(0, ey - g.k + 1); dy1 <= min(g.k - 1, ey); ++dy1)
+            for (int dx1 = max(0, ex - g.k + 1); dx1 <= min(g.k - 1, ex); ++dx1) {
+              const int dy2 = ey - dy1, dx2 = ex - dx1;  // tap from q to the changed position
+              for (int ci = 0; ci < g.C; ++ci)
+                dz = cadd(dz, cmul(g.W2[((c * g.C + ci) * g.k + dy2) * g.k + dx2], DA[ci * kk + dy1 * g.k + dx1]));
+            }
+          int qy = Ys - ey, qx = Xs - ex;
+          if (qy < 0) qy += g.Ly;
+          if (qx < 0) qx += g.Lx;
+          const int qi = c * g.N + qy * g.Lx + qx;
+          part = cadd(part, csub(clogcosh(cadd(Z2[qi], dz)), LC2[qi]));
+        }
+      } else {
+        // small torus: re-evaluate layer 2 from the updated layer 1
+        for (int e = tid; e < CN; e += 256) {
+          const int c = e / g.N, q = e % g.N;
+          double2 dz = make_double2(0.0, 0.0);
+          for (int ci = 0; ci < g.C; ++ci)
+            for (int dy = 0; dy < g.k; ++dy)
+              for (int dx = 0; dx < g.k; ++dx) {
+                const int p = shift_pos(g, q, dy, dx);
+                // the flip changes a1[ci][p] through every tap that lands on the site
+                const double2 zo = z1_at(g, sb, ci, p);
+                double2 zn = zo;
+                for (int ty = 0; ty < g.k; ++ty)
+                  for (int tx = 0; tx < g.k; ++tx)
+                    if (shift_pos(g, p, ty, tx) == site) {
+                      const double2 w = g.W1[(ci * g.k + ty) * g.k + tx];
+                      zn.x += ds * w.x;
+                      zn.y += ds * w.y;
+                    }
+                if (zn.x != zo.x || zn.y != zo.y)
+                  dz = cadd(dz, cmul(g.W2[((c * g.C + ci) * g.k + dy) * g.k + dx], csub(clogcosh(zn), a1[ci * g.N + p])));
+              }
+          part = cadd(part, csub(clogcosh(cadd(Z2[e], dz)), LC2[e]));
+        }
+      }
+      const double2 dl = block_sum(part, red);
+      acc = cadd(acc, cscale(cexp(dl), -h));
+      __syncthreads();
+    }
+  }
+  if (tid == 0) eloc[b] = make_double2(acc.x + diag, acc.y);
+}
+
+constexpr int64_t kChunk = 1 << 14;
+
+cnn_geom geom(const vmc_model* m) {
+  cnn_geom g;
+  g.Lx = m->Lx;
+  g.Ly = m->Ly;
+  g.N = m->N;
+  g.C = m->C;
+  g.k = m->k;
+  g.W = m->W;
+  const int kk = m->k * m->k;
+  g.W1 = m->params;
+  g.b1 = m->params + m->C * kk;
+  g.W2 = g.b1 + m->C;
+  g.b2 = g.W2 + m->C * m->C * kk;
+  return g;
+}
+
+size_t lds_limit() { return 160 * 1024; }
+
+template <typename Kern>
+void allow_lds(Kern k, size_t bytes) {
+  VMC_REQUIRE(bytes <= lds_limit(), "CNN too large for the per-sample LDS budget");
+  if (bytes > 64 * 1024) VMC_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+}  // namespace
+
+void cnn_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* logpsi) {
+  const cnn_geom g = geom(m);
+  const size_t lds = sizeof(double2) * ((size_t)g.C * g.N + 4);
+  allow_lds(k_cnn_forward, lds);
+  k_cnn_forward<<<(unsigned)B, 256, lds, m->ctx->stream>>>(g, s, B, logpsi);
+  VMC_HIP(hipGetLastError());
+}
+
+void cnn_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype) {
+  const cnn_geom g = geom(m);
+  const size_t lds = sizeof(double2) * 2 * (size_t)g.C * g.N;
+  if (dtype == VMC_DT_C128) {
+    allow_lds(k_cnn_grad<double2>, lds);
+    k_cnn_grad<double2><<<(unsigned)B, 256, lds, m->ctx->stream>>>(g, s, B, m->K, (double2*)O);
+  } else {
+    allow_lds(k_cnn_grad<float2>, lds);
+    k_cnn_grad<float2><<<(unsigned)B, 256, lds, m->ctx->stream>>>(g, s, B, m->K, (float2*)O);
+  }
+  VMC_HIP(hipGetLastError());
+}
+
+void cnn_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc) {
+  VMC_REQUIRE(H->kind == HAM_TFIM, "the CNN local energy supports the transverse-field Ising model");
+  VMC_REQUIRE(H->Lx == m->Lx && H->Ly == m->Ly, "lattice of the Hamiltonian differs from the CNN's");
+  const cnn_geom g = geom(m);
+  const int kk = g.k * g.k;
+  const size_t lds = sizeof(double2) * (2 * (size_t)g.C * g.N + (size_t)g.C * kk + 4);
+  allow_lds(k_cnn_eloc, lds);
+  vmc_ctx* ctx = m->ctx;
+  const int64_t chunk = std::min<int64_t>(B, kChunk);
+  ws_reserve(ctx, ws_round(sizeof(double2) * chunk * g.C * g.N));
+  double2* a1 = (double2*)ws_take(ctx, sizeof(double2) * chunk * g.C * g.N);
+  for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+    const int64_t nb = std::min(chunk, B - b0);
+    k_cnn_eloc<<<(unsigned)nb, 256, lds, ctx->stream>>>(g, s + b0 * g.W, nb, H->J, H->h, H->bonds, H->n_bonds,
+                                                        eloc + b0, a1);
+    VMC_HIP(hipGetLastError());
+  }
+}

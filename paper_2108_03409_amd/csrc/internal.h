@@ -257,6 +257,12 @@ void rbm_ensure_tables(vmc_model* m, const vmc_ham* H, int move_kind);
 void rbm_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* logpsi);
 void rbm_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
 void rbm_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
+// cnn.hip
+void cnn_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* logpsi);
+void cnn_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
+void cnn_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
+// vjp.hip
+void log_psi_vjp_impl(vmc_model* m, const uint64_t* s, int64_t B, const double2* g, double2* out);
 // sampler.hip
 void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
 // gemm64.hip: C = beta C + op(A) op(B) in float64 with arbitrary strides

@@ -78,6 +78,7 @@ _SIGS = {
     "vmc_log_psi": ([P, P, I64, P], C.c_int),
     "vmc_local_energy": ([P, P, P, I64, P, P], C.c_int),
     "vmc_grad_log_psi": ([P, P, I64, P, C.c_int], C.c_int),
+    "vmc_log_psi_vjp": ([P, P, I64, P, P], C.c_int),
     "vmc_sampler_create": ([P, P, P, C.POINTER(SamplerOpts), C.POINTER(P)], C.c_int),
     "vmc_sample": ([P, I64, P, P, C.POINTER(I64), C.POINTER(C.c_double)], C.c_int),
     "vmc_sampler_get_state": ([P, P, C.POINTER(C.c_size_t)], C.c_int),
@@ -228,6 +229,13 @@ class Model:
             out = torch.empty((B, self.K), dtype=dtype, device=s.device)
         dt = DT_C128 if out.dtype == torch.complex128 else DT_C64
         _check(load().vmc_grad_log_psi(self.h, _ptr(s), B, _ptr(out), dt), self.ctx.h)
+        return out
+
+    def log_psi_vjp(self, s: torch.Tensor, g: torch.Tensor) -> torch.Tensor:
+        """sum_n g_n conj(O_nk) for a complex128 cotangent g of shape (B,)."""
+        out = torch.empty(self.K, dtype=torch.complex128, device=s.device)
+        g = g.to(torch.complex128).contiguous()
+        _check(load().vmc_log_psi_vjp(self.h, _ptr(s), s.shape[0], _ptr(g), _ptr(out)), self.ctx.h)
         return out
 
     def close(self):
@@ -411,6 +419,33 @@ def sr_solve(ctx: Context, O: torch.Tensor, eloc: torch.Tensor, *, weights=None,
     if rc != VMC_OK and raise_on_error:
         _check(rc, ctx.h)
     return (x if rc == VMC_OK else None), d
+
+
+class NQSLogPsi(torch.autograd.Function):
+    """log psi_theta(s) as a differentiable function of the complex parameter
+    vector theta: forward runs the library's network kernels, backward its
+    vector-Jacobian kernels (grad_theta = sum_n grad_out_n conj(O_n), torch's
+    convention for holomorphic functions).  The model's parameters are set to
+    theta on every call."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, s: torch.Tensor, model: "Model"):
+        model.set_params(theta.detach().to(torch.complex128).contiguous())
+        ctx.model = model
+        ctx.save_for_backward(theta, s)
+        return model.log_psi(s)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        theta, s = ctx.saved_tensors
+        model = ctx.model
+        model.set_params(theta.detach().to(torch.complex128).contiguous())
+        g = model.log_psi_vjp(s, grad_out)
+        return g.to(theta.dtype), None, None
+
+
+def log_psi_autograd(model: "Model", theta: torch.Tensor, s: torch.Tensor) -> torch.Tensor:
+    return NQSLogPsi.apply(theta, s, model)
 
 
 def version() -> str:

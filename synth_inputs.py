@@ -87,6 +87,31 @@ def rbm_params(n_visible: int, n_hidden: int, *, std: float = 0.01,
     return _normal_params(rbm_num_params(n_visible, n_hidden), std, is_complex, seed)
 
 
+def bond_rbm_params(Lx: int, Ly: int, w: float) -> np.ndarray:
+    """RBM parameters with one hidden unit per nearest-neighbour bond of the
+    periodic Lx x Ly lattice (bond order: per site, +x then +y): W[b, i] =
+    W[b, j] = w for bond b = (i, j), all other parameters 0.  |psi|^2 is then
+    the classical Ising weight prod_b exp(K s_i s_j) with K = ln cosh(2 w)."""
+    N = Lx * Ly
+    bl = []
+    for y in range(Ly):
+        for x in range(Lx):
+            i = y * Lx + x
+            bl.append((i, y * Lx + (x + 1) % Lx))
+            bl.append((i, ((y + 1) % Ly) * Lx + x))
+    Nh = len(bl)
+    W = np.zeros((Nh, N), dtype=np.complex128)
+    for b, (i, j) in enumerate(bl):
+        W[b, i] = w
+        W[b, j] = w
+    return np.concatenate([np.zeros(N + Nh, dtype=np.complex128), W.ravel()])
+
+
+# the coupling of bond_rbm_params that puts |psi|^2 at the critical point of the
+# square-lattice Ising model: ln cosh(2 w) = K_c = ln(1 + sqrt 2) / 2
+W_CRITICAL = 0.5 * np.arccosh(np.exp(0.5 * np.log(1.0 + np.sqrt(2.0))))
+
+
 def cnn_num_params(channels: int, kernel: int) -> int:
     return channels * kernel * kernel + channels + channels * channels * kernel * kernel + channels
 

@@ -1,0 +1,72 @@
+"""GPU parity of the periodic CNN against the FP64 oracle: log psi, O_k and
+TFIM local energies (incremental window path and the small-torus path)."""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import cnn as ocnn, eloc as oeloc, lattice as olat
+from gpu_common import dev_bits, dev_c128, assert_logpsi_close, flush
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2108_03409_amd import nqsvmc as V  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return V.Context(0)
+
+
+def _cnn(ctx, Lx, Ly, C, k, std, seed):
+    p = si._normal_params(ocnn.num_params(C, k), std, True, seed=seed)
+    m = V.Model.cnn(ctx, Lx, Ly, C, k)
+    m.set_params(dev_c128(p))
+    return m, p
+
+
+GEOMS = [(16, 16, 16, 4, 0.05, 6), (4, 4, 2, 4, 0.3, 9), (6, 6, 3, 3, 0.3, 11), (7, 5, 2, 3, 0.4, 13),
+         (8, 8, 4, 2, 0.3, 17)]
+
+
+@pytest.mark.parametrize("Lx,Ly,C,k,std,B", GEOMS)
+def test_log_psi(ctx, Lx, Ly, C, k, std, B):
+    flush(f"cnn log_psi {Lx}x{Ly} C={C} k={k}")
+    m, p = _cnn(ctx, Lx, Ly, C, k, std, seed=Lx + C)
+    bits = si.random_bits(B, Lx * Ly, seed=3)
+    got = m.log_psi(dev_bits(si.pack_bits(bits))).cpu().numpy()
+    assert_logpsi_close(got, ocnn.log_psi(p, bits, Lx, Ly, C, k), 1e-10)
+
+
+@pytest.mark.parametrize("Lx,Ly,C,k,std,B", GEOMS)
+def test_grad(ctx, Lx, Ly, C, k, std, B):
+    flush(f"cnn grad {Lx}x{Ly} C={C} k={k}")
+    m, p = _cnn(ctx, Lx, Ly, C, k, std, seed=2 * Lx + C)
+    bits = si.random_bits(B, Lx * Ly, seed=4)
+    s = dev_bits(si.pack_bits(bits))
+    ref = ocnn.grad_log_psi(p, bits, Lx, Ly, C, k)
+    got = m.grad_log_psi(s, torch.complex128).cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-10 * max(1.0, np.abs(ref).max())
+    got32 = m.grad_log_psi(s, torch.complex64).cpu().numpy()
+    assert np.max(np.abs(got32 - ref)) <= 2.0 ** -22 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("Lx,Ly,C,k,std,B", [(16, 16, 16, 4, 0.05, 3), (4, 4, 2, 4, 0.3, 9), (6, 6, 3, 3, 0.3, 6),
+                                             (7, 5, 2, 3, 0.4, 7), (8, 8, 4, 2, 0.3, 5)])
+def test_local_energy(ctx, Lx, Ly, C, k, std, B):
+    flush(f"cnn eloc {Lx}x{Ly} C={C} k={k}")
+    m, p = _cnn(ctx, Lx, Ly, C, k, std, seed=3 * Lx + C)
+    H = V.Hamiltonian.tfim(ctx, Lx, Ly, True, 1.0, 3.0)
+    bits = si.random_bits(B, Lx * Ly, seed=5)
+    got = m.local_energy(H, dev_bits(si.pack_bits(bits))).cpu().numpy()
+    f = lambda b: ocnn.log_psi(p, b, Lx, Ly, C, k)
+    ref = oeloc.local_energy(f, "tfim", bits, Lx, Ly, True, 1.0, 3.0)
+    scale = []
+    for sb in bits:
+        sp, mel, cnt = olat.connected("tfim", sb, Lx, Ly, True, 1.0, 3.0)
+        scale.append(np.sum(np.abs(mel[:cnt] * np.exp(f(sp[:cnt]) - f(sb[None])[0]))))
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), scale)
+    assert np.all(err <= 1e-10), err.max()

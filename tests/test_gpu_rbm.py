@@ -149,3 +149,33 @@ def test_params_roundtrip_and_nonfinite(ctx):
     assert np.array_equal(m.get_params().cpu().numpy(), p)  # unchanged
     with pytest.raises(V.VMCError):
         V.Hamiltonian.tfim(ctx, 2, 1, True, 1.0, 1.0)  # periodic length 2 refused
+
+
+@pytest.mark.parametrize("kind", ["rbm", "cnn"])
+def test_autograd_wrapper_gradcheck_and_oracle(ctx, kind):
+    # torch.autograd.gradcheck on the library's forward/backward, plus the oracle
+    # gradient of a real loss sum_n Re(c_n log psi_n)
+    flush(f"autograd {kind}")
+    if kind == "rbm":
+        N, Nh = 6, 5
+        p = si.rbm_params(N, Nh, std=0.3, seed=12)
+        m = V.Model.rbm(ctx, N, Nh, True)
+        bits = si.random_bits(7, N, seed=13)
+        O_ref = orbm.grad_log_psi(p, bits, Nh)
+    else:
+        from oracle import cnn as ocnn
+        Lx, Ly, C, k = 4, 3, 2, 2
+        p = si._normal_params(ocnn.num_params(C, k), 0.3, True, seed=14)
+        m = V.Model.cnn(ctx, Lx, Ly, C, k)
+        bits = si.random_bits(7, Lx * Ly, seed=15)
+        O_ref = ocnn.grad_log_psi(p, bits, Lx, Ly, C, k)
+    s = dev_bits(si.pack_bits(bits))
+    theta = dev_c128(p).requires_grad_(True)
+    f = lambda th: V.log_psi_autograd(m, th, s)
+    assert torch.autograd.gradcheck(f, (theta,), eps=1e-6, atol=1e-6, rtol=1e-5)
+    c = np.random.default_rng(0).normal(size=len(bits)) + 1j * np.random.default_rng(1).normal(size=len(bits))
+    loss = (dev_c128(c) * f(theta)).real.sum()
+    loss.backward()
+    # d/d(theta) of Re(sum c_n f_n) in torch's convention: sum_n conj(c_n O_nk)
+    ref = np.conj(c @ O_ref)
+    assert np.max(np.abs(theta.grad.cpu().numpy() - ref)) < 1e-10 * max(1, np.abs(ref).max())

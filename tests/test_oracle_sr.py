@@ -134,3 +134,19 @@ def test_ar1_integrated_autocorrelation_time():
     assert abs(ess.batch_means_tau(x) - exact) < 0.15 * exact
     n_eff, _ = ess.ess(x)
     assert abs(n_eff - x.size / (2 * exact)) < 0.06 * x.size / (2 * exact)
+
+
+def test_package_ess_matches_oracle_and_ar1():
+    from paper_2108_03409_amd import stats as pstats
+    rho, T, C = 0.9, 4000, 8
+    rng = np.random.default_rng(6)
+    x = np.zeros((T, C))
+    e = rng.normal(size=(T, C))
+    for t in range(1, T):
+        x[t] = rho * x[t - 1] + e[t]
+    assert np.allclose(pstats.autocorrelation_fft(x), ess.autocorrelation(x), atol=1e-10)
+    t1, _ = pstats.tau_int(x)
+    t2, _ = ess.tau_int(x)
+    assert abs(t1 - t2) < 1e-8
+    exact = (1 + rho) / (2 * (1 - rho))
+    assert abs(t1 - exact) < 0.15 * exact
