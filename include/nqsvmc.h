@@ -115,8 +115,13 @@ int vmc_model_num_sites(const vmc_model* m, int* N);
 int vmc_model_set_params(vmc_model* m, const void* params_dev, int dtype);
 /* Writes the K parameters as complex128 (dtype C128) or complex64 (C64). */
 int vmc_model_get_params(const vmc_model* m, void* params_dev, int dtype);
-/* Precision of network evaluation: VMC_F64 (default) or VMC_F32 / VMC_BF16
- * where supported (VMC_ERR_UNSUPPORTED otherwise). */
+/* Precision of network evaluation in vmc_log_psi and vmc_local_energy:
+ * VMC_F64 (default) or, for the RBM, VMC_F32 / VMC_BF16: theta = b + W sigma on
+ * the matrix cores with float32 accumulation (bfloat16: every parameter
+ * rounded to bfloat16 first), log cosh / tanh and the connected-configuration
+ * ratios in float32, all sums over hidden units, sites and slots in float64.
+ * O_k (vmc_grad_log_psi), the sampler and the SR solve are unaffected.
+ * VMC_ERR_UNSUPPORTED for other models. */
 int vmc_model_set_precision(vmc_model* m, int prec);
 int vmc_model_destroy(vmc_model* m);
 

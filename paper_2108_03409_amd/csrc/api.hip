@@ -354,7 +354,8 @@ extern "C" int vmc_model_set_precision(vmc_model* m, int prec) {
   return guard(m ? m->ctx : nullptr, [&] {
     VMC_REQUIRE(m, "NULL model");
     VMC_REQUIRE(prec == VMC_F64 || prec == VMC_F32 || prec == VMC_BF16, "unknown precision");
-    if (prec != VMC_F64) throw vmc_error{VMC_ERR_UNSUPPORTED, "only VMC_F64 is implemented for this model"};
+    if (prec != VMC_F64 && m->kind != MODEL_RBM)
+      throw vmc_error{VMC_ERR_UNSUPPORTED, "float32 / bfloat16 evaluation is implemented for the RBM"};
     m->prec = prec;
   });
 }
@@ -365,6 +366,7 @@ extern "C" int vmc_model_destroy(vmc_model* m) {
   (void)hipStreamSynchronize(m->ctx->stream);
   if (m->params) (void)hipFree(m->params);
   if (m->Wt) (void)hipFree(m->Wt);
+  rbm_lowp_free(m);
   for (auto& t : m->tab) {
     if (t.T) (void)hipFree(t.T);
     if (t.D) (void)hipFree(t.D);
@@ -463,7 +465,9 @@ extern "C" int vmc_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double* l
     VMC_REQUIRE(s && logpsi, "NULL buffer");
     set_device(m->ctx);
     phase_scope ps(m->ctx, "log_psi");
-    if (m->kind == MODEL_RBM)
+    if (m->kind == MODEL_RBM && m->prec != VMC_F64)
+      rbm_lowp_log_psi(m, s, B, (double2*)logpsi);
+    else if (m->kind == MODEL_RBM)
       rbm_log_psi(m, s, B, (double2*)logpsi);
     else
       cnn_log_psi(m, s, B, (double2*)logpsi);
@@ -482,7 +486,9 @@ extern "C" int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int
     VMC_REQUIRE(s && eloc, "NULL buffer");
     set_device(m->ctx);
     phase_scope ps(m->ctx, "eloc");
-    if (m->kind == MODEL_RBM)
+    if (m->kind == MODEL_RBM && m->prec != VMC_F64)
+      rbm_lowp_local_energy(m, H, s, B, (double2*)eloc);
+    else if (m->kind == MODEL_RBM)
       rbm_local_energy(m, H, s, B, (double2*)eloc);
     else
       cnn_local_energy(m, H, s, B, (double2*)eloc);

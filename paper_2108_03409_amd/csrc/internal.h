@@ -107,6 +107,18 @@ struct vmc_model {
   double2* params = nullptr;  // K complex float64 master copy (device)
   double2* Wt = nullptr;      // RBM: W transposed [N][N_h]
   rbm_move_tables tab[2];     // flip / exchange tables
+  // float32 / bfloat16 evaluation (RBM): parameters rounded to the precision,
+  // stored as float32; rebuilt when the parameters or the precision change
+  uint64_t lowp_version = 0;
+  int lowp_prec = -1;
+  float2* Wt32 = nullptr;   // [N][N_h]
+  float2* ab32 = nullptr;   // [N + N_h]: a then b
+  struct lowp_tables {
+    uint64_t version = 0;
+    int prec = -1, n_moves = 0;
+    const vmc_ham* ham = nullptr;
+    float2 *T = nullptr, *LC = nullptr, *alpha = nullptr;
+  } tab32[2];
 };
 
 // ----------------------------------------------------------- Hamiltonians --
@@ -211,6 +223,52 @@ __device__ __forceinline__ double2 ctanh(double2 z) {
   return neg ? make_double2(-r.x, -r.y) : r;
 }
 
+// float32 complex helpers (low-precision network evaluation)
+__device__ __forceinline__ float2 fcadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 fcmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 fcdiv(float2 a, float2 b) {
+  if (fabsf(b.x) >= fabsf(b.y)) {
+    float r = b.y / b.x, d = b.x + b.y * r;
+    return make_float2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  } else {
+    float r = b.x / b.y, d = b.x * r + b.y;
+    return make_float2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+  }
+}
+__device__ __forceinline__ float2 fclog(float2 z) { return make_float2(logf(hypotf(z.x, z.y)), atan2f(z.y, z.x)); }
+__device__ __forceinline__ float2 fcexp(float2 z) {
+  float e = expf(z.x), s, c;
+  sincosf(z.y, &s, &c);
+  return make_float2(e * c, e * s);
+}
+__device__ __forceinline__ float2 fclogcosh(float2 z) {
+  if (z.x < 0.f) z = make_float2(-z.x, -z.y);
+  float e = expf(-2.f * z.x), s, c;
+  sincosf(-2.f * z.y, &s, &c);
+  float er = e * c, ei = e * s;
+  float lr = 0.5f * log1pf(2.f * er + er * er + ei * ei);
+  float li = atan2f(ei, 1.f + er);
+  return make_float2(z.x - 0.69314718f + lr, z.y + li);
+}
+__device__ __forceinline__ float2 fctanh(float2 z) {
+  bool neg = z.x < 0.f;
+  if (neg) z = make_float2(-z.x, -z.y);
+  float e = expf(-2.f * z.x), s, c;
+  sincosf(-2.f * z.y, &s, &c);
+  float2 w = make_float2(e * c, e * s);
+  float2 r = fcdiv(make_float2(1.f - w.x, -w.y), make_float2(1.f + w.x, w.y));
+  return neg ? make_float2(-r.x, -r.y) : r;
+}
+// round-to-nearest-even float32 -> bfloat16 -> float32
+__device__ __forceinline__ float bf16_round(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return x;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
 __device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
 #pragma unroll
@@ -263,6 +321,10 @@ void cnn_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
 void cnn_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
 // vjp.hip
 void log_psi_vjp_impl(vmc_model* m, const uint64_t* s, int64_t B, const double2* g, double2* out);
+// rbm_lowp.hip
+void rbm_lowp_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* logpsi);
+void rbm_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
+void rbm_lowp_free(vmc_model* m);
 // sampler.hip
 void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
 // gemm64.hip: C = beta C + op(A) op(B) in float64 with arbitrary strides
