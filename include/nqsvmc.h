@@ -243,6 +243,12 @@ typedef struct {
   double eps_abs;    /* additive shift */
   int mode;          /* VMC_SR_COMPLEX | VMC_SR_REAL | VMC_SR_IMAG */
   double gamma_re, gamma_im;  /* gamma = 1: SR / imaginary time; gamma = i: real time */
+  int gram;          /* S product: 0 = by O dtype (float32 matrix cores for C64,
+                        float64 for C128); 1 = split-float16 matrix-core products
+                        (C64 input only): each centred value is scaled per column
+                        by a power of two and split into hi + lo float16 parts,
+                        three products per term, float32 accumulation, relative
+                        error ~2^-21 per product term */
 } vmc_sr_opts;
 typedef struct {
   double e_mean[2];  /* <E_loc> */

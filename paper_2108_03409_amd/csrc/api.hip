@@ -698,6 +698,8 @@ extern "C" int vmc_sr_solve(vmc_ctx* ctx, const void* O, int O_dtype, const doub
                 "unknown mode");
     if (opts->mode == VMC_SR_IMAG)
       throw vmc_error{VMC_ERR_UNSUPPORTED, "Im S is antisymmetric; the Cholesky solve needs COMPLEX or REAL"};
+    VMC_REQUIRE(opts->gram == 0 || opts->gram == 1, "gram must be 0 or 1");
+    VMC_REQUIRE(opts->gram == 0 || O_dtype == VMC_DT_C64, "the split-float16 product needs complex64 O");
     set_device(ctx);
     sr_solve_impl(ctx, O, O_dtype, (const double2*)eloc, weights, N, K, opts, (double2*)x, &info);
     if (info.fail_index >= 0)

@@ -13,9 +13,8 @@
 //   k_zmfma<1>    trailing update A_rc -= L_rp L_cp^H (reduction depth 256) on
 //                 the lower 64 x 64 tiles of the trailing matrix, so the
 //                 trailing matrix is read and written once per 256 columns.
-// The complex products use four real accumulators per 16x16 block held in the
-// same lanes (RR, II, IR, RI), so re = RR + II and im = IR - RI are formed
-// in-register.  A non-positive pivot sets the fail index; every later kernel
+// The complex products use two real accumulators per 16x16 block held in the
+// same lanes: re += Pr Qr + Pi Qi and im += Pi Qr + Pr (-Qi) for P conj(Q).  A non-positive pivot sets the fail index; every later kernel
 // then exits at once.  The upper triangle of S~ is never written.
 //
 // Triangular solves: one launch per block; every group recomputes the 64-entry
@@ -175,13 +174,13 @@ __global__ __launch_bounds__(256) void k_zmfma(zargs a) {
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
 
-  doublex4 acc[2][2][4];
+  doublex4 acc[2][2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[i][j][q] = doublex4{0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < 2; ++q) acc[i][j][q] = doublex4{0.0, 0.0, 0.0, 0.0};
 
   double2 rp[4], rq[4];
   auto gload = [&](int m0) {
@@ -228,9 +227,9 @@ __global__ __launch_bounds__(256) void k_zmfma(zargs a) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           acc[i][j][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].x, fb[j].x, acc[i][j][0], 0, 0, 0);
-          acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].y, acc[i][j][1], 0, 0, 0);
-          acc[i][j][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].x, acc[i][j][2], 0, 0, 0);
-          acc[i][j][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].x, fb[j].y, acc[i][j][3], 0, 0, 0);
+          acc[i][j][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].y, acc[i][j][0], 0, 0, 0);
+          acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].x, acc[i][j][1], 0, 0, 0);
+          acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].x, -fb[j].y, acc[i][j][1], 0, 0, 0);
         }
     }
     if (st + 1 < nst) sstore(buf ^ 1);
@@ -246,8 +245,8 @@ __global__ __launch_bounds__(256) void k_zmfma(zargs a) {
         // D[l / 16 + 4 r][l % 16] (float32 holds D[4 (l / 16) + r][l % 16])
         const int row = wr * 32 + i * 16 + lk + 4 * r;
         const int col = wc * 32 + j * 16 + li;
-        const double re = acc[i][j][0][r] + acc[i][j][1][r];
-        const double im = acc[i][j][2][r] - acc[i][j][3][r];
+        const double re = acc[i][j][0][r];
+        const double im = acc[i][j][1][r];
         const int64_t R = r0 + row;
         if (R >= K) continue;
         if (MODE == 0) {

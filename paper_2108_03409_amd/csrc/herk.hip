@@ -1,15 +1,15 @@
 // S = Obar^H Obar on the float32 matrix cores (eq:qfm with centred data).
 //
 // Obar is N_s x K complex64, sample-major.  For a complex 16x16 output block
-// (rows k, columns k') the kernel keeps four float32 MFMA accumulators at the
+// (rows k, columns k') the kernel keeps two float32 MFMA accumulators at the
 // same lane positions,
-//   RR = sum_n Re O_nk Re O_nk',  II = sum Im Im,  RI = sum Re Im',  IR = sum Im Re',
-// so that S_kk' = (RR + II) + i (RI - IR) is formed in-register.  One
+//   re += Re O_nk Re O_nk' + Im O_nk Im O_nk',   im += Re O_nk Im O_nk' + (-Im O_nk) Re O_nk',
+// so S_kk' = re + i im is complete in-register (four MFMAs per 4 samples).  One
 // v_mfma_f32_16x16x4_f32 consumes 4 samples; a lane's A and B fragments are one
 // float2 (re, im) each, read from LDS.
 //
 // Work-group tile: 128 complex rows x 64 complex columns, 4 waves (2 x 2),
-// each wave 64 x 32 (4 x 2 blocks of 16 x 16, 128 accumulator registers).
+// each wave 64 x 32 (4 x 2 blocks of 16 x 16, 64 accumulator registers).
 // Samples are staged 16 at a time through double-buffered LDS.  Only tiles
 // that touch the lower triangle are launched; the linear tile index is
 // remapped so that consecutive tiles of one row stripe run on the same XCD
@@ -67,13 +67,13 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;  // wave position in the 2 x 2 grid
 
-  floatx4 acc[4][2][4];
+  floatx4 acc[4][2][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[i][j][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int q = 0; q < 2; ++q) acc[i][j][q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   // global -> register staging: A 16 x 128 float2 (8 per thread), B 16 x 64 (4 per thread)
   float2 ra[8], rb[4];
@@ -127,9 +127,9 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].x, acc[i][j][0], 0, 0, 0);
-          acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].y, acc[i][j][1], 0, 0, 0);
-          acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].y, acc[i][j][2], 0, 0, 0);
-          acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].x, acc[i][j][3], 0, 0, 0);
+          acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].y, acc[i][j][0], 0, 0, 0);
+          acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].y, acc[i][j][1], 0, 0, 0);
+          acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(-fa[i].y, fb[j].x, acc[i][j][1], 0, 0, 0);
         }
     }
     if (st + 1 < n_stages) {
@@ -148,8 +148,8 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
         const int64_t k = row0 + wr * 64 + i * 16 + 4 * lk + r;
         const int64_t kp = col0 + wc * 32 + j * 16 + li;
         if (k >= K || kp >= K || kp > k) continue;
-        double re = (double)acc[i][j][0][r] + (double)acc[i][j][1][r];
-        double im = (double)acc[i][j][2][r] - (double)acc[i][j][3][r];
+        double re = (double)acc[i][j][0][r];
+        double im = (double)acc[i][j][1][r];
         if (a.mode == VMC_SR_REAL) im = 0.0;
         if (k == kp) {
           const double2 d = make_double2(re * (1.0 + a.nu) + a.eps, 0.0);

@@ -347,6 +347,10 @@ size_t chol_linv_bytes(int64_t K);
 int chol_block();
 void chol_factor(vmc_ctx* ctx, double2* S, int64_t K, double2* Linv, long long* fail, double* pivmin);
 void chol_solve(vmc_ctx* ctx, const double2* S, int64_t K, const double2* Linv, double2* rhs, double2* y, double2* x);
+// herk16.hip
+size_t herk16_ws_bytes(int64_t N, int64_t K);
+void herk_split16(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode, double nu, double eps, double2* S,
+                  double2* diag, void* ws);
 // sr.hip
 void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N,
                    int64_t K, const vmc_sr_opts* o, double2* x, vmc_sr_info* info);

@@ -280,7 +280,8 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   const int nblk = (int)((K + CB - 1) / CB);
   const bool f32 = dtype == VMC_DT_C64;
   const size_t xsz = (f32 ? sizeof(float2) : sizeof(double2)) * (size_t)N * K;
-  size_t total = ws_round(64) + ws_round(sizeof(double2) * npart * K) + ws_round(sizeof(double2) * K) * 7 +
+  const bool split16 = o->gram == 1;
+  size_t total = (split16 ? herk16_ws_bytes(N, K) : 0) + ws_round(64) + ws_round(sizeof(double2) * npart * K) + ws_round(sizeof(double2) * K) * 7 +
                  ws_round(chol_linv_bytes(K)) +
                  ws_round(xsz) + ws_round(sizeof(double2) * (size_t)K * K) + ws_round(sizeof(double) * nblk) +
                  ws_round(sizeof(long long)) + ws_round(sizeof(double) * 4);
@@ -300,6 +301,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   double* pivmin = (double*)ws_take(ctx, sizeof(double) * nblk);
   long long* fail = (long long*)ws_take(ctx, sizeof(long long));
   double* norms = (double*)ws_take(ctx, sizeof(double) * 4);
+  void* h16ws = split16 ? ws_take(ctx, herk16_ws_bytes(N, K)) : nullptr;
 
   std::unique_ptr<phase_scope> ph(new phase_scope(ctx, "sr.center"));
   k_energy_stats<<<1, 1024, 0, st>>>(eloc, w, N, stats);
@@ -323,7 +325,9 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   ph.reset(new phase_scope(ctx, "sr.herk"));
   const unsigned nb32 = (unsigned)((K + 31) / 32);
   dim3 hg(nb32, nb32);
-  if (f32)
+  if (split16)
+    herk_split16(ctx, (const float2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag, h16ws);
+  else if (f32)
     herk_mfma_f32(ctx, (const float2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag);
   else
     k_herk_simple<double2><<<hg, 256, 0, st>>>((const double2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag);

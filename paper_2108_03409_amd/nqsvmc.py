@@ -42,7 +42,7 @@ class SamplerOpts(C.Structure):
 
 class SROpts(C.Structure):
     _fields_ = [("nu_rel", C.c_double), ("eps_abs", C.c_double), ("mode", C.c_int),
-                ("gamma_re", C.c_double), ("gamma_im", C.c_double)]
+                ("gamma_re", C.c_double), ("gamma_im", C.c_double), ("gram", C.c_int)]
 
 
 class SRInfo(C.Structure):
@@ -404,13 +404,13 @@ class MADE:
 
 
 def sr_solve(ctx: Context, O: torch.Tensor, eloc: torch.Tensor, *, weights=None, nu_rel=1e-3, eps_abs=0.0,
-             mode=SR_COMPLEX, gamma=1.0, raise_on_error=True):
+             mode=SR_COMPLEX, gamma=1.0, gram=0, raise_on_error=True):
     """Returns (x, info dict).  O: (N, K) complex64/complex128; eloc: (N,) complex128."""
     N, K = O.shape
     dt = DT_C128 if O.dtype == torch.complex128 else DT_C64
     x = torch.empty(K, dtype=torch.complex128, device=O.device)
     g = complex(gamma)
-    opts = SROpts(nu_rel, eps_abs, mode, g.real, g.imag)
+    opts = SROpts(nu_rel, eps_abs, mode, g.real, g.imag, gram)
     info = SRInfo()
     rc = load().vmc_sr_solve(ctx.h, _ptr(O), dt, _ptr(eloc), _ptr(weights), N, K, C.byref(opts), _ptr(x),
                              C.byref(info))

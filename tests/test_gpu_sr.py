@@ -55,22 +55,25 @@ def test_sr_solve_fp64_matches_oracle(ctx, N, Nh, ns, mode, gamma, nu, eps, weig
     assert abs(info["min_pivot"] - info_ref["min_pivot"]) <= 1e-9 * abs(info_ref["min_pivot"])
 
 
+@pytest.mark.parametrize("gram", [0, 1])
 @pytest.mark.parametrize("N,Nh,ns,weighted", [(16, 32, 4096, False), (5, 7, 9, True), (9, 21, 1001, False),
                                               (12, 48, 333, True)])
-def test_sr_solve_fp32_gram_within_bound(ctx, N, Nh, ns, weighted):
-    # S from complex64 O on the float32 matrix path; |dS| <= gamma_N sum |Obar||Obar| (Higham)
-    flush(f"sr fp32 N={N} Nh={Nh} ns={ns}")
+def test_sr_solve_fp32_gram_within_bound(ctx, N, Nh, ns, weighted, gram):
+    # S from complex64 O on the matrix cores: float32 products (gram 0) or split
+    # float16 products (gram 1, 2^-21 per term); |dS| <= (u + gamma_N) sum |Obar||Obar|
+    flush(f"sr c64 gram={gram} N={N} Nh={Nh} ns={ns}")
     O, el = _problem(N, Nh, ns, 0.2, seed=5 + N)
     w = np.random.default_rng(4).uniform(0.5, 1.5, ns) if weighted else None
     x_ref, _ = osr.sr_solve(O.astype(np.complex64).astype(np.complex128), el, nu_rel=1e-2, weights=w)
     x, info = V.sr_solve(ctx, torch.from_numpy(O.astype(np.complex64)).to("cuda:0"), dev_c128(el), nu_rel=1e-2,
-                         weights=None if w is None else torch.from_numpy(w).to("cuda:0"))
+                         weights=None if w is None else torch.from_numpy(w).to("cuda:0"), gram=gram)
     x = x.cpu().numpy()
     S, _ = osr.fisher_and_force(O, el, w)
     St = osr.shifted(S, 1e-2)
     kappa = np.linalg.cond(St)
     err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
-    bound = kappa * 4 * np.sqrt(ns) * 2.0 ** -24 + 1e-12
+    u = 2.0 ** -24 if gram == 0 else 2.0 ** -21
+    bound = kappa * 4 * (np.sqrt(ns) * 2.0 ** -24 + u) + 1e-12
     assert err <= bound, (err, bound)
     assert info["residual"] < 1e-10
 
