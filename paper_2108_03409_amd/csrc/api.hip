@@ -544,7 +544,7 @@ extern "C" int vmc_sampler_create(vmc_ctx* ctx, vmc_model* m, vmc_ham* H, const 
     }
     if (o->proposal == VMC_PROP_MADE_MIX)
       VMC_REQUIRE(o->p_global >= 0.0 && o->p_global <= 1.0, "p_global must be in [0, 1]");
-    VMC_REQUIRE(m->kind == MODEL_RBM, "sampler supports RBM models");
+    VMC_REQUIRE(m->kind == MODEL_RBM || o->proposal == VMC_PROP_FLIP, "CNN models are sampled with single flips");
     set_device(ctx);
     auto* S = new vmc_sampler;
     S->ctx = ctx;
@@ -587,7 +587,10 @@ extern "C" int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, do
     uint64_t t0 = S->t;
     {
       phase_scope ps(S->ctx, "sample");
-      sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
+      if (S->model->kind == MODEL_CNN)
+        cnn_sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
+      else
+        sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
     }
     const int nc = S->opts.n_chains;
     const int nrows = S->opts.proposal == VMC_PROP_MADE_MIX ? 3 : 1;

@@ -260,6 +260,128 @@ __global__ __launch_bounds__(256) void k_cnn_eloc(cnn_geom g, const uint64_t* __
   if (tid == 0) eloc[b] = make_double2(acc.x + diag, acc.y);
 }
 
+// Metropolis chains for the CNN (single-spin flips; the randomness of
+// sampler.hip): one work-group per chain, z2 and Re log cosh(z2) of the current
+// configuration in LDS, layer 1 of the chain in global scratch.  A proposal
+// evaluates Re(log psi(s') - log psi(s)) on the (2k-1) x (2k-1) window only;
+// on acceptance the window of z2 is updated in place.
+__global__ __launch_bounds__(256) void k_cnn_metropolis(cnn_geom g, int n_chains, uint64_t* __restrict__ bits,
+                                                        uint2 key, uint64_t t0, int init, int64_t therm_steps,
+                                                        int64_t n_record, int sweep, uint64_t* __restrict__ s_out,
+                                                        double2* __restrict__ logpsi_out,
+                                                        unsigned long long* __restrict__ acc,
+                                                        double2* __restrict__ a1_scratch) {
+  extern __shared__ double2 sm[];
+  const int CN = g.C * g.N, kk = g.k * g.k, win = 2 * g.k - 1;
+  double2* Z2 = sm;                        // [C][N]
+  double* RL = (double*)(sm + CN);         // [C][N] Re logcosh(z2)
+  double2* DA = sm + CN + (CN + 1) / 2;    // [C][kk]
+  double2* red = DA + g.C * kk;            // [4]
+  uint64_t* cb = (uint64_t*)(red + 4);     // [W]
+  const int c = blockIdx.x;
+  if (c >= n_chains) return;
+  const int tid = threadIdx.x;
+  double2* a1 = a1_scratch + (int64_t)c * CN;
+  if (init) {
+    if (tid == 0)
+      for (int w = 0; w < g.W; ++w) {
+        uint4 y = philox(make_uint4((uint32_t)c, (uint32_t)(w >> 1), 0u, 2u), key);
+        uint64_t word = (w & 1) ? ((uint64_t)y.z | ((uint64_t)y.w << 32)) : ((uint64_t)y.x | ((uint64_t)y.y << 32));
+        const int rem = g.N - 64 * w;
+        if (rem < 64) word &= (1ull << rem) - 1ull;
+        cb[w] = word;
+      }
+  } else {
+    for (int w = tid; w < g.W; w += 256) cb[w] = bits[(int64_t)c * g.W + w];
+  }
+  __syncthreads();
+  for (int e = tid; e < CN; e += 256) a1[e] = clogcosh(z1_at(g, cb, e / g.N, e % g.N));
+  __syncthreads();
+  for (int e = tid; e < CN; e += 256) {
+    const double2 z = z2_at(g, a1, e / g.N, e % g.N);
+    Z2[e] = z;
+    RL[e] = clogcosh(z).x;
+  }
+  __syncthreads();
+  unsigned long long accepted = 0;
+  const int64_t total = therm_steps + n_record * sweep;
+  constexpr int MAXOUT = 8;  // window outputs per thread (C (2k-1)^2 <= 2048)
+  for (int64_t step = 0; step < total; ++step) {
+    const uint64_t t = t0 + (uint64_t)step;
+    const uint4 x = philox(make_uint4((uint32_t)c, (uint32_t)t, (uint32_t)(t >> 32), 0u), key);
+    const int site = (int)to_index(x.x, (uint32_t)g.N);
+    const double u = to_uniform(x.y, x.z);
+    const double ds = -2.0 * sig_at(cb, site);
+    const int Ys = site / g.Lx, Xs = site % g.Lx;
+    for (int e = tid; e < g.C * kk; e += 256) {
+      const int ch = e / kk, tp = e % kk, dy = tp / g.k, dx = tp % g.k;
+      const int p = shift_pos(g, site, -dy, -dx);
+      const double2 z = z1_at(g, cb, ch, p);
+      const double2 w = g.W1[(ch * g.k + dy) * g.k + dx];
+      DA[e] = csub(clogcosh(make_double2(z.x + ds * w.x, z.y + ds * w.y)), a1[ch * g.N + p]);
+    }
+    __syncthreads();
+    double2 dzs[MAXOUT];
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < MAXOUT; ++q) {
+      const int e = tid + 256 * q;
+      dzs[q] = make_double2(0.0, 0.0);
+      if (e >= g.C * win * win) continue;
+      const int ch = e / (win * win), r = e % (win * win), ey = r / win, ex = r % win;
+      double2 dz = make_double2(0.0, 0.0);
+      for (int dy1 = max(0, ey - g.k + 1); dy1 <= min(g.k - 1, ey); ++dy1)
+        for (int dx1 = max(0, ex - g.k + 1); dx1 <= min(g.k - 1, ex); ++dx1)
+          for (int ci = 0; ci < g.C; ++ci)
+            dz = cadd(dz, cmul(g.W2[((ch * g.C + ci) * g.k + ey - dy1) * g.k + ex - dx1],
+                               DA[ci * kk + dy1 * g.k + dx1]));
+      dzs[q] = dz;
+      int qy = Ys - ey, qx = Xs - ex;
+      if (qy < 0) qy += g.Ly;
+      if (qx < 0) qx += g.Lx;
+      const int qi = ch * g.N + qy * g.Lx + qx;
+      part += clogcosh(cadd(Z2[qi], dz)).x - RL[qi];
+    }
+    const double r = 2.0 * block_sum(make_double2(part, 0.0), red).x;
+    const bool accept = (r >= 0.0) || (u < exp(r));
+    if (accept) {
+      ++accepted;
+#pragma unroll
+      for (int q = 0; q < MAXOUT; ++q) {
+        const int e = tid + 256 * q;
+        if (e >= g.C * win * win) continue;
+        const int ch = e / (win * win), rr = e % (win * win), ey = rr / win, ex = rr % win;
+        int qy = Ys - ey, qx = Xs - ex;
+        if (qy < 0) qy += g.Ly;
+        if (qx < 0) qx += g.Lx;
+        const int qi = ch * g.N + qy * g.Lx + qx;
+        const double2 zn = cadd(Z2[qi], dzs[q]);
+        Z2[qi] = zn;
+        RL[qi] = clogcosh(zn).x;
+      }
+      for (int e = tid; e < g.C * kk; e += 256) {
+        const int ch = e / kk, tp = e % kk, dy = tp / g.k, dx = tp % g.k;
+        const int p = shift_pos(g, site, -dy, -dx);
+        a1[ch * g.N + p] = cadd(a1[ch * g.N + p], DA[e]);
+      }
+      __syncthreads();
+      if (tid == 0) cb[site >> 6] ^= 1ull << (site & 63);
+    }
+    __syncthreads();
+    if (step >= therm_steps && ((step - therm_steps + 1) % sweep) == 0) {
+      const int64_t kr = (step - therm_steps + 1) / sweep - 1;
+      const int64_t row = kr * n_chains + c;
+      for (int w = tid; w < g.W; w += 256) s_out[row * g.W + w] = cb[w];
+      double2 lp = make_double2(0.0, 0.0);
+      for (int e = tid; e < CN; e += 256) lp = cadd(lp, clogcosh(Z2[e]));
+      lp = block_sum(lp, red);
+      if (tid == 0 && logpsi_out) logpsi_out[row] = lp;
+    }
+  }
+  for (int w = tid; w < g.W; w += 256) bits[(int64_t)c * g.W + w] = cb[w];
+  if (tid == 0) acc[c] = accepted;
+}
+
 constexpr int64_t kChunk = 1 << 14;
 
 cnn_geom geom(const vmc_model* m) {
@@ -326,4 +448,27 @@ void cnn_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, do
                                                         eloc + b0, a1);
     VMC_HIP(hipGetLastError());
   }
+}
+
+void cnn_sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out) {
+  vmc_model* m = S->model;
+  const cnn_geom g = geom(m);
+  VMC_REQUIRE(S->opts.proposal == VMC_PROP_FLIP, "the CNN sampler uses single-spin flips");
+  VMC_REQUIRE(g.Lx >= 2 * g.k - 1 && g.Ly >= 2 * g.k - 1, "the CNN sampler needs Lx, Ly >= 2 kernel - 1");
+  VMC_REQUIRE(g.C * (2 * g.k - 1) * (2 * g.k - 1) <= 8 * 256, "CNN window too large for the sampler");
+  const int CN = g.C * g.N, kk = g.k * g.k;
+  const size_t lds = sizeof(double2) * ((size_t)CN + (CN + 1) / 2 + (size_t)g.C * kk + 4) + sizeof(uint64_t) * g.W;
+  allow_lds(k_cnn_metropolis, lds);
+  vmc_ctx* ctx = S->ctx;
+  ws_reserve(ctx, ws_round(sizeof(double2) * (size_t)S->opts.n_chains * CN));
+  double2* a1 = (double2*)ws_take(ctx, sizeof(double2) * (size_t)S->opts.n_chains * CN);
+  const int64_t therm = S->thermalized ? 0 : (int64_t)S->opts.therm_sweeps * S->opts.sweep_steps;
+  const uint2 key = make_uint2((uint32_t)S->opts.seed, (uint32_t)(S->opts.seed >> 32));
+  k_cnn_metropolis<<<S->opts.n_chains, 256, lds, ctx->stream>>>(g, S->opts.n_chains, S->bits, key, S->t,
+                                                                 !S->bits_valid, therm, n_per_chain,
+                                                                 S->opts.sweep_steps, s_out, logpsi_out, S->acc, a1);
+  VMC_HIP(hipGetLastError());
+  S->t += (uint64_t)(therm + n_per_chain * S->opts.sweep_steps);
+  S->thermalized = 1;
+  S->bits_valid = 1;
 }

@@ -70,3 +70,26 @@ def test_local_energy(ctx, Lx, Ly, C, k, std, B):
         scale.append(np.sum(np.abs(mel[:cnt] * np.exp(f(sp[:cnt]) - f(sb[None])[0]))))
     err = np.abs(got - ref) / np.maximum(np.abs(ref), scale)
     assert np.all(err <= 1e-10), err.max()
+
+
+def test_sampler_replay(ctx):
+    # the CNN chains follow the same Philox stream as the oracle's Metropolis chains
+    from oracle import metropolis as omet
+    from gpu_common import host_bits
+    flush("cnn sampler replay")
+    Lx, Ly, C, k, nc, per = 8, 8, 3, 3, 8, 3
+    m, p = _cnn(ctx, Lx, Ly, C, k, 0.3, seed=21)
+    H = V.Hamiltonian.tfim(ctx, Lx, Ly, True, 1.0, 3.0)
+    S = V.Sampler(ctx, m, H, proposal=V.PROP_FLIP, n_chains=nc, therm_sweeps=2, seed=104)
+    s, lp, acc = S.sample(nc * per)
+    s = host_bits(s).reshape(per, nc, -1)
+    lp = lp.cpu().numpy().reshape(per, nc)
+    f = lambda b: ocnn.log_psi(p, b, Lx, Ly, C, k)
+    ch = omet.Chains(f, Lx * Ly, "flip", seed=104, chain_ids=np.arange(nc), therm_sweeps=2)
+    os_, ol = ch.sample(per)
+    assert ch.near_ties == 0
+    for c in range(nc):
+        for kk in range(per):
+            assert np.array_equal(s[kk, c], si.pack_bits(os_[kk, c])[0]), (kk, c)
+    assert_logpsi_close(lp.ravel(), ol.ravel(), 1e-9)
+    assert 0 < acc <= 1
