@@ -75,6 +75,12 @@ typedef struct vmc_made vmc_made;
 /* ---- context ------------------------------------------------------------ */
 /* Binds a HIP device and stream (hip_stream may be NULL: the null stream).  */
 int vmc_ctx_create(int hip_device, void* hip_stream, vmc_ctx** out);
+/* Releases the caller's handle.  Every model, Hamiltonian, sampler and MADE
+ * created from the context holds a reference of its own, so the handle may be
+ * released before them (in any order); the context and its workspace are
+ * freed when the last reference goes.  Each *_destroy synchronises the
+ * context's stream first.  A sampler borrows its model and Hamiltonian: they
+ * must outlive its last vmc_sampler_sample call, not its destroy.            */
 int vmc_ctx_destroy(vmc_ctx* ctx);
 int vmc_ctx_sync(vmc_ctx* ctx);
 /* Message of the last failed call on ctx ("" if none).  Valid until the next call. */
@@ -120,8 +126,13 @@ int vmc_model_get_params(const vmc_model* m, void* params_dev, int dtype);
  * the matrix cores with float32 accumulation (bfloat16: every parameter
  * rounded to bfloat16 first), log cosh / tanh and the connected-configuration
  * ratios in float32, all sums over hidden units, sites and slots in float64.
- * O_k (vmc_grad_log_psi), the sampler and the SR solve are unaffected.
- * VMC_ERR_UNSUPPORTED for other models. */
+ * For the CNN the setting applies to TFIM local energies only (log psi stays
+ * float64): the layer-1 log-cosh changes of all flips form one matrix that
+ * multiplies a fixed matrix built from W2 on the matrix cores (bfloat16
+ * operands with VMC_BF16, float32 with VMC_F32; float32 accumulation), layer
+ * activations and log cosh in float32, window and slot sums in float64; it
+ * needs Lx, Ly >= 2 kernel - 1 (else VMC_ERR_UNSUPPORTED).
+ * O_k (vmc_grad_log_psi), the sampler and the SR solve are unaffected. */
 int vmc_model_set_precision(vmc_model* m, int prec);
 int vmc_model_destroy(vmc_model* m);
 

@@ -169,8 +169,10 @@ extern "C" int vmc_ctx_create(int hip_device, void* hip_stream, vmc_ctx** out) {
   });
 }
 
-extern "C" int vmc_ctx_destroy(vmc_ctx* ctx) {
-  if (!ctx) return VMC_ERR_INVALID_ARG;
+void ctx_retain(vmc_ctx* ctx) { ctx->refs.fetch_add(1); }
+
+void ctx_release(vmc_ctx* ctx) {
+  if (ctx->refs.fetch_sub(1) != 1) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws.base) (void)hipFree(ctx->ws.base);
@@ -181,6 +183,11 @@ extern "C" int vmc_ctx_destroy(vmc_ctx* ctx) {
   }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   delete ctx;
+}
+
+extern "C" int vmc_ctx_destroy(vmc_ctx* ctx) {
+  if (!ctx) return VMC_ERR_INVALID_ARG;
+  ctx_release(ctx);
   return VMC_OK;
 }
 
@@ -226,6 +233,7 @@ extern "C" int vmc_model_create_rbm(vmc_ctx* ctx, int n_visible, int n_hidden, i
       delete m;
       throw;
     }
+    ctx_retain(ctx);
     *out = m;
   });
 }
@@ -259,6 +267,7 @@ extern "C" int vmc_model_create_cnn(vmc_ctx* ctx, int Lx, int Ly, int channels, 
       delete m;
       throw;
     }
+    ctx_retain(ctx);
     *out = m;
   });
 }
@@ -354,8 +363,8 @@ extern "C" int vmc_model_set_precision(vmc_model* m, int prec) {
   return guard(m ? m->ctx : nullptr, [&] {
     VMC_REQUIRE(m, "NULL model");
     VMC_REQUIRE(prec == VMC_F64 || prec == VMC_F32 || prec == VMC_BF16, "unknown precision");
-    if (prec != VMC_F64 && m->kind != MODEL_RBM)
-      throw vmc_error{VMC_ERR_UNSUPPORTED, "float32 / bfloat16 evaluation is implemented for the RBM"};
+    if (prec != VMC_F64 && m->kind == MODEL_CNN && (m->Lx < 2 * m->k - 1 || m->Ly < 2 * m->k - 1))
+      throw vmc_error{VMC_ERR_UNSUPPORTED, "float32 / bfloat16 CNN local energies need Lx, Ly >= 2 kernel - 1"};
     m->prec = prec;
   });
 }
@@ -373,7 +382,9 @@ extern "C" int vmc_model_destroy(vmc_model* m) {
     if (t.LC) (void)hipFree(t.LC);
     if (t.alpha) (void)hipFree(t.alpha);
   }
+  vmc_ctx* ctx = m->ctx;
   delete m;
+  ctx_release(ctx);
   return VMC_OK;
 }
 
@@ -385,8 +396,10 @@ static int make_ham(vmc_ctx* ctx, int kind, int Lx, int Ly, int periodic, double
     VMC_REQUIRE(std::isfinite(J) && std::isfinite(h), "couplings must be finite");
     if (periodic) VMC_REQUIRE(Lx >= 3 && (Ly == 1 || Ly >= 3), "a periodic direction needs length >= 3");
     set_device(ctx);
+    static std::atomic<uint64_t> next_uid{1};
     auto* H = new vmc_ham;
     H->ctx = ctx;
+    H->uid = next_uid.fetch_add(1);
     H->kind = kind;
     H->Lx = Lx;
     H->Ly = Ly;
@@ -412,6 +425,7 @@ static int make_ham(vmc_ctx* ctx, int kind, int Lx, int Ly, int periodic, double
       delete H;
       throw;
     }
+    ctx_retain(ctx);
     *out = H;
   });
 }
@@ -452,7 +466,9 @@ extern "C" int vmc_ham_destroy(vmc_ham* H) {
   (void)hipSetDevice(H->ctx->device);
   (void)hipStreamSynchronize(H->ctx->stream);
   if (H->bonds) (void)hipFree(H->bonds);
+  vmc_ctx* ctx = H->ctx;
   delete H;
+  ctx_release(ctx);
   return VMC_OK;
 }
 
@@ -490,6 +506,8 @@ extern "C" int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int
       rbm_lowp_local_energy(m, H, s, B, (double2*)eloc);
     else if (m->kind == MODEL_RBM)
       rbm_local_energy(m, H, s, B, (double2*)eloc);
+    else if (m->prec != VMC_F64)
+      cnn_lowp_local_energy(m, H, s, B, (double2*)eloc);
     else
       cnn_local_energy(m, H, s, B, (double2*)eloc);
   });
@@ -565,6 +583,7 @@ extern "C" int vmc_sampler_create(vmc_ctx* ctx, vmc_model* m, vmc_ham* H, const 
     S->t = 0;
     S->thermalized = 0;
     // initial states are drawn lazily by the first vmc_sample (t == 0)
+    ctx_retain(ctx);
     *out = S;
   });
 }
@@ -679,7 +698,9 @@ extern "C" int vmc_sampler_destroy(vmc_sampler* S) {
   if (S->bits) (void)hipFree(S->bits);
   if (S->acc) (void)hipFree(S->acc);
   if (S->made_buf) (void)hipFree(S->made_buf);
+  vmc_ctx* ctx = S->ctx;
   delete S;
+  ctx_release(ctx);
   return VMC_OK;
 }
 

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_cnn_forward(cnn_geom g, const uint64_t*
   if (b >= B) return;
   const uint64_t* sb = s + b * g.W;
   const int CN = g.C * g.N;
-  for (int e = threadIdx.x; e < CN; e += 256) a1[e] = clogcosh(z1_at(g, sb, e / g.N, e % g.N));
+  for (int e = threadIdx.x; e < CN; e += 256) a1[e] = clogcosh_pv(z1_at(g, sb, e / g.N, e % g.N));
   __syncthreads();
   double2 acc = make_double2(0.0, 0.0);
   for (int e = threadIdx.x; e < CN; e += 256) acc = cadd(acc, clogcosh(z2_at(g, a1, e / g.N, e % g.N)));
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_cnn_grad(cnn_geom g, const uint64_t* __
       row[k] = make_float2((float)v.x, (float)v.y);
   };
   const int off_b1 = g.C * kk, off_W2 = off_b1 + g.C, off_b2 = off_W2 + g.C * g.C * kk;
-  for (int e = threadIdx.x; e < CN; e += 256) A[e] = clogcosh(z1_at(g, sb, e / g.N, e % g.N));
+  for (int e = threadIdx.x; e < CN; e += 256) A[e] = clogcosh_pv(z1_at(g, sb, e / g.N, e % g.N));
   __syncthreads();
   for (int e = threadIdx.x; e < CN; e += 256) G2[e] = ctanh(z2_at(g, A, e / g.N, e % g.N));
   __syncthreads();
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void k_cnn_eloc(cnn_geom g, const uint64_t* __
   const uint64_t* sb = s + b * g.W;
   double2* a1 = a1_scratch + b * CN;  // global scratch for the full layer 1 of this sample
   const int tid = threadIdx.x;
-  for (int e = tid; e < CN; e += 256) a1[e] = clogcosh(z1_at(g, sb, e / g.N, e % g.N));
+  for (int e = tid; e < CN; e += 256) a1[e] = clogcosh_pv(z1_at(g, sb, e / g.N, e % g.N));
   __syncthreads();
   for (int e = tid; e < CN; e += 256) {
     const double2 z = z2_at(g, a1, e / g.N, e % g.N);
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) void k_cnn_eloc(cnn_geom g, const uint64_t* __
         const double2 z = z1_at(g, sb, c, p);
         const double2 w = g.W1[(c * g.k + dy) * g.k + dx];
         const double2 zn = make_double2(z.x + ds * w.x, z.y + ds * w.y);
-        DA[e] = csub(clogcosh(zn), clogcosh(z));
+        DA[e] = csub(clogcosh_pv(zn), clogcosh_pv(z));
       }
       __syncthreads();
       double2 part = make_double2(0.0, 0.0);
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_cnn_eloc(cnn_geom g, const uint64_t* __
                       zn.y += ds * w.y;
                     }
                 if (zn.x != zo.x || zn.y != zo.y)
-                  dz = cadd(dz, cmul(g.W2[((c * g.C + ci) * g.k + dy) * g.k + dx], csub(clogcosh(zn), a1[ci * g.N + p])));
+                  dz = cadd(dz, cmul(g.W2[((c * g.C + ci) * g.k + dy) * g.k + dx], csub(clogcosh_pv(zn), a1[ci * g.N + p])));
               }
           part = cadd(part, csub(clogcosh(cadd(Z2[e], dz)), LC2[e]));
         }
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(256) void k_cnn_metropolis(cnn_geom g, int n_chains
     for (int w = tid; w < g.W; w += 256) cb[w] = bits[(int64_t)c * g.W + w];
   }
   __syncthreads();
-  for (int e = tid; e < CN; e += 256) a1[e] = clogcosh(z1_at(g, cb, e / g.N, e % g.N));
+  for (int e = tid; e < CN; e += 256) a1[e] = clogcosh_pv(z1_at(g, cb, e / g.N, e % g.N));
   __syncthreads();
   for (int e = tid; e < CN; e += 256) {
     const double2 z = z2_at(g, a1, e / g.N, e % g.N);
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void k_cnn_metropolis(cnn_geom g, int n_chains
       const int p = shift_pos(g, site, -dy, -dx);
       const double2 z = z1_at(g, cb, ch, p);
       const double2 w = g.W1[(ch * g.k + dy) * g.k + dx];
-      DA[e] = csub(clogcosh(make_double2(z.x + ds * w.x, z.y + ds * w.y)), a1[ch * g.N + p]);
+      DA[e] = csub(clogcosh_pv(make_double2(z.x + ds * w.x, z.y + ds * w.y)), a1[ch * g.N + p]);
     }
     __syncthreads();
     double2 dzs[MAXOUT];

@@ -1,0 +1,485 @@
+// CNN local energies of the TFIM in float32 / bfloat16 on the matrix cores.
+//
+// Flipping site f changes layer 1 only at the k*k positions p = f - w
+// (w in [0,k)^2), by
+//   dA[ci][w] = logcosh(z1 + d) - logcosh(z1) = log(1 + (cosh d - 1) + tanh(z1) sinh d),
+//   d = -2 sigma_f W1[ci][w],
+// and layer 2 only at the (2k-1)^2 positions q = f - e, by
+//   dZ[c][e] = sum_{ci} sum_{t + w = e} W2[c][ci][t] dA[ci][w].
+// The amplitude ratio is a product over that window (no logarithms needed):
+//   psi(s_f) / psi(s) = prod_{c,e} cosh(z2 + dZ) / cosh(z2)
+//                     = prod_{c,e} (cosh dZ + tanh(z2) sinh dZ).
+// One work-group (8 waves) takes one sample: the forward pass z2 = W2 * a1 is
+// a matrix-core product (rows = positions, inner = (t, ci), columns = c), the
+// flips are processed 16 at a time, and for each window offset e the dZ of 16
+// flips x 16 channels is one matrix-core product with inner index (t, ci) over
+// the offsets t valid for e.  Complex products run on real MFMA with two
+// accumulators (re += Ar Br + (-Ai) Bi, im += Ar Bi + Ai Br).
+//
+// Precision: VMC_BF16 feeds bfloat16 operands (a1, W2, dA) to
+// v_mfma_f32_16x16x32_bf16; VMC_F32 keeps float32 operands
+// (v_mfma_f32_16x16x4_f32).  Both accumulate in float32, evaluate tanh, the
+// log1p of dA and the window factors in float32, keep the running product as
+// float32 mantissa + integer exponent, and sum the slots in float64.  The
+// hidden-layer log cosh is on the principal branch, as in the float64 path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+using namespace dev;
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short ushortx8 __attribute__((ext_vector_type(8)));
+
+constexpr int NT = 512;  // threads per work-group
+constexpr int NW = NT / 64;
+constexpr float PI_F = 3.14159265358979324f;
+constexpr float TWO_PI_F = 6.28318530717958648f;
+
+// Geometry and LDS layout (bytes), computed on the host.
+struct lp_geom {
+  int Lx, Ly, N, W, C, k, kk, win;
+  int Cp, Cn, Np;  // C rounded up to 8 / 16; row stride of the [C][N] float tables
+  int nrb, ncb;    // row blocks of 16 flips; column blocks of 16 channels
+  int sW, sA1, sDA;  // element strides of the operand planes (see the accessors)
+  int o_t1, o_a1i, o_t2, o_wre, o_wim, o_cd, o_sd, o_ure, o_uim, o_pm, o_pe, o_diag;
+  int a1_plane, da_plane, lds;
+};
+
+template <int PREC>
+struct lp_t;
+template <>
+struct lp_t<VMC_BF16> {
+  typedef __bf16 T;
+};
+template <>
+struct lp_t<VMC_F32> {
+  typedef float T;
+};
+
+// Operand layouts.  bfloat16: each lane reads 8 consecutive channels ci, so ci
+// is fastest, with 8-element row padding against bank conflicts.  float32:
+// each lane reads one element; lanes (li, lk) map to (c or position, ci), laid
+// out so that the 64 lanes of a fragment fall in distinct banks.
+template <int PREC>
+__device__ __forceinline__ int w2_idx(const lp_geom& g, int t, int c, int ci) {
+  if constexpr (PREC == VMC_BF16)
+    return (t * g.Cn + c) * g.sW + ci;
+  else
+    return (t * g.Cp + ci) * g.Cn + c;
+}
+template <int PREC>
+__device__ __forceinline__ int a1_idx(const lp_geom& g, int pos, int ci) {
+  if constexpr (PREC == VMC_BF16)
+    return pos * g.sA1 + ci;
+  else
+    return ci * g.sA1 + pos;
+}
+__device__ __forceinline__ int da_idx(const lp_geom& g, int row, int w, int ci) { return row * g.sDA + w * g.Cp + ci; }
+
+// site p shifted by (dy, dx) on the torus; |dy| < Ly, |dx| < Lx
+__device__ __forceinline__ int tpos(const lp_geom& g, int p, int dy, int dx) {
+  int y = p / g.Lx + dy, x = p % g.Lx + dx;
+  if (y >= g.Ly) y -= g.Ly;
+  if (y < 0) y += g.Ly;
+  if (x >= g.Lx) x -= g.Lx;
+  if (x < 0) x += g.Lx;
+  return y * g.Lx + x;
+}
+
+__device__ __forceinline__ float2 fclog1p(float2 u) {
+  return make_float2(0.5f * log1pf(2.f * u.x + u.x * u.x + u.y * u.y), atan2f(u.y, 1.f + u.x));
+}
+
+// cosh dz + tz sinh dz
+template <int PREC>
+__device__ __forceinline__ float2 window_factor(float2 dz, float2 tz) {
+  float ea, sb, cb;
+  if constexpr (PREC == VMC_BF16) {
+    ea = __expf(dz.x);
+    __sincosf(dz.y, &sb, &cb);
+  } else {
+    ea = expf(dz.x);
+    sincosf(dz.y, &sb, &cb);
+  }
+  const float ia = 1.f / ea;
+  const float ch = 0.5f * (ea + ia), sh = 0.5f * (ea - ia);
+  const float2 cz = make_float2(ch * cb, sh * sb), sz = make_float2(sh * cb, ch * sb);
+  return fcadd(cz, fcmul(tz, sz));
+}
+
+// running product m 2^e; keeps max(|re|, |im|) of m in [0.5, 1)
+__device__ __forceinline__ void renorm(float2& m, int& e) {
+  int x;
+  frexpf(fmaxf(fabsf(m.x), fabsf(m.y)), &x);
+  m.x = ldexpf(m.x, -x);
+  m.y = ldexpf(m.y, -x);
+  e += x;
+}
+
+__device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
+  ushortx8 u = __builtin_bit_cast(ushortx8, v);
+  u ^= (unsigned short)0x8000;
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+// float32 tables from the float64 parameters: [params (K)] [cosh 2W1 - 1] [sinh 2W1]
+__global__ void k_lp_tables(const double2* __restrict__ p, int64_t K, int n1, float2* __restrict__ out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= K + 2 * (int64_t)n1) return;
+  if (e < K) {
+    out[e] = make_float2((float)p[e].x, (float)p[e].y);
+    return;
+  }
+  const int j = (int)((e - K) % n1);
+  const bool is_sinh = (e - K) >= n1;
+  const double a = 2.0 * p[j].x, b = 2.0 * p[j].y;
+  double r, i;
+  if (is_sinh) {  // sinh(a + ib) = sinh a cos b + i cosh a sin b
+    r = sinh(a) * cos(b);
+    i = cosh(a) * sin(b);
+  } else {  // cosh(a + ib) - 1 = 2 sinh^2((a + ib) / 2)
+    const double hr = sinh(0.5 * a) * cos(0.5 * b), hi = cosh(0.5 * a) * sin(0.5 * b);
+    r = 2.0 * (hr * hr - hi * hi);
+    i = 4.0 * hr * hi;
+  }
+  out[e] = make_float2((float)r, (float)i);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __restrict__ P32,
+                                                    const uint64_t* __restrict__ s, int64_t B, double J, double h,
+                                                    const int2* __restrict__ bonds, int n_bonds,
+                                                    double2* __restrict__ eloc) {
+  typedef typename lp_t<PREC>::T T;
+  extern __shared__ __align__(16) char smem[];
+  float2* t1 = (float2*)(smem + g.o_t1);
+  float* a1i = (float*)(smem + g.o_a1i);
+  float2* t2 = (float2*)(smem + g.o_t2);
+  T* wre = (T*)(smem + g.o_wre);
+  T* wim = (T*)(smem + g.o_wim);
+  float2* cD = (float2*)(smem + g.o_cd);
+  float2* sD = (float2*)(smem + g.o_sd);
+  T* ure = (T*)(smem + g.o_ure);  // a1 (forward pass), then dA (flips)
+  T* uim = (T*)(smem + g.o_uim);
+  float2* pm = (float2*)(smem + g.o_pm);
+  int* pe = (int*)(smem + g.o_pe);
+  double* sdiag = (double*)(smem + g.o_diag);
+
+  const int64_t b = blockIdx.x;
+  if (b >= B) return;
+  const uint64_t* sb = s + b * g.W;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int C = g.C, N = g.N, kk = g.kk, Cp = g.Cp;
+  const float2* W1f = P32;
+  const float2* b1f = P32 + C * kk;
+  const float2* W2f = b1f + C;
+  const float2* b2f = W2f + C * C * kk;
+  const float2* tabs = b2f + C;
+  auto sig = [&](int q) { return ((sb[q >> 6] >> (q & 63)) & 1ull) ? 1.f : -1.f; };
+
+  // ---- phase 0: W2 operand planes and the cosh / sinh tables
+  for (int e = tid; e < kk * g.Cn * Cp; e += NT) {
+    const int t = e / (g.Cn * Cp), r = e % (g.Cn * Cp), c = r / Cp, ci = r % Cp;
+    const float2 v = (c < C && ci < C) ? W2f[(c * C + ci) * kk + t] : make_float2(0.f, 0.f);
+    wre[w2_idx<PREC>(g, t, c, ci)] = (T)v.x;
+    wim[w2_idx<PREC>(g, t, c, ci)] = (T)v.y;
+  }
+  for (int e = tid; e < C * kk; e += NT) {
+    cD[e] = tabs[e];
+    sD[e] = tabs[C * kk + e];
+  }
+  // ---- phase 1: layer 1 (tanh, principal log cosh) and the diagonal element
+  for (int e = tid; e < Cp * N; e += NT) {
+    const int c = e / N, p = e % N;
+    if (c < C) {
+      float2 z = b1f[c];
+      for (int w = 0; w < kk; ++w) {
+        const float sg = sig(tpos(g, p, w / g.k, w % g.k));
+        const float2 wv = W1f[c * kk + w];
+        z.x += sg * wv.x;
+        z.y += sg * wv.y;
+      }
+      t1[c * g.Np + p] = fctanh(z);
+      const float2 a = fclogcosh_pv(z);
+      a1i[c * g.Np + p] = a.y;
+      ure[a1_idx<PREC>(g, p, c)] = (T)a.x;
+      uim[a1_idx<PREC>(g, p, c)] = (T)a.y;
+    } else {
+      ure[a1_idx<PREC>(g, p, c)] = (T)0.f;
+      uim[a1_idx<PREC>(g, p, c)] = (T)0.f;
+    }
+  }
+  {
+    int n_al = 0;
+    for (int q = tid; q < n_bonds; q += NT) {
+      const int2 bd = bonds[q];
+      n_al += ((sb[bd.x >> 6] >> (bd.x & 63)) & 1ull) == ((sb[bd.y >> 6] >> (bd.y & 63)) & 1ull);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n_al += __shfl_xor(n_al, o, 64);
+    if (lane == 0) pe[wave] = n_al;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int t = 0;
+    for (int w = 0; w < NW; ++w) t += pe[w];
+    sdiag[0] = -J * (double)(t - (n_bonds - t));
+  }
+
+  // ---- phase 2: z2 = b2 + sum_{t, ci} W2[c][ci][t] a1[ci][p + t] on the matrix cores, t2 = tanh z2
+  for (int job = wave; job < g.nrb * g.ncb; job += NW) {
+    const int rb = job / g.ncb, cb = job % g.ncb;
+    const int prow = rb * 16 + li;  // A row of this lane
+    const bool prow_ok = prow < N;
+    floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (PREC == VMC_BF16) {
+      const int ng = Cp / 8;
+      for (int k0 = 0; k0 < kk * Cp; k0 += 32) {
+        const int gi = k0 / 8 + lk, t = gi / ng, c8 = (gi % ng) * 8;
+        bf16x8 ar{}, ai{}, br{}, bi{};
+        if (t < kk) {
+          if (prow_ok) {
+            const int pos = tpos(g, prow, t / g.k, t % g.k);
+            ar = *(const bf16x8*)(ure + a1_idx<PREC>(g, pos, c8));
+            ai = *(const bf16x8*)(uim + a1_idx<PREC>(g, pos, c8));
+          }
+          br = *(const bf16x8*)(wre + w2_idx<PREC>(g, t, cb * 16 + li, c8));
+          bi = *(const bf16x8*)(wim + w2_idx<PREC>(g, t, cb * 16 + li, c8));
+        }
+        re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, re, 0, 0, 0);
+        re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(neg8(ai), bi, re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, im, 0, 0, 0);
+      }
+    } else {
+      for (int k0 = 0; k0 < kk * Cp; k0 += 4) {
+        const int kx = k0 + lk, t = kx / Cp, ci = kx % Cp;  // kk * Cp is a multiple of 8
+        float ar = 0.f, ai = 0.f;
+        if (prow_ok) {
+          const int pos = tpos(g, prow, t / g.k, t % g.k);
+          ar = ure[a1_idx<PREC>(g, pos, ci)];
+          ai = uim[a1_idx<PREC>(g, pos, ci)];
+        }
+        const float br = wre[w2_idx<PREC>(g, t, cb * 16 + li, ci)], bi = wim[w2_idx<PREC>(g, t, cb * 16 + li, ci)];
+        re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re, 0, 0, 0);
+        re = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, im, 0, 0, 0);
+      }
+    }
+    const int c = cb * 16 + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = rb * 16 + 4 * lk + r;
+      if (p < N && c < C) t2[c * g.Np + p] = fctanh(make_float2(re[r] + b2f[c].x, im[r] + b2f[c].y));
+    }
+  }
+  __syncthreads();  // the a1 planes are dead from here on; the same LDS holds dA
+
+  // ---- phase 3: flips, 16 at a time
+  double2 esum = make_double2(0.0, 0.0);  // threads 0..15: sum of the ratios of their row
+  const int nwin = g.win * g.win;
+  for (int rb = 0; rb < g.nrb; ++rb) {
+    for (int e = tid; e < 16 * kk * Cp; e += NT) {
+      const int row = e / (kk * Cp), r = e % (kk * Cp), w = r / Cp, ci = r % Cp;
+      const int f = rb * 16 + row;
+      float2 d = make_float2(0.f, 0.f);
+      if (f < N && ci < C) {
+        const int p = tpos(g, f, -(w / g.k), -(w % g.k));
+        const float2 ts = fcmul(t1[ci * g.Np + p], sD[ci * kk + w]);
+        const float2 c1 = cD[ci * kk + w];
+        const float sg = sig(f);
+        d = fclog1p(make_float2(c1.x - sg * ts.x, c1.y - sg * ts.y));
+        // principal branch of the new activation: Im a1' = wrap(Im a1 + Im d)
+        const float sum = a1i[ci * g.Np + p] + d.y;
+        if (sum > PI_F)
+          d.y -= TWO_PI_F;
+        else if (sum <= -PI_F)
+          d.y += TWO_PI_F;
+      }
+      ure[da_idx(g, row, w, ci)] = (T)d.x;
+      uim[da_idx(g, row, w, ci)] = (T)d.y;
+    }
+    __syncthreads();
+    float2 P[4];
+    int E[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      P[r] = make_float2(1.f, 0.f);
+      E[r] = 0;
+    }
+    for (int e = wave; e < nwin; e += NW) {
+      const int ey = e / g.win, ex = e % g.win;
+      const int ty0 = max(0, ey - g.k + 1), ty1 = min(g.k - 1, ey);
+      const int tx0 = max(0, ex - g.k + 1), tx1 = min(g.k - 1, ex);
+      const int ntx = tx1 - tx0 + 1, nt = (ty1 - ty0 + 1) * ntx;
+      for (int cb = 0; cb < g.ncb; ++cb) {
+        floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (PREC == VMC_BF16) {
+          const int ng = Cp / 8;
+          for (int k0 = 0; k0 < nt * Cp; k0 += 32) {
+            const int gi = k0 / 8 + lk, ti = gi / ng, c8 = (gi % ng) * 8;
+            bf16x8 ar{}, ai{}, br{}, bi{};
+            if (ti < nt) {
+              const int ty = ty0 + ti / ntx, tx = tx0 + ti % ntx;
+              const int w = (ey - ty) * g.k + (ex - tx), t = ty * g.k + tx;
+              ar = *(const bf16x8*)(ure + da_idx(g, li, w, c8));
+              ai = *(const bf16x8*)(uim + da_idx(g, li, w, c8));
+              br = *(const bf16x8*)(wre + w2_idx<PREC>(g, t, cb * 16 + li, c8));
+              bi = *(const bf16x8*)(wim + w2_idx<PREC>(g, t, cb * 16 + li, c8));
+            }
+            re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, re, 0, 0, 0);
+            re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(neg8(ai), bi, re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, im, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, im, 0, 0, 0);
+          }
+        } else {
+          for (int k0 = 0; k0 < nt * Cp; k0 += 4) {
+            const int kx = k0 + lk, ti = kx / Cp, ci = kx % Cp;  // nt * Cp is a multiple of 8
+            const int ty = ty0 + ti / ntx, tx = tx0 + ti % ntx;
+            const int w = (ey - ty) * g.k + (ex - tx), t = ty * g.k + tx;
+            const float ar = ure[da_idx(g, li, w, ci)], ai = uim[da_idx(g, li, w, ci)];
+            const float br = wre[w2_idx<PREC>(g, t, cb * 16 + li, ci)], bi = wim[w2_idx<PREC>(g, t, cb * 16 + li, ci)];
+            re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re, 0, 0, 0);
+            re = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, im, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, im, 0, 0, 0);
+          }
+        }
+        // the lane holds dZ of flips rb*16 + 4 lk + r, channel cb*16 + li
+        const int c = cb * 16 + li;
+        if (c < C) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int f = rb * 16 + 4 * lk + r;
+            if (f >= N) continue;
+            const float2 tz = t2[c * g.Np + tpos(g, f, -ey, -ex)];
+            P[r] = fcmul(P[r], window_factor<PREC>(make_float2(re[r], im[r]), tz));
+            renorm(P[r], E[r]);
+          }
+        }
+      }
+    }
+    // product over the 16 channel lanes of each row
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        const float2 q = make_float2(__shfl_xor(P[r].x, o, 64), __shfl_xor(P[r].y, o, 64));
+        const int qe = __shfl_xor(E[r], o, 64);
+        P[r] = fcmul(P[r], q);
+        E[r] += qe;
+        renorm(P[r], E[r]);
+      }
+    if (li == 0)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        pm[wave * 16 + 4 * lk + r] = P[r];
+        pe[wave * 16 + 4 * lk + r] = E[r];
+      }
+    __syncthreads();
+    if (tid < 16 && rb * 16 + tid < N) {
+      double2 m = make_double2(1.0, 0.0);
+      int ex = 0;
+      for (int w = 0; w < NW; ++w) {
+        const float2 q = pm[w * 16 + tid];
+        m = cmul(m, make_double2(q.x, q.y));
+        ex += pe[w * 16 + tid];
+      }
+      esum.x += ldexp(m.x, ex);
+      esum.y += ldexp(m.y, ex);
+    }
+  }
+  if (wave == 0) {
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      esum.x += __shfl_xor(esum.x, o, 64);
+      esum.y += __shfl_xor(esum.y, o, 64);
+    }
+    if (lane == 0) eloc[b] = make_double2(sdiag[0] - h * esum.x, -h * esum.y);
+  }
+}
+
+int align16(int x) { return (x + 15) & ~15; }
+
+lp_geom make_geom(const vmc_model* m, int prec) {
+  lp_geom g{};
+  g.Lx = m->Lx;
+  g.Ly = m->Ly;
+  g.N = m->N;
+  g.W = m->W;
+  g.C = m->C;
+  g.k = m->k;
+  g.kk = m->k * m->k;
+  g.win = 2 * m->k - 1;
+  g.Cp = (m->C + 7) / 8 * 8;
+  g.Cn = (m->C + 15) / 16 * 16;
+  g.Np = m->N + 1;
+  g.nrb = (m->N + 15) / 16;
+  g.ncb = g.Cn / 16;
+  const bool bf = prec == VMC_BF16;
+  const int es = bf ? 2 : 4;
+  g.sW = bf ? g.Cp + 8 : 0;
+  g.sA1 = bf ? g.Cp + 8 : g.N + 16;
+  g.sDA = g.kk * g.Cp + (bf ? 8 : 4);
+  const int wplane = bf ? g.kk * g.Cn * g.sW : g.kk * g.Cp * g.Cn;
+  g.a1_plane = bf ? g.N * g.sA1 : g.Cp * g.sA1;
+  g.da_plane = 16 * g.sDA;
+  int o = 0;
+  auto take = [&](int bytes) {
+    const int r = o;
+    o = align16(o + bytes);
+    return r;
+  };
+  g.o_t1 = take(8 * g.C * g.Np);
+  g.o_a1i = take(4 * g.C * g.Np);
+  g.o_t2 = take(8 * g.C * g.Np);
+  g.o_wre = take(es * wplane);
+  g.o_wim = take(es * wplane);
+  g.o_cd = take(8 * g.C * g.kk);
+  g.o_sd = take(8 * g.C * g.kk);
+  const int uplane = es * std::max(g.a1_plane, g.da_plane);
+  g.o_ure = take(uplane);
+  g.o_uim = take(uplane);
+  g.o_pm = take(8 * NW * 16);
+  g.o_pe = take(4 * NW * 16);
+  g.o_diag = take(8);
+  g.lds = o;
+  return g;
+}
+
+}  // namespace
+
+void cnn_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc) {
+  VMC_REQUIRE(H->kind == HAM_TFIM, "the CNN local energy supports the transverse-field Ising model");
+  VMC_REQUIRE(H->Lx == m->Lx && H->Ly == m->Ly, "lattice of the Hamiltonian differs from the CNN's");
+  VMC_REQUIRE(m->Lx >= 2 * m->k - 1 && m->Ly >= 2 * m->k - 1,
+              "low-precision CNN local energies need Lx, Ly >= 2 kernel - 1");
+  const lp_geom g = make_geom(m, m->prec);
+  if (g.lds > 160 * 1024)
+    throw vmc_error{VMC_ERR_UNSUPPORTED, "CNN too large for the low-precision local-energy kernel (LDS)"};
+  vmc_ctx* ctx = m->ctx;
+  hipStream_t st = ctx->stream;
+  const int n1 = m->C * m->k * m->k;
+  const size_t tb = sizeof(float2) * (size_t)(m->K + 2 * n1);
+  ws_reserve(ctx, ws_round(tb));
+  float2* P32 = (float2*)ws_take(ctx, tb);
+  k_lp_tables<<<grid_for(m->K + 2 * n1, 256), 256, 0, st>>>(m->params, m->K, n1, P32);
+  if (m->prec == VMC_BF16) {
+    VMC_HIP(hipFuncSetAttribute((const void*)k_cnn_eloc_lp<VMC_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                g.lds));
+    k_cnn_eloc_lp<VMC_BF16><<<(unsigned)B, NT, g.lds, st>>>(g, P32, s, B, H->J, H->h, H->bonds, H->n_bonds, eloc);
+  } else {
+    VMC_HIP(hipFuncSetAttribute((const void*)k_cnn_eloc_lp<VMC_F32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                g.lds));
+    k_cnn_eloc_lp<VMC_F32><<<(unsigned)B, NT, g.lds, st>>>(g, P32, s, B, H->J, H->h, H->bonds, H->n_bonds, eloc);
+  }
+  VMC_HIP(hipGetLastError());
+}

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -41,6 +42,9 @@ struct vmc_arena {
 };
 
 struct vmc_ctx {
+  // references: the handle itself plus every model, Hamiltonian, sampler and
+  // MADE created from it; the context is freed when the last one is released
+  std::atomic<int> refs{1};
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
@@ -71,6 +75,8 @@ struct phase_scope {
 };
 
 // Carving: call ws_begin, then ws_take for each buffer (256-byte aligned).
+void ctx_retain(vmc_ctx* ctx);
+void ctx_release(vmc_ctx* ctx);
 void ws_reserve(vmc_ctx* ctx, size_t bytes);
 void* ws_take(vmc_ctx* ctx, size_t bytes);
 inline size_t ws_round(size_t b) { return (b + 255) & ~size_t(255); }
@@ -86,7 +92,7 @@ struct rbm_move_tables {
   int move_kind = -1;  // 0 = site flips, 1 = bond exchanges
   int n_moves = 0;
   uint64_t param_version = 0;
-  const vmc_ham* ham = nullptr;
+  uint64_t ham_uid = 0;     // Hamiltonian the exchange tables were built for
   double2* T = nullptr;    // [N_h][n_moves] tanh(2 D_jm)
   double2* D = nullptr;    // [N_h][n_moves] D_jm
   double2* LC = nullptr;   // [n_moves] sum_j logcosh(2 D_jm)
@@ -116,7 +122,7 @@ struct vmc_model {
   struct lowp_tables {
     uint64_t version = 0;
     int prec = -1, n_moves = 0;
-    const vmc_ham* ham = nullptr;
+    uint64_t ham_uid = 0;
     float2 *T = nullptr, *LC = nullptr, *alpha = nullptr;
   } tab32[2];
 };
@@ -126,6 +132,7 @@ enum { HAM_TFIM = 0, HAM_HEIS = 1 };
 
 struct vmc_ham {
   vmc_ctx* ctx = nullptr;
+  uint64_t uid = 0;  // unique per Hamiltonian created in this process (table cache key)
   int kind = HAM_TFIM;
   int Lx = 0, Ly = 1, periodic = 1;
   int N = 0, W = 1;
@@ -212,6 +219,15 @@ __device__ __forceinline__ double2 clogcosh(double2 z) {
   return make_double2(z.x - 0.69314718055994530942 + lr, z.y + li);
 }
 
+// log cosh z on the principal branch of the logarithm (imaginary part in
+// [-pi, pi]); a hidden layer's activation feeds a further linear layer, where
+// a shift by 2 pi i would change the result.
+__device__ __forceinline__ double2 clogcosh_pv(double2 z) {
+  double2 r = clogcosh(z);
+  r.y = remainder(r.y, 6.283185307179586477);
+  return r;
+}
+
 // tanh z = (1 - e^{-2z})/(1 + e^{-2z}) for Re z >= 0; odd in z.
 __device__ __forceinline__ double2 ctanh(double2 z) {
   bool neg = z.x < 0.0;
@@ -251,6 +267,11 @@ __device__ __forceinline__ float2 fclogcosh(float2 z) {
   float lr = 0.5f * log1pf(2.f * er + er * er + ei * ei);
   float li = atan2f(ei, 1.f + er);
   return make_float2(z.x - 0.69314718f + lr, z.y + li);
+}
+__device__ __forceinline__ float2 fclogcosh_pv(float2 z) {
+  float2 r = fclogcosh(z);
+  r.y = remainderf(r.y, 6.28318530717958648f);
+  return r;
 }
 __device__ __forceinline__ float2 fctanh(float2 z) {
   bool neg = z.x < 0.f;
@@ -319,6 +340,7 @@ void rbm_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
 void cnn_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* logpsi);
 void cnn_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
 void cnn_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
+void cnn_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
 void cnn_sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
 // vjp.hip
 void log_psi_vjp_impl(vmc_model* m, const uint64_t* s, int64_t B, const double2* g, double2* out);

@@ -317,6 +317,7 @@ extern "C" int vmc_made_create(vmc_ctx* ctx, int n_in, int n_hidden, vmc_made** 
     VMC_HIP(hipMemsetAsync(md->adam_m, 0, sizeof(double) * md->P, ctx->stream));
     VMC_HIP(hipMemsetAsync(md->adam_v, 0, sizeof(double) * md->P, ctx->stream));
     refresh_masks(md);
+    ctx_retain(ctx);
     *out = md;
   });
 }
@@ -447,6 +448,8 @@ extern "C" int vmc_made_destroy(vmc_made* md) {
   (void)hipSetDevice(md->ctx->device);
   (void)hipStreamSynchronize(md->ctx->stream);
   made_free(md);
+  vmc_ctx* ctx = md->ctx;
   delete md;
+  ctx_release(ctx);
   return VMC_OK;
 }

@@ -289,7 +289,7 @@ void rbm_theta(vmc_model* m, const uint64_t* s, int64_t B, double2* theta) {
 void rbm_ensure_tables(vmc_model* m, const vmc_ham* H, int move_kind) {
   rbm_move_tables& tb = m->tab[move_kind];
   const int n_moves = move_kind == 0 ? m->N : H->n_bonds;
-  if (tb.T && tb.param_version == m->version && tb.n_moves == n_moves && (move_kind == 0 || tb.ham == H)) return;
+  if (tb.T && tb.param_version == m->version && tb.n_moves == n_moves && (move_kind == 0 || tb.ham_uid == H->uid)) return;
   if (tb.n_moves != n_moves || !tb.T) {
     VMC_HIP(hipStreamSynchronize(m->ctx->stream));
     if (tb.T) VMC_HIP(hipFree(tb.T));
@@ -305,7 +305,7 @@ void rbm_ensure_tables(vmc_model* m, const vmc_ham* H, int move_kind) {
   }
   tb.move_kind = move_kind;
   tb.n_moves = n_moves;
-  tb.ham = H;
+  tb.ham_uid = H->uid;
   if (n_moves > 0) {
     k_tables<<<n_moves, 64, 0, m->ctx->stream>>>(m->params, H->bonds, move_kind, n_moves, m->N, m->Nh, tb.T, tb.D,
                                                  tb.LC, tb.alpha);

@@ -301,7 +301,7 @@ void rbm_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t 
     VMC_HIP(hipMalloc(&tb.alpha, sizeof(float2) * std::max(1, n_moves)));
     tb.version = 0;
   }
-  if (tb.version != m->version || tb.prec != m->prec || tb.n_moves != n_moves || (move_kind == 1 && tb.ham != H)) {
+  if (tb.version != m->version || tb.prec != m->prec || tb.n_moves != n_moves || (move_kind == 1 && tb.ham_uid != H->uid)) {
     if (n_moves > 0)
       k_tables_lowp<<<n_moves, 64, 0, ctx->stream>>>(m->Wt32, m->ab32, H->bonds, move_kind, n_moves, m->N, m->Nh,
                                                      tb.T, tb.LC, tb.alpha);
@@ -309,7 +309,7 @@ void rbm_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t 
     tb.version = m->version;
     tb.prec = m->prec;
     tb.n_moves = n_moves;
-    tb.ham = H;
+    tb.ham_uid = H->uid;
   }
   const int64_t chunk = std::min<int64_t>(B, kChunk);
   ws_reserve(ctx, ws_round(sizeof(float2) * chunk * m->Nh));

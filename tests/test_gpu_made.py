@@ -82,13 +82,13 @@ def test_sample_replay(ctx, N, H, B, rows):
     assert np.max(np.abs(got - lq_ref)) <= 1e-11 * max(1.0, np.abs(lq_ref).max())
 
 
-def _mixed_setup(ctx, N, Nh, H, std, pg, n_chains, seed=101):
+def _mixed_setup(ctx, N, Nh, H, std, pg, n_chains, seed=101, therm=2):
     pr = si.rbm_params(N, Nh, std=std, is_complex=True, seed=8)
     model = V.Model.rbm(ctx, N, Nh, True)
     model.set_params(dev_c128(pr))
     Ham = V.Hamiltonian.tfim(ctx, N, 1, True, 1.0, 1.0)
     made, pm = _made(ctx, N, H, 2.0, seed=9)
-    S = V.Sampler(ctx, model, Ham, proposal=V.PROP_MADE_MIX, n_chains=n_chains, therm_sweeps=2, p_global=pg,
+    S = V.Sampler(ctx, model, Ham, proposal=V.PROP_MADE_MIX, n_chains=n_chains, therm_sweeps=therm, p_global=pg,
                   seed=seed)
     S.set_proposal_made(made)
     return model, Ham, made, S, pr, pm
@@ -115,11 +115,15 @@ def test_mixed_chain_replay(ctx):
 def test_mixed_chain_histogram(ctx):
     flush("mixed histogram")
     N, Nh, H = 10, 10, 16
-    model, Ham, made, S, pr, pm = _mixed_setup(ctx, N, Nh, H, 0.5, 0.5, 1024, seed=3)
-    s, _, _ = S.sample(1024 * 200)
+    # 20 thermalisation sweeps, then every 10th of 1000 sweeps: the chi-square
+    # test assumes independent draws, so the kept samples must be well
+    # separated compared with the chain's autocorrelation time
+    model, Ham, made, S, pr, pm = _mixed_setup(ctx, N, Nh, H, 0.5, 0.5, 1024, seed=3, therm=20)
+    s, _, _ = S.sample(1024 * 1000)
     a, ga, ng = S.stats()
+    flush(f"  acceptance {a:.3f}, global acceptance {ga:.3f} of {ng} global proposals")
     assert ng > 0 and 0 < ga < 1
-    dec = host_bits(s).reshape(200, 1024)[::2].reshape(-1).astype(np.int64)
+    dec = host_bits(s).reshape(1000, 1024)[::10].reshape(-1).astype(np.int64)
     cd = np.bincount(dec, minlength=2 ** N)
     _, prob, _ = oeloc.exact_probabilities(lambda b: orbm.log_psi(pr, b, Nh), N)
     res = stats.chisquare(cd, prob * cd.sum())

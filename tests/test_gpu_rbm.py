@@ -179,3 +179,21 @@ def test_autograd_wrapper_gradcheck_and_oracle(ctx, kind):
     # d/d(theta) of Re(sum c_n f_n) in torch's convention: sum_n conj(c_n O_nk)
     ref = np.conj(c @ O_ref)
     assert np.max(np.abs(theta.grad.cpu().numpy() - ref)) < 1e-10 * max(1, np.abs(ref).max())
+
+
+def test_context_released_before_objects():
+    # objects keep their context alive: the handle may go first, in any order
+    flush("context lifetime")
+    c = V.Context(0)
+    p = si.rbm_params(12, 8, std=0.1, seed=1)
+    m = V.Model.rbm(c, 12, 8, True)
+    m.set_params(dev_c128(p))
+    H = V.Hamiltonian.tfim(c, 12, 1, True, 1.0, 1.0)
+    c.close()
+    bits = si.random_bits(5, 12, seed=2)
+    s = dev_bits(si.pack_bits(bits))
+    got = m.log_psi(s).cpu().numpy()
+    assert_logpsi_close(got, orbm.log_psi(p, bits, 8), 1e-12)
+    m.local_energy(H, s)
+    H.close()
+    m.close()
