@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 
 import synth_inputs as si  # noqa: E402
 
-PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TF": 157.3, "fp64_TF": 78.6, "fp64_valu_TF": 78.6, "bf16_mfma_TF": 2500.0}
+PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TF": 157.3, "fp64_TF": 78.6, "fp64_valu_TF": 78.6, "bf16_mfma_TF": 2500.0,
+        "fp16_mfma_TF": 2500.0}
 METRIC = "local energies/s & SR steps/s vs roofline; ESS/s learned vs local proposal"
 
 
@@ -44,7 +45,17 @@ def parse():
     ap.add_argument("--record-sweeps", type=int, default=256, help="MADE mix: recorded sweeps per chain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tau", type=float, default=1e-2)
+    ap.add_argument("--prec", choices=["f64", "f32", "bf16"], default="f64",
+                    help="network evaluation precision of log psi / local energies")
+    ap.add_argument("--peaks", action="store_true",
+                    help="measure HBM copy bandwidth and MFMA rates (f64, f32, bf16) instead of a workload")
+    ap.add_argument("--gram", type=int, choices=[0, 1], default=0,
+                    help="S Gram kernel: 0 float32 matrix cores, 1 split float16 (hi + lo) matrix cores")
     return ap.parse_args()
+
+
+def set_prec(V, model, prec):
+    model.set_precision({"f64": V.VMC_F64, "f32": V.VMC_F32, "bf16": V.VMC_BF16}[prec])
 
 
 def herk_flops(ns, K):
@@ -56,6 +67,13 @@ def herk_flops(ns, K):
 def chol_flops(K):
     """Complex Cholesky: K^3/6 complex multiply-adds x 8 real flops (leading order)."""
     return 4.0 * K ** 3 / 3.0
+
+
+def cnn_eloc_flops(N, C, k):
+    """Per CNN local energy (TFIM, N flips): the forward layer-2 correlation
+    (C^2 k^2 N complex multiply-adds) plus, per flip, the window change
+    dZ = W2 * dA with C^2 k^4 complex multiply-adds; 8 real flops each."""
+    return 8.0 * C * C * k * k * N * (1 + k * k)
 
 
 def eloc_flops(N, Nh, n_slots):
@@ -127,7 +145,7 @@ def bench_eloc(args, V, torch):
         p = si.cnn_params(cfg["channels"], cfg["kernel"], std=cfg["std"], seed=cfg["param_seed"])
         model = V.Model.cnn(ctx, Lx, Ly, cfg["channels"], cfg["kernel"])
         Nh = None
-        work = None
+        work = cnn_eloc_flops(N, cfg["channels"], cfg["kernel"])
     model.set_params(torch.from_numpy(p).to(dev))
     if cfg["ham"] == "heisenberg":
         H = V.Hamiltonian.heisenberg(ctx, Lx, Ly, True, cfg["J"])
@@ -135,14 +153,10 @@ def bench_eloc(args, V, torch):
         H = V.Hamiltonian.tfim(ctx, Lx, Ly, True, cfg["J"], cfg["h"])
     ns = cfg["n_chains"] * cfg["samples_per_chain"]
     el = torch.empty(ns, dtype=torch.complex128, device=dev)
-    if cfg["net"] == "rbm":
-        sampler = V.Sampler(ctx, model, H, proposal=V.PROP_EXCHANGE if cfg["proposal"] == "exchange" else V.PROP_FLIP,
-                            n_chains=cfg["n_chains"], therm_sweeps=20, seed=cfg["sampler_seed"])
-        get_samples = lambda: sampler.sample(ns)[0]
-    else:
-        # the CNN path has no sampler yet: uniformly random configurations of the same shape
-        s_fixed = torch.from_numpy(si.pack_bits(si.random_bits(ns, N, seed=cfg["sampler_seed"])).view(np.int64)).to(dev)
-        get_samples = lambda: s_fixed
+    sampler = V.Sampler(ctx, model, H, proposal=V.PROP_EXCHANGE if cfg["proposal"] == "exchange" else V.PROP_FLIP,
+                        n_chains=cfg["n_chains"], therm_sweeps=20, seed=cfg["sampler_seed"])
+    get_samples = lambda: sampler.sample(ns)[0]
+    set_prec(V, model, args.prec)
 
     def step():
         s = get_samples()
@@ -164,15 +178,24 @@ def bench_eloc(args, V, torch):
     out = {
         "metric": METRIC, "value": round(ns / (ms_step * 1e-3), 1), "unit": "local energies/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
         "data": "synthetic", "config": {"workload": args.workload, "samples": ns},
         "phases_ms": {"sample": round(samp_ms, 3), "eloc": round(eloc_ms, 3)},
         "eloc_kernel_per_s": round(ns / (eloc_ms * 1e-3), 1),
         "mean_energy": float(el.real.mean().item()),
     }
-    if work is not None:
-        out["eloc_roofline"] = {"bound": "alu", "achieved_TF": round(ns * work / (eloc_ms * 1e-3) / 1e12, 3),
-                                "peak": PEAK["fp64_valu_TF"], "work_per_eloc_flop": work}
+    achieved = ns * work / (eloc_ms * 1e-3) / 1e12
+    if cfg["net"] == "cnn" and args.prec != "f64":
+        peak, bound = (PEAK["bf16_mfma_TF"], "mfma") if args.prec == "bf16" else (PEAK["fp32_mfma_TF"], "mfma")
+        kern = f"k_cnn_eloc_lp<{args.prec}>"
+    elif cfg["net"] == "cnn":
+        peak, bound, kern = PEAK["fp64_valu_TF"], "alu", "k_cnn_eloc"
+    else:
+        peak, bound = PEAK["fp64_valu_TF"] if args.prec == "f64" else PEAK["fp32_mfma_TF"], "alu"
+        kern = "k_eloc" if args.prec == "f64" else "k_eloc_lowp"
+    out["roofline"] = {"kernel": kern, "bound": bound, "achieved": round(achieved, 3), "peak": peak,
+                       "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                       "work": f"{work:.4e} flop per local energy x {ns} per launch"}
     print(json.dumps(out), flush=True)
 
 
@@ -238,6 +261,43 @@ def bench_made(args, V, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_peaks(args, V, torch):
+    """Measured peaks next to the nominal ones: a 16-byte-vector device copy of
+    2 GiB (4 GiB moved) and the MFMA loops, each timed with HIP events on the
+    library's stream over `steps` launches after `warmup`."""
+    ctx = V.Context(0)
+    nb = 2 << 30
+    src = torch.empty(nb // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    out = {"metric": "measured peaks", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup}
+    for _ in range(args.warmup):
+        V.calib_copy(ctx, src, dst)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    for _ in range(args.steps):
+        V.calib_copy(ctx, src, dst)
+    ms, n = ctx.get_timing("calib.copy")
+    ctx.set_timing(False)
+    gbs = 2 * nb * n / (ms * 1e-3) / 1e9
+    out["hbm_copy"] = {"GB/s": round(gbs, 1), "nominal": PEAK["hbm_GBs"], "frac": round(gbs / PEAK["hbm_GBs"], 4),
+                       "bytes_moved_per_launch": 2 * nb, "ms_per_launch": round(ms / n, 4)}
+    nominal = {"f64": PEAK["fp64_TF"], "f32": PEAK["fp32_mfma_TF"], "bf16": PEAK["bf16_mfma_TF"]}
+    for kind, iters in [("f64", 2000), ("f32", 2000), ("bf16", 1000)]:
+        for _ in range(args.warmup):
+            V.calib_mfma(ctx, kind, 2048, iters)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        fl = 0.0
+        for _ in range(args.steps):
+            fl += V.calib_mfma(ctx, kind, 2048, iters)
+        ms, n = ctx.get_timing("calib.mfma")
+        ctx.set_timing(False)
+        tf = fl / (ms * 1e-3) / 1e12
+        out[f"mfma_{kind}"] = {"TFLOP/s": round(tf, 1), "nominal": nominal[kind], "frac": round(tf / nominal[kind], 4),
+                               "ms_per_launch": round(ms / n, 4)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -247,6 +307,8 @@ def main():
     import torch
     from paper_2108_03409_amd import nqsvmc as V
 
+    if args.peaks:
+        return bench_peaks(args, V, torch)
     if args.workload in ("heis2d_10x10_rbm_a4", "tfim2d_16x16_cnn"):
         return bench_eloc(args, V, torch)
     if args.workload == "tfim2d_20x20_rbm_a2_made":
@@ -265,20 +327,19 @@ def main():
     K = model.K
     theta = torch.from_numpy(p).to(dev)
     model.set_params(theta)
+    set_prec(V, model, args.prec)
     H = V.Hamiltonian.tfim(ctx, cfg["Lx"], cfg["Ly"], cfg["periodic"], cfg["J"], cfg["h"])
     sampler = V.Sampler(ctx, model, H, proposal=V.PROP_FLIP, n_chains=n_chains, therm_sweeps=20,
                         seed=cfg["sampler_seed"])
     O = torch.empty((ns, K), dtype=torch.complex64, device=dev)
     el = torch.empty(ns, dtype=torch.complex128, device=dev)
-    lp = torch.empty(ns, dtype=torch.complex128, device=dev)
 
     def step():
         nonlocal theta
         s, _, acc = sampler.sample(ns)
-        model.log_psi(s, out=lp)
         model.grad_log_psi(s, out=O)
         model.local_energy(H, s, out=el)
-        x, info = V.sr_solve(ctx, O, el, nu_rel=cfg["nu_rel"])
+        x, info = V.sr_solve(ctx, O, el, nu_rel=cfg["nu_rel"], gram=args.gram)
         theta = theta + args.tau * x
         model.set_params(theta)
         return info, acc
@@ -304,8 +365,10 @@ def main():
     # dominant kernel: the Gram (S) kernel, one launch per step
     herk_ms = phases["sr.herk"]
     herk_achieved = herk_flops(ns, K) / (herk_ms * 1e-3) / 1e12
-    roofline = {"kernel": "k_herk_mfma_f32 (S = Obar^H Obar)", "bound": "mfma", "achieved": round(herk_achieved, 3),
-                "peak": PEAK["fp32_mfma_TF"], "unit": "TFLOP/s", "frac": round(herk_achieved / PEAK["fp32_mfma_TF"], 4),
+    hpeak = PEAK["fp32_mfma_TF"] if args.gram == 0 else PEAK["fp16_mfma_TF"]
+    hname = "k_herk_mfma_f32" if args.gram == 0 else "k_herk16 (3 float16 products per term)"
+    roofline = {"kernel": f"{hname} (S = Obar^H Obar)", "bound": "mfma", "achieved": round(herk_achieved, 3),
+                "peak": hpeak, "unit": "TFLOP/s", "frac": round(herk_achieved / hpeak, 4),
                 "traffic": None,
                 "work": f"4*Ns*K*(K+1) = {herk_flops(ns, K):.4e} flop per launch (Ns={ns}, K={K})"}
     chol_ms = phases["sr.chol"]
@@ -318,11 +381,11 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 (S Gram from c64 O_k)",
+        "dtype": "f64 (S Gram from c64 O_k" + (", split-f16 products)" if args.gram else ")"),
         "data": "synthetic (seeded RBM parameters N(0,0.01), Metropolis samples)",
         "config": {"workload": "SR step: TFIM chain L=64 PBC J=h=1, complex RBM alpha=4 (K=16704), "
                                "16384 samples (1024 chains x 16 sweeps), nu_rel=1e-3",
-                   "global_batch": ns, "K": K, "parallelism": "single GPU"},
+                   "global_batch": ns, "K": K, "parallelism": "single GPU", "gram": args.gram, "prec": args.prec},
         "phases_ms": phases,
         "local_energies_per_s": round(eloc_per_s, 1),
         "eloc_roofline": {"bound": "alu", "achieved_TF": round(ns * eloc_flops(N, Nh, N) / (eloc_ms * 1e-3) / 1e12, 3),

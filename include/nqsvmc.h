@@ -298,6 +298,21 @@ int vmc_made_train(vmc_made* md, const uint64_t* s, int64_t B, int epochs, int b
 int vmc_made_sample(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, uint64_t* s_out, double* logq);
 int vmc_made_destroy(vmc_made* md);
 
+/* ---- measurement utilities (not part of the method) --------------------- */
+/* Plain device copy of `bytes` (a positive multiple of 16; 16-byte aligned
+ * device buffers, not overlapping) on the context's stream: the HBM bandwidth
+ * reference, and the known transfer against which hardware traffic counters
+ * are scaled.  Timed as phase "calib.copy" when timing is on.               */
+int vmc_calib_copy(vmc_ctx* ctx, const void* src, void* dst, int64_t bytes);
+/* Matrix-core loop: n_groups work-groups of 4 waves, each wave `iters` rounds
+ * of 8 independent chains of one MFMA type: kind VMC_DT_F64
+ * (v_mfma_f64_16x16x4f64), VMC_DT_F32 (v_mfma_f32_16x16x4f32) or
+ * VMC_CALIB_BF16 (v_mfma_f32_16x16x32_bf16).  out: device buffer of
+ * n_groups*256 elements (double for F64, float otherwise) that receives the
+ * accumulator sums.  *flops_host = the flops issued.  Phase "calib.mfma".    */
+enum { VMC_CALIB_BF16 = 16 };
+int vmc_calib_mfma(vmc_ctx* ctx, int kind, int n_groups, int iters, void* out, double* flops_host);
+
 #ifdef __cplusplus
 }
 #endif

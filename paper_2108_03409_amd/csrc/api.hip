@@ -6,30 +6,14 @@
 
 #include "internal.h"
 
-namespace {
-thread_local std::string g_err;
-
-template <class F>
-int guard(vmc_ctx* ctx, F&& f) {
-  try {
-    f();
-    if (ctx) ctx->err.clear();
-    return VMC_OK;
-  } catch (vmc_error& e) {
-    (ctx ? ctx->err : g_err) = e.msg;
-    return e.code;
-  } catch (std::bad_alloc&) {
-    (ctx ? ctx->err : g_err) = "host allocation failed";
-    return VMC_ERR_OOM;
-  } catch (std::exception& e) {
-    (ctx ? ctx->err : g_err) = e.what();
-    return VMC_ERR_INVALID_ARG;
-  } catch (...) {
-    (ctx ? ctx->err : g_err) = "unknown failure";
-    return VMC_ERR_INVALID_ARG;
-  }
+std::string& thread_error() {
+  static thread_local std::string e;
+  return e;
 }
 
+void set_device(vmc_ctx* ctx) { VMC_HIP(hipSetDevice(ctx->device)); }
+
+namespace {
 void* dmalloc(size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 256;
@@ -40,7 +24,6 @@ void* dmalloc(size_t bytes) {
   return p;
 }
 
-void set_device(vmc_ctx* ctx) { VMC_HIP(hipSetDevice(ctx->device)); }
 }  // namespace
 
 // ------------------------------------------------------------- workspace --
@@ -198,7 +181,7 @@ extern "C" int vmc_ctx_sync(vmc_ctx* ctx) {
   });
 }
 
-extern "C" const char* vmc_last_error(vmc_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+extern "C" const char* vmc_last_error(vmc_ctx* ctx) { return ctx ? ctx->err.c_str() : thread_error().c_str(); }
 
 extern "C" int vmc_ctx_set_workspace_limit(vmc_ctx* ctx, size_t bytes) {
   return guard(ctx, [&] {

@@ -7,6 +7,8 @@
 #include <atomic>
 #include <cstdint>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <map>
 #include <string>
 #include <utility>
@@ -19,6 +21,14 @@ struct vmc_error {
   int code;
   std::string msg;
 };
+
+// Error string of the calling thread for calls made without a context.
+std::string& thread_error();
+
+// Runs f, turning exceptions into status codes and the context's (or the
+// thread's) error string; no exception crosses the C ABI.
+template <class F>
+int guard(vmc_ctx* ctx, F&& f);
 
 #define VMC_HIP(call)                                                           \
   do {                                                                          \
@@ -63,6 +73,29 @@ struct vmc_ctx {
   std::map<std::string, std::pair<double, int64_t>> phases;
   std::vector<hipEvent_t> event_pool;
 };
+
+template <class F>
+int guard(vmc_ctx* ctx, F&& f) {
+  try {
+    f();
+    if (ctx) ctx->err.clear();
+    return VMC_OK;
+  } catch (vmc_error& e) {
+    (ctx ? ctx->err : thread_error()) = e.msg;
+    return e.code;
+  } catch (std::bad_alloc&) {
+    (ctx ? ctx->err : thread_error()) = "host allocation failed";
+    return VMC_ERR_OOM;
+  } catch (std::exception& e) {
+    (ctx ? ctx->err : thread_error()) = e.what();
+    return VMC_ERR_INVALID_ARG;
+  } catch (...) {
+    (ctx ? ctx->err : thread_error()) = "unknown failure";
+    return VMC_ERR_INVALID_ARG;
+  }
+}
+
+void set_device(vmc_ctx* ctx);
 
 // RAII bracket of one timed phase (no-op unless timing is enabled).
 struct phase_scope {

@@ -20,23 +20,6 @@ using namespace dev;
 
 namespace {
 
-thread_local std::string g_made_err;
-
-template <class F>
-int mguard(vmc_ctx* ctx, F&& f) {
-  try {
-    f();
-    if (ctx) ctx->err.clear();
-    return VMC_OK;
-  } catch (vmc_error& e) {
-    (ctx ? ctx->err : g_made_err) = e.msg;
-    return e.code;
-  } catch (std::exception& e) {
-    (ctx ? ctx->err : g_made_err) = e.what();
-    return VMC_ERR_INVALID_ARG;
-  }
-}
-
 __device__ __forceinline__ int hdeg(int k, int N) { return k % (N - 1) + 1; }
 __device__ __forceinline__ double softplus(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
 
@@ -290,7 +273,7 @@ void made_sample_impl(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, 
 }
 
 extern "C" int vmc_made_create(vmc_ctx* ctx, int n_in, int n_hidden, vmc_made** out) {
-  return mguard(ctx, [&] {
+  return guard(ctx, [&] {
     VMC_REQUIRE(ctx && out, "NULL argument");
     VMC_REQUIRE(n_in >= 2 && n_in <= 4096, "n_in must be in [2, 4096]");
     VMC_REQUIRE(n_hidden >= 1 && n_hidden <= 1024, "n_hidden must be in [1, 1024]");
@@ -329,7 +312,7 @@ extern "C" int vmc_made_num_params(const vmc_made* md, int64_t* P) {
 }
 
 extern "C" int vmc_made_set_params(vmc_made* md, const double* params_dev) {
-  return mguard(md ? md->ctx : nullptr, [&] {
+  return guard(md ? md->ctx : nullptr, [&] {
     VMC_REQUIRE(md && params_dev, "NULL argument");
     VMC_HIP(hipSetDevice(md->ctx->device));
     VMC_HIP(hipMemcpyAsync(md->params, params_dev, sizeof(double) * md->P, hipMemcpyDeviceToDevice, md->ctx->stream));
@@ -341,7 +324,7 @@ extern "C" int vmc_made_set_params(vmc_made* md, const double* params_dev) {
 }
 
 extern "C" int vmc_made_get_params(const vmc_made* md, double* params_dev) {
-  return mguard(md ? md->ctx : nullptr, [&] {
+  return guard(md ? md->ctx : nullptr, [&] {
     VMC_REQUIRE(md && params_dev, "NULL argument");
     VMC_HIP(hipSetDevice(md->ctx->device));
     VMC_HIP(hipMemcpyAsync(params_dev, md->params, sizeof(double) * md->P, hipMemcpyDeviceToDevice, md->ctx->stream));
@@ -349,7 +332,7 @@ extern "C" int vmc_made_get_params(const vmc_made* md, double* params_dev) {
 }
 
 extern "C" int vmc_made_log_q(vmc_made* md, const uint64_t* s, int64_t B, double* logq) {
-  return mguard(md ? md->ctx : nullptr, [&] {
+  return guard(md ? md->ctx : nullptr, [&] {
     VMC_REQUIRE(md, "NULL MADE");
     VMC_REQUIRE(B >= 0, "B < 0");
     if (B == 0) return;
@@ -370,7 +353,7 @@ extern "C" int vmc_made_log_q(vmc_made* md, const uint64_t* s, int64_t B, double
 }
 
 extern "C" int vmc_made_nll_grad(vmc_made* md, const uint64_t* s, int64_t B, double* grad, double* nll_host) {
-  return mguard(md ? md->ctx : nullptr, [&] {
+  return guard(md ? md->ctx : nullptr, [&] {
     VMC_REQUIRE(md, "NULL MADE");
     VMC_REQUIRE(B >= 1 && B <= (1 << 20), "B must be in [1, 2^20]");
     VMC_REQUIRE(s && grad, "NULL buffer");
@@ -393,7 +376,7 @@ extern "C" int vmc_made_nll_grad(vmc_made* md, const uint64_t* s, int64_t B, dou
 
 extern "C" int vmc_made_train(vmc_made* md, const uint64_t* s, int64_t B, int epochs, int batch, double lr,
                               double* nll_host) {
-  return mguard(md ? md->ctx : nullptr, [&] {
+  return guard(md ? md->ctx : nullptr, [&] {
     VMC_REQUIRE(md, "NULL MADE");
     VMC_REQUIRE(B >= 1 && epochs >= 1 && batch >= 1 && batch <= (1 << 16), "bad training sizes");
     VMC_REQUIRE(std::isfinite(lr) && lr > 0, "lr must be positive");
@@ -431,7 +414,7 @@ extern "C" int vmc_made_train(vmc_made* md, const uint64_t* s, int64_t B, int ep
 
 extern "C" int vmc_made_sample(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, uint64_t* s_out,
                                double* logq) {
-  return mguard(md ? md->ctx : nullptr, [&] {
+  return guard(md ? md->ctx : nullptr, [&] {
     VMC_REQUIRE(md, "NULL MADE");
     VMC_REQUIRE(B >= 0 && B <= ((int64_t)1 << 31) - 1, "B out of range");
     if (B == 0) return;

@@ -96,6 +96,8 @@ _SIGS = {
     "vmc_made_train": ([P, P, I64, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double)], C.c_int),
     "vmc_made_sample": ([P, I64, C.c_uint64, C.c_uint64, P, P], C.c_int),
     "vmc_made_destroy": ([P], C.c_int),
+    "vmc_calib_copy": ([P, P, P, I64], C.c_int),
+    "vmc_calib_mfma": ([P, C.c_int, C.c_int, C.c_int, P, C.POINTER(C.c_double)], C.c_int),
 }
 EXPORTS = tuple(_SIGS)
 
@@ -450,3 +452,24 @@ def log_psi_autograd(model: "Model", theta: torch.Tensor, s: torch.Tensor) -> to
 
 def version() -> str:
     return load().vmc_version().decode()
+
+
+def calib_copy(ctx: Context, src: torch.Tensor, dst: torch.Tensor):
+    """Device copy of src into dst (same byte size): the HBM bandwidth reference."""
+    nb = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nb
+    _check(load().vmc_calib_copy(ctx.h, _ptr(src), _ptr(dst), nb), ctx.h)
+
+
+CALIB_BF16 = 16
+CALIB_KINDS = {"f64": DT_F64, "f32": DT_F32, "bf16": CALIB_BF16}
+
+
+def calib_mfma(ctx: Context, kind: str, n_groups: int, iters: int) -> float:
+    """Runs the matrix-core loop of one type; returns the flops issued."""
+    dt = torch.float64 if kind == "f64" else torch.float32
+    out = torch.empty(n_groups * 256, dtype=dt, device=f"cuda:{ctx.device}")
+    fl = C.c_double()
+    _check(load().vmc_calib_mfma(ctx.h, CALIB_KINDS[kind], n_groups, iters, _ptr(out), C.byref(fl)), ctx.h)
+    return fl.value
+
