@@ -165,7 +165,22 @@ void ctx_release(vmc_ctx* ctx) {
     if (p.b) (void)hipEventDestroy(p.b);
   }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->ev_main) (void)hipEventDestroy(ctx->ev_main);
+  if (ctx->ev_aux) (void)hipEventDestroy(ctx->ev_aux);
   delete ctx;
+}
+
+hipStream_t aux_stream(vmc_ctx* ctx) {
+  if (!ctx->aux) {
+    VMC_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    VMC_HIP(hipEventCreateWithFlags(&ctx->ev_main, hipEventDisableTiming));
+    VMC_HIP(hipEventCreateWithFlags(&ctx->ev_aux, hipEventDisableTiming));
+  }
+  return ctx->aux;
 }
 
 extern "C" int vmc_ctx_destroy(vmc_ctx* ctx) {

@@ -10,9 +10,12 @@
 //                 float64 matrix cores (in place, one 64-row block per group);
 //   k_zmfma<2>    the rest of the panel's columns: A_rc -= L_rb L_cb^H.
 // Per panel p, once its four blocks are done:
+//   k_zmfma<2>    lookahead: the next panel's columns -= L_rp L_cp^H;
 //   k_zmfma<1>    trailing update A_rc -= L_rp L_cp^H (reduction depth 256) on
-//                 the lower 64 x 64 tiles of the trailing matrix, so the
-//                 trailing matrix is read and written once per 256 columns.
+//                 the lower 64 x 64 tiles of the rest of the trailing matrix,
+//                 on a second stream, overlapping the next panel's
+//                 factorisation; the trailing matrix is read and written once
+//                 per 256 columns.
 // The complex products use two real accumulators per 16x16 block held in the
 // same lanes: re += Pr Qr + Pi Qi and im += Pi Qr + Pr (-Qi) for P conj(Q).  A non-positive pivot sets the fail index; every later kernel
 // then exits at once.  The upper triangle of S~ is never written.
@@ -326,6 +329,14 @@ int chol_block() { return CB; }
 void chol_factor(vmc_ctx* ctx, double2* S, int64_t K, double2* Linv, long long* fail, double* pivmin) {
   hipStream_t st = ctx->stream;
   constexpr int PW = 256;  // panel width of the trailing update
+  // Lookahead: after panel P_p is factored, the next panel's columns are
+  // updated by P_p on the main stream, while the rest of the trailing matrix
+  // (columns from the panel after next on) is updated on the auxiliary stream,
+  // overlapping the factorisation of the next panel.  The only conflict is
+  // the next lookahead (it writes columns the previous auxiliary update also
+  // writes), so it waits for that update.
+  hipStream_t aux = aux_stream(ctx);
+  bool aux_busy = false;
   for (int64_t p0 = 0; p0 < K; p0 += PW) {
     const int64_t pend = std::min<int64_t>(K, p0 + PW);
     for (int64_t c0 = p0; c0 < pend; c0 += CB) {
@@ -351,19 +362,43 @@ void chol_factor(vmc_ctx* ctx, double2* S, int64_t K, double2* Linv, long long* 
         k_zmfma<2><<<(unsigned)(nrt * a.nct), 256, 0, st>>>(a);
       }
     }
-    if (pend < K) {  // trailing matrix, reduction over the whole panel
+    if (pend >= K) break;
+    const int64_t pend2 = std::min<int64_t>(K, pend + PW);
+    VMC_HIP(hipEventRecord(ctx->ev_main, st));  // panel P_p factored
+    // lookahead: columns [pend, pend2), rows >= pend, reduction over P_p
+    if (aux_busy) VMC_HIP(hipStreamWaitEvent(st, ctx->ev_aux, 0));
+    {
       zargs a{};
       a.S = S;
       a.K = K;
       a.kb0 = p0;
       a.depth = (int)(pend - p0);
       a.rbase = pend;
+      a.cbase = pend;
+      a.cend = pend2;
+      a.nct = (int)((pend2 - pend + CB - 1) / CB);
       a.fail = fail;
-      const int64_t nt = (K - pend + CB - 1) / CB;
+      const int64_t nrt = (K - pend + CB - 1) / CB;
+      k_zmfma<2><<<(unsigned)(nrt * a.nct), 256, 0, st>>>(a);
+    }
+    // the rest of the trailing matrix on the auxiliary stream
+    if (pend2 < K) {
+      VMC_HIP(hipStreamWaitEvent(aux, ctx->ev_main, 0));
+      zargs a{};
+      a.S = S;
+      a.K = K;
+      a.kb0 = p0;
+      a.depth = (int)(pend - p0);
+      a.rbase = pend2;
+      a.fail = fail;
+      const int64_t nt = (K - pend2 + CB - 1) / CB;
       a.ntiles = nt * (nt + 1) / 2;
-      k_zmfma<1><<<(unsigned)(((a.ntiles + 7) / 8) * 8), 256, 0, st>>>(a);
+      k_zmfma<1><<<(unsigned)(((a.ntiles + 7) / 8) * 8), 256, 0, aux>>>(a);
+      VMC_HIP(hipEventRecord(ctx->ev_aux, aux));
+      aux_busy = true;
     }
   }
+  if (aux_busy) VMC_HIP(hipStreamWaitEvent(st, ctx->ev_aux, 0));
   VMC_HIP(hipGetLastError());
 }
 

@@ -72,7 +72,14 @@ struct vmc_ctx {
   std::vector<pending_t> pending;
   std::map<std::string, std::pair<double, int64_t>> phases;
   std::vector<hipEvent_t> event_pool;
+  // second stream (default priority) and two events for work that overlaps
+  // the context's stream inside one call; created on first use
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_main = nullptr, ev_aux = nullptr;
 };
+
+// The context's auxiliary stream and events (created on first use).
+hipStream_t aux_stream(vmc_ctx* ctx);
 
 template <class F>
 int guard(vmc_ctx* ctx, F&& f) {

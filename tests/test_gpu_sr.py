@@ -34,6 +34,7 @@ def _problem(N, Nh, ns, std, seed, cplx=True):
     (8, 16, 300, "complex", 1j, 1e-2, 1e-4, True),
     (12, 20, 77, "complex", 1.0, 1e-3, 0.0, False),   # fewer samples than parameters
     (20, 40, 2000, "complex", 1.0, 1e-3, 0.0, False),  # K = 860: many blocks + ragged tail
+    (40, 60, 3000, "complex", 1.0, 1e-3, 0.0, False),  # K = 2500: ten panels, lookahead + ragged tail
 ])
 def test_sr_solve_fp64_matches_oracle(ctx, N, Nh, ns, mode, gamma, nu, eps, weighted):
     flush(f"sr fp64 N={N} Nh={Nh} ns={ns} mode={mode}")
@@ -57,7 +58,7 @@ def test_sr_solve_fp64_matches_oracle(ctx, N, Nh, ns, mode, gamma, nu, eps, weig
 
 @pytest.mark.parametrize("gram", [0, 1])
 @pytest.mark.parametrize("N,Nh,ns,weighted", [(16, 32, 4096, False), (5, 7, 9, True), (9, 21, 1001, False),
-                                              (12, 48, 333, True)])
+                                              (12, 48, 333, True), (40, 60, 3000, False)])
 def test_sr_solve_fp32_gram_within_bound(ctx, N, Nh, ns, weighted, gram):
     # S from complex64 O on the matrix cores: float32 products (gram 0) or split
     # float16 products (gram 1, 2^-21 per term); |dS| <= (u + gamma_N) sum |Obar||Obar|
