@@ -32,6 +32,22 @@ PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TF": 157.3, "fp64_TF": 78.6, "fp64_valu_TF
         "fp16_mfma_TF": 2500.0}
 METRIC = "local energies/s & SR steps/s vs roofline; ESS/s learned vs local proposal"
 
+# HBM bytes per launch of k_herk_mfma_f32 on the default workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB: the factors a
+# plain 2 GiB device copy reads); reported only while herk.hip is the source
+# that was profiled.
+HERK_TRAFFIC = {"source_sha256_16": "e6fe7958b53dc729", "bytes": 157852218675.0}
+
+
+def herk_traffic():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2108_03409_amd", "csrc", "herk.hip")
+    try:
+        h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return HERK_TRAFFIC["bytes"] if h == HERK_TRAFFIC["source_sha256_16"] else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -369,7 +385,9 @@ def main():
     hname = "k_herk_mfma_f32" if args.gram == 0 else "k_herk16 (3 float16 products per term)"
     roofline = {"kernel": f"{hname} (S = Obar^H Obar)", "bound": "mfma", "achieved": round(herk_achieved, 3),
                 "peak": hpeak, "unit": "TFLOP/s", "frac": round(herk_achieved / hpeak, 4),
-                "traffic": None,
+                "traffic": herk_traffic() if args.gram == 0 else None,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled)",
+                "algorithmic_bytes": 8.0 * ns * K + 16.0 * K * K,
                 "work": f"4*Ns*K*(K+1) = {herk_flops(ns, K):.4e} flop per launch (Ns={ns}, K={K})"}
     chol_ms = phases["sr.chol"]
     eloc_ms = phases["eloc"]
