@@ -604,7 +604,9 @@ extern "C" int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, do
     uint64_t t0 = S->t;
     {
       phase_scope ps(S->ctx, "sample");
-      if (S->model->kind == MODEL_CNN)
+      if (S->model->kind == MODEL_CNN && S->model->prec != VMC_F64)
+        cnn_lowp_sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
+      else if (S->model->kind == MODEL_CNN)
         cnn_sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
       else
         sampler_run(S, per_chain, s_out, (double2*)logpsi_out);

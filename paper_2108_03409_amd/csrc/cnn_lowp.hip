@@ -128,25 +128,30 @@ __device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
   return __builtin_bit_cast(bf16x8, u);
 }
 
-// float32 tables from the float64 parameters: [params (K)] [cosh 2W1 - 1] [sinh 2W1]
+// float32 tables from the float64 parameters:
+//   [params (K)] [cosh 2W1 - 1 (n1)] [sinh 2W1 (n1)] [tanh 2W1 (n1)]
 __global__ void k_lp_tables(const double2* __restrict__ p, int64_t K, int n1, float2* __restrict__ out) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= K + 2 * (int64_t)n1) return;
+  if (e >= K + 3 * (int64_t)n1) return;
   if (e < K) {
     out[e] = make_float2((float)p[e].x, (float)p[e].y);
     return;
   }
   const int j = (int)((e - K) % n1);
-  const bool is_sinh = (e - K) >= n1;
+  const int which = (int)((e - K) / n1);
   const double a = 2.0 * p[j].x, b = 2.0 * p[j].y;
   double r, i;
-  if (is_sinh) {  // sinh(a + ib) = sinh a cos b + i cosh a sin b
+  if (which == 1) {  // sinh(a + ib) = sinh a cos b + i cosh a sin b
     r = sinh(a) * cos(b);
     i = cosh(a) * sin(b);
-  } else {  // cosh(a + ib) - 1 = 2 sinh^2((a + ib) / 2)
+  } else if (which == 0) {  // cosh(a + ib) - 1 = 2 sinh^2((a + ib) / 2)
     const double hr = sinh(0.5 * a) * cos(0.5 * b), hi = cosh(0.5 * a) * sin(0.5 * b);
     r = 2.0 * (hr * hr - hi * hi);
     i = 4.0 * hr * hi;
+  } else {
+    const double2 th = ctanh(make_double2(a, b));
+    r = th.x;
+    i = th.y;
   }
   out[e] = make_float2((float)r, (float)i);
 }
@@ -407,6 +412,282 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
   }
 }
 
+// ---------------------------------------------------------------------------
+// Metropolis chains for the CNN in float32 (single-spin flips, the Philox
+// stream of the float64 sampler): one work-group per chain.  The chain keeps
+// z1, Im a1 (principal branch), z2 and t2 = tanh z2 of its configuration in
+// LDS.  A proposal at site f costs the k*k layer-1 changes dA (as in the
+// local-energy kernel, with tanh z1 evaluated on the fly), the window changes
+// dZ = W2 * dA by direct sums, and the ratio
+//   psi(s_f) / psi(s) = prod_window (cosh dZ + t2 sinh dZ)
+// (float32 mantissa, integer exponent).  On acceptance z1 += -2 sigma_f W1 and
+// z2 += dZ are updated additively and t2 is re-evaluated from z2, so rounding
+// grows only additively; log psi of a recorded sample is re-summed from z2.
+// Everything is rebuilt from the bits at the start of every call.
+struct mh_geom {
+  int Lx, Ly, N, W, C, k, kk, win, nout;
+  int o_z1, o_a1i, o_z2, o_t2, o_w2, o_da, o_cd, o_sd, o_red, o_cb, lds;
+};
+
+constexpr int MH_NT = 256;
+constexpr int MH_MAXOUT = 8;  // window outputs per thread: C (2k-1)^2 <= 2048
+
+__device__ __forceinline__ int mpos(const mh_geom& g, int p, int dy, int dx) {
+  int y = p / g.Lx + dy, x = p % g.Lx + dx;
+  if (y >= g.Ly) y -= g.Ly;
+  if (y < 0) y += g.Ly;
+  if (x >= g.Lx) x -= g.Lx;
+  if (x < 0) x += g.Lx;
+  return y * g.Lx + x;
+}
+
+// sum over the block of a double2 (all threads get the total); red holds 2 doubles per wave
+__device__ __forceinline__ double2 mh_block_sum(double2 v, double* red) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[3 * wave] = v.x;
+    red[3 * wave + 1] = v.y;
+  }
+  __syncthreads();
+  double2 t = make_double2(0.0, 0.0);
+  for (int w = 0; w < MH_NT / 64; ++w) {
+    t.x += red[3 * w];
+    t.y += red[3 * w + 1];
+  }
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(MH_NT) void k_cnn_mh_lp(mh_geom g, const float2* __restrict__ P32, int n_chains,
+                                                     uint64_t* __restrict__ bits, uint2 key, uint64_t t0, int init,
+                                                     int64_t therm_steps, int64_t n_record, int sweep,
+                                                     uint64_t* __restrict__ s_out, double2* __restrict__ logpsi_out,
+                                                     unsigned long long* __restrict__ acc,
+                                                     float2* __restrict__ a1_scratch) {
+  extern __shared__ __align__(16) char smem[];
+  float2* z1 = (float2*)(smem + g.o_z1);
+  float* a1i = (float*)(smem + g.o_a1i);
+  float2* z2 = (float2*)(smem + g.o_z2);
+  float2* t2 = (float2*)(smem + g.o_t2);
+  float2* w2 = (float2*)(smem + g.o_w2);  // [t][ci][c]
+  float2* dA = (float2*)(smem + g.o_da);  // [ci][w]
+  float2* cD = (float2*)(smem + g.o_cd);
+  float2* sD = (float2*)(smem + g.o_sd);
+  double* red = (double*)(smem + g.o_red);  // [4 waves][3]
+  uint64_t* cb = (uint64_t*)(smem + g.o_cb);
+  const int ch = blockIdx.x;
+  if (ch >= n_chains) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int C = g.C, N = g.N, kk = g.kk, CN = C * N;
+  const float2* W1f = P32;
+  const float2* b1f = P32 + C * kk;
+  const float2* W2f = b1f + C;
+  const float2* b2f = W2f + C * C * kk;
+  const float2* tabs = b2f + C;
+  float2* a1g = a1_scratch + (int64_t)ch * CN;
+
+  if (init) {
+    if (tid == 0)
+      for (int w = 0; w < g.W; ++w) {
+        const uint4 y = philox(make_uint4((uint32_t)ch, (uint32_t)(w >> 1), 0u, 2u), key);
+        uint64_t word = (w & 1) ? ((uint64_t)y.z | ((uint64_t)y.w << 32)) : ((uint64_t)y.x | ((uint64_t)y.y << 32));
+        const int rem = N - 64 * w;
+        if (rem < 64) word &= (1ull << rem) - 1ull;
+        cb[w] = word;
+      }
+  } else {
+    for (int w = tid; w < g.W; w += MH_NT) cb[w] = bits[(int64_t)ch * g.W + w];
+  }
+  for (int e = tid; e < kk * C * C; e += MH_NT) {
+    const int tt = e / (C * C), r = e % (C * C), ci = r / C, c = r % C;
+    w2[e] = W2f[(c * C + ci) * kk + tt];
+  }
+  for (int e = tid; e < C * kk; e += MH_NT) {
+    cD[e] = tabs[e];
+    sD[e] = tabs[C * kk + e];
+  }
+  __syncthreads();
+  auto sig = [&](int q) { return ((cb[q >> 6] >> (q & 63)) & 1ull) ? 1.f : -1.f; };
+  // layer 1 from the bits; a1 goes to global scratch for the layer-2 sums
+  for (int e = tid; e < CN; e += MH_NT) {
+    const int c = e / N, p = e % N;
+    float2 z = b1f[c];
+    for (int w = 0; w < kk; ++w) {
+      const float s = sig(mpos(g, p, w / g.k, w % g.k));
+      const float2 wv = W1f[c * kk + w];
+      z.x += s * wv.x;
+      z.y += s * wv.y;
+    }
+    z1[e] = z;
+    const float2 a = fclogcosh_pv(z);
+    a1i[e] = a.y;
+    a1g[e] = a;
+  }
+  __syncthreads();
+  for (int e = tid; e < CN; e += MH_NT) {
+    const int c = e / N, p = e % N;
+    float2 z = b2f[c];
+    for (int ci = 0; ci < C; ++ci)
+      for (int w = 0; w < kk; ++w)
+        z = fcadd(z, fcmul(w2[(w * C + ci) * C + c], a1g[ci * N + mpos(g, p, w / g.k, w % g.k)]));
+    z2[e] = z;
+    t2[e] = fctanh(z);
+  }
+  __syncthreads();
+
+  unsigned long long accepted = 0;
+  const int64_t total = therm_steps + n_record * sweep;
+  for (int64_t step = 0; step < total; ++step) {
+    const uint64_t t = t0 + (uint64_t)step;
+    const uint4 x = philox(make_uint4((uint32_t)ch, (uint32_t)t, (uint32_t)(t >> 32), 0u), key);
+    const int site = (int)to_index(x.x, (uint32_t)N);
+    const double u = to_uniform(x.y, x.z);
+    const float sg = sig(site);
+    // layer-1 changes at p = site - w
+    for (int e = tid; e < C * kk; e += MH_NT) {
+      const int ci = e / kk, w = e % kk;
+      const int p = mpos(g, site, -(w / g.k), -(w % g.k));
+      const float2 ts = fcmul(fctanh(z1[ci * N + p]), sD[e]);
+      float2 d = fclog1p(make_float2(cD[e].x - sg * ts.x, cD[e].y - sg * ts.y));
+      const float sum = a1i[ci * N + p] + d.y;
+      if (sum > PI_F)
+        d.y -= TWO_PI_F;
+      else if (sum <= -PI_F)
+        d.y += TWO_PI_F;
+      dA[e] = d;
+    }
+    __syncthreads();
+    // window: dZ, factors, running product
+    float2 dzs[MH_MAXOUT];
+    float2 P = make_float2(1.f, 0.f);
+    int E = 0;
+#pragma unroll
+    for (int q = 0; q < MH_MAXOUT; ++q) {
+      const int o = tid + MH_NT * q;
+      dzs[q] = make_float2(0.f, 0.f);
+      if (o >= g.nout) continue;
+      const int c = o % C, e = o / C, ey = e / g.win, ex = e % g.win;
+      float2 dz = make_float2(0.f, 0.f);
+      for (int ty = max(0, ey - g.k + 1); ty <= min(g.k - 1, ey); ++ty)
+        for (int tx = max(0, ex - g.k + 1); tx <= min(g.k - 1, ex); ++tx) {
+          const int tt = ty * g.k + tx, w = (ey - ty) * g.k + (ex - tx);
+          const float2* wr = w2 + tt * C * C + c;
+          const float2* ar = dA + w;
+          int ci = 0;
+          // four independent products per round keep several LDS loads in flight
+          float2 d1 = make_float2(0.f, 0.f), d2 = d1, d3 = d1;
+          for (; ci + 4 <= C; ci += 4) {
+            const float2 wa = wr[ci * C], wb = wr[(ci + 1) * C], wc = wr[(ci + 2) * C], wd = wr[(ci + 3) * C];
+            const float2 aa = ar[ci * kk], ab = ar[(ci + 1) * kk], ac = ar[(ci + 2) * kk], ad = ar[(ci + 3) * kk];
+            dz = fcadd(dz, fcmul(wa, aa));
+            d1 = fcadd(d1, fcmul(wb, ab));
+            d2 = fcadd(d2, fcmul(wc, ac));
+            d3 = fcadd(d3, fcmul(wd, ad));
+          }
+          for (; ci < C; ++ci) dz = fcadd(dz, fcmul(wr[ci * C], ar[ci * kk]));
+          dz = fcadd(fcadd(dz, d1), fcadd(d2, d3));
+        }
+      dzs[q] = dz;
+      P = fcmul(P, window_factor<VMC_F32>(dz, t2[c * N + mpos(g, site, -ey, -ex)]));
+      renorm(P, E);
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const float2 pq = make_float2(__shfl_xor(P.x, o, 64), __shfl_xor(P.y, o, 64));
+      const int eq = __shfl_xor(E, o, 64);
+      P = fcmul(P, pq);
+      E += eq;
+      renorm(P, E);
+    }
+    if (lane == 0) {
+      red[3 * wave] = P.x;
+      red[3 * wave + 1] = P.y;
+      red[3 * wave + 2] = (double)E;
+    }
+    __syncthreads();
+    double2 m = make_double2(1.0, 0.0);
+    double ex2 = 0.0;
+    for (int w = 0; w < MH_NT / 64; ++w) {
+      m = cmul(m, make_double2(red[3 * w], red[3 * w + 1]));
+      ex2 += red[3 * w + 2];
+    }
+    const double r = log(m.x * m.x + m.y * m.y) + 2.0 * ex2 * 0.69314718055994530942;
+    const bool accept = (r >= 0.0) || (u < exp(r));
+    if (accept) {
+      ++accepted;
+#pragma unroll
+      for (int q = 0; q < MH_MAXOUT; ++q) {
+        const int o = tid + MH_NT * q;
+        if (o >= g.nout) continue;
+        const int c = o % C, e = o / C, ey = e / g.win, ex = e % g.win;
+        const int qi = c * N + mpos(g, site, -ey, -ex);
+        const float2 zn = fcadd(z2[qi], dzs[q]);
+        z2[qi] = zn;
+        t2[qi] = fctanh(zn);
+      }
+      for (int e = tid; e < C * kk; e += MH_NT) {
+        const int ci = e / kk, w = e % kk;
+        const int p = mpos(g, site, -(w / g.k), -(w % g.k));
+        const float2 wv = W1f[e];
+        z1[ci * N + p] = make_float2(z1[ci * N + p].x - 2.f * sg * wv.x, z1[ci * N + p].y - 2.f * sg * wv.y);
+        a1i[ci * N + p] += dA[e].y;
+      }
+      if (tid == 0) cb[site >> 6] ^= 1ull << (site & 63);
+    }
+    __syncthreads();
+    if (step >= therm_steps && ((step - therm_steps + 1) % sweep) == 0) {
+      const int64_t kr = (step - therm_steps + 1) / sweep - 1;
+      const int64_t row = kr * n_chains + ch;
+      for (int w = tid; w < g.W; w += MH_NT) s_out[row * g.W + w] = cb[w];
+      if (logpsi_out) {
+        double2 lp = make_double2(0.0, 0.0);
+        for (int e = tid; e < CN; e += MH_NT) {
+          const float2 l = fclogcosh(z2[e]);
+          lp.x += l.x;
+          lp.y += l.y;
+        }
+        lp = mh_block_sum(lp, red);
+        if (tid == 0) logpsi_out[row] = lp;
+      }
+    }
+  }
+  for (int w = tid; w < g.W; w += MH_NT) bits[(int64_t)ch * g.W + w] = cb[w];
+  if (tid == 0) acc[ch] = accepted;
+}
+
+mh_geom make_mh_geom(const vmc_model* m) {
+  mh_geom g{};
+  g.Lx = m->Lx;
+  g.Ly = m->Ly;
+  g.N = m->N;
+  g.W = m->W;
+  g.C = m->C;
+  g.k = m->k;
+  g.kk = m->k * m->k;
+  g.win = 2 * m->k - 1;
+  g.nout = m->C * g.win * g.win;
+  const int CN = g.C * g.N;
+  int o = 0;
+  auto take = [&](int bytes) {
+    const int r = o;
+    o = (o + bytes + 15) & ~15;
+    return r;
+  };
+  g.o_z1 = take(8 * CN);
+  g.o_a1i = take(4 * CN);
+  g.o_z2 = take(8 * CN);
+  g.o_t2 = take(8 * CN);
+  g.o_w2 = take(8 * g.kk * g.C * g.C);
+  g.o_da = take(8 * g.C * g.kk);
+  g.o_cd = take(8 * g.C * g.kk);
+  g.o_sd = take(8 * g.C * g.kk);
+  g.o_red = take(8 * 3 * (MH_NT / 64));
+  g.o_cb = take(8 * g.W);
+  g.lds = o;
+  return g;
+}
+
 int align16(int x) { return (x + 15) & ~15; }
 
 lp_geom make_geom(const vmc_model* m, int prec) {
@@ -468,10 +749,10 @@ void cnn_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t 
   vmc_ctx* ctx = m->ctx;
   hipStream_t st = ctx->stream;
   const int n1 = m->C * m->k * m->k;
-  const size_t tb = sizeof(float2) * (size_t)(m->K + 2 * n1);
+  const size_t tb = sizeof(float2) * (size_t)(m->K + 3 * n1);
   ws_reserve(ctx, ws_round(tb));
   float2* P32 = (float2*)ws_take(ctx, tb);
-  k_lp_tables<<<grid_for(m->K + 2 * n1, 256), 256, 0, st>>>(m->params, m->K, n1, P32);
+  k_lp_tables<<<grid_for(m->K + 3 * n1, 256), 256, 0, st>>>(m->params, m->K, n1, P32);
   if (m->prec == VMC_BF16) {
     VMC_HIP(hipFuncSetAttribute((const void*)k_cnn_eloc_lp<VMC_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 g.lds));
@@ -483,3 +764,33 @@ void cnn_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t 
   }
   VMC_HIP(hipGetLastError());
 }
+
+void cnn_lowp_sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out) {
+  vmc_model* m = S->model;
+  VMC_REQUIRE(S->opts.proposal == VMC_PROP_FLIP, "the CNN sampler uses single-spin flips");
+  VMC_REQUIRE(m->Lx >= 2 * m->k - 1 && m->Ly >= 2 * m->k - 1, "the CNN sampler needs Lx, Ly >= 2 kernel - 1");
+  const mh_geom g = make_mh_geom(m);
+  VMC_REQUIRE(g.nout <= MH_MAXOUT * MH_NT, "CNN window too large for the sampler");
+  if (g.lds > 160 * 1024)
+    throw vmc_error{VMC_ERR_UNSUPPORTED, "CNN too large for the float32 sampler (LDS)"};
+  vmc_ctx* ctx = m->ctx;
+  hipStream_t st = ctx->stream;
+  const int n1 = m->C * m->k * m->k;
+  const size_t tb = sizeof(float2) * (size_t)(m->K + 3 * n1);
+  const size_t ab = sizeof(float2) * (size_t)S->opts.n_chains * m->C * m->N;
+  ws_reserve(ctx, ws_round(tb) + ws_round(ab));
+  float2* P32 = (float2*)ws_take(ctx, tb);
+  float2* a1 = (float2*)ws_take(ctx, ab);
+  k_lp_tables<<<grid_for(m->K + 3 * n1, 256), 256, 0, st>>>(m->params, m->K, n1, P32);
+  VMC_HIP(hipFuncSetAttribute((const void*)k_cnn_mh_lp, hipFuncAttributeMaxDynamicSharedMemorySize, g.lds));
+  const int64_t therm = S->thermalized ? 0 : (int64_t)S->opts.therm_sweeps * S->opts.sweep_steps;
+  const uint2 key = make_uint2((uint32_t)S->opts.seed, (uint32_t)(S->opts.seed >> 32));
+  k_cnn_mh_lp<<<S->opts.n_chains, MH_NT, g.lds, st>>>(g, P32, S->opts.n_chains, S->bits, key, S->t, !S->bits_valid,
+                                                      therm, n_per_chain, S->opts.sweep_steps, s_out, logpsi_out,
+                                                      S->acc, a1);
+  VMC_HIP(hipGetLastError());
+  S->t += (uint64_t)(therm + n_per_chain * S->opts.sweep_steps);
+  S->thermalized = 1;
+  S->bits_valid = 1;
+}
+

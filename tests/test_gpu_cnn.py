@@ -93,3 +93,47 @@ def test_sampler_replay(ctx):
             assert np.array_equal(s[kk, c], si.pack_bits(os_[kk, c])[0]), (kk, c)
     assert_logpsi_close(lp.ravel(), ol.ravel(), 1e-9)
     assert 0 < acc <= 1
+
+
+def test_lowp_sampler_histogram(ctx):
+    # float32 chains (VMC_F32 / VMC_BF16 models): the visit histogram on the
+    # 3 x 3 torus matches |psi|^2 of the float64 oracle
+    from scipy import stats
+    from gpu_common import host_bits
+    flush("cnn float32 sampler histogram")
+    Lx, Ly, C, k = 3, 3, 2, 2
+    m, p = _cnn(ctx, Lx, Ly, C, k, 0.4, seed=31)
+    m.set_precision(V.VMC_F32)
+    H = V.Hamiltonian.tfim(ctx, Lx, Ly, True, 1.0, 3.0)
+    S = V.Sampler(ctx, m, H, proposal=V.PROP_FLIP, n_chains=1024, therm_sweeps=20, seed=5)
+    s, _, acc = S.sample(1024 * 400)
+    assert 0 < acc < 1
+    dec = host_bits(s).reshape(400, 1024)[::4].reshape(-1).astype(np.int64)
+    cd = np.bincount(dec, minlength=2 ** 9)
+    _, prob, _ = oeloc.exact_probabilities(lambda b: ocnn.log_psi(p, b, Lx, Ly, C, k), 9)
+    res = stats.chisquare(cd, prob * cd.sum())
+    flush(f"  acceptance {acc:.3f}, chi2 p-value {res.pvalue:.3g}")
+    assert res.pvalue > 1e-4, res
+
+
+@pytest.mark.parametrize("Lx,Ly,C,k,std", [(8, 8, 3, 3, 0.3), (16, 16, 16, 4, 0.05), (9, 7, 17, 2, 0.1)])
+def test_lowp_sampler_log_psi(ctx, Lx, Ly, C, k, std):
+    # the chain's running log psi (float32 window products, float64 sum) stays
+    # on the oracle's log psi of the emitted configurations
+    from gpu_common import host_bits
+    flush(f"cnn float32 sampler log psi {Lx}x{Ly} C={C} k={k}")
+    m, p = _cnn(ctx, Lx, Ly, C, k, std, seed=41 + C)
+    m.set_precision(V.VMC_BF16)
+    H = V.Hamiltonian.tfim(ctx, Lx, Ly, True, 1.0, 3.0)
+    nc = 32
+    S = V.Sampler(ctx, m, H, proposal=V.PROP_FLIP, n_chains=nc, therm_sweeps=4, seed=9)
+    for call in range(2):
+        s, lp, acc = S.sample(nc * 3)
+        bits = si.unpack_bits(host_bits(s), Lx * Ly)
+        ref = ocnn.log_psi(p, bits, Lx, Ly, C, k)
+        got = lp.cpu().numpy()
+        err = np.abs(got.real - ref.real)
+        assert np.all(err <= 1e-4 * np.abs(ref.real) + 1e-3), (call, err.max())
+        dph = np.abs((got.imag - ref.imag + np.pi) % (2 * np.pi) - np.pi)
+        assert np.all(dph <= 1e-3), (call, dph.max())
+        assert 0 < acc <= 1
