@@ -3,9 +3,9 @@
 //
 // Two levels: 256-column panels, each factored as four 64-column blocks.
 // Per 64-column block b:
-//   k_chol_diag   one wavefront factors the diagonal block in LDS, writes
-//                 L_bb, inverts it and writes L_bb^{-1} (dense 64 x 64) to
-//                 the Linv buffer;
+//   k_chol_diag   one work-group factors the diagonal block in LDS (packed
+//                 lower triangle), writes L_bb, inverts it and writes
+//                 L_bb^{-1} (dense 64 x 64) to the Linv buffer;
 //   k_zmfma<0>    rows below: L_rb = A_rb L_bb^{-H}, a complex GEMM on the
 //                 float64 matrix cores (in place, one 64-row block per group);
 //   k_zmfma<2>    the rest of the panel's columns: A_rc -= L_rb L_cb^H.
@@ -37,77 +37,97 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int CB = 64;  // block size
 
-// element (r, c) of a 64 x 64 block in LDS, columns XOR-swizzled by the row so
-// that a lane per row (same c) and a lane per column (same r) both touch 64
-// distinct 16-byte slots
-__device__ __forceinline__ int sw(int r, int c) { return r * CB + (c ^ r); }
+__device__ __forceinline__ int pk(int r, int c) { return r * (r + 1) / 2 + c; }  // packed lower index
 
 // Factor and invert the diagonal block at kb0 (nb <= 64 valid rows/cols; the
-// rest is padded with the identity).  One wavefront, no cross-wave barriers:
-// lane r owns row r while factoring (right-looking, column by column), and
-// lane c owns column c of L^{-1} while inverting (row by row, in place).
-__global__ __launch_bounds__(64) void k_chol_diag(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
-                                                  double2* __restrict__ Linv, long long* __restrict__ fail,
-                                                  double* __restrict__ pivmin) {
-  extern __shared__ double2 L[];  // CB * CB, swizzled
+// rest is padded with the identity).  LDS holds the packed lower triangle.
+__global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
+                                                   double2* __restrict__ Linv, long long* __restrict__ fail,
+                                                   double* __restrict__ pivmin) {
+  __shared__ double2 L[CB * (CB + 1) / 2];
+  __shared__ int bad;
+  __shared__ double pmin;
   if (*fail >= 0) return;
-  const int l = threadIdx.x;
-  for (int r = 0; r < CB; ++r) {
-    double2 x = make_double2(0.0, 0.0);
-    if (l <= r) x = r < nb ? A[(kb0 + r) * K + kb0 + l] : make_double2(r == l ? 1.0 : 0.0, 0.0);
-    L[sw(r, l)] = x;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    if (c > r) continue;
+    double2 x;
+    if (r < nb)
+      x = A[(kb0 + r) * K + kb0 + c];
+    else
+      x = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    L[pk(r, c)] = x;
+  }
+  if (tid == 0) {
+    bad = 0;
+    pmin = INFINITY;
   }
   __syncthreads();
-  double pmin = INFINITY;
-  int bad = -1;
+  // right-looking factorisation; thread (ty, tx) updates rows ty + 16a, columns tx + 16b
+  const int ty = tid >> 4, tx = tid & 15;
   for (int j = 0; j < CB; ++j) {
-    const double d = L[sw(j, j)].x;
-    if (j < nb) {
-      pmin = fmin(pmin, d);
-      if (!(d > 0.0)) {
-        bad = j;
-        break;
+    if (tid == 0) {
+      const double d = L[pk(j, j)].x;
+      if (j < nb) {
+        pmin = fmin(pmin, d);
+        if (!(d > 0.0)) {
+          bad = 1;
+          *fail = kb0 + j;
+        }
       }
     }
-    const double lj = sqrt(d), il = 1.0 / lj;
-    double2 lr = make_double2(0.0, 0.0);
-    if (l > j) {
-      lr = cscale(L[sw(l, j)], il);
-      L[sw(l, j)] = lr;
-    }
     __syncthreads();
-    if (l == j) L[sw(j, j)] = make_double2(lj, 0.0);
-    if (l > j) {
-#pragma unroll 4
-      for (int c = j + 1; c <= l; ++c) L[sw(l, c)] = csub(L[sw(l, c)], cmul(lr, cconj(L[sw(c, j)])));
+    if (bad) break;
+    const double l = sqrt(L[pk(j, j)].x);
+    const double il = 1.0 / l;
+    if (tid > j && tid < CB) L[pk(tid, j)] = cscale(L[pk(tid, j)], il);
+    __syncthreads();
+    if (tid == 0) L[pk(j, j)] = make_double2(l, 0.0);
+#pragma unroll
+    for (int aa = 0; aa < 4; ++aa) {
+      const int r = ty + 16 * aa;
+      if (r <= j) continue;
+      const double2 lr = L[pk(r, j)];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const int c = tx + 16 * bb;
+        if (c > j && c <= r) L[pk(r, c)] = csub(L[pk(r, c)], cmul(lr, cconj(L[pk(c, j)])));
+      }
     }
     __syncthreads();
   }
-  if (l == 0) {
-    pivmin[kb0 / CB] = pmin;
-    if (bad >= 0) *fail = kb0 + bad;
+  if (tid == 0) pivmin[kb0 / CB] = pmin;
+  if (bad) return;
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    if (c <= r && r < nb) A[(kb0 + r) * K + kb0 + c] = L[pk(r, c)];
   }
-  if (bad >= 0) return;
-  for (int r = 0; r < nb; ++r)
-    if (l <= r) A[(kb0 + r) * K + kb0 + l] = L[sw(r, l)];
   __syncthreads();
-  // X = L^{-1}: X[r][c] = -(1 / L_rr) sum_{m=c}^{r-1} L[r][m] X[m][c]; row r of X
-  // replaces row r of L once every lane has read row r of L
-  if (l == 0) L[sw(0, 0)] = make_double2(1.0 / L[sw(0, 0)].x, 0.0);
+  // inverse X = L^{-1} by rows: X[r][c] = -(1/L_rr) sum_{m=c}^{r-1} L[r][m] X[m][c];
+  // row r of X overwrites row r of L once computed (rows < r already hold X).
+  // Four threads per column split the sum over m and combine by lane shuffles.
+  const int cc = tid >> 2, qq = tid & 3;
+  if (tid == 0) L[pk(0, 0)] = make_double2(1.0 / L[pk(0, 0)].x, 0.0);
   __syncthreads();
   for (int r = 1; r < CB; ++r) {
     double2 acc = make_double2(0.0, 0.0);
-    if (l < r) {
-#pragma unroll 4
-      for (int m = l; m < r; ++m) acc = cadd(acc, cmul(L[sw(r, m)], L[sw(m, l)]));
-    }
-    const double d = 1.0 / L[sw(r, r)].x;
+    if (cc < r)
+      for (int m = cc + qq; m < r; m += 4) acc = cadd(acc, cmul(L[pk(r, m)], L[pk(m, cc)]));
+    acc.x += __shfl_xor(acc.x, 1, 64);
+    acc.y += __shfl_xor(acc.y, 1, 64);
+    acc.x += __shfl_xor(acc.x, 2, 64);
+    acc.y += __shfl_xor(acc.y, 2, 64);
+    const double d = 1.0 / L[pk(r, r)].x;
     __syncthreads();
-    if (l < r) L[sw(r, l)] = cscale(acc, -d);
-    if (l == r) L[sw(r, r)] = make_double2(d, 0.0);
+    if (qq == 0 && cc < r) L[pk(r, cc)] = cscale(acc, -d);
+    if (tid == 0) L[pk(r, r)] = make_double2(d, 0.0);
     __syncthreads();
   }
-  for (int r = 0; r < CB; ++r) Linv[r * CB + l] = l <= r ? L[sw(r, l)] : make_double2(0.0, 0.0);
+  for (int e = tid; e < CB * CB; e += 256) {
+    const int r = e / CB, c = e % CB;
+    Linv[e] = c <= r ? L[pk(r, c)] : make_double2(0.0, 0.0);
+  }
 }
 
 struct zargs {
@@ -317,14 +337,12 @@ void chol_factor(vmc_ctx* ctx, double2* S, int64_t K, double2* Linv, long long* 
   // writes), so it waits for that update.
   hipStream_t aux = aux_stream(ctx);
   bool aux_busy = false;
-  VMC_HIP(hipFuncSetAttribute((const void*)k_chol_diag, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(double2) * CB * CB)));
   for (int64_t p0 = 0; p0 < K; p0 += PW) {
     const int64_t pend = std::min<int64_t>(K, p0 + PW);
     for (int64_t c0 = p0; c0 < pend; c0 += CB) {
       const int nb = (int)std::min<int64_t>(CB, K - c0);
       double2* Lb = Linv + (size_t)(c0 / CB) * CB * CB;
-      k_chol_diag<<<1, 64, sizeof(double2) * CB * CB, st>>>(S, K, c0, nb, Lb, fail, pivmin);
+      k_chol_diag<<<1, 256, 0, st>>>(S, K, c0, nb, Lb, fail, pivmin);
       const int64_t rest = K - c0 - nb;
       if (rest <= 0) continue;
       zargs a{};
