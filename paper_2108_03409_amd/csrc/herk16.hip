@@ -12,7 +12,8 @@
 // Layout for the matrix cores: the reduction runs over samples, so the split
 // data are stored column-major in groups of 8 samples: for column k and sample
 // group g, 4 x 8 halves [re_hi, re_lo, im_hi, im_lo] (64 bytes), which is one
-// lane's fragment set.
+// lane's fragment set.  The Gram kernel stages 128 + 128 columns x 32 samples
+// of these sets in LDS per step (see k_herk16).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -99,61 +100,83 @@ struct h16_args {
   int64_t n_tiles;
 };
 
-// 128 x 64 complex tile per 256-thread group (2 x 2 waves of 64 x 32); fragments
-// are read directly from global memory (each lane: 64 contiguous bytes per
-// 16-row block and sample group), 32 samples per step.
-__global__ __launch_bounds__(256) void k_herk16(h16_args a) {
+constexpr int TB = 128;  // tile edge (complex rows = columns)
+
+// 128 x 128 complex tile per 256-thread group (2 x 2 waves of 64 x 64, i.e.
+// 4 x 4 blocks of 16 x 16 per wave).  Each stage covers 32 samples (4 groups
+// of 8): the group stores the 128 + 128 columns' fragments (32 KB + 32 KB) in
+// LDS and every wave reads its fragments from there, so each value is fetched
+// from memory once per tile and stage.  The next stage's values are loaded
+// into registers while the current one is multiplied.
+__global__ __launch_bounds__(256, 1) void k_herk16(h16_args a) {
+  __shared__ halfx8 As[TB * 4 * 4];  // [col][group][Rh, Rl, Ih, Il]
+  __shared__ halfx8 Bs[TB * 4 * 4];
   const int64_t nb = a.n_tiles;
   const int64_t per = (nb + 7) / 8;
   const int64_t lin = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (lin >= nb) return;
-  int tr = (int)((sqrt(4.0 * (double)lin + 1.0) - 1.0) * 0.5);
-  while ((int64_t)(tr + 1) * (tr + 2) <= lin) ++tr;
-  while ((int64_t)tr * (tr + 1) > lin) --tr;
-  const int tc = (int)(lin - (int64_t)tr * (tr + 1));
-  const int64_t row0 = (int64_t)tr * 128, col0 = (int64_t)tc * 64;
+  int tr = (int)((sqrt(8.0 * (double)lin + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(tr + 1) * (tr + 2) / 2 <= lin) ++tr;
+  while ((int64_t)tr * (tr + 1) / 2 > lin) --tr;
+  const int tc = (int)(lin - (int64_t)tr * (tr + 1) / 2);
+  const int64_t row0 = (int64_t)tr * TB, col0 = (int64_t)tc * TB;
   const int64_t K = a.K;
-  if (col0 >= K) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
-  floatx4 acc[4][2][2];
+  floatx4 acc[4][4][2];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) acc[i][j][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j][0] = floatx4{0.f, 0.f, 0.f, 0.f};
+      acc[i][j][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
   const halfx8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+  // 128 columns x 4 groups x 4 vectors = 2048 vectors per operand, 8 per thread
+  halfx8 pa[8], pb[8];
+  auto gload = [&](int64_t g0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int id = tid + 256 * q;
+      const int col = id >> 4, gg = (id >> 2) & 3, v = id & 3;
+      const int64_t g = g0 + gg;
+      const int64_t ka = row0 + col, kb = col0 + col;
+      pa[q] = (ka < K && g < a.ngroups) ? a.H[(ka * a.ngroups + g) * 4 + v] : z;
+      pb[q] = (kb < K && g < a.ngroups) ? a.H[(kb * a.ngroups + g) * 4 + v] : z;
+    }
+  };
+  gload(0);
   for (int64_t g0 = 0; g0 < a.ngroups; g0 += 4) {
-    const int64_t g = g0 + lk;  // this lane's group of 8 samples
-    halfx8 A[4][4], Bf[2][4];
+    __syncthreads();  // previous stage's fragments are consumed
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      As[tid + 256 * q] = pa[q];
+      Bs[tid + 256 * q] = pb[q];
+    }
+    __syncthreads();
+    if (g0 + 4 < a.ngroups) gload(g0 + 4);
+    halfx8 A[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t k = row0 + wr * 64 + i * 16 + li;
-      const bool ok = k < K && g < a.ngroups;
-      const halfx8* src = a.H + (k * a.ngroups + g) * 4;
+      const int col = wr * 64 + i * 16 + li;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) A[i][q] = ok ? src[q] : z;
+      for (int v = 0; v < 4; ++v) A[i][v] = As[(col * 4 + lk) * 4 + v];
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int64_t k = col0 + wc * 32 + j * 16 + li;
-      const bool ok = k < K && g < a.ngroups;
-      const halfx8* src = a.H + (k * a.ngroups + g) * 4;
+    for (int j = 0; j < 4; ++j) {
+      const int col = wc * 64 + j * 16 + li;
+      halfx8 Bf[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Bf[j][q] = ok ? src[q] : z;
-    }
+      for (int v = 0; v < 4; ++v) Bf[v] = Bs[(col * 4 + lk) * 4 + v];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const halfx8 nih = -A[i][2], nil = -A[i][3];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int i = 0; i < 4; ++i) {
+        const halfx8 nih = -A[i][2], nil = -A[i][3];
         // re += re re' + im im',  im += re im' - im re';  each product hi hi + hi lo + lo hi
-#define P3(acc_, xh, xl, y)                                                              \
-  acc_ = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, Bf[j][y], acc_, 0, 0, 0);            \
-  acc_ = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, Bf[j][y + 1], acc_, 0, 0, 0);        \
-  acc_ = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl, Bf[j][y], acc_, 0, 0, 0);
+#define P3(acc_, xh, xl, y)                                                        \
+  acc_ = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, Bf[y], acc_, 0, 0, 0);         \
+  acc_ = __builtin_amdgcn_mfma_f32_16x16x32_f16(xh, Bf[y + 1], acc_, 0, 0, 0);     \
+  acc_ = __builtin_amdgcn_mfma_f32_16x16x32_f16(xl, Bf[y], acc_, 0, 0, 0);
         P3(acc[i][j][0], A[i][0], A[i][1], 0);
         P3(acc[i][j][0], A[i][2], A[i][3], 2);
         P3(acc[i][j][1], A[i][0], A[i][1], 2);
@@ -165,14 +188,14 @@ __global__ __launch_bounds__(256) void k_herk16(h16_args a) {
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t k = row0 + wr * 64 + i * 16 + 4 * lk + r;
-        const int64_t kp = col0 + wc * 32 + j * 16 + li;
+        const int64_t kp = col0 + wc * 64 + j * 16 + li;
         if (k >= K || kp >= K || kp > k) continue;
         const double sc = ldexp(1.0, -(a.ex[k] + a.ex[kp]));
-        double re = (double)acc[i][j][0][r] * sc;
+        const double re = (double)acc[i][j][0][r] * sc;
         double im = (double)acc[i][j][1][r] * sc;
         if (a.mode == VMC_SR_REAL) im = 0.0;
         if (k == kp) {
@@ -217,8 +240,8 @@ void herk_split16(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode,
   a.eps = eps;
   a.S = S;
   a.diag = diag;
-  const int64_t rt = (K + 127) / 128;
-  a.n_tiles = rt * (rt + 1);
+  const int64_t rt = (K + TB - 1) / TB;
+  a.n_tiles = rt * (rt + 1) / 2;  // lower-triangle tiles, diagonal included
   k_herk16<<<(unsigned)(((a.n_tiles + 7) / 8) * 8), 256, 0, st>>>(a);
   VMC_HIP(hipGetLastError());
 }
