@@ -379,6 +379,8 @@ extern "C" int vmc_model_destroy(vmc_model* m) {
     if (t.D) (void)hipFree(t.D);
     if (t.LC) (void)hipFree(t.LC);
     if (t.alpha) (void)hipFree(t.alpha);
+    if (t.Tt) (void)hipFree(t.Tt);
+    if (t.Dt) (void)hipFree(t.Dt);
   }
   vmc_ctx* ctx = m->ctx;
   delete m;

@@ -137,6 +137,8 @@ struct rbm_move_tables {
   double2* D = nullptr;    // [N_h][n_moves] D_jm
   double2* LC = nullptr;   // [n_moves] sum_j logcosh(2 D_jm)
   double2* alpha = nullptr;  // [n_moves] visible-bias difference
+  double2* Tt = nullptr;     // [n_moves][N_h] T transposed (sampler: lanes over hidden units)
+  double2* Dt = nullptr;     // [n_moves][N_h] D transposed
 };
 
 struct vmc_model {

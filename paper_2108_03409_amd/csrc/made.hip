@@ -132,6 +132,8 @@ __global__ void k_adam(double* __restrict__ p, const double* __restrict__ g, dou
 }
 
 // Autoregressive sampling, one wave per row; hidden units k = lane + 64 q.
+// The W2 and W1^T rows of site d are loaded one site ahead (they do not depend
+// on the decisions); the arithmetic order is that of the plain loop.
 template <int QH>
 __global__ __launch_bounds__(64) void k_made_sample(const double* __restrict__ W1mT, const double* __restrict__ W2m,
                                                     const double* __restrict__ b1, const double* __restrict__ b2,
@@ -143,22 +145,30 @@ __global__ __launch_bounds__(64) void k_made_sample(const double* __restrict__ W
   if (c >= B) return;
   const int lane = threadIdx.x;
   for (int w = lane; w < W; w += 64) sb[w] = 0ull;
-  double a[QH];
+  double a[QH], w2c[QH], w2n[QH], w1c[QH];
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
     const int k = lane + 64 * q;
     a[q] = k < H ? b1[k] : 0.0;
+    w2n[q] = k < H ? W2m[k] : 0.0;
   }
   __syncthreads();
   double lq = 0.0;
   uint4 x4 = make_uint4(0, 0, 0, 0);
   for (int d = 0; d < N; ++d) {
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int k = lane + 64 * q;
+      w2c[q] = w2n[q];
+      w1c[q] = k < H ? W1mT[(int64_t)d * H + k] : 0.0;
+      w2n[q] = (k < H && d + 1 < N) ? W2m[(int64_t)(d + 1) * H + k] : 0.0;
+    }
     if ((d & 3) == 0) x4 = philox(make_uint4((uint32_t)c, lo, hi, 1u + 256u * (uint32_t)(d >> 2)), key);
     double part = 0.0;
 #pragma unroll
     for (int q = 0; q < QH; ++q) {
       const int k = lane + 64 * q;
-      if (k < H) part += W2m[(int64_t)d * H + k] * fmax(a[q], 0.0);
+      if (k < H) part += w2c[q] * fmax(a[q], 0.0);
     }
     double l = wave_sum(part);
     l = __shfl(l, 0, 64) + b2[d];
@@ -170,7 +180,7 @@ __global__ __launch_bounds__(64) void k_made_sample(const double* __restrict__ W
 #pragma unroll
       for (int q = 0; q < QH; ++q) {
         const int k = lane + 64 * q;
-        if (k < H) a[q] += W1mT[(int64_t)d * H + k];
+        if (k < H) a[q] += w1c[q];
       }
       if (lane == 0) sb[d >> 6] |= 1ull << (d & 63);
     }

@@ -286,6 +286,18 @@ void rbm_theta(vmc_model* m, const uint64_t* s, int64_t B, double2* theta) {
   VMC_HIP(hipGetLastError());
 }
 
+namespace {
+// [rows][cols] -> [cols][rows] for two tables at once (sampler layout)
+__global__ void k_transpose2(const double2* __restrict__ A, const double2* __restrict__ B, int rows, int cols,
+                             double2* __restrict__ At, double2* __restrict__ Bt) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)rows * cols) return;
+  const int64_t r = e / cols, c = e % cols;
+  At[c * rows + r] = A[e];
+  Bt[c * rows + r] = B[e];
+}
+}  // namespace
+
 void rbm_ensure_tables(vmc_model* m, const vmc_ham* H, int move_kind) {
   rbm_move_tables& tb = m->tab[move_kind];
   const int n_moves = move_kind == 0 ? m->N : H->n_bonds;
@@ -296,10 +308,14 @@ void rbm_ensure_tables(vmc_model* m, const vmc_ham* H, int move_kind) {
     if (tb.D) VMC_HIP(hipFree(tb.D));
     if (tb.LC) VMC_HIP(hipFree(tb.LC));
     if (tb.alpha) VMC_HIP(hipFree(tb.alpha));
-    tb.T = tb.D = tb.LC = tb.alpha = nullptr;
+    if (tb.Tt) VMC_HIP(hipFree(tb.Tt));
+    if (tb.Dt) VMC_HIP(hipFree(tb.Dt));
+    tb.T = tb.D = tb.LC = tb.alpha = tb.Tt = tb.Dt = nullptr;
     size_t tsz = sizeof(double2) * (size_t)m->Nh * std::max(1, n_moves);
     VMC_HIP(hipMalloc(&tb.T, tsz));
     VMC_HIP(hipMalloc(&tb.D, tsz));
+    VMC_HIP(hipMalloc(&tb.Tt, tsz));
+    VMC_HIP(hipMalloc(&tb.Dt, tsz));
     VMC_HIP(hipMalloc(&tb.LC, sizeof(double2) * std::max(1, n_moves)));
     VMC_HIP(hipMalloc(&tb.alpha, sizeof(double2) * std::max(1, n_moves)));
   }
@@ -309,6 +325,8 @@ void rbm_ensure_tables(vmc_model* m, const vmc_ham* H, int move_kind) {
   if (n_moves > 0) {
     k_tables<<<n_moves, 64, 0, m->ctx->stream>>>(m->params, H->bonds, move_kind, n_moves, m->N, m->Nh, tb.T, tb.D,
                                                  tb.LC, tb.alpha);
+    const int64_t n = (int64_t)m->Nh * n_moves;
+    k_transpose2<<<grid_for(n, 256), 256, 0, m->ctx->stream>>>(tb.T, tb.D, m->Nh, n_moves, tb.Tt, tb.Dt);
     VMC_HIP(hipGetLastError());
   }
   tb.param_version = m->version;

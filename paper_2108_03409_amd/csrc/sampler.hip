@@ -24,8 +24,8 @@ namespace {
 struct sampler_args {
   const double2* params;
   const double2* Wt;
-  const double2* T;
-  const double2* D;
+  const double2* T;  // [n_moves][N_h]
+  const double2* D;  // [n_moves][N_h]
   const double2* LC;
   const double2* alpha;
   const int2* bonds;
@@ -61,13 +61,19 @@ __device__ __forceinline__ double softplus_d(double x) { return fmax(x, 0.0) + l
 // One autoregressive pass of the MADE over the wave: samples s' into out (when
 // sample == true, using Philox purpose-1 counters of (c, t)) or evaluates the
 // given configuration in out (teacher forcing).  Returns log q (uniform).
+// Hidden units k = lane + 64 q, q < QH.  The rows of W2 (logits) and W1^T
+// (hidden update) that site d needs do not depend on the decisions, so they
+// are loaded one site ahead; the arithmetic and its order are those of the
+// plain loop.
+template <int QH>
 __device__ double made_pass(const sampler_args& a, uint64_t* out, bool sample, uint32_t c, uint64_t t, int lane) {
   const int N = a.N, H = a.mH;
-  double act[QH_MAX];
+  double act[QH], w2c[QH], w2n[QH], w1c[QH];
 #pragma unroll
-  for (int q = 0; q < QH_MAX; ++q) {
+  for (int q = 0; q < QH; ++q) {
     const int k = lane + 64 * q;
     act[q] = k < H ? a.mb1[k] : 0.0;
+    w2n[q] = k < H ? a.mW2[k] : 0.0;
   }
   if (sample) {
     for (int w = lane; w < a.W; w += 64) out[w] = 0ull;
@@ -76,11 +82,18 @@ __device__ double made_pass(const sampler_args& a, uint64_t* out, bool sample, u
   double lq = 0.0;
   uint4 x4 = make_uint4(0, 0, 0, 0);
   for (int d = 0; d < N; ++d) {
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int k = lane + 64 * q;
+      w2c[q] = w2n[q];
+      w1c[q] = k < H ? a.mW1T[(int64_t)d * H + k] : 0.0;
+      w2n[q] = (k < H && d + 1 < N) ? a.mW2[(int64_t)(d + 1) * H + k] : 0.0;
+    }
     double part = 0.0;
 #pragma unroll
-    for (int q = 0; q < QH_MAX; ++q) {
+    for (int q = 0; q < QH; ++q) {
       const int k = lane + 64 * q;
-      if (k < H) part += a.mW2[(int64_t)d * H + k] * fmax(act[q], 0.0);
+      if (k < H) part += w2c[q] * fmax(act[q], 0.0);
     }
     double l = wave_sum(part);
     l = __shfl(l, 0, 64) + a.mb2[d];
@@ -95,9 +108,9 @@ __device__ double made_pass(const sampler_args& a, uint64_t* out, bool sample, u
     lq += (up ? l : 0.0) - softplus_d(l);
     if (up) {
 #pragma unroll
-      for (int q = 0; q < QH_MAX; ++q) {
+      for (int q = 0; q < QH; ++q) {
         const int k = lane + 64 * q;
-        if (k < H) act[q] += a.mW1T[(int64_t)d * H + k];
+        if (k < H) act[q] += w1c[q];
       }
       if (sample && lane == 0) out[d >> 6] |= 1ull << (d & 63);
     }
@@ -106,10 +119,14 @@ __device__ double made_pass(const sampler_args& a, uint64_t* out, bool sample, u
   return lq;
 }
 
-template <int Q, bool MIX>
+template <int Q, bool MIX, int QH>
 __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   __shared__ uint64_t cb[64];  // chain configuration, W <= 64 words
   __shared__ uint64_t sp[64];  // global proposal (MADE_MIX)
+  // theta_j of the chain (and theta'_j of a global proposal) in lane-private
+  // LDS slots [q][lane]: registers hold only t_j = tanh theta_j
+  __shared__ double2 ths[Q * 64];
+  __shared__ double2 thns[MIX ? Q * 64 : 1];
   const int c = blockIdx.x;
   if (c >= a.n_chains) return;
   const int lane = threadIdx.x;
@@ -145,63 +162,82 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   __syncthreads();
 
   // theta_j = b_j + sum_i W_ji sigma_i for the lane's hidden units
-  double2 th[Q], tt[Q];
-#pragma unroll
+  double2 tt[Q];
   for (int q = 0; q < Q; ++q) {
     const int j = lane + 64 * q;
-    th[q] = j < Nh ? a.params[N + j] : make_double2(0.0, 0.0);
-  }
-  for (int i = 0; i < N; ++i) {
-    const bool up = (cb[i >> 6] >> (i & 63)) & 1ull;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int j = lane + 64 * q;
-      if (j < Nh) {
+    double2 acc = j < Nh ? a.params[N + j] : make_double2(0.0, 0.0);
+    if (j < Nh)
+      for (int i = 0; i < N; ++i) {
+        const bool up = (cb[i >> 6] >> (i & 63)) & 1ull;
         const double2 w = a.Wt[(int64_t)i * Nh + j];
-        th[q].x += up ? w.x : -w.x;
-        th[q].y += up ? w.y : -w.y;
+        acc.x += up ? w.x : -w.x;
+        acc.y += up ? w.y : -w.y;
       }
-    }
+    ths[q * 64 + lane] = acc;
   }
 #pragma unroll
-  for (int q = 0; q < Q; ++q) tt[q] = ctanh(th[q]);
+  for (int q = 0; q < Q; ++q) tt[q] = ctanh(ths[q * 64 + lane]);
 
   unsigned long long accepted = 0, acc_g = 0, n_g = 0;
   double lq_cur = 0.0;
   bool lq_valid = false;
   const int64_t total = a.therm_steps + a.n_record * a.sweep;
+  // The move of step t + 1 is known from its counter before step t resolves:
+  // its row of T is loaded one step ahead (local-move kernels with up to 512
+  // hidden units, where the extra registers fit).
+  constexpr bool PF = !MIX && Q <= 8;
+  uint4 xn = philox(make_uint4((uint32_t)c, (uint32_t)a.t0, (uint32_t)(a.t0 >> 32), 0u), a.key);
+  double2 Tn[PF ? Q : 1];
+  if (PF) {
+    const int mn = (int)to_index(xn.x, (uint32_t)a.n_moves);
+#pragma unroll
+    for (int q = 0; q < (PF ? Q : 1); ++q) {
+      const int j = lane + 64 * q;
+      Tn[q] = j < Nh ? a.T[(int64_t)mn * Nh + j] : make_double2(0.0, 0.0);
+    }
+  }
   for (int64_t step = 0; step < total; ++step) {
     const uint64_t t = a.t0 + (uint64_t)step;
-    const uint4 x = philox(make_uint4((uint32_t)c, (uint32_t)t, (uint32_t)(t >> 32), 0u), a.key);
+    const uint4 x = xn;
     const int m = (int)to_index(x.x, (uint32_t)a.n_moves);
     const double u = to_uniform(x.y, x.z);
+    double2 Tc[PF ? Q : 1];
+    if (PF) {
+#pragma unroll
+      for (int q = 0; q < (PF ? Q : 1); ++q) Tc[q] = Tn[q];
+    }
+    if (step + 1 < total) {
+      xn = philox(make_uint4((uint32_t)c, (uint32_t)(t + 1), (uint32_t)((t + 1) >> 32), 0u), a.key);
+      if (PF) {
+        const int mn = (int)to_index(xn.x, (uint32_t)a.n_moves);
+#pragma unroll
+        for (int q = 0; q < (PF ? Q : 1); ++q) {
+          const int j = lane + 64 * q;
+          Tn[q] = j < Nh ? a.T[(int64_t)mn * Nh + j] : make_double2(0.0, 0.0);
+        }
+      }
+    }
     if (MIX && (double)x.w * 0x1.0p-32 < a.p_global) {
       // ---- global MADE proposal with exact Metropolis-Hastings acceptance ----
       ++n_g;
       if (!lq_valid) {
-        lq_cur = made_pass(a, cb, false, (uint32_t)c, t, lane);
+        lq_cur = made_pass<QH>(a, cb, false, (uint32_t)c, t, lane);
         lq_valid = true;
       }
-      const double lq_new = made_pass(a, sp, true, (uint32_t)c, t, lane);
-      double2 thn[Q];
-#pragma unroll
+      const double lq_new = made_pass<QH>(a, sp, true, (uint32_t)c, t, lane);
       for (int q = 0; q < Q; ++q) {
         const int j = lane + 64 * q;
-        thn[q] = j < Nh ? a.params[N + j] : make_double2(0.0, 0.0);
+        double2 acc = j < Nh ? a.params[N + j] : make_double2(0.0, 0.0);
+        if (j < Nh)
+          for (int i = 0; i < N; ++i) {
+            const bool up = (sp[i >> 6] >> (i & 63)) & 1ull;
+            const double2 w = a.Wt[(int64_t)i * Nh + j];
+            acc.x += up ? w.x : -w.x;
+            acc.y += up ? w.y : -w.y;
+          }
+        thns[q * 64 + lane] = acc;
       }
       double dre = 0.0;  // 2 Re(log psi(s') - log psi(s)), lane partial
-      for (int i = 0; i < N; ++i) {
-        const bool up = (sp[i >> 6] >> (i & 63)) & 1ull;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const int j = lane + 64 * q;
-          if (j < Nh) {
-            const double2 w = a.Wt[(int64_t)i * Nh + j];
-            thn[q].x += up ? w.x : -w.x;
-            thn[q].y += up ? w.y : -w.y;
-          }
-        }
-      }
       for (int i = lane; i < N; i += 64) {
         const double sn = ((sp[i >> 6] >> (i & 63)) & 1ull) ? 1.0 : -1.0;
         const double so = ((cb[i >> 6] >> (i & 63)) & 1ull) ? 1.0 : -1.0;
@@ -210,7 +246,7 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int j = lane + 64 * q;
-        if (j < Nh) dre += 2.0 * (clogcosh(thn[q]).x - clogcosh(th[q]).x);
+        if (j < Nh) dre += 2.0 * (clogcosh(thns[q * 64 + lane]).x - clogcosh(ths[q * 64 + lane]).x);
       }
       double dr = wave_sum(dre);
       dr = __shfl(dr, 0, 64);
@@ -221,8 +257,9 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
         ++acc_g;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-          th[q] = thn[q];
-          tt[q] = ctanh(thn[q]);
+          const double2 v = thns[q * 64 + lane];
+          ths[q * 64 + lane] = v;
+          tt[q] = ctanh(v);
         }
         __syncthreads();
         for (int w = lane; w < W; w += 64) cb[w] = sp[w];
@@ -247,7 +284,7 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
       for (int q = 0; q < Q; ++q) {
         const int j = lane + 64 * q;
         if (j < Nh) {
-          const double2 p = cmul(tt[q], a.T[(int64_t)j * a.n_moves + m]);
+          const double2 p = cmul(tt[q], PF ? Tc[PF ? q : 0] : a.T[(int64_t)m * Nh + j]);
           const double fx = 1.0 - sg * p.x, fy = -sg * p.y;
           prod *= fx * fx + fy * fy;
         }
@@ -263,10 +300,12 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
         for (int q = 0; q < Q; ++q) {
           const int j = lane + 64 * q;
           if (j < Nh) {
-            const double2 d = a.D[(int64_t)j * a.n_moves + m];
-            const double2 Tm = a.T[(int64_t)j * a.n_moves + m];
-            th[q].x -= 2.0 * sg * d.x;
-            th[q].y -= 2.0 * sg * d.y;
+            const double2 d = a.D[(int64_t)m * Nh + j];
+            const double2 Tm = PF ? Tc[PF ? q : 0] : a.T[(int64_t)m * Nh + j];
+            double2 thv = ths[q * 64 + lane];
+            thv.x -= 2.0 * sg * d.x;
+            thv.y -= 2.0 * sg * d.y;
+            ths[q * 64 + lane] = thv;
             const double2 p = cmul(tt[q], Tm);
             tt[q] = cdiv(make_double2(tt[q].x - sg * Tm.x, tt[q].y - sg * Tm.y),
                          make_double2(1.0 - sg * p.x, -sg * p.y));
@@ -297,8 +336,9 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
       for (int q = 0; q < Q; ++q) {
         const int j = lane + 64 * q;
         if (j < Nh) {
-          lp = cadd(lp, clogcosh(th[q]));
-          tt[q] = ctanh(th[q]);
+          const double2 thv = ths[q * 64 + lane];
+          lp = cadd(lp, clogcosh(thv));
+          tt[q] = ctanh(thv);
         }
       }
       lp = wave_sum(lp);
@@ -317,10 +357,12 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
 
 template <int Q>
 void launch(const sampler_args& a, hipStream_t st) {
-  if (a.proposal == VMC_PROP_MADE_MIX)
-    k_metropolis<Q, true><<<a.n_chains, 64, 0, st>>>(a);
+  if (a.proposal != VMC_PROP_MADE_MIX)
+    k_metropolis<Q, false, 1><<<a.n_chains, 64, 0, st>>>(a);
+  else if (a.mH <= 64 * 8)
+    k_metropolis<Q, true, 8><<<a.n_chains, 64, 0, st>>>(a);
   else
-    k_metropolis<Q, false><<<a.n_chains, 64, 0, st>>>(a);
+    k_metropolis<Q, true, QH_MAX><<<a.n_chains, 64, 0, st>>>(a);
 }
 
 }  // namespace
@@ -335,8 +377,8 @@ void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* 
   sampler_args a{};
   a.params = m->params;
   a.Wt = m->Wt;
-  a.T = tb.T;
-  a.D = tb.D;
+  a.T = tb.Tt;
+  a.D = tb.Dt;
   a.LC = tb.LC;
   a.alpha = tb.alpha;
   a.bonds = S->ham->bonds;
