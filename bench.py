@@ -59,6 +59,9 @@ def parse():
                              "tfim2d_20x20_rbm_a2_made"])
     ap.add_argument("--p-global", type=float, default=None, help="MADE mix: global proposal probability")
     ap.add_argument("--record-sweeps", type=int, default=256, help="MADE mix: recorded sweeps per chain")
+    ap.add_argument("--made-epochs", type=int, default=100, help="MADE mix: training epochs")
+    ap.add_argument("--made-lr", type=float, default=1e-3, help="MADE mix: Adam learning rate")
+    ap.add_argument("--made-hidden", type=int, default=None, help="MADE mix: hidden units (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tau", type=float, default=1e-2)
     ap.add_argument("--prec", choices=["f64", "f32", "bf16"], default="f64",
@@ -237,10 +240,11 @@ def bench_made(args, V, torch):
     data, _, _ = src.sample(cfg["train_samples"])
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    made = V.MADE(ctx, N, cfg["made_hidden"])
-    made.set_params(torch.from_numpy(si.made_params(N, cfg["made_hidden"], seed=cfg["made_seed"])).to(dev))
+    mh = args.made_hidden or cfg["made_hidden"]
+    made = V.MADE(ctx, N, mh)
+    made.set_params(torch.from_numpy(si.made_params(N, mh, seed=cfg["made_seed"])).to(dev))
     t0 = time.perf_counter()
-    nll = made.train(data, epochs=20, batch=1024, lr=1e-3)
+    nll = made.train(data, epochs=args.made_epochs, batch=1024, lr=args.made_lr)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     pg = args.p_global if args.p_global is not None else 1.0 / N
@@ -260,9 +264,15 @@ def bench_made(args, V, torch):
         a, ga, ng = S.stats()
         el = model.local_energy(H, s).real.cpu().numpy().reshape(R, nc)
         n_eff, tau = pstats.ess(el)
+        # |magnetisation| per site: the slow observable of the critical state
+        pop = np.bitwise_count(s.cpu().numpy().view(np.uint64)).sum(axis=1).astype(np.float64)
+        mag = (np.abs(2.0 * pop - N) / N).reshape(R, nc)
+        m_eff, m_tau = pstats.ess(mag)
         res[name] = {"ess": n_eff, "tau_int_sweeps": tau, "sample_s": t_s, "ess_per_s": n_eff / t_s,
                      "accept": a, "global_accept": ga, "n_global": ng,
-                     "energy": float(el.mean()), "sigma_energy": float(np.sqrt(el.var() / n_eff))}
+                     "energy": float(el.mean()), "sigma_energy": float(np.sqrt(el.var() / n_eff)),
+                     "ess_abs_m": m_eff, "tau_int_abs_m_sweeps": m_tau, "ess_abs_m_per_s": m_eff / t_s,
+                     "abs_m": float(mag.mean())}
     ratio = res["mixed"]["ess_per_s"] / res["local"]["ess_per_s"]
     out = {
         "metric": METRIC, "value": round(res["mixed"]["ess_per_s"], 2), "unit": "effective samples/s",
@@ -270,8 +280,11 @@ def bench_made(args, V, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (bond-RBM at the 2D Ising critical coupling)",
         "config": {"workload": args.workload, "n_chains": nc, "record_sweeps": R, "p_global": pg,
-                   "made_hidden": cfg["made_hidden"], "train_samples": cfg["train_samples"]},
+                   "made_hidden": mh, "train_samples": cfg["train_samples"], "made_epochs": args.made_epochs,
+                   "made_lr": args.made_lr},
         "local": res["local"], "mixed": res["mixed"], "ess_per_s_ratio_mixed_over_local": round(ratio, 3),
+        "abs_m_ess_per_s_ratio_mixed_over_local": round(res["mixed"]["ess_abs_m_per_s"] /
+                                                        res["local"]["ess_abs_m_per_s"], 3),
         "train_s": round(t_train, 3), "train_data_s": round(t_data, 3), "final_nll": nll,
     }
     print(json.dumps(out), flush=True)
