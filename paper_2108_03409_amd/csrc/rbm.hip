@@ -110,9 +110,124 @@ __global__ __launch_bounds__(64) void k_tables(const double2* __restrict__ param
   }
 }
 
-// Fused enumeration + evaluation + reduction of E_loc; one wave per sample.
-// LDS: t_j (Nh complex) and the compacted move list (<= n_moves ints).
+// Local energies, S samples per wavefront, for move sets shared by all samples
+// (single-spin flips of the TFIM; the kernel also accepts bonds, masked per
+// sample to the anti-aligned ones).  Lanes run over the moves, and every table
+// entry T_jm read from memory serves the S samples, whose tanh theta_j sit in
+// LDS.  For each (sample,
+// move) the product prod_j (1 - sigma t_j T_jm) is kept with exact
+// power-of-two rescaling, and
+//   E_loc = diag + mel * sum_m exp(-2 sigma_m alpha_m + LC_m + log prod).
+template <int S>
 __global__ __launch_bounds__(64) void k_eloc(const double2* __restrict__ theta, const uint64_t* __restrict__ s,
+                                             int64_t B, int N, int W, int Nh, int ham_kind, double J, double h,
+                                             const int2* __restrict__ bonds, int n_bonds,
+                                             const double2* __restrict__ T, const double2* __restrict__ LC,
+                                             const double2* __restrict__ alpha, int n_moves,
+                                             double2* __restrict__ eloc) {
+  extern __shared__ double2 tl[];  // [S][Nh]
+  const int64_t b0 = (int64_t)blockIdx.x * S;
+  if (b0 >= B) return;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < S * Nh; e += 64) {
+    const int q = e / Nh, j = e - q * Nh;
+    tl[e] = b0 + q < B ? ctanh(theta[(b0 + q) * Nh + j]) : make_double2(0.0, 0.0);
+  }
+  // diagonal element: coupling * (n_aligned - n_anti), exact integer count
+  double diag[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    int n_al = 0;
+    if (b0 + q < B) {
+      const uint64_t* sn = s + (b0 + q) * W;
+      for (int b = lane; b < n_bonds; b += 64) {
+        const int2 bd = bonds[b];
+        n_al += get_bit(sn, bd.x) == get_bit(sn, bd.y);
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n_al += __shfl_xor(n_al, o, 64);
+    const int n_anti = n_bonds - n_al;
+    diag[q] = ham_kind == HAM_TFIM ? -J * (double)(n_al - n_anti) : J * (double)(n_al - n_anti);
+  }
+  __syncthreads();
+  const double mel = ham_kind == HAM_TFIM ? -h : 2.0 * J;
+  const bool off = ham_kind == HAM_TFIM ? h != 0.0 : J != 0.0;
+  double2 acc[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) acc[q] = make_double2(0.0, 0.0);
+  if (off)
+    for (int m0 = 0; m0 < n_moves; m0 += 64) {
+      const int m = m0 + lane;
+      if (m >= n_moves) continue;
+      const int site = ham_kind == HAM_TFIM ? m : bonds[m].x;
+      const int site2 = ham_kind == HAM_TFIM ? -1 : bonds[m].y;
+      double sg[S];
+      bool active[S];
+      double2 P[S];
+      int e2[S];
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        const bool in = b0 + q < B;
+        const uint64_t* sn = s + (in ? b0 + q : b0) * W;
+        const int bi = get_bit(sn, site);
+        sg[q] = bi ? 1.0 : -1.0;
+        active[q] = in && (site2 < 0 || bi != get_bit(sn, site2));
+        P[q] = make_double2(1.0, 0.0);
+        e2[q] = 0;
+      }
+      const double2* Tm = T + m;
+      for (int j0 = 0; j0 < Nh; j0 += 32) {
+        const int j1 = min(Nh, j0 + 32);
+        for (int jb = j0; jb < j1; jb += 8) {
+          // eight table loads in flight before the products that use them
+          double2 Tv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            Tv[u] = jb + u < j1 ? Tm[(int64_t)(jb + u) * n_moves] : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (jb + u >= j1) break;
+            const int j = jb + u;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+              const double2 tt = cmul(tl[q * Nh + j], Tv[u]);
+              P[q] = cmul(P[q], make_double2(1.0 - sg[q] * tt.x, -sg[q] * tt.y));
+            }
+          }
+        }
+        // keep |P| near 1: exact power-of-two rescaling
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+          int e;
+          frexp(fmax(fabs(P[q].x), fabs(P[q].y)), &e);
+          P[q].x = ldexp(P[q].x, -e);
+          P[q].y = ldexp(P[q].y, -e);
+          e2[q] += e;
+        }
+      }
+      const double2 al = alpha[m], lcm = LC[m];
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        if (!active[q]) continue;
+        double2 lr = cadd(cscale(al, -2.0 * sg[q]), lcm);
+        const double2 lp = clog(P[q]);
+        lr.x += lp.x + (double)e2[q] * 0.69314718055994530942;
+        lr.y += lp.y;
+        acc[q] = cadd(acc[q], cscale(cexp(lr), mel));
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    const double2 v = wave_sum(acc[q]);
+    if (lane == 0 && b0 + q < B) eloc[b0 + q] = make_double2(v.x + diag[q], v.y);
+  }
+}
+
+// Fused enumeration + evaluation + reduction of E_loc, one wave per sample, for
+// move sets that depend on the sample (exchanges of anti-aligned bonds).
+// LDS: t_j (Nh complex) and the compacted move list (<= n_moves ints).
+__global__ __launch_bounds__(64) void k_eloc_compact(const double2* __restrict__ theta, const uint64_t* __restrict__ s,
                                              int64_t B, int N, int W, int Nh, int ham_kind, double J, double h,
                                              const int2* __restrict__ bonds, int n_bonds,
                                              const double2* __restrict__ T, const double2* __restrict__ LC,
@@ -179,10 +294,17 @@ __global__ __launch_bounds__(64) void k_eloc(const double2* __restrict__ theta, 
       const double2* Tm = T + m;
       for (int j0 = 0; j0 < Nh; j0 += 32) {
         const int j1 = min(Nh, j0 + 32);
-        for (int j = j0; j < j1; ++j) {
-          const double2 tt = cmul(t[j], Tm[(int64_t)j * n_moves]);
-          const double2 f = make_double2(1.0 - sg * tt.x, -sg * tt.y);
-          P = cmul(P, f);
+        for (int jb = j0; jb < j1; jb += 8) {
+          double2 Tv[8];  // eight table loads in flight before their products
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            Tv[u] = jb + u < j1 ? Tm[(int64_t)(jb + u) * n_moves] : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (jb + u >= j1) break;
+            const double2 tt = cmul(t[jb + u], Tv[u]);
+            P = cmul(P, make_double2(1.0 - sg * tt.x, -sg * tt.y));
+          }
         }
         // keep |P| near 1: exact power-of-two rescaling
         int e;
@@ -354,14 +476,31 @@ void rbm_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, do
   const int64_t chunk = std::min<int64_t>(B, kChunk);
   ws_reserve(ctx, ws_round(sizeof(double2) * chunk * m->Nh));
   double2* theta = (double2*)ws_take(ctx, sizeof(double2) * chunk * m->Nh);
-  const size_t lds = sizeof(double2) * m->Nh + sizeof(int) * std::max(1, tb.n_moves);
-  VMC_REQUIRE(lds <= 64 * 1024, "model too large for the local-energy kernel's LDS budget");
+  // flips: 4 samples per wavefront share the table reads; exchanges: one
+  // sample per wavefront over its compacted list of anti-aligned bonds
+  const int S = m->Nh <= 1024 ? 4 : 2;
+  const size_t lds = sizeof(double2) * (size_t)S * m->Nh;
+  const size_t lds1 = sizeof(double2) * m->Nh + sizeof(int) * std::max(1, tb.n_moves);
+  VMC_REQUIRE(lds1 <= 64 * 1024, "model too large for the local-energy kernel's LDS budget");
   for (int64_t b0 = 0; b0 < B; b0 += chunk) {
     const int64_t nb = std::min(chunk, B - b0);
     rbm_theta(m, s + b0 * m->W, nb, theta);
-    k_eloc<<<(unsigned)nb, 64, lds, ctx->stream>>>(theta, s + b0 * m->W, nb, m->N, m->W, m->Nh, H->kind, H->J, H->h,
-                                                   H->bonds, H->n_bonds, tb.T, tb.LC, tb.alpha, tb.n_moves,
-                                                   eloc + b0);
+    if (move_kind == 1) {
+      k_eloc_compact<<<(unsigned)nb, 64, lds1, ctx->stream>>>(theta, s + b0 * m->W, nb, m->N, m->W, m->Nh, H->kind,
+                                                              H->J, H->h, H->bonds, H->n_bonds, tb.T, tb.LC, tb.alpha,
+                                                              tb.n_moves, eloc + b0);
+      VMC_HIP(hipGetLastError());
+      continue;
+    }
+    const unsigned grid = (unsigned)((nb + S - 1) / S);
+#define ELOC_LAUNCH(SS)                                                                                             \
+  k_eloc<SS><<<grid, 64, lds, ctx->stream>>>(theta, s + b0 * m->W, nb, m->N, m->W, m->Nh, H->kind, H->J, H->h,     \
+                                             H->bonds, H->n_bonds, tb.T, tb.LC, tb.alpha, tb.n_moves, eloc + b0)
+    if (S == 4)
+      ELOC_LAUNCH(4);
+    else
+      ELOC_LAUNCH(2);
+#undef ELOC_LAUNCH
     VMC_HIP(hipGetLastError());
   }
 }
