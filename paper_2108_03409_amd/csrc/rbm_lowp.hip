@@ -206,9 +206,16 @@ __global__ __launch_bounds__(64) void k_eloc_lowp(const float2* __restrict__ the
       int e2 = 0;
       for (int j0 = 0; j0 < Nh; j0 += 16) {
         const int j1 = min(Nh, j0 + 16);
-        for (int j = j0; j < j1; ++j) {
-          const float2 tt = fcmul(t[j], T[(int64_t)j * n_moves + m]);
-          P = fcmul(P, make_float2(1.f - sg * tt.x, -sg * tt.y));
+        for (int jb = j0; jb < j1; jb += 8) {
+          float2 Tv[8];  // eight table loads in flight before their products
+#pragma unroll
+          for (int u = 0; u < 8; ++u) Tv[u] = jb + u < j1 ? T[(int64_t)(jb + u) * n_moves + m] : make_float2(0.f, 0.f);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (jb + u >= j1) break;
+            const float2 tt = fcmul(t[jb + u], Tv[u]);
+            P = fcmul(P, make_float2(1.f - sg * tt.x, -sg * tt.y));
+          }
         }
         int e;
         frexpf(fmaxf(fabsf(P.x), fabsf(P.y)), &e);
