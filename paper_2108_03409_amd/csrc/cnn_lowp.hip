@@ -429,8 +429,8 @@ struct mh_geom {
   int o_z1, o_a1i, o_z2, o_t2, o_w2, o_da, o_cd, o_sd, o_red, o_cb, lds;
 };
 
-constexpr int MH_NT = 256;
-constexpr int MH_MAXOUT = 8;  // window outputs per thread: C (2k-1)^2 <= 2048
+constexpr int MH_NT = 512;
+constexpr int MH_MAXOUT = 4;  // window outputs per thread: C (2k-1)^2 <= 2048
 
 __device__ __forceinline__ int mpos(const mh_geom& g, int p, int dy, int dx) {
   int y = p / g.Lx + dy, x = p % g.Lx + dx;

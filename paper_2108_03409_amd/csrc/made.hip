@@ -110,13 +110,28 @@ __global__ void k_mask_grad(double* __restrict__ g, int N, int H) {
   }
 }
 
+// column sums: a group takes 16 columns; its 16 row lanes sum every 16th row
+// (eight independent partial sums each), then the lanes combine in a fixed order
 __global__ __launch_bounds__(256) void k_colsum(const double* __restrict__ M, int64_t rows, int cols,
                                                 double* __restrict__ out) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= cols) return;
-  double acc = 0.0;
-  for (int64_t r = 0; r < rows; ++r) acc += M[r * cols + c];
-  out[c] = acc;
+  __shared__ double part[16][17];
+  const int cl = threadIdx.x & 15, rl = threadIdx.x >> 4;
+  const int c = blockIdx.x * 16 + cl;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (c < cols) {
+    int64_t r = rl;
+    for (; r + 7 * 16 < rows; r += 8 * 16)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += M[(r + 16 * u) * cols + c];
+    for (; r < rows; r += 16) acc[0] += M[r * cols + c];
+  }
+  part[rl][cl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (rl == 0 && c < cols) {
+    double s = 0.0;
+    for (int q = 0; q < 16; ++q) s += part[q][cl];
+    out[c] = s;
+  }
 }
 
 __global__ void k_adam(double* __restrict__ p, const double* __restrict__ g, double* __restrict__ m,
@@ -247,8 +262,8 @@ void backward(vmc_made* md, int64_t nb, const made_ws& w, double* nll_slot, doub
   k_relu_mask<<<grid_for(nb * H, 256), 256, 0, ctx->stream>>>(w.dH, w.A1, nb * H);
   dgemm(ctx, dgemm_args{w.dH, 1, H, w.X, N, 1, gW1, N, H, N, nb, 0.0});
   k_mask_grad<<<grid_for((int64_t)N * H, 256), 256, 0, ctx->stream>>>(w.grad, N, H);
-  k_colsum<<<grid_for(H, 256), 256, 0, ctx->stream>>>(w.dH, nb, H, gb1);
-  k_colsum<<<grid_for(N, 256), 256, 0, ctx->stream>>>(w.G, nb, N, gb2);
+  k_colsum<<<grid_for(H, 16), 256, 0, ctx->stream>>>(w.dH, nb, H, gb1);
+  k_colsum<<<grid_for(N, 16), 256, 0, ctx->stream>>>(w.G, nb, N, gb2);
   VMC_HIP(hipGetLastError());
 }
 
