@@ -55,6 +55,23 @@ __device__ __forceinline__ double2 z1_at(const cnn_geom& g, const uint64_t* s, i
 }
 
 // layer 1 into a1[c][p] (LDS), layer 2 value at (c, p) from LDS a1
+// sum_ci W2[c][ci][tap] DA[ci][w] for one (c, tap, w): w2 points at W2[c][0][tap],
+// da at DA[0][w]; both advance by k*k per input channel.  Four independent
+// partial sums keep several loads in flight.
+__device__ __forceinline__ double2 window_tap(const double2* __restrict__ w2, const double2* __restrict__ da, int C,
+                                              int kk) {
+  double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0, s3 = s0;
+  int ci = 0;
+  for (; ci + 4 <= C; ci += 4) {
+    s0 = cadd(s0, cmul(w2[ci * kk], da[ci * kk]));
+    s1 = cadd(s1, cmul(w2[(ci + 1) * kk], da[(ci + 1) * kk]));
+    s2 = cadd(s2, cmul(w2[(ci + 2) * kk], da[(ci + 2) * kk]));
+    s3 = cadd(s3, cmul(w2[(ci + 3) * kk], da[(ci + 3) * kk]));
+  }
+  for (; ci < C; ++ci) s0 = cadd(s0, cmul(w2[ci * kk], da[ci * kk]));
+  return cadd(cadd(s0, s1), cadd(s2, s3));
+}
+
 __device__ __forceinline__ double2 z2_at(const cnn_geom& g, const double2* a1, int c, int p) {
   double2 z = g.b2[c];
   const int kk = g.k * g.k;
@@ -218,8 +235,7 @@ __global__ __launch_bounds__(256) void k_cnn_eloc(cnn_geom g, const uint64_t* __
           for (int dy1 = max(0, ey - g.k + 1); dy1 <= min(g.k - 1, ey); ++dy1)
             for (int dx1 = max(0, ex - g.k + 1); dx1 <= min(g.k - 1, ex); ++dx1) {
               const int dy2 = ey - dy1, dx2 = ex - dx1;  // tap from q to the changed position
-              for (int ci = 0; ci < g.C; ++ci)
-                dz = cadd(dz, cmul(g.W2[((c * g.C + ci) * g.k + dy2) * g.k + dx2], DA[ci * kk + dy1 * g.k + dx1]));
+              dz = cadd(dz, window_tap(g.W2 + (c * g.C * g.k + dy2) * g.k + dx2, DA + dy1 * g.k + dx1, g.C, kk));
             }
           int qy = Ys - ey, qx = Xs - ex;
           if (qy < 0) qy += g.Ly;
@@ -332,9 +348,7 @@ __global__ __launch_bounds__(256) void k_cnn_metropolis(cnn_geom g, int n_chains
       double2 dz = make_double2(0.0, 0.0);
       for (int dy1 = max(0, ey - g.k + 1); dy1 <= min(g.k - 1, ey); ++dy1)
         for (int dx1 = max(0, ex - g.k + 1); dx1 <= min(g.k - 1, ex); ++dx1)
-          for (int ci = 0; ci < g.C; ++ci)
-            dz = cadd(dz, cmul(g.W2[((ch * g.C + ci) * g.k + ey - dy1) * g.k + ex - dx1],
-                               DA[ci * kk + dy1 * g.k + dx1]));
+          dz = cadd(dz, window_tap(g.W2 + (ch * g.C * g.k + ey - dy1) * g.k + ex - dx1, DA + dy1 * g.k + dx1, g.C, kk));
       dzs[q] = dz;
       int qy = Ys - ey, qx = Xs - ex;
       if (qy < 0) qy += g.Ly;
