@@ -68,6 +68,9 @@ def parse():
                     help="network evaluation precision of log psi / local energies")
     ap.add_argument("--peaks", action="store_true",
                     help="measure HBM copy bandwidth and MFMA rates (f64, f32, bf16) instead of a workload")
+    ap.add_argument("--solver", choices=["cholesky", "cg"], default="cholesky",
+                    help="SR solve: dense Cholesky of S (default) or matrix-free conjugate gradient")
+    ap.add_argument("--cg-tol", type=float, default=1e-8, help="conjugate gradient: relative residual target")
     ap.add_argument("--gram", type=int, choices=[0, 1], default=0,
                     help="S Gram kernel: 0 float32 matrix cores, 1 split float16 (hi + lo) matrix cores")
     return ap.parse_args()
@@ -368,7 +371,10 @@ def main():
         s, _, acc = sampler.sample(ns)
         model.grad_log_psi(s, out=O)
         model.local_energy(H, s, out=el)
-        x, info = V.sr_solve(ctx, O, el, nu_rel=cfg["nu_rel"], gram=args.gram)
+        if args.solver == "cg":
+            x, info = V.sr_solve_cg(ctx, O, el, nu_rel=cfg["nu_rel"], tol=args.cg_tol, max_iter=5000)
+        else:
+            x, info = V.sr_solve(ctx, O, el, nu_rel=cfg["nu_rel"], gram=args.gram)
         theta = theta + args.tau * x
         model.set_params(theta)
         return info, acc
@@ -385,23 +391,33 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     phases = {}
-    for ph in ["sample", "log_psi", "grad", "eloc", "sr.center", "sr.herk", "sr.chol", "sr.trsv", "sr.resid"]:
+    for ph in ["sample", "log_psi", "grad", "eloc", "sr.center", "sr.herk", "sr.chol", "sr.trsv", "sr.cg", "sr.resid"]:
         ms, n = ctx.get_timing(ph)
         phases[ph] = round(ms / max(n, 1), 3)
     ctx.set_timing(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
 
-    # dominant kernel: the Gram (S) kernel, one launch per step
-    herk_ms = phases["sr.herk"]
-    herk_achieved = herk_flops(ns, K) / (herk_ms * 1e-3) / 1e12
-    hpeak = PEAK["fp32_mfma_TF"] if args.gram == 0 else PEAK["fp16_mfma_TF"]
-    hname = "k_herk_mfma_f32" if args.gram == 0 else "k_herk16 (3 float16 products per term)"
-    roofline = {"kernel": f"{hname} (S = Obar^H Obar)", "bound": "mfma", "achieved": round(herk_achieved, 3),
-                "peak": hpeak, "unit": "TFLOP/s", "frac": round(herk_achieved / hpeak, 4),
-                "traffic": herk_traffic() if args.gram == 0 else None,
-                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled)",
-                "algorithmic_bytes": 8.0 * ns * K + 16.0 * K * K,
-                "work": f"4*Ns*K*(K+1) = {herk_flops(ns, K):.4e} flop per launch (Ns={ns}, K={K})"}
+    if args.solver == "cg":
+        # dominant kernels: the two passes over O per CG product (HBM-bound)
+        iters = infos[-1][0]["iterations"] + 1  # + the true-residual product
+        cg_ms = phases["sr.cg"] + phases["sr.resid"]
+        gbs = iters * 2 * 8.0 * ns * K / (cg_ms * 1e-3) / 1e9
+        roofline = {"kernel": "k_ov + k_ohu (S v = Obar^H (Obar v), two passes over complex64 O)", "bound": "hbm",
+                    "achieved": round(gbs, 1), "peak": PEAK["hbm_GBs"], "unit": "GB/s",
+                    "frac": round(gbs / PEAK["hbm_GBs"], 4), "traffic": None,
+                    "work": f"2 x 8 Ns K = {16.0 * ns * K:.4e} bytes per product, {iters} products"}
+    else:
+        # dominant kernel: the Gram (S) kernel, one launch per step
+        herk_ms = phases["sr.herk"]
+        herk_achieved = herk_flops(ns, K) / (herk_ms * 1e-3) / 1e12
+        hpeak = PEAK["fp32_mfma_TF"] if args.gram == 0 else PEAK["fp16_mfma_TF"]
+        hname = "k_herk_mfma_f32" if args.gram == 0 else "k_herk16 (3 float16 products per term)"
+        roofline = {"kernel": f"{hname} (S = Obar^H Obar)", "bound": "mfma", "achieved": round(herk_achieved, 3),
+                    "peak": hpeak, "unit": "TFLOP/s", "frac": round(herk_achieved / hpeak, 4),
+                    "traffic": herk_traffic() if args.gram == 0 else None,
+                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled)",
+                    "algorithmic_bytes": 8.0 * ns * K + 16.0 * K * K,
+                    "work": f"4*Ns*K*(K+1) = {herk_flops(ns, K):.4e} flop per launch (Ns={ns}, K={K})"}
     chol_ms = phases["sr.chol"]
     eloc_ms = phases["eloc"]
     eloc_per_s = ns / (eloc_ms * 1e-3)
@@ -416,7 +432,8 @@ def main():
         "data": "synthetic (seeded RBM parameters N(0,0.01), Metropolis samples)",
         "config": {"workload": "SR step: TFIM chain L=64 PBC J=h=1, complex RBM alpha=4 (K=16704), "
                                "16384 samples (1024 chains x 16 sweeps), nu_rel=1e-3",
-                   "global_batch": ns, "K": K, "parallelism": "single GPU", "gram": args.gram, "prec": args.prec},
+                   "global_batch": ns, "K": K, "parallelism": "single GPU", "gram": args.gram, "prec": args.prec,
+                   "solver": args.solver},
         "phases_ms": phases,
         "local_energies_per_s": round(eloc_per_s, 1),
         "eloc_roofline": {"bound": "alu", "achieved_TF": round(ns * eloc_flops(N, Nh, N) / (eloc_ms * 1e-3) / 1e12, 3),
@@ -424,6 +441,7 @@ def main():
         "chol_TF": round(chol_flops(K) / (chol_ms * 1e-3) / 1e12, 3) if chol_ms > 0 else None,
         "roofline": roofline,
         "energy": infos[-1][0]["e_mean"].real, "residual": infos[-1][0]["residual"],
+        "cg_iterations": infos[-1][0].get("iterations"),
         "accept": round(infos[-1][1], 4),
     }
     if not args.no_cpu_baseline:

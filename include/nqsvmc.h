@@ -271,6 +271,32 @@ typedef struct {
 int vmc_sr_solve(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, const double* weights,
                  int64_t N, int64_t K, const vmc_sr_opts* opts, double* x, vmc_sr_info* info_host);
 
+/* The same shifted system solved by conjugate gradient (the paper notes, with
+ * the diagonal shift of Sec. 3.1, that the shifted equation may be solved by
+ * an iterative solver such as conjugate gradient).  S is never formed: each
+ * iteration applies S v = Obar^H (Obar v) as two passes over O itself, the
+ * centring and weights applied in float64 ((Obar v)_n = sqrt(w_n)(O_n.v -
+ * <O>.v), (Obar^H u)_k = sum_n conj(O_nk) sqrt(w_n) u_n - conj(<O_k>) sum_n
+ * sqrt(w_n) u_n, w normalised), so the operator is exactly that of the given
+ * O, plus the shift
+ * nu_rel diag(S) + eps_abs; Jacobi preconditioner M = (1 + nu_rel) diag(S) +
+ * eps_abs.  Stops when the recursive residual ||r|| / ||b|| <= tol (checked
+ * every 8 iterations) or after max_iter iterations; info->residual is then
+ * the true residual ||b - S~ x|| / ||b||, recomputed with one more product
+ * (check it against tol: reaching max_iter is not an error).  info->min_pivot
+ * is NaN and fail_index -1; opts->gram is ignored.  Workspace O((N + K) *
+ * (1 + N / 256)) values: no K x K matrix and no copy of O, so K is not limited
+ * to 65536.
+ * VMC_ERR_UNSUPPORTED for VMC_SR_IMAG.  iterations_host (may be NULL)
+ * receives the number of iterations.  The call synchronises.                 */
+typedef struct {
+  double tol;    /* relative residual target, > 0 */
+  int max_iter;  /* >= 1 */
+} vmc_cg_opts;
+int vmc_sr_solve_cg(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, const double* weights,
+                    int64_t N, int64_t K, const vmc_sr_opts* opts, const vmc_cg_opts* cg, double* x,
+                    vmc_sr_info* info_host, int* iterations_host);
+
 /* ---- learned proposal: masked autoregressive network (MADE) ------------- */
 /* q(s) = prod_d p_d^{s_d} (1-p_d)^{1-s_d},  p = sigmoid(W2m relu(W1m sigma' + b1) + b2)
  * with MADE masks (Germain et al. 2015; hidden degree m(k) = k mod (N-1) + 1,

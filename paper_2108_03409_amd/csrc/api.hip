@@ -736,3 +736,34 @@ extern "C" int vmc_sr_solve(vmc_ctx* ctx, const void* O, int O_dtype, const doub
   if (info_host) *info_host = info;
   return rc;
 }
+
+extern "C" int vmc_sr_solve_cg(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, const double* weights,
+                               int64_t N, int64_t K, const vmc_sr_opts* opts, const vmc_cg_opts* cg, double* x,
+                               vmc_sr_info* info_host, int* iterations_host) {
+  vmc_sr_info info{};
+  info.fail_index = -1;
+  info.residual = NAN;
+  info.min_pivot = NAN;
+  int iters = 0;
+  int rc = guard(ctx, [&] {
+    VMC_REQUIRE(ctx && opts && cg, "NULL argument");
+    VMC_REQUIRE(O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_C128, "O dtype must be C64 or C128");
+    VMC_REQUIRE(N >= 1 && K >= 1, "N and K must be positive");
+    VMC_REQUIRE(O && eloc && x, "NULL buffer");
+    VMC_REQUIRE(std::isfinite(opts->nu_rel) && opts->nu_rel >= 0 && std::isfinite(opts->eps_abs) &&
+                    opts->eps_abs >= 0,
+                "shifts must be finite and non-negative");
+    VMC_REQUIRE(opts->mode == VMC_SR_COMPLEX || opts->mode == VMC_SR_REAL || opts->mode == VMC_SR_IMAG,
+                "unknown mode");
+    if (opts->mode == VMC_SR_IMAG)
+      throw vmc_error{VMC_ERR_UNSUPPORTED, "Im S is antisymmetric; conjugate gradient needs COMPLEX or REAL"};
+    VMC_REQUIRE(std::isfinite(cg->tol) && cg->tol > 0 && cg->max_iter >= 1, "tol > 0 and max_iter >= 1 required");
+    set_device(ctx);
+    sr_solve_cg_impl(ctx, O, O_dtype, (const double2*)eloc, weights, N, K, opts, cg->tol, cg->max_iter, (double2*)x,
+                     &info, &iters);
+    if (!std::isfinite(info.residual)) throw vmc_error{VMC_ERR_NONFINITE, "solution is not finite"};
+  });
+  if (info_host) *info_host = info;
+  if (iterations_host) *iterations_host = iters;
+  return rc;
+}

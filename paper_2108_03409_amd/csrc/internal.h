@@ -420,6 +420,9 @@ void herk_split16(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode,
 // sr.hip
 void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N,
                    int64_t K, const vmc_sr_opts* o, double2* x, vmc_sr_info* info);
+void sr_solve_cg_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N,
+                      int64_t K, const vmc_sr_opts* o, double tol, int max_iter, double2* x, vmc_sr_info* info,
+                      int* iters);
 // ham
 void ham_connected_impl(vmc_ham* H, const uint64_t* s, int64_t B, uint64_t* sp, double* mel, int32_t* cnt);
 

@@ -268,6 +268,210 @@ __global__ __launch_bounds__(1024) void k_norms(const double2* __restrict__ a, c
 
 __global__ void k_init_fail(long long* f) { *f = -1; }
 
+// ---- matrix-free conjugate gradient (diagonal shift + iterative solver) ----
+
+// The centred, weight-scaled samples are applied without forming them:
+//   (Obar v)_n   = sq_n (sum_k O_nk v_k - <O>.v),        sq_n = sqrt(w_n / sum w)
+//   (Obar^H u)_k = sum_n conj(O_nk) sq_n u_n - conj(<O_k>) sum_n sq_n u_n
+// so the operator is exactly that of the given O (float64 arithmetic).
+
+__global__ void k_sqw(const double* __restrict__ w, int64_t N, const double* __restrict__ stats,
+                      double* __restrict__ sq) {
+  const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (n < N) sq[n] = sqrt((w ? w[n] : 1.0) / stats[0]);
+}
+
+// per column chunk: Fpart = sum sq^2 conj(O - <O>) (E - <E>), Dpart = (sum sq^2 |O - <O>|^2, 0)
+template <typename InT>
+__global__ __launch_bounds__(256) void k_force_diag(const InT* __restrict__ O, const double* __restrict__ sq,
+                                                    const double2* __restrict__ e, int64_t N, int64_t K,
+                                                    const double2* __restrict__ mean, const double* __restrict__ stats,
+                                                    double2* __restrict__ Fpart, double2* __restrict__ Dpart) {
+  const int64_t k = blockIdx.x * 256ll + threadIdx.x;
+  if (k >= K) return;
+  const int64_t n0 = (int64_t)blockIdx.y * kColChunk, n1 = min(N, n0 + kColChunk);
+  const double2 eb = make_double2(stats[1], stats[2]);
+  const double2 mk = mean[k];
+  double2 f = make_double2(0.0, 0.0);
+  double dd = 0.0;
+  for (int64_t n = n0; n < n1; ++n) {
+    const double wn = sq[n] * sq[n];
+    const double2 d = csub(load_c(O, n * K + k), mk);
+    const double2 p = cmul(cconj(d), csub(e[n], eb));
+    f.x += wn * p.x;
+    f.y += wn * p.y;
+    dd += wn * (d.x * d.x + d.y * d.y);
+  }
+  Fpart[(int64_t)blockIdx.y * K + k] = f;
+  Dpart[(int64_t)blockIdx.y * K + k] = make_double2(dd, 0.0);
+}
+
+// u_n = sq_n (sum_k O_nk v_k - mv[0]), one group per row
+template <typename InT>
+__global__ __launch_bounds__(256) void k_ov(const InT* __restrict__ O, int64_t N, int64_t K,
+                                            const double2* __restrict__ v, const double* __restrict__ mv,
+                                            const double* __restrict__ sq, double2* __restrict__ u) {
+  __shared__ double2 red[4];
+  const int64_t n = blockIdx.x;
+  if (n >= N) return;
+  const InT* row = O + n * K;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t k = threadIdx.x; k < K; k += 256) acc = cadd(acc, cmul(load_c(row, k), v[k]));
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double2 s = cadd(cadd(red[0], red[1]), cadd(red[2], red[3]));
+    u[n] = cscale(make_double2(s.x - mv[0], s.y - mv[1]), sq[n]);
+  }
+}
+
+// partial[chunk][k] = sum_{n in chunk} conj(O_nk) sq_n u_n
+template <typename InT>
+__global__ __launch_bounds__(256) void k_ohu(const InT* __restrict__ O, int64_t N, int64_t K,
+                                             const double2* __restrict__ u, const double* __restrict__ sq,
+                                             double2* __restrict__ partial) {
+  const int64_t k = blockIdx.x * 256ll + threadIdx.x;
+  if (k >= K) return;
+  const int64_t n0 = (int64_t)blockIdx.y * kColChunk, n1 = min(N, n0 + kColChunk);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t n = n0; n < n1; ++n) acc = cadd(acc, cscale(cmul(cconj(load_c(O, n * K + k)), u[n]), sq[n]));
+  partial[(int64_t)blockIdx.y * K + k] = acc;
+}
+
+// out[0..1] = sum_n sq_n u_n
+__global__ __launch_bounds__(1024) void k_wsum(const double* __restrict__ sq, const double2* __restrict__ u, int64_t N,
+                                               double* __restrict__ out) {
+  __shared__ double red[2][16];
+  double sr = 0, si = 0;
+  for (int64_t n = threadIdx.x; n < N; n += 1024) {
+    sr += sq[n] * u[n].x;
+    si += sq[n] * u[n].y;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = sr;
+    red[1][threadIdx.x >> 6] = si;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, b = 0;
+    for (int q = 0; q < 16; ++q) {
+      a += red[0][q];
+      b += red[1][q];
+    }
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+// Ap_k = [[sum_chunks partial - conj(<O_k>) su]] + (nu dS_k + eps) p_k
+__global__ void k_cg_apply(const double2* __restrict__ partial, int nchunk, int64_t K, const double2* __restrict__ p,
+                           const double2* __restrict__ mean, const double* __restrict__ su,
+                           const double* __restrict__ dS, double nu, double eps, int mode, double2* __restrict__ Ap) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int c = 0; c < nchunk; ++c) acc = cadd(acc, partial[(int64_t)c * K + k]);
+  acc = csub(acc, cmul(cconj(mean[k]), make_double2(su[0], su[1])));
+  if (mode == VMC_SR_REAL) acc.y = 0.0;
+  const double sh = nu * dS[k] + eps;
+  Ap[k] = make_double2(acc.x + sh * p[k].x, acc.y + sh * p[k].y);
+}
+
+__global__ void k_conj(const double2* __restrict__ a, int64_t K, double2* __restrict__ out) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < K) out[k] = cconj(a[k]);
+}
+
+// out[0..1] = sum conj(a_k) b_k; with c != NULL also out[2..3] = sum conj(c_k) c_k
+__global__ __launch_bounds__(1024) void k_cg_dot(const double2* __restrict__ a, const double2* __restrict__ b,
+                                                 const double2* __restrict__ c, int64_t K, double* __restrict__ out) {
+  __shared__ double red[3][16];
+  double sr = 0, si = 0, sc = 0;
+  for (int64_t k = threadIdx.x; k < K; k += 1024) {
+    const double2 p = cmul(cconj(a[k]), b[k]);
+    sr += p.x;
+    si += p.y;
+    if (c) sc += c[k].x * c[k].x + c[k].y * c[k].y;
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  sc = wave_sum(sc);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = sr;
+    red[1][w] = si;
+    red[2][w] = sc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (int q = 0; q < 16; ++q) {
+      a0 += red[0][q];
+      a1 += red[1][q];
+      a2 += red[2][q];
+    }
+    out[0] = a0;
+    out[1] = a1;
+    if (c) out[2] = a2;
+  }
+}
+
+// scalars: sc[0..1] = r^H z, sc[2..3] = p^H A p, sc[4..5] = new r^H z, sc[6] = r^H r
+__global__ void k_cg_step1(double2* __restrict__ x, double2* __restrict__ r, double2* __restrict__ z,
+                           const double2* __restrict__ p, const double2* __restrict__ Ap,
+                           const double* __restrict__ M, const double* __restrict__ sc, int64_t K) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double2 al = cdiv(make_double2(sc[0], sc[1]), make_double2(sc[2], sc[3]));
+  x[k] = cadd(x[k], cmul(al, p[k]));
+  const double2 rn = csub(r[k], cmul(al, Ap[k]));
+  r[k] = rn;
+  z[k] = cscale(rn, 1.0 / M[k]);
+}
+
+__global__ void k_cg_step2(double2* __restrict__ p, const double2* __restrict__ z, const double* __restrict__ sc,
+                           int64_t K) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const double2 be = cdiv(make_double2(sc[4], sc[5]), make_double2(sc[0], sc[1]));
+  p[k] = cadd(z[k], cmul(be, p[k]));
+}
+
+__global__ void k_cg_rotate(double* __restrict__ sc) {
+  sc[0] = sc[4];
+  sc[1] = sc[5];
+}
+
+// M_k = (1 + nu) dS_k + eps (1 where that vanishes); z = b / M; p = z; x = 0; r = b
+__global__ void k_cg_init(const double2* __restrict__ b, const double* __restrict__ dS, double nu, double eps,
+                          int64_t K, double* __restrict__ M, double2* __restrict__ x, double2* __restrict__ r,
+                          double2* __restrict__ z, double2* __restrict__ p) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double m = (1.0 + nu) * dS[k] + eps;
+  if (!(m > 0.0)) m = 1.0;
+  M[k] = m;
+  x[k] = make_double2(0.0, 0.0);
+  r[k] = b[k];
+  z[k] = cscale(b[k], 1.0 / m);
+  p[k] = z[k];
+}
+
+__global__ void k_cg_resid(const double2* __restrict__ b, const double2* __restrict__ Ax, int64_t K,
+                           double2* __restrict__ res) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < K) res[k] = csub(b[k], Ax[k]);
+}
+
+__global__ void k_take_real(const double2* __restrict__ a, int64_t K, double* __restrict__ out) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < K) out[k] = a[k].x;
+}
+
+
 }  // namespace
 
 void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N, int64_t K,
@@ -381,4 +585,121 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   VMC_HIP(hipMemcpyAsync(hn, norms, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
   VMC_HIP(hipStreamSynchronize(st));
   info->residual = hn[1] > 0 ? std::sqrt(hn[0] / hn[1]) : std::sqrt(hn[0]);
+}
+
+// Shifted SR solve by Jacobi-preconditioned conjugate gradient, with
+// S v = Obar^H (Obar v) applied from the samples (S is never formed).
+void sr_solve_cg_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N,
+                      int64_t K, const vmc_sr_opts* o, double tol, int max_iter, double2* x, vmc_sr_info* info,
+                      int* iters) {
+  hipStream_t st = ctx->stream;
+  const int nchunk = (int)((N + kColChunk - 1) / kColChunk);
+  const bool f32 = dtype == VMC_DT_C64;
+  const size_t vk = ws_round(sizeof(double2) * K);
+  const size_t pk = ws_round(sizeof(double2) * (size_t)nchunk * K);
+  size_t total = ws_round(64) + 2 * pk + vk * 11 + ws_round(sizeof(double) * K) * 2 + ws_round(sizeof(double2) * N) +
+                 ws_round(sizeof(double) * N) + ws_round(sizeof(double) * 16);
+  ws_reserve(ctx, total);
+  double* stats = (double*)ws_take(ctx, 64);
+  double2* partial = (double2*)ws_take(ctx, sizeof(double2) * (size_t)nchunk * K);
+  double2* partial2 = (double2*)ws_take(ctx, sizeof(double2) * (size_t)nchunk * K);
+  double2* mean = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* cmean = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* F = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* b = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* xs = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* r = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* z = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* pv = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* Ap = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* dSc = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* spare = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double* dS = (double*)ws_take(ctx, sizeof(double) * K);
+  double* M = (double*)ws_take(ctx, sizeof(double) * K);
+  double2* u = (double2*)ws_take(ctx, sizeof(double2) * N);
+  double* sq = (double*)ws_take(ctx, sizeof(double) * N);
+  double* sc = (double*)ws_take(ctx, sizeof(double) * 16);  // [0..6] CG scalars, [8..9] <O>.v, [10..11] sum sq u
+  (void)spare;
+
+  std::unique_ptr<phase_scope> ph(new phase_scope(ctx, "sr.center"));
+  k_energy_stats<<<1, 1024, 0, st>>>(eloc, w, N, stats);
+  dim3 cg(grid_for(K, 256), nchunk);
+  if (f32)
+    k_col_partial<float2><<<cg, 256, 0, st>>>((const float2*)O, w, N, K, partial);
+  else
+    k_col_partial<double2><<<cg, 256, 0, st>>>((const double2*)O, w, N, K, partial);
+  k_reduce_partial<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, stats, mean);
+  k_conj<<<grid_for(K, 256), 256, 0, st>>>(mean, K, cmean);
+  k_sqw<<<grid_for(N, 256), 256, 0, st>>>(w, N, stats, sq);
+  if (f32)
+    k_force_diag<float2><<<cg, 256, 0, st>>>((const float2*)O, sq, eloc, N, K, mean, stats, partial, partial2);
+  else
+    k_force_diag<double2><<<cg, 256, 0, st>>>((const double2*)O, sq, eloc, N, K, mean, stats, partial, partial2);
+  k_reduce_plain<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, F);
+  k_reduce_plain<<<grid_for(K, 256), 256, 0, st>>>(partial2, nchunk, K, dSc);
+  k_take_real<<<grid_for(K, 256), 256, 0, st>>>(dSc, K, dS);
+  k_rhs<<<grid_for(K, 256), 256, 0, st>>>(F, K, o->gamma_re, o->gamma_im, o->mode, b);
+  VMC_HIP(hipGetLastError());
+  ph.reset();
+
+  auto matvec = [&](const double2* v, double2* out) {
+    k_cg_dot<<<1, 1024, 0, st>>>(cmean, v, nullptr, K, sc + 8);  // <O>.v
+    if (f32) {
+      k_ov<float2><<<(unsigned)N, 256, 0, st>>>((const float2*)O, N, K, v, sc + 8, sq, u);
+      k_ohu<float2><<<cg, 256, 0, st>>>((const float2*)O, N, K, u, sq, partial);
+    } else {
+      k_ov<double2><<<(unsigned)N, 256, 0, st>>>((const double2*)O, N, K, v, sc + 8, sq, u);
+      k_ohu<double2><<<cg, 256, 0, st>>>((const double2*)O, N, K, u, sq, partial);
+    }
+    k_wsum<<<1, 1024, 0, st>>>(sq, u, N, sc + 10);
+    k_cg_apply<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, v, mean, sc + 10, dS, o->nu_rel, o->eps_abs,
+                                                 o->mode, out);
+  };
+
+  ph.reset(new phase_scope(ctx, "sr.cg"));
+  const unsigned gk = grid_for(K, 256);
+  k_cg_init<<<gk, 256, 0, st>>>(b, dS, o->nu_rel, o->eps_abs, K, M, xs, r, z, pv);
+  k_cg_dot<<<1, 1024, 0, st>>>(r, z, b, K, sc);  // sc[0..1] = r^H z, sc[2] = b^H b
+  double* hsc = (double*)pinned_host(ctx, sizeof(double) * 16);
+  VMC_HIP(hipMemcpyAsync(hsc, sc, sizeof(double) * 8, hipMemcpyDeviceToHost, st));
+  VMC_HIP(hipStreamSynchronize(st));
+  const double bb = hsc[2];
+  int it = 0;
+  if (bb > 0.0) {
+    for (it = 0; it < max_iter;) {
+      matvec(pv, Ap);
+      k_cg_dot<<<1, 1024, 0, st>>>(pv, Ap, nullptr, K, sc + 2);
+      k_cg_step1<<<gk, 256, 0, st>>>(xs, r, z, pv, Ap, M, sc, K);
+      k_cg_dot<<<1, 1024, 0, st>>>(r, z, r, K, sc + 4);  // sc[4..5] = r^H z, sc[6] = r^H r
+      k_cg_step2<<<gk, 256, 0, st>>>(pv, z, sc, K);
+      k_cg_rotate<<<1, 1, 0, st>>>(sc);
+      ++it;
+      if (it % 8 == 0 || it == max_iter) {
+        VMC_HIP(hipMemcpyAsync(hsc, sc, sizeof(double) * 8, hipMemcpyDeviceToHost, st));
+        VMC_HIP(hipStreamSynchronize(st));
+        if (!std::isfinite(hsc[6]) || std::sqrt(hsc[6] / bb) <= tol) break;
+      }
+    }
+  }
+  VMC_HIP(hipGetLastError());
+  ph.reset();
+
+  // true residual ||b - A x|| / ||b||
+  ph.reset(new phase_scope(ctx, "sr.resid"));
+  matvec(xs, Ap);
+  k_cg_resid<<<gk, 256, 0, st>>>(b, Ap, K, z);
+  k_norms<<<1, 1024, 0, st>>>(z, b, K, sc);
+  VMC_HIP(hipMemcpyAsync(x, xs, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
+  VMC_HIP(hipGetLastError());
+  ph.reset();
+  VMC_HIP(hipMemcpyAsync(hsc, sc, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+  VMC_HIP(hipMemcpyAsync(hsc + 2, stats, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+  VMC_HIP(hipStreamSynchronize(st));
+  info->residual = hsc[1] > 0 ? std::sqrt(hsc[0] / hsc[1]) : std::sqrt(hsc[0]);
+  info->e_mean[0] = hsc[3];
+  info->e_mean[1] = hsc[4];
+  info->e_var = hsc[5];
+  info->fail_index = -1;
+  info->min_pivot = NAN;
+  *iters = it;
 }

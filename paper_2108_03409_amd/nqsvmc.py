@@ -45,6 +45,10 @@ class SROpts(C.Structure):
                 ("gamma_re", C.c_double), ("gamma_im", C.c_double), ("gram", C.c_int)]
 
 
+class CGOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int)]
+
+
 class SRInfo(C.Structure):
     _fields_ = [("e_mean", C.c_double * 2), ("e_var", C.c_double), ("residual", C.c_double),
                 ("min_pivot", C.c_double), ("fail_index", C.c_int64)]
@@ -87,6 +91,8 @@ _SIGS = {
     "vmc_sampler_get_stats": ([P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
     "vmc_sampler_destroy": ([P], C.c_int),
     "vmc_sr_solve": ([P, P, C.c_int, P, P, I64, I64, C.POINTER(SROpts), P, C.POINTER(SRInfo)], C.c_int),
+    "vmc_sr_solve_cg": ([P, P, C.c_int, P, P, I64, I64, C.POINTER(SROpts), C.POINTER(CGOpts), P, C.POINTER(SRInfo),
+                         C.POINTER(C.c_int)], C.c_int),
     "vmc_made_create": ([P, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_made_num_params": ([P, C.POINTER(I64)], C.c_int),
     "vmc_made_set_params": ([P, P], C.c_int),
@@ -418,6 +424,27 @@ def sr_solve(ctx: Context, O: torch.Tensor, eloc: torch.Tensor, *, weights=None,
                              C.byref(info))
     d = dict(e_mean=complex(info.e_mean[0], info.e_mean[1]), e_var=info.e_var, residual=info.residual,
              min_pivot=info.min_pivot, fail_index=info.fail_index, status=ERRORS.get(rc, "OK") if rc else "OK")
+    if rc != VMC_OK and raise_on_error:
+        _check(rc, ctx.h)
+    return (x if rc == VMC_OK else None), d
+
+
+def sr_solve_cg(ctx: Context, O: torch.Tensor, eloc: torch.Tensor, *, weights=None, nu_rel=1e-3, eps_abs=0.0,
+                mode=SR_COMPLEX, gamma=1.0, tol=1e-10, max_iter=1000, raise_on_error=True):
+    """The shifted SR system by preconditioned conjugate gradient (S never
+    formed).  Returns (x, info dict with 'iterations')."""
+    N, K = O.shape
+    dt = DT_C128 if O.dtype == torch.complex128 else DT_C64
+    x = torch.empty(K, dtype=torch.complex128, device=O.device)
+    g = complex(gamma)
+    opts = SROpts(nu_rel, eps_abs, mode, g.real, g.imag, 0)
+    cg = CGOpts(tol, max_iter)
+    info = SRInfo()
+    it = C.c_int()
+    rc = load().vmc_sr_solve_cg(ctx.h, _ptr(O), dt, _ptr(eloc), _ptr(weights), N, K, C.byref(opts), C.byref(cg),
+                                _ptr(x), C.byref(info), C.byref(it))
+    d = dict(e_mean=complex(info.e_mean[0], info.e_mean[1]), e_var=info.e_var, residual=info.residual,
+             iterations=it.value, status=ERRORS.get(rc, "OK") if rc else "OK")
     if rc != VMC_OK and raise_on_error:
         _check(rc, ctx.h)
     return (x if rc == VMC_OK else None), d

@@ -88,3 +88,44 @@ def test_not_pd_reported(ctx):
     with pytest.raises(V.VMCError) as e:
         V.sr_solve(ctx, dev_c128(O), dev_c128(el), mode=V.SR_IMAG)
     assert e.value.name == "UNSUPPORTED"
+
+
+@pytest.mark.parametrize("N,Nh,ns,mode,gamma,nu,eps,weighted,dt", [
+    (10, 10, 1024, "real", 1.0, 1e-3, 0.0, False, "c128"),
+    (8, 16, 300, "complex", 1.0, 1e-2, 0.0, False, "c128"),
+    (8, 16, 300, "complex", 1j, 1e-2, 1e-4, True, "c128"),
+    (12, 20, 77, "complex", 1.0, 1e-3, 0.0, False, "c128"),   # fewer samples than parameters
+    (20, 40, 2000, "complex", 1.0, 1e-3, 0.0, False, "c64"),
+    (40, 60, 3000, "complex", 1.0, 1e-3, 0.0, False, "c64"),  # K = 2500
+])
+def test_sr_solve_cg_matches_oracle(ctx, N, Nh, ns, mode, gamma, nu, eps, weighted, dt):
+    # conjugate gradient on the same shifted system: the solution agrees with
+    # the oracle's Cholesky solution to the residual tolerance times the condition
+    flush(f"sr cg N={N} Nh={Nh} ns={ns} mode={mode} {dt}")
+    O, el = _problem(N, Nh, ns, 0.2, seed=N * Nh + 7, cplx=(mode != "real"))
+    if dt == "c64":
+        O = O.astype(np.complex64).astype(np.complex128)
+    w = np.random.default_rng(5).uniform(0.5, 1.5, ns) if weighted else None
+    x_ref, info_ref = osr.sr_solve(O, el, nu_rel=nu, eps_abs=eps, mode=mode, gamma=gamma, weights=w)
+    Od = dev_c128(O) if dt == "c128" else torch.from_numpy(O.astype(np.complex64)).to("cuda:0")
+    tol = 1e-11
+    x, info = V.sr_solve_cg(ctx, Od, dev_c128(el), weights=None if w is None else torch.from_numpy(w).to("cuda:0"),
+                            nu_rel=nu, eps_abs=eps, mode=V.SR_REAL if mode == "real" else V.SR_COMPLEX, gamma=gamma,
+                            tol=tol, max_iter=5000)
+    x = x.cpu().numpy()
+    S, F = osr.fisher_and_force(O, el, w)
+    kappa = np.linalg.cond(osr.shifted(osr.project(S, mode), nu, eps))
+    err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+    flush(f"  iterations {info['iterations']}, residual {info['residual']:.2e}, error {err:.2e}, kappa {kappa:.1e}")
+    assert info["residual"] <= 10 * tol
+    assert err <= 10 * tol * kappa + 1e-12
+    assert abs(info["e_mean"] - info_ref["e_mean"]) < 1e-12 * max(1, abs(info_ref["e_mean"]))
+
+
+def test_sr_solve_cg_iteration_cap(ctx):
+    # max_iter reached: the call succeeds and reports the true residual
+    O, el = _problem(20, 40, 2000, 0.2, seed=99)
+    x, info = V.sr_solve_cg(ctx, dev_c128(O), dev_c128(el), nu_rel=1e-4, tol=1e-14, max_iter=3)
+    assert info["iterations"] == 3 and np.isfinite(info["residual"]) and info["residual"] > 1e-14
+    with pytest.raises(V.VMCError):
+        V.sr_solve_cg(ctx, dev_c128(O), dev_c128(el), mode=V.SR_IMAG)
