@@ -313,6 +313,17 @@ def bench_peaks(args, V, torch):
     gbs = 2 * nb * n / (ms * 1e-3) / 1e9
     out["hbm_copy"] = {"GB/s": round(gbs, 1), "nominal": PEAK["hbm_GBs"], "frac": round(gbs / PEAK["hbm_GBs"], 4),
                        "bytes_moved_per_launch": 2 * nb, "ms_per_launch": round(ms / n, 4)}
+    for _ in range(args.warmup):
+        V.calib_read(ctx, src)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    for _ in range(args.steps):
+        V.calib_read(ctx, src)
+    ms, n = ctx.get_timing("calib.read")
+    ctx.set_timing(False)
+    gbs = nb * n / (ms * 1e-3) / 1e9
+    out["hbm_read"] = {"GB/s": round(gbs, 1), "nominal": PEAK["hbm_GBs"], "frac": round(gbs / PEAK["hbm_GBs"], 4),
+                       "bytes_read_per_launch": nb, "ms_per_launch": round(ms / n, 4)}
     nominal = {"f64": PEAK["fp64_TF"], "f32": PEAK["fp32_mfma_TF"], "bf16": PEAK["bf16_mfma_TF"]}
     for kind, iters in [("f64", 2000), ("f32", 2000), ("bf16", 1000)]:
         for _ in range(args.warmup):

@@ -330,6 +330,11 @@ int vmc_made_destroy(vmc_made* md);
  * reference, and the known transfer against which hardware traffic counters
  * are scaled.  Timed as phase "calib.copy" when timing is on.               */
 int vmc_calib_copy(vmc_ctx* ctx, const void* src, void* dst, int64_t bytes);
+/* Read-only stream over `bytes` (a positive multiple of 16, 16-byte aligned):
+ * the bandwidth ceiling of read-dominated kernels.  out: device buffer of
+ * 8192 x 16 bytes receiving one xor-folded word per work-group.  Phase
+ * "calib.read".                                                              */
+int vmc_calib_read(vmc_ctx* ctx, const void* src, int64_t bytes, void* out);
 /* Matrix-core loop: n_groups work-groups of 4 waves, each wave `iters` rounds
  * of 8 independent chains of one MFMA type: kind VMC_DT_F64
  * (v_mfma_f64_16x16x4f64), VMC_DT_F32 (v_mfma_f32_16x16x4f32) or

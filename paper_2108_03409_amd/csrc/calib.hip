@@ -9,6 +9,8 @@
 
 namespace {
 
+constexpr int kCalibReadGroups = 256 * 32;
+
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -16,8 +18,60 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // 16-byte vector copy, grid-stride
 __global__ __launch_bounds__(256) void k_calib_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                                     int64_t n16) {
+  // four 16-byte loads in flight per thread per round
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+  int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+// Read-only stream: every 16-byte word is loaded once (four loads in flight per
+// thread per round) and folded with xor; one word per group is written.
+__global__ __launch_bounds__(256) void k_calib_read(const uint4* __restrict__ src, int64_t n16,
+                                                    uint4* __restrict__ out) {
+  __shared__ uint4 red[4];
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = blockIdx.x * 256ll + threadIdx.x;
+  uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    acc.x ^= a.x ^ b.x ^ c.x ^ d.x;
+    acc.y ^= a.y ^ b.y ^ c.y ^ d.y;
+    acc.z ^= a.z ^ b.z ^ c.z ^ d.z;
+    acc.w ^= a.w ^ b.w ^ c.w ^ d.w;
+  }
+  for (; i < n16; i += stride) {
+    const uint4 a = src[i];
+    acc.x ^= a.x;
+    acc.y ^= a.y;
+    acc.z ^= a.z;
+    acc.w ^= a.w;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    acc.x ^= __shfl_xor(acc.x, o, 64);
+    acc.y ^= __shfl_xor(acc.y, o, 64);
+    acc.z ^= __shfl_xor(acc.z, o, 64);
+    acc.w ^= __shfl_xor(acc.w, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint4 r = red[0];
+    for (int q = 1; q < 4; ++q) {
+      r.x ^= red[q].x;
+      r.y ^= red[q].y;
+      r.z ^= red[q].z;
+      r.w ^= red[q].w;
+    }
+    out[blockIdx.x] = r;
+  }
 }
 
 // Each wave runs `iters` rounds of 8 independent MFMA chains; the sum of the
@@ -79,8 +133,20 @@ extern "C" int vmc_calib_copy(vmc_ctx* ctx, const void* src, void* dst, int64_t 
     set_device(ctx);
     phase_scope ps(ctx, "calib.copy");
     const int64_t n16 = bytes / 16;
-    const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 256 * 64);
+    const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 256 * 32);
     k_calib_copy<<<(unsigned)blocks, 256, 0, ctx->stream>>>((const uint4*)src, (uint4*)dst, n16);
+    VMC_HIP(hipGetLastError());
+  });
+}
+
+extern "C" int vmc_calib_read(vmc_ctx* ctx, const void* src, int64_t bytes, void* out) {
+  return guard(ctx, [&] {
+    VMC_REQUIRE(ctx && src && out, "NULL argument");
+    VMC_REQUIRE(bytes > 0 && bytes % 16 == 0, "bytes must be a positive multiple of 16");
+    VMC_REQUIRE(((uintptr_t)src | (uintptr_t)out) % 16 == 0, "buffers must be 16-byte aligned");
+    set_device(ctx);
+    phase_scope ps(ctx, "calib.read");
+    k_calib_read<<<(unsigned)kCalibReadGroups, 256, 0, ctx->stream>>>((const uint4*)src, bytes / 16, (uint4*)out);
     VMC_HIP(hipGetLastError());
   });
 }

@@ -315,9 +315,19 @@ __global__ __launch_bounds__(256) void k_ov(const InT* __restrict__ O, int64_t N
   const int64_t n = blockIdx.x;
   if (n >= N) return;
   const InT* row = O + n * K;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int64_t k = threadIdx.x; k < K; k += 256) acc = cadd(acc, cmul(load_c(row, k), v[k]));
-  acc = wave_sum(acc);
+  double2 acc = make_double2(0.0, 0.0), acc2 = acc;
+  int64_t k = threadIdx.x;
+  // two independent accumulators, four loads in flight per thread
+  for (; k + 3 * 256 < K; k += 4 * 256) {
+    const double2 o0 = load_c(row, k), o1 = load_c(row, k + 256), o2 = load_c(row, k + 512),
+                  o3 = load_c(row, k + 768);
+    acc = cadd(acc, cmul(o0, v[k]));
+    acc2 = cadd(acc2, cmul(o1, v[k + 256]));
+    acc = cadd(acc, cmul(o2, v[k + 512]));
+    acc2 = cadd(acc2, cmul(o3, v[k + 768]));
+  }
+  for (; k < K; k += 256) acc = cadd(acc, cmul(load_c(row, k), v[k]));
+  acc = wave_sum(cadd(acc, acc2));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -334,9 +344,18 @@ __global__ __launch_bounds__(256) void k_ohu(const InT* __restrict__ O, int64_t 
   const int64_t k = blockIdx.x * 256ll + threadIdx.x;
   if (k >= K) return;
   const int64_t n0 = (int64_t)blockIdx.y * kColChunk, n1 = min(N, n0 + kColChunk);
-  double2 acc = make_double2(0.0, 0.0);
-  for (int64_t n = n0; n < n1; ++n) acc = cadd(acc, cscale(cmul(cconj(load_c(O, n * K + k)), u[n]), sq[n]));
-  partial[(int64_t)blockIdx.y * K + k] = acc;
+  double2 acc = make_double2(0.0, 0.0), acc2 = acc;
+  int64_t n = n0;
+  for (; n + 3 < n1; n += 4) {
+    const double2 o0 = load_c(O, n * K + k), o1 = load_c(O, (n + 1) * K + k), o2 = load_c(O, (n + 2) * K + k),
+                  o3 = load_c(O, (n + 3) * K + k);
+    acc = cadd(acc, cscale(cmul(cconj(o0), u[n]), sq[n]));
+    acc2 = cadd(acc2, cscale(cmul(cconj(o1), u[n + 1]), sq[n + 1]));
+    acc = cadd(acc, cscale(cmul(cconj(o2), u[n + 2]), sq[n + 2]));
+    acc2 = cadd(acc2, cscale(cmul(cconj(o3), u[n + 3]), sq[n + 3]));
+  }
+  for (; n < n1; ++n) acc = cadd(acc, cscale(cmul(cconj(load_c(O, n * K + k)), u[n]), sq[n]));
+  partial[(int64_t)blockIdx.y * K + k] = cadd(acc, acc2);
 }
 
 // out[0..1] = sum_n sq_n u_n

@@ -103,6 +103,7 @@ _SIGS = {
     "vmc_made_sample": ([P, I64, C.c_uint64, C.c_uint64, P, P], C.c_int),
     "vmc_made_destroy": ([P], C.c_int),
     "vmc_calib_copy": ([P, P, P, I64], C.c_int),
+    "vmc_calib_read": ([P, P, I64, P], C.c_int),
     "vmc_calib_mfma": ([P, C.c_int, C.c_int, C.c_int, P, C.POINTER(C.c_double)], C.c_int),
 }
 EXPORTS = tuple(_SIGS)
@@ -486,6 +487,13 @@ def calib_copy(ctx: Context, src: torch.Tensor, dst: torch.Tensor):
     nb = src.numel() * src.element_size()
     assert dst.numel() * dst.element_size() == nb
     _check(load().vmc_calib_copy(ctx.h, _ptr(src), _ptr(dst), nb), ctx.h)
+
+
+def calib_read(ctx: Context, src: torch.Tensor):
+    """Read-only pass over src: the read bandwidth reference."""
+    nb = src.numel() * src.element_size()
+    out = torch.empty(8192 * 2, dtype=torch.int64, device=src.device)
+    _check(load().vmc_calib_read(ctx.h, _ptr(src), nb, _ptr(out)), ctx.h)
 
 
 CALIB_BF16 = 16
