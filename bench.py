@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tfim1d_L64_rbm_a4_sr",
                     choices=["tfim1d_L64_rbm_a4_sr", "heis2d_10x10_rbm_a4", "tfim2d_16x16_cnn",
-                             "tfim2d_20x20_rbm_a2_made"])
+                             "tfim2d_20x20_rbm_a2_made", "tfim2d_20x20_rbm_a2_sr"])
     ap.add_argument("--p-global", type=float, default=None, help="MADE mix: global proposal probability")
     ap.add_argument("--record-sweeps", type=int, default=256, help="MADE mix: recorded sweeps per chain")
     ap.add_argument("--made-epochs", type=int, default=100, help="MADE mix: training epochs")
@@ -368,6 +368,8 @@ def main():
     ctx = V.Context(0)
     model = V.Model.rbm(ctx, N, Nh, True)
     K = model.K
+    if K > 65536:
+        args.solver = "cg"  # a dense K x K S would not fit: the matrix-free solve is the only option
     theta = torch.from_numpy(p).to(dev)
     model.set_params(theta)
     set_prec(V, model, args.prec)
@@ -441,8 +443,9 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 (S Gram from c64 O_k" + (", split-f16 products)" if args.gram else ")"),
         "data": "synthetic (seeded RBM parameters N(0,0.01), Metropolis samples)",
-        "config": {"workload": "SR step: TFIM chain L=64 PBC J=h=1, complex RBM alpha=4 (K=16704), "
-                               "16384 samples (1024 chains x 16 sweeps), nu_rel=1e-3",
+        "config": {"workload": (f"SR step ({args.workload}): TFIM {cfg['Lx']}x{cfg['Ly']} PBC J={cfg['J']} "
+                                f"h={cfg['h']}, complex RBM alpha={cfg['alpha']} (K={K}), {ns} samples "
+                                f"({n_chains} chains x {per_chain} sweeps), nu_rel={cfg['nu_rel']}"),
                    "global_batch": ns, "K": K, "parallelism": "single GPU", "gram": args.gram, "prec": args.prec,
                    "solver": args.solver},
         "phases_ms": phases,
@@ -455,7 +458,7 @@ def main():
         "cg_iterations": infos[-1][0].get("iterations"),
         "accept": round(infos[-1][1], 4),
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "tfim1d_L64_rbm_a4_sr":
         out["cpu_baseline"] = cpu_baseline(cfg, p, N, Nh, n_chains, per_chain)
     print(json.dumps(out), flush=True)
 

@@ -152,6 +152,12 @@ WORKLOADS = {
         net="rbm", alpha=4, is_complex=True, std=0.01, param_seed=3,
         n_chains=1024, samples_per_chain=16, sampler_seed=103, proposal="flip",
         nu_rel=1e-3),
+    # SR at the learned-proposal lattice scale: K = 321 200 (no dense S)
+    "tfim2d_20x20_rbm_a2_sr": dict(
+        ham="tfim", Lx=20, Ly=20, periodic=True, J=1.0, h=3.0,
+        net="rbm", alpha=2, is_complex=True, std=0.01, param_seed=6,
+        n_chains=1024, samples_per_chain=4, sampler_seed=106, proposal="flip",
+        nu_rel=1e-3),
     "tfim2d_16x16_cnn": dict(
         ham="tfim", Lx=16, Ly=16, periodic=True, J=1.0, h=3.0,
         net="cnn", channels=16, kernel=4, std=0.05, param_seed=4,

@@ -129,3 +129,30 @@ def test_sr_solve_cg_iteration_cap(ctx):
     assert info["iterations"] == 3 and np.isfinite(info["residual"]) and info["residual"] > 1e-14
     with pytest.raises(V.VMCError):
         V.sr_solve_cg(ctx, dev_c128(O), dev_c128(el), mode=V.SR_IMAG)
+
+
+def test_sr_solve_cg_beyond_dense_limit(ctx):
+    # K = 70 800 > 65 536: the dense solve refuses, conjugate gradient runs.
+    # Pin (additive shift only): (Obar^H Obar + eps I)^{-1} Obar^H = Obar^H (Obar Obar^H + eps I)^{-1},
+    # so x = -Obar^H (Obar Obar^H + eps I)^{-1} e~ with an N_s x N_s solve on the host.
+    flush("sr cg K = 70800")
+    N, Nh, ns, eps = 100, 700, 256, 1e-3
+    p = si.rbm_params(N, Nh, std=0.05, is_complex=True, seed=71)
+    bits = si.random_bits(ns, N, seed=72)
+    O = orbm.grad_log_psi(p, bits, Nh).astype(np.complex64)
+    el = np.random.default_rng(73).normal(size=ns) + 1j * np.random.default_rng(74).normal(size=ns)
+    Od = torch.from_numpy(O).to("cuda:0")
+    with pytest.raises(V.VMCError):
+        V.sr_solve(ctx, Od, dev_c128(el), nu_rel=0.0, eps_abs=eps)
+    x, info = V.sr_solve_cg(ctx, Od, dev_c128(el), nu_rel=0.0, eps_abs=eps, tol=1e-12, max_iter=2000)
+    x = x.cpu().numpy()
+    Oc = O.astype(np.complex128)
+    Ob = (Oc - Oc.mean(axis=0)) / np.sqrt(ns)
+    et = (el - el.mean()) / np.sqrt(ns)
+    G = Ob @ Ob.conj().T
+    ref = -Ob.conj().T @ np.linalg.solve(G + eps * np.eye(ns), et)
+    kappa = (np.linalg.eigvalsh(G).max() + eps) / eps  # condition of Obar^H Obar + eps I
+    err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+    flush(f"  iterations {info['iterations']}, residual {info['residual']:.2e}, error {err:.2e}, kappa {kappa:.1e}")
+    assert info["residual"] <= 1e-11
+    assert err <= 10 * 1e-12 * kappa + 1e-12
