@@ -105,33 +105,34 @@ def eloc_flops(N, Nh, n_slots):
 
 
 def cpu_baseline(cfg, p, N, Nh, n_chains, per_chain):
-    """The FP64 oracle on a bounded sample of the same step, scaled to one step."""
+    """The FP64 oracle on a bounded sample of the same step (about 10 s of host
+    work), each phase scaled to the full step."""
     from oracle import rbm as orbm, eloc as oeloc, metropolis as omet, sr as osr
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     f = lambda b: orbm.log_psi(p, b, Nh)
+    ns_full = n_chains * per_chain
     t = {}
-    # sampling: 32 chains x one sweep, scaled to n_chains x per_chain sweeps
-    ch = omet.Chains(f, N, "flip", seed=103, chain_ids=np.arange(32), therm_sweeps=0)
+    # sampling: 128 chains x one sweep, scaled to n_chains x per_chain sweeps
+    ch = omet.Chains(f, N, "flip", seed=103, chain_ids=np.arange(128), therm_sweeps=0)
     t0 = time.perf_counter()
-    s, _ = ch.sample(1)
-    t["sample"] = (time.perf_counter() - t0) * (n_chains * per_chain) / 32
+    ch.sample(1)
+    t["sample"] = (time.perf_counter() - t0) * ns_full / 128
     bits = si.random_bits(1024, N, seed=7)
     t0 = time.perf_counter()
     orbm.log_psi(p, bits, Nh)
-    t["log_psi"] = (time.perf_counter() - t0) * 16
+    t["log_psi"] = (time.perf_counter() - t0) * ns_full / 1024
     t0 = time.perf_counter()
     O = orbm.grad_log_psi(p, bits, Nh)
-    t["grad"] = (time.perf_counter() - t0) * 16
+    t["grad"] = (time.perf_counter() - t0) * ns_full / 1024
     t0 = time.perf_counter()
-    el = oeloc.local_energy(f, "tfim", bits[:32], N, 1, True, 1.0, 1.0)
-    t["eloc"] = (time.perf_counter() - t0) * (n_chains * per_chain) / 32
-    ns = 256
-    el_s = np.resize(el, ns)
+    el = oeloc.local_energy(f, "tfim", bits[:256], N, 1, True, 1.0, 1.0)
+    t["eloc"] = (time.perf_counter() - t0) * ns_full / 256
+    ns = 1024
     t0 = time.perf_counter()
-    S, F = osr.fisher_and_force(O[:ns], el_s)
-    t["S_F"] = (time.perf_counter() - t0) * (n_chains * per_chain) / ns
-    Kp = 768
+    S, F = osr.fisher_and_force(O[:ns], np.resize(el, ns))
+    t["S_F"] = (time.perf_counter() - t0) * ns_full / ns
+    Kp = 2048
     A = osr.shifted(S[:Kp, :Kp], 1e-3)
     del S
     t0 = time.perf_counter()
@@ -143,9 +144,10 @@ def cpu_baseline(cfg, p, N, Nh, n_chains, per_chain):
     total = sum(t.values())
     return {
         "value": 1.0 / total, "unit": "SR steps/s", "cores": threads, "kind": "oracle",
-        "sample": ("oracle timed on: 32 chains x 1 sweep (scaled to 1024 x 16), log psi and O_k on 1024 "
-                   "samples (x16), E_loc on 32 samples (x512), S/F on 256 samples (x64), Cholesky and "
-                   "triangular solves on the leading 768 x 768 block of S~ (scaled by (K/768)^3 and ^2)"),
+        "sample": (f"oracle timed on: 128 chains x 1 sweep (scaled to {n_chains} x {per_chain}), log psi and O_k "
+                   f"on 1024 samples, E_loc on 256 samples, S/F on 1024 samples (each scaled to {ns_full}), "
+                   f"Cholesky and triangular solves on the leading {Kp} x {Kp} block of S~ (scaled by "
+                   f"(K/{Kp})^3 and ^2)"),
         "phase_s": {k: round(v, 3) for k, v in t.items()},
     }
 
