@@ -57,3 +57,57 @@ class GroundStateSearch:
             if callback is not None:
                 callback(info)
         return out
+
+
+class TDVP:
+    """Time-dependent variational principle (Sec. 3): theta' = x with
+    (S + eps I) x = -[[gamma F]], gamma = i for real time (psi' = -i H psi) and
+    gamma = 1 for imaginary time, integrated by the Euler or the second-order
+    Heun scheme of the paper's integrator options.  Expectations come either
+    from Metropolis samples of the library's sampler or, for small systems,
+    from all 2^N configurations weighted by |psi|^2 (exact TDVP).  The paper
+    advises against the diagonal shift for time evolution, so only a small
+    additive eps_abs regularises S by default."""
+
+    def __init__(self, ctx: V.Context, model: V.Model, ham: V.Hamiltonian, theta: torch.Tensor, *,
+                 real_time: bool = True, eps_abs: float = 1e-8, nu_rel: float = 0.0, exact_states=None,
+                 sampler: V.Sampler | None = None, n_samples: int = 0, mode: int = V.SR_COMPLEX):
+        self.ctx, self.model, self.ham = ctx, model, ham
+        self.theta = theta.to(torch.complex128).contiguous()
+        self.gamma = 1j if real_time else 1.0
+        self.eps_abs, self.nu_rel, self.mode = eps_abs, nu_rel, mode
+        self.states = exact_states  # device (2^N, W) int64 or None
+        self.sampler, self.n_samples = sampler, n_samples
+        self.t = 0.0
+        self.last_info = None
+
+    def _batch(self):
+        if self.states is not None:
+            lp = self.model.log_psi(self.states)
+            w = torch.exp(2.0 * (lp.real - lp.real.max()))
+            return self.states, (w / w.sum()).contiguous()
+        s, _, _ = self.sampler.sample(self.n_samples)
+        return s, None
+
+    def rhs(self, theta: torch.Tensor) -> torch.Tensor:
+        self.model.set_params(theta.contiguous())
+        s, w = self._batch()
+        O = self.model.grad_log_psi(s, torch.complex128)
+        el = self.model.local_energy(self.ham, s)
+        x, info = V.sr_solve(self.ctx, O, el, weights=w, nu_rel=self.nu_rel, eps_abs=self.eps_abs, mode=self.mode,
+                             gamma=self.gamma)
+        self.last_info = info
+        return x
+
+    def step(self, dt: float, method: str = "heun") -> dict:
+        k1 = self.rhs(self.theta)
+        if method == "euler":
+            self.theta = self.theta + dt * k1
+        elif method == "heun":
+            k2 = self.rhs(self.theta + dt * k1)
+            self.theta = self.theta + 0.5 * dt * (k1 + k2)
+        else:
+            raise ValueError("method must be 'euler' or 'heun'")
+        self.model.set_params(self.theta)
+        self.t += dt
+        return self.last_info
