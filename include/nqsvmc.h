@@ -113,6 +113,25 @@ int vmc_model_create_rbm(vmc_ctx* ctx, int n_visible, int n_hidden, int is_compl
  *   log psi   = sum_{c,y,x} logcosh(z2[c,y,x])
  * Flat order: [W1 (C*k*k), b1 (C), W2 (C*C*k*k, [c_out][c_in][dy][dx]), b2 (C)], complex. */
 int vmc_model_create_cnn(vmc_ctx* ctx, int Lx, int Ly, int channels, int kernel, vmc_model** out);
+/* Autoregressive state with direct sampling (Sec. 2.4 "Autoregressive neural
+ * quantum states"): psi(s) = sqrt(q(s)), q(s) = prod_i p_i(s_i | s_<i) given by a
+ * masked network with one ReLU hidden layer of n_hidden units (MADE; hidden
+ * degree m(k) = k mod (N - 1) + 1, inputs and outputs have degree d + 1 for
+ * site d):  a = (W1 * M1) s + b1,  l = (W2 * M2) relu(a) + b2,
+ *   log psi(s) = (1/2) sum_i [s_i l_i - softplus(l_i)],  s_i in {0, 1} (bit i),
+ * with M1[k, d] = [m(k) >= d + 1] and M2[i, k] = [i + 1 > m(k)].  Real and
+ * normalised over all 2^N configurations.  Only the unmasked weights are
+ * parameters, K = N n_hidden + n_hidden + N, in the order
+ *   [W1 (k ascending, then d = 0 .. m(k)-1) | b1 (n_hidden) |
+ *    W2 (i ascending, then k ascending with m(k) <= i) | b2 (N)];
+ * imaginary parts passed to set_params are dropped.  Float64 only
+ * (set_precision with F32/BF16 returns VMC_ERR_UNSUPPORTED), no vmc_log_psi_vjp.
+ * A sampler on this model draws independent samples directly (the Philox
+ * stream of the masked network's sampler with the sampler's seed and counter
+ * = the number of earlier vmc_sample calls); its proposal must be
+ * VMC_PROP_FLIP, sweep and thermalisation settings are ignored and the
+ * reported acceptance is 1.  N in [2, 1024], n_hidden in [1, 1024].          */
+int vmc_model_create_autoregressive(vmc_ctx* ctx, int n_sites, int n_hidden, vmc_model** out);
 int vmc_model_num_params(const vmc_model* m, int64_t* K);
 int vmc_model_num_sites(const vmc_model* m, int* N);
 /* Copies K parameters from device memory (dtype C128, C64 or, for real RBMs, F64)

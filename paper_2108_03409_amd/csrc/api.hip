@@ -270,6 +270,35 @@ extern "C" int vmc_model_create_cnn(vmc_ctx* ctx, int Lx, int Ly, int channels, 
   });
 }
 
+extern "C" int vmc_model_create_autoregressive(vmc_ctx* ctx, int n_sites, int n_hidden, vmc_model** out) {
+  return guard(ctx, [&] {
+    VMC_REQUIRE(ctx && out, "NULL argument");
+    VMC_REQUIRE(n_sites >= 2 && n_sites <= 1024, "n_sites must be in [2, 1024]");
+    VMC_REQUIRE(n_hidden >= 1 && n_hidden <= 1024, "n_hidden must be in [1, 1024]");
+    set_device(ctx);
+    auto* m = new vmc_model;
+    m->ctx = ctx;
+    m->kind = MODEL_AR;
+    m->N = n_sites;
+    m->W = (n_sites + 63) / 64;
+    m->Nh = n_hidden;
+    m->is_complex = 0;
+    m->K = (int64_t)n_sites * n_hidden + n_hidden + n_sites;
+    try {
+      m->params = (double2*)dmalloc(sizeof(double2) * m->K);
+      VMC_HIP(hipMemsetAsync(m->params, 0, sizeof(double2) * m->K, ctx->stream));
+      ar_init(m);
+    } catch (...) {
+      ar_free(m);
+      if (m->params) (void)hipFree(m->params);
+      delete m;
+      throw;
+    }
+    ctx_retain(ctx);
+    *out = m;
+  });
+}
+
 extern "C" int vmc_model_num_params(const vmc_model* m, int64_t* K) {
   if (!m || !K) return VMC_ERR_INVALID_ARG;
   *K = m->K;
@@ -342,6 +371,8 @@ extern "C" int vmc_model_set_params(vmc_model* m, const void* params_dev, int dt
       int64_t n = (int64_t)m->N * m->Nh;
       k_rbm_transpose<<<grid_for(n, 256), 256, 0, ctx->stream>>>(m->params, m->N, m->Nh, m->Wt);
       VMC_HIP(hipGetLastError());
+    } else if (m->kind == MODEL_AR) {
+      ar_set_params(m);
     }
     m->version++;
   });
@@ -361,6 +392,8 @@ extern "C" int vmc_model_set_precision(vmc_model* m, int prec) {
   return guard(m ? m->ctx : nullptr, [&] {
     VMC_REQUIRE(m, "NULL model");
     VMC_REQUIRE(prec == VMC_F64 || prec == VMC_F32 || prec == VMC_BF16, "unknown precision");
+    if (prec != VMC_F64 && m->kind == MODEL_AR)
+      throw vmc_error{VMC_ERR_UNSUPPORTED, "the autoregressive state is evaluated in float64 only"};
     if (prec != VMC_F64 && m->kind == MODEL_CNN && (m->Lx < 2 * m->k - 1 || m->Ly < 2 * m->k - 1))
       throw vmc_error{VMC_ERR_UNSUPPORTED, "float32 / bfloat16 CNN local energies need Lx, Ly >= 2 kernel - 1"};
     m->prec = prec;
@@ -374,6 +407,7 @@ extern "C" int vmc_model_destroy(vmc_model* m) {
   if (m->params) (void)hipFree(m->params);
   if (m->Wt) (void)hipFree(m->Wt);
   rbm_lowp_free(m);
+  ar_free(m);
   for (auto& t : m->tab) {
     if (t.T) (void)hipFree(t.T);
     if (t.D) (void)hipFree(t.D);
@@ -485,6 +519,8 @@ extern "C" int vmc_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double* l
       rbm_lowp_log_psi(m, s, B, (double2*)logpsi);
     else if (m->kind == MODEL_RBM)
       rbm_log_psi(m, s, B, (double2*)logpsi);
+    else if (m->kind == MODEL_AR)
+      ar_log_psi(m, s, B, (double2*)logpsi);
     else
       cnn_log_psi(m, s, B, (double2*)logpsi);
   });
@@ -506,6 +542,8 @@ extern "C" int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int
       rbm_lowp_local_energy(m, H, s, B, (double2*)eloc);
     else if (m->kind == MODEL_RBM)
       rbm_local_energy(m, H, s, B, (double2*)eloc);
+    else if (m->kind == MODEL_AR)
+      ar_local_energy(m, H, s, B, (double2*)eloc);
     else if (m->prec != VMC_F64)
       cnn_lowp_local_energy(m, H, s, B, (double2*)eloc);
     else
@@ -524,6 +562,8 @@ extern "C" int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void
     phase_scope ps(m->ctx, "grad");
     if (m->kind == MODEL_RBM)
       rbm_grad(m, s, B, O, dtype);
+    else if (m->kind == MODEL_AR)
+      ar_grad(m, s, B, O, dtype);
     else
       cnn_grad(m, s, B, O, dtype);
   });
@@ -534,6 +574,8 @@ extern "C" int vmc_log_psi_vjp(vmc_model* m, const uint64_t* s, int64_t B, const
     VMC_REQUIRE(m, "NULL model");
     VMC_REQUIRE(B >= 0, "B < 0");
     VMC_REQUIRE(out, "NULL out");
+    if (m->kind == MODEL_AR)
+      throw vmc_error{VMC_ERR_UNSUPPORTED, "no vector-Jacobian product for the autoregressive state"};
     set_device(m->ctx);
     phase_scope ps(m->ctx, "vjp");
     if (B == 0) {
@@ -562,7 +604,8 @@ extern "C" int vmc_sampler_create(vmc_ctx* ctx, vmc_model* m, vmc_ham* H, const 
     }
     if (o->proposal == VMC_PROP_MADE_MIX)
       VMC_REQUIRE(o->p_global >= 0.0 && o->p_global <= 1.0, "p_global must be in [0, 1]");
-    VMC_REQUIRE(m->kind == MODEL_RBM || o->proposal == VMC_PROP_FLIP, "CNN models are sampled with single flips");
+    VMC_REQUIRE(m->kind == MODEL_RBM || o->proposal == VMC_PROP_FLIP,
+                "CNN models are sampled with single flips; autoregressive states take VMC_PROP_FLIP (direct sampling)");
     set_device(ctx);
     auto* S = new vmc_sampler;
     S->ctx = ctx;
@@ -603,6 +646,17 @@ extern "C" int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, do
     if (S->opts.proposal == VMC_PROP_MADE_MIX)
       VMC_REQUIRE(S->made_buf, "VMC_PROP_MADE_MIX needs vmc_sampler_set_proposal_made first");
     set_device(S->ctx);
+    if (S->model->kind == MODEL_AR) {  // direct sampling: independent draws, nothing rejected
+      phase_scope ps(S->ctx, "sample");
+      ar_sample(S, per_chain * S->opts.n_chains, s_out, (double2*)logpsi_out);
+      S->bits_valid = 1;
+      S->thermalized = 1;
+      S->last_accept = 1.0;
+      S->last_global_accept = 0.0;
+      S->last_n_global = 0;
+      if (accept_rate_host) *accept_rate_host = 1.0;
+      return;
+    }
     uint64_t t0 = S->t;
     {
       phase_scope ps(S->ctx, "sample");

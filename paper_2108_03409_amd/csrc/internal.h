@@ -123,9 +123,10 @@ inline size_t ws_round(size_t b) { return (b + 255) & ~size_t(255); }
 void* pinned_host(vmc_ctx* ctx, size_t bytes);
 
 // ---------------------------------------------------------------- models --
-enum { MODEL_RBM = 0, MODEL_CNN = 1 };
+enum { MODEL_RBM = 0, MODEL_CNN = 1, MODEL_AR = 2 };
 
 struct vmc_ham;
+struct vmc_made;
 
 // Per (model, move set) tables of the RBM ratio identity (see rbm.hip).
 struct rbm_move_tables {
@@ -167,6 +168,13 @@ struct vmc_model {
     uint64_t ham_uid = 0;
     float2 *T = nullptr, *LC = nullptr, *alpha = nullptr;
   } tab32[2];
+  // autoregressive state (psi = sqrt(q) of a masked network with Nh hidden units):
+  // the network's dense masked parameters, the compact-to-dense index pairs and
+  // W2 * M2 transposed (Nh x N)
+  vmc_made* made = nullptr;
+  int2* ar_idx = nullptr;
+  double* ar_w2t = nullptr;
+  int64_t ar_r1 = 0, ar_r2 = 0, ar_r3 = 0;  // ends of the W1, b1 and W2 blocks of the compact vector
 };
 
 // ----------------------------------------------------------- Hamiltonians --
@@ -385,6 +393,17 @@ void cnn_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, do
 void cnn_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
 void cnn_sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
 void cnn_lowp_sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
+// arnqs.hip (autoregressive state)
+void ar_init(vmc_model* m);
+void ar_free(vmc_model* m);
+void ar_set_params(vmc_model* m);
+void ar_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* out);
+void ar_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
+void ar_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
+void ar_sample(vmc_sampler* S, int64_t B, uint64_t* s_out, double2* logpsi_out);
+// made.hip
+void made_refresh(vmc_made* md);
+void made_sample_impl(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, uint64_t* s_out, double* logq);
 // vjp.hip
 void log_psi_vjp_impl(vmc_model* m, const uint64_t* s, int64_t B, const double2* g, double2* out);
 // rbm_lowp.hip

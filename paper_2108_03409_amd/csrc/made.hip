@@ -274,6 +274,8 @@ void made_free(vmc_made* md) {
 
 }  // namespace
 
+void made_refresh(vmc_made* md) { refresh_masks(md); }
+
 void made_sample_impl(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, uint64_t* s_out, double* logq) {
   const int QH = (md->H + 63) / 64;
   const uint2 key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));

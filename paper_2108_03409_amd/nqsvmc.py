@@ -67,6 +67,7 @@ _SIGS = {
     "vmc_ctx_get_timing": ([P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
     "vmc_model_create_rbm": ([P, C.c_int, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_model_create_cnn": ([P, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
+    "vmc_model_create_autoregressive": ([P, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_model_num_params": ([P, C.POINTER(I64)], C.c_int),
     "vmc_model_num_sites": ([P, C.POINTER(C.c_int)], C.c_int),
     "vmc_model_set_params": ([P, P, C.c_int], C.c_int),
@@ -202,6 +203,14 @@ class Model:
     def cnn(cls, ctx, Lx, Ly, channels, kernel):
         h = P()
         _check(load().vmc_model_create_cnn(ctx.h, Lx, Ly, channels, kernel, C.byref(h)), ctx.h)
+        return cls(ctx, h)
+
+    @classmethod
+    def autoregressive(cls, ctx, n_sites, n_hidden):
+        """psi = sqrt(q) of a masked autoregressive network; samplers on it draw
+        independent samples directly (no Markov chain)."""
+        h = P()
+        _check(load().vmc_model_create_autoregressive(ctx.h, n_sites, n_hidden, C.byref(h)), ctx.h)
         return cls(ctx, h)
 
     def set_params(self, params: torch.Tensor):

@@ -125,6 +125,13 @@ def made_num_params(n_in: int, n_hidden: int) -> int:
     return n_hidden * n_in + n_hidden + n_in * n_hidden + n_in
 
 
+def ar_params(n_sites: int, n_hidden: int, *, seed: int, std: float = 0.5) -> np.ndarray:
+    """Live parameters of the autoregressive state (N H + H + N reals), i.i.d.
+    normal with standard deviation ``std``."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, std, size=n_sites * n_hidden + n_hidden + n_sites).astype(np.float64)
+
+
 def made_params(n_in: int, n_hidden: int, *, seed: int = 205) -> np.ndarray:
     """Flat MADE parameters [W1 (H x N), b1 (H), W2 (N x H), b2 (N)], float64,
     uniform in +-1/sqrt(fan_in) (a common dense-layer initialisation)."""
