@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tfim1d_L64_rbm_a4_sr",
                     choices=["tfim1d_L64_rbm_a4_sr", "heis2d_10x10_rbm_a4", "tfim2d_16x16_cnn",
-                             "tfim2d_20x20_rbm_a2_made", "tfim2d_20x20_rbm_a2_sr"])
+                             "tfim2d_20x20_rbm_a2_made", "tfim2d_20x20_rbm_a2_sr", "tfim1d_L50_ar_sr"])
     ap.add_argument("--p-global", type=float, default=None, help="MADE mix: global proposal probability")
     ap.add_argument("--record-sweeps", type=int, default=256, help="MADE mix: recorded sweeps per chain")
     ap.add_argument("--made-epochs", type=int, default=100, help="MADE mix: training epochs")
@@ -295,6 +295,90 @@ def bench_made(args, V, torch):
     print(json.dumps(out), flush=True)
 
 
+def ar_eloc_flops(N, H):
+    """Multiply-adds (2 flop each) one TFIM local energy of the autoregressive
+    state needs: the forward pass (live W1 and W2 entries) plus, per flipped
+    site d, the hidden units of degree > d and the live W2 entries leaving them."""
+    m = np.arange(H) % (N - 1) + 1
+    fwd = m.sum() + (N - m).sum()
+    per = sum(int((m > d).sum() + (N - m[m > d]).sum()) for d in range(N))
+    return 2.0 * (fwd + per)
+
+
+def bench_ar_sr(args, V, torch):
+    """SR steps/s of the autoregressive state: one step = direct samples,
+    O_k, local energies, the shifted solve of the real SR equation, update."""
+    cfg = si.WORKLOADS[args.workload]
+    dev = "cuda:0"
+    N, Hh = cfg["Lx"] * cfg["Ly"], cfg["hidden"]
+    ns = cfg["n_chains"] * cfg["samples_per_chain"]
+    ctx = V.Context(0)
+    model = V.Model.autoregressive(ctx, N, Hh)
+    K = model.K
+    theta = torch.from_numpy(si.ar_params(N, Hh, seed=cfg["param_seed"], std=cfg["std"])).to(dev)
+    model.set_params(theta)
+    H = V.Hamiltonian.tfim(ctx, cfg["Lx"], cfg["Ly"], cfg["periodic"], cfg["J"], cfg["h"])
+    sampler = V.Sampler(ctx, model, H, n_chains=cfg["n_chains"], seed=cfg["sampler_seed"])
+    O = torch.empty((ns, K), dtype=torch.float32, device=dev)  # real parameters: real O_k
+    el = torch.empty(ns, dtype=torch.complex128, device=dev)
+
+    def step():
+        nonlocal theta
+        s, _, _ = sampler.sample(ns)
+        model.grad_log_psi(s, out=O)
+        model.local_energy(H, s, out=el)
+        x, info = V.sr_solve(ctx, O, el, nu_rel=cfg["nu_rel"], eps_abs=cfg["eps_abs"], mode=V.SR_REAL)
+        theta = theta + args.tau * x.real
+        model.set_params(theta)
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = {}
+    for ph in ["sample", "grad", "eloc", "sr.center", "sr.herk", "sr.chol", "sr.trsv", "sr.resid"]:
+        ms, n = ctx.get_timing(ph)
+        phases[ph] = round(ms / max(n, 1), 3)
+    ctx.set_timing(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    herk_ms = phases["sr.herk"]
+    # real S = Obar^T Obar, lower triangle: Ns K (K + 1) flop (two real samples per complex row)
+    real_flops = herk_flops(ns, K) / 4.0
+    herk_achieved = real_flops / (herk_ms * 1e-3) / 1e12
+    eloc_ms = phases["eloc"]
+    ew = ar_eloc_flops(N, Hh)
+    out = {
+        "metric": METRIC, "value": round(1e3 / ms_step, 4), "unit": "SR steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (S Gram from real f32 O_k on f32 matrix cores)",
+        "data": "synthetic (seeded autoregressive-state parameters N(0, 0.1), direct samples)",
+        "config": {"workload": (f"SR step ({args.workload}): TFIM chain L={N} PBC J={cfg['J']} h={cfg['h']}, "
+                                f"autoregressive state (masked network, {Hh} hidden units, K={K} live real "
+                                f"parameters), {ns} direct samples, nu_rel={cfg['nu_rel']}, "
+                                f"eps_abs={cfg['eps_abs']}"),
+                   "global_batch": ns, "K": K, "parallelism": "single GPU"},
+        "phases_ms": phases,
+        "local_energies_per_s": round(ns / (eloc_ms * 1e-3), 1),
+        "eloc_roofline": {"kernel": "k_ar_eloc", "bound": "alu",
+                          "achieved_TF": round(ns * ew / (eloc_ms * 1e-3) / 1e12, 3),
+                          "peak": PEAK["fp64_valu_TF"], "work": f"{ew:.4e} flop (multiply-adds) per local energy"},
+        "grad_GBs": round(4.0 * ns * K / (phases["grad"] * 1e-3) / 1e9, 1),
+        "roofline": {"kernel": "k_herk_mfma_f32<real> + k_herk_reduce (S = Obar^T Obar, sample range split)",
+                     "bound": "mfma", "achieved": round(herk_achieved, 3), "peak": PEAK["fp32_mfma_TF"],
+                     "unit": "TFLOP/s", "frac": round(herk_achieved / PEAK["fp32_mfma_TF"], 4), "traffic": None,
+                     "work": f"Ns*K*(K+1) = {real_flops:.4e} flop per solve (Ns={ns}, K={K})"},
+        "energy": infos[-1]["e_mean"].real, "energy_per_site": infos[-1]["e_mean"].real / N,
+        "residual": infos[-1]["residual"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_peaks(args, V, torch):
     """Measured peaks next to the nominal ones: a 16-byte-vector device copy of
     2 GiB (4 GiB moved) and the MFMA loops, each timed with HIP events on the
@@ -358,6 +442,8 @@ def main():
         return bench_eloc(args, V, torch)
     if args.workload == "tfim2d_20x20_rbm_a2_made":
         return bench_made(args, V, torch)
+    if args.workload == "tfim1d_L50_ar_sr":
+        return bench_ar_sr(args, V, torch)
 
     cfg = si.WORKLOADS[args.workload]
     N = cfg["Lx"] * cfg["Ly"]

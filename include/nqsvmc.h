@@ -194,7 +194,8 @@ int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B,
 
 /* Log-derivatives O_k(s) = d log psi(s) / d theta_k (Sec. 2.2; the complex
  * derivative for holomorphic nets, Sec. 2.3), flat parameter order.
- *   O: B*K elements, sample-major (row n = sample n), dtype C128 or C64.      */
+ *   O: B*K elements, sample-major (row n = sample n), dtype C128 or C64; the
+ *   autoregressive state (real parameters, real O) also writes F64 or F32.   */
 int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
 
 /* Reverse-mode product with the log-derivatives (the backward of log psi for
@@ -261,10 +262,13 @@ int vmc_sampler_destroy(vmc_sampler* S);
  * <.> is the sample mean (weights == NULL) or the weighted mean with weights
  * normalised to sum 1.  The factor 2 of the SR gradient (eq:energy_gradient)
  * is left to the caller's step size: theta <- theta + tau * x.
- *   O: N*K sample-major, dtype C64 or C128;  eloc: N complex128;
+ *   O: N*K sample-major, dtype C64 or C128, or real F32 / F64 (real
+ *   log-derivatives: S is then real whatever the mode);  eloc: N complex128;
  *   weights: N doubles or NULL;  x: K complex128 (written on success).
- * S is formed on the matrix cores from centred O in float32 (C64 input) or
- * float64 (C128 input); factorisation and solves are float64.
+ * S is formed on the matrix cores from centred O in float32 (C64 / F32 input)
+ * or float64 (C128 / F64 input); factorisation and solves are float64.  Real O
+ * is packed two samples per complex row (Re of the Gram of the packed matrix
+ * is S), which halves the Gram work.
  * Returns VMC_ERR_NOT_PD with info->fail_index = first failing column, or
  * VMC_ERR_UNSUPPORTED for VMC_SR_IMAG (Im S is antisymmetric, not PD).
  * info_host (may be NULL) is written on return; the call synchronises.       */
@@ -273,9 +277,9 @@ typedef struct {
   double eps_abs;    /* additive shift */
   int mode;          /* VMC_SR_COMPLEX | VMC_SR_REAL | VMC_SR_IMAG */
   double gamma_re, gamma_im;  /* gamma = 1: SR / imaginary time; gamma = i: real time */
-  int gram;          /* S product: 0 = by O dtype (float32 matrix cores for C64,
-                        float64 for C128); 1 = split-float16 matrix-core products
-                        (C64 input only): each centred value is scaled per column
+  int gram;          /* S product: 0 = by O dtype (float32 matrix cores for C64 / F32,
+                        float64 for C128 / F64); 1 = split-float16 matrix-core products
+                        (C64 / F32 input only): each centred value is scaled per column
                         by a power of two and split into hi + lo float16 parts,
                         three products per term, float32 accumulation, relative
                         error ~2^-21 per product term */

@@ -554,7 +554,10 @@ extern "C" int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int
 extern "C" int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype) {
   return guard(m ? m->ctx : nullptr, [&] {
     VMC_REQUIRE(m, "NULL model");
-    VMC_REQUIRE(dtype == VMC_DT_C128 || dtype == VMC_DT_C64, "dtype must be C128 or C64");
+    VMC_REQUIRE(dtype == VMC_DT_C128 || dtype == VMC_DT_C64 || dtype == VMC_DT_F32 || dtype == VMC_DT_F64,
+                "dtype must be C128, C64, F32 or F64");
+    if (dtype == VMC_DT_F32 || dtype == VMC_DT_F64)
+      VMC_REQUIRE(m->kind == MODEL_AR, "real O_k (F32 / F64) are written for the autoregressive state only");
     VMC_REQUIRE(B >= 0, "B < 0");
     if (B == 0) return;
     VMC_REQUIRE(s && O, "NULL buffer");
@@ -767,7 +770,8 @@ extern "C" int vmc_sr_solve(vmc_ctx* ctx, const void* O, int O_dtype, const doub
   info.fail_index = -1;
   int rc = guard(ctx, [&] {
     VMC_REQUIRE(ctx && opts, "NULL argument");
-    VMC_REQUIRE(O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_C128, "O dtype must be C64 or C128");
+    VMC_REQUIRE(O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_C128 || O_dtype == VMC_DT_F32 || O_dtype == VMC_DT_F64,
+                "O dtype must be C64, C128, F32 or F64");
     VMC_REQUIRE(N >= 1 && K >= 1, "N and K must be positive");
     VMC_REQUIRE(K <= 65536, "K above 65536 is not supported by the dense solve");
     VMC_REQUIRE(O && eloc && x, "NULL buffer");
@@ -779,7 +783,8 @@ extern "C" int vmc_sr_solve(vmc_ctx* ctx, const void* O, int O_dtype, const doub
     if (opts->mode == VMC_SR_IMAG)
       throw vmc_error{VMC_ERR_UNSUPPORTED, "Im S is antisymmetric; the Cholesky solve needs COMPLEX or REAL"};
     VMC_REQUIRE(opts->gram == 0 || opts->gram == 1, "gram must be 0 or 1");
-    VMC_REQUIRE(opts->gram == 0 || O_dtype == VMC_DT_C64, "the split-float16 product needs complex64 O");
+    VMC_REQUIRE(opts->gram == 0 || O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_F32,
+                "the split-float16 product needs float32 O (C64 or F32)");
     set_device(ctx);
     sr_solve_impl(ctx, O, O_dtype, (const double2*)eloc, weights, N, K, opts, (double2*)x, &info);
     if (info.fail_index >= 0)

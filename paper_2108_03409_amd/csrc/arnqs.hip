@@ -17,6 +17,7 @@
 // O_k = d log psi / d theta_k is the per-sample backward pass of the same network.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -186,6 +187,145 @@ __global__ __launch_bounds__(AR_NT) void k_ar_eloc(const uint64_t* __restrict__ 
   }
 }
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same local energies with both masked weight matrices held in LDS (staged
+// once per group) and one wave per configuration: lanes over hidden units for
+// the forward pre-activations and the move updates (registers), lanes over
+// outputs for the logits.  Hidden units whose degree does not exceed min P have
+// a zero W1 column entry for every site of P, so their change is exactly zero
+// and the output loop skips them.  Configurations are taken grid-stride.
+template <int QH>
+__global__ __launch_bounds__(AR_NT) void k_ar_eloc_lds(const uint64_t* __restrict__ s, int64_t B, int N, int H,
+                                                       int W, const double* __restrict__ W1mT,
+                                                       const double* __restrict__ W2t, const double* __restrict__ b1,
+                                                       const double* __restrict__ b2, int kind, double J, double hx,
+                                                       const int2* __restrict__ bonds, int n_bonds,
+                                                       double2* __restrict__ eloc) {
+  extern __shared__ double lds[];
+  double* W1s = lds;                 // [N][H]
+  double* W2s = W1s + N * H;         // [H][N]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* x = W2s + H * N + wave * (3 * N + 64 * QH);  // per wave: x, l, t, hidden changes
+  double* l = x + N;
+  double* t = l + N;
+  double* dhs = t + N;
+  for (int e = threadIdx.x; e < N * H; e += AR_NT) {
+    W1s[e] = W1mT[e];
+    W2s[e] = W2t[e];
+  }
+  __syncthreads();
+  const int Nm1 = N - 1;
+  const double mel = kind == HAM_TFIM ? -hx : 2.0 * J;
+  const bool offdiag = kind == HAM_TFIM ? hx != 0.0 : J != 0.0;
+  for (int64_t b = (int64_t)blockIdx.x * AR_WAVES + wave; b < B; b += (int64_t)gridDim.x * AR_WAVES) {
+    const uint64_t* srow = s + b * W;
+    for (int i = lane; i < N; i += 64) x[i] = (double)((srow[i >> 6] >> (i & 63)) & 1ull);
+    wave_sync();
+    double a[QH], hr[QH];
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int k = lane + 64 * q;
+      const int kc = k < H ? k : H - 1;
+      double acc = b1[kc];
+      for (int d = 0; d < N; ++d) {
+        const double w = W1s[d * H + kc];  // zero beyond the unit's degree
+        acc = fma(w, x[d], acc);
+      }
+      a[q] = acc;
+      hr[q] = k < H ? fmax(acc, 0.0) : 0.0;
+    }
+    for (int i0 = 0; i0 < N; i0 += 64) {
+      const int i = i0 + lane;
+      const int ic = i < N ? i : N - 1;
+      double acc = b2[ic];
+#pragma unroll
+      for (int q = 0; q < QH; ++q)
+        for (int kk = 0; kk < 64; ++kk) {
+          const int k = 64 * q + kk;
+          if (k >= H) break;
+          acc = fma(W2s[k * N + ic], lane_bcast(hr[q], kk), acc);
+        }
+      if (i < N) {
+        l[i] = acc;
+        t[i] = x[i] * acc - ar_softplus(acc);
+      }
+    }
+    wave_sync();
+    double e = 0.0;
+    int n_al = 0;
+    // one connected configuration: sites p0 < p1 (p1 = -1 for a flip)
+    auto move = [&](int p0, int p1) {
+      const double d0 = 1.0 - 2.0 * x[p0];
+      const double d1 = p1 >= 0 ? 1.0 - 2.0 * x[p1] : 0.0;
+#pragma unroll
+      for (int q = 0; q < QH; ++q) {
+        const int k = lane + 64 * q;
+        const int kc = k < H ? k : H - 1;
+        double ap = fma(W1s[p0 * H + kc], d0, a[q]);
+        if (p1 >= 0) ap = fma(W1s[p1 * H + kc], d1, ap);
+        dhs[k] = k < H ? fmax(ap, 0.0) - hr[q] : 0.0;  // exactly 0 for units of degree <= min P
+      }
+      wave_sync();
+      double acc = 0.0;
+      for (int i0 = p0; i0 < N; i0 += 64) {
+        const int i = i0 + lane;
+        const int ic = i < N ? i : N - 1;
+        // four independent chains over the hidden units (broadcast LDS reads of the changes)
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int k = 0;
+        for (; k + 4 <= H; k += 4) {
+          s0 = fma(W2s[k * N + ic], dhs[k], s0);
+          s1 = fma(W2s[(k + 1) * N + ic], dhs[k + 1], s1);
+          s2 = fma(W2s[(k + 2) * N + ic], dhs[k + 2], s2);
+          s3 = fma(W2s[(k + 3) * N + ic], dhs[k + 3], s3);
+        }
+        for (; k < H; ++k) s0 = fma(W2s[k * N + ic], dhs[k], s0);
+        const double lp = l[ic] + ((s0 + s1) + (s2 + s3));
+        if (i < N) {
+          const double xi = (i == p0 || i == p1) ? 1.0 - x[i] : x[i];
+          acc += (xi * lp - ar_softplus(lp)) - t[i];
+        }
+      }
+      acc = wave_sum(acc);
+      e += mel * exp(0.5 * acc);
+      wave_sync();  // dhs is rewritten by the next move
+    };
+    for (int b0 = 0; b0 < n_bonds; b0 += 64) {
+      const int q = b0 + lane;
+      bool al = false, anti = false;
+      int2 bd = make_int2(0, 0);
+      if (q < n_bonds) {
+        bd = bonds[q];
+        al = get_bit(srow, bd.x) == get_bit(srow, bd.y);
+        anti = !al;
+      }
+      n_al += __popcll(__ballot(al));
+      if (kind == HAM_HEIS && offdiag) {
+        unsigned long long am = __ballot(anti);
+        while (am) {
+          const int src = __ffsll((long long)am) - 1;
+          am &= am - 1ull;
+          const int bx = __builtin_amdgcn_readlane(bd.x, src), by = __builtin_amdgcn_readlane(bd.y, src);
+          move(min(bx, by), max(bx, by));
+        }
+      }
+    }
+    if (kind == HAM_TFIM && offdiag)
+      for (int p = 0; p < N; ++p) move(p, -1);
+    if (lane == 0) {
+      const int n_anti = n_bonds - n_al;
+      const double diag = (kind == HAM_TFIM ? -J : J) * (double)(n_al - n_anti);
+      eloc[b] = make_double2(diag + e, 0.0);
+    }
+    wave_sync();  // x, l, t are rewritten by the next configuration
+  }
+}
+
 // O_k = (1/2) d log q / d theta_k for SB configurations per group:
 //   g_l[i] = s_i - sigmoid(l_i),  g_h[k] = [a_k > 0] sum_i (W2 * M2)[i, k] g_l[i],
 //   W1 (k, d): g_h[k] s_d,  b1 k: g_h[k],  W2 (i, k): g_l[i] relu(a_k),  b2 i: g_l[i].
@@ -234,10 +374,12 @@ __global__ __launch_bounds__(AR_NT) void k_ar_grad(const uint64_t* __restrict__ 
         v = gl[pr.x];
       v *= 0.5;
       OutT* row = O + (b0 + q) * K;
-      if constexpr (sizeof(OutT) == 16)
+      if constexpr (std::is_same<OutT, double2>::value)
         row[j] = make_double2(v, 0.0);
-      else
+      else if constexpr (std::is_same<OutT, float2>::value)
         row[j] = make_float2((float)v, 0.0f);
+      else
+        row[j] = (OutT)v;
     }
   }
 }
@@ -358,9 +500,32 @@ void ar_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* out) {
 
 void ar_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc) {
   const ar_ptrs p = ptrs(m);
+  const int QH = (m->Nh + 63) / 64;
+  const int QHp = QH <= 1 ? 1 : QH <= 2 ? 2 : QH <= 4 ? 4 : 8;
+  const size_t lds_w =
+      sizeof(double) * (2 * (size_t)m->N * m->Nh + (size_t)AR_WAVES * (3 * (size_t)m->N + 64 * (size_t)QHp));
+  if (lds_w <= kArLdsMax) {
+    // one resident wave of groups: as many as the LDS of 256 compute units holds (at most 8 each)
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)(160 * 1024) / (int64_t)lds_w));
+    const int64_t groups = std::min<int64_t>((B + AR_WAVES - 1) / AR_WAVES, 256 * per_cu);
+#define AR_ELOC_LDS(Q)                                                                                          \
+  k_ar_eloc_lds<Q><<<(unsigned)groups, AR_NT, lds_w, m->ctx->stream>>>(s, B, m->N, m->Nh, m->W, p.W1mT,         \
+                                                                       m->ar_w2t, p.b1, p.b2, H->kind, H->J,   \
+                                                                       H->h, H->bonds, H->n_bonds, eloc)
+    if (QH <= 1)
+      AR_ELOC_LDS(1);
+    else if (QH <= 2)
+      AR_ELOC_LDS(2);
+    else if (QH <= 4)
+      AR_ELOC_LDS(4);
+    else
+      AR_ELOC_LDS(8);
+#undef AR_ELOC_LDS
+    VMC_HIP(hipGetLastError());
+    return;
+  }
   const size_t lds = sizeof(double) * (3 * (size_t)m->N + 2 * (size_t)m->Nh) + sizeof(int) * (size_t)H->n_bonds;
   VMC_REQUIRE(lds <= kArLdsMax, "network too large for the per-configuration local-energy tile");
-  const int QH = (m->Nh + 63) / 64;
   for (int64_t b0 = 0; b0 < B; b0 += INT32_MAX) {
     const int64_t nb = std::min<int64_t>(INT32_MAX, B - b0);
 #define AR_ELOC(Q)                                                                                                 \
@@ -399,11 +564,21 @@ void ar_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype) {
       AR_GRAD(4, double2);
     else
       AR_GRAD(1, double2);
-  } else {
+  } else if (dtype == VMC_DT_C64) {
     if (sb == 4)
       AR_GRAD(4, float2);
     else
       AR_GRAD(1, float2);
+  } else if (dtype == VMC_DT_F64) {
+    if (sb == 4)
+      AR_GRAD(4, double);
+    else
+      AR_GRAD(1, double);
+  } else {
+    if (sb == 4)
+      AR_GRAD(4, float);
+    else
+      AR_GRAD(1, float);
   }
 #undef AR_GRAD
   VMC_HIP(hipGetLastError());

@@ -15,6 +15,12 @@
 // remapped so that consecutive tiles of one row stripe run on the same XCD
 // (shared L2).  The epilogue writes S~ (float64, projection and diagonal shift
 // applied) to the lower triangle and its conjugate to the upper triangle.
+//
+// Real mode (only Re S is used) keeps the first accumulator alone: half the
+// matrix-core work.  When the tiles alone cannot fill the chip (small K, many
+// samples) the sample range is split over blockIdx.y; each split stores its
+// float32 accumulators in register order and a second kernel adds the splits in
+// float64 (fixed order, so the result is reproducible) before the epilogue.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -37,7 +43,44 @@ struct herk_args {
   double2* diag;
   int n_row_tiles;
   int64_t n_tiles;
+  int ksplit;        // sample-range splits (1 = none)
+  float* part;       // [ksplit][n_tiles][64][256] partial accumulators when ksplit > 1
 };
+
+constexpr int kAccPerThread = 64;  // 4 x 2 blocks x 2 accumulators x 4 values
+
+__device__ __forceinline__ int64_t remap_tile(int64_t bid, int64_t nb) {
+  // XCD-aware remap: hardware places block i on XCD i % 8
+  const int64_t per = (nb + 7) / 8;
+  return (bid % 8) * per + bid / 8;
+}
+
+// writes one lane's values of the 16 x 16 blocks; get(i, j, q, r) returns accumulator q
+template <typename Get>
+__device__ __forceinline__ void herk_epilogue(const herk_args& a, int64_t row0, int64_t col0, int wr, int wc, int li,
+                                              int lk, Get get) {
+  const int64_t K = a.K;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t k = row0 + wr * 64 + i * 16 + 4 * lk + r;
+        const int64_t kp = col0 + wc * 32 + j * 16 + li;
+        if (k >= K || kp >= K || kp > k) continue;
+        const double re = get(i, j, 0, r);
+        const double im = a.mode == VMC_SR_REAL ? 0.0 : get(i, j, 1, r);
+        if (k == kp) {
+          const double2 d = make_double2(re * (1.0 + a.nu) + a.eps, 0.0);
+          a.diag[k] = d;
+          a.S[k * K + k] = d;
+        } else {
+          a.S[k * K + kp] = make_double2(re, im);
+          a.S[kp * K + k] = make_double2(re, -im);
+        }
+      }
+}
 
 __device__ __forceinline__ void tile_of(int64_t b, int& tr, int& tc) {
   // row tile tr holds tiles tc = 0 .. 2 tr + 1; cumulative count tr (tr + 1)
@@ -48,15 +91,13 @@ __device__ __forceinline__ void tile_of(int64_t b, int& tr, int& tc) {
   tc = (int)(b - (int64_t)t * (t + 1));
 }
 
+template <bool REAL>
 __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
   __shared__ float2 As[2][BK][BM + PAD];
   __shared__ float2 Bs[2][BK][BN + PAD];
 
-  // XCD-aware remap: hardware places block i on XCD i % 8
   const int64_t nb = a.n_tiles;
-  const int64_t per = (nb + 7) / 8;
-  const int64_t bid = blockIdx.x;
-  const int64_t lin = (bid % 8) * per + bid / 8;
+  const int64_t lin = remap_tile(blockIdx.x, nb);
   if (lin >= nb) return;
   int tr, tc;
   tile_of(lin, tr, tc);
@@ -107,13 +148,16 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
   };
 
   const int64_t n_stages = (N + BK - 1) / BK;
-  gload(0);
+  const int64_t sp = (n_stages + a.ksplit - 1) / a.ksplit;
+  const int64_t st0 = blockIdx.y * sp, st1 = min(n_stages, st0 + sp);
+  const int li = lane & 15, lk = lane >> 4;
+  if (st0 < st1) {  // uniform over the group
+  gload(st0 * BK);
   sstore(0);
   __syncthreads();
-  const int li = lane & 15, lk = lane >> 4;
-  for (int64_t st = 0; st < n_stages; ++st) {
-    const int buf = (int)(st & 1);
-    if (st + 1 < n_stages) gload((st + 1) * BK);
+  for (int64_t st = st0; st < st1; ++st) {
+    const int buf = (int)((st - st0) & 1);
+    if (st + 1 < st1) gload((st + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const int n = ks * 4 + lk;
@@ -128,44 +172,90 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
         for (int j = 0; j < 2; ++j) {
           acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].x, acc[i][j][0], 0, 0, 0);
           acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].y, acc[i][j][0], 0, 0, 0);
-          acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].y, acc[i][j][1], 0, 0, 0);
-          acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(-fa[i].y, fb[j].x, acc[i][j][1], 0, 0, 0);
+          if (!REAL) {
+            acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].y, acc[i][j][1], 0, 0, 0);
+            acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(-fa[i].y, fb[j].x, acc[i][j][1], 0, 0, 0);
+          }
         }
     }
-    if (st + 1 < n_stages) {
+    if (st + 1 < st1) {
       sstore(buf ^ 1);
     }
     __syncthreads();
   }
+  }
 
+  if (a.ksplit > 1) {  // partial accumulators in register order, coalesced over threads
+    float* dst = a.part + ((int64_t)blockIdx.y * nb + lin) * (kAccPerThread * 256) + tid;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (REAL && q == 1) continue;
+            dst[(((i * 2 + j) * 2 + q) * 4 + r) * 256] = acc[i][j][q][r];
+          }
+    return;
+  }
   // epilogue: lane holds D[4 * (lane / 16) + r][lane % 16] of each block
+  herk_epilogue(a, row0, col0, wr, wc, li, lk, [&](int i, int j, int q, int r) { return (double)acc[i][j][q][r]; });
+}
+
+// adds the split partial accumulators (float64, split order) and writes S~
+template <bool REAL>
+__global__ __launch_bounds__(256) void k_herk_reduce(herk_args a) {
+  const int64_t nb = a.n_tiles;
+  const int64_t lin = remap_tile(blockIdx.x, nb);
+  if (lin >= nb) return;
+  int tr, tc;
+  tile_of(lin, tr, tc);
+  const int64_t row0 = (int64_t)tr * BM, col0 = (int64_t)tc * BN;
+  if (col0 >= a.K) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  double acc[4][2][2][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t k = row0 + wr * 64 + i * 16 + 4 * lk + r;
-        const int64_t kp = col0 + wc * 32 + j * 16 + li;
-        if (k >= K || kp >= K || kp > k) continue;
-        double re = (double)acc[i][j][0][r];
-        double im = (double)acc[i][j][1][r];
-        if (a.mode == VMC_SR_REAL) im = 0.0;
-        if (k == kp) {
-          const double2 d = make_double2(re * (1.0 + a.nu) + a.eps, 0.0);
-          a.diag[k] = d;
-          a.S[k * K + k] = d;
-        } else {
-          a.S[k * K + kp] = make_double2(re, im);
-          a.S[kp * K + k] = make_double2(re, -im);
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double s = 0.0;
+          if (!(REAL && q == 1))
+            for (int sp = 0; sp < a.ksplit; ++sp)
+              s += (double)a.part[((int64_t)sp * nb + lin) * (kAccPerThread * 256) + (((i * 2 + j) * 2 + q) * 4 + r) * 256 +
+                                  tid];
+          acc[i][j][q][r] = s;
         }
-      }
+  herk_epilogue(a, row0, col0, wr, wc, lane & 15, lane >> 4, [&](int i, int j, int q, int r) { return acc[i][j][q][r]; });
 }
 
 }  // namespace
 
+int herk_splits(int64_t N, int64_t K) {
+  const int64_t rt = (K + BM - 1) / BM;
+  const int64_t n_tiles = rt * (rt + 1);
+  const int64_t n_stages = (N + BK - 1) / BK;
+  // aim at about 1024 groups (four per compute unit), keeping at least 64 stages per split
+  int64_t s = (1024 + n_tiles - 1) / n_tiles;
+  s = std::min<int64_t>(s, n_stages / 64);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
+}
+
+size_t herk_ws_bytes(int64_t N, int64_t K) {
+  const int s = herk_splits(N, K);
+  if (s <= 1) return 0;
+  const int64_t rt = (K + BM - 1) / BM;
+  return sizeof(float) * (size_t)s * (size_t)(rt * (rt + 1)) * kAccPerThread * 256;
+}
+
 void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode, double nu, double eps, double2* S,
-                   double2* diag) {
+                   double2* diag, void* ws) {
   herk_args a{};
   a.X = X;
   a.N = N;
@@ -178,7 +268,22 @@ void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode
   a.n_row_tiles = (int)((K + BM - 1) / BM);
   const int64_t rt = a.n_row_tiles;
   a.n_tiles = rt * (rt + 1);  // row tile t holds 2t + 2 column tiles
+  a.ksplit = herk_splits(N, K);
+  a.part = (float*)ws;
+  if (a.ksplit > 1 && !ws) throw vmc_error{VMC_ERR_WORKSPACE, "internal: split Gram without workspace"};
   const int64_t grid = ((a.n_tiles + 7) / 8) * 8;
-  k_herk_mfma_f32<<<(unsigned)grid, 256, 0, ctx->stream>>>(a);
+  const dim3 g((unsigned)grid, (unsigned)a.ksplit);
+  const bool real = mode == VMC_SR_REAL;
+  if (real)
+    k_herk_mfma_f32<true><<<g, 256, 0, ctx->stream>>>(a);
+  else
+    k_herk_mfma_f32<false><<<g, 256, 0, ctx->stream>>>(a);
   VMC_HIP(hipGetLastError());
+  if (a.ksplit > 1) {
+    if (real)
+      k_herk_reduce<true><<<(unsigned)grid, 256, 0, ctx->stream>>>(a);
+    else
+      k_herk_reduce<false><<<(unsigned)grid, 256, 0, ctx->stream>>>(a);
+    VMC_HIP(hipGetLastError());
+  }
 }

@@ -425,8 +425,9 @@ struct dgemm_args {
 };
 void dgemm(vmc_ctx* ctx, const dgemm_args& g);
 // herk.hip
+size_t herk_ws_bytes(int64_t N, int64_t K);
 void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode, double nu, double eps, double2* S,
-                   double2* diag);
+                   double2* diag, void* ws);
 // chol.hip
 size_t chol_linv_bytes(int64_t K);
 int chol_block();

@@ -205,6 +205,49 @@ __global__ __launch_bounds__(64) void k_made_sample(const double* __restrict__ W
   if (lane == 0 && logq) logq[c] = lq;
 }
 
+// The same sampling with one row per lane, for narrow hidden layers (H <= HM):
+// each lane keeps its H pre-activations in registers, the weights of site d are
+// the same for every lane (scalar loads), and no cross-lane reduction is
+// needed.  Same Philox stream and decisions as k_made_sample.
+template <int HM>
+__global__ __launch_bounds__(64) void k_made_sample_lane(const double* __restrict__ W1mT,
+                                                         const double* __restrict__ W2m,
+                                                         const double* __restrict__ b1,
+                                                         const double* __restrict__ b2, int N, int H, int W,
+                                                         int64_t B, uint2 key, uint32_t lo, uint32_t hi,
+                                                         uint64_t* __restrict__ s_out, double* __restrict__ logq) {
+  const int64_t c = blockIdx.x * 64ll + threadIdx.x;
+  const bool live = c < B;
+  double a[HM];
+#pragma unroll
+  for (int k = 0; k < HM; ++k) a[k] = k < H ? b1[k] : 0.0;
+  double lq = 0.0;
+  uint64_t word = 0ull;
+  uint4 x4 = make_uint4(0, 0, 0, 0);
+  for (int d = 0; d < N; ++d) {
+    double l = 0.0;
+#pragma unroll
+    for (int k = 0; k < HM; ++k)
+      if (k < H) l = fma(W2m[(int64_t)d * H + k], fmax(a[k], 0.0), l);
+    l += b2[d];
+    if ((d & 3) == 0) x4 = philox(make_uint4((uint32_t)c, lo, hi, 1u + 256u * (uint32_t)(d >> 2)), key);
+    const double p = 1.0 / (1.0 + exp(-l));
+    const uint32_t xr = (d & 3) == 0 ? x4.x : (d & 3) == 1 ? x4.y : (d & 3) == 2 ? x4.z : x4.w;
+    const bool up = (double)xr * 0x1.0p-32 < p;
+    lq += (up ? l : 0.0) - softplus(l);
+    const double u = up ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < HM; ++k)
+      if (k < H) a[k] = fma(W1mT[(int64_t)d * H + k], u, a[k]);
+    word |= (up ? 1ull : 0ull) << (d & 63);
+    if ((d & 63) == 63 || d == N - 1) {
+      if (live) s_out[c * W + (d >> 6)] = word;
+      word = 0ull;
+    }
+  }
+  if (live && logq) logq[c] = lq;
+}
+
 struct made_ws {
   double *X, *A1, *Hd, *L, *G, *dH, *grad, *nll;
 };
@@ -283,6 +326,17 @@ void made_sample_impl(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, 
   const double* b2 = b1 + md->H + (int64_t)md->N * md->H;
   hipStream_t st = md->ctx->stream;
   const uint32_t lo = (uint32_t)counter, hi = (uint32_t)(counter >> 32);
+  if (md->H <= 64) {
+    const unsigned g = (unsigned)((B + 63) / 64);
+    if (md->H <= 32)
+      k_made_sample_lane<32><<<g, 64, 0, st>>>(md->W1mT, md->W2m, b1, b2, md->N, md->H, md->W, B, key, lo, hi, s_out,
+                                               logq);
+    else
+      k_made_sample_lane<64><<<g, 64, 0, st>>>(md->W1mT, md->W2m, b1, b2, md->N, md->H, md->W, B, key, lo, hi, s_out,
+                                               logq);
+    VMC_HIP(hipGetLastError());
+    return;
+  }
 #define MADE_LAUNCH(Q) \
   k_made_sample<Q><<<(unsigned)B, 64, 0, st>>>(md->W1mT, md->W2m, b1, b2, md->N, md->H, md->W, B, key, lo, hi, s_out, logq)
   if (QH <= 1)

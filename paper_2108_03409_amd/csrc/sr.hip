@@ -12,6 +12,8 @@
 #include <cmath>
 #include <memory>
 
+#include <type_traits>
+
 #include "internal.h"
 
 using namespace dev;
@@ -22,11 +24,13 @@ constexpr int kColChunk = 256;  // samples per partial-sum chunk
 
 template <typename InT>
 __device__ __forceinline__ double2 load_c(const InT* p, int64_t i) {
-  if constexpr (sizeof(InT) == sizeof(double2)) {
-    return ((const double2*)p)[i];
-  } else {
-    const float2 f = ((const float2*)p)[i];
+  if constexpr (std::is_same<InT, double2>::value) {
+    return p[i];
+  } else if constexpr (std::is_same<InT, float2>::value) {
+    const float2 f = p[i];
     return make_double2(f.x, f.y);
+  } else {  // real O
+    return make_double2((double)p[i], 0.0);
   }
 }
 
@@ -137,6 +141,43 @@ __global__ __launch_bounds__(256) void k_center_force(const InT* __restrict__ O,
     const double2 p = cmul(cconj(d), de);
     acc.x += wn * p.x;
     acc.y += wn * p.y;
+  }
+  Fpartial[(int64_t)blockIdx.y * K + k] = acc;
+}
+
+// Real O: two consecutive samples share one complex row of the centred matrix,
+//   Xc[m][k] = (sqrt(w_2m) (O_2m,k - mean_k), sqrt(w_2m+1) (O_2m+1,k - mean_k)),
+// so that Re(Xc^H Xc) = sum_n w_n (O_n - mean)(O_n - mean)^T with half the rows
+// (the imaginary part of that product is not S and is never formed).
+template <typename InT, typename XT>
+__global__ __launch_bounds__(256) void k_center_force_pair(const InT* __restrict__ O, const double* __restrict__ w,
+                                                           const double2* __restrict__ e, int64_t N, int64_t K,
+                                                           const double2* __restrict__ mean,
+                                                           const double* __restrict__ stats, XT* __restrict__ Xc,
+                                                           double2* __restrict__ Fpartial) {
+  const int64_t k = blockIdx.x * 256ll + threadIdx.x;
+  if (k >= K) return;
+  const int64_t n0 = (int64_t)blockIdx.y * kColChunk, n1 = min(N, n0 + kColChunk);  // n0 even
+  const double wsum = stats[0];
+  const double2 eb = make_double2(stats[1], stats[2]);
+  const double mk = mean[k].x;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t n = n0; n < n1; n += 2) {
+    double v[2] = {0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (n + h >= N) break;
+      const double wn = (w ? w[n + h] : 1.0) / wsum;
+      const double d = (double)O[(n + h) * K + k] - mk;
+      v[h] = sqrt(wn) * d;
+      const double2 de = csub(e[n + h], eb);
+      acc.x += wn * d * de.x;
+      acc.y += wn * d * de.y;
+    }
+    if constexpr (std::is_same<XT, double2>::value)
+      Xc[(n >> 1) * K + k] = make_double2(v[0], v[1]);
+    else
+      Xc[(n >> 1) * K + k] = make_float2((float)v[0], (float)v[1]);
   }
   Fpartial[(int64_t)blockIdx.y * K + k] = acc;
 }
@@ -501,10 +542,14 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   const int npart = std::max(nchunk, kchunk);
   const int CB = chol_block();
   const int nblk = (int)((K + CB - 1) / CB);
-  const bool f32 = dtype == VMC_DT_C64;
-  const size_t xsz = (f32 ? sizeof(float2) : sizeof(double2)) * (size_t)N * K;
+  const bool real_o = dtype == VMC_DT_F32 || dtype == VMC_DT_F64;
+  const bool f32 = dtype == VMC_DT_C64 || dtype == VMC_DT_F32;
+  const int64_t Nx = real_o ? (N + 1) / 2 : N;     // rows of the centred matrix (real O: sample pairs)
+  const int hmode = real_o ? VMC_SR_REAL : o->mode;  // S is real for real O
+  const size_t xsz = (f32 ? sizeof(float2) : sizeof(double2)) * (size_t)Nx * K;
   const bool split16 = o->gram == 1;
-  size_t total = (split16 ? herk16_ws_bytes(N, K) : 0) + ws_round(64) + ws_round(sizeof(double2) * npart * K) + ws_round(sizeof(double2) * K) * 7 +
+  const size_t hws = (!split16 && f32) ? herk_ws_bytes(Nx, K) : 0;
+  size_t total = (split16 ? herk16_ws_bytes(Nx, K) : 0) + ws_round(hws) + ws_round(64) + ws_round(sizeof(double2) * npart * K) + ws_round(sizeof(double2) * K) * 7 +
                  ws_round(chol_linv_bytes(K)) +
                  ws_round(xsz) + ws_round(sizeof(double2) * (size_t)K * K) + ws_round(sizeof(double) * nblk) +
                  ws_round(sizeof(long long)) + ws_round(sizeof(double) * 4);
@@ -524,23 +569,33 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   double* pivmin = (double*)ws_take(ctx, sizeof(double) * nblk);
   long long* fail = (long long*)ws_take(ctx, sizeof(long long));
   double* norms = (double*)ws_take(ctx, sizeof(double) * 4);
-  void* h16ws = split16 ? ws_take(ctx, herk16_ws_bytes(N, K)) : nullptr;
+  void* h16ws = split16 ? ws_take(ctx, herk16_ws_bytes(Nx, K)) : nullptr;
+  void* hws_p = hws ? ws_take(ctx, hws) : nullptr;
 
   std::unique_ptr<phase_scope> ph(new phase_scope(ctx, "sr.center"));
   k_energy_stats<<<1, 1024, 0, st>>>(eloc, w, N, stats);
   dim3 cg(grid_for(K, 256), nchunk);
-  if (f32) {
+  if (dtype == VMC_DT_C64)
     k_col_partial<float2><<<cg, 256, 0, st>>>((const float2*)O, w, N, K, partial);
-  } else {
+  else if (dtype == VMC_DT_C128)
     k_col_partial<double2><<<cg, 256, 0, st>>>((const double2*)O, w, N, K, partial);
-  }
+  else if (dtype == VMC_DT_F32)
+    k_col_partial<float><<<cg, 256, 0, st>>>((const float*)O, w, N, K, partial);
+  else
+    k_col_partial<double><<<cg, 256, 0, st>>>((const double*)O, w, N, K, partial);
   k_reduce_partial<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, stats, mean);
-  if (f32)
+  if (dtype == VMC_DT_C64)
     k_center_force<float2, float2><<<cg, 256, 0, st>>>((const float2*)O, w, eloc, N, K, mean, stats, (float2*)Xc,
                                                         partial);
-  else
+  else if (dtype == VMC_DT_C128)
     k_center_force<double2, double2><<<cg, 256, 0, st>>>((const double2*)O, w, eloc, N, K, mean, stats,
                                                           (double2*)Xc, partial);
+  else if (dtype == VMC_DT_F32)
+    k_center_force_pair<float, float2><<<cg, 256, 0, st>>>((const float*)O, w, eloc, N, K, mean, stats,
+                                                            (float2*)Xc, partial);
+  else
+    k_center_force_pair<double, double2><<<cg, 256, 0, st>>>((const double*)O, w, eloc, N, K, mean, stats,
+                                                              (double2*)Xc, partial);
   k_reduce_plain<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, F);
   VMC_HIP(hipGetLastError());
   ph.reset();
@@ -549,11 +604,11 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   const unsigned nb32 = (unsigned)((K + 31) / 32);
   dim3 hg(nb32, nb32);
   if (split16)
-    herk_split16(ctx, (const float2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag, h16ws);
+    herk_split16(ctx, (const float2*)Xc, Nx, K, hmode, o->nu_rel, o->eps_abs, S, diag, h16ws);
   else if (f32)
-    herk_mfma_f32(ctx, (const float2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag);
+    herk_mfma_f32(ctx, (const float2*)Xc, Nx, K, hmode, o->nu_rel, o->eps_abs, S, diag, hws_p);
   else
-    k_herk_simple<double2><<<hg, 256, 0, st>>>((const double2*)Xc, N, K, o->mode, o->nu_rel, o->eps_abs, S, diag);
+    k_herk_simple<double2><<<hg, 256, 0, st>>>((const double2*)Xc, Nx, K, hmode, o->nu_rel, o->eps_abs, S, diag);
   VMC_HIP(hipGetLastError());
   ph.reset();
 

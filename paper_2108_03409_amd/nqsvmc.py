@@ -245,7 +245,8 @@ class Model:
         B = s.shape[0]
         if out is None:
             out = torch.empty((B, self.K), dtype=dtype, device=s.device)
-        dt = DT_C128 if out.dtype == torch.complex128 else DT_C64
+        dt = {torch.complex128: DT_C128, torch.complex64: DT_C64, torch.float64: DT_F64,
+              torch.float32: DT_F32}[out.dtype]
         _check(load().vmc_grad_log_psi(self.h, _ptr(s), B, _ptr(out), dt), self.ctx.h)
         return out
 
@@ -423,9 +424,10 @@ class MADE:
 
 def sr_solve(ctx: Context, O: torch.Tensor, eloc: torch.Tensor, *, weights=None, nu_rel=1e-3, eps_abs=0.0,
              mode=SR_COMPLEX, gamma=1.0, gram=0, raise_on_error=True):
-    """Returns (x, info dict).  O: (N, K) complex64/complex128; eloc: (N,) complex128."""
+    """Returns (x, info dict).  O: (N, K) complex64/complex128, or float32/float64
+    for real log-derivatives; eloc: (N,) complex128."""
     N, K = O.shape
-    dt = DT_C128 if O.dtype == torch.complex128 else DT_C64
+    dt = {torch.complex128: DT_C128, torch.complex64: DT_C64, torch.float64: DT_F64, torch.float32: DT_F32}[O.dtype]
     x = torch.empty(K, dtype=torch.complex128, device=O.device)
     g = complex(gamma)
     opts = SROpts(nu_rel, eps_abs, mode, g.real, g.imag, gram)

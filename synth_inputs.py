@@ -143,7 +143,7 @@ def made_params(n_in: int, n_hidden: int, *, seed: int = 205) -> np.ndarray:
     return np.concatenate([w1.ravel(), b1, w2.ravel(), b2]).astype(np.float64)
 
 
-# The five workloads the library is built and measured for.  Sizes only; the
+# The workloads the library is built and measured for.  Sizes only; the
 # arithmetic lives elsewhere.
 WORKLOADS = {
     "tfim1d_L10_rbm_real": dict(
@@ -165,6 +165,14 @@ WORKLOADS = {
         net="rbm", alpha=2, is_complex=True, std=0.01, param_seed=6,
         n_chains=1024, samples_per_chain=4, sampler_seed=106, proposal="flip",
         nu_rel=1e-3),
+    # SR step with an autoregressive state and direct sampling, at the scale of
+    # the paper's SR-step benchmark (50-site periodic TFIM chain, about 1.5 k
+    # parameters, 3e5 samples): 29 hidden units give 1 529 live parameters
+    "tfim1d_L50_ar_sr": dict(
+        ham="tfim", Lx=50, Ly=1, periodic=True, J=1.0, h=1.0,
+        net="ar", hidden=29, std=0.1, param_seed=7,
+        n_chains=1000, samples_per_chain=300, sampler_seed=107, proposal="direct",
+        nu_rel=1e-3, eps_abs=1e-8),
     "tfim2d_16x16_cnn": dict(
         ham="tfim", Lx=16, Ly=16, periodic=True, J=1.0, h=3.0,
         net="cnn", channels=16, kernel=4, std=0.05, param_seed=4,

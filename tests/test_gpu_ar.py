@@ -105,6 +105,10 @@ def test_grad_matches_oracle(N, H):
     assert np.max(np.abs(O.real - ref)) < 1e-12
     O32 = m.grad_log_psi(s, torch.complex64).cpu().numpy()
     assert np.max(np.abs(O32.real - ref)) <= 2.0 ** -24 * np.abs(ref).max() + 1e-30
+    R64 = m.grad_log_psi(s, torch.float64).cpu().numpy()
+    assert np.array_equal(R64, O.real)
+    R32 = m.grad_log_psi(s, torch.float32).cpu().numpy()
+    assert np.array_equal(R32, O32.real)
 
 
 def test_direct_samples_match_oracle_stream():

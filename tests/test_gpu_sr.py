@@ -79,6 +79,51 @@ def test_sr_solve_fp32_gram_within_bound(ctx, N, Nh, ns, weighted, gram):
     assert info["residual"] < 1e-10
 
 
+@pytest.mark.parametrize("N,Nh,ns,cplx", [(10, 10, 20000, True), (20, 40, 20000, True), (20, 40, 20001, False)])
+def test_sr_solve_split_gram(ctx, N, Nh, ns, cplx):
+    # few output tiles and many samples: the Gram kernel splits the sample range
+    # and adds the float32 partial accumulators in float64
+    flush(f"sr split gram N={N} Nh={Nh} ns={ns} complex={cplx}")
+    O, el = _problem(N, Nh, ns, 0.2, seed=7 + N, cplx=cplx)
+    mode = "complex" if cplx else "real"
+    x_ref, _ = osr.sr_solve(O.astype(np.complex64).astype(np.complex128), el, nu_rel=1e-2, mode=mode)
+    x, info = V.sr_solve(ctx, torch.from_numpy(O.astype(np.complex64)).to("cuda:0"), dev_c128(el), nu_rel=1e-2,
+                         mode=V.SR_COMPLEX if cplx else V.SR_REAL)
+    x = x.cpu().numpy()
+    S, _ = osr.fisher_and_force(O, el)
+    kappa = np.linalg.cond(osr.shifted(osr.project(S, mode), 1e-2))
+    err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+    bound = kappa * 4 * (np.sqrt(ns) * 2.0 ** -24 + 2.0 ** -24) + 1e-12
+    assert err <= bound, (err, bound)
+    assert info["residual"] < 1e-10
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("N,Nh,ns,mode,weighted", [(10, 10, 1024, "real", False), (9, 21, 1001, "real", True),
+                                                   (8, 16, 301, "complex", False), (40, 60, 3001, "real", False),
+                                                   (10, 10, 40001, "real", False)])
+def test_sr_solve_real_o(ctx, N, Nh, ns, mode, weighted, dt):
+    # real log-derivatives: two samples per complex row of the centred matrix
+    # (odd sample counts leave a half-empty last row)
+    flush(f"sr real O {dt} N={N} Nh={Nh} ns={ns} mode={mode}")
+    O, el = _problem(N, Nh, ns, 0.2, seed=11 + N, cplx=False)
+    Or = O.real.astype(np.float64 if dt == "f64" else np.float32)
+    w = np.random.default_rng(5).uniform(0.5, 1.5, ns) if weighted else None
+    x_ref, info_ref = osr.sr_solve(Or.astype(np.float64).astype(np.complex128), el, nu_rel=1e-2, mode=mode,
+                                   weights=w)
+    x, info = V.sr_solve(ctx, torch.from_numpy(Or).to("cuda:0"), dev_c128(el), nu_rel=1e-2,
+                         weights=None if w is None else torch.from_numpy(w).to("cuda:0"),
+                         mode=V.SR_REAL if mode == "real" else V.SR_COMPLEX)
+    x = x.cpu().numpy()
+    S, _ = osr.fisher_and_force(Or.astype(np.float64).astype(np.complex128), el, w)
+    kappa = np.linalg.cond(osr.shifted(osr.project(S, mode), 1e-2))
+    err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+    bound = max(1e-12, 1e-13 * kappa) if dt == "f64" else kappa * 4 * (np.sqrt(ns) * 2.0 ** -24 + 2.0 ** -24) + 1e-12
+    assert err <= bound, (err, bound)
+    assert info["residual"] < 1e-10
+    assert abs(info["e_mean"] - info_ref["e_mean"]) < 1e-12 * max(1, abs(info_ref["e_mean"]))
+
+
 def test_not_pd_reported(ctx):
     O, el = _problem(12, 20, 50, 0.2, seed=8)
     x, info = V.sr_solve(ctx, dev_c128(O), dev_c128(el), nu_rel=0.0, raise_on_error=False)
