@@ -16,8 +16,11 @@
 // (shared L2).  The epilogue writes S~ (float64, projection and diagonal shift
 // applied) to the lower triangle and its conjugate to the upper triangle.
 //
-// Real mode (only Re S is used) keeps the first accumulator alone: half the
-// matrix-core work.  When the tiles alone cannot fill the chip (small K, many
+// Real mode (only Re S is used) keeps the first accumulator alone, half the
+// matrix-core work per sample; with the registers that frees it takes square
+// 128 x 128 tiles (each wave 64 x 64), so the matrix-core work per staged sample
+// and per barrier stays that of the complex tile and the operand traffic per
+// flop halves.  When the tiles alone cannot fill the chip (small K, many
 // samples) the sample range is split over blockIdx.y; each split stores its
 // float32 accumulators in register order and a second kernel adds the splits in
 // float64 (fixed order, so the result is reproducible) before the epilogue.
@@ -30,9 +33,16 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 128;  // complex rows per tile
-constexpr int BN = 64;   // complex columns per tile
 constexpr int BK = 16;   // samples per LDS stage
 constexpr int PAD = 2;   // float2 padding per LDS row
+
+// complex mode: 128 x 64 tiles, two accumulators; real mode: 128 x 128, one
+template <bool REAL>
+struct herk_shape {
+  static constexpr int BN = REAL ? 128 : 64;  // columns per tile
+  static constexpr int JN = REAL ? 4 : 2;     // 16-column blocks per wave
+  static constexpr int QN = REAL ? 1 : 2;     // accumulators per block
+};
 
 struct herk_args {
   const float2* X;  // [N][K]
@@ -47,7 +57,7 @@ struct herk_args {
   float* part;       // [ksplit][n_tiles][64][256] partial accumulators when ksplit > 1
 };
 
-constexpr int kAccPerThread = 64;  // 4 x 2 blocks x 2 accumulators x 4 values
+constexpr int kAccPerThread = 64;  // 4 x JN blocks x QN accumulators x 4 values (both modes)
 
 __device__ __forceinline__ int64_t remap_tile(int64_t bid, int64_t nb) {
   // XCD-aware remap: hardware places block i on XCD i % 8
@@ -55,22 +65,46 @@ __device__ __forceinline__ int64_t remap_tile(int64_t bid, int64_t nb) {
   return (bid % 8) * per + bid / 8;
 }
 
+// lower-triangle tile (tr, tc) of linear index b: complex mode has 2 t + 2 column
+// tiles in row tile t (cumulative t (t + 1)), real mode t + 1 (cumulative t (t + 1) / 2)
+template <bool REAL>
+__device__ __forceinline__ void tile_of(int64_t b, int& tr, int& tc) {
+  if (REAL) {
+    int t = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(t + 1) * (t + 2) / 2 <= b) ++t;
+    while ((int64_t)t * (t + 1) / 2 > b) --t;
+    tr = t;
+    tc = (int)(b - (int64_t)t * (t + 1) / 2);
+  } else {
+    int t = (int)((sqrt(4.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(t + 1) * (t + 2) <= b) ++t;
+    while ((int64_t)t * (t + 1) > b) --t;
+    tr = t;
+    tc = (int)(b - (int64_t)t * (t + 1));
+  }
+}
+
+__device__ __forceinline__ int acc_index(int i, int j, int q, int r, int JN, int QN) {
+  return ((i * JN + j) * QN + q) * 4 + r;
+}
+
 // writes one lane's values of the 16 x 16 blocks; get(i, j, q, r) returns accumulator q
-template <typename Get>
+template <bool REAL, typename Get>
 __device__ __forceinline__ void herk_epilogue(const herk_args& a, int64_t row0, int64_t col0, int wr, int wc, int li,
                                               int lk, Get get) {
+  using sh = herk_shape<REAL>;
   const int64_t K = a.K;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < sh::JN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t k = row0 + wr * 64 + i * 16 + 4 * lk + r;
-        const int64_t kp = col0 + wc * 32 + j * 16 + li;
+        const int64_t kp = col0 + wc * (16 * sh::JN) + j * 16 + li;
         if (k >= K || kp >= K || kp > k) continue;
         const double re = get(i, j, 0, r);
-        const double im = a.mode == VMC_SR_REAL ? 0.0 : get(i, j, 1, r);
+        const double im = (REAL || a.mode == VMC_SR_REAL) ? 0.0 : get(i, j, sh::QN - 1, r);
         if (k == kp) {
           const double2 d = make_double2(re * (1.0 + a.nu) + a.eps, 0.0);
           a.diag[k] = d;
@@ -82,17 +116,11 @@ __device__ __forceinline__ void herk_epilogue(const herk_args& a, int64_t row0, 
       }
 }
 
-__device__ __forceinline__ void tile_of(int64_t b, int& tr, int& tc) {
-  // row tile tr holds tiles tc = 0 .. 2 tr + 1; cumulative count tr (tr + 1)
-  int t = (int)((sqrt(4.0 * (double)b + 1.0) - 1.0) * 0.5);
-  while ((int64_t)(t + 1) * (t + 2) <= b) ++t;
-  while ((int64_t)t * (t + 1) > b) --t;
-  tr = t;
-  tc = (int)(b - (int64_t)t * (t + 1));
-}
-
 template <bool REAL>
 __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
+  using sh = herk_shape<REAL>;
+  constexpr int BN = sh::BN, JN = sh::JN, QN = sh::QN;
+  constexpr int NA = BK * BM / 256, NB = BK * BN / 256;  // float2 per thread per stage
   __shared__ float2 As[2][BK][BM + PAD];
   __shared__ float2 Bs[2][BK][BN + PAD];
 
@@ -100,7 +128,7 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
   const int64_t lin = remap_tile(blockIdx.x, nb);
   if (lin >= nb) return;
   int tr, tc;
-  tile_of(lin, tr, tc);
+  tile_of<REAL>(lin, tr, tc);
   const int64_t row0 = (int64_t)tr * BM, col0 = (int64_t)tc * BN;
   const int64_t K = a.K, N = a.N;
   if (col0 >= K) return;
@@ -108,26 +136,26 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;  // wave position in the 2 x 2 grid
 
-  floatx4 acc[4][2][2];
+  floatx4 acc[4][JN][QN];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JN; ++j)
 #pragma unroll
-      for (int q = 0; q < 2; ++q) acc[i][j][q] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int q = 0; q < QN; ++q) acc[i][j][q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  // global -> register staging: A 16 x 128 float2 (8 per thread), B 16 x 64 (4 per thread)
-  float2 ra[8], rb[4];
+  // global -> register staging of one stage: A BK x BM, B BK x BN float2
+  float2 ra[NA], rb[NB];
   auto gload = [&](int64_t n0) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < NA; ++r) {
       const int q = tid + 256 * r;
       const int nn = q / BM, cc = q % BM;
       const int64_t n = n0 + nn, c = row0 + cc;
       ra[r] = (n < N && c < K) ? a.X[n * K + c] : make_float2(0.f, 0.f);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < NB; ++r) {
       const int q = tid + 256 * r;
       const int nn = q / BN, cc = q % BN;
       const int64_t n = n0 + nn, c = col0 + cc;
@@ -136,12 +164,12 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < NA; ++r) {
       const int q = tid + 256 * r;
       As[buf][q / BM][q % BM] = ra[r];
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < NB; ++r) {
       const int q = tid + 256 * r;
       Bs[buf][q / BN][q % BN] = rb[r];
     }
@@ -152,37 +180,35 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
   const int64_t st0 = blockIdx.y * sp, st1 = min(n_stages, st0 + sp);
   const int li = lane & 15, lk = lane >> 4;
   if (st0 < st1) {  // uniform over the group
-  gload(st0 * BK);
-  sstore(0);
-  __syncthreads();
-  for (int64_t st = st0; st < st1; ++st) {
-    const int buf = (int)((st - st0) & 1);
-    if (st + 1 < st1) gload((st + 1) * BK);
-#pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
-      const int n = ks * 4 + lk;
-      float2 fa[4], fb[2];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) fa[i] = As[buf][n][wr * 64 + i * 16 + li];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) fb[j] = Bs[buf][n][wc * 32 + j * 16 + li];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].x, acc[i][j][0], 0, 0, 0);
-          acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].y, acc[i][j][0], 0, 0, 0);
-          if (!REAL) {
-            acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].y, acc[i][j][1], 0, 0, 0);
-            acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(-fa[i].y, fb[j].x, acc[i][j][1], 0, 0, 0);
-          }
-        }
-    }
-    if (st + 1 < st1) {
-      sstore(buf ^ 1);
-    }
+    gload(st0 * BK);
+    sstore(0);
     __syncthreads();
-  }
+    for (int64_t st = st0; st < st1; ++st) {
+      const int buf = (int)((st - st0) & 1);
+      if (st + 1 < st1) gload((st + 1) * BK);
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int n = ks * 4 + lk;
+        float2 fa[4], fb[JN];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fa[i] = As[buf][n][wr * 64 + i * 16 + li];
+#pragma unroll
+        for (int j = 0; j < JN; ++j) fb[j] = Bs[buf][n][wc * (16 * JN) + j * 16 + li];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < JN; ++j) {
+            acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].x, acc[i][j][0], 0, 0, 0);
+            acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].y, fb[j].y, acc[i][j][0], 0, 0, 0);
+            if constexpr (!REAL) {
+              acc[i][j][QN - 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[i].x, fb[j].y, acc[i][j][QN - 1], 0, 0, 0);
+              acc[i][j][QN - 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(-fa[i].y, fb[j].x, acc[i][j][QN - 1], 0, 0, 0);
+            }
+          }
+      }
+      if (st + 1 < st1) sstore(buf ^ 1);
+      __syncthreads();
+    }
   }
 
   if (a.ksplit > 1) {  // partial accumulators in register order, coalesced over threads
@@ -190,68 +216,72 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < JN; ++j)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < QN; ++q)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            if (REAL && q == 1) continue;
-            dst[(((i * 2 + j) * 2 + q) * 4 + r) * 256] = acc[i][j][q][r];
-          }
+          for (int r = 0; r < 4; ++r) dst[acc_index(i, j, q, r, JN, QN) * 256] = acc[i][j][q][r];
     return;
   }
   // epilogue: lane holds D[4 * (lane / 16) + r][lane % 16] of each block
-  herk_epilogue(a, row0, col0, wr, wc, li, lk, [&](int i, int j, int q, int r) { return (double)acc[i][j][q][r]; });
+  herk_epilogue<REAL>(a, row0, col0, wr, wc, li, lk,
+                      [&](int i, int j, int q, int r) { return (double)acc[i][j][q][r]; });
 }
 
 // adds the split partial accumulators (float64, split order) and writes S~
 template <bool REAL>
 __global__ __launch_bounds__(256) void k_herk_reduce(herk_args a) {
+  using sh = herk_shape<REAL>;
+  constexpr int JN = sh::JN, QN = sh::QN;
   const int64_t nb = a.n_tiles;
   const int64_t lin = remap_tile(blockIdx.x, nb);
   if (lin >= nb) return;
   int tr, tc;
-  tile_of(lin, tr, tc);
-  const int64_t row0 = (int64_t)tr * BM, col0 = (int64_t)tc * BN;
+  tile_of<REAL>(lin, tr, tc);
+  const int64_t row0 = (int64_t)tr * BM, col0 = (int64_t)tc * sh::BN;
   if (col0 >= a.K) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  double acc[4][2][2][4];
+  double acc[4][JN][QN][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JN; ++j)
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < QN; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           double s = 0.0;
-          if (!(REAL && q == 1))
-            for (int sp = 0; sp < a.ksplit; ++sp)
-              s += (double)a.part[((int64_t)sp * nb + lin) * (kAccPerThread * 256) + (((i * 2 + j) * 2 + q) * 4 + r) * 256 +
-                                  tid];
+          for (int sp = 0; sp < a.ksplit; ++sp)
+            s += (double)a.part[((int64_t)sp * nb + lin) * (kAccPerThread * 256) + acc_index(i, j, q, r, JN, QN) * 256 +
+                                tid];
           acc[i][j][q][r] = s;
         }
-  herk_epilogue(a, row0, col0, wr, wc, lane & 15, lane >> 4, [&](int i, int j, int q, int r) { return acc[i][j][q][r]; });
+  herk_epilogue<REAL>(a, row0, col0, wr, wc, lane & 15, lane >> 4,
+                      [&](int i, int j, int q, int r) { return acc[i][j][q][r]; });
+}
+
+int64_t herk_tiles(int64_t K, bool real) {
+  const int64_t rt = (K + BM - 1) / BM;
+  return real ? rt * (rt + 1) / 2 : rt * (rt + 1);
 }
 
 }  // namespace
 
-int herk_splits(int64_t N, int64_t K) {
-  const int64_t rt = (K + BM - 1) / BM;
-  const int64_t n_tiles = rt * (rt + 1);
+int herk_splits(int64_t N, int64_t K, int mode) {
+  const int64_t n_tiles = herk_tiles(K, mode == VMC_SR_REAL);
   const int64_t n_stages = (N + BK - 1) / BK;
-  // aim at about 1024 groups (four per compute unit), keeping at least 64 stages per split
-  int64_t s = (1024 + n_tiles - 1) / n_tiles;
+  // at most 1024 groups (whole rounds of resident groups, no thin last round),
+  // keeping at least 64 stages per split
+  int64_t s = 1024 / n_tiles;
   s = std::min<int64_t>(s, n_stages / 64);
   return (int)std::max<int64_t>(1, std::min<int64_t>(s, 64));
 }
 
-size_t herk_ws_bytes(int64_t N, int64_t K) {
-  const int s = herk_splits(N, K);
+size_t herk_ws_bytes(int64_t N, int64_t K, int mode) {
+  const int s = herk_splits(N, K, mode);
   if (s <= 1) return 0;
-  const int64_t rt = (K + BM - 1) / BM;
-  return sizeof(float) * (size_t)s * (size_t)(rt * (rt + 1)) * kAccPerThread * 256;
+  return sizeof(float) * (size_t)s * (size_t)herk_tiles(K, mode == VMC_SR_REAL) * kAccPerThread * 256;
 }
 
 void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode, double nu, double eps, double2* S,
@@ -266,14 +296,13 @@ void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode
   a.S = S;
   a.diag = diag;
   a.n_row_tiles = (int)((K + BM - 1) / BM);
-  const int64_t rt = a.n_row_tiles;
-  a.n_tiles = rt * (rt + 1);  // row tile t holds 2t + 2 column tiles
-  a.ksplit = herk_splits(N, K);
+  const bool real = mode == VMC_SR_REAL;
+  a.n_tiles = herk_tiles(K, real);
+  a.ksplit = herk_splits(N, K, mode);
   a.part = (float*)ws;
   if (a.ksplit > 1 && !ws) throw vmc_error{VMC_ERR_WORKSPACE, "internal: split Gram without workspace"};
   const int64_t grid = ((a.n_tiles + 7) / 8) * 8;
   const dim3 g((unsigned)grid, (unsigned)a.ksplit);
-  const bool real = mode == VMC_SR_REAL;
   if (real)
     k_herk_mfma_f32<true><<<g, 256, 0, ctx->stream>>>(a);
   else
