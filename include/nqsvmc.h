@@ -294,6 +294,45 @@ typedef struct {
 int vmc_sr_solve(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, const double* weights,
                  int64_t N, int64_t K, const vmc_sr_opts* opts, double* x, vmc_sr_info* info_host);
 
+/* The shifted system regularised through the eigendecomposition of S~
+ * (Sec. 3.3 "Pseudo-inverse" and "Eliminating noisy contributions"):
+ *   S~ = V diag(lambda) V^dagger (device Jacobi, vmc_eigh),
+ *   rho = V^dagger [[gamma F]],  x = -V diag(lambda^+) rho, where
+ *   lambda_j^+ = 1/lambda_j (0 if lambda_j = 0)                  eps_pinv = 0
+ *              = 0 if |lambda_j/lambda_1| < eps_pinv, else 1/lambda_j   hard
+ *              = 1/(lambda_j (1 + (eps_pinv/|lambda_j/lambda_1|)^6))   soft
+ * with lambda_1 the eigenvalue of largest modulus, times 1/(1 + (eps_snr /
+ * SNR_j)^6) when eps_snr > 0.  SNR_j = |rho_j| / sqrt(var_j / N) estimates the
+ * signal-to-noise ratio of the Monte Carlo mean rho_j: var_j is the weighted
+ * variance over samples of the eigen-basis components of the per-sample terms
+ * f_n = [[gamma (E_n - <E>) conj(O_n - <O>)]] whose weighted sum is [[gamma F]]
+ * (formed as V^dagger H V with H = sum_n w_n f_n f_n^dagger on the matrix cores).
+ * Same inputs, projection modes (COMPLEX or REAL) and shifts as vmc_sr_solve.
+ * info: residual = ||S~ x + [[gamma F]]|| / ||[[gamma F]]|| (not small when
+ * components are cut), min_pivot = smallest eigenvalue of S~, fail_index -1.
+ * evals (K float64, device, may be NULL): the eigenvalues (unordered);
+ * snr (K float64, device, may be NULL): SNR_j (computed whenever snr is given);
+ * *sweeps_host (may be NULL): Jacobi sweeps used.  O(K^3) per sweep: meant for
+ * K up to a few thousand (K <= 16384).                                       */
+typedef struct {
+  double eps_pinv;  /* cutoff relative to |lambda_1| (0: plain inverse of the non-zero eigenvalues) */
+  int soft;         /* 0: hard cutoff, 1: soft cutoff */
+  double eps_snr;   /* signal-to-noise cutoff (0: none) */
+  double tol;       /* Jacobi stops at ||offdiag(A)||_F <= tol ||A||_F (0: 1e-14) */
+  int max_sweeps;   /* Jacobi sweep limit (0: 50) */
+} vmc_eig_opts;
+int vmc_sr_solve_eig(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, const double* weights,
+                     int64_t N, int64_t K, const vmc_sr_opts* opts, const vmc_eig_opts* eig, double* x,
+                     vmc_sr_info* info_host, double* evals, double* snr, int* sweeps_host);
+
+/* Eigendecomposition of a Hermitian K x K complex128 matrix (row-major, both
+ * triangles, device) by parallel cyclic Jacobi rotations in float64:
+ * A = V diag(evals) V^dagger, V unitary (K x K complex128, row-major, columns
+ * are eigenvectors), evals K float64 (unordered).  A is not modified.  tol and
+ * max_sweeps as in vmc_eig_opts (0: defaults).  Synchronises the stream.     */
+int vmc_eigh(vmc_ctx* ctx, const double* A, int64_t K, double tol, int max_sweeps, double* evals, double* V,
+             int* sweeps_host);
+
 /* The same shifted system solved by conjugate gradient (the paper notes, with
  * the diagonal shift of Sec. 3.1, that the shifted equation may be solved by
  * an iterative solver such as conjugate gradient).  S is never formed: each

@@ -18,6 +18,18 @@ Readings:
     and back substitution; a non-positive pivot is reported, never repaired;
   * the factor 2 of the SR gradient is absorbed into the step size: the
     solve returns x with [[S~]] x = -[[gamma F]].
+
+Eigen-decomposition regularisations (Sec. 3.3, ``eigen_solve``): with
+S~ = V diag(lambda) V^dagger (numpy's Hermitian eigensolver as the library
+step), rho = V^dagger (-[[gamma F]]) and x = V diag(lambda^+) rho, where
+lambda^+ follows the hard cutoff (eq:pinv_cutoff), the soft cutoff, and the
+signal-to-noise factor of the "eliminating noisy contributions" subsection.
+Readings: lambda_1 is the eigenvalue of largest modulus; the cutoffs combine
+as a product of the pinv inverse and the SNR factor; a zero eigenvalue gets
+lambda^+ = 0; the SNR of rho_j is |rho_j| over the standard error of a mean of
+N_s samples, sqrt(var_j / N_s), with var_j the weighted variance of the
+eigen-basis components of the per-sample terms
+f_n = [[gamma (E_n - <E>) conj(O_n - <O>)]] whose weighted sum is [[gamma F]].
 """
 from __future__ import annotations
 
@@ -125,3 +137,49 @@ def sr_solve(O, eloc, *, nu_rel=1e-3, eps_abs=0.0, mode="complex", gamma=1.0,
     x = back_sub_h(L, forward_sub(L, rhs))
     info["residual"] = np.linalg.norm(St @ x - rhs) / max(np.linalg.norm(rhs), 1e-300)
     return x, info
+
+
+def eigen_solve(O, eloc, *, nu_rel=0.0, eps_abs=0.0, mode="complex", gamma=1.0, weights=None,
+                eps_pinv=0.0, soft=False, eps_snr=0.0):
+    """Regularised solve through the eigendecomposition of S~; returns
+    (x, info) with info['evals'] (ascending) and info['snr'] (same order)."""
+    O = np.asarray(O, dtype=np.complex128)
+    e = np.asarray(eloc, dtype=np.complex128)
+    N = O.shape[0]
+    w = _weights(N, weights)
+    S, F = fisher_and_force(O, e, weights)
+    St = shifted(project(S, mode), nu_rel, eps_abs)
+    rhs = -project(gamma * F, mode)
+    lam, V = np.linalg.eigh(St)
+    rho = V.conj().T @ rhs
+    # per-sample terms and their eigen-basis components (plain definition)
+    Ob = O - w @ O
+    dE = e - np.sum(w * e)
+    f = project(gamma * dE[:, None] * Ob.conj(), mode)       # (N, K), sum_n w_n f_n = [[gamma F]]
+    P = f @ V.conj()                                           # P_nj = sum_k f_nk conj(V_kj)
+    mean_P = w @ P
+    var = w @ (np.abs(P) ** 2) - np.abs(mean_P) ** 2
+    sig = np.sqrt(np.maximum(var, 0.0) / N)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        snr = np.where(sig > 0, np.abs(rho) / sig, np.where(np.abs(rho) > 0, np.inf, 0.0))
+    lam1 = np.max(np.abs(lam))
+    inv = np.zeros(len(lam))
+    for j, l in enumerate(lam):
+        if l == 0.0:
+            continue
+        r = abs(l) / lam1
+        if eps_pinv <= 0.0:
+            inv[j] = 1.0 / l
+        elif soft:
+            inv[j] = 1.0 / (l * (1.0 + (eps_pinv / r) ** 6))
+        else:
+            inv[j] = 0.0 if r < eps_pinv else 1.0 / l
+        if eps_snr > 0.0:
+            if snr[j] == 0.0:
+                inv[j] = 0.0
+            elif np.isfinite(snr[j]):
+                inv[j] /= 1.0 + (eps_snr / snr[j]) ** 6
+    x = V @ (inv * rho)
+    mean, evar = energy_stats(e, weights)
+    res = np.linalg.norm(St @ x - rhs) / max(np.linalg.norm(rhs), 1e-300)
+    return x, dict(evals=lam, snr=snr, rho=rho, var=var, e_mean=mean, e_var=evar, residual=res)

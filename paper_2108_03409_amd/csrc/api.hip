@@ -786,13 +786,52 @@ extern "C" int vmc_sr_solve(vmc_ctx* ctx, const void* O, int O_dtype, const doub
     VMC_REQUIRE(opts->gram == 0 || O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_F32,
                 "the split-float16 product needs float32 O (C64 or F32)");
     set_device(ctx);
-    sr_solve_impl(ctx, O, O_dtype, (const double2*)eloc, weights, N, K, opts, (double2*)x, &info);
+    sr_solve_impl(ctx, O, O_dtype, (const double2*)eloc, weights, N, K, opts, (double2*)x, &info, nullptr, nullptr,
+                  nullptr, nullptr);
     if (info.fail_index >= 0)
       throw vmc_error{VMC_ERR_NOT_PD, "shifted S is not positive definite at column " +
                                           std::to_string(info.fail_index)};
     if (!std::isfinite(info.residual)) throw vmc_error{VMC_ERR_NONFINITE, "solution is not finite"};
   });
   if (info_host) *info_host = info;
+  return rc;
+}
+
+extern "C" int vmc_sr_solve_eig(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, const double* weights,
+                                int64_t N, int64_t K, const vmc_sr_opts* opts, const vmc_eig_opts* eo, double* x,
+                                vmc_sr_info* info_host, double* evals, double* snr, int* sweeps_host) {
+  vmc_sr_info info{};
+  info.fail_index = -1;
+  info.residual = NAN;
+  int sw = 0;
+  int rc = guard(ctx, [&] {
+    VMC_REQUIRE(ctx && opts && eo, "NULL argument");
+    VMC_REQUIRE(O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_C128 || O_dtype == VMC_DT_F32 || O_dtype == VMC_DT_F64,
+                "O dtype must be C64, C128, F32 or F64");
+    VMC_REQUIRE(N >= 1 && K >= 1, "N and K must be positive");
+    VMC_REQUIRE(K <= 16384, "K above 16384 is not supported by the eigendecomposition");
+    VMC_REQUIRE(O && eloc && x, "NULL buffer");
+    VMC_REQUIRE(std::isfinite(opts->nu_rel) && opts->nu_rel >= 0 && std::isfinite(opts->eps_abs) &&
+                    opts->eps_abs >= 0,
+                "shifts must be finite and non-negative");
+    VMC_REQUIRE(opts->mode == VMC_SR_COMPLEX || opts->mode == VMC_SR_REAL || opts->mode == VMC_SR_IMAG,
+                "unknown mode");
+    if (opts->mode == VMC_SR_IMAG)
+      throw vmc_error{VMC_ERR_UNSUPPORTED, "Im S is antisymmetric; the eigen solve needs COMPLEX or REAL"};
+    VMC_REQUIRE(opts->gram == 0 || opts->gram == 1, "gram must be 0 or 1");
+    VMC_REQUIRE(opts->gram == 0 || O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_F32,
+                "the split-float16 product needs float32 O (C64 or F32)");
+    VMC_REQUIRE(std::isfinite(eo->eps_pinv) && eo->eps_pinv >= 0 && std::isfinite(eo->eps_snr) && eo->eps_snr >= 0,
+                "cutoffs must be finite and non-negative");
+    VMC_REQUIRE(eo->soft == 0 || eo->soft == 1, "soft must be 0 or 1");
+    VMC_REQUIRE(std::isfinite(eo->tol) && eo->tol >= 0 && eo->max_sweeps >= 0, "bad Jacobi settings");
+    set_device(ctx);
+    sr_solve_impl(ctx, O, O_dtype, (const double2*)eloc, weights, N, K, opts, (double2*)x, &info, eo, evals, snr,
+                  &sw);
+    if (!std::isfinite(info.residual)) throw vmc_error{VMC_ERR_NONFINITE, "solution is not finite"};
+  });
+  if (info_host) *info_host = info;
+  if (sweeps_host) *sweeps_host = sw;
   return rc;
 }
 

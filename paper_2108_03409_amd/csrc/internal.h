@@ -425,7 +425,7 @@ struct dgemm_args {
 };
 void dgemm(vmc_ctx* ctx, const dgemm_args& g);
 // herk.hip
-size_t herk_ws_bytes(int64_t N, int64_t K);
+size_t herk_ws_bytes(int64_t N, int64_t K, int mode);
 void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode, double nu, double eps, double2* S,
                    double2* diag, void* ws);
 // chol.hip
@@ -439,7 +439,12 @@ void herk_split16(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode,
                   double2* diag, void* ws);
 // sr.hip
 void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N,
-                   int64_t K, const vmc_sr_opts* o, double2* x, vmc_sr_info* info);
+                   int64_t K, const vmc_sr_opts* o, double2* x, vmc_sr_info* info, const vmc_eig_opts* eo,
+                   double* evals, double* snr, int* sweeps);
+// eig.hip
+size_t eig_ws_bytes(int64_t K);
+int eig_hermitian(vmc_ctx* ctx, const double2* S, int64_t K, double tol, int max_sweeps, double* lam, double2* V,
+                  void* ws);
 void sr_solve_cg_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N,
                       int64_t K, const vmc_sr_opts* o, double tol, int max_iter, double2* x, vmc_sr_info* info,
                       int* iters);

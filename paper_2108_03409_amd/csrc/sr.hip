@@ -532,10 +532,162 @@ __global__ void k_take_real(const double2* __restrict__ a, int64_t K, double* __
 }
 
 
+// ---- eigen-decomposition regularisation (pseudo-inverse cutoffs, SNR) ----
+
+// rho_j = sum_k conj(V_kj) b_k  (V row-major K x K)
+__global__ void k_vh_mul(const double2* __restrict__ V, const double2* __restrict__ b, int64_t K,
+                         double2* __restrict__ rho) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= K) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t k = 0; k < K; ++k) acc = cadd(acc, cmul(cconj(V[k * K + j]), b[k]));
+  rho[j] = acc;
+}
+
+// x_k = sum_j V_kj y_j, one wave per row
+__global__ __launch_bounds__(64) void k_v_mul(const double2* __restrict__ V, const double2* __restrict__ y, int64_t K,
+                                              double2* __restrict__ x) {
+  const int64_t k = blockIdx.x;
+  const int lane = threadIdx.x;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t j = lane; j < K; j += 64) acc = cadd(acc, cmul(V[k * K + j], y[j]));
+  acc = wave_sum(acc);
+  if (lane == 0) x[k] = acc;
+}
+
+// Y_nk = sqrt(w_n) conj(f_nk),  f_nk = [[gamma (E_n - Ebar) conj(O_nk - mean_k)]]: the per-sample
+// terms whose weighted sum is [[gamma F]]
+template <typename InT, typename XT>
+__global__ __launch_bounds__(256) void k_force_terms(const InT* __restrict__ O, const double* __restrict__ w,
+                                                     const double2* __restrict__ e, int64_t N, int64_t K,
+                                                     const double2* __restrict__ mean, const double* __restrict__ stats,
+                                                     double gr, double gi, int mode, XT* __restrict__ Y) {
+  const int64_t k = blockIdx.x * 256ll + threadIdx.x;
+  if (k >= K) return;
+  const int64_t n0 = (int64_t)blockIdx.y * kColChunk, n1 = min(N, n0 + kColChunk);
+  const double wsum = stats[0];
+  const double2 eb = make_double2(stats[1], stats[2]);
+  const double2 mk = mean[k];
+  for (int64_t n = n0; n < n1; ++n) {
+    const double sq = sqrt((w ? w[n] : 1.0) / wsum);
+    const double2 d = csub(load_c(O, n * K + k), mk);
+    double2 f = cmul(make_double2(gr, gi), cmul(csub(e[n], eb), cconj(d)));
+    if (mode == VMC_SR_REAL) f.y = 0.0;
+    const double2 y = make_double2(sq * f.x, -sq * f.y);
+    if constexpr (std::is_same<XT, double2>::value)
+      Y[n * K + k] = y;
+    else
+      Y[n * K + k] = make_float2((float)y.x, (float)y.y);
+  }
+}
+
+// C = A B, K x K complex float64 (row-major), 32 x 32 tiles, 4 outputs per thread
+__global__ __launch_bounds__(256) void k_zgemm_nn(const double2* __restrict__ A, const double2* __restrict__ B,
+                                                  int64_t K, double2* __restrict__ C) {
+  __shared__ double2 As[32][33], Bs[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // ty 0..7
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  double2 acc[4] = {};
+  for (int64_t k0 = 0; k0 < K; k0 += 32) {
+    for (int q = 0; q < 4; ++q) {
+      const int rr = ty + 8 * q;
+      As[rr][tx] = (r0 + rr < K && k0 + tx < K) ? A[(r0 + rr) * K + k0 + tx] : make_double2(0.0, 0.0);
+      Bs[rr][tx] = (k0 + rr < K && c0 + tx < K) ? B[(k0 + rr) * K + c0 + tx] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < 32; ++kk) {
+      const double2 b = Bs[kk][tx];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = cadd(acc[q], cmul(As[ty + 8 * q][kk], b));
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < 4; ++q) {
+    const int64_t r = r0 + ty + 8 * q, c = c0 + tx;
+    if (r < K && c < K) C[r * K + c] = acc[q];
+  }
+}
+
+// var_j = sum_k conj(V_kj) W_kj - |rho_j|^2  with W = H V (the weighted second moment
+// of the eigen-basis components of the per-sample terms, minus the squared mean)
+__global__ void k_snr_var(const double2* __restrict__ V, const double2* __restrict__ W, const double2* __restrict__ rho,
+                          int64_t K, double* __restrict__ var) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= K) return;
+  double acc = 0.0;
+  for (int64_t k = 0; k < K; ++k) {
+    const double2 v = V[k * K + j], q = W[k * K + j];
+    acc += v.x * q.x + v.y * q.y;  // Re(conj(v) q)
+  }
+  const double2 r = rho[j];
+  var[j] = acc - (r.x * r.x + r.y * r.y);
+}
+
+__global__ __launch_bounds__(1024) void k_absmax(const double* __restrict__ a, int64_t K, double* __restrict__ out) {
+  __shared__ double red[16];
+  double m = 0.0;
+  for (int64_t k = threadIdx.x; k < K; k += 1024) m = fmax(m, fabs(a[k]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int q = 0; q < 16; ++q) r = fmax(r, red[q]);
+    out[0] = r;
+  }
+}
+
+// y_j = lambda_j^+ rho_j with the regularised inverse of the eigenvalue:
+//   hard:  0 if |lambda_j / lambda_1| < eps_pinv, else 1 / lambda_j
+//   soft:  1 / (lambda_j (1 + (eps_pinv / |lambda_j / lambda_1|)^6))
+//   SNR:   times 1 / (1 + (eps_snr / SNR_j)^6),  SNR_j = |rho_j| / sqrt(var_j / N_s)
+// and lambda_j^+ = 0 for lambda_j = 0.
+__global__ void k_pinv_scale(const double* __restrict__ lam, const double* __restrict__ lmax,
+                             const double2* __restrict__ rho, const double* __restrict__ var, int64_t K, double ns,
+                             double eps_pinv, int soft, double eps_snr, double2* __restrict__ y,
+                             double* __restrict__ snr_out) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= K) return;
+  const double l = lam[j];
+  const double rel = lmax[0] > 0.0 ? fabs(l) / lmax[0] : 0.0;
+  double inv = 0.0;
+  if (l != 0.0) {
+    if (eps_pinv <= 0.0) {
+      inv = 1.0 / l;
+    } else if (soft) {
+      const double q = eps_pinv / rel;
+      const double q2 = q * q;
+      inv = 1.0 / (l * (1.0 + q2 * q2 * q2));
+    } else {
+      inv = rel < eps_pinv ? 0.0 : 1.0 / l;
+    }
+  }
+  double snr = INFINITY;
+  if (var) {
+    const double2 r = rho[j];
+    const double sig = sqrt(fmax(var[j], 0.0) / ns);
+    const double ar = sqrt(r.x * r.x + r.y * r.y);
+    snr = sig > 0.0 ? ar / sig : (ar > 0.0 ? INFINITY : 0.0);
+    if (eps_snr > 0.0) {
+      if (snr == 0.0) {
+        inv = 0.0;
+      } else if (isfinite(snr)) {
+        const double q = eps_snr / snr;
+        const double q2 = q * q;
+        inv /= 1.0 + q2 * q2 * q2;
+      }
+    }
+  }
+  if (snr_out) snr_out[j] = snr;
+  y[j] = make_double2(inv * rho[j].x, inv * rho[j].y);
+}
+
 }  // namespace
 
 void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N, int64_t K,
-                   const vmc_sr_opts* o, double2* x, vmc_sr_info* info) {
+                   const vmc_sr_opts* o, double2* x, vmc_sr_info* info, const vmc_eig_opts* eo, double* evals,
+                   double* snr, int* sweeps) {
   hipStream_t st = ctx->stream;
   const int nchunk = (int)((N + kColChunk - 1) / kColChunk);
   const int kchunk = (int)((K + 255) / 256);
@@ -548,8 +700,18 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   const int hmode = real_o ? VMC_SR_REAL : o->mode;  // S is real for real O
   const size_t xsz = (f32 ? sizeof(float2) : sizeof(double2)) * (size_t)Nx * K;
   const bool split16 = o->gram == 1;
-  const size_t hws = (!split16 && f32) ? herk_ws_bytes(Nx, K) : 0;
-  size_t total = (split16 ? herk16_ws_bytes(Nx, K) : 0) + ws_round(hws) + ws_round(64) + ws_round(sizeof(double2) * npart * K) + ws_round(sizeof(double2) * K) * 7 +
+  const bool eig = eo != nullptr;
+  const bool use_snr = eig && (eo->eps_snr > 0.0 || snr);
+  const size_t hws = (!split16 && f32) ? std::max(herk_ws_bytes(Nx, K, hmode),
+                                                  use_snr ? herk_ws_bytes(N, K, o->mode) : (size_t)0)
+                                       : 0;
+  const size_t ysz = use_snr ? (f32 ? sizeof(float2) : sizeof(double2)) * (size_t)N * K : 0;
+  const size_t kk = sizeof(double2) * (size_t)K * K;
+  const size_t eig_extra = eig ? ws_round(eig_ws_bytes(K)) + ws_round(kk) + ws_round(sizeof(double) * K) * 3 +
+                                     ws_round(sizeof(double2) * K) * 2 + ws_round(64) +
+                                     (use_snr ? ws_round(ysz) + ws_round(kk) : 0)
+                               : 0;
+  size_t total = eig_extra + (split16 ? herk16_ws_bytes(Nx, K) : 0) + ws_round(hws) + ws_round(64) + ws_round(sizeof(double2) * npart * K) + ws_round(sizeof(double2) * K) * 7 +
                  ws_round(chol_linv_bytes(K)) +
                  ws_round(xsz) + ws_round(sizeof(double2) * (size_t)K * K) + ws_round(sizeof(double) * nblk) +
                  ws_round(sizeof(long long)) + ws_round(sizeof(double) * 4);
@@ -571,6 +733,16 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   double* norms = (double*)ws_take(ctx, sizeof(double) * 4);
   void* h16ws = split16 ? ws_take(ctx, herk16_ws_bytes(Nx, K)) : nullptr;
   void* hws_p = hws ? ws_take(ctx, hws) : nullptr;
+  void* eig_ws = eig ? ws_take(ctx, eig_ws_bytes(K)) : nullptr;
+  double2* Vm = eig ? (double2*)ws_take(ctx, kk) : nullptr;
+  double* lam = eig ? (double*)ws_take(ctx, sizeof(double) * K) : nullptr;
+  double* var = eig ? (double*)ws_take(ctx, sizeof(double) * K) : nullptr;
+  double* snr_d = eig ? (double*)ws_take(ctx, sizeof(double) * K) : nullptr;
+  double2* rho = eig ? (double2*)ws_take(ctx, sizeof(double2) * K) : nullptr;
+  double2* yv2 = eig ? (double2*)ws_take(ctx, sizeof(double2) * K) : nullptr;
+  double* lmax = eig ? (double*)ws_take(ctx, 64) : nullptr;
+  void* Ysnr = use_snr ? ws_take(ctx, ysz) : nullptr;
+  double2* Hm = use_snr ? (double2*)ws_take(ctx, kk) : nullptr;
 
   std::unique_ptr<phase_scope> ph(new phase_scope(ctx, "sr.center"));
   k_energy_stats<<<1, 1024, 0, st>>>(eloc, w, N, stats);
@@ -611,6 +783,80 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
     k_herk_simple<double2><<<hg, 256, 0, st>>>((const double2*)Xc, Nx, K, hmode, o->nu_rel, o->eps_abs, S, diag);
   VMC_HIP(hipGetLastError());
   ph.reset();
+
+  if (eig) {
+    info->fail_index = -1;
+    // second moment of the per-sample force terms (SNR): H = Y^H Y
+    if (use_snr) {
+      ph.reset(new phase_scope(ctx, "sr.snr"));
+      const int fmode = o->mode == VMC_SR_REAL ? VMC_SR_REAL : VMC_SR_COMPLEX;
+      if (dtype == VMC_DT_C64)
+        k_force_terms<float2, float2><<<cg, 256, 0, st>>>((const float2*)O, w, eloc, N, K, mean, stats, o->gamma_re,
+                                                           o->gamma_im, o->mode, (float2*)Ysnr);
+      else if (dtype == VMC_DT_F32)
+        k_force_terms<float, float2><<<cg, 256, 0, st>>>((const float*)O, w, eloc, N, K, mean, stats, o->gamma_re,
+                                                          o->gamma_im, o->mode, (float2*)Ysnr);
+      else if (dtype == VMC_DT_C128)
+        k_force_terms<double2, double2><<<cg, 256, 0, st>>>((const double2*)O, w, eloc, N, K, mean, stats,
+                                                             o->gamma_re, o->gamma_im, o->mode, (double2*)Ysnr);
+      else
+        k_force_terms<double, double2><<<cg, 256, 0, st>>>((const double*)O, w, eloc, N, K, mean, stats, o->gamma_re,
+                                                            o->gamma_im, o->mode, (double2*)Ysnr);
+      VMC_HIP(hipGetLastError());
+      if (f32)
+        herk_mfma_f32(ctx, (const float2*)Ysnr, N, K, fmode, 0.0, 0.0, Hm, rho, hws_p);
+      else
+        k_herk_simple<double2><<<hg, 256, 0, st>>>((const double2*)Ysnr, N, K, fmode, 0.0, 0.0, Hm, rho);
+      VMC_HIP(hipGetLastError());
+      ph.reset();
+    }
+    ph.reset(new phase_scope(ctx, "sr.eig"));
+    const int sw = eig_hermitian(ctx, S, K, eo->tol > 0.0 ? eo->tol : 1e-14, eo->max_sweeps > 0 ? eo->max_sweeps : 50,
+                                 lam, Vm, eig_ws);
+    if (sweeps) *sweeps = sw;
+    ph.reset();
+    ph.reset(new phase_scope(ctx, "sr.trsv"));
+    k_rhs<<<grid_for(K, 256), 256, 0, st>>>(F, K, o->gamma_re, o->gamma_im, o->mode, rhs);
+    k_vh_mul<<<grid_for(K, 256), 256, 0, st>>>(Vm, rhs, K, rho);
+    if (use_snr) {
+      double2* Wm = (double2*)eig_ws;  // the Jacobi workspace is free again
+      const dim3 gg((unsigned)((K + 31) / 32), (unsigned)((K + 31) / 32));
+      k_zgemm_nn<<<gg, 256, 0, st>>>(Hm, Vm, K, Wm);
+      k_snr_var<<<grid_for(K, 256), 256, 0, st>>>(Vm, Wm, rho, K, var);
+    }
+    k_absmax<<<1, 1024, 0, st>>>(lam, K, lmax);
+    k_pinv_scale<<<grid_for(K, 256), 256, 0, st>>>(lam, lmax, rho, use_snr ? var : nullptr, K, (double)N,
+                                                   eo->eps_pinv, eo->soft, eo->eps_snr, yv2, snr_d);
+    k_v_mul<<<(unsigned)K, 64, 0, st>>>(Vm, yv2, K, sol);
+    VMC_HIP(hipGetLastError());
+    ph.reset();
+    if (evals) VMC_HIP(hipMemcpyAsync(evals, lam, sizeof(double) * K, hipMemcpyDeviceToDevice, st));
+    if (snr) VMC_HIP(hipMemcpyAsync(snr, snr_d, sizeof(double) * K, hipMemcpyDeviceToDevice, st));
+    // residual of the regularised solution against the unregularised (shifted) system
+    ph.reset(new phase_scope(ctx, "sr.resid"));
+    VMC_HIP(hipMemcpyAsync(res, rhs, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
+    k_resid_upper<<<(unsigned)K, 64, 0, st>>>(S, K, diag, sol, res);
+    k_resid_lower_part<<<dim3(grid_for(K, 256), kchunk), 256, 0, st>>>(S, K, sol, partial);
+    k_resid_finish<<<grid_for(K, 256), 256, 0, st>>>(partial, kchunk, K, rhs, res);
+    k_norms<<<1, 1024, 0, st>>>(res, rhs, K, norms);
+    VMC_HIP(hipMemcpyAsync(x, sol, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
+    VMC_HIP(hipGetLastError());
+    ph.reset();
+    const size_t hb = sizeof(double) * (6 + K);
+    double* hh = (double*)pinned_host(ctx, hb);
+    VMC_HIP(hipMemcpyAsync(hh, norms, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+    VMC_HIP(hipMemcpyAsync(hh + 2, stats, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+    VMC_HIP(hipMemcpyAsync(hh + 6, lam, sizeof(double) * K, hipMemcpyDeviceToHost, st));
+    VMC_HIP(hipStreamSynchronize(st));
+    info->residual = hh[1] > 0 ? std::sqrt(hh[0] / hh[1]) : std::sqrt(hh[0]);
+    info->e_mean[0] = hh[3];
+    info->e_mean[1] = hh[4];
+    info->e_var = hh[5];
+    double pm = INFINITY;
+    for (int64_t j = 0; j < K; ++j) pm = std::min(pm, hh[6 + j]);
+    info->min_pivot = pm;  // smallest eigenvalue of the shifted S
+    return;
+  }
 
   ph.reset(new phase_scope(ctx, "sr.chol"));
   k_init_fail<<<1, 1, 0, st>>>(fail);

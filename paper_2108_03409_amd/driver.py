@@ -71,11 +71,14 @@ class TDVP:
 
     def __init__(self, ctx: V.Context, model: V.Model, ham: V.Hamiltonian, theta: torch.Tensor, *,
                  real_time: bool = True, eps_abs: float = 1e-8, nu_rel: float = 0.0, exact_states=None,
-                 sampler: V.Sampler | None = None, n_samples: int = 0, mode: int = V.SR_COMPLEX):
+                 sampler: V.Sampler | None = None, n_samples: int = 0, mode: int = V.SR_COMPLEX,
+                 eps_pinv: float = 0.0, soft_pinv: bool = True, eps_snr: float = 0.0):
         self.ctx, self.model, self.ham = ctx, model, ham
         self.theta = theta.to(torch.complex128).contiguous()
         self.gamma = 1j if real_time else 1.0
         self.eps_abs, self.nu_rel, self.mode = eps_abs, nu_rel, mode
+        # eigen-decomposition regularisation (Sec. 3.3) when a cutoff is set
+        self.eps_pinv, self.soft_pinv, self.eps_snr = eps_pinv, soft_pinv, eps_snr
         self.states = exact_states  # device (2^N, W) int64 or None
         self.sampler, self.n_samples = sampler, n_samples
         self.t = 0.0
@@ -94,8 +97,13 @@ class TDVP:
         s, w = self._batch()
         O = self.model.grad_log_psi(s, torch.complex128)
         el = self.model.local_energy(self.ham, s)
-        x, info = V.sr_solve(self.ctx, O, el, weights=w, nu_rel=self.nu_rel, eps_abs=self.eps_abs, mode=self.mode,
-                             gamma=self.gamma)
+        if self.eps_pinv > 0.0 or self.eps_snr > 0.0:
+            x, info = V.sr_solve_eig(self.ctx, O, el, weights=w, nu_rel=self.nu_rel, eps_abs=self.eps_abs,
+                                     mode=self.mode, gamma=self.gamma, eps_pinv=self.eps_pinv, soft=self.soft_pinv,
+                                     eps_snr=self.eps_snr)
+        else:
+            x, info = V.sr_solve(self.ctx, O, el, weights=w, nu_rel=self.nu_rel, eps_abs=self.eps_abs,
+                                 mode=self.mode, gamma=self.gamma)
         self.last_info = info
         return x
 

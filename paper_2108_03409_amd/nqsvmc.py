@@ -49,6 +49,11 @@ class CGOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int)]
 
 
+class EigOpts(C.Structure):
+    _fields_ = [("eps_pinv", C.c_double), ("soft", C.c_int), ("eps_snr", C.c_double), ("tol", C.c_double),
+                ("max_sweeps", C.c_int)]
+
+
 class SRInfo(C.Structure):
     _fields_ = [("e_mean", C.c_double * 2), ("e_var", C.c_double), ("residual", C.c_double),
                 ("min_pivot", C.c_double), ("fail_index", C.c_int64)]
@@ -94,6 +99,9 @@ _SIGS = {
     "vmc_sr_solve": ([P, P, C.c_int, P, P, I64, I64, C.POINTER(SROpts), P, C.POINTER(SRInfo)], C.c_int),
     "vmc_sr_solve_cg": ([P, P, C.c_int, P, P, I64, I64, C.POINTER(SROpts), C.POINTER(CGOpts), P, C.POINTER(SRInfo),
                          C.POINTER(C.c_int)], C.c_int),
+    "vmc_sr_solve_eig": ([P, P, C.c_int, P, P, I64, I64, C.POINTER(SROpts), C.POINTER(EigOpts), P,
+                          C.POINTER(SRInfo), P, P, C.POINTER(C.c_int)], C.c_int),
+    "vmc_eigh": ([P, P, I64, C.c_double, C.c_int, P, P, C.POINTER(C.c_int)], C.c_int),
     "vmc_made_create": ([P, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_made_num_params": ([P, C.POINTER(I64)], C.c_int),
     "vmc_made_set_params": ([P, P], C.c_int),
@@ -460,6 +468,44 @@ def sr_solve_cg(ctx: Context, O: torch.Tensor, eloc: torch.Tensor, *, weights=No
     if rc != VMC_OK and raise_on_error:
         _check(rc, ctx.h)
     return (x if rc == VMC_OK else None), d
+
+
+def sr_solve_eig(ctx: Context, O: torch.Tensor, eloc: torch.Tensor, *, weights=None, nu_rel=0.0, eps_abs=0.0,
+                 mode=SR_COMPLEX, gamma=1.0, gram=0, eps_pinv=0.0, soft=False, eps_snr=0.0, want_snr=False,
+                 tol=0.0, max_sweeps=0, raise_on_error=True):
+    """The TDVP / SR equation regularised through the eigendecomposition of S~
+    (pseudo-inverse cutoffs, signal-to-noise filter).  Returns (x, info) with
+    info['evals'] (device, unordered), info['snr'] (device or None), info['sweeps']."""
+    N, K = O.shape
+    dt = {torch.complex128: DT_C128, torch.complex64: DT_C64, torch.float64: DT_F64, torch.float32: DT_F32}[O.dtype]
+    dev = O.device
+    x = torch.empty(K, dtype=torch.complex128, device=dev)
+    ev = torch.empty(K, dtype=torch.float64, device=dev)
+    snr = torch.empty(K, dtype=torch.float64, device=dev) if (want_snr or eps_snr > 0) else None
+    g = complex(gamma)
+    opts = SROpts(nu_rel, eps_abs, mode, g.real, g.imag, gram)
+    eo = EigOpts(eps_pinv, int(bool(soft)), eps_snr, tol, max_sweeps)
+    info = SRInfo()
+    sw = C.c_int()
+    rc = load().vmc_sr_solve_eig(ctx.h, _ptr(O), dt, _ptr(eloc), _ptr(weights), N, K, C.byref(opts), C.byref(eo),
+                                 _ptr(x), C.byref(info), _ptr(ev), _ptr(snr), C.byref(sw))
+    d = dict(e_mean=complex(info.e_mean[0], info.e_mean[1]), e_var=info.e_var, residual=info.residual,
+             min_eval=info.min_pivot, evals=ev, snr=snr, sweeps=sw.value, status=ERRORS.get(rc, "OK") if rc else "OK")
+    if rc != VMC_OK and raise_on_error:
+        _check(rc, ctx.h)
+    return (x if rc == VMC_OK else None), d
+
+
+def eigh(ctx: Context, A: torch.Tensor, *, tol=0.0, max_sweeps=0):
+    """Hermitian eigendecomposition on the device: (evals (K,) float64 unordered,
+    V (K, K) complex128 with eigenvectors as columns, sweeps)."""
+    K = A.shape[0]
+    A = A.to(torch.complex128).contiguous()
+    ev = torch.empty(K, dtype=torch.float64, device=A.device)
+    V = torch.empty((K, K), dtype=torch.complex128, device=A.device)
+    sw = C.c_int()
+    _check(load().vmc_eigh(ctx.h, _ptr(A), K, tol, max_sweeps, _ptr(ev), _ptr(V), C.byref(sw)), ctx.h)
+    return ev, V, sw.value
 
 
 class NQSLogPsi(torch.autograd.Function):

@@ -1,0 +1,150 @@
+"""Device Hermitian eigensolver and the eigen-decomposition regularisations of
+the TDVP equation (pseudo-inverse cutoffs, signal-to-noise filter; Sec. 3.3)
+through the C ABI, against numpy's eigensolver and oracle.sr.eigen_solve."""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import rbm as orbm, eloc as oeloc, sr as osr
+from gpu_common import DEV, dev_c128, flush
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2108_03409_amd import nqsvmc as V  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return V.Context(0)
+
+
+def _hermitian(K, seed, spread=6.0, cplx=True):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(K + 3, K)) + (1j * rng.normal(size=(K + 3, K)) if cplx else 0.0)
+    X = X * np.logspace(0, -spread / 2, K)
+    return X.conj().T @ X
+
+
+@pytest.mark.parametrize("K,cplx", [(1, True), (2, True), (7, True), (64, False), (333, True), (1000, True)])
+def test_eigh_matches_numpy(ctx, K, cplx):
+    flush(f"eigh K={K}")
+    A = _hermitian(K, seed=K, cplx=cplx)
+    ev, Vm, sweeps = V.eigh(ctx, dev_c128(A))
+    ev, Vm = ev.cpu().numpy(), Vm.cpu().numpy()
+    ref = np.linalg.eigvalsh(A)
+    nrm = np.abs(ref).max()
+    assert np.max(np.abs(np.sort(ev) - ref)) <= 1e-12 * nrm
+    assert np.linalg.norm((Vm * ev) @ Vm.conj().T - A) <= 1e-12 * np.linalg.norm(A)
+    assert np.linalg.norm(Vm.conj().T @ Vm - np.eye(K)) <= 1e-11
+    assert sweeps <= 20
+
+
+def _problem(N, Nh, ns, std, seed, cplx=True):
+    p = si.rbm_params(N, Nh, std=std, is_complex=cplx, seed=seed)
+    bits = si.random_bits(ns, N, seed=seed + 1)
+    O = orbm.grad_log_psi(p, bits, Nh)
+    el = oeloc.local_energy(lambda x: orbm.log_psi(p, x, Nh), "tfim", bits, N, 1, True, 1.0, 1.0)
+    return O, el
+
+
+def _cut_between(O, el, mode, nu, frac):
+    """a relative cutoff halfway (geometrically) between two eigenvalue ratios"""
+    S, _ = osr.fisher_and_force(O, el)
+    lam = np.linalg.eigvalsh(osr.shifted(osr.project(S, mode), nu, 0.0))
+    r = np.sort(np.abs(lam) / np.abs(lam).max())
+    j = int(frac * len(r))
+    return float(np.sqrt(r[j] * r[j + 1]))
+
+
+CASES = [
+    # N, Nh, ns, mode, gamma, nu, pinv (frac or 0), soft, snr, weighted
+    (8, 16, 400, "complex", 1.0, 1e-3, 0.0, False, 0.0, False),   # no cutoff: the Cholesky solution
+    (8, 16, 400, "complex", 1.0, 0.0, 0.3, False, 0.0, False),    # hard cutoff
+    (8, 16, 400, "complex", 1j, 0.0, 0.3, True, 0.0, True),       # soft cutoff, real time, weighted
+    (10, 10, 1000, "real", 1.0, 0.0, 0.2, True, 2.0, False),      # soft + SNR, real projection
+    (12, 20, 3000, "complex", 1j, 0.0, 0.0, False, 1.5, False),   # SNR only (K = 272)
+]
+
+
+@pytest.mark.parametrize("N,Nh,ns,mode,gamma,nu,frac,soft,snr,weighted", CASES)
+def test_sr_solve_eig_matches_oracle(ctx, N, Nh, ns, mode, gamma, nu, frac, soft, snr, weighted):
+    flush(f"sr eig N={N} Nh={Nh} ns={ns} mode={mode} gamma={gamma} frac={frac} soft={soft} snr={snr}")
+    O, el = _problem(N, Nh, ns, 0.2, seed=N * Nh + 1, cplx=(mode != "real"))
+    w = np.random.default_rng(9).uniform(0.5, 1.5, ns) if weighted else None
+    eps = _cut_between(O, el, mode, nu, frac) if frac > 0 else 0.0
+    x_ref, info_ref = osr.eigen_solve(O, el, nu_rel=nu, mode=mode, gamma=gamma, weights=w, eps_pinv=eps, soft=soft,
+                                      eps_snr=snr)
+    x, info = V.sr_solve_eig(ctx, dev_c128(O), dev_c128(el), weights=None if w is None else
+                             torch.from_numpy(w).to(DEV), nu_rel=nu, mode=V.SR_REAL if mode == "real" else V.SR_COMPLEX,
+                             gamma=gamma, eps_pinv=eps, soft=soft, eps_snr=snr, want_snr=True)
+    x = x.cpu().numpy()
+    ev = np.sort(info["evals"].cpu().numpy())
+    assert np.max(np.abs(ev - info_ref["evals"])) <= 1e-12 * np.abs(info_ref["evals"]).max()
+    lam = info_ref["evals"]
+    # conditioning of the kept part bounds the error of x
+    kept = np.abs(lam) >= max(eps, 1e-300) * np.abs(lam).max()
+    kappa = np.abs(lam).max() / np.abs(lam[kept]).min()
+    err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+    assert err <= max(1e-11, 1e-14 * kappa * 100), (err, kappa)
+    if snr > 0 or True:
+        s_ref = np.sort(info_ref["snr"])
+        s_got = np.sort(info["snr"].cpu().numpy())
+        fin = np.isfinite(s_ref)
+        assert np.allclose(s_got[fin], s_ref[fin], rtol=1e-8, atol=1e-12)
+    assert abs(info["e_mean"] - info_ref["e_mean"]) < 1e-12 * max(1, abs(info_ref["e_mean"]))
+    assert abs(info["residual"] - info_ref["residual"]) <= 1e-8 + 1e-6 * info_ref["residual"]
+
+
+def test_sr_solve_eig_real_o_float32(ctx):
+    # real log-derivatives in float32: S from the matrix cores, eigen solve in float64
+    flush("sr eig real O f32")
+    O, el = _problem(10, 10, 2001, 0.2, seed=31, cplx=False)
+    Or = O.real.astype(np.float32)
+    x_ref, info_ref = osr.eigen_solve(Or.astype(np.float64).astype(np.complex128), el, nu_rel=1e-2, mode="real",
+                                      eps_pinv=1e-6, soft=True)
+    x, info = V.sr_solve_eig(ctx, torch.from_numpy(Or).to(DEV), dev_c128(el), nu_rel=1e-2, mode=V.SR_REAL,
+                             eps_pinv=1e-6, soft=True)
+    x = x.cpu().numpy()
+    lam = info_ref["evals"]
+    kappa = np.abs(lam).max() / np.abs(lam).min()
+    err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+    assert err <= kappa * 4 * (np.sqrt(2001) * 2.0 ** -24 + 2.0 ** -24) + 1e-12
+
+
+def test_pinv_tdvp_follows_exact_evolution(ctx):
+    # exact TDVP (all 2^6 configurations) with the soft pseudo-inverse instead of
+    # an additive shift: the cutoff only removes directions that do not change psi
+    import scipy.linalg as sla
+    from kron_ref import tfim as kron_tfim, code_to_kron
+    from oracle.eloc import all_states
+    from gpu_common import dev_bits
+    from paper_2108_03409_amd.driver import TDVP
+    flush("real-time TDVP with the soft pseudo-inverse, N = 6")
+    N, Nh, h, T, dt = 6, 12, 1.0, 0.3, 0.005
+    model = V.Model.rbm(ctx, N, Nh, True)
+    ham = V.Hamiltonian.tfim(ctx, N, 1, True, 1.0, h)
+    p0 = si.rbm_params(N, Nh, std=0.15, is_complex=True, seed=21)
+    states = all_states(N)
+    s_dev = dev_bits(si.pack_bits(states))
+    tdvp = TDVP(ctx, model, ham, torch.from_numpy(p0.astype(np.complex128)).to(DEV), real_time=True, eps_abs=0.0,
+                exact_states=s_dev, eps_pinv=1e-8, soft_pinv=True)
+    for _ in range(int(round(T / dt))):
+        tdvp.step(dt, "heun")
+    codes = (states.astype(np.int64) << np.arange(N)).sum(1)
+    idx = code_to_kron(codes, N)
+
+    def vec(p):
+        v = np.zeros(2 ** N, dtype=complex)
+        v[idx] = np.exp(orbm.log_psi(p, states, Nh))
+        return v / np.linalg.norm(v)
+
+    Hk = kron_tfim(N, 1, True, 1.0, h).toarray()
+    v_exact = sla.expm(-1j * T * Hk) @ vec(p0)
+    v_t = vec(tdvp.theta.cpu().numpy())
+    fid = abs(np.vdot(v_exact, v_t)) ** 2
+    flush(f"  fidelity {fid:.8f}")
+    assert fid > 0.9999

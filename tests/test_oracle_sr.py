@@ -150,3 +150,94 @@ def test_package_ess_matches_oracle_and_ar1():
     assert abs(t1 - t2) < 1e-8
     exact = (1 + rho) / (2 * (1 - rho))
     assert abs(t1 - exact) < 0.15 * exact
+
+
+# ---- eigen-decomposition regularisations (Sec. 3.3) ----
+
+def _eig_problem(ns=400, K=12, seed=3, cplx=True):
+    rng = np.random.default_rng(seed)
+    O = rng.normal(size=(ns, K)) + (1j * rng.normal(size=(ns, K)) if cplx else 0.0)
+    O = O * np.logspace(0, -3, K)            # spread the spectrum of S
+    e = rng.normal(size=ns) + 1j * rng.normal(size=ns) * 0.3 + O[:, 0].real
+    return O, e
+
+
+def test_eigen_solve_without_cutoff_is_the_cholesky_solve():
+    O, e = _eig_problem()
+    for mode, gamma in [("complex", 1.0), ("real", 1.0), ("complex", 1j)]:
+        x_e, _ = sr.eigen_solve(O, e, nu_rel=1e-3, mode=mode, gamma=gamma)
+        x_c, _ = sr.sr_solve(O, e, nu_rel=1e-3, mode=mode, gamma=gamma)
+        assert np.linalg.norm(x_e - x_c) <= 1e-10 * np.linalg.norm(x_c)
+
+
+def test_hard_cutoff_equals_library_pseudo_inverse():
+    # numpy's pinv (singular values of the Hermitian matrix, relative cutoff) is an
+    # independent route to the truncated inverse of eq:pinv_cutoff
+    O, e = _eig_problem(seed=4)
+    S, F = sr.fisher_and_force(O, e)
+    lam = np.linalg.eigvalsh(S)
+    r = np.abs(lam) / np.abs(lam).max()
+    eps = np.sqrt(r[3] * r[4])                 # strictly between two eigenvalue ratios
+    x, info = sr.eigen_solve(O, e, eps_pinv=eps)
+    x_ref = np.linalg.pinv(S, rcond=eps, hermitian=True) @ (-F)
+    assert np.linalg.norm(x - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+    assert info["residual"] > 1e-6             # components were dropped
+
+
+def test_soft_cutoff_values():
+    # one eigen-direction at |lambda / lambda_1| = eps / 2: weight 1 / (1 + 2^6) of 1/lambda
+    rng = np.random.default_rng(5)
+    K = 6
+    Q, _ = np.linalg.qr(rng.normal(size=(K, K)) + 1j * rng.normal(size=(K, K)))
+    d = np.array([1.0, 0.5, 0.1, 1e-2, 1e-3, 1e-4])
+    S = (Q * d) @ Q.conj().T
+    # samples with exactly this S: rows sqrt(K) * sqrt(d_j) q_j^dagger with signs, mean zero
+    O = np.concatenate([np.sqrt(K) * (Q * np.sqrt(d)).conj().T, -np.sqrt(K) * (Q * np.sqrt(d)).conj().T])
+    e = np.concatenate([np.ones(K), -np.ones(K)])
+    S_o, F_o = sr.fisher_and_force(O, e)
+    assert np.allclose(S_o, S, atol=1e-13)
+    eps = 2e-2                                  # lambda_4 / lambda_1 = 1e-2 = eps / 2
+    x, info = sr.eigen_solve(O, e, eps_pinv=eps, soft=True)
+    lam, V = np.linalg.eigh(S_o)
+    rho = V.conj().T @ (-F_o)
+    y = V.conj().T @ x
+    for j in range(K):
+        want = 1.0 / (lam[j] * (1.0 + (eps / (abs(lam[j]) / lam.max())) ** 6))
+        assert abs(y[j] - want * rho[j]) <= 1e-9 * abs(rho[j] / lam[j]) + 1e-14
+    j4 = np.argmin(np.abs(lam - 1e-2))
+    assert abs(y[j4] / (rho[j4] / lam[j4]) - 1.0 / 65.0) < 1e-9
+    assert abs(abs(y[np.argmin(np.abs(lam - 0.1))] / (rho[np.argmin(np.abs(lam - 0.1))] / 0.1)) - 1.0) < 1e-4
+
+
+def test_snr_estimate_and_zero_signal():
+    O, e = _eig_problem(ns=3000, K=5, seed=6)
+    x, info = sr.eigen_solve(O, e, eps_snr=1.0)
+    # the variance is the plain (ddof 0) variance of the per-sample eigen components
+    S, F = sr.fisher_and_force(O, e)
+    lam, V = np.linalg.eigh(S)
+    Ob = O - O.mean(0)
+    f = (e - e.mean())[:, None] * Ob.conj()
+    P = f @ V.conj()
+    assert np.allclose(info["var"], np.var(P, axis=0), rtol=1e-10)
+    assert np.allclose(np.abs(info["rho"]), np.abs(P.mean(0)), rtol=1e-10)
+    # replicas (K = 1, so the eigen-basis is fixed): the standard error predicts
+    # the spread of rho over independent sample sets
+    rng = np.random.default_rng(7)
+    rhos, sigs = [], []
+    for _ in range(400):
+        Orep = rng.normal(size=(300, 1)) + 1j * rng.normal(size=(300, 1))
+        erep = 0.5 * Orep[:, 0].real + rng.normal(size=300)
+        _, inf = sr.eigen_solve(Orep, erep)
+        rhos.append(inf["rho"][0])
+        sigs.append(np.abs(inf["rho"][0]) / inf["snr"][0])
+    spread = np.std(np.array(rhos))
+    assert abs(np.mean(sigs) / spread - 1.0) < 0.12
+    # a component with exactly zero signal has SNR 0 and is dropped
+    O2 = np.zeros((4, 2), dtype=complex)
+    O2[:, 0] = [1, -1, 1, -1]
+    O2[:, 1] = [1, 1, -1, -1]
+    e2 = np.array([1.0, -1.0, 1.0, -1.0])       # correlated with column 0 only
+    x2, inf2 = sr.eigen_solve(O2, e2, eps_snr=0.5)
+    assert np.min(inf2["snr"]) == 0.0
+    y2 = np.linalg.eigh(sr.fisher_and_force(O2, e2)[0])[1].conj().T @ x2
+    assert abs(y2[np.argmin(inf2["snr"])]) == 0.0
