@@ -325,6 +325,14 @@ int vmc_sr_solve_eig(vmc_ctx* ctx, const void* O, int O_dtype, const double* elo
                      int64_t N, int64_t K, const vmc_sr_opts* opts, const vmc_eig_opts* eig, double* x,
                      vmc_sr_info* info_host, double* evals, double* snr, int* sweeps_host);
 
+/* Quadratic form of the (unshifted) quantum Fisher matrix, eq:qfm:
+ *   *out_host = v^dagger S v = sum_n w_n |(O_n - <O>) . v|^2   (weights normalised;
+ *   NULL = uniform), computed from the samples without forming S (the step-size
+ * control of the adaptive integrator measures changes in this norm, Sec. 4.3
+ * "Stepper").  O as in vmc_sr_solve; v: K complex128 (device).  Synchronises. */
+int vmc_fisher_quad(vmc_ctx* ctx, const void* O, int O_dtype, const double* weights, int64_t N, int64_t K,
+                    const double* v, double* out_host);
+
 /* Eigendecomposition of a Hermitian K x K complex128 matrix (row-major, both
  * triangles, device) by parallel cyclic Jacobi rotations in float64:
  * A = V diag(evals) V^dagger, V unitary (K x K complex128, row-major, columns

@@ -835,6 +835,19 @@ extern "C" int vmc_sr_solve_eig(vmc_ctx* ctx, const void* O, int O_dtype, const 
   return rc;
 }
 
+extern "C" int vmc_fisher_quad(vmc_ctx* ctx, const void* O, int O_dtype, const double* weights, int64_t N, int64_t K,
+                               const double* v, double* out_host) {
+  return guard(ctx, [&] {
+    VMC_REQUIRE(ctx && O && v && out_host, "NULL argument");
+    VMC_REQUIRE(O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_C128 || O_dtype == VMC_DT_F32 || O_dtype == VMC_DT_F64,
+                "O dtype must be C64, C128, F32 or F64");
+    VMC_REQUIRE(N >= 1 && K >= 1, "N and K must be positive");
+    set_device(ctx);
+    phase_scope ps(ctx, "fisher");
+    *out_host = fisher_quad_impl(ctx, O, O_dtype, weights, N, K, (const double2*)v);
+  });
+}
+
 extern "C" int vmc_sr_solve_cg(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, const double* weights,
                                int64_t N, int64_t K, const vmc_sr_opts* opts, const vmc_cg_opts* cg, double* x,
                                vmc_sr_info* info_host, int* iterations_host) {

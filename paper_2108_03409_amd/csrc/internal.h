@@ -441,6 +441,8 @@ void herk_split16(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode,
 void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N,
                    int64_t K, const vmc_sr_opts* o, double2* x, vmc_sr_info* info, const vmc_eig_opts* eo,
                    double* evals, double* snr, int* sweeps);
+double fisher_quad_impl(vmc_ctx* ctx, const void* O, int dtype, const double* w, int64_t N, int64_t K,
+                        const double2* v);
 // eig.hip
 size_t eig_ws_bytes(int64_t K);
 int eig_hermitian(vmc_ctx* ctx, const double2* S, int64_t K, double tol, int max_sweeps, double* lam, double2* V,

@@ -907,6 +907,66 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   info->residual = hn[1] > 0 ? std::sqrt(hn[0] / hn[1]) : std::sqrt(hn[0]);
 }
 
+namespace {
+__global__ __launch_bounds__(1024) void k_wtotal(const double* __restrict__ w, int64_t N, double* __restrict__ stats) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t n = threadIdx.x; n < N; n += 1024) s += w ? w[n] : 1.0;
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int q = 0; q < 16; ++q) r += red[q];
+    stats[0] = r;
+  }
+}
+}  // namespace
+
+// v^H S v = sum_n w_n |(O_n - <O>) . v|^2 (weights normalised), from the samples
+double fisher_quad_impl(vmc_ctx* ctx, const void* O, int dtype, const double* w, int64_t N, int64_t K,
+                        const double2* v) {
+  hipStream_t st = ctx->stream;
+  const int nchunk = (int)((N + kColChunk - 1) / kColChunk);
+  ws_reserve(ctx, ws_round(64) + ws_round(sizeof(double2) * (size_t)nchunk * K) + ws_round(sizeof(double2) * K) * 2 +
+                      ws_round(sizeof(double) * N) + ws_round(sizeof(double2) * N) + ws_round(sizeof(double) * 16));
+  double* stats = (double*)ws_take(ctx, 64);
+  double2* partial = (double2*)ws_take(ctx, sizeof(double2) * (size_t)nchunk * K);
+  double2* mean = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double2* cmean = (double2*)ws_take(ctx, sizeof(double2) * K);
+  double* sq = (double*)ws_take(ctx, sizeof(double) * N);
+  double2* u = (double2*)ws_take(ctx, sizeof(double2) * N);
+  double* sc = (double*)ws_take(ctx, sizeof(double) * 16);
+  k_wtotal<<<1, 1024, 0, st>>>(w, N, stats);
+  const dim3 cg(grid_for(K, 256), nchunk);
+  if (dtype == VMC_DT_C64)
+    k_col_partial<float2><<<cg, 256, 0, st>>>((const float2*)O, w, N, K, partial);
+  else if (dtype == VMC_DT_C128)
+    k_col_partial<double2><<<cg, 256, 0, st>>>((const double2*)O, w, N, K, partial);
+  else if (dtype == VMC_DT_F32)
+    k_col_partial<float><<<cg, 256, 0, st>>>((const float*)O, w, N, K, partial);
+  else
+    k_col_partial<double><<<cg, 256, 0, st>>>((const double*)O, w, N, K, partial);
+  k_reduce_partial<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, stats, mean);
+  k_conj<<<grid_for(K, 256), 256, 0, st>>>(mean, K, cmean);
+  k_cg_dot<<<1, 1024, 0, st>>>(cmean, v, nullptr, K, sc + 8);  // <O> . v
+  k_sqw<<<grid_for(N, 256), 256, 0, st>>>(w, N, stats, sq);
+  if (dtype == VMC_DT_C64)
+    k_ov<float2><<<(unsigned)N, 256, 0, st>>>((const float2*)O, N, K, v, sc + 8, sq, u);
+  else if (dtype == VMC_DT_C128)
+    k_ov<double2><<<(unsigned)N, 256, 0, st>>>((const double2*)O, N, K, v, sc + 8, sq, u);
+  else if (dtype == VMC_DT_F32)
+    k_ov<float><<<(unsigned)N, 256, 0, st>>>((const float*)O, N, K, v, sc + 8, sq, u);
+  else
+    k_ov<double><<<(unsigned)N, 256, 0, st>>>((const double*)O, N, K, v, sc + 8, sq, u);
+  k_norms<<<1, 1024, 0, st>>>(u, u, N, sc);
+  VMC_HIP(hipGetLastError());
+  double* h = (double*)pinned_host(ctx, sizeof(double) * 2);
+  VMC_HIP(hipMemcpyAsync(h, sc, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+  VMC_HIP(hipStreamSynchronize(st));
+  return h[0];
+}
+
 // Shifted SR solve by Jacobi-preconditioned conjugate gradient, with
 // S v = Obar^H (Obar v) applied from the samples (S is never formed).
 void sr_solve_cg_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N,

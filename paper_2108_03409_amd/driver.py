@@ -107,6 +107,27 @@ class TDVP:
         self.last_info = info
         return x
 
+    def fisher_norm(self, theta: torch.Tensor, v: torch.Tensor) -> float:
+        """(1 / N_p) sqrt(v^dagger S v) with S at theta (Sec. 4.3 "Stepper")."""
+        self.model.set_params(theta.contiguous())
+        s, w = self._batch()
+        O = self.model.grad_log_psi(s, torch.complex128)
+        q = V.fisher_quad(self.ctx, O, v, weights=w)
+        return max(q, 0.0) ** 0.5 / v.numel()
+
+    def step_adaptive(self, stepper: "AdaptiveHeun") -> dict:
+        """One accepted step of the adaptive Heun integrator; the step size is
+        stepper.dt on entry and is updated for the next step."""
+        theta0 = self.theta
+        t_new, theta, dt_used = stepper.step(self.t, lambda y: self.rhs(y), theta0,
+                                             lambda v: self.fisher_norm(theta0, v))
+        self.theta = theta
+        self.model.set_params(self.theta)
+        self.t = t_new
+        info = dict(self.last_info or {})
+        info["dt"] = dt_used
+        return info
+
     def step(self, dt: float, method: str = "heun") -> dict:
         k1 = self.rhs(self.theta)
         if method == "euler":
@@ -119,3 +140,42 @@ class TDVP:
         self.model.set_params(self.theta)
         self.t += dt
         return self.last_info
+
+
+class AdaptiveHeun:
+    """Second-order adaptive integrator of the paper's stepper module (Sec. 4.3):
+    one Heun step of size tau and two of size tau / 2 give y^(tau) and
+    y^(tau/2); with delta = ||y^(tau) - y^(tau/2)|| the step size becomes
+    tau (eps / delta)^(1/3).  Readings: a step is accepted when delta <= eps
+    (otherwise it is recomputed with the reduced tau), the accepted value is the
+    two-half-step solution, and the factor is clamped to [min_factor, max_factor].
+    f(y) returns dy/dt; norm(v) is the user's measure (e.g. the Fisher norm)."""
+
+    def __init__(self, dt: float = 1e-3, tol: float = 1e-6, min_factor: float = 0.2, max_factor: float = 2.0,
+                 dt_min: float = 1e-12, dt_max: float = float("inf"), max_tries: int = 50):
+        self.dt, self.tol = dt, tol
+        self.min_factor, self.max_factor = min_factor, max_factor
+        self.dt_min, self.dt_max, self.max_tries = dt_min, dt_max, max_tries
+        self.n_rejected = 0
+
+    @staticmethod
+    def _heun(f, y, k1, h):
+        return y + 0.5 * h * (k1 + f(y + h * k1))
+
+    def step(self, t, f, y, norm):
+        """Returns (t + tau_used, y_new, tau_used)."""
+        k1 = f(y)
+        for _ in range(self.max_tries):
+            h = self.dt
+            y_full = self._heun(f, y, k1, h)
+            y_mid = self._heun(f, y, k1, 0.5 * h)
+            y_half = self._heun(f, y_mid, f(y_mid), 0.5 * h)
+            delta = norm(y_full - y_half)
+            factor = (self.tol / delta) ** (1.0 / 3.0) if delta > 0 else self.max_factor
+            factor = min(self.max_factor, max(self.min_factor, factor))
+            accept = delta <= self.tol or h <= self.dt_min
+            self.dt = min(self.dt_max, max(self.dt_min, h * factor))
+            if accept:
+                return t + h, y_half, h
+            self.n_rejected += 1
+        raise RuntimeError("adaptive step size did not reach the tolerance")

@@ -102,6 +102,7 @@ _SIGS = {
     "vmc_sr_solve_eig": ([P, P, C.c_int, P, P, I64, I64, C.POINTER(SROpts), C.POINTER(EigOpts), P,
                           C.POINTER(SRInfo), P, P, C.POINTER(C.c_int)], C.c_int),
     "vmc_eigh": ([P, P, I64, C.c_double, C.c_int, P, P, C.POINTER(C.c_int)], C.c_int),
+    "vmc_fisher_quad": ([P, P, C.c_int, P, I64, I64, P, C.POINTER(C.c_double)], C.c_int),
     "vmc_made_create": ([P, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_made_num_params": ([P, C.POINTER(I64)], C.c_int),
     "vmc_made_set_params": ([P, P], C.c_int),
@@ -494,6 +495,16 @@ def sr_solve_eig(ctx: Context, O: torch.Tensor, eloc: torch.Tensor, *, weights=N
     if rc != VMC_OK and raise_on_error:
         _check(rc, ctx.h)
     return (x if rc == VMC_OK else None), d
+
+
+def fisher_quad(ctx: Context, O: torch.Tensor, v: torch.Tensor, weights=None) -> float:
+    """v^dagger S v with S the connected covariance of the rows of O (weights normalised)."""
+    N, K = O.shape
+    dt = {torch.complex128: DT_C128, torch.complex64: DT_C64, torch.float64: DT_F64, torch.float32: DT_F32}[O.dtype]
+    v = v.to(torch.complex128).contiguous()
+    out = C.c_double()
+    _check(load().vmc_fisher_quad(ctx.h, _ptr(O), dt, _ptr(weights), N, K, _ptr(v), C.byref(out)), ctx.h)
+    return out.value
 
 
 def eigh(ctx: Context, A: torch.Tensor, *, tol=0.0, max_sweeps=0):

@@ -90,11 +90,10 @@ def test_sr_solve_eig_matches_oracle(ctx, N, Nh, ns, mode, gamma, nu, frac, soft
     kappa = np.abs(lam).max() / np.abs(lam[kept]).min()
     err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
     assert err <= max(1e-11, 1e-14 * kappa * 100), (err, kappa)
-    if snr > 0 or True:
-        s_ref = np.sort(info_ref["snr"])
-        s_got = np.sort(info["snr"].cpu().numpy())
-        fin = np.isfinite(s_ref)
-        assert np.allclose(s_got[fin], s_ref[fin], rtol=1e-8, atol=1e-12)
+    s_ref = np.sort(info_ref["snr"])
+    s_got = np.sort(info["snr"].cpu().numpy())
+    fin = np.isfinite(s_ref)
+    assert np.allclose(s_got[fin], s_ref[fin], rtol=1e-8, atol=1e-12)
     assert abs(info["e_mean"] - info_ref["e_mean"]) < 1e-12 * max(1, abs(info_ref["e_mean"]))
     assert abs(info["residual"] - info_ref["residual"]) <= 1e-8 + 1e-6 * info_ref["residual"]
 
@@ -148,3 +147,55 @@ def test_pinv_tdvp_follows_exact_evolution(ctx):
     fid = abs(np.vdot(v_exact, v_t)) ** 2
     flush(f"  fidelity {fid:.8f}")
     assert fid > 0.9999
+
+
+@pytest.mark.parametrize("dt", ["c128", "c64", "f64", "f32"])
+def test_fisher_quad_matches_oracle(ctx, dt):
+    flush(f"fisher quad {dt}")
+    cplx = dt.startswith("c")
+    O, el = _problem(9, 21, 777, 0.2, seed=41, cplx=cplx)
+    w = np.random.default_rng(2).uniform(0.5, 1.5, 777)
+    v = np.random.default_rng(3).normal(size=O.shape[1]) + 1j * np.random.default_rng(4).normal(size=O.shape[1])
+    On = {"c128": O, "c64": O.astype(np.complex64), "f64": O.real, "f32": O.real.astype(np.float32)}[dt]
+    S, _ = osr.fisher_and_force(np.asarray(On).astype(np.complex128), el, w)
+    ref = float(np.real(np.vdot(v, S @ v)))
+    got = V.fisher_quad(ctx, torch.from_numpy(np.ascontiguousarray(On)).to(DEV), dev_c128(v),
+                        weights=torch.from_numpy(w).to(DEV))
+    assert abs(got - ref) <= 1e-11 * abs(ref)
+
+
+def test_adaptive_heun_tdvp_follows_exact_evolution(ctx):
+    # exact TDVP with the adaptive Heun stepper and the Fisher norm: the step
+    # size grows from a small start while the state tracks exp(-iHt) psi(0)
+    import scipy.linalg as sla
+    from kron_ref import tfim as kron_tfim, code_to_kron
+    from oracle.eloc import all_states
+    from gpu_common import dev_bits
+    from paper_2108_03409_amd.driver import TDVP, AdaptiveHeun
+    flush("adaptive Heun TDVP, N = 6")
+    N, Nh, h, T = 6, 12, 1.0, 0.3
+    model = V.Model.rbm(ctx, N, Nh, True)
+    ham = V.Hamiltonian.tfim(ctx, N, 1, True, 1.0, h)
+    p0 = si.rbm_params(N, Nh, std=0.15, is_complex=True, seed=21)
+    states = all_states(N)
+    tdvp = TDVP(ctx, model, ham, torch.from_numpy(p0.astype(np.complex128)).to(DEV), real_time=True,
+                eps_abs=1e-8, exact_states=dev_bits(si.pack_bits(states)))
+    st = AdaptiveHeun(dt=1e-4, tol=1e-6)
+    dts = []
+    while tdvp.t < T - 1e-12:
+        st.dt = min(st.dt, T - tdvp.t)
+        dts.append(tdvp.step_adaptive(st)["dt"])
+    codes = (states.astype(np.int64) << np.arange(N)).sum(1)
+    idx = code_to_kron(codes, N)
+
+    def vec(p):
+        v = np.zeros(2 ** N, dtype=complex)
+        v[idx] = np.exp(orbm.log_psi(p, states, Nh))
+        return v / np.linalg.norm(v)
+
+    Hk = kron_tfim(N, 1, True, 1.0, h).toarray()
+    v_exact = sla.expm(-1j * tdvp.t * Hk) @ vec(p0)
+    fid = abs(np.vdot(v_exact, vec(tdvp.theta.cpu().numpy()))) ** 2
+    flush(f"  steps {len(dts)}  dt {dts[0]:.1e} -> {max(dts):.1e}  rejected {st.n_rejected}  fidelity {fid:.8f}")
+    assert fid > 0.9999
+    assert max(dts) > 10 * dts[0]
