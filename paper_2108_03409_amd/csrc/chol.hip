@@ -45,8 +45,8 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int6
                                                    double2* __restrict__ Linv, long long* __restrict__ fail,
                                                    double* __restrict__ pivmin) {
   __shared__ double2 L[CB * (CB + 1) / 2];
-  __shared__ int bad;
-  __shared__ double pmin;
+  __shared__ double2 X[CB * (CB + 1) / 2];
+  __shared__ double dpiv[CB];
   if (*fail >= 0) return;
   const int tid = threadIdx.x;
   for (int e = tid; e < CB * CB; e += 256) {
@@ -59,36 +59,30 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int6
       x = make_double2(r == c ? 1.0 : 0.0, 0.0);
     L[pk(r, c)] = x;
   }
-  if (tid == 0) {
-    bad = 0;
-    pmin = INFINITY;
-  }
   __syncthreads();
-  // right-looking factorisation; thread (ty, tx) updates rows ty + 16a, columns tx + 16b
+  // Right-looking elimination on the unscaled Schur complement, one barrier per
+  // column: A_rc -= A_rj conj(A_cj) / A_jj for j < c <= r (column j is only read
+  // in its step); the pivots d_j = A_jj are kept and L_rj = A_rj / sqrt(d_j) is
+  // formed afterwards.  Thread (ty, tx) owns rows ty + 16a, columns tx + 16b.
   const int ty = tid >> 4, tx = tid & 15;
+  int bad = -1;
+  double pmin = INFINITY;
   for (int j = 0; j < CB; ++j) {
-    if (tid == 0) {
-      const double d = L[pk(j, j)].x;
-      if (j < nb) {
-        pmin = fmin(pmin, d);
-        if (!(d > 0.0)) {
-          bad = 1;
-          *fail = kb0 + j;
-        }
+    const double d = L[pk(j, j)].x;  // the same value in every thread
+    if (j < nb) {
+      pmin = fmin(pmin, d);
+      if (!(d > 0.0)) {
+        bad = j;
+        break;
       }
     }
-    __syncthreads();
-    if (bad) break;
-    const double l = sqrt(L[pk(j, j)].x);
-    const double il = 1.0 / l;
-    if (tid > j && tid < CB) L[pk(tid, j)] = cscale(L[pk(tid, j)], il);
-    __syncthreads();
-    if (tid == 0) L[pk(j, j)] = make_double2(l, 0.0);
+    if (tid == 0) dpiv[j] = d;
+    const double id = 1.0 / d;
 #pragma unroll
     for (int aa = 0; aa < 4; ++aa) {
       const int r = ty + 16 * aa;
       if (r <= j) continue;
-      const double2 lr = L[pk(r, j)];
+      const double2 lr = cscale(L[pk(r, j)], id);
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
         const int c = tx + 16 * bb;
@@ -97,36 +91,49 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int6
     }
     __syncthreads();
   }
-  if (tid == 0) pivmin[kb0 / CB] = pmin;
-  if (bad) return;
+  if (tid == 0) {
+    pivmin[kb0 / CB] = pmin;
+    if (bad >= 0) *fail = kb0 + bad;
+  }
+  if (bad >= 0) return;  // uniform: every thread saw the same pivot
+  for (int e = tid; e < CB * (CB + 1) / 2; e += 256) {
+    int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= e) ++r;
+    while (r * (r + 1) / 2 > e) --r;
+    const int c = e - r * (r + 1) / 2;
+    const double s = sqrt(dpiv[c]);
+    L[e] = r == c ? make_double2(s, 0.0) : cscale(L[e], 1.0 / s);
+  }
+  __syncthreads();
   for (int e = tid; e < CB * CB; e += 256) {
     const int r = e / CB, c = e % CB;
     if (c <= r && r < nb) A[(kb0 + r) * K + kb0 + c] = L[pk(r, c)];
   }
-  __syncthreads();
-  // inverse X = L^{-1} by rows: X[r][c] = -(1/L_rr) sum_{m=c}^{r-1} L[r][m] X[m][c];
-  // row r of X overwrites row r of L once computed (rows < r already hold X).
-  // Four threads per column split the sum over m and combine by lane shuffles.
+  // Inverse X = L^{-1} column by column, four lanes per column (one quad of a
+  // wave): X_cc = 1 / L_cc, X_rc = -(1 / L_rr) sum_{m=c}^{r-1} L_rm X_mc.  A column
+  // depends only on itself, so the quad needs no group barrier; its lane 0 writes
+  // X_rc and the quad reads it back in later rows (same wave, ordered by a fence).
   const int cc = tid >> 2, qq = tid & 3;
-  if (tid == 0) L[pk(0, 0)] = make_double2(1.0 / L[pk(0, 0)].x, 0.0);
-  __syncthreads();
-  for (int r = 1; r < CB; ++r) {
+  if (qq == 0) X[pk(cc, cc)] = make_double2(1.0 / L[pk(cc, cc)].x, 0.0);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int r = cc + 1; r < CB; ++r) {  // trip count differs per quad, shuffles stay inside the quad
     double2 acc = make_double2(0.0, 0.0);
-    if (cc < r)
-      for (int m = cc + qq; m < r; m += 4) acc = cadd(acc, cmul(L[pk(r, m)], L[pk(m, cc)]));
-    acc.x += __shfl_xor(acc.x, 1, 64);
-    acc.y += __shfl_xor(acc.y, 1, 64);
-    acc.x += __shfl_xor(acc.x, 2, 64);
-    acc.y += __shfl_xor(acc.y, 2, 64);
-    const double d = 1.0 / L[pk(r, r)].x;
-    __syncthreads();
-    if (qq == 0 && cc < r) L[pk(r, cc)] = cscale(acc, -d);
-    if (tid == 0) L[pk(r, r)] = make_double2(d, 0.0);
-    __syncthreads();
+    for (int m = cc + qq; m < r; m += 4) acc = cadd(acc, cmul(L[pk(r, m)], X[pk(m, cc)]));
+    acc.x += __shfl_xor(acc.x, 1, 4);
+    acc.y += __shfl_xor(acc.y, 1, 4);
+    acc.x += __shfl_xor(acc.x, 2, 4);
+    acc.y += __shfl_xor(acc.y, 2, 4);
+    if (qq == 0) X[pk(r, cc)] = cscale(acc, -1.0 / L[pk(r, r)].x);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  __syncthreads();
   for (int e = tid; e < CB * CB; e += 256) {
     const int r = e / CB, c = e % CB;
-    Linv[e] = c <= r ? L[pk(r, c)] : make_double2(0.0, 0.0);
+    Linv[e] = c <= r ? X[pk(r, c)] : make_double2(0.0, 0.0);
   }
 }
 
