@@ -52,8 +52,8 @@ def herk_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="tfim1d_L64_rbm_a4_sr",
                     choices=["tfim1d_L64_rbm_a4_sr", "heis2d_10x10_rbm_a4", "tfim2d_16x16_cnn",
                              "tfim2d_20x20_rbm_a2_made", "tfim2d_20x20_rbm_a2_sr", "tfim1d_L50_ar_sr"])

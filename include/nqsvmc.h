@@ -132,6 +132,17 @@ int vmc_model_create_cnn(vmc_ctx* ctx, int Lx, int Ly, int channels, int kernel,
  * VMC_PROP_FLIP, sweep and thermalisation settings are ignored and the
  * reported acceptance is 1.  N in [2, 1024], n_hidden in [1, 1024].          */
 int vmc_model_create_autoregressive(vmc_ctx* ctx, int n_sites, int n_hidden, vmc_model** out);
+/* Tabulated wave function (test model): the K = 2^N parameters are the
+ * complex log-amplitudes, theta_code = log psi(s), code = sum_i bit_i 2^i
+ * (n_sites <= 24).  log psi is a lookup, O_k(s) = [k = code(s)] (one-hot rows
+ * of length 2^N), local energies read the connected amplitudes from the table,
+ * and a sampler runs Metropolis chains with the same Philox stream, proposals
+ * (flip or exchange) and acceptance rule as for the networks.  A table holding
+ * an eigenvector has E_loc = E_0 wherever psi != 0 (Sec. 5.1).
+ * logpsi_table_c128: 2^N complex128 on the device (NULL: all zero, i.e. the
+ * uniform state); must be finite (VMC_ERR_NONFINITE).  Float64 only; no
+ * vmc_log_psi_vjp.                                                          */
+int vmc_model_create_table(vmc_ctx* ctx, int n_sites, const void* logpsi_table_c128, vmc_model** out);
 int vmc_model_num_params(const vmc_model* m, int64_t* K);
 int vmc_model_num_sites(const vmc_model* m, int* N);
 /* Copies K parameters from device memory (dtype C128, C64 or, for real RBMs, F64)

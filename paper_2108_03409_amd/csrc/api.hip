@@ -299,6 +299,44 @@ extern "C" int vmc_model_create_autoregressive(vmc_ctx* ctx, int n_sites, int n_
   });
 }
 
+extern "C" int vmc_model_create_table(vmc_ctx* ctx, int n_sites, const void* logpsi_table_c128, vmc_model** out) {
+  vmc_model* m = nullptr;
+  int rc = guard(ctx, [&] {
+    VMC_REQUIRE(ctx && out, "NULL argument");
+    VMC_REQUIRE(n_sites >= 1 && n_sites <= 24, "n_sites must be in [1, 24]");
+    set_device(ctx);
+    m = new vmc_model;
+    m->ctx = ctx;
+    m->kind = MODEL_TABLE;
+    m->N = n_sites;
+    m->W = 1;
+    m->is_complex = 1;
+    m->K = (int64_t)1 << n_sites;
+    try {
+      m->params = (double2*)dmalloc(sizeof(double2) * m->K);
+      VMC_HIP(hipMemsetAsync(m->params, 0, sizeof(double2) * m->K, ctx->stream));
+    } catch (...) {
+      if (m->params) (void)hipFree(m->params);
+      delete m;
+      m = nullptr;
+      throw;
+    }
+    ctx_retain(ctx);
+  });
+  if (rc != VMC_OK) return rc;
+  if (logpsi_table_c128) {
+    rc = vmc_model_set_params(m, logpsi_table_c128, VMC_DT_C128);
+    if (rc != VMC_OK) {
+      std::string msg = vmc_last_error(ctx);
+      (void)vmc_model_destroy(m);
+      guard(ctx, [&] { throw vmc_error{rc, msg}; });
+      return rc;
+    }
+  }
+  *out = m;
+  return VMC_OK;
+}
+
 extern "C" int vmc_model_num_params(const vmc_model* m, int64_t* K) {
   if (!m || !K) return VMC_ERR_INVALID_ARG;
   *K = m->K;
@@ -394,6 +432,8 @@ extern "C" int vmc_model_set_precision(vmc_model* m, int prec) {
     VMC_REQUIRE(prec == VMC_F64 || prec == VMC_F32 || prec == VMC_BF16, "unknown precision");
     if (prec != VMC_F64 && m->kind == MODEL_AR)
       throw vmc_error{VMC_ERR_UNSUPPORTED, "the autoregressive state is evaluated in float64 only"};
+    if (prec != VMC_F64 && m->kind == MODEL_TABLE)
+      throw vmc_error{VMC_ERR_UNSUPPORTED, "the tabulated model is float64 only"};
     if (prec != VMC_F64 && m->kind == MODEL_CNN && (m->Lx < 2 * m->k - 1 || m->Ly < 2 * m->k - 1))
       throw vmc_error{VMC_ERR_UNSUPPORTED, "float32 / bfloat16 CNN local energies need Lx, Ly >= 2 kernel - 1"};
     m->prec = prec;
@@ -521,6 +561,8 @@ extern "C" int vmc_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double* l
       rbm_log_psi(m, s, B, (double2*)logpsi);
     else if (m->kind == MODEL_AR)
       ar_log_psi(m, s, B, (double2*)logpsi);
+    else if (m->kind == MODEL_TABLE)
+      table_log_psi(m, s, B, (double2*)logpsi);
     else
       cnn_log_psi(m, s, B, (double2*)logpsi);
   });
@@ -544,6 +586,8 @@ extern "C" int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int
       rbm_local_energy(m, H, s, B, (double2*)eloc);
     else if (m->kind == MODEL_AR)
       ar_local_energy(m, H, s, B, (double2*)eloc);
+    else if (m->kind == MODEL_TABLE)
+      table_local_energy(m, H, s, B, (double2*)eloc);
     else if (m->prec != VMC_F64)
       cnn_lowp_local_energy(m, H, s, B, (double2*)eloc);
     else
@@ -567,6 +611,8 @@ extern "C" int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void
       rbm_grad(m, s, B, O, dtype);
     else if (m->kind == MODEL_AR)
       ar_grad(m, s, B, O, dtype);
+    else if (m->kind == MODEL_TABLE)
+      table_grad(m, s, B, O, dtype);
     else
       cnn_grad(m, s, B, O, dtype);
   });
@@ -577,8 +623,8 @@ extern "C" int vmc_log_psi_vjp(vmc_model* m, const uint64_t* s, int64_t B, const
     VMC_REQUIRE(m, "NULL model");
     VMC_REQUIRE(B >= 0, "B < 0");
     VMC_REQUIRE(out, "NULL out");
-    if (m->kind == MODEL_AR)
-      throw vmc_error{VMC_ERR_UNSUPPORTED, "no vector-Jacobian product for the autoregressive state"};
+    if (m->kind == MODEL_AR || m->kind == MODEL_TABLE)
+      throw vmc_error{VMC_ERR_UNSUPPORTED, "no vector-Jacobian product for this model kind"};
     set_device(m->ctx);
     phase_scope ps(m->ctx, "vjp");
     if (B == 0) {
@@ -607,8 +653,10 @@ extern "C" int vmc_sampler_create(vmc_ctx* ctx, vmc_model* m, vmc_ham* H, const 
     }
     if (o->proposal == VMC_PROP_MADE_MIX)
       VMC_REQUIRE(o->p_global >= 0.0 && o->p_global <= 1.0, "p_global must be in [0, 1]");
-    VMC_REQUIRE(m->kind == MODEL_RBM || o->proposal == VMC_PROP_FLIP,
-                "CNN models are sampled with single flips; autoregressive states take VMC_PROP_FLIP (direct sampling)");
+    VMC_REQUIRE(m->kind == MODEL_RBM || o->proposal == VMC_PROP_FLIP ||
+                    (m->kind == MODEL_TABLE && o->proposal == VMC_PROP_EXCHANGE),
+                "CNN models are sampled with single flips; autoregressive states take VMC_PROP_FLIP (direct "
+                "sampling); tabulated models take flips or exchanges");
     set_device(ctx);
     auto* S = new vmc_sampler;
     S->ctx = ctx;
@@ -663,7 +711,9 @@ extern "C" int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, do
     uint64_t t0 = S->t;
     {
       phase_scope ps(S->ctx, "sample");
-      if (S->model->kind == MODEL_CNN && S->model->prec != VMC_F64)
+      if (S->model->kind == MODEL_TABLE)
+        table_sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
+      else if (S->model->kind == MODEL_CNN && S->model->prec != VMC_F64)
         cnn_lowp_sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
       else if (S->model->kind == MODEL_CNN)
         cnn_sampler_run(S, per_chain, s_out, (double2*)logpsi_out);

@@ -73,6 +73,7 @@ _SIGS = {
     "vmc_model_create_rbm": ([P, C.c_int, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_model_create_cnn": ([P, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_model_create_autoregressive": ([P, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
+    "vmc_model_create_table": ([P, C.c_int, P, C.POINTER(P)], C.c_int),
     "vmc_model_num_params": ([P, C.POINTER(I64)], C.c_int),
     "vmc_model_num_sites": ([P, C.POINTER(C.c_int)], C.c_int),
     "vmc_model_set_params": ([P, P, C.c_int], C.c_int),
@@ -212,6 +213,14 @@ class Model:
     def cnn(cls, ctx, Lx, Ly, channels, kernel):
         h = P()
         _check(load().vmc_model_create_cnn(ctx.h, Lx, Ly, channels, kernel, C.byref(h)), ctx.h)
+        return cls(ctx, h)
+
+    @classmethod
+    def table(cls, ctx, n_sites, logpsi=None):
+        """Tabulated log-amplitudes (2^n_sites complex128, device); test model."""
+        h = P()
+        lp = None if logpsi is None else logpsi.to(torch.complex128).contiguous()
+        _check(load().vmc_model_create_table(ctx.h, n_sites, _ptr(lp), C.byref(h)), ctx.h)
         return cls(ctx, h)
 
     @classmethod
