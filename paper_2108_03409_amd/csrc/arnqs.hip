@@ -194,135 +194,169 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // The same local energies with both masked weight matrices held in LDS (staged
-// once per group) and one wave per configuration: lanes over hidden units for
-// the forward pre-activations and the move updates (registers), lanes over
-// outputs for the logits.  Hidden units whose degree does not exceed min P have
-// a zero W1 column entry for every site of P, so their change is exactly zero
-// and the output loop skips them.  Configurations are taken grid-stride.
-template <int QH>
-__global__ __launch_bounds__(AR_NT) void k_ar_eloc_lds(const uint64_t* __restrict__ s, int64_t B, int N, int H,
+// once per group) and one wave per configuration.  The connected moves are taken
+// AR_CM at a time and their (move, output) pairs -- output i >= min P of the
+// move -- are laid out over the lanes, so a wave instruction serves several
+// moves when their triangles are short: for each chunk the changes of the
+// hidden units (lanes over (move, unit)), then the new logit and its
+// log-likelihood term per pair, then per-move sums over 16-lane groups.  Moves
+// and pairs are summed in a fixed order (reproducible results).
+constexpr int AR_CM = 4;  // moves per chunk (64 / AR_CM lanes per move in the sums)
+
+__global__ __launch_bounds__(AR_NT) void k_ar_eloc_tri(const uint64_t* __restrict__ s, int64_t B, int N, int H,
                                                        int W, const double* __restrict__ W1mT,
                                                        const double* __restrict__ W2t, const double* __restrict__ b1,
                                                        const double* __restrict__ b2, int kind, double J, double hx,
                                                        const int2* __restrict__ bonds, int n_bonds,
                                                        double2* __restrict__ eloc) {
   extern __shared__ double lds[];
-  double* W1s = lds;                 // [N][H]
-  double* W2s = W1s + N * H;         // [H][N]
+  double* W1s = lds;          // [N][H]
+  double* W2s = W1s + N * H;  // [H][N]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* x = W2s + H * N + wave * (3 * N + 64 * QH);  // per wave: x, l, t, hidden changes
+  const int per = (3 + AR_CM) * N + (2 + AR_CM) * H + (n_bonds + 1) / 2;  // doubles per wave
+  double* x = W2s + H * N + wave * per;
   double* l = x + N;
   double* t = l + N;
-  double* dhs = t + N;
+  double* a = t + N;
+  double* hh = a + H;
+  double* DH = hh + H;         // [AR_CM][H] hidden-unit changes of the chunk's moves
+  double* buf = DH + AR_CM * H;  // [AR_CM][N] per-pair log-likelihood changes
+  int* mv = (int*)(buf + AR_CM * N);  // anti-aligned bonds (Heisenberg), bond order
   for (int e = threadIdx.x; e < N * H; e += AR_NT) {
     W1s[e] = W1mT[e];
     W2s[e] = W2t[e];
   }
   __syncthreads();
-  const int Nm1 = N - 1;
   const double mel = kind == HAM_TFIM ? -hx : 2.0 * J;
   const bool offdiag = kind == HAM_TFIM ? hx != 0.0 : J != 0.0;
+  const int grp = lane >> 4, gl = lane & 15;  // 16-lane group of the per-move sums
   for (int64_t b = (int64_t)blockIdx.x * AR_WAVES + wave; b < B; b += (int64_t)gridDim.x * AR_WAVES) {
     const uint64_t* srow = s + b * W;
     for (int i = lane; i < N; i += 64) x[i] = (double)((srow[i >> 6] >> (i & 63)) & 1ull);
     wave_sync();
-    double a[QH], hr[QH];
-#pragma unroll
-    for (int q = 0; q < QH; ++q) {
-      const int k = lane + 64 * q;
-      const int kc = k < H ? k : H - 1;
-      double acc = b1[kc];
-      for (int d = 0; d < N; ++d) {
-        const double w = W1s[d * H + kc];  // zero beyond the unit's degree
-        acc = fma(w, x[d], acc);
-      }
-      a[q] = acc;
-      hr[q] = k < H ? fmax(acc, 0.0) : 0.0;
-    }
-    for (int i0 = 0; i0 < N; i0 += 64) {
-      const int i = i0 + lane;
-      const int ic = i < N ? i : N - 1;
-      double acc = b2[ic];
-#pragma unroll
-      for (int q = 0; q < QH; ++q)
-        for (int kk = 0; kk < 64; ++kk) {
-          const int k = 64 * q + kk;
-          if (k >= H) break;
-          acc = fma(W2s[k * N + ic], lane_bcast(hr[q], kk), acc);
-        }
-      if (i < N) {
-        l[i] = acc;
-        t[i] = x[i] * acc - ar_softplus(acc);
-      }
+    for (int k = lane; k < H; k += 64) {
+      double acc = b1[k];
+      for (int d = 0; d < N; ++d) acc = fma(W1s[d * H + k], x[d], acc);  // zero beyond the unit's degree
+      a[k] = acc;
+      hh[k] = fmax(acc, 0.0);
     }
     wave_sync();
-    double e = 0.0;
-    int n_al = 0;
-    // one connected configuration: sites p0 < p1 (p1 = -1 for a flip)
-    auto move = [&](int p0, int p1) {
-      const double d0 = 1.0 - 2.0 * x[p0];
-      const double d1 = p1 >= 0 ? 1.0 - 2.0 * x[p1] : 0.0;
-#pragma unroll
-      for (int q = 0; q < QH; ++q) {
-        const int k = lane + 64 * q;
-        const int kc = k < H ? k : H - 1;
-        double ap = fma(W1s[p0 * H + kc], d0, a[q]);
-        if (p1 >= 0) ap = fma(W1s[p1 * H + kc], d1, ap);
-        dhs[k] = k < H ? fmax(ap, 0.0) - hr[q] : 0.0;  // exactly 0 for units of degree <= min P
-      }
-      wave_sync();
-      double acc = 0.0;
-      for (int i0 = p0; i0 < N; i0 += 64) {
-        const int i = i0 + lane;
-        const int ic = i < N ? i : N - 1;
-        // four independent chains over the hidden units (broadcast LDS reads of the changes)
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int k = 0;
-        for (; k + 4 <= H; k += 4) {
-          s0 = fma(W2s[k * N + ic], dhs[k], s0);
-          s1 = fma(W2s[(k + 1) * N + ic], dhs[k + 1], s1);
-          s2 = fma(W2s[(k + 2) * N + ic], dhs[k + 2], s2);
-          s3 = fma(W2s[(k + 3) * N + ic], dhs[k + 3], s3);
-        }
-        for (; k < H; ++k) s0 = fma(W2s[k * N + ic], dhs[k], s0);
-        const double lp = l[ic] + ((s0 + s1) + (s2 + s3));
-        if (i < N) {
-          const double xi = (i == p0 || i == p1) ? 1.0 - x[i] : x[i];
-          acc += (xi * lp - ar_softplus(lp)) - t[i];
-        }
-      }
-      acc = wave_sum(acc);
-      e += mel * exp(0.5 * acc);
-      wave_sync();  // dhs is rewritten by the next move
-    };
-    for (int b0 = 0; b0 < n_bonds; b0 += 64) {
-      const int q = b0 + lane;
+    for (int i = lane; i < N; i += 64) {
+      double acc = b2[i];
+      for (int k = 0; k < H; ++k) acc = fma(W2s[k * N + i], hh[k], acc);
+      l[i] = acc;
+      t[i] = x[i] * acc - ar_softplus(acc);
+    }
+    // moves: diagonal count and the anti-aligned bond list
+    int n_al = 0, M = 0;
+    for (int q0 = 0; q0 < n_bonds; q0 += 64) {
+      const int q = q0 + lane;
       bool al = false, anti = false;
-      int2 bd = make_int2(0, 0);
       if (q < n_bonds) {
-        bd = bonds[q];
+        const int2 bd = bonds[q];
         al = get_bit(srow, bd.x) == get_bit(srow, bd.y);
         anti = !al;
       }
       n_al += __popcll(__ballot(al));
-      if (kind == HAM_HEIS && offdiag) {
-        unsigned long long am = __ballot(anti);
-        while (am) {
-          const int src = __ffsll((long long)am) - 1;
-          am &= am - 1ull;
-          const int bx = __builtin_amdgcn_readlane(bd.x, src), by = __builtin_amdgcn_readlane(bd.y, src);
-          move(min(bx, by), max(bx, by));
+      const unsigned long long am = __ballot(anti);
+      if (kind == HAM_HEIS && anti) mv[M + __popcll(am & ((1ull << lane) - 1ull))] = q;
+      M += __popcll(am);
+    }
+    if (kind == HAM_TFIM) M = N;
+    if (!offdiag) M = 0;
+    wave_sync();
+    auto move_sites = [&](int m, int& p0, int& p1) {
+      if (kind == HAM_TFIM) {
+        p0 = m;
+        p1 = -1;
+      } else {
+        const int2 bd = bonds[mv[m]];
+        p0 = min(bd.x, bd.y);
+        p1 = max(bd.x, bd.y);
+      }
+    };
+    double e = 0.0;
+    for (int m0 = 0; m0 < M; m0 += AR_CM) {
+      const int cm = min(AR_CM, M - m0);
+      int p0s[AR_CM], p1s[AR_CM], off[AR_CM + 1];
+      off[0] = 0;
+#pragma unroll
+      for (int mm = 0; mm < AR_CM; ++mm) {
+        int p0 = N, p1 = -1;
+        if (mm < cm) move_sites(m0 + mm, p0, p1);
+        p0s[mm] = p0;
+        p1s[mm] = p1;
+        off[mm + 1] = off[mm] + (mm < cm ? N - p0 : 0);
+      }
+      // hidden-unit changes, lanes over (move, unit)
+      for (int q = lane; q < cm * H; q += 64) {
+        const int mm = q / H, k = q - mm * H;
+        int p0 = p0s[0], p1 = p1s[0];
+#pragma unroll
+        for (int r = 1; r < AR_CM; ++r)
+          if (mm == r) {
+            p0 = p0s[r];
+            p1 = p1s[r];
+          }
+        double ap = fma(W1s[p0 * H + k], 1.0 - 2.0 * x[p0], a[k]);
+        if (p1 >= 0) ap = fma(W1s[p1 * H + k], 1.0 - 2.0 * x[p1], ap);
+        DH[q] = fmax(ap, 0.0) - hh[k];  // exactly 0 for units of degree <= p0
+      }
+      wave_sync();
+      // (move, output) pairs over the lanes
+      const int total = off[AR_CM];  // moves past cm add nothing
+      for (int q0 = 0; q0 < total; q0 += 64) {
+        const int q = q0 + lane;
+        if (q < total) {
+          int mm = 0;
+#pragma unroll
+          for (int r = 1; r < AR_CM; ++r) mm += q >= off[r] ? 1 : 0;
+          int p0 = p0s[0], p1 = p1s[0], o = off[0];
+#pragma unroll
+          for (int r = 1; r < AR_CM; ++r)
+            if (mm == r) {
+              p0 = p0s[r];
+              p1 = p1s[r];
+              o = off[r];
+            }
+          const int i = p0 + (q - o);
+          const double* dh = DH + mm * H;
+          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+          int k = 0;
+          for (; k + 4 <= H; k += 4) {
+            s0 = fma(W2s[k * N + i], dh[k], s0);
+            s1 = fma(W2s[(k + 1) * N + i], dh[k + 1], s1);
+            s2 = fma(W2s[(k + 2) * N + i], dh[k + 2], s2);
+            s3 = fma(W2s[(k + 3) * N + i], dh[k + 3], s3);
+          }
+          for (; k < H; ++k) s0 = fma(W2s[k * N + i], dh[k], s0);
+          const double lp = l[i] + ((s0 + s1) + (s2 + s3));
+          const double xi = (i == p0 || i == p1) ? 1.0 - x[i] : x[i];
+          buf[mm * N + i] = (xi * lp - ar_softplus(lp)) - t[i];
         }
       }
+      wave_sync();
+      // per-move sums: 16 lanes per move, fixed order
+      double acc = 0.0;
+      int p0g = p0s[0];
+#pragma unroll
+      for (int r = 1; r < AR_CM; ++r)
+        if (grp == r) p0g = p0s[r];
+      if (grp < cm)
+        for (int i = p0g + gl; i < N; i += 16) acc += buf[grp * N + i];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+      const double r = grp < cm ? mel * exp(0.5 * acc) : 0.0;
+#pragma unroll
+      for (int mm = 0; mm < AR_CM; ++mm) e += lane_bcast(r, 16 * mm);
+      wave_sync();  // DH and buf are rewritten by the next chunk
     }
-    if (kind == HAM_TFIM && offdiag)
-      for (int p = 0; p < N; ++p) move(p, -1);
     if (lane == 0) {
       const int n_anti = n_bonds - n_al;
       const double diag = (kind == HAM_TFIM ? -J : J) * (double)(n_al - n_anti);
       eloc[b] = make_double2(diag + e, 0.0);
     }
-    wave_sync();  // x, l, t are rewritten by the next configuration
+    wave_sync();  // per-wave arrays are rewritten by the next configuration
   }
 }
 
@@ -500,32 +534,21 @@ void ar_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* out) {
 
 void ar_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc) {
   const ar_ptrs p = ptrs(m);
-  const int QH = (m->Nh + 63) / 64;
-  const int QHp = QH <= 1 ? 1 : QH <= 2 ? 2 : QH <= 4 ? 4 : 8;
-  const size_t lds_w =
-      sizeof(double) * (2 * (size_t)m->N * m->Nh + (size_t)AR_WAVES * (3 * (size_t)m->N + 64 * (size_t)QHp));
+  const size_t per_wave = (size_t)(3 + AR_CM) * m->N + (size_t)(2 + AR_CM) * m->Nh + ((size_t)H->n_bonds + 1) / 2;
+  const size_t lds_w = sizeof(double) * (2 * (size_t)m->N * m->Nh + (size_t)AR_WAVES * per_wave);
   if (lds_w <= kArLdsMax) {
     // one resident wave of groups: as many as the LDS of 256 compute units holds (at most 8 each)
     const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)(160 * 1024) / (int64_t)lds_w));
     const int64_t groups = std::min<int64_t>((B + AR_WAVES - 1) / AR_WAVES, 256 * per_cu);
-#define AR_ELOC_LDS(Q)                                                                                          \
-  k_ar_eloc_lds<Q><<<(unsigned)groups, AR_NT, lds_w, m->ctx->stream>>>(s, B, m->N, m->Nh, m->W, p.W1mT,         \
-                                                                       m->ar_w2t, p.b1, p.b2, H->kind, H->J,   \
-                                                                       H->h, H->bonds, H->n_bonds, eloc)
-    if (QH <= 1)
-      AR_ELOC_LDS(1);
-    else if (QH <= 2)
-      AR_ELOC_LDS(2);
-    else if (QH <= 4)
-      AR_ELOC_LDS(4);
-    else
-      AR_ELOC_LDS(8);
-#undef AR_ELOC_LDS
+    k_ar_eloc_tri<<<(unsigned)groups, AR_NT, lds_w, m->ctx->stream>>>(s, B, m->N, m->Nh, m->W, p.W1mT, m->ar_w2t,
+                                                                       p.b1, p.b2, H->kind, H->J, H->h, H->bonds,
+                                                                       H->n_bonds, eloc);
     VMC_HIP(hipGetLastError());
     return;
   }
   const size_t lds = sizeof(double) * (3 * (size_t)m->N + 2 * (size_t)m->Nh) + sizeof(int) * (size_t)H->n_bonds;
   VMC_REQUIRE(lds <= kArLdsMax, "network too large for the per-configuration local-energy tile");
+  const int QH = (m->Nh + 63) / 64;
   for (int64_t b0 = 0; b0 < B; b0 += INT32_MAX) {
     const int64_t nb = std::min<int64_t>(INT32_MAX, B - b0);
 #define AR_ELOC(Q)                                                                                                 \
