@@ -132,6 +132,17 @@ int vmc_model_create_cnn(vmc_ctx* ctx, int Lx, int Ly, int channels, int kernel,
  * VMC_PROP_FLIP, sweep and thermalisation settings are ignored and the
  * reported acceptance is 1.  N in [2, 1024], n_hidden in [1, 1024].          */
 int vmc_model_create_autoregressive(vmc_ctx* ctx, int n_sites, int n_hidden, vmc_model** out);
+/* Translation-symmetric single-layer network with ELU activation on a ring of
+ * L sites, the ground-state ansatz of the paper's example (Sec. 5.1,
+ * eq:gs_nqs):
+ *   theta_{a,w} = b_a + sum_l W_{a,l} sigma_{(l + w) mod L},  sigma = 2 s - 1,
+ *   log psi(s)  = sum_{a=1..alpha} sum_{w=0..L-1} ELU(theta_{a,w}),
+ *   ELU(x) = x (x > 0), e^x - 1 (x <= 0).
+ * Real parameters [W (alpha x L, row-major), b (alpha)], K = alpha (L + 1).
+ * Float64; O_k also as F64 / F32; samplers take single flips (VMC_PROP_FLIP);
+ * no vmc_log_psi_vjp.  L in [2, 1024], alpha in [1, 64], and alpha L small
+ * enough for the per-configuration LDS tile (else VMC_ERR_INVALID_ARG).      */
+int vmc_model_create_symelu(vmc_ctx* ctx, int L, int alpha, vmc_model** out);
 /* Tabulated wave function (test model): the K = 2^N parameters are the
  * complex log-amplitudes, theta_code = log psi(s), code = sum_i bit_i 2^i
  * (n_sites <= 24).  log psi is a lookup, O_k(s) = [k = code(s)] (one-hot rows
@@ -206,7 +217,8 @@ int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B,
 /* Log-derivatives O_k(s) = d log psi(s) / d theta_k (Sec. 2.2; the complex
  * derivative for holomorphic nets, Sec. 2.3), flat parameter order.
  *   O: B*K elements, sample-major (row n = sample n), dtype C128 or C64; the
- *   autoregressive state (real parameters, real O) also writes F64 or F32.   */
+ *   real-parameter networks (autoregressive state, symmetric ELU network)
+ *   also write F64 or F32.                                                    */
 int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
 
 /* Reverse-mode product with the log-derivatives (the backward of log psi for

@@ -299,6 +299,36 @@ extern "C" int vmc_model_create_autoregressive(vmc_ctx* ctx, int n_sites, int n_
   });
 }
 
+extern "C" int vmc_model_create_symelu(vmc_ctx* ctx, int L, int alpha, vmc_model** out) {
+  return guard(ctx, [&] {
+    VMC_REQUIRE(ctx && out, "NULL argument");
+    VMC_REQUIRE(L >= 2 && L <= 1024, "L must be in [2, 1024]");
+    VMC_REQUIRE(alpha >= 1 && alpha <= 64, "alpha must be in [1, 64]");
+    set_device(ctx);
+    auto* m = new vmc_model;
+    m->ctx = ctx;
+    m->kind = MODEL_SYMELU;
+    m->N = L;
+    m->Lx = L;
+    m->Ly = 1;
+    m->W = (L + 63) / 64;
+    m->C = alpha;
+    m->is_complex = 0;
+    m->K = (int64_t)alpha * (L + 1);
+    try {
+      symelu_check(m);
+      m->params = (double2*)dmalloc(sizeof(double2) * m->K);
+      VMC_HIP(hipMemsetAsync(m->params, 0, sizeof(double2) * m->K, ctx->stream));
+    } catch (...) {
+      if (m->params) (void)hipFree(m->params);
+      delete m;
+      throw;
+    }
+    ctx_retain(ctx);
+    *out = m;
+  });
+}
+
 extern "C" int vmc_model_create_table(vmc_ctx* ctx, int n_sites, const void* logpsi_table_c128, vmc_model** out) {
   vmc_model* m = nullptr;
   int rc = guard(ctx, [&] {
@@ -432,8 +462,8 @@ extern "C" int vmc_model_set_precision(vmc_model* m, int prec) {
     VMC_REQUIRE(prec == VMC_F64 || prec == VMC_F32 || prec == VMC_BF16, "unknown precision");
     if (prec != VMC_F64 && m->kind == MODEL_AR)
       throw vmc_error{VMC_ERR_UNSUPPORTED, "the autoregressive state is evaluated in float64 only"};
-    if (prec != VMC_F64 && m->kind == MODEL_TABLE)
-      throw vmc_error{VMC_ERR_UNSUPPORTED, "the tabulated model is float64 only"};
+    if (prec != VMC_F64 && (m->kind == MODEL_TABLE || m->kind == MODEL_SYMELU))
+      throw vmc_error{VMC_ERR_UNSUPPORTED, "this model kind is evaluated in float64 only"};
     if (prec != VMC_F64 && m->kind == MODEL_CNN && (m->Lx < 2 * m->k - 1 || m->Ly < 2 * m->k - 1))
       throw vmc_error{VMC_ERR_UNSUPPORTED, "float32 / bfloat16 CNN local energies need Lx, Ly >= 2 kernel - 1"};
     m->prec = prec;
@@ -563,6 +593,8 @@ extern "C" int vmc_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double* l
       ar_log_psi(m, s, B, (double2*)logpsi);
     else if (m->kind == MODEL_TABLE)
       table_log_psi(m, s, B, (double2*)logpsi);
+    else if (m->kind == MODEL_SYMELU)
+      symelu_log_psi(m, s, B, (double2*)logpsi);
     else
       cnn_log_psi(m, s, B, (double2*)logpsi);
   });
@@ -588,6 +620,8 @@ extern "C" int vmc_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int
       ar_local_energy(m, H, s, B, (double2*)eloc);
     else if (m->kind == MODEL_TABLE)
       table_local_energy(m, H, s, B, (double2*)eloc);
+    else if (m->kind == MODEL_SYMELU)
+      symelu_local_energy(m, H, s, B, (double2*)eloc);
     else if (m->prec != VMC_F64)
       cnn_lowp_local_energy(m, H, s, B, (double2*)eloc);
     else
@@ -601,7 +635,8 @@ extern "C" int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void
     VMC_REQUIRE(dtype == VMC_DT_C128 || dtype == VMC_DT_C64 || dtype == VMC_DT_F32 || dtype == VMC_DT_F64,
                 "dtype must be C128, C64, F32 or F64");
     if (dtype == VMC_DT_F32 || dtype == VMC_DT_F64)
-      VMC_REQUIRE(m->kind == MODEL_AR, "real O_k (F32 / F64) are written for the autoregressive state only");
+      VMC_REQUIRE(m->kind == MODEL_AR || m->kind == MODEL_SYMELU,
+                  "real O_k (F32 / F64) are written for the real-parameter networks (autoregressive, symmetric ELU)");
     VMC_REQUIRE(B >= 0, "B < 0");
     if (B == 0) return;
     VMC_REQUIRE(s && O, "NULL buffer");
@@ -613,6 +648,8 @@ extern "C" int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void
       ar_grad(m, s, B, O, dtype);
     else if (m->kind == MODEL_TABLE)
       table_grad(m, s, B, O, dtype);
+    else if (m->kind == MODEL_SYMELU)
+      symelu_grad(m, s, B, O, dtype);
     else
       cnn_grad(m, s, B, O, dtype);
   });
@@ -623,7 +660,7 @@ extern "C" int vmc_log_psi_vjp(vmc_model* m, const uint64_t* s, int64_t B, const
     VMC_REQUIRE(m, "NULL model");
     VMC_REQUIRE(B >= 0, "B < 0");
     VMC_REQUIRE(out, "NULL out");
-    if (m->kind == MODEL_AR || m->kind == MODEL_TABLE)
+    if (m->kind == MODEL_AR || m->kind == MODEL_TABLE || m->kind == MODEL_SYMELU)
       throw vmc_error{VMC_ERR_UNSUPPORTED, "no vector-Jacobian product for this model kind"};
     set_device(m->ctx);
     phase_scope ps(m->ctx, "vjp");
@@ -713,6 +750,8 @@ extern "C" int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, do
       phase_scope ps(S->ctx, "sample");
       if (S->model->kind == MODEL_TABLE)
         table_sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
+      else if (S->model->kind == MODEL_SYMELU)
+        symelu_sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
       else if (S->model->kind == MODEL_CNN && S->model->prec != VMC_F64)
         cnn_lowp_sampler_run(S, per_chain, s_out, (double2*)logpsi_out);
       else if (S->model->kind == MODEL_CNN)

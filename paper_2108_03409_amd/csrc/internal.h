@@ -123,7 +123,7 @@ inline size_t ws_round(size_t b) { return (b + 255) & ~size_t(255); }
 void* pinned_host(vmc_ctx* ctx, size_t bytes);
 
 // ---------------------------------------------------------------- models --
-enum { MODEL_RBM = 0, MODEL_CNN = 1, MODEL_AR = 2, MODEL_TABLE = 3 };
+enum { MODEL_RBM = 0, MODEL_CNN = 1, MODEL_AR = 2, MODEL_TABLE = 3, MODEL_SYMELU = 4 };
 
 struct vmc_ham;
 struct vmc_made;
@@ -393,6 +393,12 @@ void cnn_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, do
 void cnn_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
 void cnn_sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
 void cnn_lowp_sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
+// symelu.hip (translation-symmetric ELU network; C holds alpha)
+void symelu_check(const vmc_model* m);
+void symelu_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* out);
+void symelu_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
+void symelu_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
+void symelu_sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
 // table.hip (tabulated log-amplitudes, test model)
 void table_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* out);
 void table_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);

@@ -2,8 +2,9 @@
 
 One iteration is Algorithm 1 of the paper followed by the Euler update of
 imaginary-time TDVP (Sec. 3.1): draw samples with the Metropolis chains, form
-O_k and the local energies, solve (S + nu_n diag S + eps I) x = -F, and set
-theta <- theta + tau x.  The diagonal shift decays geometrically, as in the
+O_k and the local energies, solve (S + nu_n diag S + eps I) x = -F (through the
+pseudo-inverse of that matrix when a cutoff eps_pinv is given, as in the
+paper's ground-state example), and set theta <- theta + tau x.  The diagonal shift decays geometrically, as in the
 ground-state example of Sec. 5 (nu_n = max(nu_0 q^n, nu_min)).  Every step of
 the iteration runs in the HIP library; this module only sequences the calls.
 """
@@ -22,7 +23,7 @@ class GroundStateSearch:
     def __init__(self, ctx: V.Context, model: V.Model, ham: V.Hamiltonian, theta: torch.Tensor, *,
                  n_chains: int = 256, sweeps_per_step: int = 8, tau: float = 0.05, nu=None,
                  eps_abs: float = 0.0, mode: int = V.SR_COMPLEX, o_dtype=torch.complex64, gram: int = 0,
-                 proposal: int = V.PROP_FLIP, therm_sweeps: int = 20, seed: int = 1):
+                 proposal: int = V.PROP_FLIP, therm_sweeps: int = 20, seed: int = 1, eps_pinv: float = 0.0):
         self.ctx, self.model, self.ham = ctx, model, ham
         self.theta = theta.to(torch.complex128).contiguous()
         self.model.set_params(self.theta)
@@ -30,6 +31,7 @@ class GroundStateSearch:
                                  therm_sweeps=therm_sweeps, seed=seed)
         self.n_samples = n_chains * sweeps_per_step
         self.tau, self.eps_abs, self.mode, self.gram = tau, eps_abs, mode, gram
+        self.eps_pinv = eps_pinv  # > 0: pseudo-inverse cutoff on top of the diagonal shift (Sec. 3.3)
         self.nu = nu if nu is not None else geometric_shift()
         dev = self.theta.device
         self.O = torch.empty((self.n_samples, model.K), dtype=o_dtype, device=dev)
@@ -40,8 +42,12 @@ class GroundStateSearch:
         s, _, acc = self.sampler.sample(self.n_samples)
         self.model.grad_log_psi(s, out=self.O)
         self.model.local_energy(self.ham, s, out=self.el)
-        x, info = V.sr_solve(self.ctx, self.O, self.el, nu_rel=self.nu(self.n), eps_abs=self.eps_abs,
-                             mode=self.mode, gram=self.gram)
+        if self.eps_pinv > 0.0:
+            x, info = V.sr_solve_eig(self.ctx, self.O, self.el, nu_rel=self.nu(self.n), eps_abs=self.eps_abs,
+                                     mode=self.mode, gram=self.gram, eps_pinv=self.eps_pinv)
+        else:
+            x, info = V.sr_solve(self.ctx, self.O, self.el, nu_rel=self.nu(self.n), eps_abs=self.eps_abs,
+                                 mode=self.mode, gram=self.gram)
         self.theta = self.theta + self.tau * x
         self.model.set_params(self.theta)
         self.n += 1

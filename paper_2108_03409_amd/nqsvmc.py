@@ -74,6 +74,7 @@ _SIGS = {
     "vmc_model_create_cnn": ([P, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_model_create_autoregressive": ([P, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_model_create_table": ([P, C.c_int, P, C.POINTER(P)], C.c_int),
+    "vmc_model_create_symelu": ([P, C.c_int, C.c_int, C.POINTER(P)], C.c_int),
     "vmc_model_num_params": ([P, C.POINTER(I64)], C.c_int),
     "vmc_model_num_sites": ([P, C.POINTER(C.c_int)], C.c_int),
     "vmc_model_set_params": ([P, P, C.c_int], C.c_int),
@@ -213,6 +214,13 @@ class Model:
     def cnn(cls, ctx, Lx, Ly, channels, kernel):
         h = P()
         _check(load().vmc_model_create_cnn(ctx.h, Lx, Ly, channels, kernel, C.byref(h)), ctx.h)
+        return cls(ctx, h)
+
+    @classmethod
+    def symelu(cls, ctx, L, alpha):
+        """Translation-symmetric ELU network on a ring (the paper's ground-state ansatz)."""
+        h = P()
+        _check(load().vmc_model_create_symelu(ctx.h, L, alpha, C.byref(h)), ctx.h)
         return cls(ctx, h)
 
     @classmethod

@@ -132,6 +132,13 @@ def ar_params(n_sites: int, n_hidden: int, *, seed: int, std: float = 0.5) -> np
     return rng.normal(0.0, std, size=n_sites * n_hidden + n_hidden + n_sites).astype(np.float64)
 
 
+def symelu_params(L: int, alpha: int, *, seed: int, std: float = 0.1) -> np.ndarray:
+    """Real parameters [W (alpha x L), b (alpha)] of the translation-symmetric ELU
+    network, i.i.d. normal with standard deviation ``std``."""
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, std, size=alpha * (L + 1)).astype(np.float64)
+
+
 def made_params(n_in: int, n_hidden: int, *, seed: int = 205) -> np.ndarray:
     """Flat MADE parameters [W1 (H x N), b1 (H), W2 (N x H), b2 (N)], float64,
     uniform in +-1/sqrt(fan_in) (a common dense-layer initialisation)."""
