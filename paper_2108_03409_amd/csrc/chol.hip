@@ -41,7 +41,9 @@ __device__ __forceinline__ int pk(int r, int c) { return r * (r + 1) / 2 + c; } 
 
 // Factor and invert the diagonal block at kb0 (nb <= 64 valid rows/cols; the
 // rest is padded with the identity).  LDS holds the packed lower triangle.
-__global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
+constexpr int CD_NT = 512;  // threads of the diagonal-block kernel
+
+__global__ __launch_bounds__(CD_NT) void k_chol_diag(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
                                                    double2* __restrict__ Linv, long long* __restrict__ fail,
                                                    double* __restrict__ pivmin) {
   __shared__ double2 L[CB * (CB + 1) / 2];
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int6
   __shared__ double dpiv[CB];
   if (*fail >= 0) return;
   const int tid = threadIdx.x;
-  for (int e = tid; e < CB * CB; e += 256) {
+  for (int e = tid; e < CB * CB; e += CD_NT) {
     const int r = e / CB, c = e % CB;
     if (c > r) continue;
     double2 x;
@@ -63,7 +65,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int6
   // Right-looking elimination on the unscaled Schur complement, one barrier per
   // column: A_rc -= A_rj conj(A_cj) / A_jj for j < c <= r (column j is only read
   // in its step); the pivots d_j = A_jj are kept and L_rj = A_rj / sqrt(d_j) is
-  // formed afterwards.  Thread (ty, tx) owns rows ty + 16a, columns tx + 16b.
+  // formed afterwards.  Thread (ty, tx) owns rows ty + 32a, columns tx + 16b.
   const int ty = tid >> 4, tx = tid & 15;
   int bad = -1;
   double pmin = INFINITY;
@@ -79,8 +81,8 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int6
     if (tid == 0) dpiv[j] = d;
     const double id = 1.0 / d;
 #pragma unroll
-    for (int aa = 0; aa < 4; ++aa) {
-      const int r = ty + 16 * aa;
+    for (int aa = 0; aa < 2; ++aa) {
+      const int r = ty + 32 * aa;
       if (r <= j) continue;
       const double2 lr = cscale(L[pk(r, j)], id);
 #pragma unroll
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int6
     if (bad >= 0) *fail = kb0 + bad;
   }
   if (bad >= 0) return;  // uniform: every thread saw the same pivot
-  for (int e = tid; e < CB * (CB + 1) / 2; e += 256) {
+  for (int e = tid; e < CB * (CB + 1) / 2; e += CD_NT) {
     int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
     while ((r + 1) * (r + 2) / 2 <= e) ++r;
     while (r * (r + 1) / 2 > e) --r;
@@ -105,33 +107,43 @@ __global__ __launch_bounds__(256) void k_chol_diag(double2* __restrict__ A, int6
     L[e] = r == c ? make_double2(s, 0.0) : cscale(L[e], 1.0 / s);
   }
   __syncthreads();
-  for (int e = tid; e < CB * CB; e += 256) {
+  for (int e = tid; e < CB * CB; e += CD_NT) {
     const int r = e / CB, c = e % CB;
     if (c <= r && r < nb) A[(kb0 + r) * K + kb0 + c] = L[pk(r, c)];
   }
-  // Inverse X = L^{-1} column by column, four lanes per column (one quad of a
-  // wave): X_cc = 1 / L_cc, X_rc = -(1 / L_rr) sum_{m=c}^{r-1} L_rm X_mc.  A column
-  // depends only on itself, so the quad needs no group barrier; its lane 0 writes
-  // X_rc and the quad reads it back in later rows (same wave, ordered by a fence).
-  const int cc = tid >> 2, qq = tid & 3;
+  // Inverse X = L^{-1} column by column, eight lanes per column (an aligned
+  // 8-lane group of a wave): X_cc = 1 / L_cc, X_rc = -(1 / L_rr) sum_{m=c}^{r-1}
+  // L_rm X_mc, each lane with four independent partial sums.  A column depends
+  // only on itself, so the group needs no barrier; its lane 0 writes X_rc and
+  // the group reads it back in later rows (same wave, ordered by a fence).
+  const int cc = tid >> 3, qq = tid & 7;
   if (qq == 0) X[pk(cc, cc)] = make_double2(1.0 / L[pk(cc, cc)].x, 0.0);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int r = cc + 1; r < CB; ++r) {  // trip count differs per quad, shuffles stay inside the quad
-    double2 acc = make_double2(0.0, 0.0);
-    for (int m = cc + qq; m < r; m += 4) acc = cadd(acc, cmul(L[pk(r, m)], X[pk(m, cc)]));
-    acc.x += __shfl_xor(acc.x, 1, 4);
-    acc.y += __shfl_xor(acc.y, 1, 4);
-    acc.x += __shfl_xor(acc.x, 2, 4);
-    acc.y += __shfl_xor(acc.y, 2, 4);
+  for (int r = cc + 1; r < CB; ++r) {  // trip count differs per group, shuffles stay inside it
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
+    int m = cc + qq;
+    for (; m + 24 < r; m += 32) {
+      a0 = cadd(a0, cmul(L[pk(r, m)], X[pk(m, cc)]));
+      a1 = cadd(a1, cmul(L[pk(r, m + 8)], X[pk(m + 8, cc)]));
+      a2 = cadd(a2, cmul(L[pk(r, m + 16)], X[pk(m + 16, cc)]));
+      a3 = cadd(a3, cmul(L[pk(r, m + 24)], X[pk(m + 24, cc)]));
+    }
+    for (; m < r; m += 8) a0 = cadd(a0, cmul(L[pk(r, m)], X[pk(m, cc)]));
+    double2 acc = cadd(cadd(a0, a1), cadd(a2, a3));
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) {
+      acc.x += __shfl_xor(acc.x, o, 8);
+      acc.y += __shfl_xor(acc.y, o, 8);
+    }
     if (qq == 0) X[pk(r, cc)] = cscale(acc, -1.0 / L[pk(r, r)].x);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   __syncthreads();
-  for (int e = tid; e < CB * CB; e += 256) {
+  for (int e = tid; e < CB * CB; e += CD_NT) {
     const int r = e / CB, c = e % CB;
     Linv[e] = c <= r ? X[pk(r, c)] : make_double2(0.0, 0.0);
   }
@@ -349,7 +361,7 @@ void chol_factor(vmc_ctx* ctx, double2* S, int64_t K, double2* Linv, long long* 
     for (int64_t c0 = p0; c0 < pend; c0 += CB) {
       const int nb = (int)std::min<int64_t>(CB, K - c0);
       double2* Lb = Linv + (size_t)(c0 / CB) * CB * CB;
-      k_chol_diag<<<1, 256, 0, st>>>(S, K, c0, nb, Lb, fail, pivmin);
+      k_chol_diag<<<1, CD_NT, 0, st>>>(S, K, c0, nb, Lb, fail, pivmin);
       const int64_t rest = K - c0 - nb;
       if (rest <= 0) continue;
       zargs a{};
