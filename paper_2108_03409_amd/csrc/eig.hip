@@ -11,7 +11,9 @@
 //     t^2 + 2 tau t - 1 = 0,  tau = (b - a) / (2 |z|),
 // zeroes A_pq (A <- J^H A J on rows and columns p, q; V <- V J).  The pairs of a
 // round are disjoint, so the update is a set of independent 2 x 2 block
-// transforms, one per thread, in place.  Sweeps stop when the off-diagonal
+// transforms, one per thread; a round is one launch (every thread derives the
+// rotations it needs from the previous round's matrix, so the matrix is
+// double-buffered; V is updated in place).  Sweeps stop when the off-diagonal
 // Frobenius norm is below tol times the full norm.
 #include <hip/hip_runtime.h>
 
@@ -43,9 +45,7 @@ __device__ __forceinline__ void round_pair(int i, int r, int Kp, int& p, int& q)
   }
 }
 
-__global__ void k_jacobi_params(const double2* __restrict__ A, int64_t Kp, int r, jrot* __restrict__ rot) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Kp / 2) return;
+__device__ __forceinline__ jrot make_rot(const double2* __restrict__ A, int64_t Kp, int i, int r) {
   int p, q;
   round_pair(i, r, (int)Kp, p, q);
   const double a = A[(int64_t)p * Kp + p].x, b = A[(int64_t)q * Kp + q].x;
@@ -72,57 +72,67 @@ __global__ void k_jacobi_params(const double2* __restrict__ A, int64_t Kp, int r
     R.b_new = b + t * az;
     R.active = 1;
   }
-  rot[i] = R;
+  return R;
 }
 
-// block (bi, bj): rows {p_bi, q_bi} x columns {p_bj, q_bj} <- J_bi^H M J_bj
-__global__ __launch_bounds__(256) void k_jacobi_apply(double2* __restrict__ A, int64_t Kp,
-                                                      const jrot* __restrict__ rot) {
+// One round in one launch.  Groups with blockIdx.y < ceil(half / 4) update the
+// matrix: block (bi, bj) of rows {p_bi, q_bi} x columns {p_bj, q_bj} becomes
+// J_bi^H M J_bj, read from Ain and written to Aout (the rotations of a round are
+// derived by every thread from Ain, so Ain must not change during the round).
+// The remaining groups update V <- V J in place (each thread owns two entries of
+// one row).
+__global__ __launch_bounds__(256) void k_jacobi_round(const double2* __restrict__ Ain, double2* __restrict__ Aout,
+                                                      double2* __restrict__ V, int64_t Kp, int r, int ya) {
   const int64_t half = Kp / 2;
-  const int64_t bj = blockIdx.x * 64ll + (threadIdx.x & 63);
-  const int64_t bi = blockIdx.y * 4ll + (threadIdx.x >> 6);
-  if (bi >= half || bj >= half) return;
-  const jrot Ri = rot[bi], Rj = rot[bj];
-  if (!Ri.active && !Rj.active) return;
-  double2* r0 = A + (int64_t)Ri.p * Kp;
-  double2* r1 = A + (int64_t)Ri.q * Kp;
-  if (bi == bj) {  // the pair's own 2 x 2 block: diagonal by construction
-    r0[Ri.p] = make_double2(Ri.a_new, 0.0);
-    r1[Ri.q] = make_double2(Ri.b_new, 0.0);
-    r0[Ri.q] = make_double2(0.0, 0.0);
-    r1[Ri.p] = make_double2(0.0, 0.0);
-    return;
+  if ((int)blockIdx.y < ya) {
+    const int64_t bj = blockIdx.x * 64ll + (threadIdx.x & 63);
+    const int64_t bi = blockIdx.y * 4ll + (threadIdx.x >> 6);
+    if (bi >= half || bj >= half) return;
+    const jrot Ri = make_rot(Ain, Kp, (int)bi, r), Rj = make_rot(Ain, Kp, (int)bj, r);
+    const double2* r0 = Ain + (int64_t)Ri.p * Kp;
+    const double2* r1 = Ain + (int64_t)Ri.q * Kp;
+    double2* w0 = Aout + (int64_t)Ri.p * Kp;
+    double2* w1 = Aout + (int64_t)Ri.q * Kp;
+    if (bi == bj) {
+      if (Ri.active) {  // the pair's own 2 x 2 block: diagonal by construction
+        w0[Ri.p] = make_double2(Ri.a_new, 0.0);
+        w1[Ri.q] = make_double2(Ri.b_new, 0.0);
+        w0[Ri.q] = make_double2(0.0, 0.0);
+        w1[Ri.p] = make_double2(0.0, 0.0);
+      } else {
+        w0[Ri.p] = r0[Ri.p];
+        w1[Ri.q] = r1[Ri.q];
+        w0[Ri.q] = r0[Ri.q];
+        w1[Ri.p] = r1[Ri.p];
+      }
+      return;
+    }
+    const double2 m00 = r0[Rj.p], m01 = r0[Rj.q], m10 = r1[Rj.p], m11 = r1[Rj.q];
+    // T = M J_j:  T[:,0] = c M[:,0] - s e M[:,1],  T[:,1] = s M[:,0] + c e M[:,1]
+    const double2 em01 = cmul(Rj.e, m01), em11 = cmul(Rj.e, m11);
+    const double2 t00 = make_double2(Rj.c * m00.x - Rj.s * em01.x, Rj.c * m00.y - Rj.s * em01.y);
+    const double2 t10 = make_double2(Rj.c * m10.x - Rj.s * em11.x, Rj.c * m10.y - Rj.s * em11.y);
+    const double2 t01 = make_double2(Rj.s * m00.x + Rj.c * em01.x, Rj.s * m00.y + Rj.c * em01.y);
+    const double2 t11 = make_double2(Rj.s * m10.x + Rj.c * em11.x, Rj.s * m10.y + Rj.c * em11.y);
+    // M' = J_i^H T:  row 0 = c T[0,:] - s conj(e) T[1,:],  row 1 = s T[0,:] + c conj(e) T[1,:]
+    const double2 ce = cconj(Ri.e);
+    const double2 u10 = cmul(ce, t10), u11 = cmul(ce, t11);
+    w0[Rj.p] = make_double2(Ri.c * t00.x - Ri.s * u10.x, Ri.c * t00.y - Ri.s * u10.y);
+    w0[Rj.q] = make_double2(Ri.c * t01.x - Ri.s * u11.x, Ri.c * t01.y - Ri.s * u11.y);
+    w1[Rj.p] = make_double2(Ri.s * t00.x + Ri.c * u10.x, Ri.s * t00.y + Ri.c * u10.y);
+    w1[Rj.q] = make_double2(Ri.s * t01.x + Ri.c * u11.x, Ri.s * t01.y + Ri.c * u11.y);
+  } else {
+    const int64_t n = blockIdx.x * 64ll + (threadIdx.x & 63);
+    const int64_t bj = (blockIdx.y - ya) * 4ll + (threadIdx.x >> 6);
+    if (n >= Kp || bj >= half) return;
+    const jrot R = make_rot(Ain, Kp, (int)bj, r);
+    if (!R.active) return;
+    double2* row = V + n * Kp;
+    const double2 v0 = row[R.p], v1 = row[R.q];
+    const double2 ev1 = cmul(R.e, v1);
+    row[R.p] = make_double2(R.c * v0.x - R.s * ev1.x, R.c * v0.y - R.s * ev1.y);
+    row[R.q] = make_double2(R.s * v0.x + R.c * ev1.x, R.s * v0.y + R.c * ev1.y);
   }
-  const double2 m00 = r0[Rj.p], m01 = r0[Rj.q], m10 = r1[Rj.p], m11 = r1[Rj.q];
-  // T = M J_j:  T[:,0] = c M[:,0] - s e M[:,1],  T[:,1] = s M[:,0] + c e M[:,1]
-  const double2 em01 = cmul(Rj.e, m01), em11 = cmul(Rj.e, m11);
-  const double2 t00 = make_double2(Rj.c * m00.x - Rj.s * em01.x, Rj.c * m00.y - Rj.s * em01.y);
-  const double2 t10 = make_double2(Rj.c * m10.x - Rj.s * em11.x, Rj.c * m10.y - Rj.s * em11.y);
-  const double2 t01 = make_double2(Rj.s * m00.x + Rj.c * em01.x, Rj.s * m00.y + Rj.c * em01.y);
-  const double2 t11 = make_double2(Rj.s * m10.x + Rj.c * em11.x, Rj.s * m10.y + Rj.c * em11.y);
-  // M' = J_i^H T:  row 0 = c T[0,:] - s conj(e) T[1,:],  row 1 = s T[0,:] + c conj(e) T[1,:]
-  const double2 ce = cconj(Ri.e);
-  const double2 u10 = cmul(ce, t10), u11 = cmul(ce, t11);
-  r0[Rj.p] = make_double2(Ri.c * t00.x - Ri.s * u10.x, Ri.c * t00.y - Ri.s * u10.y);
-  r0[Rj.q] = make_double2(Ri.c * t01.x - Ri.s * u11.x, Ri.c * t01.y - Ri.s * u11.y);
-  r1[Rj.p] = make_double2(Ri.s * t00.x + Ri.c * u10.x, Ri.s * t00.y + Ri.c * u10.y);
-  r1[Rj.q] = make_double2(Ri.s * t01.x + Ri.c * u11.x, Ri.s * t01.y + Ri.c * u11.y);
-}
-
-// V <- V J on the column pairs of the round (rows n)
-__global__ __launch_bounds__(256) void k_jacobi_vec(double2* __restrict__ V, int64_t Kp,
-                                                    const jrot* __restrict__ rot) {
-  const int64_t half = Kp / 2;
-  const int64_t n = blockIdx.x * 64ll + (threadIdx.x & 63);
-  const int64_t bj = blockIdx.y * 4ll + (threadIdx.x >> 6);
-  if (n >= Kp || bj >= half) return;
-  const jrot R = rot[bj];
-  if (!R.active) return;
-  double2* row = V + n * Kp;
-  const double2 v0 = row[R.p], v1 = row[R.q];
-  const double2 ev1 = cmul(R.e, v1);
-  row[R.p] = make_double2(R.c * v0.x - R.s * ev1.x, R.c * v0.y - R.s * ev1.y);
-  row[R.q] = make_double2(R.s * v0.x + R.c * ev1.x, R.s * v0.y + R.c * ev1.y);
 }
 
 // out[0] += sum of |A_ij|^2 off the diagonal, out[1] += sum of all |A_ij|^2 (per row, one wave)
@@ -167,7 +177,7 @@ __global__ void k_eig_out(const double2* __restrict__ A, const double2* __restri
 
 size_t eig_ws_bytes(int64_t K) {
   const int64_t Kp = K + (K & 1);
-  return ws_round(sizeof(double2) * Kp * Kp) * 2 + ws_round(sizeof(jrot) * (Kp / 2 + 1)) + ws_round(2 * sizeof(double));
+  return ws_round(sizeof(double2) * Kp * Kp) * 3 + ws_round(2 * sizeof(double));
 }
 
 int eig_hermitian(vmc_ctx* ctx, const double2* S, int64_t K, double tol, int max_sweeps, double* lam, double2* V,
@@ -177,10 +187,10 @@ int eig_hermitian(vmc_ctx* ctx, const double2* S, int64_t K, double tol, int max
   char* w = (char*)ws;
   double2* A = (double2*)w;
   w += ws_round(sizeof(double2) * Kp * Kp);
+  double2* A2 = (double2*)w;
+  w += ws_round(sizeof(double2) * Kp * Kp);
   double2* Vp = (double2*)w;
   w += ws_round(sizeof(double2) * Kp * Kp);
-  jrot* rot = (jrot*)w;
-  w += ws_round(sizeof(jrot) * (Kp / 2 + 1));
   double* nrm = (double*)w;
   k_pad_copy<<<grid_for(Kp * Kp, 256), 256, 0, st>>>(S, K, Kp, A, Vp);
   VMC_HIP(hipGetLastError());
@@ -188,8 +198,10 @@ int eig_hermitian(vmc_ctx* ctx, const double2* S, int64_t K, double tol, int max
   int sweeps = 0;
   if (Kp >= 2) {
     const int64_t half = Kp / 2;
-    const dim3 ga((unsigned)((half + 63) / 64), (unsigned)((half + 3) / 4));
-    const dim3 gv((unsigned)((Kp + 63) / 64), (unsigned)((half + 3) / 4));
+    const int ya = (int)((half + 3) / 4);        // row-pair groups of the matrix update
+    const int yv = (int)((half + 3) / 4);        // column-pair groups of the V update
+    const unsigned gx = (unsigned)std::max<int64_t>((half + 63) / 64, (Kp + 63) / 64);
+    const dim3 g(gx, (unsigned)(ya + yv));
     for (;;) {
       VMC_HIP(hipMemsetAsync(nrm, 0, 2 * sizeof(double), st));
       k_offnorm<<<(unsigned)((Kp + 3) / 4), 256, 0, st>>>(A, Kp, nrm);
@@ -197,9 +209,8 @@ int eig_hermitian(vmc_ctx* ctx, const double2* S, int64_t K, double tol, int max
       VMC_HIP(hipStreamSynchronize(st));
       if (!(hn[0] > tol * tol * hn[1]) || sweeps >= max_sweeps) break;
       for (int r = 0; r < Kp - 1; ++r) {
-        k_jacobi_params<<<(unsigned)((half + 255) / 256), 256, 0, st>>>(A, Kp, r, rot);
-        k_jacobi_apply<<<ga, 256, 0, st>>>(A, Kp, rot);
-        k_jacobi_vec<<<gv, 256, 0, st>>>(Vp, Kp, rot);
+        k_jacobi_round<<<g, 256, 0, st>>>(A, A2, Vp, Kp, r, ya);
+        std::swap(A, A2);
       }
       VMC_HIP(hipGetLastError());
       ++sweeps;
