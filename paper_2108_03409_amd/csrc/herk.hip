@@ -117,12 +117,16 @@ __device__ __forceinline__ void herk_epilogue(const herk_args& a, int64_t row0, 
 }
 
 template <bool REAL>
-__global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
+__global__ __launch_bounds__(256, 2) void k_herk_mfma_f32(herk_args a) {
   using sh = herk_shape<REAL>;
   constexpr int BN = sh::BN, JN = sh::JN, QN = sh::QN;
   constexpr int NA = BK * BM / 256, NB = BK * BN / 256;  // float2 per thread per stage
-  __shared__ float2 As[2][BK][BM + PAD];
-  __shared__ float2 Bs[2][BK][BN + PAD];
+  // complex mode: two LDS stages (one barrier per stage); real mode: one stage
+  // (two barriers per stage) so that its square tiles leave room for four
+  // resident groups per compute unit
+  constexpr int NBUF = REAL ? 1 : 2;
+  __shared__ float2 As[NBUF][BK][BM + PAD];
+  __shared__ float2 Bs[NBUF][BK][BN + PAD];
 
   const int64_t nb = a.n_tiles;
   const int64_t lin = remap_tile(blockIdx.x, nb);
@@ -184,7 +188,7 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
     sstore(0);
     __syncthreads();
     for (int64_t st = st0; st < st1; ++st) {
-      const int buf = (int)((st - st0) & 1);
+      const int buf = NBUF == 2 ? (int)((st - st0) & 1) : 0;
       if (st + 1 < st1) gload((st + 1) * BK);
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
@@ -206,8 +210,16 @@ __global__ __launch_bounds__(256) void k_herk_mfma_f32(herk_args a) {
             }
           }
       }
-      if (st + 1 < st1) sstore(buf ^ 1);
-      __syncthreads();
+      if constexpr (NBUF == 2) {
+        if (st + 1 < st1) sstore(buf ^ 1);
+        __syncthreads();
+      } else {
+        __syncthreads();  // every wave is done with the stage
+        if (st + 1 < st1) {
+          sstore(0);
+          __syncthreads();
+        }
+      }
     }
   }
 
