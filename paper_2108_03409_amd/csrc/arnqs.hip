@@ -418,6 +418,77 @@ __global__ __launch_bounds__(AR_NT) void k_ar_grad(const uint64_t* __restrict__ 
   }
 }
 
+// The same O_k with one wave per configuration and both masked weight matrices
+// in LDS (staged once per group, configurations taken grid-stride): the forward
+// pass, g_l and g_h with lanes over units, then the K outputs with lanes over the
+// live parameters (coalesced row writes).
+template <typename OutT>
+__global__ __launch_bounds__(AR_NT) void k_ar_grad_w(const uint64_t* __restrict__ s, int64_t B, int N, int H, int W,
+                                                     const double* __restrict__ W1mT,
+                                                     const double* __restrict__ W2t, const double* __restrict__ b1,
+                                                     const double* __restrict__ b2, const int2* __restrict__ idx,
+                                                     int64_t r1, int64_t r2, int64_t r3, int64_t K,
+                                                     OutT* __restrict__ O) {
+  extern __shared__ double lds[];
+  double* W1s = lds;          // [N][H]
+  double* W2s = W1s + N * H;  // [H][N]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* x = W2s + H * N + wave * (2 * N + 2 * H);
+  double* gl = x + N;   // logits, then s_i - sigmoid(l_i)
+  double* hh = gl + N;  // ReLU(a), with a kept as the sign of the gate below
+  double* gh = hh + H;
+  for (int e = threadIdx.x; e < N * H; e += AR_NT) {
+    W1s[e] = W1mT[e];
+    W2s[e] = W2t[e];
+  }
+  __syncthreads();
+  for (int64_t b = (int64_t)blockIdx.x * AR_WAVES + wave; b < B; b += (int64_t)gridDim.x * AR_WAVES) {
+    const uint64_t* srow = s + b * W;
+    for (int i = lane; i < N; i += 64) x[i] = (double)((srow[i >> 6] >> (i & 63)) & 1ull);
+    wave_sync();
+    for (int k = lane; k < H; k += 64) {
+      double acc = b1[k];
+      for (int d = 0; d < N; ++d) acc = fma(W1s[d * H + k], x[d], acc);
+      hh[k] = fmax(acc, 0.0);
+      gh[k] = acc > 0.0 ? 1.0 : 0.0;  // ReLU gate
+    }
+    wave_sync();
+    for (int i = lane; i < N; i += 64) {
+      double acc = b2[i];
+      for (int k = 0; k < H; ++k) acc = fma(W2s[k * N + i], hh[k], acc);
+      gl[i] = x[i] - 1.0 / (1.0 + exp(-acc));
+    }
+    wave_sync();
+    for (int k = lane; k < H; k += 64) {
+      double acc = 0.0;
+      for (int i = ar_deg(k, N); i < N; ++i) acc = fma(W2s[k * N + i], gl[i], acc);
+      gh[k] *= acc;
+    }
+    wave_sync();
+    OutT* row = O + b * K;
+    for (int64_t j = lane; j < K; j += 64) {
+      const int2 pr = idx[j];
+      double v;
+      if (j < r1)
+        v = gh[pr.x] * x[pr.y];
+      else if (j < r2)
+        v = gh[pr.x];
+      else if (j < r3)
+        v = gl[pr.x] * hh[pr.y];
+      else
+        v = gl[pr.x];
+      v *= 0.5;
+      if constexpr (std::is_same<OutT, double2>::value)
+        row[j] = make_double2(v, 0.0);
+      else if constexpr (std::is_same<OutT, float2>::value)
+        row[j] = make_float2((float)v, 0.0f);
+      else
+        row[j] = (OutT)v;
+    }
+    wave_sync();
+  }
+}
+
 // compact live parameters -> dense masked layout [W1 (H x N) | b1 | W2 (N x H) | b2]
 __global__ void k_ar_scatter(const double2* __restrict__ theta, const int2* __restrict__ idx, int64_t r1, int64_t r2,
                              int64_t r3, int64_t K, int N, int H, double* __restrict__ dense) {
@@ -572,6 +643,26 @@ void ar_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, dou
 
 void ar_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype) {
   const ar_ptrs p = ptrs(m);
+  const size_t lds_w = sizeof(double) * (2 * (size_t)m->N * m->Nh + (size_t)AR_WAVES * (2 * (size_t)m->N + 2 * m->Nh));
+  if (lds_w <= kArLdsMax) {
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)(160 * 1024) / (int64_t)lds_w));
+    const unsigned g = (unsigned)std::min<int64_t>((B + AR_WAVES - 1) / AR_WAVES, 256 * per_cu);
+    hipStream_t st = m->ctx->stream;
+#define AR_GRAD_W(T)                                                                                           \
+  k_ar_grad_w<T><<<g, AR_NT, lds_w, st>>>(s, B, m->N, m->Nh, m->W, p.W1mT, m->ar_w2t, p.b1, p.b2, m->ar_idx, \
+                                          m->ar_r1, m->ar_r2, m->ar_r3, m->K, (T*)O)
+    if (dtype == VMC_DT_C128)
+      AR_GRAD_W(double2);
+    else if (dtype == VMC_DT_C64)
+      AR_GRAD_W(float2);
+    else if (dtype == VMC_DT_F64)
+      AR_GRAD_W(double);
+    else
+      AR_GRAD_W(float);
+#undef AR_GRAD_W
+    VMC_HIP(hipGetLastError());
+    return;
+  }
   const size_t per = sizeof(double) * (2 * (size_t)m->N + 3 * (size_t)m->Nh);
   const int sb = 4 * per <= kArLdsMax ? 4 : 1;
   VMC_REQUIRE(per <= kArLdsMax, "network too large for the per-configuration gradient tile");
