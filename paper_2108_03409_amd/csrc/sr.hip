@@ -106,13 +106,28 @@ __global__ __launch_bounds__(256) void k_col_partial(const InT* __restrict__ O, 
   partial[(int64_t)blockIdx.y * K + k] = acc;
 }
 
-__global__ void k_reduce_partial(const double2* __restrict__ partial, int nchunk, int64_t K,
-                                 const double* __restrict__ stats, double2* __restrict__ out) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= K) return;
+// Column sums of the per-chunk partials: a group of 16 waves owns 64 columns;
+// wave w adds chunks w, w + 16, ... in order and the 16 wave sums are combined
+// in wave order (deterministic).  out[k] = scale * sum_c partial[c][k], scale =
+// 1 / stats[0] when stats is given.
+constexpr int kRedWaves = 16;
+
+__global__ __launch_bounds__(64 * kRedWaves) void k_reduce_cols(const double2* __restrict__ partial, int nchunk,
+                                                                int64_t K, const double* __restrict__ stats,
+                                                                double2* __restrict__ out) {
+  __shared__ double2 red[kRedWaves][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t k = blockIdx.x * 64ll + lane;
   double2 acc = make_double2(0.0, 0.0);
-  for (int c = 0; c < nchunk; ++c) acc = cadd(acc, partial[(int64_t)c * K + k]);
-  out[k] = cscale(acc, 1.0 / stats[0]);
+  if (k < K)
+    for (int c = wave; c < nchunk; c += kRedWaves) acc = cadd(acc, partial[(int64_t)c * K + k]);
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && k < K) {
+    double2 s = red[0][lane];
+    for (int w = 1; w < kRedWaves; ++w) s = cadd(s, red[w][lane]);
+    out[k] = stats ? cscale(s, 1.0 / stats[0]) : s;
+  }
 }
 
 // Xc[n][k] = sqrt(w_n / wsum) (O_nk - mean_k); Fpartial[chunk][k] = sum w_n conj(O_nk - mean_k) (E_n - Ebar)
@@ -182,13 +197,6 @@ __global__ __launch_bounds__(256) void k_center_force_pair(const InT* __restrict
   Fpartial[(int64_t)blockIdx.y * K + k] = acc;
 }
 
-__global__ void k_reduce_plain(const double2* __restrict__ partial, int nchunk, int64_t K, double2* __restrict__ out) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= K) return;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int c = 0; c < nchunk; ++c) acc = cadd(acc, partial[(int64_t)c * K + k]);
-  out[k] = acc;
-}
 
 // S[r][c] = sum_n conj(Xc[n][r]) Xc[n][c] for the 32x32 tile (r >= c block-wise),
 // written to both triangles; projection and shift applied here.
@@ -755,7 +763,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
     k_col_partial<float><<<cg, 256, 0, st>>>((const float*)O, w, N, K, partial);
   else
     k_col_partial<double><<<cg, 256, 0, st>>>((const double*)O, w, N, K, partial);
-  k_reduce_partial<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, stats, mean);
+  k_reduce_cols<<<(unsigned)((K + 63) / 64), 64 * kRedWaves, 0, st>>>(partial, nchunk, K, stats, mean);
   if (dtype == VMC_DT_C64)
     k_center_force<float2, float2><<<cg, 256, 0, st>>>((const float2*)O, w, eloc, N, K, mean, stats, (float2*)Xc,
                                                         partial);
@@ -768,7 +776,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   else
     k_center_force_pair<double, double2><<<cg, 256, 0, st>>>((const double*)O, w, eloc, N, K, mean, stats,
                                                               (double2*)Xc, partial);
-  k_reduce_plain<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, F);
+  k_reduce_cols<<<(unsigned)((K + 63) / 64), 64 * kRedWaves, 0, st>>>(partial, nchunk, K, nullptr, F);
   VMC_HIP(hipGetLastError());
   ph.reset();
 
@@ -947,7 +955,7 @@ double fisher_quad_impl(vmc_ctx* ctx, const void* O, int dtype, const double* w,
     k_col_partial<float><<<cg, 256, 0, st>>>((const float*)O, w, N, K, partial);
   else
     k_col_partial<double><<<cg, 256, 0, st>>>((const double*)O, w, N, K, partial);
-  k_reduce_partial<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, stats, mean);
+  k_reduce_cols<<<(unsigned)((K + 63) / 64), 64 * kRedWaves, 0, st>>>(partial, nchunk, K, stats, mean);
   k_conj<<<grid_for(K, 256), 256, 0, st>>>(mean, K, cmean);
   k_cg_dot<<<1, 1024, 0, st>>>(cmean, v, nullptr, K, sc + 8);  // <O> . v
   k_sqw<<<grid_for(N, 256), 256, 0, st>>>(w, N, stats, sq);
@@ -1008,15 +1016,15 @@ void sr_solve_cg_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* elo
     k_col_partial<float2><<<cg, 256, 0, st>>>((const float2*)O, w, N, K, partial);
   else
     k_col_partial<double2><<<cg, 256, 0, st>>>((const double2*)O, w, N, K, partial);
-  k_reduce_partial<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, stats, mean);
+  k_reduce_cols<<<(unsigned)((K + 63) / 64), 64 * kRedWaves, 0, st>>>(partial, nchunk, K, stats, mean);
   k_conj<<<grid_for(K, 256), 256, 0, st>>>(mean, K, cmean);
   k_sqw<<<grid_for(N, 256), 256, 0, st>>>(w, N, stats, sq);
   if (f32)
     k_force_diag<float2><<<cg, 256, 0, st>>>((const float2*)O, sq, eloc, N, K, mean, stats, partial, partial2);
   else
     k_force_diag<double2><<<cg, 256, 0, st>>>((const double2*)O, sq, eloc, N, K, mean, stats, partial, partial2);
-  k_reduce_plain<<<grid_for(K, 256), 256, 0, st>>>(partial, nchunk, K, F);
-  k_reduce_plain<<<grid_for(K, 256), 256, 0, st>>>(partial2, nchunk, K, dSc);
+  k_reduce_cols<<<(unsigned)((K + 63) / 64), 64 * kRedWaves, 0, st>>>(partial, nchunk, K, nullptr, F);
+  k_reduce_cols<<<(unsigned)((K + 63) / 64), 64 * kRedWaves, 0, st>>>(partial2, nchunk, K, nullptr, dSc);
   k_take_real<<<grid_for(K, 256), 256, 0, st>>>(dSc, K, dS);
   k_rhs<<<grid_for(K, 256), 256, 0, st>>>(F, K, o->gamma_re, o->gamma_im, o->mode, b);
   VMC_HIP(hipGetLastError());
