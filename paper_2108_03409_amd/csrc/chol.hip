@@ -111,36 +111,33 @@ __global__ __launch_bounds__(CD_NT) void k_chol_diag(double2* __restrict__ A, in
     const int r = e / CB, c = e % CB;
     if (c <= r && r < nb) A[(kb0 + r) * K + kb0 + c] = L[pk(r, c)];
   }
-  // Inverse X = L^{-1} column by column, eight lanes per column (an aligned
-  // 8-lane group of a wave): X_cc = 1 / L_cc, X_rc = -(1 / L_rr) sum_{m=c}^{r-1}
-  // L_rm X_mc, each lane with four independent partial sums.  A column depends
-  // only on itself, so the group needs no barrier; its lane 0 writes X_rc and
-  // the group reads it back in later rows (same wave, ordered by a fence).
-  const int cc = tid >> 3, qq = tid & 7;
-  if (qq == 0) X[pk(cc, cc)] = make_double2(1.0 / L[pk(cc, cc)].x, 0.0);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int r = cc + 1; r < CB; ++r) {  // trip count differs per group, shuffles stay inside it
-    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
-    int m = cc + qq;
-    for (; m + 24 < r; m += 32) {
-      a0 = cadd(a0, cmul(L[pk(r, m)], X[pk(m, cc)]));
-      a1 = cadd(a1, cmul(L[pk(r, m + 8)], X[pk(m + 8, cc)]));
-      a2 = cadd(a2, cmul(L[pk(r, m + 16)], X[pk(m + 16, cc)]));
-      a3 = cadd(a3, cmul(L[pk(r, m + 24)], X[pk(m + 24, cc)]));
-    }
-    for (; m < r; m += 8) a0 = cadd(a0, cmul(L[pk(r, m)], X[pk(m, cc)]));
-    double2 acc = cadd(cadd(a0, a1), cadd(a2, a3));
+  // Inverse X = L^{-1}, right-looking like the elimination, one barrier per
+  // step: B = I; at step k every row i > k takes B_ic -= (L_ik / L_kk) B_kc for
+  // c <= k (row k is final after step k - 1 and is only read); finally
+  // X_ic = B_ic / L_ii.
+  for (int e = tid; e < CB * CB; e += CD_NT) {
+    const int r = e / CB, c = e % CB;
+    if (c <= r) X[pk(r, c)] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < CB - 1; ++k) {
+    const double ik = 1.0 / L[pk(k, k)].x;
 #pragma unroll
-    for (int o = 4; o > 0; o >>= 1) {
-      acc.x += __shfl_xor(acc.x, o, 8);
-      acc.y += __shfl_xor(acc.y, o, 8);
+    for (int aa = 0; aa < 2; ++aa) {
+      const int r = ty + 32 * aa;
+      if (r <= k) continue;
+      const double2 f = cscale(L[pk(r, k)], ik);
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const int c = tx + 16 * bb;
+        if (c <= k) X[pk(r, c)] = csub(X[pk(r, c)], cmul(f, X[pk(k, c)]));
+      }
     }
-    if (qq == 0) X[pk(r, cc)] = cscale(acc, -1.0 / L[pk(r, r)].x);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __syncthreads();
+  }
+  for (int e = tid; e < CB * CB; e += CD_NT) {
+    const int r = e / CB, c = e % CB;
+    if (c <= r) X[pk(r, c)] = cscale(X[pk(r, c)], 1.0 / L[pk(r, r)].x);
   }
   __syncthreads();
   for (int e = tid; e < CB * CB; e += CD_NT) {
