@@ -16,9 +16,14 @@
 //                 on a second stream, overlapping the next panel's
 //                 factorisation; the trailing matrix is read and written once
 //                 per 256 columns.
-// The complex products use two real accumulators per 16x16 block held in the
-// same lanes: re += Pr Qr + Pi Qi and im += Pi Qr + Pr (-Qi) for P conj(Q).  A non-positive pivot sets the fail index; every later kernel
-// then exits at once.  The upper triangle of S~ is never written.
+// The complex products P conj(Q) take three real products per term (Gauss's
+// identity, as in the 3M complex GEMM): with A = sum Pr Qr, B = sum Pi Qi and
+// C = sum (Pr + Pi)(Qr - Qi), held in three accumulators at the same lanes,
+//   Re = A + B,   Im = C - A + B,
+// so a 16x16 complex block costs three float64 MFMAs per 4 reduction columns
+// instead of four; the error bound of Im grows by at most a factor of about 2.
+// A non-positive pivot sets the fail index; every later kernel then exits at
+// once.  The upper triangle of S~ is never written.
 //
 // Triangular solves: one launch per block; every group recomputes the 64-entry
 // block solution from L_bb^{-1} (a 64 x 64 product) and then updates its share
@@ -166,7 +171,7 @@ struct zargs {
 // MODE 2 (inside panel):  as MODE 1 for R >= rbase, cbase <= C < cend, C <= R (rectangular tile grid)
 // The reduction is staged 16 columns at a time through double-buffered LDS.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_zmfma(zargs a) {
+__global__ __launch_bounds__(256, 2) void k_zmfma(zargs a) {
   __shared__ double2 Ps[2][16][CB + 1];
   __shared__ double2 Qs[2][16][CB + 1];
   if (*a.fail >= 0) return;
@@ -193,13 +198,13 @@ __global__ __launch_bounds__(256) void k_zmfma(zargs a) {
   const int wr = wave >> 1, wc = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
 
-  doublex4 acc[2][2][2];
+  doublex4 acc[2][2][3];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int q = 0; q < 2; ++q) acc[i][j][q] = doublex4{0.0, 0.0, 0.0, 0.0};
+      for (int q = 0; q < 3; ++q) acc[i][j][q] = doublex4{0.0, 0.0, 0.0, 0.0};
 
   double2 rp[4], rq[4];
   auto gload = [&](int m0) {
@@ -237,18 +242,24 @@ __global__ __launch_bounds__(256) void k_zmfma(zargs a) {
     for (int ks = 0; ks < 4; ++ks) {
       const int m = ks * 4 + lk;
       double2 fa[2], fb[2];
+      double sa[2], db[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) fa[i] = Ps[buf][m][wr * 32 + i * 16 + li];
+      for (int i = 0; i < 2; ++i) {
+        fa[i] = Ps[buf][m][wr * 32 + i * 16 + li];
+        sa[i] = fa[i].x + fa[i].y;
+      }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) fb[j] = Qs[buf][m][wc * 32 + j * 16 + li];
+      for (int j = 0; j < 2; ++j) {
+        fb[j] = Qs[buf][m][wc * 32 + j * 16 + li];
+        db[j] = fb[j].x - fb[j].y;
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           acc[i][j][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].x, fb[j].x, acc[i][j][0], 0, 0, 0);
-          acc[i][j][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].y, acc[i][j][0], 0, 0, 0);
-          acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].x, acc[i][j][1], 0, 0, 0);
-          acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].x, -fb[j].y, acc[i][j][1], 0, 0, 0);
+          acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i].y, fb[j].y, acc[i][j][1], 0, 0, 0);
+          acc[i][j][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[i], db[j], acc[i][j][2], 0, 0, 0);
         }
     }
     if (st + 1 < nst) sstore(buf ^ 1);
@@ -264,8 +275,8 @@ __global__ __launch_bounds__(256) void k_zmfma(zargs a) {
         // D[l / 16 + 4 r][l % 16] (float32 holds D[4 (l / 16) + r][l % 16])
         const int row = wr * 32 + i * 16 + lk + 4 * r;
         const int col = wc * 32 + j * 16 + li;
-        const double re = acc[i][j][0][r];
-        const double im = acc[i][j][1][r];
+        const double re = acc[i][j][0][r] + acc[i][j][1][r];
+        const double im = (acc[i][j][2][r] - acc[i][j][0][r]) + acc[i][j][1][r];
         const int64_t R = r0 + row;
         if (R >= K) continue;
         if (MODE == 0) {
