@@ -98,6 +98,32 @@ def test_sr_solve_eig_matches_oracle(ctx, N, Nh, ns, mode, gamma, nu, frac, soft
     assert abs(info["residual"] - info_ref["residual"]) <= 1e-8 + 1e-6 * info_ref["residual"]
 
 
+@pytest.mark.parametrize("N,Nh,ns", [(12, 48, 333), (9, 21, 1001)])
+def test_gram_c64_eigenvalues_within_bound(ctx, N, Nh, ns):
+    # S from complex64 O on the float32 matrix cores (three real products per
+    # complex term).  K = 636 (even) takes the direct-to-LDS Gram kernel, K = 219
+    # (odd) the register-staged one; both sample counts are ragged.  Weyl:
+    # |d lambda| <= ||dS||_2 <= ||dS||_F, with |dS_kk'| <= 2 (N_s + 8) u M_kk',
+    # M = |Obar|^T |Obar| (the factor 2 covers the imaginary part of the
+    # three-product form, whose terms are bounded by 2 |Obar_k| |Obar_k'|).
+    flush(f"gram c64 eigenvalues N={N} Nh={Nh} ns={ns}")
+    O, el = _problem(N, Nh, ns, 0.2, seed=N + Nh, cplx=True)
+    O32 = O.astype(np.complex64)
+    Od = O32.astype(np.complex128)
+    _, info_ref = osr.eigen_solve(Od, el, nu_rel=1e-2, mode="complex", eps_pinv=1e-8)
+    _, info = V.sr_solve_eig(ctx, torch.from_numpy(O32).to(DEV), dev_c128(el), nu_rel=1e-2, mode=V.SR_COMPLEX,
+                             eps_pinv=1e-8)
+    ev = np.sort(info["evals"].cpu().numpy())
+    Ob = (Od - Od.mean(axis=0)) / np.sqrt(ns)
+    M = np.abs(Ob).T @ np.abs(Ob)
+    bound = 1.01 * np.linalg.norm(2.0 * (ns + 8) * 2.0 ** -24 * M)
+    err = np.max(np.abs(ev - info_ref["evals"]))
+    assert err <= bound, (err, bound)
+    # a wrong sign or a dropped term in the three-product form moves the
+    # spectrum by O(||S||), far beyond float32 rounding
+    assert err <= 1e-5 * np.abs(info_ref["evals"]).max(), err
+
+
 def test_sr_solve_eig_real_o_float32(ctx):
     # real log-derivatives in float32: S from the matrix cores, eigen solve in float64
     flush("sr eig real O f32")
