@@ -285,6 +285,9 @@ __global__ __launch_bounds__(256, 2) void k_herk_mfma_f32(herk_args a) {
 // 16-byte aligned, so that a lane's two values are both inside or both outside.
 __device__ float4 g_zero16 = {0.f, 0.f, 0.f, 0.f};
 
+// samples per stage of the direct-to-LDS kernel and its resident waves per SIMD
+constexpr int kDmaStage = 12, kDmaOcc = 3;
+
 typedef __attribute__((address_space(1))) const void* gptr_t;
 typedef __attribute__((address_space(3))) void* lptr_t;
 
@@ -296,13 +299,13 @@ using accs_c = floatx4[4][herk_shape<false>::JN][herk_shape<false>::QN];
 // The compiler makes any LDS read that follows a direct-to-LDS load wait for
 // it; with the reads first, that wait falls on the next stage's first read,
 // after the barrier, so the loads overlap the whole stage's products.
-template <bool COMPUTE>
+template <int SD, bool COMPUTE>
 __device__ __forceinline__ void herk_c_stage(const float2* Ac, const float2* Bc, float2* An, float2* Bn,
                                              const float2* __restrict__ X, int64_t N, int64_t K, int64_t n0,
                                              bool load_next, int64_t row0, int64_t col0, int wave, int lane,
                                              accs_c& acc) {
   using sh = herk_shape<false>;
-  constexpr int BN = sh::BN, JN = sh::JN, NKS = BK / 4;
+  constexpr int BN = sh::BN, JN = sh::JN, NKS = SD / 4;
   const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
   float2 fa[NKS][4], fb[NKS][JN];
   if constexpr (COMPUTE) {
@@ -316,19 +319,18 @@ __device__ __forceinline__ void herk_c_stage(const float2* Ac, const float2* Bc,
     }
   }
   if (load_next) {
-    // wave w loads A rows 4w .. 4w + 3 (one per instruction) and B rows
-    // 4w .. 4w + 3 (two per instruction) of the stage starting at sample n0
+    // wave w loads A rows w, w + 4, ... (one per instruction) and B row pairs
+    // w, w + 4, ... (two rows per instruction) of the stage starting at sample n0
     const float2* zero = (const float2*)&g_zero16;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int n = wave * 4 + t;
+    for (int n = wave; n < SD; n += 4) {
       const int64_t gn = n0 + n, c = row0 + 2 * lane;
       const float2* src = (gn < N && c < K) ? X + gn * K + c : zero;
       __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)(An + n * BM), 16, 0, 0);
     }
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int n = wave * 4 + 2 * t;
+    for (int pr = wave; pr < SD / 2; pr += 4) {
+      const int n = 2 * pr;
       const int64_t gn = n0 + n + (lane >> 5), c = col0 + 2 * (lane & 31);
       const float2* src = (gn < N && c < K) ? X + gn * K + c : zero;
       __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)(Bn + n * BN), 16, 0, 0);
@@ -354,11 +356,12 @@ __device__ __forceinline__ void herk_c_stage(const float2* Ac, const float2* Bc,
   }
 }
 
-__global__ __launch_bounds__(256, 2) void k_herk_c_dma(herk_args a) {
+template <int SD, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_herk_c_dma(herk_args a) {
   using sh = herk_shape<false>;
   constexpr int BN = sh::BN, JN = sh::JN, QN = sh::QN;
-  __shared__ float2 As[2][BK * BM];
-  __shared__ float2 Bs[2][BK * BN];
+  __shared__ float2 As[2][SD * BM];
+  __shared__ float2 Bs[2][SD * BN];
 
   const int64_t nb = a.n_tiles;
   const int64_t lin = remap_tile(blockIdx.x, nb);
@@ -381,19 +384,22 @@ __global__ __launch_bounds__(256, 2) void k_herk_c_dma(herk_args a) {
 #pragma unroll
       for (int q = 0; q < QN; ++q) acc[i][j][q] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+  // the sample range of this split, as in the register-staged kernel (stages
+  // of BK samples), walked in stages of SD samples
   const int64_t n_stages = (N + BK - 1) / BK;
   const int64_t sp = (n_stages + a.ksplit - 1) / a.ksplit;
-  const int64_t st0 = blockIdx.y * sp, st1 = min(n_stages, st0 + sp);
+  const int64_t s0 = min(N, blockIdx.y * sp * BK), s1 = min(N, (blockIdx.y + 1) * sp * BK);
+  const int64_t st0 = 0, st1 = (s1 - s0 + SD - 1) / SD;
   if (st0 < st1) {  // uniform over the group
     // first stage into buffer 0 (loads only)
-    herk_c_stage<false>(As[1], Bs[1], As[0], Bs[0], a.X, N, K, st0 * BK, true, row0, col0, wave, lane, acc);
+    herk_c_stage<SD, false>(As[1], Bs[1], As[0], Bs[0], a.X, s1, K, s0, true, row0, col0, wave, lane, acc);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     for (int64_t st = st0; st < st1; ++st) {
       const int buf = (int)((st - st0) & 1);
       // the other buffer was released by every wave at the previous barrier
-      herk_c_stage<true>(As[buf], Bs[buf], As[buf ^ 1], Bs[buf ^ 1], a.X, N, K, (st + 1) * BK, st + 1 < st1, row0, col0,
-                   wave, lane, acc);
+      herk_c_stage<SD, true>(As[buf], Bs[buf], As[buf ^ 1], Bs[buf ^ 1], a.X, s1, K, s0 + (st + 1) * SD, st + 1 < st1,
+                             row0, col0, wave, lane, acc);
       __builtin_amdgcn_sched_barrier(0);  // the wait below stays after the products
       __builtin_amdgcn_s_waitcnt(0);      // this wave's rows of the next stage have landed
       __syncthreads();                // and every wave is done with this stage
@@ -495,7 +501,7 @@ void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode
   if (real)
     k_herk_mfma_f32<true><<<g, 256, 0, ctx->stream>>>(a);
   else if (K % 2 == 0 && (uintptr_t)X % 16 == 0)
-    k_herk_c_dma<<<g, 256, 0, ctx->stream>>>(a);
+    k_herk_c_dma<kDmaStage, kDmaOcc><<<g, 256, 0, ctx->stream>>>(a);
   else
     k_herk_mfma_f32<false><<<g, 256, 0, ctx->stream>>>(a);
   VMC_HIP(hipGetLastError());
