@@ -25,9 +25,10 @@
 // A non-positive pivot sets the fail index; every later kernel then exits at
 // once.  The upper triangle of S~ is never written.
 //
-// Triangular solves: one launch per block; every group recomputes the 64-entry
-// block solution from L_bb^{-1} (a 64 x 64 product) and then updates its share
-// of the remaining right-hand side.
+// Triangular solves: one launch per block.  Launch b updates the remaining
+// right-hand side with block b's solution (64 rows or columns per group, a
+// quad or a wave per 16 terms); the group that holds the next block's entries,
+// final after its update, forms that block's solution from L_bb^{-1}.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -291,61 +292,133 @@ __global__ __launch_bounds__(256, 2) void k_zmfma(zargs a) {
       }
 }
 
-// forward step of block b: y_b = Linv_b rhs_b; rhs[R] -= sum_m L[R][kb0+m] y_b[m] for R >= kb0 + 64
-__global__ __launch_bounds__(256) void k_fwd_step(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
-                                                  const double2* __restrict__ Linv, double2* __restrict__ rhs,
-                                                  double2* __restrict__ y) {
-  __shared__ double2 yb[CB];
-  __shared__ double2 part[4][CB];
-  const int tid = threadIdx.x;
-  {
-    const int r = tid & 63, q = tid >> 6;  // 4 partial sums over m per row
-    double2 acc = make_double2(0.0, 0.0);
-    for (int m = q; m <= r; m += 4)
-      if (m < nb) acc = cadd(acc, cmul(Linv[r * CB + m], rhs[kb0 + m]));
-    part[q][r] = acc;
-  }
-  __syncthreads();
-  if (tid < CB) {
-    const double2 s = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
-    yb[tid] = tid < nb ? s : make_double2(0.0, 0.0);
-    if (blockIdx.x == 0 && tid < nb) y[kb0 + tid] = s;
-  }
-  __syncthreads();
-  const int64_t R = kb0 + CB + (int64_t)blockIdx.x * 256 + tid;
-  if (R >= K) return;
-  const double2* row = A + R * K + kb0;
-  double2 acc = rhs[R];
-  for (int m = 0; m < nb; ++m) acc = csub(acc, cmul(row[m], yb[m]));
-  rhs[R] = acc;
+__device__ __forceinline__ double2 shfl_xor2(double2 v, int o) {
+  return make_double2(__shfl_xor(v.x, o, 64), __shfl_xor(v.y, o, 64));
 }
 
-// backward step of block b: x_b = Linv_b^H v_b; v[c] -= sum_m conj(L[kb0+m][c]) x_b[m] for c < kb0
-__global__ __launch_bounds__(256) void k_bwd_step(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
-                                                  const double2* __restrict__ Linv, double2* __restrict__ v,
-                                                  double2* __restrict__ x) {
+// sum over the four lanes q = lane % 4 of a quad
+__device__ __forceinline__ double2 quad_sum(double2 v) {
+  v = cadd(v, shfl_xor2(v, 1));
+  return cadd(v, shfl_xor2(v, 2));
+}
+
+// y_0 = Linv_0 rhs_0 (one group; thread (r, q) = (tid / 4, tid % 4) sums m = q, q + 4, ...)
+__global__ __launch_bounds__(256) void k_fwd_first(const double2* __restrict__ Linv, const double2* __restrict__ rhs,
+                                                   double2* __restrict__ y, int nb) {
+  const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
+  double2 s = make_double2(0.0, 0.0);
+  for (int m = q; m <= r && m < nb; m += 4) s = cadd(s, cmul(Linv[r * CB + m], rhs[m]));
+  s = quad_sum(s);
+  if (q == 0 && r < nb) y[r] = s;
+}
+
+// Forward update of block b (y_b in y): rhs[R] -= sum_m L[R][kb0 + m] y_b[m] for
+// R >= kb0 + 64, 64 rows per group, thread (r, q) summing m = q, q + 4, ...
+// (each quad reads 64 contiguous bytes of its row per step).  Group 0 holds the
+// rows of block b + 1, which are then final: it also forms
+// y_{b+1} = Linv_{b+1} rhs_{b+1}.
+__global__ __launch_bounds__(256) void k_fwd_update(const double2* __restrict__ A, int64_t K, int64_t kb0,
+                                                    const double2* __restrict__ Linv_next, int nb_next,
+                                                    double2* __restrict__ rhs, double2* __restrict__ y) {
+  __shared__ double2 yb[CB];
+  __shared__ double2 rs[CB];
+  const int tid = threadIdx.x;
+  const int r = tid >> 2, q = tid & 3;
+  // group 0: this thread's entries of Linv_{b+1} (m = q + 4 t <= r), loaded
+  // first so that they arrive while the rows are updated
+  double2 lv[CB / 4];
+  if (blockIdx.x == 0) {
+#pragma unroll
+    for (int t = 0; t < CB / 4; ++t) {
+      const int m = q + 4 * t;
+      lv[t] = (m <= r && m < nb_next) ? Linv_next[r * CB + m] : make_double2(0.0, 0.0);
+    }
+  }
+  if (tid < CB) yb[tid] = y[kb0 + tid];
+  __syncthreads();
+  const int64_t R = kb0 + CB + (int64_t)blockIdx.x * CB + r;
+  double2 acc = make_double2(0.0, 0.0);
+  if (R < K) {
+    const double2* row = A + R * K + kb0;
+#pragma unroll
+    for (int j = 0; j < CB / 4; ++j) acc = cadd(acc, cmul(row[4 * j + q], yb[4 * j + q]));
+  }
+  acc = quad_sum(acc);
+  double2 nv = make_double2(0.0, 0.0);
+  if (R < K && q == 0) {
+    nv = csub(rhs[R], acc);
+    rhs[R] = nv;
+  }
+  if (blockIdx.x != 0) return;  // uniform over the group
+  if (q == 0) rs[r] = nv;
+  __syncthreads();
+  double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int t = 0; t < CB / 4; ++t) s = cadd(s, cmul(lv[t], rs[q + 4 * t]));
+  s = quad_sum(s);
+  if (q == 0 && r < nb_next) y[kb0 + CB + r] = s;
+}
+
+// x_b = Linv_b^H v_b for the last block b (one group): (Linv^H)[r][m] = conj(Linv[m][r]), m >= r
+__global__ __launch_bounds__(256) void k_bwd_first(const double2* __restrict__ Linv, const double2* __restrict__ v,
+                                                   double2* __restrict__ x, int nb) {
+  const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
+  double2 s = make_double2(0.0, 0.0);
+  for (int m = r + q; m < nb; m += 4) s = cadd(s, cmul(cconj(Linv[m * CB + r]), v[m]));
+  s = quad_sum(s);
+  if (q == 0 && r < nb) x[r] = s;
+}
+
+// Backward update of block b (x_b in x): v[c] -= sum_m conj(L[kb0 + m][c]) x_b[m]
+// for c < kb0, 64 columns per group, wave q summing m = 16 q .. 16 q + 15 (each
+// step reads 64 consecutive columns of one row).  The last group holds the
+// columns of block b - 1, which are then final: it also forms
+// x_{b-1} = Linv_{b-1}^H v_{b-1}.
+__global__ __launch_bounds__(256) void k_bwd_update(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
+                                                    const double2* __restrict__ Linv_prev, double2* __restrict__ v,
+                                                    double2* __restrict__ x) {
   __shared__ double2 xb[CB];
   __shared__ double2 part[4][CB];
+  __shared__ double2 vs[CB];
   const int tid = threadIdx.x;
-  {
-    const int r = tid & 63, q = tid >> 6;
-    double2 acc = make_double2(0.0, 0.0);
-    // (Linv^H)[r][m] = conj(Linv[m][r]), non-zero for m >= r
-    for (int m = r + q; m < nb; m += 4) acc = cadd(acc, cmul(cconj(Linv[m * CB + r]), v[kb0 + m]));
-    part[q][r] = acc;
+  const int r = tid >> 2, q4 = tid & 3;
+  // last group: this thread's entries conj(Linv_{b-1}[m][r]) (m = r + q4 + 4 t < 64),
+  // loaded first so that they arrive while the columns are updated
+  double2 lv[CB / 4];
+  if (blockIdx.x == gridDim.x - 1) {
+#pragma unroll
+    for (int t = 0; t < CB / 4; ++t) {
+      const int m = r + q4 + 4 * t;
+      lv[t] = m < CB ? cconj(Linv_prev[m * CB + r]) : make_double2(0.0, 0.0);
+    }
   }
+  if (tid < CB) xb[tid] = tid < nb ? x[kb0 + tid] : make_double2(0.0, 0.0);
+  __syncthreads();
+  const int cl = tid & 63, q = tid >> 6;
+  const int64_t c = (int64_t)blockIdx.x * CB + cl;  // < kb0: the grid covers kb0 / 64 column blocks
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int j = 0; j < CB / 4; ++j) {
+    const int m = q * (CB / 4) + j;
+    if (m < nb) acc = cadd(acc, cmul(cconj(A[(kb0 + m) * K + c]), xb[m]));
+  }
+  part[q][cl] = acc;
   __syncthreads();
   if (tid < CB) {
-    const double2 s = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
-    xb[tid] = tid < nb ? s : make_double2(0.0, 0.0);
-    if (blockIdx.x == 0 && tid < nb) x[kb0 + tid] = s;
+    const double2 nv = csub(v[c], cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid])));
+    v[c] = nv;
+    vs[tid] = nv;
   }
+  if (blockIdx.x != gridDim.x - 1) return;  // uniform over the group
   __syncthreads();
-  const int64_t c = (int64_t)blockIdx.x * 256 + tid;
-  if (c >= kb0) return;
-  double2 acc = v[c];
-  for (int m = 0; m < nb; ++m) acc = csub(acc, cmul(cconj(A[(kb0 + m) * K + c]), xb[m]));
-  v[c] = acc;
+  double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int t = 0; t < CB / 4; ++t) {
+    const int m = r + q4 + 4 * t;
+    if (m < CB) s = cadd(s, cmul(lv[t], vs[m]));
+  }
+  s = quad_sum(s);
+  if (q4 == 0) x[kb0 - CB + r] = s;
 }
 
 }  // namespace
@@ -433,18 +506,22 @@ void chol_factor(vmc_ctx* ctx, double2* S, int64_t K, double2* Linv, long long* 
 void chol_solve(vmc_ctx* ctx, const double2* S, int64_t K, const double2* Linv, double2* rhs, double2* y, double2* x) {
   hipStream_t st = ctx->stream;
   const int nblk = (int)((K + CB - 1) / CB);
-  for (int b = 0; b < nblk; ++b) {
+  auto nb_of = [&](int b) { return (int)std::min<int64_t>(CB, K - (int64_t)b * CB); };
+  // L y = rhs: y_0 first; launch b updates the rows below block b and forms y_{b+1}
+  k_fwd_first<<<1, 256, 0, st>>>(Linv, rhs, y, nb_of(0));
+  for (int b = 0; b + 1 < nblk; ++b) {
     const int64_t kb0 = (int64_t)b * CB;
-    const int nb = (int)std::min<int64_t>(CB, K - kb0);
-    const int64_t rest = std::max<int64_t>(0, K - kb0 - CB);
-    k_fwd_step<<<(unsigned)std::max<int64_t>(1, (rest + 255) / 256), 256, 0, st>>>(S, K, kb0, nb,
-                                                                                   Linv + (size_t)b * CB * CB, rhs, y);
+    const int64_t rows = K - kb0 - CB;
+    k_fwd_update<<<(unsigned)((rows + CB - 1) / CB), 256, 0, st>>>(S, K, kb0, Linv + (size_t)(b + 1) * CB * CB,
+                                                                    nb_of(b + 1), rhs, y);
   }
-  for (int b = nblk - 1; b >= 0; --b) {
+  // L^H x = y (in place in y): x of the last block first; launch b updates the
+  // columns left of block b and forms x_{b-1}
+  const int64_t kl = (int64_t)(nblk - 1) * CB;
+  k_bwd_first<<<1, 256, 0, st>>>(Linv + (size_t)(nblk - 1) * CB * CB, y + kl, x + kl, nb_of(nblk - 1));
+  for (int b = nblk - 1; b >= 1; --b) {
     const int64_t kb0 = (int64_t)b * CB;
-    const int nb = (int)std::min<int64_t>(CB, K - kb0);
-    k_bwd_step<<<(unsigned)std::max<int64_t>(1, (kb0 + 255) / 256), 256, 0, st>>>(S, K, kb0, nb,
-                                                                                  Linv + (size_t)b * CB * CB, y, x);
+    k_bwd_update<<<(unsigned)b, 256, 0, st>>>(S, K, kb0, nb_of(b), Linv + (size_t)(b - 1) * CB * CB, y, x);
   }
   VMC_HIP(hipGetLastError());
 }
