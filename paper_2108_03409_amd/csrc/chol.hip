@@ -46,7 +46,8 @@ constexpr int CB = 64;  // block size
 __device__ __forceinline__ int pk(int r, int c) { return r * (r + 1) / 2 + c; }  // packed lower index
 
 // Factor and invert the diagonal block at kb0 (nb <= 64 valid rows/cols; the
-// rest is padded with the identity).  LDS holds the packed lower triangle.
+// rest is padded with the identity).  LDS holds the packed lower triangles of
+// the block (L) and of its inverse (X).
 constexpr int CD_NT = 512;  // threads of the diagonal-block kernel
 
 __global__ __launch_bounds__(CD_NT) void k_chol_diag(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
@@ -55,24 +56,41 @@ __global__ __launch_bounds__(CD_NT) void k_chol_diag(double2* __restrict__ A, in
   __shared__ double2 L[CB * (CB + 1) / 2];
   __shared__ double2 X[CB * (CB + 1) / 2];
   __shared__ double dpiv[CB];
+  __shared__ double sq[CB], isq[CB];
   if (*fail >= 0) return;
   const int tid = threadIdx.x;
-  for (int e = tid; e < CB * CB; e += CD_NT) {
-    const int r = e / CB, c = e % CB;
-    if (c > r) continue;
-    double2 x;
-    if (r < nb)
-      x = A[(kb0 + r) * K + kb0 + c];
-    else
-      x = make_double2(r == c ? 1.0 : 0.0, 0.0);
-    L[pk(r, c)] = x;
+  // thread (ty, tx) owns rows ty + 32 a, columns tx + 16 b of both triangles
+  const int ty = tid >> 4, tx = tid & 15;
+  {
+    double2 v[2][4];
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const int r = ty + 32 * aa, c = tx + 16 * bb;
+        v[aa][bb] = (c <= r && r < nb) ? A[(kb0 + r) * K + kb0 + c] : make_double2(r == c ? 1.0 : 0.0, 0.0);
+      }
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const int r = ty + 32 * aa, c = tx + 16 * bb;
+        if (c <= r) {
+          L[pk(r, c)] = v[aa][bb];
+          X[pk(r, c)] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+        }
+      }
   }
   __syncthreads();
-  // Right-looking elimination on the unscaled Schur complement, one barrier per
-  // column: A_rc -= A_rj conj(A_cj) / A_jj for j < c <= r (column j is only read
-  // in its step); the pivots d_j = A_jj are kept and L_rj = A_rj / sqrt(d_j) is
-  // formed afterwards.  Thread (ty, tx) owns rows ty + 32a, columns tx + 16b.
-  const int ty = tid >> 4, tx = tid & 15;
+  // Right-looking elimination on the unscaled Schur complement and the inverse
+  // of the unit-lower factor together, one barrier per column j.  With
+  // f_r = A_rj / A_jj (the multiplier of row r, which equals L_rj / L_jj):
+  //   A_rc -= f_r conj(A_cj)   for j < c <= r   (elimination),
+  //   B_rc -= f_r B_jc         for c <= j < r   (B = I at the start; row j of B
+  //                                              is final after step j - 1).
+  // Column j of A and row j of B are only read in step j, and the two updates
+  // write disjoint entries.  Afterwards L_rc = A_rc / sqrt(d_c), L_cc = sqrt(d_c)
+  // and L^{-1}_rc = B_rc / sqrt(d_r), with the pivots d_j = A_jj kept.
   int bad = -1;
   double pmin = INFINITY;
   for (int j = 0; j < CB; ++j) {
@@ -90,11 +108,15 @@ __global__ __launch_bounds__(CD_NT) void k_chol_diag(double2* __restrict__ A, in
     for (int aa = 0; aa < 2; ++aa) {
       const int r = ty + 32 * aa;
       if (r <= j) continue;
-      const double2 lr = cscale(L[pk(r, j)], id);
+      const double2 f = cscale(L[pk(r, j)], id);
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
         const int c = tx + 16 * bb;
-        if (c > j && c <= r) L[pk(r, c)] = csub(L[pk(r, c)], cmul(lr, cconj(L[pk(c, j)])));
+        if (c > r) continue;
+        if (c > j)
+          L[pk(r, c)] = csub(L[pk(r, c)], cmul(f, cconj(L[pk(c, j)])));
+        else
+          X[pk(r, c)] = csub(X[pk(r, c)], cmul(f, X[pk(j, c)]));
       }
     }
     __syncthreads();
@@ -104,52 +126,25 @@ __global__ __launch_bounds__(CD_NT) void k_chol_diag(double2* __restrict__ A, in
     if (bad >= 0) *fail = kb0 + bad;
   }
   if (bad >= 0) return;  // uniform: every thread saw the same pivot
-  for (int e = tid; e < CB * (CB + 1) / 2; e += CD_NT) {
-    int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-    while ((r + 1) * (r + 2) / 2 <= e) ++r;
-    while (r * (r + 1) / 2 > e) --r;
-    const int c = e - r * (r + 1) / 2;
-    const double s = sqrt(dpiv[c]);
-    L[e] = r == c ? make_double2(s, 0.0) : cscale(L[e], 1.0 / s);
+  if (tid < CB) {
+    const double t = sqrt(dpiv[tid]);
+    sq[tid] = t;
+    isq[tid] = 1.0 / t;
   }
   __syncthreads();
-  for (int e = tid; e < CB * CB; e += CD_NT) {
-    const int r = e / CB, c = e % CB;
-    if (c <= r && r < nb) A[(kb0 + r) * K + kb0 + c] = L[pk(r, c)];
-  }
-  // Inverse X = L^{-1}, right-looking like the elimination, one barrier per
-  // step: B = I; at step k every row i > k takes B_ic -= (L_ik / L_kk) B_kc for
-  // c <= k (row k is final after step k - 1 and is only read); finally
-  // X_ic = B_ic / L_ii.
-  for (int e = tid; e < CB * CB; e += CD_NT) {
-    const int r = e / CB, c = e % CB;
-    if (c <= r) X[pk(r, c)] = make_double2(r == c ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-  for (int k = 0; k < CB - 1; ++k) {
-    const double ik = 1.0 / L[pk(k, k)].x;
 #pragma unroll
-    for (int aa = 0; aa < 2; ++aa) {
-      const int r = ty + 32 * aa;
-      if (r <= k) continue;
-      const double2 f = cscale(L[pk(r, k)], ik);
+  for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        const int c = tx + 16 * bb;
-        if (c <= k) X[pk(r, c)] = csub(X[pk(r, c)], cmul(f, X[pk(k, c)]));
+    for (int bb = 0; bb < 4; ++bb) {
+      const int r = ty + 32 * aa, c = tx + 16 * bb;
+      double2 lv = make_double2(0.0, 0.0), xv = make_double2(0.0, 0.0);
+      if (c <= r) {
+        lv = r == c ? make_double2(sq[c], 0.0) : cscale(L[pk(r, c)], isq[c]);
+        xv = cscale(X[pk(r, c)], isq[r]);
+        if (r < nb) A[(kb0 + r) * K + kb0 + c] = lv;
       }
+      Linv[r * CB + c] = xv;
     }
-    __syncthreads();
-  }
-  for (int e = tid; e < CB * CB; e += CD_NT) {
-    const int r = e / CB, c = e % CB;
-    if (c <= r) X[pk(r, c)] = cscale(X[pk(r, c)], 1.0 / L[pk(r, r)].x);
-  }
-  __syncthreads();
-  for (int e = tid; e < CB * CB; e += CD_NT) {
-    const int r = e / CB, c = e % CB;
-    Linv[e] = c <= r ? X[pk(r, c)] : make_double2(0.0, 0.0);
-  }
 }
 
 struct zargs {
