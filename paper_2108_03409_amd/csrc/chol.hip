@@ -329,19 +329,22 @@ __global__ __launch_bounds__(256) void k_fwd_update(const double2* __restrict__ 
       lv[t] = (m <= r && m < nb_next) ? Linv_next[r * CB + m] : make_double2(0.0, 0.0);
     }
   }
+  // the row entries and the right-hand side do not depend on y_b: their loads
+  // are issued before y_b is published through LDS
+  const int64_t R = kb0 + CB + (int64_t)blockIdx.x * CB + r;
+  double2 av[CB / 4];
+#pragma unroll
+  for (int j = 0; j < CB / 4; ++j) av[j] = R < K ? A[R * K + kb0 + 4 * j + q] : make_double2(0.0, 0.0);
+  const double2 rv = (R < K && q == 0) ? rhs[R] : make_double2(0.0, 0.0);
   if (tid < CB) yb[tid] = y[kb0 + tid];
   __syncthreads();
-  const int64_t R = kb0 + CB + (int64_t)blockIdx.x * CB + r;
   double2 acc = make_double2(0.0, 0.0);
-  if (R < K) {
-    const double2* row = A + R * K + kb0;
 #pragma unroll
-    for (int j = 0; j < CB / 4; ++j) acc = cadd(acc, cmul(row[4 * j + q], yb[4 * j + q]));
-  }
+  for (int j = 0; j < CB / 4; ++j) acc = cadd(acc, cmul(av[j], yb[4 * j + q]));
   acc = quad_sum(acc);
   double2 nv = make_double2(0.0, 0.0);
   if (R < K && q == 0) {
-    nv = csub(rhs[R], acc);
+    nv = csub(rv, acc);
     rhs[R] = nv;
   }
   if (blockIdx.x != 0) return;  // uniform over the group
@@ -387,20 +390,26 @@ __global__ __launch_bounds__(256) void k_bwd_update(const double2* __restrict__ 
       lv[t] = m < CB ? cconj(Linv_prev[m * CB + r]) : make_double2(0.0, 0.0);
     }
   }
-  if (tid < CB) xb[tid] = tid < nb ? x[kb0 + tid] : make_double2(0.0, 0.0);
-  __syncthreads();
+  // the column entries and v do not depend on x_b: their loads are issued
+  // before x_b is published through LDS
   const int cl = tid & 63, q = tid >> 6;
   const int64_t c = (int64_t)blockIdx.x * CB + cl;  // < kb0: the grid covers kb0 / 64 column blocks
-  double2 acc = make_double2(0.0, 0.0);
+  double2 av[CB / 4];
 #pragma unroll
   for (int j = 0; j < CB / 4; ++j) {
     const int m = q * (CB / 4) + j;
-    if (m < nb) acc = cadd(acc, cmul(cconj(A[(kb0 + m) * K + c]), xb[m]));
+    av[j] = m < nb ? cconj(A[(kb0 + m) * K + c]) : make_double2(0.0, 0.0);
   }
+  const double2 vc = tid < CB ? v[c] : make_double2(0.0, 0.0);
+  if (tid < CB) xb[tid] = tid < nb ? x[kb0 + tid] : make_double2(0.0, 0.0);
+  __syncthreads();
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int j = 0; j < CB / 4; ++j) acc = cadd(acc, cmul(av[j], xb[q * (CB / 4) + j]));
   part[q][cl] = acc;
   __syncthreads();
   if (tid < CB) {
-    const double2 nv = csub(v[c], cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid])));
+    const double2 nv = csub(vc, cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid])));
     v[c] = nv;
     vs[tid] = nv;
   }
