@@ -203,7 +203,8 @@ __device__ __forceinline__ void wave_sync() {
 // and pairs are summed in a fixed order (reproducible results).
 constexpr int AR_CM = 4;  // moves per chunk (64 / AR_CM lanes per move in the sums)
 
-__global__ __launch_bounds__(AR_NT) void k_ar_eloc_tri(const uint64_t* __restrict__ s, int64_t B, int N, int H,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ar_eloc_tri(const uint64_t* __restrict__ s, int64_t B, int N, int H,
                                                        int W, const double* __restrict__ W1mT,
                                                        const double* __restrict__ W2t, const double* __restrict__ b1,
                                                        const double* __restrict__ b2, int kind, double J, double hx,
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(AR_NT) void k_ar_eloc_tri(const uint64_t* __restric
   double* DH = hh + H;         // [AR_CM][H] hidden-unit changes of the chunk's moves
   double* buf = DH + AR_CM * H;  // [AR_CM][N] per-pair log-likelihood changes
   int* mv = (int*)(buf + AR_CM * N);  // anti-aligned bonds (Heisenberg), bond order
-  for (int e = threadIdx.x; e < N * H; e += AR_NT) {
+  for (int e = threadIdx.x; e < N * H; e += NT) {
     W1s[e] = W1mT[e];
     W2s[e] = W2t[e];
   }
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(AR_NT) void k_ar_eloc_tri(const uint64_t* __restric
   const double mel = kind == HAM_TFIM ? -hx : 2.0 * J;
   const bool offdiag = kind == HAM_TFIM ? hx != 0.0 : J != 0.0;
   const int grp = lane >> 4, gl = lane & 15;  // 16-lane group of the per-move sums
-  for (int64_t b = (int64_t)blockIdx.x * AR_WAVES + wave; b < B; b += (int64_t)gridDim.x * AR_WAVES) {
+  for (int64_t b = (int64_t)blockIdx.x * (NT / 64) + wave; b < B; b += (int64_t)gridDim.x * (NT / 64)) {
     const uint64_t* srow = s + b * W;
     for (int i = lane; i < N; i += 64) x[i] = (double)((srow[i >> 6] >> (i & 63)) & 1ull);
     wave_sync();
@@ -606,14 +607,21 @@ void ar_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* out) {
 void ar_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc) {
   const ar_ptrs p = ptrs(m);
   const size_t per_wave = (size_t)(3 + AR_CM) * m->N + (size_t)(2 + AR_CM) * m->Nh + ((size_t)H->n_bonds + 1) / 2;
-  const size_t lds_w = sizeof(double) * (2 * (size_t)m->N * m->Nh + (size_t)AR_WAVES * per_wave);
+  auto lds_of = [&](int waves) { return sizeof(double) * (2 * (size_t)m->N * m->Nh + (size_t)waves * per_wave); };
+  // eight waves per group share one copy of the weights where it fits (more
+  // resident waves per compute unit for the same LDS), else four
+  const int nt = lds_of(8) <= kArLdsMax ? 512 : 256;
+  const size_t lds_w = lds_of(nt / 64);
   if (lds_w <= kArLdsMax) {
     // one resident wave of groups: as many as the LDS of 256 compute units holds (at most 8 each)
     const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)(160 * 1024) / (int64_t)lds_w));
-    const int64_t groups = std::min<int64_t>((B + AR_WAVES - 1) / AR_WAVES, 256 * per_cu);
-    k_ar_eloc_tri<<<(unsigned)groups, AR_NT, lds_w, m->ctx->stream>>>(s, B, m->N, m->Nh, m->W, p.W1mT, m->ar_w2t,
-                                                                       p.b1, p.b2, H->kind, H->J, H->h, H->bonds,
-                                                                       H->n_bonds, eloc);
+    const int64_t groups = std::min<int64_t>((B + nt / 64 - 1) / (nt / 64), 256 * per_cu);
+    if (nt == 512)
+      k_ar_eloc_tri<512><<<(unsigned)groups, 512, lds_w, m->ctx->stream>>>(
+          s, B, m->N, m->Nh, m->W, p.W1mT, m->ar_w2t, p.b1, p.b2, H->kind, H->J, H->h, H->bonds, H->n_bonds, eloc);
+    else
+      k_ar_eloc_tri<256><<<(unsigned)groups, 256, lds_w, m->ctx->stream>>>(
+          s, B, m->N, m->Nh, m->W, p.W1mT, m->ar_w2t, p.b1, p.b2, H->kind, H->J, H->h, H->bonds, H->n_bonds, eloc);
     VMC_HIP(hipGetLastError());
     return;
   }
