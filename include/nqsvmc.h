@@ -289,9 +289,13 @@ int vmc_sampler_destroy(vmc_sampler* S);
  *   log-derivatives: S is then real whatever the mode);  eloc: N complex128;
  *   weights: N doubles or NULL;  x: K complex128 (written on success).
  * S is formed on the matrix cores from centred O in float32 (C64 / F32 input)
- * or float64 (C128 / F64 input); factorisation and solves are float64.  Real O
- * is packed two samples per complex row (Re of the Gram of the packed matrix
- * is S), which halves the Gram work.
+ * or float64 (C128 / F64 input); factorisation and solves are float64.  The
+ * complex products of the float32 Gram and of the Cholesky's block updates use
+ * three real products per term (Re = A + B, Im = C - A + B with A = sum Re Re',
+ * B = sum Im Im', C = sum (Re - Im)(Re' + Im') for the Gram; the bound on the
+ * rounding error of Im grows by at most a factor of about 2).  Real O is packed
+ * two samples per complex row (Re of the Gram of the packed matrix is S), which
+ * halves the Gram work.
  * Returns VMC_ERR_NOT_PD with info->fail_index = first failing column, or
  * VMC_ERR_UNSUPPORTED for VMC_SR_IMAG (Im S is antisymmetric, not PD).
  * info_host (may be NULL) is written on return; the call synchronises.       */
