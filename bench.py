@@ -518,7 +518,8 @@ def main():
                     "traffic": herk_traffic() if args.gram == 0 else None,
                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled)",
                     "algorithmic_bytes": 8.0 * ns * K + 16.0 * K * K,
-                    "work": f"4*Ns*K*(K+1) = {herk_flops(ns, K):.4e} flop per launch (Ns={ns}, K={K})"}
+                    "work": f"4*Ns*K*(K+1) = {herk_flops(ns, K):.4e} flop per launch (Ns={ns}, K={K}), the "
+                            "conventional complex count (four real products per term)"}
         if args.gram == 0:
             # the kernel forms each complex product from three real ones
             # (Gauss's identity): the matrix-core work it issues is 3/4 of the
