@@ -58,7 +58,10 @@ def test_sr_solve_fp64_matches_oracle(ctx, N, Nh, ns, mode, gamma, nu, eps, weig
 
 @pytest.mark.parametrize("gram", [0, 1])
 @pytest.mark.parametrize("N,Nh,ns,weighted", [(16, 32, 4096, False), (5, 7, 9, True), (9, 21, 1001, False),
-                                              (12, 48, 333, True), (40, 60, 3000, False)])
+                                              (12, 48, 333, True), (40, 60, 3000, False),
+                                              # even K with fewer samples than one 12-sample stage,
+                                              # and one full stage plus one sample
+                                              (4, 4, 5, False), (6, 10, 13, True)])
 def test_sr_solve_fp32_gram_within_bound(ctx, N, Nh, ns, weighted, gram):
     # S from complex64 O on the matrix cores: float32 products (gram 0) or split
     # float16 products (gram 1, 2^-21 per term); |dS| <= (u + gamma_N) sum |Obar||Obar|
