@@ -13,7 +13,11 @@
 //
 // Work-group tile: 128 complex rows x 64 complex columns, 4 waves (2 x 2),
 // each wave 64 x 32 (4 x 2 blocks of 16 x 16, 96 accumulator registers).
-// Samples are staged 16 at a time through double-buffered LDS.  Only tiles
+// With K even and Obar 16-byte aligned (k_herk_c_dma) the samples are loaded
+// 12 at a time straight from global memory into double-buffered LDS
+// (global_load_lds_dwordx4, no staging registers), three groups per compute
+// unit; otherwise (k_herk_mfma_f32) 16 at a time through registers into
+// double-buffered LDS, two groups per compute unit.  Only tiles
 // that touch the lower triangle are launched; the linear tile index is
 // remapped so that consecutive tiles of one row stripe run on the same XCD
 // (shared L2).  The epilogue writes S~ (float64, projection and diagonal shift
