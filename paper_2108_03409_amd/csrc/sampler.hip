@@ -183,17 +183,24 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   bool lq_valid = false;
   const int64_t total = a.therm_steps + a.n_record * a.sweep;
   // The move of step t + 1 is known from its counter before step t resolves:
-  // its row of T is loaded one step ahead (local-move kernels with up to 512
-  // hidden units, where the extra registers fit).
+  // its rows of T (the ratio) and D (the update on acceptance) are loaded one
+  // step ahead (local-move kernels with up to 512 hidden units, where the
+  // extra registers fit).
   constexpr bool PF = !MIX && Q <= 8;
   uint4 xn = philox(make_uint4((uint32_t)c, (uint32_t)a.t0, (uint32_t)(a.t0 >> 32), 0u), a.key);
-  double2 Tn[PF ? Q : 1];
+  double2 Tn[PF ? Q : 1], Dn[PF ? Q : 1];
+  double2 aln = make_double2(0.0, 0.0), lcn = aln;  // alpha and LC of that move
+  int2 bdn = make_int2(0, 0);                       // its bond (exchange moves)
   if (PF) {
     const int mn = (int)to_index(xn.x, (uint32_t)a.n_moves);
+    aln = a.alpha[mn];
+    lcn = a.LC[mn];
+    if (a.proposal == VMC_PROP_EXCHANGE) bdn = a.bonds[mn];
 #pragma unroll
     for (int q = 0; q < (PF ? Q : 1); ++q) {
       const int j = lane + 64 * q;
       Tn[q] = j < Nh ? a.T[(int64_t)mn * Nh + j] : make_double2(0.0, 0.0);
+      Dn[q] = j < Nh ? a.D[(int64_t)mn * Nh + j] : make_double2(0.0, 0.0);
     }
   }
   for (int64_t step = 0; step < total; ++step) {
@@ -201,19 +208,28 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
     const uint4 x = xn;
     const int m = (int)to_index(x.x, (uint32_t)a.n_moves);
     const double u = to_uniform(x.y, x.z);
-    double2 Tc[PF ? Q : 1];
+    double2 Tc[PF ? Q : 1], Dc[PF ? Q : 1];
+    const double2 alc = aln, lcc = lcn;
+    const int2 bdc = bdn;
     if (PF) {
 #pragma unroll
-      for (int q = 0; q < (PF ? Q : 1); ++q) Tc[q] = Tn[q];
+      for (int q = 0; q < (PF ? Q : 1); ++q) {
+        Tc[q] = Tn[q];
+        Dc[q] = Dn[q];
+      }
     }
     if (step + 1 < total) {
       xn = philox(make_uint4((uint32_t)c, (uint32_t)(t + 1), (uint32_t)((t + 1) >> 32), 0u), a.key);
       if (PF) {
         const int mn = (int)to_index(xn.x, (uint32_t)a.n_moves);
+        aln = a.alpha[mn];
+        lcn = a.LC[mn];
+        if (a.proposal == VMC_PROP_EXCHANGE) bdn = a.bonds[mn];
 #pragma unroll
         for (int q = 0; q < (PF ? Q : 1); ++q) {
           const int j = lane + 64 * q;
           Tn[q] = j < Nh ? a.T[(int64_t)mn * Nh + j] : make_double2(0.0, 0.0);
+          Dn[q] = j < Nh ? a.D[(int64_t)mn * Nh + j] : make_double2(0.0, 0.0);
         }
       }
     }
@@ -270,7 +286,7 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
     int site = m, site2 = -1;
     bool identity = false;
     if (a.proposal == VMC_PROP_EXCHANGE) {
-      const int2 bd = a.bonds[m];
+      const int2 bd = PF ? bdc : a.bonds[m];
       site = bd.x;
       site2 = bd.y;
       identity = ((cb[site >> 6] >> (site & 63)) & 1ull) == ((cb[site2 >> 6] >> (site2 & 63)) & 1ull);
@@ -291,7 +307,7 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
       }
       double L = wave_sum(log(prod));
       L = __shfl(L, 0, 64);  // one value for the whole wave: a uniform decision
-      const double2 al = a.alpha[m], lc = a.LC[m];
+      const double2 al = PF ? alc : a.alpha[m], lc = PF ? lcc : a.LC[m];
       const double r = 2.0 * (-2.0 * sg * al.x + lc.x) + L;
       const bool acc = (r >= 0.0) || (u < exp(r));
       if (acc) {
@@ -300,7 +316,7 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
         for (int q = 0; q < Q; ++q) {
           const int j = lane + 64 * q;
           if (j < Nh) {
-            const double2 d = a.D[(int64_t)m * Nh + j];
+            const double2 d = PF ? Dc[PF ? q : 0] : a.D[(int64_t)m * Nh + j];
             const double2 Tm = PF ? Tc[PF ? q : 0] : a.T[(int64_t)m * Nh + j];
             double2 thv = ths[q * 64 + lane];
             thv.x -= 2.0 * sg * d.x;
