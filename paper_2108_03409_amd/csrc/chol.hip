@@ -48,7 +48,9 @@ __device__ __forceinline__ int pk(int r, int c) { return r * (r + 1) / 2 + c; } 
 // Factor and invert the diagonal block at kb0 (nb <= 64 valid rows/cols; the
 // rest is padded with the identity).  LDS holds the packed lower triangles of
 // the block (L) and of its inverse (X).
-constexpr int CD_NT = 512;  // threads of the diagonal-block kernel
+constexpr int CD_NT = 512;         // threads of the diagonal-block kernel
+constexpr int CD_RS = CD_NT / 16;  // row stride of a thread's entries
+constexpr int CD_RA = CB / CD_RS;  // rows per thread
 
 __global__ __launch_bounds__(CD_NT) void k_chol_diag(double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
                                                    double2* __restrict__ Linv, long long* __restrict__ fail,
@@ -59,22 +61,22 @@ __global__ __launch_bounds__(CD_NT) void k_chol_diag(double2* __restrict__ A, in
   __shared__ double sq[CB], isq[CB];
   if (*fail >= 0) return;
   const int tid = threadIdx.x;
-  // thread (ty, tx) owns rows ty + 32 a, columns tx + 16 b of both triangles
+  // thread (ty, tx) owns rows ty + CD_RS a, columns tx + 16 b of both triangles
   const int ty = tid >> 4, tx = tid & 15;
   {
-    double2 v[2][4];
+    double2 v[CD_RA][4];
 #pragma unroll
-    for (int aa = 0; aa < 2; ++aa)
+    for (int aa = 0; aa < CD_RA; ++aa)
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
-        const int r = ty + 32 * aa, c = tx + 16 * bb;
+        const int r = ty + CD_RS * aa, c = tx + 16 * bb;
         v[aa][bb] = (c <= r && r < nb) ? A[(kb0 + r) * K + kb0 + c] : make_double2(r == c ? 1.0 : 0.0, 0.0);
       }
 #pragma unroll
-    for (int aa = 0; aa < 2; ++aa)
+    for (int aa = 0; aa < CD_RA; ++aa)
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
-        const int r = ty + 32 * aa, c = tx + 16 * bb;
+        const int r = ty + CD_RS * aa, c = tx + 16 * bb;
         if (c <= r) {
           L[pk(r, c)] = v[aa][bb];
           X[pk(r, c)] = make_double2(r == c ? 1.0 : 0.0, 0.0);
@@ -105,8 +107,8 @@ __global__ __launch_bounds__(CD_NT) void k_chol_diag(double2* __restrict__ A, in
     if (tid == 0) dpiv[j] = d;
     const double id = 1.0 / d;
 #pragma unroll
-    for (int aa = 0; aa < 2; ++aa) {
-      const int r = ty + 32 * aa;
+    for (int aa = 0; aa < CD_RA; ++aa) {
+      const int r = ty + CD_RS * aa;
       if (r <= j) continue;
       const double2 f = cscale(L[pk(r, j)], id);
 #pragma unroll
@@ -133,10 +135,10 @@ __global__ __launch_bounds__(CD_NT) void k_chol_diag(double2* __restrict__ A, in
   }
   __syncthreads();
 #pragma unroll
-  for (int aa = 0; aa < 2; ++aa)
+  for (int aa = 0; aa < CD_RA; ++aa)
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
-      const int r = ty + 32 * aa, c = tx + 16 * bb;
+      const int r = ty + CD_RS * aa, c = tx + 16 * bb;
       double2 lv = make_double2(0.0, 0.0), xv = make_double2(0.0, 0.0);
       if (c <= r) {
         lv = r == c ? make_double2(sq[c], 0.0) : cscale(L[pk(r, c)], isq[c]);
