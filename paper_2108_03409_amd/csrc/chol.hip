@@ -381,16 +381,14 @@ __global__ __launch_bounds__(256) void k_bwd_update(const double2* __restrict__ 
   __shared__ double2 part[4][CB];
   __shared__ double2 vs[CB];
   const int tid = threadIdx.x;
-  const int r = tid >> 2, q4 = tid & 3;
-  // last group: this thread's entries conj(Linv_{b-1}[m][r]) (m = r + q4 + 4 t < 64),
-  // loaded first so that they arrive while the columns are updated
+  const int wv = tid >> 6, ln = tid & 63;
+  // last group: wave w holds conj(Linv_{b-1}[m][ln]) for the rows m = w + 4 t
+  // (each load one contiguous row; entries above the diagonal are stored as
+  // zeros), loaded first so that they arrive while the columns are updated
   double2 lv[CB / 4];
   if (blockIdx.x == gridDim.x - 1) {
 #pragma unroll
-    for (int t = 0; t < CB / 4; ++t) {
-      const int m = r + q4 + 4 * t;
-      lv[t] = m < CB ? cconj(Linv_prev[m * CB + r]) : make_double2(0.0, 0.0);
-    }
+    for (int t = 0; t < CB / 4; ++t) lv[t] = cconj(Linv_prev[(wv + 4 * t) * CB + ln]);
   }
   // the column entries and v do not depend on x_b: their loads are issued
   // before x_b is published through LDS
@@ -417,14 +415,13 @@ __global__ __launch_bounds__(256) void k_bwd_update(const double2* __restrict__ 
   }
   if (blockIdx.x != gridDim.x - 1) return;  // uniform over the group
   __syncthreads();
+  // x_{b-1}[ln] = sum_m conj(Linv_{b-1}[m][ln]) v_{b-1}[m], wave w over m = w + 4 t
   double2 s = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int t = 0; t < CB / 4; ++t) {
-    const int m = r + q4 + 4 * t;
-    if (m < CB) s = cadd(s, cmul(lv[t], vs[m]));
-  }
-  s = quad_sum(s);
-  if (q4 == 0) x[kb0 - CB + r] = s;
+  for (int t = 0; t < CB / 4; ++t) s = cadd(s, cmul(lv[t], vs[wv + 4 * t]));
+  part[wv][ln] = s;  // the column update's reads of part finished before the barrier above
+  __syncthreads();
+  if (tid < CB) x[kb0 - CB + tid] = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
 }
 
 }  // namespace
