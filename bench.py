@@ -430,8 +430,8 @@ def bench_peaks(args, V, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-                                   "and not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; sharding over several GPUs is not built",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
     from paper_2108_03409_amd import nqsvmc as V
