@@ -50,7 +50,7 @@ enum {
   VMC_ERR_HIP = -3,          /* a HIP runtime call failed                     */
   VMC_ERR_NOT_PD = -4,       /* shifted S not positive definite (see info)    */
   VMC_ERR_NONFINITE = -5,    /* NaN/Inf in parameters or results              */
-  VMC_ERR_UNSUPPORTED = -6,  /* valid request this build does not implement   */
+  VMC_ERR_UNSUPPORTED = -6,  /* valid request the library does not implement  */
   VMC_ERR_WORKSPACE = -7     /* request exceeds the workspace limit           */
 };
 
