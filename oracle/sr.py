@@ -30,6 +30,14 @@ lambda^+ = 0; the SNR of rho_j is |rho_j| over the standard error of a mean of
 N_s samples, sqrt(var_j / N_s), with var_j the weighted variance of the
 eigen-basis components of the per-sample terms
 f_n = [[gamma (E_n - <E>) conj(O_n - <O>)]] whose weighted sum is [[gamma F]].
+
+The Im projection (eq:tdvp_im, real parameters of a non-holomorphic network)
+gives Im[S~] x = -Im[gamma F] with A = Im S~ real and antisymmetric (zero
+diagonal, so the relative shift does nothing and an additive one would break
+the antisymmetry: it is refused).  A has no real eigendecomposition; the
+Hermitian matrix H = i A does (eigenvalues in +- pairs), and A x = b is
+H x = i b.  The cutoffs of Sec. 3.3 act on the eigenvalues of H, i.e. on the
+singular values of A (pairs are kept or dropped together, so x stays real).
 """
 from __future__ import annotations
 
@@ -142,20 +150,27 @@ def sr_solve(O, eloc, *, nu_rel=1e-3, eps_abs=0.0, mode="complex", gamma=1.0,
 def eigen_solve(O, eloc, *, nu_rel=0.0, eps_abs=0.0, mode="complex", gamma=1.0, weights=None,
                 eps_pinv=0.0, soft=False, eps_snr=0.0):
     """Regularised solve through the eigendecomposition of S~; returns
-    (x, info) with info['evals'] (ascending) and info['snr'] (same order)."""
+    (x, info) with info['evals'] (ascending) and info['snr'] (same order).
+    For mode "imag" the eigenvalues are those of i Im[S~] and x is real."""
     O = np.asarray(O, dtype=np.complex128)
     e = np.asarray(eloc, dtype=np.complex128)
     N = O.shape[0]
     w = _weights(N, weights)
     S, F = fisher_and_force(O, e, weights)
+    if mode == "imag" and eps_abs != 0.0:
+        raise ValueError("an additive shift breaks the antisymmetry of Im S")
     St = shifted(project(S, mode), nu_rel, eps_abs)
     rhs = -project(gamma * F, mode)
-    lam, V = np.linalg.eigh(St)
-    rho = V.conj().T @ rhs
+    # the Hermitian matrix that is decomposed, and the right-hand side in its frame
+    Hm, rhs_h = (1j * St, 1j * rhs) if mode == "imag" else (St, rhs)
+    lam, V = np.linalg.eigh(Hm)
+    rho = V.conj().T @ rhs_h
     # per-sample terms and their eigen-basis components (plain definition)
     Ob = O - w @ O
     dE = e - np.sum(w * e)
     f = project(gamma * dE[:, None] * Ob.conj(), mode)       # (N, K), sum_n w_n f_n = [[gamma F]]
+    if mode == "imag":
+        f = 1j * f
     P = f @ V.conj()                                           # P_nj = sum_k f_nk conj(V_kj)
     mean_P = w @ P
     var = w @ (np.abs(P) ** 2) - np.abs(mean_P) ** 2
@@ -180,6 +195,8 @@ def eigen_solve(O, eloc, *, nu_rel=0.0, eps_abs=0.0, mode="complex", gamma=1.0, 
             elif np.isfinite(snr[j]):
                 inv[j] /= 1.0 + (eps_snr / snr[j]) ** 6
     x = V @ (inv * rho)
+    if mode == "imag":
+        x = x.real.astype(np.complex128)
     mean, evar = energy_stats(e, weights)
     res = np.linalg.norm(St @ x - rhs) / max(np.linalg.norm(rhs), 1e-300)
     return x, dict(evals=lam, snr=snr, rho=rho, var=var, e_mean=mean, e_var=evar, residual=res)

@@ -241,3 +241,66 @@ def test_snr_estimate_and_zero_signal():
     assert np.min(inf2["snr"]) == 0.0
     y2 = np.linalg.eigh(sr.fisher_and_force(O2, e2)[0])[1].conj().T @ x2
     assert abs(y2[np.argmin(inf2["snr"])]) == 0.0
+
+
+# ---- Im projection (eq:tdvp_im): real parameters, antisymmetric Im S ----
+
+def test_imag_mode_hard_cutoff_equals_svd_pseudo_inverse():
+    # numpy's SVD-based pinv of the real antisymmetric Im S (singular values =
+    # |eigenvalues of i Im S|) is an independent route to the truncated inverse
+    O, e = _eig_problem(ns=500, K=11, seed=21)        # odd K: Im S has a zero eigenvalue
+    for gamma in (1j, 1.0, 0.3 - 0.7j):
+        S, F = sr.fisher_and_force(O, e)
+        A = S.imag
+        assert np.allclose(A, -A.T, atol=1e-15) and np.max(np.abs(np.diag(A))) <= 1e-15
+        sv = np.sort(np.linalg.svd(A, compute_uv=False))[::-1]
+        eps = np.sqrt(sv[5] * sv[6]) / sv[0]          # strictly between two singular-value pairs
+        x, info = sr.eigen_solve(O, e, mode="imag", gamma=gamma, eps_pinv=eps)
+        x_ref = np.linalg.pinv(A, rcond=eps) @ (-(gamma * F).imag)
+        assert np.max(np.abs(x.imag)) == 0.0
+        assert np.linalg.norm(x.real - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+        # eigenvalues of i Im S come in +- pairs
+        lam = info["evals"]
+        assert np.allclose(np.sort(lam), np.sort(-lam), atol=1e-12 * np.abs(lam).max())
+
+
+def test_imag_mode_on_real_parametrisation_equals_holomorphic_solve():
+    # A holomorphic network written with real parameters (Re p, Im p) has the
+    # log-derivatives O' = [O, i O].  Its Im-projected equation Im[S'] q = Im[-i F']
+    # reads  Im S u + Re S v = -Re F  and  -Re S u + Im S v = -Im F, the real and
+    # imaginary parts of S (u + i v) = -i F: the holomorphic real-time equation.
+    O, e = _eig_problem(ns=600, K=9, seed=22)
+    Op = np.concatenate([O, 1j * O], axis=1)
+    q, info = sr.eigen_solve(Op, e, mode="imag", gamma=1j, eps_pinv=1e-12)
+    x_c, _ = sr.eigen_solve(O, e, mode="complex", gamma=1j, eps_pinv=1e-12)
+    K = O.shape[1]
+    z = q[:K].real + 1j * q[K:].real
+    assert np.linalg.norm(z - x_c) <= 1e-9 * np.linalg.norm(x_c)
+    # the spectrum of i Im S' is +- that of S
+    lam_s = np.linalg.eigvalsh(sr.fisher_and_force(O, e)[0])
+    assert np.allclose(np.sort(np.abs(info["evals"])), np.sort(np.concatenate([lam_s, lam_s])),
+                       rtol=1e-9, atol=1e-14)
+
+
+def test_imag_mode_conserves_energy_to_first_order():
+    # dE/dt = sum_k dE/dtheta_k x_k = 2 Re F . x with real parameters
+    # (eq:energy_gradient); with gamma = i the Im equation gives
+    # x = -A^+ Re F, A^+ antisymmetric, so Re F . x = 0 for every cutoff
+    # (pairs +-lambda share their cutoff and SNR factors)
+    rng = np.random.default_rng(23)
+    ns, K = 800, 10
+    O = rng.normal(size=(ns, K)) + 1j * rng.normal(size=(ns, K))   # non-holomorphic: arbitrary complex O
+    e = rng.normal(size=ns) + 0.5j * rng.normal(size=ns) + 0.3 * O[:, 2] + 0.2j * O[:, 5].real
+    S, F = sr.fisher_and_force(O, e)
+    for kw in (dict(eps_pinv=1e-10), dict(eps_pinv=0.05, soft=True), dict(eps_pinv=1e-8, eps_snr=2.0)):
+        x, _ = sr.eigen_solve(O, e, mode="imag", gamma=1j, **kw)
+        assert abs(np.dot(F.real, x.real)) <= 1e-12 * np.linalg.norm(F.real) * np.linalg.norm(x.real)
+        # the Re projection does not conserve it
+    x_re, _ = sr.eigen_solve(O, e, mode="real", gamma=1j, eps_pinv=1e-10)
+    assert abs(np.dot(F.real, x_re.real)) > 1e-3 * np.linalg.norm(F.real) * np.linalg.norm(x_re.real)
+
+
+def test_imag_mode_refuses_additive_shift():
+    O, e = _eig_problem(ns=50, K=4, seed=24)
+    with pytest.raises(ValueError):
+        sr.eigen_solve(O, e, mode="imag", eps_abs=1e-3, eps_pinv=1e-8)
