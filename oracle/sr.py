@@ -72,6 +72,28 @@ def fisher_and_force(O, eloc, weights=None):
     return S, F
 
 
+def force(O, eloc, weights=None):
+    """F alone (eq:force_vector), F_k = <conj(O_k) E> - <conj(O_k)><E>, for
+    sample counts where forming S would not fit."""
+    O = np.asarray(O, dtype=np.complex128)
+    e = np.asarray(eloc, dtype=np.complex128)
+    w = _weights(O.shape[0], weights)
+    mean_O = w @ O
+    return (w * e) @ O.conj() - mean_O.conj() * np.sum(w * e)
+
+
+def fisher_rows(O, rows, weights=None):
+    """Selected rows of S (eq:qfm), S_rk' = <conj(O_r) O_k'> - <conj(O_r)><O_k'>,
+    one row at a time: (len(rows), K)."""
+    O = np.asarray(O, dtype=np.complex128)
+    w = _weights(O.shape[0], weights)
+    mean_O = w @ O
+    out = np.empty((len(rows), O.shape[1]), dtype=np.complex128)
+    for i, r in enumerate(rows):
+        out[i] = (w * O[:, r].conj()) @ O - mean_O[r].conj() * mean_O
+    return out
+
+
 def project(A, mode):
     if mode == "complex":
         return A

@@ -304,3 +304,20 @@ def test_imag_mode_refuses_additive_shift():
     O, e = _eig_problem(ns=50, K=4, seed=24)
     with pytest.raises(ValueError):
         sr.eigen_solve(O, e, mode="imag", eps_abs=1e-3, eps_pinv=1e-8)
+
+
+# ---- per-row S and F alone (the large-K parity path) ----
+
+def test_fisher_rows_and_force_equal_the_full_matrices():
+    # the row-at-a-time S and the S-free F are the same connected correlators
+    # as fisher_and_force (itself pinned by the energy gradient and the
+    # Fubini-Study curvature above), with and without weights
+    rng = np.random.default_rng(31)
+    ns, K = 257, 40
+    O = rng.normal(size=(ns, K)) + 1j * rng.normal(size=(ns, K)) + 0.3
+    e = rng.normal(size=ns) + 1j * rng.normal(size=ns)
+    for w in (None, rng.uniform(0.1, 2.0, size=ns)):
+        S, F = sr.fisher_and_force(O, e, w)
+        rows = [0, 7, 39, 13]
+        assert np.allclose(sr.fisher_rows(O, rows, w), S[rows], rtol=0, atol=1e-13)
+        assert np.allclose(sr.force(O, e, w), F, rtol=0, atol=1e-13)
