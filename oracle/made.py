@@ -145,21 +145,34 @@ def sample(params, B, N, H, seed, lo, hi, rows=None):
     return x, lq
 
 
-def mixed_transition_matrix(logpsi_fn, params, N, H, p_global, states=None):
-    """Exact one-step kernel P = p_g P_MADE + (1 - p_g) P_flip over all 2^N states:
-    P_MADE(s -> s') = q(s') min(1, pi(s') q(s) / (pi(s) q(s'))), P_flip as in
-    metropolis.transition_matrix; diagonals take the remainder."""
-    from .metropolis import transition_matrix
+def global_transition_matrix(logpsi_fn, params, N, H, states=None):
+    """Exact kernel of one global proposal over all 2^N states (the independent
+    Metropolis-Hastings kernel of q): P(s -> s') = q(s') min(1, pi(s') q(s) /
+    (pi(s) q(s'))) for s' != s, the diagonal takes the remainder."""
+    from .eloc import all_states
 
-    Pf, states, lp = transition_matrix(logpsi_fn, "flip", N, None, states)
+    if states is None:
+        states = all_states(N)
+    lp = logpsi_fn(states)
     lq = log_q(params, states, N, H)
     q = np.exp(lq)
     lpi = 2.0 * lp.real
     n = len(states)
-    Pm = np.zeros((n, n))
+    P = np.zeros((n, n))
     for k in range(n):
         r = (lpi - lpi[k]) + (lq[k] - lq)
-        Pm[k] = q * np.minimum(1.0, np.exp(np.minimum(r, 0.0)))
-        Pm[k, k] = 0.0
-        Pm[k, k] = 1.0 - Pm[k].sum()
-    return p_global * Pm + (1 - p_global) * Pf, states, lp, lq
+        P[k] = q * np.minimum(1.0, np.exp(np.minimum(r, 0.0)))
+        P[k, k] = 0.0
+        P[k, k] = 1.0 - P[k].sum()
+    return P, states, lp, lq
+
+
+def sweep_transition_matrix(logpsi_fn, params, N, H, global_steps, flip_steps, states=None):
+    """Kernel of one sweep of the mixed sampler: global_steps global proposals,
+    then flip_steps single-spin flips (matrix product in that order)."""
+    from .metropolis import transition_matrix
+
+    Pg, states, lp, lq = global_transition_matrix(logpsi_fn, params, N, H, states)
+    Pf, _, _ = transition_matrix(logpsi_fn, "flip", N, None, states)
+    P = np.linalg.matrix_power(Pg, global_steps) @ np.linalg.matrix_power(Pf, flip_steps)
+    return P, states, lp, lq

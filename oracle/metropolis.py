@@ -89,13 +89,19 @@ class Chains:
     """A set of Metropolis chains (possibly a subset of a larger ensemble,
     given by ``chain_ids``) that replays the library's random stream.
 
-    proposal "made_mix" (not in the paper): proposal t is global iff
-    x3 * 2^-32 < p_global, its s' ~ q drawn by oracle.made.sample with (row,
-    counter) = (chain, t), and accepted with the Metropolis-Hastings ratio
-    |psi(s')|^2 q(s) / (|psi(s)|^2 q(s')); otherwise a single-spin flip."""
+    proposal "made_mix" (not in the paper): every sweep (thermalisation
+    sweeps included) starts with ``global_steps`` global proposals made by all
+    chains together, then ``sweep_steps`` single-spin flips as for "flip".
+    Global proposal g (counted from 0 over the chains' life, apart from the
+    flip counter t) of chain c draws s' ~ q with oracle.made.sample at (row,
+    counter) = (c, g) and u = unif(x1, x2) of x = Philox((c, g_lo, g_hi, 3)),
+    and is accepted with the Metropolis-Hastings rule for the independent
+    proposal q: r = 2 Re(log psi(s') - log psi(s)) + log q(s) - log q(s'),
+    accept iff r >= 0 or u < exp(r).  Each global step and each flip leaves
+    |psi|^2 invariant, so their composition does too."""
 
     def __init__(self, logpsi_fn, n_sites, proposal, seed, chain_ids,
-                 bond_list=None, sweep_steps=None, therm_sweeps=20, made=None, p_global=0.0):
+                 bond_list=None, sweep_steps=None, therm_sweeps=20, made=None, global_steps=0):
         self.f = logpsi_fn
         self.key = philox.seed_key(seed)
         self.proposal = proposal
@@ -105,7 +111,8 @@ class Chains:
         self.therm = therm_sweeps
         self.seed = seed
         self.made = made            # (params, N, H) of the frozen proposal network
-        self.p_global = p_global
+        self.global_steps = global_steps
+        self.g = 0                  # global proposals made so far (per chain)
         self.n_global = 0
         self.acc_global = 0
         self.states = initial_states(len(self.cids), n_sites, self.key,
@@ -118,9 +125,8 @@ class Chains:
         self.near_ties = 0
 
     def step(self):
-        if self.proposal == "made_mix":
-            return self._step_mix()
-        sp, u = propose(self.proposal, self.states, self.t, self.key, self.cids, self.bonds)
+        kind = "flip" if self.proposal == "made_mix" else self.proposal
+        sp, u = propose(kind, self.states, self.t, self.key, self.cids, self.bonds)
         lp = self.f(sp)
         r = 2.0 * (lp.real - self.logpsi.real)
         with np.errstate(divide="ignore"):
@@ -132,52 +138,50 @@ class Chains:
         self.proposed += len(acc)
         self.t += 1
 
-    def _step_mix(self):
+    def global_step(self):
+        """One MADE proposal for every chain, Metropolis-Hastings acceptance."""
         from . import made as omade
 
         mp, N, H = self.made
+        g = self.g
+        sp, lq_new = omade.sample(mp, len(self.cids), N, H, self.seed, g & 0xFFFFFFFF, g >> 32, rows=self.cids)
+        lq_old = omade.log_q(mp, self.states, N, H)
+        lp_new = self.f(sp)
         ctr = np.zeros((len(self.cids), 4), dtype=np.uint32)
         ctr[:, 0] = self.cids.astype(np.uint32)
-        ctr[:, 1] = np.uint32(self.t & 0xFFFFFFFF)
-        ctr[:, 2] = np.uint32(self.t >> 32)
+        ctr[:, 1] = np.uint32(g & 0xFFFFFFFF)
+        ctr[:, 2] = np.uint32(g >> 32)
+        ctr[:, 3] = 3
         x = philox.philox4x32_10(ctr, self.key)
         u = philox.to_uniform(x[:, 1], x[:, 2])
-        glob = x[:, 3].astype(np.float64) * 2.0 ** -32 < self.p_global
-        for r in range(len(self.cids)):
-            if glob[r]:
-                sp, lq_new = omade.sample(mp, 1, N, H, self.seed, self.t & 0xFFFFFFFF, self.t >> 32,
-                                          rows=[self.cids[r]])
-                lq_old = omade.log_q(mp, self.states[r][None], N, H)[0]
-                lp_new = self.f(sp)[0]
-                rr = 2.0 * (lp_new.real - self.logpsi[r].real) + lq_old - lq_new[0]
-                self.n_global += 1
-                if rr >= 0.0 or u[r] < np.exp(rr):
-                    self.states[r] = sp[0]
-                    self.logpsi[r] = lp_new
-                    self.accepted += 1
-                    self.acc_global += 1
-            else:
-                sp = self.states[r].copy()
-                sp[philox.to_index(x[r, 0], sp.shape[0])] ^= 1
-                lp_new = self.f(sp[None])[0]
-                rr = 2.0 * (lp_new.real - self.logpsi[r].real)
-                if rr >= 0.0 or u[r] < np.exp(rr):
-                    self.states[r] = sp
-                    self.logpsi[r] = lp_new
-                    self.accepted += 1
-            self.proposed += 1
-        self.t += 1
+        r = 2.0 * (lp_new.real - self.logpsi.real) + lq_old - lq_new
+        with np.errstate(divide="ignore"):
+            self.near_ties += int(np.sum(np.abs(r - np.log(u)) < 1e-12))
+        acc = accept(r, u)
+        self.states[acc] = sp[acc]
+        self.logpsi[acc] = lp_new[acc]
+        self.accepted += int(acc.sum())
+        self.acc_global += int(acc.sum())
+        self.n_global += len(acc)
+        self.proposed += len(acc)
+        self.g += 1
+
+    def _sweep(self):
+        if self.proposal == "made_mix":
+            for _ in range(self.global_steps):
+                self.global_step()
+        for _ in range(self.sweep):
+            self.step()
 
     def sample(self, n_per_chain):
         """Returns (configs (n_per_chain, n_chains, N), logpsi (n_per_chain, n_chains))."""
         if not self.thermalized:
-            for _ in range(self.therm * self.sweep):
-                self.step()
+            for _ in range(self.therm):
+                self._sweep()
             self.thermalized = True
         out_s, out_l = [], []
         for _ in range(n_per_chain):
-            for _ in range(self.sweep):
-                self.step()
+            self._sweep()
             out_s.append(self.states.copy())
             out_l.append(self.logpsi.copy())
         return np.stack(out_s), np.stack(out_l)

@@ -90,16 +90,40 @@ def test_training_lowers_nll():
     assert nll1 < nll0 - 1.0
 
 
-@pytest.mark.parametrize("pg", [0.3, 1.0])
-def test_mixed_kernel_is_stationary(pg):
+def test_global_kernel_detailed_balance_and_sweep_stationarity():
+    # the independent MH kernel of q satisfies detailed balance with pi = |psi|^2;
+    # a sweep (global proposals, then flips) is a product of pi-invariant kernels
     N, H = 6, 16
     pr = si.rbm_params(N, N, std=0.5, seed=3)
     f = lambda b: rbm.log_psi(pr, b, N)
     pm = si.made_params(N, H, seed=8) * 2.0
-    P, states, lp, lq = made.mixed_transition_matrix(f, pm, N, H, pg)
+    Pg, states, lp, lq = made.global_transition_matrix(f, pm, N, H)
     pi = np.exp(2 * (lp.real - lp.real.max()))
     pi /= pi.sum()
-    assert np.all(P >= -1e-15) and np.allclose(P.sum(1), 1.0, atol=1e-13)
-    assert np.max(np.abs(pi @ P - pi)) < 1e-14
-    D = pi[:, None] * P
+    assert np.all(Pg >= -1e-15) and np.allclose(Pg.sum(1), 1.0, atol=1e-13)
+    assert np.max(np.abs(pi @ Pg - pi)) < 1e-14
+    D = pi[:, None] * Pg
     assert np.max(np.abs(D - D.T)) < 1e-15
+    for G, L in [(1, 3), (4, 6), (2, 0)]:
+        P, *_ = made.sweep_transition_matrix(f, pm, N, H, G, L)
+        assert np.allclose(P.sum(1), 1.0, atol=1e-12)
+        assert np.max(np.abs(pi @ P - pi)) < 1e-13
+
+
+def test_mixed_oracle_chains_sample_psi_squared():
+    # the oracle's mixed chains (global MADE steps + flips) histogram against
+    # |psi|^2 on all 2^6 states (chi-square, samples thinned to every 4th sweep)
+    from scipy import stats
+    from oracle import metropolis as omet, eloc as oeloc
+    N, H = 6, 16
+    pr = si.rbm_params(N, N, std=0.5, seed=3)
+    f = lambda b: rbm.log_psi(pr, b, N)
+    pm = si.made_params(N, H, seed=8) * 2.0
+    ch = omet.Chains(f, N, "made_mix", seed=5, chain_ids=np.arange(256), sweep_steps=2, therm_sweeps=10,
+                     made=(pm, N, H), global_steps=1)
+    s, _ = ch.sample(80)
+    assert 0 < ch.acc_global < ch.n_global
+    codes = (s[::4].reshape(-1, N).astype(np.int64) << np.arange(N)).sum(1)
+    cnt = np.bincount(codes, minlength=2 ** N)
+    _, prob, _ = oeloc.exact_probabilities(f, N)
+    assert stats.chisquare(cnt, prob * cnt.sum()).pvalue > 1e-4
