@@ -297,7 +297,8 @@ int vmc_sampler_destroy(vmc_sampler* S);
  * two samples per complex row (Re of the Gram of the packed matrix is S), which
  * halves the Gram work.
  * Returns VMC_ERR_NOT_PD with info->fail_index = first failing column, or
- * VMC_ERR_UNSUPPORTED for VMC_SR_IMAG (Im S is antisymmetric, not PD).
+ * VMC_ERR_UNSUPPORTED for VMC_SR_IMAG (Im S is antisymmetric, not PD: that
+ * projection is solved by vmc_sr_solve_eig).
  * info_host (may be NULL) is written on return; the call synchronises.       */
 typedef struct {
   double nu_rel;     /* relative diagonal shift (the paper's nu) */
@@ -321,6 +322,20 @@ typedef struct {
 int vmc_sr_solve(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, const double* weights,
                  int64_t N, int64_t K, const vmc_sr_opts* opts, double* x, vmc_sr_info* info_host);
 
+/* Test export of the first half of vmc_sr_solve (eq:qfm, eq:force_vector):
+ * the shifted matrix and the force exactly as the solve forms them (same
+ * kernels, same arguments), with no factorisation.
+ *   S_out: K*K complex128 (device, row-major, both triangles) receives
+ *          S~ = [[S]] + nu_rel diag([[S]]) + eps_abs I; for VMC_SR_IMAG it
+ *          receives the Hermitian matrix i Im[S] (purely imaginary entries,
+ *          zero diagonal) that the eigen solve decomposes;
+ *   F_out: K complex128 (device) receives F (not projected, no gamma).
+ * info_host (may be NULL): e_mean and e_var; residual and min_pivot NaN.
+ * Same argument rules as vmc_sr_solve; the call synchronises.               */
+int vmc_sr_fisher(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, const double* weights,
+                  int64_t N, int64_t K, const vmc_sr_opts* opts, double* S_out, double* F_out,
+                  vmc_sr_info* info_host);
+
 /* The shifted system regularised through the eigendecomposition of S~
  * (Sec. 3.3 "Pseudo-inverse" and "Eliminating noisy contributions"):
  *   S~ = V diag(lambda) V^dagger (device Jacobi, vmc_eigh),
@@ -334,9 +349,20 @@ int vmc_sr_solve(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, c
  * variance over samples of the eigen-basis components of the per-sample terms
  * f_n = [[gamma (E_n - <E>) conj(O_n - <O>)]] whose weighted sum is [[gamma F]]
  * (formed as V^dagger H V with H = sum_n w_n f_n f_n^dagger on the matrix cores).
- * Same inputs, projection modes (COMPLEX or REAL) and shifts as vmc_sr_solve.
+ * Same inputs, projection modes and shifts as vmc_sr_solve, plus the Im
+ * projection (eq:tdvp_im, real parameters of a non-holomorphic network, where
+ * it keeps the symplectic structure and conserves energy; Sec. 2.3):
+ * VMC_SR_IMAG solves Im[S~] x = -Im[gamma F] with A = Im[S~] real and
+ * antisymmetric.  A has no real eigendecomposition; the Hermitian i A does
+ * (eigenvalues in +- pairs, lambda_1 and the cutoffs as above), and A x = b is
+ * (i A) x = i b, so the formulas above apply to i A, i b and the per-sample
+ * terms i Im[f_n]; x is real (imaginary parts written as 0).  IMAG needs
+ * complex O (C64 or C128) and eps_abs = 0 (else VMC_ERR_INVALID_ARG; nu_rel
+ * has no effect since diag Im S = 0); with eps_pinv = 0 a numerically zero
+ * eigenvalue (odd K) is inverted, so set a cutoff.
  * info: residual = ||S~ x + [[gamma F]]|| / ||[[gamma F]]|| (not small when
- * components are cut), min_pivot = smallest eigenvalue of S~, fail_index -1.
+ * components are cut), min_pivot = smallest eigenvalue of S~ (of i A for
+ * IMAG), fail_index -1.
  * evals (K float64, device, may be NULL): the eigenvalues (unordered);
  * snr (K float64, device, may be NULL): SNR_j (computed whenever snr is given);
  * *sweeps_host (may be NULL): Jacobi sweeps used.  O(K^3) per sweep: meant for

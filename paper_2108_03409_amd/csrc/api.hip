@@ -905,8 +905,11 @@ extern "C" int vmc_sr_solve_eig(vmc_ctx* ctx, const void* O, int O_dtype, const 
                 "shifts must be finite and non-negative");
     VMC_REQUIRE(opts->mode == VMC_SR_COMPLEX || opts->mode == VMC_SR_REAL || opts->mode == VMC_SR_IMAG,
                 "unknown mode");
-    if (opts->mode == VMC_SR_IMAG)
-      throw vmc_error{VMC_ERR_UNSUPPORTED, "Im S is antisymmetric; the eigen solve needs COMPLEX or REAL"};
+    if (opts->mode == VMC_SR_IMAG) {
+      VMC_REQUIRE(O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_C128,
+                  "the Im projection needs complex O (C64 or C128): Im S of real log-derivatives is zero");
+      VMC_REQUIRE(opts->eps_abs == 0.0, "an additive shift breaks the antisymmetry of Im S (eps_abs must be 0)");
+    }
     VMC_REQUIRE(opts->gram == 0 || opts->gram == 1, "gram must be 0 or 1");
     VMC_REQUIRE(opts->gram == 0 || O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_F32,
                 "the split-float16 product needs float32 O (C64 or F32)");
@@ -921,6 +924,36 @@ extern "C" int vmc_sr_solve_eig(vmc_ctx* ctx, const void* O, int O_dtype, const 
   });
   if (info_host) *info_host = info;
   if (sweeps_host) *sweeps_host = sw;
+  return rc;
+}
+
+extern "C" int vmc_sr_fisher(vmc_ctx* ctx, const void* O, int O_dtype, const double* eloc, const double* weights,
+                             int64_t N, int64_t K, const vmc_sr_opts* opts, double* S_out, double* F_out,
+                             vmc_sr_info* info_host) {
+  vmc_sr_info info{};
+  info.fail_index = -1;
+  info.residual = NAN;
+  info.min_pivot = NAN;
+  int rc = guard(ctx, [&] {
+    VMC_REQUIRE(ctx && opts, "NULL argument");
+    VMC_REQUIRE(O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_C128 || O_dtype == VMC_DT_F32 || O_dtype == VMC_DT_F64,
+                "O dtype must be C64, C128, F32 or F64");
+    VMC_REQUIRE(N >= 1 && K >= 1, "N and K must be positive");
+    VMC_REQUIRE(K <= 65536, "K above 65536 is not supported by the dense solve");
+    VMC_REQUIRE(O && eloc && S_out && F_out, "NULL buffer");
+    VMC_REQUIRE(std::isfinite(opts->nu_rel) && opts->nu_rel >= 0 && std::isfinite(opts->eps_abs) &&
+                    opts->eps_abs >= 0,
+                "shifts must be finite and non-negative");
+    VMC_REQUIRE(opts->mode == VMC_SR_COMPLEX || opts->mode == VMC_SR_REAL || opts->mode == VMC_SR_IMAG,
+                "unknown mode");
+    VMC_REQUIRE(opts->gram == 0 || opts->gram == 1, "gram must be 0 or 1");
+    VMC_REQUIRE(opts->gram == 0 || O_dtype == VMC_DT_C64 || O_dtype == VMC_DT_F32,
+                "the split-float16 product needs float32 O (C64 or F32)");
+    set_device(ctx);
+    sr_solve_impl(ctx, O, O_dtype, (const double2*)eloc, weights, N, K, opts, nullptr, &info, nullptr, nullptr,
+                  nullptr, nullptr, (double2*)S_out, (double2*)F_out);
+  });
+  if (info_host) *info_host = info;
   return rc;
 }
 

@@ -21,7 +21,9 @@
 // that touch the lower triangle are launched; the linear tile index is
 // remapped so that consecutive tiles of one row stripe run on the same XCD
 // (shared L2).  The epilogue writes S~ (float64, projection and diagonal shift
-// applied) to the lower triangle and its conjugate to the upper triangle.
+// applied) to the lower triangle and its conjugate to the upper triangle; for
+// the Im projection it writes the Hermitian matrix i Im S (purely imaginary,
+// zero diagonal) in place of the real antisymmetric Im S.
 //
 // Real mode (only Re S is used) keeps one accumulator, A + B, half the
 // matrix-core work per sample of the conventional complex product; with the
@@ -117,6 +119,7 @@ __device__ __forceinline__ void herk_epilogue(const herk_args& a, int64_t row0, 
           const double A = get(i, j, 0, r), B = get(i, j, 1, r);
           re = A + B;
           im = (get(i, j, 2, r) - A) + B;
+          if (a.mode == VMC_SR_IMAG) re = 0.0;  // i Im S (Hermitian; zero diagonal)
         }
         if (k == kp) {
           const double2 d = make_double2(re * (1.0 + a.nu) + a.eps, 0.0);

@@ -195,9 +195,10 @@ __global__ __launch_bounds__(256, 1) void k_herk16(h16_args a) {
         const int64_t kp = col0 + wc * 64 + j * 16 + li;
         if (k >= K || kp >= K || kp > k) continue;
         const double sc = ldexp(1.0, -(a.ex[k] + a.ex[kp]));
-        const double re = (double)acc[i][j][0][r] * sc;
+        double re = (double)acc[i][j][0][r] * sc;
         double im = (double)acc[i][j][1][r] * sc;
         if (a.mode == VMC_SR_REAL) im = 0.0;
+        if (a.mode == VMC_SR_IMAG) re = 0.0;  // i Im S
         if (k == kp) {
           const double2 d = make_double2(re * (1.0 + a.nu) + a.eps, 0.0);
           a.diag[k] = d;

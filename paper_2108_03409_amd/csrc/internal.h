@@ -451,7 +451,7 @@ void herk_split16(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode,
 // sr.hip
 void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N,
                    int64_t K, const vmc_sr_opts* o, double2* x, vmc_sr_info* info, const vmc_eig_opts* eo,
-                   double* evals, double* snr, int* sweeps);
+                   double* evals, double* snr, int* sweeps, double2* S_out = nullptr, double2* F_out = nullptr);
 double fisher_quad_impl(vmc_ctx* ctx, const void* O, int dtype, const double* w, int64_t N, int64_t K,
                         const double2* v);
 // eig.hip

@@ -237,6 +237,7 @@ __global__ __launch_bounds__(256) void k_herk_simple(const XT* __restrict__ X, i
       if (r >= K || c >= K || c > r) continue;
       double2 v = acc[i][j];
       if (mode == VMC_SR_REAL) v.y = 0.0;
+      if (mode == VMC_SR_IMAG) v.x = 0.0;  // i Im S
       if (r == c) {
         v = make_double2(v.x * (1.0 + nu) + eps, 0.0);
         diag[r] = v;
@@ -246,13 +247,21 @@ __global__ __launch_bounds__(256) void k_herk_simple(const XT* __restrict__ X, i
     }
 }
 
-// rhs = -[[gamma F]]
+// rhs = -[[gamma F]]; for the Im projection the system Im[S~] x = -Im[gamma F]
+// is held as (i Im S~) x = -i Im[gamma F], so rhs = (0, -Im[gamma F])
 __global__ void k_rhs(const double2* __restrict__ F, int64_t K, double gr, double gi, int mode, double2* __restrict__ rhs) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= K) return;
   double2 v = cmul(make_double2(gr, gi), F[k]);
   if (mode == VMC_SR_REAL) v.y = 0.0;
+  if (mode == VMC_SR_IMAG) v.x = 0.0;
   rhs[k] = make_double2(-v.x, -v.y);
+}
+
+// x <- Re x (the Im projection's solution is real)
+__global__ void k_keep_real(double2* __restrict__ x, int64_t K) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < K) x[k].y = 0.0;
 }
 
 // r_k = sum_c S~[k][c] x_c - rhs_k, using the upper triangle (S~ itself) and
@@ -564,7 +573,7 @@ __global__ __launch_bounds__(64) void k_v_mul(const double2* __restrict__ V, con
 }
 
 // Y_nk = sqrt(w_n) conj(f_nk),  f_nk = [[gamma (E_n - Ebar) conj(O_nk - mean_k)]]: the per-sample
-// terms whose weighted sum is [[gamma F]]
+// terms whose weighted sum is [[gamma F]] (i Im[.] for the Im projection)
 template <typename InT, typename XT>
 __global__ __launch_bounds__(256) void k_force_terms(const InT* __restrict__ O, const double* __restrict__ w,
                                                      const double2* __restrict__ e, int64_t N, int64_t K,
@@ -581,6 +590,7 @@ __global__ __launch_bounds__(256) void k_force_terms(const InT* __restrict__ O, 
     const double2 d = csub(load_c(O, n * K + k), mk);
     double2 f = cmul(make_double2(gr, gi), cmul(csub(e[n], eb), cconj(d)));
     if (mode == VMC_SR_REAL) f.y = 0.0;
+    if (mode == VMC_SR_IMAG) f.x = 0.0;  // i Im[.], the terms of the rhs held as i b
     const double2 y = make_double2(sq * f.x, -sq * f.y);
     if constexpr (std::is_same<XT, double2>::value)
       Y[n * K + k] = y;
@@ -695,7 +705,7 @@ __global__ void k_pinv_scale(const double* __restrict__ lam, const double* __res
 
 void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, const double* w, int64_t N, int64_t K,
                    const vmc_sr_opts* o, double2* x, vmc_sr_info* info, const vmc_eig_opts* eo, double* evals,
-                   double* snr, int* sweeps) {
+                   double* snr, int* sweeps, double2* S_out, double2* F_out) {
   hipStream_t st = ctx->stream;
   const int nchunk = (int)((N + kColChunk - 1) / kColChunk);
   const int kchunk = (int)((K + 255) / 256);
@@ -792,6 +802,21 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   VMC_HIP(hipGetLastError());
   ph.reset();
 
+  if (S_out) {  // test export: S~ and F as formed for the solve, no factorisation
+    VMC_HIP(hipMemcpyAsync(S_out, S, sizeof(double2) * (size_t)K * K, hipMemcpyDeviceToDevice, st));
+    VMC_HIP(hipMemcpyAsync(F_out, F, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
+    double* hs = (double*)pinned_host(ctx, sizeof(double) * 4);
+    VMC_HIP(hipMemcpyAsync(hs, stats, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+    VMC_HIP(hipStreamSynchronize(st));
+    info->e_mean[0] = hs[1];
+    info->e_mean[1] = hs[2];
+    info->e_var = hs[3];
+    info->fail_index = -1;
+    info->residual = NAN;
+    info->min_pivot = NAN;
+    return;
+  }
+
   if (eig) {
     info->fail_index = -1;
     // second moment of the per-sample force terms (SNR): H = Y^H Y
@@ -836,6 +861,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
     k_pinv_scale<<<grid_for(K, 256), 256, 0, st>>>(lam, lmax, rho, use_snr ? var : nullptr, K, (double)N,
                                                    eo->eps_pinv, eo->soft, eo->eps_snr, yv2, snr_d);
     k_v_mul<<<(unsigned)K, 64, 0, st>>>(Vm, yv2, K, sol);
+    if (o->mode == VMC_SR_IMAG) k_keep_real<<<grid_for(K, 256), 256, 0, st>>>(sol, K);
     VMC_HIP(hipGetLastError());
     ph.reset();
     if (evals) VMC_HIP(hipMemcpyAsync(evals, lam, sizeof(double) * K, hipMemcpyDeviceToDevice, st));

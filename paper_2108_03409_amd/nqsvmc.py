@@ -99,6 +99,7 @@ _SIGS = {
     "vmc_sampler_get_stats": ([P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
     "vmc_sampler_destroy": ([P], C.c_int),
     "vmc_sr_solve": ([P, P, C.c_int, P, P, I64, I64, C.POINTER(SROpts), P, C.POINTER(SRInfo)], C.c_int),
+    "vmc_sr_fisher": ([P, P, C.c_int, P, P, I64, I64, C.POINTER(SROpts), P, P, C.POINTER(SRInfo)], C.c_int),
     "vmc_sr_solve_cg": ([P, P, C.c_int, P, P, I64, I64, C.POINTER(SROpts), C.POINTER(CGOpts), P, C.POINTER(SRInfo),
                          C.POINTER(C.c_int)], C.c_int),
     "vmc_sr_solve_eig": ([P, P, C.c_int, P, P, I64, I64, C.POINTER(SROpts), C.POINTER(EigOpts), P,
@@ -465,6 +466,21 @@ def sr_solve(ctx: Context, O: torch.Tensor, eloc: torch.Tensor, *, weights=None,
     if rc != VMC_OK and raise_on_error:
         _check(rc, ctx.h)
     return (x if rc == VMC_OK else None), d
+
+
+def sr_fisher(ctx: Context, O: torch.Tensor, eloc: torch.Tensor, *, weights=None, nu_rel=0.0, eps_abs=0.0,
+              mode=SR_COMPLEX, gram=0):
+    """Test export: (S~ (K, K) complex128, F (K,) complex128, info) exactly as
+    sr_solve forms them (for SR_IMAG the matrix is i Im S)."""
+    N, K = O.shape
+    dt = {torch.complex128: DT_C128, torch.complex64: DT_C64, torch.float64: DT_F64, torch.float32: DT_F32}[O.dtype]
+    S = torch.empty((K, K), dtype=torch.complex128, device=O.device)
+    F = torch.empty(K, dtype=torch.complex128, device=O.device)
+    opts = SROpts(nu_rel, eps_abs, mode, 1.0, 0.0, gram)
+    info = SRInfo()
+    _check(load().vmc_sr_fisher(ctx.h, _ptr(O), dt, _ptr(eloc), _ptr(weights), N, K, C.byref(opts), _ptr(S), _ptr(F),
+                                C.byref(info)), ctx.h)
+    return S, F, dict(e_mean=complex(info.e_mean[0], info.e_mean[1]), e_var=info.e_var)
 
 
 def sr_solve_cg(ctx: Context, O: torch.Tensor, eloc: torch.Tensor, *, weights=None, nu_rel=1e-3, eps_abs=0.0,

@@ -225,3 +225,134 @@ def test_adaptive_heun_tdvp_follows_exact_evolution(ctx):
     flush(f"  steps {len(dts)}  dt {dts[0]:.1e} -> {max(dts):.1e}  rejected {st.n_rejected}  fidelity {fid:.8f}")
     assert fid > 0.9999
     assert max(dts) > 10 * dts[0]
+
+
+# ---- the Im projection of the TDVP equation (eq:tdvp_im, Sec. 2.3) --------
+
+def _cut_between_imag(O, el, frac, w=None):
+    """a relative cutoff between two distinct moduli of the eigenvalues of i Im S
+    (they come in +- pairs: a cut never separates a pair)"""
+    S, _ = osr.fisher_and_force(O, el, w)
+    lam = np.linalg.eigvalsh(1j * osr.project(S, "imag"))
+    r = np.sort(np.abs(lam) / np.abs(lam).max())
+    j = int(frac * len(r))
+    while r[j + 1] <= r[j] * (1 + 1e-6):
+        j += 1
+    return float(np.sqrt(r[j] * r[j + 1]))
+
+
+IMAG_CASES = [
+    # N, Nh, ns, gamma, pinv frac, soft, snr, weighted  (O: complex log-derivatives of real parameters)
+    (8, 16, 400, 1j, 0.3, False, 0.0, False),     # hard cutoff, real time: Im S x = -Re F
+    (8, 16, 400, 1.0, 0.3, True, 0.0, True),      # soft cutoff, gamma = 1, weighted
+    (9, 12, 1000, 1j, 0.2, True, 2.0, False),     # soft + SNR, odd K (one zero eigenvalue)
+]
+
+
+@pytest.mark.parametrize("N,Nh,ns,gamma,frac,soft,snr,weighted", IMAG_CASES)
+def test_sr_solve_eig_imag_matches_oracle(ctx, N, Nh, ns, gamma, frac, soft, snr, weighted):
+    flush(f"sr eig imag N={N} Nh={Nh} ns={ns} gamma={gamma} frac={frac} soft={soft} snr={snr}")
+    O, el = _problem(N, Nh, ns, 0.2, seed=N * Nh + 3, cplx=True)
+    w = np.random.default_rng(10).uniform(0.5, 1.5, ns) if weighted else None
+    eps = _cut_between_imag(O, el, frac, w)
+    x_ref, info_ref = osr.eigen_solve(O, el, mode="imag", gamma=gamma, weights=w, eps_pinv=eps, soft=soft,
+                                      eps_snr=snr)
+    x, info = V.sr_solve_eig(ctx, dev_c128(O), dev_c128(el), weights=None if w is None else
+                             torch.from_numpy(w).to(DEV), mode=V.SR_IMAG, gamma=gamma, eps_pinv=eps, soft=soft,
+                             eps_snr=snr, want_snr=True)
+    x = x.cpu().numpy()
+    assert np.all(x.imag == 0)
+    ev = np.sort(info["evals"].cpu().numpy())
+    lam = info_ref["evals"]
+    assert np.max(np.abs(ev - lam)) <= 1e-12 * np.abs(lam).max()
+    kept = np.abs(lam) >= eps * np.abs(lam).max()
+    kappa = np.abs(lam).max() / np.abs(lam[kept]).min()
+    err = np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)
+    assert err <= max(1e-11, 1e-14 * kappa * 100), (err, kappa)
+    s_ref, s_got = np.sort(info_ref["snr"]), np.sort(info["snr"].cpu().numpy())
+    fin = np.isfinite(s_ref)
+    assert np.allclose(s_got[fin], s_ref[fin], rtol=1e-8, atol=1e-12)
+    assert abs(info["residual"] - info_ref["residual"]) <= 1e-8 + 1e-6 * info_ref["residual"]
+    # energy conservation of the Im form: Re F . x = 0 (x = A^+ b with A^+ antisymmetric)
+    if gamma == 1j:
+        _, F = osr.fisher_and_force(O, el, w)
+        assert abs(np.dot(F.real, x.real)) <= 1e-12 * np.linalg.norm(F.real) * np.linalg.norm(x)
+
+
+def test_sr_solve_eig_imag_refusals(ctx):
+    O, el = _problem(6, 6, 50, 0.2, seed=2, cplx=True)
+    with pytest.raises(V.VMCError):
+        V.sr_solve_eig(ctx, dev_c128(O), dev_c128(el), mode=V.SR_IMAG, eps_abs=1e-3, eps_pinv=1e-8)
+    with pytest.raises(V.VMCError):
+        V.sr_solve_eig(ctx, torch.from_numpy(O.real.copy()).to(DEV), dev_c128(el), mode=V.SR_IMAG, eps_pinv=1e-8)
+    with pytest.raises(V.VMCError):
+        V.sr_solve(ctx, dev_c128(O), dev_c128(el), mode=V.SR_IMAG)
+
+
+@pytest.mark.parametrize("eps_pinv,soft", [(0.0, False), (1e-3, False), (1e-3, True)])
+def test_imag_form_of_holomorphic_net_is_the_complex_solve(ctx, eps_pinv, soft):
+    # Sec. 2.3: solving the complex equation for complex parameters equals the Im
+    # form for their real and imaginary parts, O_real = [O, i O]
+    flush(f"imag form of a holomorphic net eps={eps_pinv} soft={soft}")
+    O, el = _problem(8, 8, 500, 0.2, seed=77, cplx=True)
+    K = O.shape[1]
+    Or = np.concatenate([O, 1j * O], axis=1)
+    xc, _ = V.sr_solve_eig(ctx, dev_c128(O), dev_c128(el), mode=V.SR_COMPLEX, gamma=1j, eps_pinv=eps_pinv,
+                           soft=soft)
+    xr, _ = V.sr_solve_eig(ctx, dev_c128(Or), dev_c128(el), mode=V.SR_IMAG, gamma=1j,
+                           eps_pinv=eps_pinv if eps_pinv > 0 else 1e-12, soft=soft)
+    xc, xr = xc.cpu().numpy(), xr.cpu().numpy().real
+    err = np.linalg.norm(xr[:K] + 1j * xr[K:] - xc) / np.linalg.norm(xc)
+    assert err <= 1e-9, err
+
+
+def test_imag_form_conserves_energy_in_real_time(ctx):
+    # a non-holomorphic network of real parameters: modulus and phase from two
+    # real RBMs, log psi = l_A(s; a) + i l_B(s; b), O = [O_A, i O_B], started from
+    # a = b.  Exact weights over all 2^6 configurations, Heun steps, pseudo-
+    # inverse cutoff 1e-8, t = 0.1.  The Im form (eq:tdvp_im) conserves the
+    # energy up to the integrator's error (which falls as dt^2: 4.7e-5 at
+    # dt = 0.005, 1.1e-5 at 0.0025 with the oracle's solve); the Re form
+    # (eq:tdvp_re) drifts by a step-independent 7e-4.
+    from kron_ref import tfim as kron_tfim, code_to_kron
+    from oracle.eloc import all_states
+    from gpu_common import dev_bits
+    N, Nh, h, T = 6, 1, 1.0, 0.1
+    states = all_states(N)
+    s_dev = dev_bits(si.pack_bits(states))
+    idx = code_to_kron((states.astype(np.int64) << np.arange(N)).sum(1), N)
+    Hk = kron_tfim(N, 1, True, 1.0, h).toarray()[np.ix_(idx, idx)]   # library code order
+    mA = V.Model.rbm(ctx, N, Nh, False)
+    mB = V.Model.rbm(ctx, N, Nh, False)
+    p0 = si.rbm_params(N, Nh, std=0.3, is_complex=False, seed=51).real
+    K = len(p0)
+
+    def rhs(th, mode):
+        mA.set_params(torch.from_numpy(th[:K].copy()).to(DEV))
+        mB.set_params(torch.from_numpy(th[K:].copy()).to(DEV))
+        lp = mA.log_psi(s_dev).real + 1j * mB.log_psi(s_dev).real
+        O = torch.cat([mA.grad_log_psi(s_dev).real.to(torch.complex128),
+                       1j * mB.grad_log_psi(s_dev).real.to(torch.complex128)], dim=1).contiguous()
+        lph = lp.cpu().numpy()
+        psi = np.exp(lph - lph.real.max())
+        el = (Hk @ psi) / psi
+        w = np.abs(psi) ** 2
+        x, _ = V.sr_solve_eig(ctx, O, dev_c128(el), weights=torch.from_numpy(w / w.sum()).to(DEV), mode=mode,
+                              gamma=1j, eps_pinv=1e-8)
+        return x.cpu().numpy().real, float(np.real(np.sum(w * el) / w.sum()))
+
+    drift = {}
+    for mode, name in [(V.SR_IMAG, "imag"), (V.SR_REAL, "real")]:
+        for dt in (0.005, 0.0025):
+            th = np.concatenate([p0, p0])
+            _, E0 = rhs(th, mode)
+            for _ in range(int(round(T / dt))):
+                k1, _ = rhs(th, mode)
+                k2, _ = rhs(th + dt * k1, mode)
+                th = th + 0.5 * dt * (k1 + k2)
+            _, E1 = rhs(th, mode)
+            drift[name, dt] = E1 - E0
+    flush(f"  energy drift over t = {T}: " + ", ".join(f"{k[0]} dt={k[1]}: {v:.3e}" for k, v in drift.items()))
+    assert abs(drift["imag", 0.0025]) < abs(drift["imag", 0.005]) / 2.5        # integrator error, ~dt^2
+    assert abs(drift["imag", 0.0025]) < 0.05 * abs(drift["real", 0.0025])
+    assert abs(drift["real", 0.0025] - drift["real", 0.005]) < 0.1 * abs(drift["real", 0.005])
