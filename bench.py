@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--workload", default="tfim1d_L64_rbm_a4_sr",
                     choices=["tfim1d_L64_rbm_a4_sr", "heis2d_10x10_rbm_a4", "tfim2d_16x16_cnn",
                              "tfim2d_20x20_rbm_a2_made", "tfim2d_20x20_rbm_a2_sr", "tfim1d_L50_ar_sr"])
-    ap.add_argument("--p-global", type=float, default=None, help="MADE mix: global proposal probability")
+    ap.add_argument("--global-steps", type=int, default=1,
+                    help="MADE mix: global proposals of all chains at the start of every sweep")
     ap.add_argument("--record-sweeps", type=int, default=256, help="MADE mix: recorded sweeps per chain")
     ap.add_argument("--made-epochs", type=int, default=100, help="MADE mix: training epochs")
     ap.add_argument("--made-lr", type=float, default=1e-3, help="MADE mix: Adam learning rate")
@@ -252,12 +253,12 @@ def bench_made(args, V, torch):
     nll = made.train(data, epochs=args.made_epochs, batch=1024, lr=args.made_lr)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    pg = args.p_global if args.p_global is not None else 1.0 / N
+    G = args.global_steps
     R = args.record_sweeps
     res = {}
     for name, prop in [("local", V.PROP_FLIP), ("mixed", V.PROP_MADE_MIX)]:
         S = V.Sampler(ctx, model, H, proposal=prop, n_chains=nc, therm_sweeps=100, seed=cfg["sampler_seed"],
-                      p_global=pg)
+                      global_steps=G)
         if prop == V.PROP_MADE_MIX:
             S.set_proposal_made(made)
         S.sample(nc)                       # thermalisation + one sweep, untimed
@@ -284,7 +285,7 @@ def bench_made(args, V, torch):
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(res["mixed"]["sample_s"] * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (bond-RBM at the 2D Ising critical coupling)",
-        "config": {"workload": args.workload, "n_chains": nc, "record_sweeps": R, "p_global": pg,
+        "config": {"workload": args.workload, "n_chains": nc, "record_sweeps": R, "global_steps": G,
                    "made_hidden": mh, "train_samples": cfg["train_samples"], "made_epochs": args.made_epochs,
                    "made_lr": args.made_lr},
         "local": res["local"], "mixed": res["mixed"], "ess_per_s_ratio_mixed_over_local": round(ratio, 3),

@@ -249,7 +249,7 @@ typedef struct {
   int n_chains;      /* > 0 */
   int sweep_steps;   /* proposals per sweep; 0 means N */
   int therm_sweeps;  /* thermalisation sweeps before the first sample */
-  double p_global;   /* MADE_MIX: probability of a global proposal */
+  int global_steps;  /* MADE_MIX: global proposals at the start of every sweep, in [0, 1024] */
   uint64_t seed;
 } vmc_sampler_opts;
 /* The sampler keeps a reference to m (and H for bonds); both must outlive it. */
@@ -268,8 +268,9 @@ int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, double* logps
  * set_state the chains continue exactly as the saved sampler would have.    */
 int vmc_sampler_get_state(vmc_sampler* S, void* buf_host, size_t* bytes);
 int vmc_sampler_set_state(vmc_sampler* S, const void* buf_host, size_t bytes);
-/* Acceptance statistics of the last vmc_sample call: overall acceptance, the
- * acceptance of global (MADE) proposals and their number (MADE_MIX only). */
+/* Acceptance statistics of the last vmc_sample call: overall acceptance (flips
+ * and global proposals), the acceptance of global (MADE) proposals and their
+ * number (MADE_MIX only). */
 int vmc_sampler_get_stats(vmc_sampler* S, double* accept_rate_host, double* global_accept_rate_host,
                           int64_t* n_global_host);
 /* Frozen MADE proposal used by VMC_PROP_MADE_MIX (the sampler copies its
@@ -439,11 +440,19 @@ int vmc_made_nll_grad(vmc_made* md, const uint64_t* s, int64_t B, double* grad, 
 int vmc_made_train(vmc_made* md, const uint64_t* s, int64_t B, int epochs, int batch, double lr, double* nll_host);
 /* Autoregressive samples: row c uses Philox((c, counter_lo, counter_hi, 1 + 256*(d/4))),
  * site d up iff x_{d%4} * 2^-32 < p_d.  s_out: B*W words; logq: B doubles.
- * In VMC_PROP_MADE_MIX, proposal t of chain c is global iff x3 * 2^-32 < p_global
- * (x = the proposal's Philox block) and its sample uses (c, t) as (row, counter);
- * it is accepted iff r >= 0 or u < exp(r),
- *   r = 2 Re(log psi(s') - log psi(s)) + log q(s) - log q(s').  A local proposal
- * is the single-spin flip of VMC_PROP_FLIP.                                    */
+ * In VMC_PROP_MADE_MIX every sweep (thermalisation sweeps included) starts
+ * with global_steps global proposals made by all chains together, then the
+ * sweep's single-spin flips of VMC_PROP_FLIP (their counter t counts flips
+ * only).  Global proposal g of chain c (g counted from 0 over the sampler's
+ * life) is the sample of row c with counter g, accepted iff r >= 0 or
+ * u < exp(r),  r = 2 Re(log psi(s') - log psi(s)) + log q(s) - log q(s'),
+ * u = ((x1 << 21) | (x2 >> 11)) 2^-53 of x = Philox((c, g_lo, g_hi, 3)).
+ * Each global step and each flip leaves |psi|^2 invariant.  The sampler's
+ * global passes are blocked over 16 sites at a time on the float64 matrix
+ * cores (same logits up to rounding order; log q of the chain state and of
+ * the proposal come from the same code and are consistent to the bit).  The
+ * MADE must fit that pass: 16 (H + 1) + 2304 doubles plus 16 W words of LDS
+ * (H <= 1024 with W <= 64 does).                                              */
 int vmc_made_sample(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, uint64_t* s_out, double* logq);
 int vmc_made_destroy(vmc_made* md);
 

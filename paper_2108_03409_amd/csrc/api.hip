@@ -689,7 +689,7 @@ extern "C" int vmc_sampler_create(vmc_ctx* ctx, vmc_model* m, vmc_ham* H, const 
       VMC_REQUIRE(m->N % 2 == 0, "exchange sampling starts in Sz = 0 and needs an even site count");
     }
     if (o->proposal == VMC_PROP_MADE_MIX)
-      VMC_REQUIRE(o->p_global >= 0.0 && o->p_global <= 1.0, "p_global must be in [0, 1]");
+      VMC_REQUIRE(o->global_steps >= 0 && o->global_steps <= 1024, "global_steps must be in [0, 1024]");
     VMC_REQUIRE(m->kind == MODEL_RBM || o->proposal == VMC_PROP_FLIP ||
                     (m->kind == MODEL_TABLE && o->proposal == VMC_PROP_EXCHANGE),
                 "CNN models are sampled with single flips; autoregressive states take VMC_PROP_FLIP (direct "
@@ -772,7 +772,7 @@ extern "C" int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, do
         tg += (double)h[nc + c];
         ng += (double)h[2 * nc + c];
       }
-    const double steps = (double)(S->t - t0) * nc;
+    const double steps = (double)(S->t - t0) * nc + ng;  // flips and global proposals
     S->last_accept = steps > 0 ? tot / steps : 0.0;
     S->last_global_accept = ng > 0 ? tg / ng : 0.0;
     S->last_n_global = (int64_t)ng;
@@ -782,9 +782,9 @@ extern "C" int vmc_sample(vmc_sampler* S, int64_t n_samples, uint64_t* s_out, do
 
 namespace {
 struct state_header {
-  uint64_t magic, N, W, n_chains, t, thermalized, seed, proposal;
+  uint64_t magic, N, W, n_chains, t, thermalized, seed, proposal, g;
 };
-const uint64_t kStateMagic = 0x4e51535653414d31ull;  // "NQSVSAM1"
+const uint64_t kStateMagic = 0x4e51535653414d32ull;  // "NQSVSAM2"
 }  // namespace
 
 extern "C" int vmc_sampler_get_state(vmc_sampler* S, void* buf_host, size_t* bytes) {
@@ -799,7 +799,7 @@ extern "C" int vmc_sampler_get_state(vmc_sampler* S, void* buf_host, size_t* byt
     VMC_REQUIRE(*bytes >= need, "state buffer too small");
     set_device(S->ctx);
     state_header h{kStateMagic, (uint64_t)S->N, (uint64_t)S->W, (uint64_t)S->opts.n_chains, S->t,
-                   (uint64_t)S->thermalized, S->opts.seed, (uint64_t)S->opts.proposal};
+                   (uint64_t)S->thermalized, S->opts.seed, (uint64_t)S->opts.proposal, S->g};
     std::memcpy(buf_host, &h, sizeof(h));
     VMC_HIP(hipStreamSynchronize(S->ctx->stream));
     VMC_HIP(hipMemcpy((char*)buf_host + sizeof(h), S->bits, need - sizeof(h), hipMemcpyDeviceToHost));
@@ -823,6 +823,7 @@ extern "C" int vmc_sampler_set_state(vmc_sampler* S, const void* buf_host, size_
     VMC_HIP(hipStreamSynchronize(S->ctx->stream));
     VMC_HIP(hipMemcpy(S->bits, (const char*)buf_host + sizeof(h), need - sizeof(h), hipMemcpyHostToDevice));
     S->t = h.t;
+    S->g = h.g;
     S->thermalized = (int)h.thermalized;
     S->opts.seed = h.seed;
     S->bits_valid = 1;
@@ -845,7 +846,9 @@ extern "C" int vmc_sampler_destroy(vmc_sampler* S) {
   (void)hipStreamSynchronize(S->ctx->stream);
   if (S->bits) (void)hipFree(S->bits);
   if (S->acc) (void)hipFree(S->acc);
-  if (S->made_buf) (void)hipFree(S->made_buf);
+  for (void* p : {(void*)S->made_buf, (void*)S->mix_perm, (void*)S->mix_prop, (void*)S->mix_lq,
+                  (void*)S->mix_theta, (void*)S->mix_theta_prop})
+    if (p) (void)hipFree(p);
   vmc_ctx* ctx = S->ctx;
   delete S;
   ctx_release(ctx);

@@ -212,6 +212,12 @@ struct vmc_sampler {
   // frozen MADE proposal (VMC_PROP_MADE_MIX): [W1m^T (N x H) | W2m (N x H) | b1 (H) | b2 (N)]
   int made_H = 0;
   double* made_buf = nullptr;
+  int* mix_perm = nullptr;            // [H] units sorted by degree, then [N + 1] first position per degree
+  uint64_t g = 0;                     // global proposals per chain so far
+  uint64_t* mix_prop = nullptr;       // [n_chains][W] proposals of a global step
+  double* mix_lq = nullptr;           // [2][n_chains] log q of the chain states and of the proposals
+  double2* mix_theta = nullptr;       // [n_chains][N_h] theta of the chain states between launches
+  double2* mix_theta_prop = nullptr;  // [n_chains][N_h] theta of the proposals
 };
 
 struct vmc_made {
@@ -423,6 +429,11 @@ void rbm_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t 
 void rbm_lowp_free(vmc_model* m);
 // sampler.hip
 void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
+void mix_ensure(vmc_sampler* S);
+// mixsampler.hip
+void mix_made_layout(int N, int H, std::vector<int>& perm, std::vector<int>& mstart);
+bool mix_made_fits(int H, int W);
+void mix_global_step(vmc_sampler* S, uint64_t g);
 // gemm64.hip: C = beta C + op(A) op(B) in float64 with arbitrary strides
 struct dgemm_args {
   const double* A;

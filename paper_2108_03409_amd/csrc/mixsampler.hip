@@ -1,0 +1,365 @@
+// Global moves of the learned-proposal sampler (VMC_PROP_MADE_MIX): every
+// sweep starts with global Metropolis-Hastings steps in which all chains
+// propose together an independent sample s' ~ q of the frozen masked network
+// (MADE), accepted with
+//   r = 2 Re(log psi(s') - log psi(s)) + log q(s) - log q(s'),
+// an independence-sampler kernel that keeps |psi|^2 invariant (Hastings 1970);
+// the sweep's single-spin flips follow (sampler.hip).
+//
+// One global step is three launches over all chains:
+//  1. k_made_block: log q of every chain state (teacher forcing) and, in the
+//     other half of the grid, a sample s' with its log q.  The autoregressive
+//     pass is blocked: sites are taken MP = 16 at a time, and for each block
+//       - the logits' part from hidden units whose inputs are all known
+//         (degree m(k) <= d0) is a float64 matrix-core product
+//         [16 chains x H] . [H x 16 sites];
+//       - the units whose degree falls inside the block (about 1.3 per site
+//         for H = 512, N = 400) are finished site by site, 16 lanes per chain;
+//       - the block's bits update the pre-activations of the later units as a
+//         second product [16 chains x 16 sites] . [16 sites x H].
+//     The sequential dependence per sample is then 16 short site steps per
+//     block instead of one H-wide reduction per site.  The teacher-forced and
+//     the sampling pass run the same code and arithmetic, so log q(s) is the
+//     same function of s whether s was drawn or given: q(s) and q(s') in the
+//     acceptance ratio are exactly consistent.
+//  2. theta' = b + W sigma' of the proposals (rbm_theta, float64).
+//  3. k_mix_accept: the ratio from the chain's theta (kept between launches)
+//     and theta', the uniform of Philox((c, g_lo, g_hi, 3)), and on acceptance
+//     the proposal's bits and theta replace the chain's.
+#include "internal.h"
+
+using namespace dev;
+
+namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int MC = 16;    // chains per work-group (rows of v_mfma_f64_16x16x4)
+constexpr int MP = 16;    // sites per block (columns of the logits product)
+constexpr int UCAP = 64;  // in-block units whose weights are staged in LDS
+
+struct made_block_args {
+  const double* W1mT;  // [N][H] masked W1, transposed (row d: W1m[k][d] over k)
+  const double* W2m;   // [N][H] masked W2 (row i: W2m[i][k] over k)
+  const double* b1;    // [H]
+  const double* b2;    // [N]
+  const int* perm;     // [H] hidden units sorted by degree m(k) (ascending k within a degree)
+  const int* mstart;   // [N + 1] first position in perm with degree >= v
+  int N, H, W;
+  int n_chains;
+  const uint64_t* cur;  // [n_chains][W] chain states (teacher forcing, blockIdx.y == 0)
+  uint64_t* prop;       // [n_chains][W] proposals (sampling, blockIdx.y == 1)
+  double* lq_cur;       // [n_chains]
+  double* lq_prop;      // [n_chains]
+  uint2 key;
+  uint32_t lo, hi;
+};
+
+__device__ __forceinline__ double softplus_f64(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
+
+__device__ __forceinline__ int degree(int k, int N) { return k % (N - 1) + 1; }
+
+__global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
+  extern __shared__ double smem[];
+  const int N = a.N, H = a.H, W = a.W;
+  const int Hs = H + 1;
+  double* as_ = smem;                                 // [MC][Hs] pre-activations
+  double* un_ = as_ + MC * Hs;                        // union: [4][256] partial logits | staged weights
+  double* red_ = un_;
+  double* w2s = un_;                                  // [MP][UCAP]
+  double* w1s = un_ + MP * UCAP;                      // [MP][UCAP]
+  double* Ls_ = un_ + 2 * MP * UCAP;                  // [MC][MP] logits from the finished units (+ b2)
+  uint64_t* bits_ = (uint64_t*)(Ls_ + MC * MP);       // [MC][W]
+  int* us_ = (int*)(bits_ + MC * W);                  // [UCAP]
+
+  const bool sample = blockIdx.y == 1;
+  const int c0 = blockIdx.x * MC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+
+  for (int e = tid; e < MC * H; e += 256) {
+    const int c = e / H, k = e % H;
+    as_[c * Hs + k] = a.b1[k];
+  }
+  for (int e = tid; e < MC * W; e += 256) {
+    const int c = e / W, w = e % W;
+    bits_[e] = (!sample && c0 + c < a.n_chains) ? a.cur[(int64_t)(c0 + c) * W + w] : 0ull;
+  }
+  __syncthreads();
+
+  // phase B lane roles: chain cl of this wave, 16 lanes per chain
+  const int cl = wave * 4 + lk;
+  const int sub = li;
+  const uint32_t cg = (uint32_t)(c0 + cl);
+  double lq = 0.0;
+  uint4 x4 = make_uint4(0, 0, 0, 0);
+  const int Hq = ((H + 15) / 16) * 4;  // hidden units per wave in phase A (a multiple of 4)
+
+  for (int d0 = 0; d0 < N; d0 += MP) {
+    const int P = min(MP, N - d0);
+    // ---- phase A: logits of the block's sites from the finished units ----
+    if (d0 > 0) {
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+      const int kb = wave * Hq, ke = min(H, kb + Hq);
+      for (int k0 = kb; k0 < ke; k0 += 4) {
+        const int k = k0 + lk;
+        double av = 0.0, bv = 0.0;
+        if (k < ke) {
+          if (degree(k, N) <= d0) av = fmax(as_[li * Hs + k], 0.0);  // A[chain li][unit k]
+          if (d0 + li < N) bv = a.W2m[(int64_t)(d0 + li) * H + k];    // B[unit k][site li]
+        }
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red_[wave * 256 + (lk + 4 * r) * 16 + li] = acc[r];
+    }
+    __syncthreads();
+    {
+      const int c = tid >> 4, i = tid & 15;
+      double v = 0.0;
+      if (d0 + i < N) {
+        v = a.b2[d0 + i];
+        if (d0 > 0) v += ((red_[tid] + red_[256 + tid]) + red_[512 + tid]) + red_[768 + tid];
+      }
+      Ls_[c * MP + i] = v;
+    }
+    __syncthreads();
+    // ---- stage the weights of the units whose degree lies inside the block ----
+    const int j0 = a.mstart[d0 + 1];
+    const int nU = a.mstart[d0 + P] - j0;
+    const bool staged = nU <= UCAP;
+    if (staged) {
+      for (int e = tid; e < MP * nU; e += 256) {
+        const int i = e / nU, j = e % nU;
+        const int u = a.perm[j0 + j];
+        const bool in = i < P;
+        w2s[i * UCAP + j] = in ? a.W2m[(int64_t)(d0 + i) * H + u] : 0.0;
+        w1s[i * UCAP + j] = in ? a.W1mT[(int64_t)(d0 + i) * H + u] : 0.0;
+        if (i == 0) us_[j] = u;
+      }
+    }
+    __syncthreads();
+    // ---- phase B: the block's sites one by one, 16 lanes per chain ----
+    for (int i = 0; i < P; ++i) {
+      const int d = d0 + i;
+      double part = 0.0;
+      if (staged) {
+        for (int j = sub; j < nU; j += 16) {
+          const int u = us_[j];
+          if (degree(u, N) <= d) part += w2s[i * UCAP + j] * fmax(as_[cl * Hs + u], 0.0);
+        }
+      } else {
+        for (int j = sub; j < nU; j += 16) {
+          const int u = a.perm[j0 + j];
+          if (degree(u, N) <= d) part += a.W2m[(int64_t)d * H + u] * fmax(as_[cl * Hs + u], 0.0);
+        }
+      }
+      part += __shfl_xor(part, 8, 16);
+      part += __shfl_xor(part, 4, 16);
+      part += __shfl_xor(part, 2, 16);
+      part += __shfl_xor(part, 1, 16);
+      part = __shfl(part, 0, 16);  // one value per chain: a uniform decision
+      const double l = Ls_[cl * MP + i] + part;
+      bool up;
+      if (sample) {
+        if ((d & 3) == 0) x4 = philox(make_uint4(cg, a.lo, a.hi, 1u + 256u * (uint32_t)(d >> 2)), a.key);
+        const uint32_t xr = (d & 3) == 0 ? x4.x : (d & 3) == 1 ? x4.y : (d & 3) == 2 ? x4.z : x4.w;
+        up = (double)xr * 0x1.0p-32 < 1.0 / (1.0 + exp(-l));
+      } else {
+        up = (bits_[cl * W + (d >> 6)] >> (d & 63)) & 1ull;
+      }
+      lq += (up ? l : 0.0) - softplus_f64(l);
+      if (up) {
+        if (staged) {
+          for (int j = sub; j < nU; j += 16) {
+            const int u = us_[j];
+            if (degree(u, N) > d) as_[cl * Hs + u] += w1s[i * UCAP + j];
+          }
+        } else {
+          for (int j = sub; j < nU; j += 16) {
+            const int u = a.perm[j0 + j];
+            if (degree(u, N) > d) as_[cl * Hs + u] += a.W1mT[(int64_t)d * H + u];
+          }
+        }
+        if (sample && sub == 0) bits_[cl * W + (d >> 6)] |= 1ull << (d & 63);
+      }
+    }
+    __syncthreads();
+    // ---- phase C: the block's inputs into the units of higher degree ----
+    if (d0 + P < N) {
+      const int ntile = (H + 15) / 16;
+      for (int t = wave; t < ntile; t += 4) {
+        const int k0 = t * 16;
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const int i = ks * 4 + lk;
+          double av = 0.0, bv = 0.0;
+          if (i < P) {
+            av = (double)((bits_[li * W + ((d0 + i) >> 6)] >> ((d0 + i) & 63)) & 1ull);  // A[chain li][site i]
+            if (k0 + li < H) bv = a.W1mT[(int64_t)(d0 + i) * H + k0 + li];              // B[site i][unit]
+          }
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        const int k = k0 + li;
+        if (k < H && degree(k, N) >= d0 + P) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) as_[(lk + 4 * r) * Hs + k] += acc[r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (c0 + cl < a.n_chains && sub == 0) {
+    if (sample)
+      a.lq_prop[c0 + cl] = lq;
+    else
+      a.lq_cur[c0 + cl] = lq;
+  }
+  if (sample)
+    for (int e = tid; e < MC * W; e += 256) {
+      const int c = e / W;
+      if (c0 + c < a.n_chains) a.prop[(int64_t)c0 * W + e] = bits_[e];
+    }
+}
+
+struct mix_accept_args {
+  const double2* params;  // RBM [a (N) | b | W]
+  int N, W, Nh;
+  int n_chains;
+  uint64_t* bits;         // [n_chains][W]
+  const uint64_t* prop;   // [n_chains][W]
+  double2* theta;         // [n_chains][Nh]
+  const double2* theta_prop;
+  const double* lq_cur;
+  const double* lq_prop;
+  uint2 key;
+  uint32_t lo, hi;
+  unsigned long long* acc;  // [3][n_chains]: accepted (all), accepted global, global proposals
+};
+
+template <int Q>
+__global__ __launch_bounds__(64) void k_mix_accept(mix_accept_args a) {
+  const int c = blockIdx.x;
+  if (c >= a.n_chains) return;
+  const int lane = threadIdx.x;
+  const int N = a.N, W = a.W, Nh = a.Nh;
+  const uint64_t* sc = a.bits + (int64_t)c * W;
+  const uint64_t* sp = a.prop + (int64_t)c * W;
+  double dre = 0.0;  // 2 Re(log psi(s') - log psi(s)), lane partial
+  for (int i = lane; i < N; i += 64) {
+    const double sn = get_bit(sp, i) ? 1.0 : -1.0;
+    const double so = get_bit(sc, i) ? 1.0 : -1.0;
+    dre += 2.0 * a.params[i].x * (sn - so);
+  }
+  double2 thn[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int j = lane + 64 * q;
+    thn[q] = j < Nh ? a.theta_prop[(int64_t)c * Nh + j] : make_double2(0.0, 0.0);
+    if (j < Nh) dre += 2.0 * (clogcosh(thn[q]).x - clogcosh(a.theta[(int64_t)c * Nh + j]).x);
+  }
+  double dr = wave_sum(dre);
+  dr = __shfl(dr, 0, 64);
+  const double r = dr + a.lq_cur[c] - a.lq_prop[c];
+  const uint4 x = philox(make_uint4((uint32_t)c, a.lo, a.hi, 3u), a.key);
+  const double u = to_uniform(x.y, x.z);
+  const bool acc = (r >= 0.0) || (u < exp(r));
+  if (acc) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int j = lane + 64 * q;
+      if (j < Nh) a.theta[(int64_t)c * Nh + j] = thn[q];
+    }
+    for (int w = lane; w < W; w += 64) a.bits[(int64_t)c * W + w] = sp[w];
+  }
+  if (lane == 0) {
+    a.acc[c] += acc ? 1ull : 0ull;
+    a.acc[a.n_chains + c] += acc ? 1ull : 0ull;
+    a.acc[2 * (int64_t)a.n_chains + c] += 1ull;
+  }
+}
+
+size_t made_block_lds(int H, int W) {
+  return sizeof(double) * ((size_t)MC * (H + 1) + std::max(4 * 256, 2 * MP * UCAP) + MC * MP) +
+         sizeof(uint64_t) * MC * (size_t)W + sizeof(int) * UCAP;
+}
+
+}  // namespace
+
+// units sorted by degree m(k) = k mod (N - 1) + 1 and the first position of
+// each degree (host side, once per proposal network)
+void mix_made_layout(int N, int H, std::vector<int>& perm, std::vector<int>& mstart) {
+  perm.resize(H);
+  mstart.assign(N + 1, 0);
+  std::vector<int> cnt(N + 1, 0);
+  for (int k = 0; k < H; ++k) ++cnt[k % (N - 1) + 1];
+  for (int v = 1; v <= N; ++v) mstart[v] = mstart[v - 1] + cnt[v - 1];
+  std::vector<int> pos(mstart.begin(), mstart.end());
+  for (int k = 0; k < H; ++k) perm[pos[k % (N - 1) + 1]++] = k;
+}
+
+bool mix_made_fits(int H, int W) {
+  int dev = 0, lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return false;
+  return made_block_lds(H, W) <= (size_t)lds;
+}
+
+void mix_global_step(vmc_sampler* S, uint64_t g) {
+  vmc_model* m = S->model;
+  hipStream_t st = S->ctx->stream;
+  const int nc = S->opts.n_chains;
+  const int N = m->N, H = S->made_H, W = m->W;
+  const int64_t nh = (int64_t)N * H;
+  made_block_args b{};
+  b.W1mT = S->made_buf;
+  b.W2m = S->made_buf + nh;
+  b.b1 = S->made_buf + 2 * nh;
+  b.b2 = S->made_buf + 2 * nh + H;
+  b.perm = S->mix_perm;
+  b.mstart = S->mix_perm + H;
+  b.N = N;
+  b.H = H;
+  b.W = W;
+  b.n_chains = nc;
+  b.cur = S->bits;
+  b.prop = S->mix_prop;
+  b.lq_cur = S->mix_lq;
+  b.lq_prop = S->mix_lq + nc;
+  b.key = make_uint2((uint32_t)S->opts.seed, (uint32_t)(S->opts.seed >> 32));
+  b.lo = (uint32_t)g;
+  b.hi = (uint32_t)(g >> 32);
+  const size_t lds = made_block_lds(H, W);
+  k_made_block<<<dim3((unsigned)((nc + MC - 1) / MC), 2), 256, lds, st>>>(b);
+  VMC_HIP(hipGetLastError());
+  rbm_theta(m, S->mix_prop, nc, S->mix_theta_prop);
+  mix_accept_args c{};
+  c.params = m->params;
+  c.N = N;
+  c.W = W;
+  c.Nh = m->Nh;
+  c.n_chains = nc;
+  c.bits = S->bits;
+  c.prop = S->mix_prop;
+  c.theta = S->mix_theta;
+  c.theta_prop = S->mix_theta_prop;
+  c.lq_cur = S->mix_lq;
+  c.lq_prop = S->mix_lq + nc;
+  c.key = b.key;
+  c.lo = b.lo;
+  c.hi = b.hi;
+  c.acc = S->acc;
+  const int Q = (m->Nh + 63) / 64;
+  if (Q <= 1)
+    k_mix_accept<1><<<nc, 64, 0, st>>>(c);
+  else if (Q <= 2)
+    k_mix_accept<2><<<nc, 64, 0, st>>>(c);
+  else if (Q <= 4)
+    k_mix_accept<4><<<nc, 64, 0, st>>>(c);
+  else if (Q <= 8)
+    k_mix_accept<8><<<nc, 64, 0, st>>>(c);
+  else
+    k_mix_accept<16><<<nc, 64, 0, st>>>(c);
+  VMC_HIP(hipGetLastError());
+}

@@ -9,12 +9,10 @@
 // rule t' = (t - sigma T) / (1 - sigma t T); theta is rebuilt from the spins
 // at the start of every call and t from theta at every recorded sample.
 //
-// VMC_PROP_MADE_MIX: each proposal is, with probability p_global, an
-// independent sample s' ~ q of the frozen MADE (drawn in-kernel by the same
-// wave, hidden units across lanes) accepted with the Metropolis-Hastings rule
-//   r = 2 Re(log psi(s') - log psi(s)) + log q(s) - log q(s'),
-// and otherwise a single-spin flip.  log q of the current state is cached and
-// recomputed (teacher-forced pass) only after a local move changed the state.
+// VMC_PROP_MADE_MIX: each sweep starts with global Metropolis-Hastings steps
+// made by all chains together (mixsampler.hip); the sweep's single-spin flips
+// then run here, one launch per sweep, with each chain's theta kept in device
+// memory between the launches.
 #include "internal.h"
 
 using namespace dev;
@@ -42,91 +40,17 @@ struct sampler_args {
   int sweep;
   uint64_t* s_out;
   double2* logpsi_out;
-  unsigned long long* acc;
-  // MADE_MIX
-  const double* mW1T;  // [N][H]
-  const double* mW2;   // [N][H]
-  const double* mb1;   // [H]
-  const double* mb2;   // [N]
-  int mH;
-  double p_global;
-  unsigned long long* acc_global;  // [n_chains] accepted global proposals
-  unsigned long long* n_global;    // [n_chains] global proposals made
+  unsigned long long* acc;  // [n_chains] accepted proposals (added to)
+  double2* theta_store;     // [n_chains][N_h] theta kept between launches (NULL: none)
+  int theta_in;             // 1: start from theta_store instead of rebuilding theta from the spins
 };
 
-constexpr int QH_MAX = 16;  // MADE hidden units per lane (H <= 1024)
-
-__device__ __forceinline__ double softplus_d(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
-
-// One autoregressive pass of the MADE over the wave: samples s' into out (when
-// sample == true, using Philox purpose-1 counters of (c, t)) or evaluates the
-// given configuration in out (teacher forcing).  Returns log q (uniform).
-// Hidden units k = lane + 64 q, q < QH.  The rows of W2 (logits) and W1^T
-// (hidden update) that site d needs do not depend on the decisions, so they
-// are loaded one site ahead; the arithmetic and its order are those of the
-// plain loop.
-template <int QH>
-__device__ double made_pass(const sampler_args& a, uint64_t* out, bool sample, uint32_t c, uint64_t t, int lane) {
-  const int N = a.N, H = a.mH;
-  double act[QH], w2c[QH], w2n[QH], w1c[QH];
-#pragma unroll
-  for (int q = 0; q < QH; ++q) {
-    const int k = lane + 64 * q;
-    act[q] = k < H ? a.mb1[k] : 0.0;
-    w2n[q] = k < H ? a.mW2[k] : 0.0;
-  }
-  if (sample) {
-    for (int w = lane; w < a.W; w += 64) out[w] = 0ull;
-    __syncthreads();
-  }
-  double lq = 0.0;
-  uint4 x4 = make_uint4(0, 0, 0, 0);
-  for (int d = 0; d < N; ++d) {
-#pragma unroll
-    for (int q = 0; q < QH; ++q) {
-      const int k = lane + 64 * q;
-      w2c[q] = w2n[q];
-      w1c[q] = k < H ? a.mW1T[(int64_t)d * H + k] : 0.0;
-      w2n[q] = (k < H && d + 1 < N) ? a.mW2[(int64_t)(d + 1) * H + k] : 0.0;
-    }
-    double part = 0.0;
-#pragma unroll
-    for (int q = 0; q < QH; ++q) {
-      const int k = lane + 64 * q;
-      if (k < H) part += w2c[q] * fmax(act[q], 0.0);
-    }
-    double l = wave_sum(part);
-    l = __shfl(l, 0, 64) + a.mb2[d];
-    bool up;
-    if (sample) {
-      if ((d & 3) == 0) x4 = philox(make_uint4(c, (uint32_t)t, (uint32_t)(t >> 32), 1u + 256u * (uint32_t)(d >> 2)), a.key);
-      const uint32_t xr = (d & 3) == 0 ? x4.x : (d & 3) == 1 ? x4.y : (d & 3) == 2 ? x4.z : x4.w;
-      up = (double)xr * 0x1.0p-32 < 1.0 / (1.0 + exp(-l));
-    } else {
-      up = (out[d >> 6] >> (d & 63)) & 1ull;
-    }
-    lq += (up ? l : 0.0) - softplus_d(l);
-    if (up) {
-#pragma unroll
-      for (int q = 0; q < QH; ++q) {
-        const int k = lane + 64 * q;
-        if (k < H) act[q] += w1c[q];
-      }
-      if (sample && lane == 0) out[d >> 6] |= 1ull << (d & 63);
-    }
-  }
-  __syncthreads();
-  return lq;
-}
-
-template <int Q, bool MIX, int QH>
+template <int Q>
 __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   __shared__ uint64_t cb[64];  // chain configuration, W <= 64 words
-  __shared__ uint64_t sp[64];  // global proposal (MADE_MIX)
-  // theta_j of the chain (and theta'_j of a global proposal) in lane-private
-  // LDS slots [q][lane]: registers hold only t_j = tanh theta_j
+  // theta_j of the chain in lane-private LDS slots [q][lane]: registers hold
+  // only t_j = tanh theta_j
   __shared__ double2 ths[Q * 64];
-  __shared__ double2 thns[MIX ? Q * 64 : 1];
   const int c = blockIdx.x;
   if (c >= a.n_chains) return;
   const int lane = threadIdx.x;
@@ -161,32 +85,36 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   }
   __syncthreads();
 
-  // theta_j = b_j + sum_i W_ji sigma_i for the lane's hidden units
+  // theta_j = b_j + sum_i W_ji sigma_i for the lane's hidden units (or the
+  // value kept from the previous launch of this call)
   double2 tt[Q];
   for (int q = 0; q < Q; ++q) {
     const int j = lane + 64 * q;
     double2 acc = j < Nh ? a.params[N + j] : make_double2(0.0, 0.0);
-    if (j < Nh)
-      for (int i = 0; i < N; ++i) {
-        const bool up = (cb[i >> 6] >> (i & 63)) & 1ull;
-        const double2 w = a.Wt[(int64_t)i * Nh + j];
-        acc.x += up ? w.x : -w.x;
-        acc.y += up ? w.y : -w.y;
+    if (j < Nh) {
+      if (a.theta_in) {
+        acc = a.theta_store[(int64_t)c * Nh + j];
+      } else {
+        for (int i = 0; i < N; ++i) {
+          const bool up = (cb[i >> 6] >> (i & 63)) & 1ull;
+          const double2 w = a.Wt[(int64_t)i * Nh + j];
+          acc.x += up ? w.x : -w.x;
+          acc.y += up ? w.y : -w.y;
+        }
       }
+    }
     ths[q * 64 + lane] = acc;
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) tt[q] = ctanh(ths[q * 64 + lane]);
 
-  unsigned long long accepted = 0, acc_g = 0, n_g = 0;
-  double lq_cur = 0.0;
-  bool lq_valid = false;
+  unsigned long long accepted = 0;
   const int64_t total = a.therm_steps + a.n_record * a.sweep;
   // The move of step t + 1 is known from its counter before step t resolves:
   // its rows of T (the ratio) and D (the update on acceptance) are loaded one
   // step ahead (local-move kernels with up to 512 hidden units, where the
   // extra registers fit).
-  constexpr bool PF = !MIX && Q <= 8;
+  constexpr bool PF = Q <= 8;
   uint4 xn = philox(make_uint4((uint32_t)c, (uint32_t)a.t0, (uint32_t)(a.t0 >> 32), 0u), a.key);
   double2 Tn[PF ? Q : 1], Dn[PF ? Q : 1];
   double2 aln = make_double2(0.0, 0.0), lcn = aln;  // alpha and LC of that move
@@ -233,56 +161,7 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
         }
       }
     }
-    if (MIX && (double)x.w * 0x1.0p-32 < a.p_global) {
-      // ---- global MADE proposal with exact Metropolis-Hastings acceptance ----
-      ++n_g;
-      if (!lq_valid) {
-        lq_cur = made_pass<QH>(a, cb, false, (uint32_t)c, t, lane);
-        lq_valid = true;
-      }
-      const double lq_new = made_pass<QH>(a, sp, true, (uint32_t)c, t, lane);
-      for (int q = 0; q < Q; ++q) {
-        const int j = lane + 64 * q;
-        double2 acc = j < Nh ? a.params[N + j] : make_double2(0.0, 0.0);
-        if (j < Nh)
-          for (int i = 0; i < N; ++i) {
-            const bool up = (sp[i >> 6] >> (i & 63)) & 1ull;
-            const double2 w = a.Wt[(int64_t)i * Nh + j];
-            acc.x += up ? w.x : -w.x;
-            acc.y += up ? w.y : -w.y;
-          }
-        thns[q * 64 + lane] = acc;
-      }
-      double dre = 0.0;  // 2 Re(log psi(s') - log psi(s)), lane partial
-      for (int i = lane; i < N; i += 64) {
-        const double sn = ((sp[i >> 6] >> (i & 63)) & 1ull) ? 1.0 : -1.0;
-        const double so = ((cb[i >> 6] >> (i & 63)) & 1ull) ? 1.0 : -1.0;
-        dre += 2.0 * a.params[i].x * (sn - so);
-      }
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int j = lane + 64 * q;
-        if (j < Nh) dre += 2.0 * (clogcosh(thns[q * 64 + lane]).x - clogcosh(ths[q * 64 + lane]).x);
-      }
-      double dr = wave_sum(dre);
-      dr = __shfl(dr, 0, 64);
-      const double r = dr + lq_cur - lq_new;
-      const bool accg = (r >= 0.0) || (u < exp(r));
-      if (accg) {
-        ++accepted;
-        ++acc_g;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const double2 v = thns[q * 64 + lane];
-          ths[q * 64 + lane] = v;
-          tt[q] = ctanh(v);
-        }
-        __syncthreads();
-        for (int w = lane; w < W; w += 64) cb[w] = sp[w];
-        lq_cur = lq_new;
-        __syncthreads();
-      }
-    } else {
+    {
     int site = m, site2 = -1;
     bool identity = false;
     if (a.proposal == VMC_PROP_EXCHANGE) {
@@ -333,7 +212,6 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
           if (site2 >= 0) cb[site2 >> 6] ^= 1ull << (site2 & 63);
         }
         __syncthreads();
-        lq_valid = false;
       }
     }
     }
@@ -362,23 +240,33 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
     }
   }
   for (int w = lane; w < W; w += 64) a.bits[(int64_t)c * W + w] = cb[w];
-  if (lane == 0) {
-    a.acc[c] = accepted;
-    if (MIX) {
-      a.acc_global[c] = acc_g;
-      a.n_global[c] = n_g;
+  if (a.theta_store)
+    for (int q = 0; q < Q; ++q) {
+      const int j = lane + 64 * q;
+      if (j < Nh) a.theta_store[(int64_t)c * Nh + j] = ths[q * 64 + lane];
     }
-  }
+  if (lane == 0) a.acc[c] += accepted;
 }
 
-template <int Q>
-void launch(const sampler_args& a, hipStream_t st) {
-  if (a.proposal != VMC_PROP_MADE_MIX)
-    k_metropolis<Q, false, 1><<<a.n_chains, 64, 0, st>>>(a);
-  else if (a.mH <= 64 * 8)
-    k_metropolis<Q, true, 8><<<a.n_chains, 64, 0, st>>>(a);
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 0ull;
+}
+
+void launch(const sampler_args& a, int Q, hipStream_t st) {
+  if (Q <= 1)
+    k_metropolis<1><<<a.n_chains, 64, 0, st>>>(a);
+  else if (Q <= 2)
+    k_metropolis<2><<<a.n_chains, 64, 0, st>>>(a);
+  else if (Q <= 4)
+    k_metropolis<4><<<a.n_chains, 64, 0, st>>>(a);
+  else if (Q <= 8)
+    k_metropolis<8><<<a.n_chains, 64, 0, st>>>(a);
+  else if (Q <= 16)
+    k_metropolis<16><<<a.n_chains, 64, 0, st>>>(a);
   else
-    k_metropolis<Q, true, QH_MAX><<<a.n_chains, 64, 0, st>>>(a);
+    throw vmc_error{VMC_ERR_UNSUPPORTED, "sampler supports up to 1024 hidden units"};
+  VMC_HIP(hipGetLastError());
 }
 
 }  // namespace
@@ -390,6 +278,8 @@ void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* 
   const int move_kind = S->opts.proposal == VMC_PROP_EXCHANGE ? 1 : 0;
   rbm_ensure_tables(m, S->ham, move_kind);
   const rbm_move_tables& tb = m->tab[move_kind];
+  const int nc = S->opts.n_chains;
+  hipStream_t st = S->ctx->stream;
   sampler_args a{};
   a.params = m->params;
   a.Wt = m->Wt;
@@ -403,47 +293,53 @@ void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* 
   a.N = m->N;
   a.W = m->W;
   a.Nh = m->Nh;
-  a.n_chains = S->opts.n_chains;
+  a.n_chains = nc;
   a.bits = S->bits;
   a.key = make_uint2((uint32_t)S->opts.seed, (uint32_t)(S->opts.seed >> 32));
+  a.acc = S->acc;
+  a.sweep = S->opts.sweep_steps;
+  const int Q = (m->Nh + 63) / 64;
+  k_zero_u64<<<grid_for(3 * (int64_t)nc, 256), 256, 0, st>>>(S->acc, 3 * (int64_t)nc);
+  if (S->opts.proposal != VMC_PROP_MADE_MIX) {
+    a.t0 = S->t;
+    a.init = !S->bits_valid;
+    a.therm_steps = S->thermalized ? 0 : (int64_t)S->opts.therm_sweeps * S->opts.sweep_steps;
+    a.n_record = n_per_chain;
+    a.s_out = s_out;
+    a.logpsi_out = logpsi_out;
+    launch(a, Q, st);
+    S->t += (uint64_t)(a.therm_steps + a.n_record * a.sweep);
+    S->thermalized = 1;
+    S->bits_valid = 1;
+    return;
+  }
+  // MADE_MIX: per sweep, global_steps global steps of all chains, then one
+  // launch of the sweep's flips; theta is rebuilt once per call and kept in
+  // S->mix_theta between the launches
+  mix_ensure(S);
+  a.theta_store = S->mix_theta;
   a.t0 = S->t;
   a.init = !S->bits_valid;
-  a.therm_steps = S->thermalized ? 0 : (int64_t)S->opts.therm_sweeps * S->opts.sweep_steps;
-  a.n_record = n_per_chain;
-  a.sweep = S->opts.sweep_steps;
-  a.s_out = s_out;
-  a.logpsi_out = logpsi_out;
-  a.acc = S->acc;
-  if (S->opts.proposal == VMC_PROP_MADE_MIX) {
-    VMC_REQUIRE(S->made_buf && S->made_H > 0 && S->made_H <= 64 * QH_MAX, "no MADE proposal set");
-    const int64_t nh = (int64_t)m->N * S->made_H;
-    a.mW1T = S->made_buf;
-    a.mW2 = S->made_buf + nh;
-    a.mb1 = S->made_buf + 2 * nh;
-    a.mb2 = S->made_buf + 2 * nh + S->made_H;
-    a.mH = S->made_H;
-    a.p_global = S->opts.p_global;
-    a.acc_global = S->acc + S->opts.n_chains;
-    a.n_global = S->acc + 2 * (int64_t)S->opts.n_chains;
-  }
-  const int Q = (m->Nh + 63) / 64;
-  hipStream_t st = S->ctx->stream;
-  if (Q <= 1)
-    launch<1>(a, st);
-  else if (Q <= 2)
-    launch<2>(a, st);
-  else if (Q <= 4)
-    launch<4>(a, st);
-  else if (Q <= 8)
-    launch<8>(a, st);
-  else if (Q <= 16)
-    launch<16>(a, st);
-  else
-    throw vmc_error{VMC_ERR_UNSUPPORTED, "sampler supports up to 1024 hidden units"};
-  VMC_HIP(hipGetLastError());
-  S->t += (uint64_t)(a.therm_steps + a.n_record * a.sweep);
-  S->thermalized = 1;
+  a.theta_in = 0;
+  a.therm_steps = 0;
+  a.n_record = 0;
+  launch(a, Q, st);  // initial states (first call) and theta, no proposals
   S->bits_valid = 1;
+  a.init = 0;
+  a.theta_in = 1;
+  const int64_t n_therm = S->thermalized ? 0 : S->opts.therm_sweeps;
+  for (int64_t sw = 0; sw < n_therm + n_per_chain; ++sw) {
+    for (int gs = 0; gs < S->opts.global_steps; ++gs) mix_global_step(S, S->g++);
+    const bool rec = sw >= n_therm;
+    a.t0 = S->t;
+    a.therm_steps = rec ? 0 : a.sweep;
+    a.n_record = rec ? 1 : 0;
+    a.s_out = rec ? s_out + (sw - n_therm) * (int64_t)nc * m->W : nullptr;
+    a.logpsi_out = (rec && logpsi_out) ? logpsi_out + (sw - n_therm) * (int64_t)nc : nullptr;
+    launch(a, Q, st);
+    S->t += (uint64_t)a.sweep;
+  }
+  S->thermalized = 1;
 }
 
 namespace {
@@ -460,19 +356,40 @@ __global__ void k_copy_made(const double* __restrict__ W1mT, const double* __res
 }
 }  // namespace
 
+// work buffers of the global steps (allocated on first use)
+void mix_ensure(vmc_sampler* S) {
+  const int64_t nc = S->opts.n_chains;
+  if (S->mix_prop) return;
+  VMC_HIP(hipMalloc(&S->mix_prop, sizeof(uint64_t) * nc * S->W));
+  VMC_HIP(hipMalloc(&S->mix_lq, sizeof(double) * 2 * nc));
+  VMC_HIP(hipMalloc(&S->mix_theta, sizeof(double2) * nc * S->model->Nh));
+  VMC_HIP(hipMalloc(&S->mix_theta_prop, sizeof(double2) * nc * S->model->Nh));
+}
+
 extern "C" int vmc_sampler_set_proposal_made(vmc_sampler* S, const vmc_made* md) {
   if (!S || !md) return VMC_ERR_INVALID_ARG;
   try {
     VMC_REQUIRE(md->ctx == S->ctx, "MADE belongs to another context");
     VMC_REQUIRE(md->N == S->N, "MADE input size differs from the sampler's site count");
-    VMC_REQUIRE(md->H <= 64 * QH_MAX, "MADE hidden size above 1024");
+    VMC_REQUIRE(md->H <= 1024, "MADE hidden size above 1024");
     VMC_HIP(hipSetDevice(S->ctx->device));
+    VMC_REQUIRE(mix_made_fits(md->H, md->W),
+                "MADE proposal too large for the batched global step (its pre-activations for 16 chains must fit "
+                "in one work-group's LDS)");
     const int64_t nh = (int64_t)md->N * md->H;
     const size_t bytes = sizeof(double) * (size_t)(2 * nh + md->H + md->N);
+    std::vector<int> perm, mstart;
+    mix_made_layout(md->N, md->H, perm, mstart);
+    perm.insert(perm.end(), mstart.begin(), mstart.end());
     VMC_HIP(hipStreamSynchronize(S->ctx->stream));
     if (S->made_buf) VMC_HIP(hipFree(S->made_buf));
+    if (S->mix_perm) VMC_HIP(hipFree(S->mix_perm));
     S->made_buf = nullptr;
+    S->mix_perm = nullptr;
+    S->made_H = 0;
     VMC_HIP(hipMalloc(&S->made_buf, bytes));
+    VMC_HIP(hipMalloc(&S->mix_perm, sizeof(int) * perm.size()));
+    VMC_HIP(hipMemcpy(S->mix_perm, perm.data(), sizeof(int) * perm.size(), hipMemcpyHostToDevice));
     S->made_H = md->H;
     const int64_t n = std::max<int64_t>(nh, std::max(md->H, md->N));
     k_copy_made<<<grid_for(n, 256), 256, 0, S->ctx->stream>>>(md->W1mT, md->W2m, md->params, md->N, md->H,

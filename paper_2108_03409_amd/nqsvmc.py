@@ -37,7 +37,7 @@ class VMCError(RuntimeError):
 
 class SamplerOpts(C.Structure):
     _fields_ = [("proposal", C.c_int), ("n_chains", C.c_int), ("sweep_steps", C.c_int),
-                ("therm_sweeps", C.c_int), ("p_global", C.c_double), ("seed", C.c_uint64)]
+                ("therm_sweeps", C.c_int), ("global_steps", C.c_int), ("seed", C.c_uint64)]
 
 
 class SROpts(C.Structure):
@@ -340,9 +340,9 @@ class Hamiltonian:
 
 class Sampler:
     def __init__(self, ctx: Context, model: Model, ham: Hamiltonian, *, proposal=PROP_FLIP, n_chains=16,
-                 sweep_steps=0, therm_sweeps=20, p_global=0.0, seed=0):
+                 sweep_steps=0, therm_sweeps=20, global_steps=0, seed=0):
         self.ctx, self.model, self.ham = ctx, model, ham
-        self.opts = SamplerOpts(proposal, n_chains, sweep_steps, therm_sweeps, p_global, seed)
+        self.opts = SamplerOpts(proposal, n_chains, sweep_steps, therm_sweeps, global_steps, seed)
         h = P()
         _check(load().vmc_sampler_create(ctx.h, model.h, ham.h, C.byref(self.opts), C.byref(h)), ctx.h)
         self.h = h

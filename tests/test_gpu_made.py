@@ -7,7 +7,7 @@ from scipy import stats
 
 import synth_inputs as si
 from oracle import made as omade, rbm as orbm, eloc as oeloc, metropolis as omet
-from gpu_common import dev_bits, host_bits, dev_c128, flush
+from gpu_common import dev_bits, host_bits, dev_c128, flush, assert_logpsi_close
 
 pytestmark = pytest.mark.gpu
 
@@ -82,34 +82,81 @@ def test_sample_replay(ctx, N, H, B, rows):
     assert np.max(np.abs(got - lq_ref)) <= 1e-11 * max(1.0, np.abs(lq_ref).max())
 
 
-def _mixed_setup(ctx, N, Nh, H, std, pg, n_chains, seed=101, therm=2):
+def _mixed_setup(ctx, N, Nh, H, std, G, n_chains, seed=101, therm=2, sweep=0, made_scale=2.0):
     pr = si.rbm_params(N, Nh, std=std, is_complex=True, seed=8)
     model = V.Model.rbm(ctx, N, Nh, True)
     model.set_params(dev_c128(pr))
     Ham = V.Hamiltonian.tfim(ctx, N, 1, True, 1.0, 1.0)
-    made, pm = _made(ctx, N, H, 2.0, seed=9)
-    S = V.Sampler(ctx, model, Ham, proposal=V.PROP_MADE_MIX, n_chains=n_chains, therm_sweeps=therm, p_global=pg,
-                  seed=seed)
+    made, pm = _made(ctx, N, H, made_scale, seed=9)
+    S = V.Sampler(ctx, model, Ham, proposal=V.PROP_MADE_MIX, n_chains=n_chains, therm_sweeps=therm, global_steps=G,
+                  seed=seed, sweep_steps=sweep)
     S.set_proposal_made(made)
     return model, Ham, made, S, pr, pm
 
 
-def test_mixed_chain_replay(ctx):
-    flush("mixed replay")
-    N, Nh, H, nc, per = 10, 10, 16, 8, 6
-    model, Ham, made, S, pr, pm = _mixed_setup(ctx, N, Nh, H, 0.4, 0.3, nc)
+@pytest.mark.parametrize("N,H,G,sweep", [(10, 16, 1, 0), (10, 16, 3, 4), (3, 70, 2, 0), (37, 100, 1, 5)])
+def test_mixed_chain_replay(ctx, N, H, G, sweep):
+    # global MADE steps of all chains, then flips: the chains replay the
+    # oracle's, and so do the global-proposal counts and acceptance; (3, 70) has
+    # more in-block units than the staged path holds, (37, 100) spans three
+    # 16-site blocks with a ragged last one
+    flush(f"mixed replay N={N} H={H} G={G} sweep={sweep}")
+    Nh, nc, per = N, 19, 5
+    model, Ham, made, S, pr, pm = _mixed_setup(ctx, N, Nh, H, 0.15, G, nc, sweep=sweep, made_scale=0.5)
     s, lp, acc = S.sample(nc * per)
     a, ga, ng = S.stats()
     s = host_bits(s).reshape(per, nc, -1)
     f = lambda b: orbm.log_psi(pr, b, Nh)
     ch = omet.Chains(f, N, "made_mix", seed=101, chain_ids=np.arange(nc), therm_sweeps=2, made=(pm, N, H),
-                     p_global=0.3)
+                     global_steps=G, sweep_steps=sweep or None)
     os_, ol = ch.sample(per)
     for c in range(nc):
         for k in range(per):
             assert np.array_equal(s[k, c], si.pack_bits(os_[k, c])[0]), (k, c)
-    assert ng == ch.n_global and ng > 0
-    assert abs(ga - ch.acc_global / ch.n_global) < 1e-12
+    assert ng == nc * G * (per + 2) and ch.n_global == ng   # the first call includes 2 thermalisation sweeps
+    assert 0 < ch.acc_global < ch.n_global and abs(ga - ch.acc_global / ch.n_global) < 1e-12
+    assert_logpsi_close(lp.cpu().numpy().reshape(per, nc), ol, rtol=1e-10)
+    # a second call continues the same chains (and the state blob carries the global counter)
+    blob = S.get_state()
+    s2, _, _ = S.sample(nc * 2)
+    os2, _ = ch.sample(2)
+    assert np.array_equal(host_bits(s2).reshape(2, nc, -1), si.pack_bits(os2.reshape(-1, N)).reshape(2, nc, -1))
+    S.set_state(blob)
+    s3, _, _ = S.sample(nc * 2)
+    assert torch.equal(s2, s3)
+
+
+def test_mixed_chain_replay_at_learned_proposal_shape(ctx):
+    # the learned-proposal workload's shape: 20 x 20 lattice, RBM alpha = 2, a
+    # MADE 400 -> 512 -> 400, 4096 chains with two global steps per sweep;
+    # four chains replayed by the oracle over two thermalisation and two
+    # recorded sweeps (weak weights on both networks so that global proposals
+    # are accepted often enough to exercise both outcomes)
+    flush("mixed replay 20x20, 4096 chains")
+    L, H, nc, G = 20, 512, 4096, 2
+    N = L * L
+    Nh = 2 * N
+    p = si.rbm_params(N, Nh, std=0.01, is_complex=True, seed=5)
+    model = V.Model.rbm(ctx, N, Nh, True)
+    model.set_params(dev_c128(p))
+    Ham = V.Hamiltonian.tfim(ctx, L, L, True, 1.0, 3.0)
+    pm = si.made_params(N, H, seed=205) * 0.3
+    made = V.MADE(ctx, N, H)
+    made.set_params(torch.from_numpy(pm).to("cuda:0"))
+    S = V.Sampler(ctx, model, Ham, proposal=V.PROP_MADE_MIX, n_chains=nc, therm_sweeps=2, global_steps=G, seed=77)
+    S.set_proposal_made(made)
+    s, _, _ = S.sample(nc * 2)
+    a, ga, ng = S.stats()
+    flush(f"  acceptance {a:.3f}, global {ga:.3f} of {ng}")
+    s = host_bits(s).reshape(2, nc, -1)
+    rows = np.array([0, 17, 2048, 4095])
+    f = lambda b: orbm.log_psi(p, b, Nh)
+    ch = omet.Chains(f, N, "made_mix", seed=77, chain_ids=rows, therm_sweeps=2, made=(pm, N, H), global_steps=G)
+    os_, _ = ch.sample(2)
+    for r, c in enumerate(rows):
+        for k in range(2):
+            assert np.array_equal(s[k, c], si.pack_bits(os_[k, r])[0]), (k, c)
+    assert 0 < ch.acc_global < ch.n_global
 
 
 def test_mixed_chain_histogram(ctx):
@@ -117,8 +164,11 @@ def test_mixed_chain_histogram(ctx):
     N, Nh, H = 10, 10, 16
     # 20 thermalisation sweeps, then every 10th of 1000 sweeps: the chi-square
     # test assumes independent draws, so the kept samples must be well
-    # separated compared with the chain's autocorrelation time
-    model, Ham, made, S, pr, pm = _mixed_setup(ctx, N, Nh, H, 0.5, 0.5, 1024, seed=3, therm=20)
+    # separated compared with the chain's autocorrelation time (the exact
+    # sweep kernel of this state and proposal, one global step and 10 flips,
+    # has its second eigenvalue at 0.37: tau ~ 1.6 sweeps; global acceptance
+    # 0.37 and flip acceptance 0.63 at stationarity)
+    model, Ham, made, S, pr, pm = _mixed_setup(ctx, N, Nh, H, 0.1, 1, 1024, seed=3, therm=20, made_scale=0.5)
     s, _, _ = S.sample(1024 * 1000)
     a, ga, ng = S.stats()
     flush(f"  acceptance {a:.3f}, global acceptance {ga:.3f} of {ng} global proposals")
@@ -134,7 +184,7 @@ def test_trained_proposal_is_accepted_more(ctx):
     # train q on the chain's own samples: global acceptance must rise
     flush("made training gain")
     N, Nh, H = 10, 10, 32
-    model, Ham, made, S, pr, pm = _mixed_setup(ctx, N, Nh, H, 0.6, 0.5, 512, seed=11)
+    model, Ham, made, S, pr, pm = _mixed_setup(ctx, N, Nh, H, 0.6, 1, 512, seed=11)
     S.sample(512 * 20)
     _, ga0, _ = S.stats()
     local = V.Sampler(ctx, model, Ham, proposal=V.PROP_FLIP, n_chains=1024, therm_sweeps=20, seed=12)
@@ -144,3 +194,36 @@ def test_trained_proposal_is_accepted_more(ctx):
     S.sample(512 * 20)
     _, ga1, _ = S.stats()
     assert ga1 > ga0 + 0.1, (ga0, ga1)
+
+
+def test_trained_proposal_decorrelates_the_order_parameter(ctx):
+    # 8 x 8 bond-RBM at the 2D Ising critical coupling (local flips slow down
+    # there): a MADE trained on thermalised local-chain samples, one global step
+    # per sweep, lowers the integrated autocorrelation time of |M| in sweeps
+    from paper_2108_03409_amd import stats as pstats
+    flush("made: tau_int(|M|) mixed vs local, 8x8 critical")
+    L, H, nc, R = 8, 128, 512, 400
+    N = L * L
+    p = si.bond_rbm_params(L, L, si.W_CRITICAL)
+    Nh = (len(p) - N) // (N + 1)
+    model = V.Model.rbm(ctx, N, Nh, True)
+    model.set_params(dev_c128(p))
+    Ham = V.Hamiltonian.tfim(ctx, L, L, True, 1.0, 3.0)
+    src = V.Sampler(ctx, model, Ham, proposal=V.PROP_FLIP, n_chains=1024, therm_sweeps=200, seed=31)
+    data, _, _ = src.sample(1024 * 16)
+    made = V.MADE(ctx, N, H)
+    made.set_params(torch.from_numpy(si.made_params(N, H, seed=205)).to("cuda:0"))
+    made.train(data, epochs=40, batch=256, lr=2e-3)
+    taus = {}
+    for name, prop in [("local", V.PROP_FLIP), ("mixed", V.PROP_MADE_MIX)]:
+        S = V.Sampler(ctx, model, Ham, proposal=prop, n_chains=nc, therm_sweeps=50, seed=41, global_steps=1)
+        if prop == V.PROP_MADE_MIX:
+            S.set_proposal_made(made)
+        s, _, _ = S.sample(nc * R)
+        pop = np.bitwise_count(host_bits(s)).sum(axis=1).astype(np.float64)
+        mag = (np.abs(2.0 * pop - N) / N).reshape(R, nc)
+        taus[name] = pstats.ess(mag)[1]
+        if prop == V.PROP_MADE_MIX:
+            flush(f"  global acceptance {S.stats()[1]:.3f}")
+    flush(f"  tau_int(|M|): local {taus['local']:.2f}, mixed {taus['mixed']:.2f} sweeps")
+    assert taus["mixed"] < 0.7 * taus["local"], taus
