@@ -28,15 +28,17 @@ sys.path.insert(0, ROOT)
 
 import synth_inputs as si  # noqa: E402
 
+# fp32_valu_TF: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz, without
+# packed-FP32 instructions (the build disables them)
 PEAK = {"hbm_GBs": 8000.0, "fp32_mfma_TF": 157.3, "fp64_TF": 78.6, "fp64_valu_TF": 78.6, "bf16_mfma_TF": 2500.0,
-        "fp16_mfma_TF": 2500.0}
+        "fp16_mfma_TF": 2500.0, "fp32_valu_TF": 78.6}
 METRIC = "local energies/s & SR steps/s vs roofline; ESS/s learned vs local proposal"
 
 # HBM bytes per launch of k_herk_mfma_f32 on the default workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB: the factors a
 # plain 2 GiB device copy reads); reported only while herk.hip is the source
 # that was profiled.
-HERK_TRAFFIC = {"source_sha256_16": "afd69f44a0f011a8", "bytes": 158969002976.0}
+HERK_TRAFFIC = {"source_sha256_16": "56b04f15ff98737a", "bytes": 158760895488.0}
 
 
 def herk_traffic():
@@ -64,6 +66,8 @@ def parse():
     ap.add_argument("--made-lr", type=float, default=1e-3, help="MADE mix: Adam learning rate")
     ap.add_argument("--made-hidden", type=int, default=None, help="MADE mix: hidden units (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="SR-step workload only (skip the local-energy and learned-proposal workloads)")
     ap.add_argument("--tau", type=float, default=1e-2)
     ap.add_argument("--prec", choices=["f64", "f32", "bf16"], default="f64",
                     help="network evaluation precision of log psi / local energies")
@@ -105,57 +109,75 @@ def eloc_flops(N, Nh, n_slots):
     return 2.0 * N * Nh + 14.0 * Nh * n_slots
 
 
-def cpu_baseline(cfg, p, N, Nh, n_chains, per_chain):
-    """The FP64 oracle on a bounded sample of the same step (about 10 s of host
-    work), each phase scaled to the full step."""
+def cpu_baseline(cfg, p, N, Nh, n_chains, per_chain, runs=10, warm=3):
+    """The float64 oracle on a bounded sample of the same step, each phase
+    scaled to the full step.  Timed with the BLAS pool limited to one thread
+    and to all the host threads the process may use (threadpoolctl), each the
+    median over `runs` runs after `warm` warm-ups.  Per phase the speed-up of
+    the second over the first shows how many of those threads it really used
+    (the oracle's Metropolis, local-energy, Cholesky and solve loops are
+    Python loops over small numpy operations: they stay near 1)."""
+    from threadpoolctl import threadpool_limits
     from oracle import rbm as orbm, eloc as oeloc, metropolis as omet, sr as osr
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    all_threads = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
     f = lambda b: orbm.log_psi(p, b, Nh)
+    K = len(p)
     ns_full = n_chains * per_chain
-    t = {}
-    # sampling: 128 chains x one sweep, scaled to n_chains x per_chain sweeps
-    ch = omet.Chains(f, N, "flip", seed=103, chain_ids=np.arange(128), therm_sweeps=0)
-    t0 = time.perf_counter()
-    ch.sample(1)
-    t["sample"] = (time.perf_counter() - t0) * ns_full / 128
-    bits = si.random_bits(1024, N, seed=7)
-    t0 = time.perf_counter()
-    orbm.log_psi(p, bits, Nh)
-    t["log_psi"] = (time.perf_counter() - t0) * ns_full / 1024
-    t0 = time.perf_counter()
+    n_ch, n_ev, n_el, n_sf, Ks, Kp = 32, 512, 64, 256, 4096, 1024
+    bits = si.random_bits(n_ev, N, seed=7)
     O = orbm.grad_log_psi(p, bits, Nh)
-    t["grad"] = (time.perf_counter() - t0) * ns_full / 1024
-    t0 = time.perf_counter()
-    el = oeloc.local_energy(f, "tfim", bits[:256], N, 1, True, 1.0, 1.0)
-    t["eloc"] = (time.perf_counter() - t0) * ns_full / 256
-    ns = 1024
-    t0 = time.perf_counter()
-    S, F = osr.fisher_and_force(O[:ns], np.resize(el, ns))
-    t["S_F"] = (time.perf_counter() - t0) * ns_full / ns
-    Kp = 2048
+    el = oeloc.local_energy(f, "tfim", bits[:n_el], N, 1, True, 1.0, 1.0)
+    Os = np.ascontiguousarray(O[:n_sf, :Ks])
+    els = np.resize(el, n_sf)
+    S, F = osr.fisher_and_force(Os, els)
     A = osr.shifted(S[:Kp, :Kp], 1e-3)
+    L, _, _ = osr.cholesky(A)
     del S
-    t0 = time.perf_counter()
-    L, fail, _ = osr.cholesky(A)
-    t["cholesky"] = (time.perf_counter() - t0) * (len(p) / Kp) ** 3
-    t0 = time.perf_counter()
-    osr.back_sub_h(L, osr.forward_sub(L, -F[:Kp]))
-    t["solve"] = (time.perf_counter() - t0) * (len(p) / Kp) ** 2
-    total = sum(t.values())
+    work = {   # phase: (callable on the bounded sample, factor to the full step)
+        "sample": (lambda: omet.Chains(f, N, "flip", seed=103, chain_ids=np.arange(n_ch), therm_sweeps=0).sample(1),
+                   ns_full / n_ch),
+        "log_psi": (lambda: orbm.log_psi(p, bits, Nh), ns_full / n_ev),
+        "grad": (lambda: orbm.grad_log_psi(p, bits, Nh), ns_full / n_ev),
+        "eloc": (lambda: oeloc.local_energy(f, "tfim", bits[:n_el], N, 1, True, 1.0, 1.0), ns_full / n_el),
+        "S_F": (lambda: osr.fisher_and_force(Os, els), (ns_full / n_sf) * (K / Ks) ** 2),
+        "cholesky": (lambda: osr.cholesky(A), (K / Kp) ** 3),
+        "solve": (lambda: osr.back_sub_h(L, osr.forward_sub(L, -F[:Kp])), (K / Kp) ** 2),
+    }
+    out = {}
+    for label, nthr in (("one_thread", 1), ("all_threads", all_threads)):
+        wall = {k: [] for k in work}
+        with threadpool_limits(limits=nthr):
+            for r in range(warm + runs):
+                for k, (fn, _) in work.items():
+                    t0 = time.perf_counter()
+                    fn()
+                    if r >= warm:
+                        wall[k].append(time.perf_counter() - t0)
+        phase_s = {k: float(np.median(wall[k])) * work[k][1] for k in work}
+        out[label] = {"value": 1.0 / sum(phase_s.values()), "blas_threads": nthr,
+                      "phase_s": {k: round(v, 3) for k, v in phase_s.items()}}
+    one, best = out["one_thread"], out["all_threads"]
+    best["speedup_over_one_thread"] = {k: round(one["phase_s"][k] / max(best["phase_s"][k], 1e-12), 2) for k in work}
     return {
-        "value": 1.0 / total, "unit": "SR steps/s", "cores": threads, "kind": "oracle",
-        "sample": (f"oracle timed on: 128 chains x 1 sweep (scaled to {n_chains} x {per_chain}), log psi and O_k "
-                   f"on 1024 samples, E_loc on 256 samples, S/F on 1024 samples (each scaled to {ns_full}), "
-                   f"Cholesky and triangular solves on the leading {Kp} x {Kp} block of S~ (scaled by "
-                   f"(K/{Kp})^3 and ^2)"),
-        "phase_s": {k: round(v, 3) for k, v in t.items()},
+        "value": best["value"], "unit": "SR steps/s", "cores": all_threads, "kind": "oracle",
+        "sample": (f"float64 oracle, median of {runs} runs after {warm} warm-ups, on: {n_ch} chains x 1 sweep "
+                   f"(scaled to {n_chains} x {per_chain}), log psi and O_k on {n_ev} samples, E_loc on {n_el} "
+                   f"(each scaled to {ns_full} samples), S/F on {n_sf} samples x the first {Ks} parameters (scaled "
+                   f"by samples x (K/{Ks})^2), Cholesky and triangular solves on the leading {Kp} x {Kp} block of "
+                   f"S~ (scaled by (K/{Kp})^3 and ^2); every phase extrapolated; value = all {all_threads} host "
+                   f"threads in the BLAS pool; one_thread = the same with one"),
+        "one_thread": one, "all_threads": best,
     }
 
 
 def bench_eloc(args, V, torch):
+    print(json.dumps(eloc_result(V, torch, args.workload, args.prec, args.steps, args.warmup)), flush=True)
+
+
+def eloc_result(V, torch, workload, prec, steps, warmup):
     """Local energies/s: one step = sample + local energies of every sample."""
-    cfg = si.WORKLOADS[args.workload]
+    cfg = si.WORKLOADS[workload]
     dev = "cuda:0"
     ctx = V.Context(0)
     Lx, Ly = cfg["Lx"], cfg["Ly"]
@@ -181,55 +203,62 @@ def bench_eloc(args, V, torch):
     sampler = V.Sampler(ctx, model, H, proposal=V.PROP_EXCHANGE if cfg["proposal"] == "exchange" else V.PROP_FLIP,
                         n_chains=cfg["n_chains"], therm_sweeps=20, seed=cfg["sampler_seed"])
     get_samples = lambda: sampler.sample(ns)[0]
-    set_prec(V, model, args.prec)
+    set_prec(V, model, prec)
 
     def step():
         s = get_samples()
         model.local_energy(H, s, out=el)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     ctx.set_timing(True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    eloc_ms = ctx.get_timing("eloc")[0] / args.steps
-    samp_ms = ctx.get_timing("sample")[0] / args.steps
+    eloc_ms = ctx.get_timing("eloc")[0] / steps
+    samp_ms = ctx.get_timing("sample")[0] / steps
     ctx.set_timing(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_step = (t1 - t0) * 1e3 / steps
     out = {
         "metric": METRIC, "value": round(ns / (ms_step * 1e-3), 1), "unit": "local energies/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
-        "data": "synthetic", "config": {"workload": args.workload, "samples": ns},
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec,
+        "data": "synthetic", "config": {"workload": workload, "samples": ns},
         "phases_ms": {"sample": round(samp_ms, 3), "eloc": round(eloc_ms, 3)},
         "eloc_kernel_per_s": round(ns / (eloc_ms * 1e-3), 1),
         "mean_energy": float(el.real.mean().item()),
     }
     achieved = ns * work / (eloc_ms * 1e-3) / 1e12
-    if cfg["net"] == "cnn" and args.prec != "f64":
-        peak, bound = (PEAK["bf16_mfma_TF"], "mfma") if args.prec == "bf16" else (PEAK["fp32_mfma_TF"], "mfma")
-        kern = f"k_cnn_eloc_lp<{args.prec}>"
+    if cfg["net"] == "cnn" and prec != "f64":
+        peak, bound = (PEAK["bf16_mfma_TF"], "mfma") if prec == "bf16" else (PEAK["fp32_mfma_TF"], "mfma")
+        kern = f"k_cnn_eloc_lp<{prec}>"
     elif cfg["net"] == "cnn":
         peak, bound, kern = PEAK["fp64_valu_TF"], "alu", "k_cnn_eloc"
     else:
-        peak, bound = PEAK["fp64_valu_TF"] if args.prec == "f64" else PEAK["fp32_mfma_TF"], "alu"
-        kern = "k_eloc" if args.prec == "f64" else "k_eloc_lowp"
+        # the slot ratios (14 N_h flop per slot) are vector ALU work: float64,
+        # or float32 without packed instructions in the low-precision path
+        peak, bound = PEAK["fp64_valu_TF"] if prec == "f64" else PEAK["fp32_valu_TF"], "alu"
+        kern = "k_eloc" if prec == "f64" else "k_eloc_lowp"
     out["roofline"] = {"kernel": kern, "bound": bound, "achieved": round(achieved, 3), "peak": peak,
                        "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
                        "work": f"{work:.4e} flop per local energy x {ns} per launch"}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_made(args, V, torch):
+    print(json.dumps(made_result(V, torch, args.workload, args.global_steps, args.record_sweeps, args.made_epochs,
+                                 args.made_lr, args.made_hidden)), flush=True)
+
+
+def made_result(V, torch, workload, global_steps, record_sweeps, made_epochs, made_lr, made_hidden=None):
     """Effective samples/s of the energy series: trained MADE mixed with flips
     against flips alone, on the critical bond-RBM state of a 20 x 20 lattice."""
     from paper_2108_03409_amd import stats as pstats
 
-    cfg = si.WORKLOADS[args.workload]
+    cfg = si.WORKLOADS[workload]
     dev = "cuda:0"
     Lx, Ly = cfg["Lx"], cfg["Ly"]
     N = Lx * Ly
@@ -246,15 +275,15 @@ def bench_made(args, V, torch):
     data, _, _ = src.sample(cfg["train_samples"])
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    mh = args.made_hidden or cfg["made_hidden"]
+    mh = made_hidden or cfg["made_hidden"]
     made = V.MADE(ctx, N, mh)
     made.set_params(torch.from_numpy(si.made_params(N, mh, seed=cfg["made_seed"])).to(dev))
     t0 = time.perf_counter()
-    nll = made.train(data, epochs=args.made_epochs, batch=1024, lr=args.made_lr)
+    nll = made.train(data, epochs=made_epochs, batch=1024, lr=made_lr)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    G = args.global_steps
-    R = args.record_sweeps
+    G = global_steps
+    R = record_sweeps
     res = {}
     for name, prop in [("local", V.PROP_FLIP), ("mixed", V.PROP_MADE_MIX)]:
         S = V.Sampler(ctx, model, H, proposal=prop, n_chains=nc, therm_sweeps=100, seed=cfg["sampler_seed"],
@@ -285,15 +314,18 @@ def bench_made(args, V, torch):
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(res["mixed"]["sample_s"] * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (bond-RBM at the 2D Ising critical coupling)",
-        "config": {"workload": args.workload, "n_chains": nc, "record_sweeps": R, "global_steps": G,
-                   "made_hidden": mh, "train_samples": cfg["train_samples"], "made_epochs": args.made_epochs,
-                   "made_lr": args.made_lr},
+        "config": {"workload": workload, "n_chains": nc, "record_sweeps": R, "global_steps": G,
+                   "made_hidden": mh, "train_samples": cfg["train_samples"], "made_epochs": made_epochs,
+                   "made_lr": made_lr},
         "local": res["local"], "mixed": res["mixed"], "ess_per_s_ratio_mixed_over_local": round(ratio, 3),
         "abs_m_ess_per_s_ratio_mixed_over_local": round(res["mixed"]["ess_abs_m_per_s"] /
                                                         res["local"]["ess_abs_m_per_s"], 3),
+        # the same ratio with the proposal's training and its data charged to the mixed run
+        "ess_per_s_ratio_incl_training": round(res["mixed"]["ess"] / (res["mixed"]["sample_s"] + t_train + t_data) /
+                                               res["local"]["ess_per_s"], 3),
         "train_s": round(t_train, 3), "train_data_s": round(t_data, 3), "final_nll": nll,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def ar_eloc_flops(N, H):
@@ -509,25 +541,27 @@ def main():
                     "frac": round(gbs / PEAK["hbm_GBs"], 4), "traffic": None,
                     "work": f"2 x 8 Ns K = {16.0 * ns * K:.4e} bytes per product, {iters} products"}
     else:
-        # dominant kernel: the Gram (S) kernel, one launch per step
+        # dominant kernel: the Gram (S) kernel, one launch per step.  It forms
+        # each complex product from three real ones (Gauss's identity), so the
+        # matrix-core work its algorithm needs is 3/4 of the conventional
+        # complex count 4 Ns K (K + 1); the latter is kept as effective_TF.
         herk_ms = phases["sr.herk"]
-        herk_achieved = herk_flops(ns, K) / (herk_ms * 1e-3) / 1e12
+        conv = herk_flops(ns, K)
+        work = 0.75 * conv if args.gram == 0 else conv
+        herk_achieved = work / (herk_ms * 1e-3) / 1e12
         hpeak = PEAK["fp32_mfma_TF"] if args.gram == 0 else PEAK["fp16_mfma_TF"]
-        hname = "k_herk_mfma_f32" if args.gram == 0 else "k_herk16 (3 float16 products per term)"
-        roofline = {"kernel": f"{hname} (S = Obar^H Obar)", "bound": "mfma", "achieved": round(herk_achieved, 3),
+        hname = ("k_herk_c_dma<12,3> (S = Obar^H Obar, float32 matrix cores, three real products per complex term)"
+                 if args.gram == 0 else "k_herk16 (S = Obar^H Obar, split-float16 matrix cores)")
+        roofline = {"kernel": hname, "bound": "mfma", "achieved": round(herk_achieved, 3),
                     "peak": hpeak, "unit": "TFLOP/s", "frac": round(herk_achieved / hpeak, 4),
                     "traffic": herk_traffic() if args.gram == 0 else None,
-                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, scaled)",
+                    "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy)",
                     "algorithmic_bytes": 8.0 * ns * K + 16.0 * K * K,
-                    "work": f"4*Ns*K*(K+1) = {herk_flops(ns, K):.4e} flop per launch (Ns={ns}, K={K}), the "
-                            "conventional complex count (four real products per term)"}
-        if args.gram == 0:
-            # the kernel forms each complex product from three real ones
-            # (Gauss's identity): the matrix-core work it issues is 3/4 of the
-            # conventional count above
-            issued = 0.75 * herk_achieved
-            roofline["mfma_issued"] = {"flop": 0.75 * herk_flops(ns, K), "TF": round(issued, 3),
-                                       "frac": round(issued / hpeak, 4)}
+                    "work": (f"3*Ns*K*(K+1) = {work:.4e} flop per launch (Ns={ns}, K={K}): three real "
+                             "products per complex term, lower triangle with the diagonal" if args.gram == 0 else
+                             f"4*Ns*K*(K+1) = {work:.4e} flop per launch (Ns={ns}, K={K})"),
+                    "effective_TF": round(conv / (herk_ms * 1e-3) / 1e12, 3),
+                    "effective_work": f"4*Ns*K*(K+1) = {conv:.4e} flop, the conventional complex count"}
     chol_ms = phases["sr.chol"]
     eloc_ms = phases["eloc"]
     eloc_per_s = ns / (eloc_ms * 1e-3)
@@ -538,7 +572,9 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 (S Gram from c64 O_k" + (", split-f16 products)" if args.gram else ")"),
+        "dtype": ("c64 O_k; S on the " + ("float32 matrix cores (3 real products per complex term)"
+                  if args.gram == 0 else "float16 matrix cores (split hi+lo)") +
+                  "; f64 E_loc, Cholesky and triangular solves"),
         "data": "synthetic (seeded RBM parameters N(0,0.01), Metropolis samples)",
         "config": {"workload": (f"SR step ({args.workload}): TFIM {cfg['Lx']}x{cfg['Ly']} PBC J={cfg['J']} "
                                 f"h={cfg['h']}, complex RBM alpha={cfg['alpha']} (K={K}), {ns} samples "
@@ -547,7 +583,8 @@ def main():
                    "solver": args.solver},
         "phases_ms": phases,
         "local_energies_per_s": round(eloc_per_s, 1),
-        "eloc_roofline": {"bound": "alu", "achieved_TF": round(ns * eloc_flops(N, Nh, N) / (eloc_ms * 1e-3) / 1e12, 3),
+        "eloc_roofline": {"kernel": "k_eloc<4>", "bound": "alu",
+                          "achieved_TF": round(ns * eloc_flops(N, Nh, N) / (eloc_ms * 1e-3) / 1e12, 3),
                           "peak": PEAK["fp64_valu_TF"]},
         "chol_TF": round(chol_flops(K) / (chol_ms * 1e-3) / 1e12, 3) if chol_ms > 0 else None,
         "roofline": roofline,
@@ -557,7 +594,34 @@ def main():
     }
     if not args.no_cpu_baseline and args.workload == "tfim1d_L64_rbm_a4_sr":
         out["cpu_baseline"] = cpu_baseline(cfg, p, N, Nh, n_chains, per_chain)
+    if not args.no_extra and args.workload == "tfim1d_L64_rbm_a4_sr":
+        out["other_workloads"] = other_workloads(V, torch)
     print(json.dumps(out), flush=True)
+
+
+def other_workloads(V, torch):
+    """The rest of the metric on its own workloads, short runs: local
+    energies/s of the Heisenberg RBM (bfloat16 and float64) and of the CNN
+    (bfloat16 and float32), and the learned proposal's effective samples/s
+    against local moves (64 recorded sweeps)."""
+    res = {}
+    for name, wl, prec, steps, warm in [("heis2d_10x10_rbm_a4_bf16", "heis2d_10x10_rbm_a4", "bf16", 10, 3),
+                                        ("heis2d_10x10_rbm_a4_f64", "heis2d_10x10_rbm_a4", "f64", 10, 3),
+                                        ("tfim2d_16x16_cnn_bf16", "tfim2d_16x16_cnn", "bf16", 3, 1),
+                                        ("tfim2d_16x16_cnn_f32", "tfim2d_16x16_cnn", "f32", 3, 1)]:
+        r = eloc_result(V, torch, wl, prec, steps, warm)
+        res[name] = {"local_energies_per_s": r["value"], "eloc_kernel_per_s": r["eloc_kernel_per_s"],
+                     "ms_per_step": r["ms_per_step"], "phases_ms": r["phases_ms"], "roofline": r["roofline"]}
+        torch.cuda.empty_cache()
+    m = made_result(V, torch, "tfim2d_20x20_rbm_a2_made", 1, 64, 100, 1e-3)
+    res["tfim2d_20x20_rbm_a2_made"] = {
+        k: m[k] for k in ("ess_per_s_ratio_mixed_over_local", "abs_m_ess_per_s_ratio_mixed_over_local",
+                          "ess_per_s_ratio_incl_training", "train_s", "final_nll")}
+    for side in ("local", "mixed"):
+        res["tfim2d_20x20_rbm_a2_made"][side] = {
+            k: m[side][k] for k in ("ess_per_s", "tau_int_sweeps", "ess_abs_m_per_s", "tau_int_abs_m_sweeps",
+                                    "sample_s", "global_accept", "sigma_energy")}
+    return res
 
 
 if __name__ == "__main__":
