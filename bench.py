@@ -562,6 +562,16 @@ def main():
                              f"4*Ns*K*(K+1) = {work:.4e} flop per launch (Ns={ns}, K={K})"),
                     "effective_TF": round(conv / (herk_ms * 1e-3) / 1e12, 3),
                     "effective_work": f"4*Ns*K*(K+1) = {conv:.4e} flop, the conventional complex count"}
+    # the reverse-mode product of log psi (the autograd backward) at the same batch,
+    # outside the timed steps: out_k = sum_n g_n conj(O_nk), O recomputed, never stored
+    s_last, _, _ = sampler.sample(ns)
+    gvec = torch.randn(ns, dtype=torch.complex128, device=dev)
+    model.log_psi_vjp(s_last, gvec)
+    ctx.set_timing(True)
+    for _ in range(5):
+        model.log_psi_vjp(s_last, gvec)
+    vjp_ms = ctx.get_timing("vjp")[0] / 5
+    ctx.set_timing(False)
     chol_ms = phases["sr.chol"]
     eloc_ms = phases["eloc"]
     eloc_per_s = ns / (eloc_ms * 1e-3)
@@ -587,6 +597,7 @@ def main():
                           "achieved_TF": round(ns * eloc_flops(N, Nh, N) / (eloc_ms * 1e-3) / 1e12, 3),
                           "peak": PEAK["fp64_valu_TF"]},
         "chol_TF": round(chol_flops(K) / (chol_ms * 1e-3) / 1e12, 3) if chol_ms > 0 else None,
+        "log_psi_vjp_ms": round(vjp_ms, 3),
         "roofline": roofline,
         "energy": infos[-1][0]["e_mean"].real, "residual": infos[-1][0]["residual"],
         "cg_iterations": infos[-1][0].get("iterations"),

@@ -662,13 +662,9 @@ extern "C" int vmc_log_psi_vjp(vmc_model* m, const uint64_t* s, int64_t B, const
     VMC_REQUIRE(out, "NULL out");
     if (m->kind == MODEL_AR || m->kind == MODEL_TABLE || m->kind == MODEL_SYMELU)
       throw vmc_error{VMC_ERR_UNSUPPORTED, "no vector-Jacobian product for this model kind"};
+    VMC_REQUIRE(B == 0 || (s && g), "NULL buffer");
     set_device(m->ctx);
     phase_scope ps(m->ctx, "vjp");
-    if (B == 0) {
-      VMC_HIP(hipMemsetAsync(out, 0, sizeof(double2) * m->K, m->ctx->stream));
-      return;
-    }
-    VMC_REQUIRE(s && g, "NULL buffer");
     log_psi_vjp_impl(m, s, B, (const double2*)g, (double2*)out);
   });
 }

@@ -115,24 +115,36 @@ __global__ __launch_bounds__(256) void k_cnn_forward(cnn_geom g, const uint64_t*
 }
 
 // O_k rows [W1 (C k k), b1 (C), W2 (C C k k), b2 (C)].  LDS: bufA [C][N] (a1, later
-// d log psi / d z1), bufB [C][N] (tanh z2).
+// d log psi / d z1), bufB [C][N] (tanh z2).  Work-group x takes samples x,
+// x + gridDim.x, ...  With gv == NULL each O_k(s_b) is written to row b of O;
+// otherwise (reverse-mode product) the group accumulates g_b conj(O_k(s_b))
+// over its samples into row x of part, each entry by the one thread that
+// forms it, so no sample's O is stored.
 template <typename OutT>
 __global__ __launch_bounds__(256) void k_cnn_grad(cnn_geom g, const uint64_t* __restrict__ s, int64_t B, int64_t K,
-                                                  OutT* __restrict__ O) {
+                                                  OutT* __restrict__ O, const double2* __restrict__ gv,
+                                                  double2* __restrict__ part) {
   extern __shared__ double2 sm[];
   const int CN = g.C * g.N, kk = g.k * g.k;
   double2* A = sm;
   double2* G2 = sm + CN;
-  const int64_t b = blockIdx.x;
-  if (b >= B) return;
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
   const uint64_t* sb = s + b * g.W;
-  OutT* row = O + b * K;
+  OutT* row = gv ? nullptr : O + b * K;
+  const bool first = b == (int64_t)blockIdx.x;
+  const double2 gb = gv ? gv[b] : make_double2(0.0, 0.0);
   auto put = [&](int64_t k, double2 v) {
-    if constexpr (sizeof(OutT) == sizeof(double2))
+    if (gv) {
+      const double2 t = cmul(gb, cconj(v));
+      double2* q = part + (int64_t)blockIdx.x * K + k;
+      *q = first ? t : cadd(*q, t);
+    } else if constexpr (sizeof(OutT) == sizeof(double2)) {
       row[k] = v;
-    else
+    } else {
       row[k] = make_float2((float)v.x, (float)v.y);
+    }
   };
+  __syncthreads();  // the previous sample's last LDS reads are done
   const int off_b1 = g.C * kk, off_W2 = off_b1 + g.C, off_b2 = off_W2 + g.C * g.C * kk;
   for (int e = threadIdx.x; e < CN; e += 256) A[e] = clogcosh_pv(z1_at(g, sb, e / g.N, e % g.N));
   __syncthreads();
@@ -176,6 +188,7 @@ __global__ __launch_bounds__(256) void k_cnn_grad(cnn_geom g, const uint64_t* __
     double2 acc = make_double2(0.0, 0.0);
     for (int p = 0; p < g.N; ++p) acc = cadd(acc, A[c * g.N + p]);
     put(off_b1 + c, acc);
+  }
   }
 }
 
@@ -437,11 +450,19 @@ void cnn_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype) {
   const size_t lds = sizeof(double2) * 2 * (size_t)g.C * g.N;
   if (dtype == VMC_DT_C128) {
     allow_lds(k_cnn_grad<double2>, lds);
-    k_cnn_grad<double2><<<(unsigned)B, 256, lds, m->ctx->stream>>>(g, s, B, m->K, (double2*)O);
+    k_cnn_grad<double2><<<(unsigned)B, 256, lds, m->ctx->stream>>>(g, s, B, m->K, (double2*)O, nullptr, nullptr);
   } else {
     allow_lds(k_cnn_grad<float2>, lds);
-    k_cnn_grad<float2><<<(unsigned)B, 256, lds, m->ctx->stream>>>(g, s, B, m->K, (float2*)O);
+    k_cnn_grad<float2><<<(unsigned)B, 256, lds, m->ctx->stream>>>(g, s, B, m->K, (float2*)O, nullptr, nullptr);
   }
+  VMC_HIP(hipGetLastError());
+}
+
+void cnn_vjp_partial(vmc_model* m, const uint64_t* s, int64_t B, const double2* gv, int groups, double2* part) {
+  const cnn_geom g = geom(m);
+  const size_t lds = sizeof(double2) * 2 * (size_t)g.C * g.N;
+  allow_lds(k_cnn_grad<double2>, lds);
+  k_cnn_grad<double2><<<(unsigned)groups, 256, lds, m->ctx->stream>>>(g, s, B, m->K, nullptr, gv, part);
   VMC_HIP(hipGetLastError());
 }
 

@@ -4,6 +4,8 @@
 // 64 x 64 output tile per 256-thread group (2 x 2 waves of 32 x 32, each
 // 2 x 2 blocks of v_mfma_f64_16x16x4), the reduction staged 16 deep through
 // LDS.  Loads are coalesced along whichever stride of each operand is 1.
+// Split-K (nsplit > 1): grid z reduces over its own range of k and writes its
+// own C slice (C + z cz); the caller adds the slices.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -26,7 +28,10 @@ __global__ __launch_bounds__(256) void k_dgemm(dgemm_args g) {
     for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
   const bool a_k_fast = g.sak == 1;
   const bool b_n_fast = g.sbn == 1;
-  for (int64_t k0 = 0; k0 < g.K; k0 += 16) {
+  const int64_t kz0 = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t kz1 = g.kchunk ? min(g.K, kz0 + g.kchunk) : g.K;
+  double* const Cz = g.C + (int64_t)blockIdx.z * g.cz;
+  for (int64_t k0 = kz0; k0 < kz1; k0 += 16) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int q = tid + 256 * j;
@@ -39,7 +44,7 @@ __global__ __launch_bounds__(256) void k_dgemm(dgemm_args g) {
         kk = q >> 6;
       }
       const int64_t m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : 0.0;
+      As[kk][mm] = (m < g.M && k < kz1) ? g.A[m * g.sam + k * g.sak] : 0.0;
       int nn, kb;
       if (b_n_fast) {
         nn = q & 63;
@@ -49,7 +54,7 @@ __global__ __launch_bounds__(256) void k_dgemm(dgemm_args g) {
         kb = q & 15;
       }
       const int64_t n = n0 + nn, kq = k0 + kb;
-      Bs[kb][nn] = (n < g.N && kq < g.K) ? g.B[kq * g.sbk + n * g.sbn] : 0.0;
+      Bs[kb][nn] = (n < g.N && kq < kz1) ? g.B[kq * g.sbk + n * g.sbn] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -77,7 +82,7 @@ __global__ __launch_bounds__(256) void k_dgemm(dgemm_args g) {
         const int64_t m = m0 + wr * 32 + i * 16 + lk + 4 * r;
         const int64_t n = n0 + wc * 32 + j * 16 + li;
         if (m < g.M && n < g.N) {
-          double* c = g.C + m * g.ldc + n;
+          double* c = Cz + m * g.ldc + n;
           *c = (g.beta == 0.0 ? 0.0 : g.beta * *c) + acc[i][j][r];
         }
       }
@@ -85,9 +90,9 @@ __global__ __launch_bounds__(256) void k_dgemm(dgemm_args g) {
 
 }  // namespace
 
-void dgemm(vmc_ctx* ctx, const dgemm_args& g) {
+void dgemm(vmc_ctx* ctx, const dgemm_args& g, int nsplit) {
   if (g.M <= 0 || g.N <= 0) return;
-  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64));
+  dim3 grid((unsigned)((g.N + 63) / 64), (unsigned)((g.M + 63) / 64), (unsigned)std::max(1, nsplit));
   k_dgemm<<<grid, 256, 0, ctx->stream>>>(g);
   VMC_HIP(hipGetLastError());
 }

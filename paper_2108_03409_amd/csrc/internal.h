@@ -395,6 +395,7 @@ void rbm_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
 // cnn.hip
 void cnn_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* logpsi);
 void cnn_grad(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dtype);
+void cnn_vjp_partial(vmc_model* m, const uint64_t* s, int64_t B, const double2* gv, int groups, double2* part);
 void cnn_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
 void cnn_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
 void cnn_sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* logpsi_out);
@@ -444,8 +445,10 @@ struct dgemm_args {
   int64_t ldc;
   int64_t M, N, K;
   double beta;
+  int64_t kchunk = 0;  // split-K: grid z takes rows [z kchunk, (z + 1) kchunk) of the reduction (0: all)
+  int64_t cz = 0;      // ... and writes C + z cz
 };
-void dgemm(vmc_ctx* ctx, const dgemm_args& g);
+void dgemm(vmc_ctx* ctx, const dgemm_args& g, int nsplit = 1);
 // herk.hip
 size_t herk_ws_bytes(int64_t N, int64_t K, int mode);
 void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode, double nu, double eps, double2* S,

@@ -36,7 +36,8 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 constexpr int MC = 16;    // chains per work-group (rows of v_mfma_f64_16x16x4)
 constexpr int MP = 16;    // sites per block (columns of the logits product)
-constexpr int UCAP = 64;  // in-block units whose weights are staged in LDS
+constexpr int UCAP = 32;  // in-block units whose weights are staged in LDS
+constexpr int CH = 16;    // matrix-core steps whose operand loads are issued together
 
 struct made_block_args {
   const double* W1mT;  // [N][H] masked W1, transposed (row d: W1m[k][d] over k)
@@ -55,8 +56,6 @@ struct made_block_args {
   uint32_t lo, hi;
 };
 
-__device__ __forceinline__ double softplus_f64(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
-
 __device__ __forceinline__ int degree(int k, int N) { return k % (N - 1) + 1; }
 
 __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
@@ -68,9 +67,10 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
   double* red_ = un_;
   double* w2s = un_;                                  // [MP][UCAP]
   double* w1s = un_ + MP * UCAP;                      // [MP][UCAP]
-  double* Ls_ = un_ + 2 * MP * UCAP;                  // [MC][MP] logits from the finished units (+ b2)
+  double* Ls_ = un_ + 4 * 256;                        // [MC][MP] logits from the finished units (+ b2)
   uint64_t* bits_ = (uint64_t*)(Ls_ + MC * MP);       // [MC][W]
   int* us_ = (int*)(bits_ + MC * W);                  // [UCAP]
+  int* deg_ = us_ + UCAP;                             // [H] degree m(k)
 
   const bool sample = blockIdx.y == 1;
   const int c0 = blockIdx.x * MC;
@@ -81,6 +81,7 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
     const int c = e / H, k = e % H;
     as_[c * Hs + k] = a.b1[k];
   }
+  for (int k = tid; k < H; k += 256) deg_[k] = degree(k, N);
   for (int e = tid; e < MC * W; e += 256) {
     const int c = e / W, w = e % W;
     bits_[e] = (!sample && c0 + c < a.n_chains) ? a.cur[(int64_t)(c0 + c) * W + w] : 0ull;
@@ -101,14 +102,21 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
     if (d0 > 0) {
       doublex4 acc = {0.0, 0.0, 0.0, 0.0};
       const int kb = wave * Hq, ke = min(H, kb + Hq);
-      for (int k0 = kb; k0 < ke; k0 += 4) {
-        const int k = k0 + lk;
-        double av = 0.0, bv = 0.0;
-        if (k < ke) {
-          if (degree(k, N) <= d0) av = fmax(as_[li * Hs + k], 0.0);  // A[chain li][unit k]
-          if (d0 + li < N) bv = a.W2m[(int64_t)(d0 + li) * H + k];    // B[unit k][site li]
+      const double* w2row = a.W2m + (int64_t)(d0 + li) * H;
+      const bool site_in = d0 + li < N;
+      for (int kc = kb; kc < ke; kc += 4 * CH) {
+        double bv[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {  // operand loads of CH steps in flight together
+          const int k = kc + 4 * q + lk;
+          bv[q] = (site_in && k < ke) ? w2row[k] : 0.0;  // B[unit k][site li]
         }
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          const int k = kc + 4 * q + lk;
+          const double av = (k < ke && deg_[k] <= d0) ? fmax(as_[li * Hs + k], 0.0) : 0.0;  // A[chain li][unit k]
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[q], acc, 0, 0, 0);
+        }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) red_[wave * 256 + (lk + 4 * r) * 16 + li] = acc[r];
@@ -146,12 +154,12 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
       if (staged) {
         for (int j = sub; j < nU; j += 16) {
           const int u = us_[j];
-          if (degree(u, N) <= d) part += w2s[i * UCAP + j] * fmax(as_[cl * Hs + u], 0.0);
+          if (deg_[u] <= d) part += w2s[i * UCAP + j] * fmax(as_[cl * Hs + u], 0.0);
         }
       } else {
         for (int j = sub; j < nU; j += 16) {
           const int u = a.perm[j0 + j];
-          if (degree(u, N) <= d) part += a.W2m[(int64_t)d * H + u] * fmax(as_[cl * Hs + u], 0.0);
+          if (deg_[u] <= d) part += a.W2m[(int64_t)d * H + u] * fmax(as_[cl * Hs + u], 0.0);
         }
       }
       part += __shfl_xor(part, 8, 16);
@@ -160,25 +168,27 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
       part += __shfl_xor(part, 1, 16);
       part = __shfl(part, 0, 16);  // one value per chain: a uniform decision
       const double l = Ls_[cl * MP + i] + part;
+      const double e = exp(-fabs(l));  // p = sigmoid(l) and softplus(l) from one exponential
       bool up;
       if (sample) {
         if ((d & 3) == 0) x4 = philox(make_uint4(cg, a.lo, a.hi, 1u + 256u * (uint32_t)(d >> 2)), a.key);
         const uint32_t xr = (d & 3) == 0 ? x4.x : (d & 3) == 1 ? x4.y : (d & 3) == 2 ? x4.z : x4.w;
-        up = (double)xr * 0x1.0p-32 < 1.0 / (1.0 + exp(-l));
+        const double p = (l >= 0.0 ? 1.0 : e) / (1.0 + e);
+        up = (double)xr * 0x1.0p-32 < p;
       } else {
         up = (bits_[cl * W + (d >> 6)] >> (d & 63)) & 1ull;
       }
-      lq += (up ? l : 0.0) - softplus_f64(l);
+      lq += (up ? l : 0.0) - (fmax(l, 0.0) + log1p(e));
       if (up) {
         if (staged) {
           for (int j = sub; j < nU; j += 16) {
             const int u = us_[j];
-            if (degree(u, N) > d) as_[cl * Hs + u] += w1s[i * UCAP + j];
+            if (deg_[u] > d) as_[cl * Hs + u] += w1s[i * UCAP + j];
           }
         } else {
           for (int j = sub; j < nU; j += 16) {
             const int u = a.perm[j0 + j];
-            if (degree(u, N) > d) as_[cl * Hs + u] += a.W1mT[(int64_t)d * H + u];
+            if (deg_[u] > d) as_[cl * Hs + u] += a.W1mT[(int64_t)d * H + u];
           }
         }
         if (sample && sub == 0) bits_[cl * W + (d >> 6)] |= 1ull << (d & 63);
@@ -188,23 +198,33 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
     // ---- phase C: the block's inputs into the units of higher degree ----
     if (d0 + P < N) {
       const int ntile = (H + 15) / 16;
-      for (int t = wave; t < ntile; t += 4) {
-        const int k0 = t * 16;
-        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+      double av[4];  // A[chain li][site 4 ks + lk]: the same for every tile
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          const int i = ks * 4 + lk;
-          double av = 0.0, bv = 0.0;
-          if (i < P) {
-            av = (double)((bits_[li * W + ((d0 + i) >> 6)] >> ((d0 + i) & 63)) & 1ull);  // A[chain li][site i]
-            if (k0 + li < H) bv = a.W1mT[(int64_t)(d0 + i) * H + k0 + li];              // B[site i][unit]
+      for (int ks = 0; ks < 4; ++ks) {
+        const int i = ks * 4 + lk;
+        av[ks] = i < P ? (double)((bits_[li * W + ((d0 + i) >> 6)] >> ((d0 + i) & 63)) & 1ull) : 0.0;
+      }
+      for (int t0 = wave; t0 < ntile; t0 += 4 * (CH / 4)) {
+        double bv[CH / 4][4];
+#pragma unroll
+        for (int q = 0; q < CH / 4; ++q) {  // B[site][unit] of CH / 4 tiles in flight together
+          const int k = (t0 + 4 * q) * 16 + li;
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) {
+            const int i = ks * 4 + lk;
+            bv[q][ks] = (i < P && k < H) ? a.W1mT[(int64_t)(d0 + i) * H + k] : 0.0;
           }
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
-        const int k = k0 + li;
-        if (k < H && degree(k, N) >= d0 + P) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) as_[(lk + 4 * r) * Hs + k] += acc[r];
+        for (int q = 0; q < CH / 4; ++q) {
+          const int k = (t0 + 4 * q) * 16 + li;
+          doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], bv[q][ks], acc, 0, 0, 0);
+          if (k < H && deg_[k] >= d0 + P) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) as_[(lk + 4 * r) * Hs + k] += acc[r];
+          }
         }
       }
     }
@@ -280,9 +300,11 @@ __global__ __launch_bounds__(64) void k_mix_accept(mix_accept_args a) {
   }
 }
 
+static_assert(2 * MP * UCAP <= 4 * 256, "staged weights share the partial-logit buffer");
+
 size_t made_block_lds(int H, int W) {
-  return sizeof(double) * ((size_t)MC * (H + 1) + std::max(4 * 256, 2 * MP * UCAP) + MC * MP) +
-         sizeof(uint64_t) * MC * (size_t)W + sizeof(int) * UCAP;
+  return sizeof(double) * ((size_t)MC * (H + 1) + 4 * 256 + MC * MP) + sizeof(uint64_t) * MC * (size_t)W +
+         sizeof(int) * (UCAP + (size_t)H);
 }
 
 }  // namespace

@@ -181,6 +181,33 @@ def test_autograd_wrapper_gradcheck_and_oracle(ctx, kind):
     assert np.max(np.abs(theta.grad.cpu().numpy() - ref)) < 1e-10 * max(1, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("kind,N,Nh,B", [("rbm", 20, 40, 70000), ("rbm", 64, 256, 1000), ("cnn", 0, 0, 700)])
+def test_log_psi_vjp_matches_oracle(ctx, kind, N, Nh, B):
+    # out_k = sum_n g_n conj(O_nk) with O never stored: the RBM's product over
+    # sample ranges (70 000 samples: two chunks of the workspace), the CNN's
+    # partial rows over more samples than work-groups
+    flush(f"vjp {kind} N={N} Nh={Nh} B={B}")
+    rng = np.random.default_rng(B)
+    g = rng.normal(size=B) + 1j * rng.normal(size=B)
+    if kind == "rbm":
+        p = si.rbm_params(N, Nh, std=0.1, seed=N)
+        m = V.Model.rbm(ctx, N, Nh, True)
+        bits = si.random_bits(B, N, seed=N + 1)
+        O_ref = orbm.grad_log_psi(p, bits, Nh)
+    else:
+        from oracle import cnn as ocnn
+        Lx, Ly, C, k = 6, 5, 3, 3
+        p = si._normal_params(ocnn.num_params(C, k), 0.2, True, seed=16)
+        m = V.Model.cnn(ctx, Lx, Ly, C, k)
+        bits = si.random_bits(B, Lx * Ly, seed=17)
+        O_ref = ocnn.grad_log_psi(p, bits, Lx, Ly, C, k)
+    m.set_params(dev_c128(p))
+    out = m.log_psi_vjp(dev_bits(si.pack_bits(bits)), dev_c128(g)).cpu().numpy()
+    ref = g @ O_ref.conj()
+    scale = np.abs(g) @ np.abs(O_ref)
+    assert np.all(np.abs(out - ref) <= 1e-13 * (B + 64) * scale + 1e-300)
+
+
 def test_context_released_before_objects():
     # objects keep their context alive: the handle may go first, in any order
     flush("context lifetime")
