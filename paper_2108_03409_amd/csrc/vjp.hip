@@ -157,6 +157,7 @@ void log_psi_vjp_impl(vmc_model* m, const uint64_t* s, int64_t B, const double2*
   } else {
     bytes = sizeof(double2) * (size_t)std::min<int64_t>(B, kCnnGroups) * m->K;
   }
+  bytes = ws_round(bytes);
   ws_reserve(ctx, bytes);
   char* ws = (char*)ws_take(ctx, bytes);
   vjp_run(m, s, B, g, out, ws, bytes);
