@@ -228,6 +228,20 @@ int vmc_grad_log_psi(vmc_model* m, const uint64_t* s, int64_t B, void* O, int dt
  * O is recomputed from the configurations; no activations are stored.        */
 int vmc_log_psi_vjp(vmc_model* m, const uint64_t* s, int64_t B, const double* g, double* out);
 
+/* vmc_log_psi_vjp for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, result and kernels, but the scratch is a fixed 32 MiB
+ * device array of the library (one per GPU, held until the process ends)
+ * instead of the context's workspace, and the call makes no allocation of any
+ * kind and does not synchronise.  Samples are processed in chunks that fit
+ * the array, so any B works; a model whose smallest chunk does not fit (RBM:
+ * 512 (N_h + 1)(N + 1) bytes plus one sample's 32 N_h + 8 N + 24 bytes; CNN:
+ * 16 K bytes) returns VMC_ERR_WORKSPACE.  RBM and CNN models only
+ * (VMC_ERR_UNSUPPORTED otherwise).  All calls on one GPU share the array:
+ * calls that overlap on one GPU (other streams, other contexts, other host
+ * threads) race and give wrong results; serialise them.                     */
+int vmc_log_psi_vjp_noalloc(vmc_model* m, const uint64_t* s, int64_t B, const double* g, double* out);
+
 /* Metropolis sampler of p(s) = |psi(s)|^2/<psi|psi> (Sec. 2.1, Sec. 4.2
  * "Sampler"), all chains in sync.
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed & 0xffffffff,
@@ -451,8 +465,8 @@ int vmc_made_train(vmc_made* md, const uint64_t* s, int64_t B, int epochs, int b
  * global passes are blocked over 16 sites at a time on the float64 matrix
  * cores (same logits up to rounding order; log q of the chain state and of
  * the proposal come from the same code and are consistent to the bit).  The
- * MADE must fit that pass: 16 (H + 1) + 2304 doubles plus 16 W words of LDS
- * (H <= 1024 with W <= 64 does).                                              */
+ * MADE must fit that pass: 16 (H + 1) + 1280 doubles, 16 W words and H + 32
+ * ints of LDS (H <= 1024 with W <= 64 does).                                 */
 int vmc_made_sample(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, uint64_t* s_out, double* logq);
 int vmc_made_destroy(vmc_made* md);
 

@@ -669,6 +669,19 @@ extern "C" int vmc_log_psi_vjp(vmc_model* m, const uint64_t* s, int64_t B, const
   });
 }
 
+extern "C" int vmc_log_psi_vjp_noalloc(vmc_model* m, const uint64_t* s, int64_t B, const double* g, double* out) {
+  return guard(m ? m->ctx : nullptr, [&] {
+    VMC_REQUIRE(m, "NULL model");
+    VMC_REQUIRE(B >= 0, "B < 0");
+    VMC_REQUIRE(out, "NULL out");
+    if (m->kind != MODEL_RBM && m->kind != MODEL_CNN)
+      throw vmc_error{VMC_ERR_UNSUPPORTED, "no vector-Jacobian product for this model kind"};
+    VMC_REQUIRE(B == 0 || (s && g), "NULL buffer");
+    set_device(m->ctx);
+    log_psi_vjp_noalloc_impl(m, s, B, (const double2*)g, (double2*)out);
+  });
+}
+
 // ---------------------------------------------------------------- sampler --
 extern "C" int vmc_sampler_create(vmc_ctx* ctx, vmc_model* m, vmc_ham* H, const vmc_sampler_opts* o,
                                   vmc_sampler** out) {

@@ -424,6 +424,7 @@ void made_refresh(vmc_made* md);
 void made_sample_impl(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, uint64_t* s_out, double* logq);
 // vjp.hip
 void log_psi_vjp_impl(vmc_model* m, const uint64_t* s, int64_t B, const double2* g, double2* out);
+void log_psi_vjp_noalloc_impl(vmc_model* m, const uint64_t* s, int64_t B, const double2* g, double2* out);
 // rbm_lowp.hip
 void rbm_lowp_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* logpsi);
 void rbm_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);

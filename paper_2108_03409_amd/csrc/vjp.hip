@@ -13,11 +13,14 @@
 //       work-group accumulates g_n conj(O_n) over its samples into one row of
 //       partial sums, which a second kernel adds in a fixed order.
 //
-// Scratch: the context's workspace; the work is chunked over samples to fit
-// the scratch it is given.
+// Scratch: the context's workspace (vmc_log_psi_vjp), or, for callers that
+// cannot allocate, a fixed device array owned by this file
+// (vmc_log_psi_vjp_noalloc).  Either way the work is chunked over samples to
+// fit the scratch it is given.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
 
@@ -141,6 +144,35 @@ void vjp_run(vmc_model* m, const uint64_t* s, int64_t B, const double2* g, doubl
     vjp_cnn(m, s, B, g, out, scratch, bytes);
 }
 
+// the smallest scratch that lets a model run (one sample per chunk / one partial row)
+size_t min_scratch(const vmc_model* m) {
+  if (m->kind == MODEL_RBM) return rbm_fixed_bytes(m) + 3 * 256 + rbm_per_sample_bytes(m);
+  return sizeof(double2) * (size_t)m->K;
+}
+
+// ---- fixed scratch for callers that cannot allocate ------------------------
+constexpr size_t kNoAllocBytes = (size_t)32 << 20;  // 32 MiB per device
+__device__ __align__(256) char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// Device address of `scratch` on the current device, looked up once per device
+// with that device current (each device holds its own copy of the array; in
+// host code the array's name is only a stand-in, never a device address).
+char* noalloc_scratch() {
+  int dev = 0;
+  VMC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw vmc_error{VMC_ERR_UNSUPPORTED, "device index above 63"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    VMC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  return (char*)g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 void log_psi_vjp_impl(vmc_model* m, const uint64_t* s, int64_t B, const double2* g, double2* out) {
@@ -161,4 +193,18 @@ void log_psi_vjp_impl(vmc_model* m, const uint64_t* s, int64_t B, const double2*
   ws_reserve(ctx, bytes);
   char* ws = (char*)ws_take(ctx, bytes);
   vjp_run(m, s, B, g, out, ws, bytes);
+}
+
+void log_psi_vjp_noalloc_impl(vmc_model* m, const uint64_t* s, int64_t B, const double2* g, double2* out) {
+  const size_t need = min_scratch(m);
+  if (need > kNoAllocBytes)
+    throw vmc_error{VMC_ERR_WORKSPACE, "model needs " + std::to_string(need) + " bytes of scratch; the fixed " +
+                                           "no-allocation scratch holds " + std::to_string(kNoAllocBytes)};
+  char* sc = noalloc_scratch();
+  if (B == 0) {
+    k_zero2<<<grid_for(m->K, 256), 256, 0, m->ctx->stream>>>(out, m->K);
+    VMC_HIP(hipGetLastError());
+    return;
+  }
+  vjp_run(m, s, B, g, out, sc, kNoAllocBytes);
 }

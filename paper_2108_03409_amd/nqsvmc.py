@@ -91,6 +91,7 @@ _SIGS = {
     "vmc_local_energy": ([P, P, P, I64, P, P], C.c_int),
     "vmc_grad_log_psi": ([P, P, I64, P, C.c_int], C.c_int),
     "vmc_log_psi_vjp": ([P, P, I64, P, P], C.c_int),
+    "vmc_log_psi_vjp_noalloc": ([P, P, I64, P, P], C.c_int),
     "vmc_sampler_create": ([P, P, P, C.POINTER(SamplerOpts), C.POINTER(P)], C.c_int),
     "vmc_sample": ([P, I64, P, P, C.POINTER(I64), C.POINTER(C.c_double)], C.c_int),
     "vmc_sampler_get_state": ([P, P, C.POINTER(C.c_size_t)], C.c_int),
@@ -282,6 +283,13 @@ class Model:
         out = torch.empty(self.K, dtype=torch.complex128, device=s.device)
         g = g.to(torch.complex128).contiguous()
         _check(load().vmc_log_psi_vjp(self.h, _ptr(s), s.shape[0], _ptr(g), _ptr(out)), self.ctx.h)
+        return out
+
+    def log_psi_vjp_noalloc(self, s: torch.Tensor, g: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """log_psi_vjp into a caller-provided out (K complex128) without any
+        allocation inside the library (fixed scratch; calls must not overlap)."""
+        g = g.to(torch.complex128).contiguous()
+        _check(load().vmc_log_psi_vjp_noalloc(self.h, _ptr(s), s.shape[0], _ptr(g), _ptr(out)), self.ctx.h)
         return out
 
     def close(self):
