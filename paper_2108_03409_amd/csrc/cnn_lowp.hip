@@ -47,7 +47,7 @@ struct lp_geom {
   int Cp, Cn, Np;  // C rounded up to 8 / 16; row stride of the [C][N] float tables
   int nrb, ncb;    // row blocks of 16 flips; column blocks of 16 channels
   int sW, sA1, sDA;  // element strides of the operand planes (see the accessors)
-  int o_t1, o_a1i, o_t2, o_wre, o_wim, o_cd, o_sd, o_ure, o_uim, o_pm, o_pe, o_diag;
+  int o_t1, o_a1i, o_t2, o_wre, o_wim, o_cd, o_sd, o_ure, o_uim, o_pm, o_pe, o_diag, o_pyx, o_tap;
   int a1_plane, da_plane, lds;
 };
 
@@ -99,15 +99,16 @@ __device__ __forceinline__ float2 fclog1p(float2 u) {
 // cosh dz + tz sinh dz
 template <int PREC>
 __device__ __forceinline__ float2 window_factor(float2 dz, float2 tz) {
-  float ea, sb, cb;
+  float ea, sb, cb, ia;
   if constexpr (PREC == VMC_BF16) {
     ea = __expf(dz.x);
     __sincosf(dz.y, &sb, &cb);
+    ia = __builtin_amdgcn_rcpf(ea);  // hardware reciprocal (1 ulp), well inside the bfloat16 error
   } else {
     ea = expf(dz.x);
     sincosf(dz.y, &sb, &cb);
+    ia = 1.f / ea;
   }
-  const float ia = 1.f / ea;
   const float ch = 0.5f * (ea + ia), sh = 0.5f * (ea - ia);
   const float2 cz = make_float2(ch * cb, sh * sb), sz = make_float2(sh * cb, ch * sb);
   return fcadd(cz, fcmul(tz, sz));
@@ -156,7 +157,18 @@ __global__ void k_lp_tables(const double2* __restrict__ p, int64_t K, int n1, fl
   out[e] = make_float2((float)r, (float)i);
 }
 
-template <int PREC>
+// site p shifted by (dy, dx), |dy| < Ly, |dx| < Lx, from the (y, x) table of
+// the positions (no division)
+__device__ __forceinline__ int tpos_t(const lp_geom& g, const int* __restrict__ pyx, int p, int dy, int dx) {
+  const int v = pyx[p];
+  int y = (v >> 16) + dy, x = (v & 0xffff) + dx;
+  y += y < 0 ? g.Ly : (y >= g.Ly ? -g.Ly : 0);
+  x += x < 0 ? g.Lx : (x >= g.Lx ? -g.Lx : 0);
+  return y * g.Lx + x;
+}
+
+// CP: the padded channel count Cp when known at compile time (0: g.Cp)
+template <int PREC, int CP>
 __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __restrict__ P32,
                                                     const uint64_t* __restrict__ s, int64_t B, double J, double h,
                                                     const int2* __restrict__ bonds, int n_bonds,
@@ -175,13 +187,15 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
   float2* pm = (float2*)(smem + g.o_pm);
   int* pe = (int*)(smem + g.o_pe);
   double* sdiag = (double*)(smem + g.o_diag);
+  int* pyx = (int*)(smem + g.o_pyx);  // [N] (y << 16) | x
+  int* tap = (int*)(smem + g.o_tap);   // [win^2][kk]: (w << 16) | t of the taps of each window offset
 
   const int64_t b = blockIdx.x;
   if (b >= B) return;
   const uint64_t* sb = s + b * g.W;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int C = g.C, N = g.N, kk = g.kk, Cp = g.Cp;
+  const int C = g.C, N = g.N, kk = g.kk, Cp = CP ? CP : g.Cp;
   const float2* W1f = P32;
   const float2* b1f = P32 + C * kk;
   const float2* W2f = b1f + C;
@@ -189,7 +203,21 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
   const float2* tabs = b2f + C;
   auto sig = [&](int q) { return ((sb[q >> 6] >> (q & 63)) & 1ull) ? 1.f : -1.f; };
 
-  // ---- phase 0: W2 operand planes and the cosh / sinh tables
+  // ---- phase 0: position and tap tables, W2 operand planes, the cosh / sinh tables
+  for (int p = tid; p < N; p += NT) pyx[p] = ((p / g.Lx) << 16) | (p % g.Lx);
+  for (int e = tid; e < g.win * g.win * kk; e += NT) {
+    const int ew = e / kk, ti = e % kk, ey = ew / g.win, ex = ew % g.win;
+    const int ty0 = max(0, ey - g.k + 1), ty1 = min(g.k - 1, ey);
+    const int tx0 = max(0, ex - g.k + 1), tx1 = min(g.k - 1, ex);
+    const int ntx = tx1 - tx0 + 1, nt = (ty1 - ty0 + 1) * ntx;
+    int v = 0;
+    if (ti < nt) {
+      const int ty = ty0 + ti / ntx, tx = tx0 + ti % ntx;
+      v = (((ey - ty) * g.k + (ex - tx)) << 16) | (ty * g.k + tx);
+    }
+    tap[e] = v;
+  }
+  __syncthreads();
   for (int e = tid; e < kk * g.Cn * Cp; e += NT) {
     const int t = e / (g.Cn * Cp), r = e % (g.Cn * Cp), c = r / Cp, ci = r % Cp;
     const float2 v = (c < C && ci < C) ? W2f[(c * C + ci) * kk + t] : make_float2(0.f, 0.f);
@@ -206,7 +234,7 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
     if (c < C) {
       float2 z = b1f[c];
       for (int w = 0; w < kk; ++w) {
-        const float sg = sig(tpos(g, p, w / g.k, w % g.k));
+        const float sg = sig(tpos_t(g, pyx, p, w / g.k, w % g.k));
         const float2 wv = W1f[c * kk + w];
         z.x += sg * wv.x;
         z.y += sg * wv.y;
@@ -246,12 +274,13 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
     floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
     if constexpr (PREC == VMC_BF16) {
       const int ng = Cp / 8;
+      floatx4 ii = {0.f, 0.f, 0.f, 0.f};  // sum Im a Im w, subtracted from re at the end
       for (int k0 = 0; k0 < kk * Cp; k0 += 32) {
         const int gi = k0 / 8 + lk, t = gi / ng, c8 = (gi % ng) * 8;
         bf16x8 ar{}, ai{}, br{}, bi{};
         if (t < kk) {
           if (prow_ok) {
-            const int pos = tpos(g, prow, t / g.k, t % g.k);
+            const int pos = tpos_t(g, pyx, prow, t / g.k, t % g.k);
             ar = *(const bf16x8*)(ure + a1_idx<PREC>(g, pos, c8));
             ai = *(const bf16x8*)(uim + a1_idx<PREC>(g, pos, c8));
           }
@@ -259,16 +288,17 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
           bi = *(const bf16x8*)(wim + w2_idx<PREC>(g, t, cb * 16 + li, c8));
         }
         re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, re, 0, 0, 0);
-        re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(neg8(ai), bi, re, 0, 0, 0);
+        ii = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, bi, ii, 0, 0, 0);
         im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, im, 0, 0, 0);
         im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, im, 0, 0, 0);
       }
+      re -= ii;
     } else {
       for (int k0 = 0; k0 < kk * Cp; k0 += 4) {
         const int kx = k0 + lk, t = kx / Cp, ci = kx % Cp;  // kk * Cp is a multiple of 8
         float ar = 0.f, ai = 0.f;
         if (prow_ok) {
-          const int pos = tpos(g, prow, t / g.k, t % g.k);
+          const int pos = tpos_t(g, pyx, prow, t / g.k, t % g.k);
           ar = ure[a1_idx<PREC>(g, pos, ci)];
           ai = uim[a1_idx<PREC>(g, pos, ci)];
         }
@@ -297,7 +327,7 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
       const int f = rb * 16 + row;
       float2 d = make_float2(0.f, 0.f);
       if (f < N && ci < C) {
-        const int p = tpos(g, f, -(w / g.k), -(w % g.k));
+        const int p = tpos_t(g, pyx, f, -(w / g.k), -(w % g.k));
         const float2 ts = fcmul(t1[ci * g.Np + p], sD[ci * kk + w]);
         const float2 c1 = cD[ci * kk + w];
         const float sg = sig(f);
@@ -320,36 +350,43 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
       P[r] = make_float2(1.f, 0.f);
       E[r] = 0;
     }
+    // (y, x) of this lane's four flips f = rb * 16 + 4 lk + r
+    int fy[4], fx[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = pyx[min(rb * 16 + 4 * lk + r, N - 1)];
+      fy[r] = v >> 16;
+      fx[r] = v & 0xffff;
+    }
     for (int e = wave; e < nwin; e += NW) {
       const int ey = e / g.win, ex = e % g.win;
-      const int ty0 = max(0, ey - g.k + 1), ty1 = min(g.k - 1, ey);
-      const int tx0 = max(0, ex - g.k + 1), tx1 = min(g.k - 1, ex);
-      const int ntx = tx1 - tx0 + 1, nt = (ty1 - ty0 + 1) * ntx;
+      const int nt = (min(g.k - 1, ey) - max(0, ey - g.k + 1) + 1) * (min(g.k - 1, ex) - max(0, ex - g.k + 1) + 1);
+      const int* tp = tap + e * kk;
       for (int cb = 0; cb < g.ncb; ++cb) {
         floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
         if constexpr (PREC == VMC_BF16) {
           const int ng = Cp / 8;
+          floatx4 ii = {0.f, 0.f, 0.f, 0.f};
           for (int k0 = 0; k0 < nt * Cp; k0 += 32) {
             const int gi = k0 / 8 + lk, ti = gi / ng, c8 = (gi % ng) * 8;
             bf16x8 ar{}, ai{}, br{}, bi{};
             if (ti < nt) {
-              const int ty = ty0 + ti / ntx, tx = tx0 + ti % ntx;
-              const int w = (ey - ty) * g.k + (ex - tx), t = ty * g.k + tx;
+              const int v = tp[ti], w = v >> 16, t = v & 0xffff;
               ar = *(const bf16x8*)(ure + da_idx(g, li, w, c8));
               ai = *(const bf16x8*)(uim + da_idx(g, li, w, c8));
               br = *(const bf16x8*)(wre + w2_idx<PREC>(g, t, cb * 16 + li, c8));
               bi = *(const bf16x8*)(wim + w2_idx<PREC>(g, t, cb * 16 + li, c8));
             }
             re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, re, 0, 0, 0);
-            re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(neg8(ai), bi, re, 0, 0, 0);
+            ii = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, bi, ii, 0, 0, 0);
             im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, im, 0, 0, 0);
             im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, im, 0, 0, 0);
           }
+          re -= ii;
         } else {
           for (int k0 = 0; k0 < nt * Cp; k0 += 4) {
             const int kx = k0 + lk, ti = kx / Cp, ci = kx % Cp;  // nt * Cp is a multiple of 8
-            const int ty = ty0 + ti / ntx, tx = tx0 + ti % ntx;
-            const int w = (ey - ty) * g.k + (ex - tx), t = ty * g.k + tx;
+            const int v = tp[ti], w = v >> 16, t = v & 0xffff;
             const float ar = ure[da_idx(g, li, w, ci)], ai = uim[da_idx(g, li, w, ci)];
             const float br = wre[w2_idx<PREC>(g, t, cb * 16 + li, ci)], bi = wim[w2_idx<PREC>(g, t, cb * 16 + li, ci)];
             re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re, 0, 0, 0);
@@ -365,7 +402,10 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
           for (int r = 0; r < 4; ++r) {
             const int f = rb * 16 + 4 * lk + r;
             if (f >= N) continue;
-            const float2 tz = t2[c * g.Np + tpos(g, f, -ey, -ex)];
+            int y = fy[r] - ey, x = fx[r] - ex;  // ey < Ly, ex < Lx: one wrap at most
+            y += y < 0 ? g.Ly : 0;
+            x += x < 0 ? g.Lx : 0;
+            const float2 tz = t2[c * g.Np + y * g.Lx + x];
             P[r] = fcmul(P[r], window_factor<PREC>(make_float2(re[r], im[r]), tz));
             renorm(P[r], E[r]);
           }
@@ -732,6 +772,8 @@ lp_geom make_geom(const vmc_model* m, int prec) {
   g.o_pm = take(8 * NW * 16);
   g.o_pe = take(4 * NW * 16);
   g.o_diag = take(8);
+  g.o_pyx = take(4 * g.N);
+  g.o_tap = take(4 * g.win * g.win * g.kk);
   g.lds = o;
   return g;
 }
@@ -753,15 +795,14 @@ void cnn_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t 
   ws_reserve(ctx, ws_round(tb));
   float2* P32 = (float2*)ws_take(ctx, tb);
   k_lp_tables<<<grid_for(m->K + 3 * n1, 256), 256, 0, st>>>(m->params, m->K, n1, P32);
-  if (m->prec == VMC_BF16) {
-    VMC_HIP(hipFuncSetAttribute((const void*)k_cnn_eloc_lp<VMC_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                g.lds));
-    k_cnn_eloc_lp<VMC_BF16><<<(unsigned)B, NT, g.lds, st>>>(g, P32, s, B, H->J, H->h, H->bonds, H->n_bonds, eloc);
-  } else {
-    VMC_HIP(hipFuncSetAttribute((const void*)k_cnn_eloc_lp<VMC_F32>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                g.lds));
-    k_cnn_eloc_lp<VMC_F32><<<(unsigned)B, NT, g.lds, st>>>(g, P32, s, B, H->J, H->h, H->bonds, H->n_bonds, eloc);
-  }
+  auto launch = [&](auto kern) {
+    VMC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, g.lds));
+    kern<<<(unsigned)B, NT, g.lds, st>>>(g, P32, s, B, H->J, H->h, H->bonds, H->n_bonds, eloc);
+  };
+  if (m->prec == VMC_BF16)
+    g.Cp == 16 ? launch(k_cnn_eloc_lp<VMC_BF16, 16>) : launch(k_cnn_eloc_lp<VMC_BF16, 0>);
+  else
+    g.Cp == 16 ? launch(k_cnn_eloc_lp<VMC_F32, 16>) : launch(k_cnn_eloc_lp<VMC_F32, 0>);
   VMC_HIP(hipGetLastError());
 }
 
