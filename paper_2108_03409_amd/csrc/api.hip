@@ -174,6 +174,11 @@ void ctx_release(vmc_ctx* ctx) {
   delete ctx;
 }
 
+int cu_count(vmc_ctx* ctx) {
+  if (ctx->n_cu <= 0) VMC_HIP(hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  return ctx->n_cu;
+}
+
 hipStream_t aux_stream(vmc_ctx* ctx) {
   if (!ctx->aux) {
     VMC_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));

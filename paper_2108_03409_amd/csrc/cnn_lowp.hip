@@ -36,7 +36,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short ushortx8 __attribute__((ext_vector_type(8)));
 
-constexpr int NT = 512;  // threads per work-group
+constexpr int NT = 1024;  // threads per work-group (four waves per SIMD)
 constexpr int NW = NT / 64;
 constexpr float PI_F = 3.14159265358979324f;
 constexpr float TWO_PI_F = 6.28318530717958648f;
@@ -47,7 +47,11 @@ struct lp_geom {
   int Cp, Cn, Np;  // C rounded up to 8 / 16; row stride of the [C][N] float tables
   int nrb, ncb;    // row blocks of 16 flips; column blocks of 16 channels
   int sW, sA1, sDA;  // element strides of the operand planes (see the accessors)
-  int o_t1, o_a1i, o_t2, o_wre, o_wim, o_cd, o_sd, o_ure, o_uim, o_pm, o_pe, o_diag, o_pyx, o_tap;
+  int Lh, nslot;     // row length of the spin halo (Lx + k - 1); tap slots per window offset
+  int p1_dc, p1_dp;  // phase 1 stride of NT elements as (channels, positions)
+  int p3_drow, p3_dpr;  // dA stride of NT elements as (rows, pairs) of kk * Cp pairs per row
+  int o_t1, o_a1i, o_t2, o_wre, o_wim, o_cd, o_sd, o_ure, o_uim, o_pm, o_pe, o_diag, o_pyx, o_wyx, o_eh, o_opt,
+      o_sp;
   int a1_plane, da_plane, lds;
 };
 
@@ -83,17 +87,64 @@ __device__ __forceinline__ int a1_idx(const lp_geom& g, int pos, int ci) {
 __device__ __forceinline__ int da_idx(const lp_geom& g, int row, int w, int ci) { return row * g.sDA + w * g.Cp + ci; }
 
 // site p shifted by (dy, dx) on the torus; |dy| < Ly, |dx| < Lx
-__device__ __forceinline__ int tpos(const lp_geom& g, int p, int dy, int dx) {
-  int y = p / g.Lx + dy, x = p % g.Lx + dx;
-  if (y >= g.Ly) y -= g.Ly;
-  if (y < 0) y += g.Ly;
-  if (x >= g.Lx) x -= g.Lx;
-  if (x < 0) x += g.Lx;
-  return y * g.Lx + x;
+// Fast float32 elementary functions of the flip loops.  Measured in a float32
+// emulation (exact log2 and reciprocal assumed): about 4 ulp relative each.
+
+// atan r for r in [0, 1] as r + r z Q(z), z = r^2: Q of degree 7, its
+// coefficients fitted to the relative error of the whole polynomial (1.5e-8 in
+// exact arithmetic)
+__device__ __forceinline__ float atan01(float r) {
+  const float z = r * r;
+  float q = 2.849890618e-03f;
+  q = fmaf(q, z, -1.606863365e-02f);
+  q = fmaf(q, z, 4.269152507e-02f);
+  q = fmaf(q, z, -7.504294813e-02f);
+  q = fmaf(q, z, 1.064093411e-01f);
+  q = fmaf(q, z, -1.420364380e-01f);
+  q = fmaf(q, z, 1.999261975e-01f);
+  q = fmaf(q, z, -3.333307207e-01f);
+  return fmaf(q * z, r, r);
 }
 
+// atan2 by reduction to the first octant: r = min / max by the hardware
+// reciprocal, then pi/2 - a, pi - a and the sign of y
+__device__ __forceinline__ float atan2_fast(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  const float r = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
+  float a = atan01(r);
+  if (ay > ax) a = 1.57079632679489662f - a;
+  if (x < 0.f) a = PI_F - a;
+  return copysignf(a, y);
+}
+
+// log1p v = log(w) v / (w - 1) with w = 1 + v rounded: the rounding of w
+// cancels in the quotient (hardware log2 and reciprocal)
+__device__ __forceinline__ float log1p_fast(float v) {
+  const float w = 1.f + v, wm = w - 1.f;
+  if (wm == 0.f) return v;
+  return __builtin_amdgcn_logf(w) * 0.693147180559945309f * (v * __builtin_amdgcn_rcpf(wm));
+}
+
+// log(1 + u), complex u
 __device__ __forceinline__ float2 fclog1p(float2 u) {
-  return make_float2(0.5f * log1pf(2.f * u.x + u.x * u.x + u.y * u.y), atan2f(u.y, 1.f + u.x));
+  return make_float2(0.5f * log1p_fast(fmaf(u.x, u.x + 2.f, u.y * u.y)), atan2_fast(u.y, 1.f + u.x));
+}
+
+// tanh z and the principal log cosh z from one exponential and one sine /
+// cosine pair: with w = e^{-2 z'}, z' = +-z and Re z' >= 0,
+//   tanh z' = (1 - w) / (1 + w),  log cosh z = z' - log 2 + log(1 + w)
+__device__ __forceinline__ void fctanh_logcosh_pv(float2 z, float2& t, float2& a) {
+  const bool neg = z.x < 0.f;
+  if (neg) z = make_float2(-z.x, -z.y);
+  const float e = expf(-2.f * z.x);
+  float sn, cs;
+  sincosf(-2.f * z.y, &sn, &cs);
+  const float er = e * cs, ei = e * sn;
+  const float2 r = fcdiv(make_float2(1.f - er, -ei), make_float2(1.f + er, ei));
+  t = neg ? make_float2(-r.x, -r.y) : r;
+  const float2 l = fclog1p(make_float2(er, ei));
+  a = make_float2(z.x - 0.69314718f + l.x, remainderf(z.y + l.y, TWO_PI_F));
 }
 
 // cosh dz + tz sinh dz
@@ -121,12 +172,6 @@ __device__ __forceinline__ void renorm(float2& m, int& e) {
   m.x = ldexpf(m.x, -x);
   m.y = ldexpf(m.y, -x);
   e += x;
-}
-
-__device__ __forceinline__ bf16x8 neg8(bf16x8 v) {
-  ushortx8 u = __builtin_bit_cast(ushortx8, v);
-  u ^= (unsigned short)0x8000;
-  return __builtin_bit_cast(bf16x8, u);
 }
 
 // float32 tables from the float64 parameters:
@@ -167,7 +212,9 @@ __device__ __forceinline__ int tpos_t(const lp_geom& g, const int* __restrict__ 
   return y * g.Lx + x;
 }
 
-// CP: the padded channel count Cp when known at compile time (0: g.Cp)
+// CP: the padded channel count Cp when known at compile time (0: g.Cp).
+// Persistent: each work-group builds the sample-independent tables once and
+// then takes samples b = blockIdx.x, blockIdx.x + gridDim.x, ...
 template <int PREC, int CP>
 __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __restrict__ P32,
                                                     const uint64_t* __restrict__ s, int64_t B, double J, double h,
@@ -187,37 +234,42 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
   float2* pm = (float2*)(smem + g.o_pm);
   int* pe = (int*)(smem + g.o_pe);
   double* sdiag = (double*)(smem + g.o_diag);
-  int* pyx = (int*)(smem + g.o_pyx);  // [N] (y << 16) | x
-  int* tap = (int*)(smem + g.o_tap);   // [win^2][kk]: (w << 16) | t of the taps of each window offset
+  int* pyx = (int*)(smem + g.o_pyx);       // [N] (y << 16) | x
+  int* wyx = (int*)(smem + g.o_wyx);       // [kk] (wy << 16) | wx of the layer-1 offsets
+  int4* eh = (int4*)(smem + g.o_eh);       // [win^2] (ey, ex, matrix-core steps, taps) of the window offsets
+  unsigned* opt = (unsigned*)(smem + g.o_opt);  // [win^2][nslot] (A element << 16) | B element of each tap slot
+  float* sp = (float*)(smem + g.o_sp);     // [Ly + k - 1][Lh] spins +-1, periodic halo of k - 1 rows / columns
 
-  const int64_t b = blockIdx.x;
-  if (b >= B) return;
-  const uint64_t* sb = s + b * g.W;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int C = g.C, N = g.N, kk = g.kk, Cp = CP ? CP : g.Cp;
+  const int C = g.C, N = g.N, kk = g.kk, k = g.k, Cp = CP ? CP : g.Cp, Lh = g.Lh;
+  const int nwin = g.win * g.win;
+  static_assert(NW == 16, "window offset 0 is shared by sixteen waves");
   const float2* W1f = P32;
   const float2* b1f = P32 + C * kk;
   const float2* W2f = b1f + C;
   const float2* b2f = W2f + C * C * kk;
   const float2* tabs = b2f + C;
-  auto sig = [&](int q) { return ((sb[q >> 6] >> (q & 63)) & 1ull) ? 1.f : -1.f; };
 
-  // ---- phase 0: position and tap tables, W2 operand planes, the cosh / sinh tables
+  // ---- set-up: position and offset tables, tap slots, W2 operand planes, cosh / sinh tables
   for (int p = tid; p < N; p += NT) pyx[p] = ((p / g.Lx) << 16) | (p % g.Lx);
-  for (int e = tid; e < g.win * g.win * kk; e += NT) {
-    const int ew = e / kk, ti = e % kk, ey = ew / g.win, ex = ew % g.win;
-    const int ty0 = max(0, ey - g.k + 1), ty1 = min(g.k - 1, ey);
-    const int tx0 = max(0, ex - g.k + 1), tx1 = min(g.k - 1, ex);
+  for (int w = tid; w < kk; w += NT) wyx[w] = ((w / k) << 16) | (w % k);
+  for (int q = tid; q < nwin * g.nslot; q += NT) {
+    const int e = q / g.nslot, ti = q % g.nslot, ey = e / g.win, ex = e % g.win;
+    const int ty0 = max(0, ey - k + 1), ty1 = min(k - 1, ey);
+    const int tx0 = max(0, ex - k + 1), tx1 = min(k - 1, ex);
     const int ntx = tx1 - tx0 + 1, nt = (ty1 - ty0 + 1) * ntx;
-    int v = 0;
+    // slots past the taps read the zero tap kk of the dA rows
+    unsigned v = (unsigned)(kk * Cp) << 16;
     if (ti < nt) {
       const int ty = ty0 + ti / ntx, tx = tx0 + ti % ntx;
-      v = (((ey - ty) * g.k + (ex - tx)) << 16) | (ty * g.k + tx);
+      const int w = (ey - ty) * k + (ex - tx), t = ty * k + tx;
+      v = ((unsigned)(w * Cp) << 16) | (unsigned)(PREC == VMC_BF16 ? t * g.Cn * g.sW : t * Cp * g.Cn);
     }
-    tap[e] = v;
+    opt[q] = v;
+    if (ti == 0) eh[e] = make_int4(ey, ex, PREC == VMC_BF16 ? (nt * Cp + 31) / 32 : nt * Cp / 4, nt);
   }
-  __syncthreads();
   for (int e = tid; e < kk * g.Cn * Cp; e += NT) {
     const int t = e / (g.Cn * Cp), r = e % (g.Cn * Cp), c = r / Cp, ci = r % Cp;
     const float2 v = (c < C && ci < C) ? W2f[(c * C + ci) * kk + t] : make_float2(0.f, 0.f);
@@ -228,227 +280,328 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
     cD[e] = tabs[e];
     sD[e] = tabs[C * kk + e];
   }
-  // ---- phase 1: layer 1 (tanh, principal log cosh) and the diagonal element
-  for (int e = tid; e < Cp * N; e += NT) {
-    const int c = e / N, p = e % N;
-    if (c < C) {
-      float2 z = b1f[c];
-      for (int w = 0; w < kk; ++w) {
-        const float sg = sig(tpos_t(g, pyx, p, w / g.k, w % g.k));
-        const float2 wv = W1f[c * kk + w];
-        z.x += sg * wv.x;
-        z.y += sg * wv.y;
-      }
-      t1[c * g.Np + p] = fctanh(z);
-      const float2 a = fclogcosh_pv(z);
-      a1i[c * g.Np + p] = a.y;
-      ure[a1_idx<PREC>(g, p, c)] = (T)a.x;
-      uim[a1_idx<PREC>(g, p, c)] = (T)a.y;
-    } else {
-      ure[a1_idx<PREC>(g, p, c)] = (T)0.f;
-      uim[a1_idx<PREC>(g, p, c)] = (T)0.f;
-    }
-  }
-  {
-    int n_al = 0;
-    for (int q = tid; q < n_bonds; q += NT) {
-      const int2 bd = bonds[q];
-      n_al += ((sb[bd.x >> 6] >> (bd.x & 63)) & 1ull) == ((sb[bd.y >> 6] >> (bd.y & 63)) & 1ull);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) n_al += __shfl_xor(n_al, o, 64);
-    if (lane == 0) pe[wave] = n_al;
-  }
   __syncthreads();
-  if (tid == 0) {
-    int t = 0;
-    for (int w = 0; w < NW; ++w) t += pe[w];
-    sdiag[0] = -J * (double)(t - (n_bonds - t));
-  }
 
-  // ---- phase 2: z2 = b2 + sum_{t, ci} W2[c][ci][t] a1[ci][p + t] on the matrix cores, t2 = tanh z2
-  for (int job = wave; job < g.nrb * g.ncb; job += NW) {
-    const int rb = job / g.ncb, cb = job % g.ncb;
-    const int prow = rb * 16 + li;  // A row of this lane
-    const bool prow_ok = prow < N;
-    floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
-    if constexpr (PREC == VMC_BF16) {
-      const int ng = Cp / 8;
-      floatx4 ii = {0.f, 0.f, 0.f, 0.f};  // sum Im a Im w, subtracted from re at the end
-      for (int k0 = 0; k0 < kk * Cp; k0 += 32) {
-        const int gi = k0 / 8 + lk, t = gi / ng, c8 = (gi % ng) * 8;
-        bf16x8 ar{}, ai{}, br{}, bi{};
-        if (t < kk) {
-          if (prow_ok) {
-            const int pos = tpos_t(g, pyx, prow, t / g.k, t % g.k);
-            ar = *(const bf16x8*)(ure + a1_idx<PREC>(g, pos, c8));
-            ai = *(const bf16x8*)(uim + a1_idx<PREC>(g, pos, c8));
-          }
-          br = *(const bf16x8*)(wre + w2_idx<PREC>(g, t, cb * 16 + li, c8));
-          bi = *(const bf16x8*)(wim + w2_idx<PREC>(g, t, cb * 16 + li, c8));
-        }
-        re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, re, 0, 0, 0);
-        ii = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, bi, ii, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, im, 0, 0, 0);
-      }
-      re -= ii;
-    } else {
-      for (int k0 = 0; k0 < kk * Cp; k0 += 4) {
-        const int kx = k0 + lk, t = kx / Cp, ci = kx % Cp;  // kk * Cp is a multiple of 8
-        float ar = 0.f, ai = 0.f;
-        if (prow_ok) {
-          const int pos = tpos_t(g, pyx, prow, t / g.k, t % g.k);
-          ar = ure[a1_idx<PREC>(g, pos, ci)];
-          ai = uim[a1_idx<PREC>(g, pos, ci)];
-        }
-        const float br = wre[w2_idx<PREC>(g, t, cb * 16 + li, ci)], bi = wim[w2_idx<PREC>(g, t, cb * 16 + li, ci)];
-        re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re, 0, 0, 0);
-        re = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, re, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, im, 0, 0, 0);
-        im = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, im, 0, 0, 0);
-      }
+  const int P1 = kk * Cp;  // (layer-1 offset, channel) pairs of one dA row
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const uint64_t* sb = s + b * g.W;
+    // ---- spins with their periodic halo, and the diagonal element
+    for (int q = tid; q < (g.Ly + k - 1) * Lh; q += NT) {
+      int y = q / Lh, x = q % Lh;
+      y -= y >= g.Ly ? g.Ly : 0;
+      x -= x >= g.Lx ? g.Lx : 0;
+      const int p = y * g.Lx + x;
+      sp[q] = ((sb[p >> 6] >> (p & 63)) & 1ull) ? 1.f : -1.f;
     }
-    const int c = cb * 16 + li;
+    {
+      int n_al = 0;
+      for (int q = tid; q < n_bonds; q += NT) {
+        const int2 bd = bonds[q];
+        n_al += ((sb[bd.x >> 6] >> (bd.x & 63)) & 1ull) == ((sb[bd.y >> 6] >> (bd.y & 63)) & 1ull);
+      }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int p = rb * 16 + 4 * lk + r;
-      if (p < N && c < C) t2[c * g.Np + p] = fctanh(make_float2(re[r] + b2f[c].x, im[r] + b2f[c].y));
-    }
-  }
-  __syncthreads();  // the a1 planes are dead from here on; the same LDS holds dA
-
-  // ---- phase 3: flips, 16 at a time
-  double2 esum = make_double2(0.0, 0.0);  // threads 0..15: sum of the ratios of their row
-  const int nwin = g.win * g.win;
-  for (int rb = 0; rb < g.nrb; ++rb) {
-    for (int e = tid; e < 16 * kk * Cp; e += NT) {
-      const int row = e / (kk * Cp), r = e % (kk * Cp), w = r / Cp, ci = r % Cp;
-      const int f = rb * 16 + row;
-      float2 d = make_float2(0.f, 0.f);
-      if (f < N && ci < C) {
-        const int p = tpos_t(g, pyx, f, -(w / g.k), -(w % g.k));
-        const float2 ts = fcmul(t1[ci * g.Np + p], sD[ci * kk + w]);
-        const float2 c1 = cD[ci * kk + w];
-        const float sg = sig(f);
-        d = fclog1p(make_float2(c1.x - sg * ts.x, c1.y - sg * ts.y));
-        // principal branch of the new activation: Im a1' = wrap(Im a1 + Im d)
-        const float sum = a1i[ci * g.Np + p] + d.y;
-        if (sum > PI_F)
-          d.y -= TWO_PI_F;
-        else if (sum <= -PI_F)
-          d.y += TWO_PI_F;
-      }
-      ure[da_idx(g, row, w, ci)] = (T)d.x;
-      uim[da_idx(g, row, w, ci)] = (T)d.y;
+      for (int o = 32; o > 0; o >>= 1) n_al += __shfl_xor(n_al, o, 64);
+      if (lane == 0) pe[wave] = n_al;
     }
     __syncthreads();
-    float2 P[4];
-    int E[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      P[r] = make_float2(1.f, 0.f);
-      E[r] = 0;
+    if (tid == 0) {
+      int t = 0;
+      for (int w = 0; w < NW; ++w) t += pe[w];
+      sdiag[0] = -J * (double)(t - (n_bonds - t));
     }
-    // (y, x) of this lane's four flips f = rb * 16 + 4 lk + r
-    int fy[4], fx[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int v = pyx[min(rb * 16 + 4 * lk + r, N - 1)];
-      fy[r] = v >> 16;
-      fx[r] = v & 0xffff;
-    }
-    for (int e = wave; e < nwin; e += NW) {
-      const int ey = e / g.win, ex = e % g.win;
-      const int nt = (min(g.k - 1, ey) - max(0, ey - g.k + 1) + 1) * (min(g.k - 1, ex) - max(0, ex - g.k + 1) + 1);
-      const int* tp = tap + e * kk;
-      for (int cb = 0; cb < g.ncb; ++cb) {
-        floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
-        if constexpr (PREC == VMC_BF16) {
-          const int ng = Cp / 8;
-          floatx4 ii = {0.f, 0.f, 0.f, 0.f};
-          for (int k0 = 0; k0 < nt * Cp; k0 += 32) {
-            const int gi = k0 / 8 + lk, ti = gi / ng, c8 = (gi % ng) * 8;
-            bf16x8 ar{}, ai{}, br{}, bi{};
-            if (ti < nt) {
-              const int v = tp[ti], w = v >> 16, t = v & 0xffff;
-              ar = *(const bf16x8*)(ure + da_idx(g, li, w, c8));
-              ai = *(const bf16x8*)(uim + da_idx(g, li, w, c8));
-              br = *(const bf16x8*)(wre + w2_idx<PREC>(g, t, cb * 16 + li, c8));
-              bi = *(const bf16x8*)(wim + w2_idx<PREC>(g, t, cb * 16 + li, c8));
-            }
-            re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, re, 0, 0, 0);
-            ii = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, bi, ii, 0, 0, 0);
-            im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, im, 0, 0, 0);
-            im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, im, 0, 0, 0);
-          }
-          re -= ii;
-        } else {
-          for (int k0 = 0; k0 < nt * Cp; k0 += 4) {
-            const int kx = k0 + lk, ti = kx / Cp, ci = kx % Cp;  // nt * Cp is a multiple of 8
-            const int v = tp[ti], w = v >> 16, t = v & 0xffff;
-            const float ar = ure[da_idx(g, li, w, ci)], ai = uim[da_idx(g, li, w, ci)];
-            const float br = wre[w2_idx<PREC>(g, t, cb * 16 + li, ci)], bi = wim[w2_idx<PREC>(g, t, cb * 16 + li, ci)];
-            re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re, 0, 0, 0);
-            re = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, re, 0, 0, 0);
-            im = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, im, 0, 0, 0);
-            im = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, im, 0, 0, 0);
-          }
-        }
-        // the lane holds dZ of flips rb*16 + 4 lk + r, channel cb*16 + li
-        const int c = cb * 16 + li;
+
+    // ---- phase 1: layer 1 (tanh, principal log cosh) of every (channel, position)
+    {
+      int c = tid / N, p = tid % N;
+      for (int e = tid; e < Cp * N; e += NT) {
         if (c < C) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int f = rb * 16 + 4 * lk + r;
-            if (f >= N) continue;
-            int y = fy[r] - ey, x = fx[r] - ex;  // ey < Ly, ex < Lx: one wrap at most
-            y += y < 0 ? g.Ly : 0;
-            x += x < 0 ? g.Lx : 0;
-            const float2 tz = t2[c * g.Np + y * g.Lx + x];
-            P[r] = fcmul(P[r], window_factor<PREC>(make_float2(re[r], im[r]), tz));
-            renorm(P[r], E[r]);
-          }
+          const int v = pyx[p];
+          const float* q = sp + (v >> 16) * Lh + (v & 0xffff);
+          const float2* wc = W1f + c * kk;
+          float2 z = b1f[c];
+          for (int wy = 0; wy < k; ++wy)
+            for (int wx = 0; wx < k; ++wx) {
+              const float sg = q[wy * Lh + wx];
+              const float2 wv = wc[wy * k + wx];
+              z.x = fmaf(sg, wv.x, z.x);
+              z.y = fmaf(sg, wv.y, z.y);
+            }
+          float2 tz, a;
+          fctanh_logcosh_pv(z, tz, a);
+          t1[c * g.Np + p] = tz;
+          a1i[c * g.Np + p] = a.y;
+          ure[a1_idx<PREC>(g, p, c)] = (T)a.x;
+          uim[a1_idx<PREC>(g, p, c)] = (T)a.y;
+        } else {
+          ure[a1_idx<PREC>(g, p, c)] = (T)0.f;
+          uim[a1_idx<PREC>(g, p, c)] = (T)0.f;
+        }
+        p += g.p1_dp;
+        c += g.p1_dc;
+        if (p >= N) {
+          p -= N;
+          ++c;
         }
       }
     }
-    // product over the 16 channel lanes of each row
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) {
-        const float2 q = make_float2(__shfl_xor(P[r].x, o, 64), __shfl_xor(P[r].y, o, 64));
-        const int qe = __shfl_xor(E[r], o, 64);
-        P[r] = fcmul(P[r], q);
-        E[r] += qe;
-        renorm(P[r], E[r]);
+    __syncthreads();
+
+    // ---- phase 2: z2 = b2 + sum_{t, ci} W2[c][ci][t] a1[ci][p + t] on the matrix cores, t2 = tanh z2
+    for (int job = wave; job < g.nrb * g.ncb; job += NW) {
+      const int rb = job / g.ncb, cb = job % g.ncb;
+      const int prow = rb * 16 + li;  // A row of this lane
+      const bool prow_ok = prow < N;
+      floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (PREC == VMC_BF16) {
+        const int ng = Cp / 8;
+        floatx4 ii = {0.f, 0.f, 0.f, 0.f};  // sum Im a Im w, subtracted from re at the end
+        for (int k0 = 0; k0 < kk * Cp; k0 += 32) {
+          const int gi = k0 / 8 + lk, t = gi / ng, c8 = (gi % ng) * 8;
+          bf16x8 ar{}, ai{}, br{}, bi{};
+          if (t < kk) {
+            if (prow_ok) {
+              const int vw = wyx[t];
+              const int pos = tpos_t(g, pyx, prow, vw >> 16, vw & 0xffff);
+              ar = *(const bf16x8*)(ure + a1_idx<PREC>(g, pos, c8));
+              ai = *(const bf16x8*)(uim + a1_idx<PREC>(g, pos, c8));
+            }
+            br = *(const bf16x8*)(wre + w2_idx<PREC>(g, t, cb * 16 + li, c8));
+            bi = *(const bf16x8*)(wim + w2_idx<PREC>(g, t, cb * 16 + li, c8));
+          }
+          re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, re, 0, 0, 0);
+          ii = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, bi, ii, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, im, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, im, 0, 0, 0);
+        }
+        re -= ii;
+      } else {
+        for (int k0 = 0; k0 < kk * Cp; k0 += 4) {
+          const int kx = k0 + lk, t = kx / Cp, ci = kx % Cp;  // kk * Cp is a multiple of 8
+          float ar = 0.f, ai = 0.f;
+          if (prow_ok) {
+            const int vw = wyx[t];
+            const int pos = tpos_t(g, pyx, prow, vw >> 16, vw & 0xffff);
+            ar = ure[a1_idx<PREC>(g, pos, ci)];
+            ai = uim[a1_idx<PREC>(g, pos, ci)];
+          }
+          const float br = wre[w2_idx<PREC>(g, t, cb * 16 + li, ci)], bi = wim[w2_idx<PREC>(g, t, cb * 16 + li, ci)];
+          re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re, 0, 0, 0);
+          re = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, re, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, im, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, im, 0, 0, 0);
+        }
       }
-    if (li == 0)
+      const int c = cb * 16 + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        pm[wave * 16 + 4 * lk + r] = P[r];
-        pe[wave * 16 + 4 * lk + r] = E[r];
+        const int p = rb * 16 + 4 * lk + r;
+        if (p < N && c < C) t2[c * g.Np + p] = fctanh(make_float2(re[r] + b2f[c].x, im[r] + b2f[c].y));
       }
-    __syncthreads();
-    if (tid < 16 && rb * 16 + tid < N) {
-      double2 m = make_double2(1.0, 0.0);
-      int ex = 0;
-      for (int w = 0; w < NW; ++w) {
-        const float2 q = pm[w * 16 + tid];
-        m = cmul(m, make_double2(q.x, q.y));
-        ex += pe[w * 16 + tid];
-      }
-      esum.x += ldexp(m.x, ex);
-      esum.y += ldexp(m.y, ex);
     }
-  }
-  if (wave == 0) {
+    __syncthreads();  // the a1 planes are dead from here on; the same LDS holds dA
+    // bfloat16: the zero tap kk of the dA rows (read by the padded tap slots)
+    if constexpr (PREC == VMC_BF16)
+      for (int q = tid; q < 16 * Cp; q += NT) {
+        ure[da_idx(g, q / Cp, kk, q % Cp)] = (T)0.f;
+        uim[da_idx(g, q / Cp, kk, q % Cp)] = (T)0.f;
+      }
+
+    // ---- phase 3: flips, 16 at a time
+    double2 esum = make_double2(0.0, 0.0);  // threads 0..15: sum of the ratios of their row
+    for (int rb = 0; rb < g.nrb; ++rb) {
+      // dA[row][w][ci] of flips f = rb * 16 + row; thread -> pairs pr = (w, ci), rows row, row + ...
+      auto da_elem = [&](int row, int w, int ci, int vw, float2 c1, float2 s1) {
+        const int f = rb * 16 + row;
+        float2 d = make_float2(0.f, 0.f);
+        if (f < N && ci < C) {
+          // position f - w on the torus: f - (wy Lx + wx), plus N if fy < wy, plus Lx if fx < wx
+          const int vf = pyx[f];
+          const int fy = vf >> 16, fx = vf & 0xffff, wy = vw >> 16, wx = vw & 0xffff;
+          const int p = f - __mul24(wy, g.Lx) - wx + (fy < wy ? N : 0) + (fx < wx ? g.Lx : 0);
+          const float sg = sp[__mul24(fy, Lh) + fx];
+          const float2 ts = fcmul(t1[ci * g.Np + p], s1);
+          d = fclog1p(make_float2(c1.x - sg * ts.x, c1.y - sg * ts.y));
+          // principal branch of the new activation: Im a1' = wrap(Im a1 + Im d)
+          const float sum = a1i[ci * g.Np + p] + d.y;
+          d.y += sum > PI_F ? -TWO_PI_F : (sum <= -PI_F ? TWO_PI_F : 0.f);
+        }
+        ure[da_idx(g, row, w, ci)] = (T)d.x;
+        uim[da_idx(g, row, w, ci)] = (T)d.y;
+      };
+      if (g.p3_dpr == 0) {  // kk * Cp divides the group: the thread's pair is fixed
+        const int pr = tid % P1, w = pr / Cp, ci = pr % Cp;
+        if (tid < g.p3_drow * P1) {
+          const int vw = wyx[w];
+          const float2 c1 = ci < C ? cD[ci * kk + w] : make_float2(0.f, 0.f);
+          const float2 s1 = ci < C ? sD[ci * kk + w] : make_float2(0.f, 0.f);
+          for (int row = tid / P1; row < 16; row += g.p3_drow) da_elem(row, w, ci, vw, c1, s1);
+        }
+      } else {
+        for (int q = tid; q < 16 * P1; q += NT) {
+          const int row = q / P1, pr = q % P1, w = pr / Cp, ci = pr % Cp;
+          const float2 c1 = ci < C ? cD[ci * kk + w] : make_float2(0.f, 0.f);
+          const float2 s1 = ci < C ? sD[ci * kk + w] : make_float2(0.f, 0.f);
+          da_elem(row, w, ci, wyx[w], c1, s1);
+        }
+      }
+      __syncthreads();
+      float2 P[4];
+      int E[4];
 #pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
-      esum.x += __shfl_xor(esum.x, o, 64);
-      esum.y += __shfl_xor(esum.y, o, 64);
+      for (int r = 0; r < 4; ++r) {
+        P[r] = make_float2(1.f, 0.f);
+        E[r] = 0;
+      }
+      // (y, x) of this lane's four flips f = rb * 16 + 4 lk + r
+      int fy[4], fx[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int v = pyx[min(rb * 16 + 4 * lk + r, N - 1)];
+        fy[r] = v >> 16;
+        fx[r] = v & 0xffff;
+      }
+      const T* a_re = ure + li * g.sDA;  // dA row of this lane's A operand (flip rb * 16 + li)
+      const T* a_im = uim + li * g.sDA;
+      // dZ of window offset e for 16 flips x 16 channels per column block, then the window
+      // factors of the lane's rows.  The running products are renormalised after every second
+      // factor (two float32 factors cannot overflow unless one exceeds 2^63 in magnitude).
+      // Window offset 0 (one tap) is shared: every wave forms its dZ and takes the factors
+      // of one row r = wave & 3 in the 16 lanes lk = wave >> 2; offsets 1 .. nwin - 1
+      // ((2k - 1)^2 - 1 = 4 k (k - 1): 48 for k = 4) split over the waves, so that no wave
+      // waits at the barrier for one extra offset.
+      int nf = 0;
+      auto window = [&](int e, bool shared) {
+        const int4 hd = eh[e];
+        const int ey = __builtin_amdgcn_readfirstlane(hd.x), ex = __builtin_amdgcn_readfirstlane(hd.y);
+        const int steps = __builtin_amdgcn_readfirstlane(hd.z), nt = __builtin_amdgcn_readfirstlane(hd.w);
+        const unsigned* op = opt + e * g.nslot;
+        const int eoff = __mul24(ey, g.Lx) + ex;
+        for (int cb = 0; cb < g.ncb; ++cb) {
+          floatx4 re = {0.f, 0.f, 0.f, 0.f}, im = {0.f, 0.f, 0.f, 0.f};
+          if constexpr (PREC == VMC_BF16) {
+            const T* b_re = wre + (cb * 16 + li) * g.sW;
+            const T* b_im = wim + (cb * 16 + li) * g.sW;
+            floatx4 ii;
+            // step st: operands of the lane's tap slot and channel group
+            auto operands = [&](int st, bf16x8& ar, bf16x8& ai, bf16x8& br, bf16x8& bi) {
+              int ti, c8;
+              if constexpr (CP == 16) {
+                ti = 2 * st + (lk >> 1);
+                c8 = (lk & 1) * 8;
+              } else {
+                const int ng = Cp / 8, gi = 4 * st + lk;
+                ti = gi / ng;
+                c8 = (gi % ng) * 8;
+              }
+              const unsigned v = op[ti];
+              const int ao = (int)(v >> 16) + c8, bo = (int)(v & 0xffffu) + c8;
+              ar = *(const bf16x8*)(a_re + ao);
+              ai = *(const bf16x8*)(a_im + ao);
+              br = *(const bf16x8*)(b_re + bo);
+              bi = *(const bf16x8*)(b_im + bo);
+            };
+            {  // first step (every window offset has one) with zero accumulators
+              bf16x8 ar, ai, br, bi;
+              operands(0, ar, ai, br, bi);
+              const floatx4 z = {0.f, 0.f, 0.f, 0.f};
+              re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, z, 0, 0, 0);
+              ii = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, bi, z, 0, 0, 0);
+              im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, z, 0, 0, 0);
+              im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, im, 0, 0, 0);
+            }
+            for (int st = 1; st < steps; ++st) {
+              bf16x8 ar, ai, br, bi;
+              operands(st, ar, ai, br, bi);
+              re = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br, re, 0, 0, 0);
+              ii = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, bi, ii, 0, 0, 0);
+              im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi, im, 0, 0, 0);
+              im = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, br, im, 0, 0, 0);
+            }
+            re -= ii;
+          } else {
+            const T* b_re = wre + cb * 16 + li;
+            const T* b_im = wim + cb * 16 + li;
+            for (int ti = 0; ti < nt; ++ti) {
+              const unsigned v = op[ti];
+              const int ao = (int)(v >> 16), bo = (int)(v & 0xffffu);
+#pragma unroll 4
+              for (int c4 = 0; c4 < Cp; c4 += 4) {
+                const int ci = c4 + lk;
+                const float ar = a_re[ao + ci], ai = a_im[ao + ci];
+                const float br = b_re[bo + ci * g.Cn], bi = b_im[bo + ci * g.Cn];
+                re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re, 0, 0, 0);
+                re = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, re, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, im, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, im, 0, 0, 0);
+              }
+            }
+          }
+          // the lane holds dZ of flips rb*16 + 4 lk + r, channel cb*16 + li; position
+          // f - e on the torus: f - (ey Lx + ex), plus N if fy < ey, plus Lx if fx < ex
+          const int c = cb * 16 + li;
+          const bool mine = c < C && (!shared || lk == (wave >> 2));
+          if (mine) {
+            const int cbase = __mul24(c, g.Np) - eoff;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              if (shared && r != (wave & 3)) continue;
+              const int f = rb * 16 + 4 * lk + r;
+              if (f >= N) continue;
+              const int q = cbase + f + (fy[r] < ey ? N : 0) + (fx[r] < ex ? g.Lx : 0);
+              P[r] = fcmul(P[r], window_factor<PREC>(make_float2(re[r], im[r]), t2[q]));
+            }
+          }
+          if (++nf == 2) {
+            nf = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) renorm(P[r], E[r]);
+          }
+        }
+      };
+      window(0, true);
+      for (int e = 1 + wave; e < nwin; e += NW) window(e, false);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) renorm(P[r], E[r]);
+      // product over the 16 channel lanes of each row: every factor has max(|re|, |im|)
+      // in [0.5, 1], so the 16-fold product stays within [2^-16, 2^8] in magnitude
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+          const float2 q = make_float2(__shfl_xor(P[r].x, o, 64), __shfl_xor(P[r].y, o, 64));
+          E[r] += __shfl_xor(E[r], o, 64);
+          P[r] = fcmul(P[r], q);
+        }
+        renorm(P[r], E[r]);
+      }
+      if (li == 0)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          pm[wave * 16 + 4 * lk + r] = P[r];
+          pe[wave * 16 + 4 * lk + r] = E[r];
+        }
+      __syncthreads();
+      if (tid < 16 && rb * 16 + tid < N) {
+        double2 m = make_double2(1.0, 0.0);
+        int ex = 0;
+        for (int w = 0; w < NW; ++w) {
+          const float2 q = pm[w * 16 + tid];
+          m = cmul(m, make_double2(q.x, q.y));
+          ex += pe[w * 16 + tid];
+        }
+        esum.x += ldexp(m.x, ex);
+        esum.y += ldexp(m.y, ex);
+      }
     }
-    if (lane == 0) eloc[b] = make_double2(sdiag[0] - h * esum.x, -h * esum.y);
+    if (wave == 0) {
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        esum.x += __shfl_xor(esum.x, o, 64);
+        esum.y += __shfl_xor(esum.y, o, 64);
+      }
+      if (lane == 0) eloc[b] = make_double2(sdiag[0] - h * esum.x, -h * esum.y);
+    }
+    __syncthreads();  // pm / pe, the spins and the planes are rewritten by the next sample
   }
 }
 
@@ -745,11 +898,23 @@ lp_geom make_geom(const vmc_model* m, int prec) {
   g.Np = m->N + 1;
   g.nrb = (m->N + 15) / 16;
   g.ncb = g.Cn / 16;
+  g.Lh = m->Lx + m->k - 1;
   const bool bf = prec == VMC_BF16;
+  // tap slots per window offset: bfloat16 steps take 32 / Cp taps at a time and
+  // may run past the last tap (those slots read the zero tap); float32 does not
+  g.nslot = g.kk;
+  if (bf) {
+    const int ng = g.Cp / 8;
+    for (int nt = 1; nt <= g.kk; ++nt) g.nslot = std::max(g.nslot, (4 * ((nt * ng + 3) / 4) - 1) / ng + 1);
+  }
+  g.p1_dc = NT / g.N;
+  g.p1_dp = NT % g.N;
+  g.p3_drow = NT / (g.kk * g.Cp);
+  g.p3_dpr = NT % (g.kk * g.Cp);
   const int es = bf ? 2 : 4;
   g.sW = bf ? g.Cp + 8 : 0;
   g.sA1 = bf ? g.Cp + 8 : g.N + 16;
-  g.sDA = g.kk * g.Cp + (bf ? 8 : 4);
+  g.sDA = bf ? (g.kk + 1) * g.Cp + 8 : g.kk * g.Cp + 4;  // bfloat16: kk taps and the zero tap
   const int wplane = bf ? g.kk * g.Cn * g.sW : g.kk * g.Cp * g.Cn;
   g.a1_plane = bf ? g.N * g.sA1 : g.Cp * g.sA1;
   g.da_plane = 16 * g.sDA;
@@ -773,8 +938,13 @@ lp_geom make_geom(const vmc_model* m, int prec) {
   g.o_pe = take(4 * NW * 16);
   g.o_diag = take(8);
   g.o_pyx = take(4 * g.N);
-  g.o_tap = take(4 * g.win * g.win * g.kk);
+  g.o_wyx = take(4 * g.kk);
+  g.o_eh = take(16 * g.win * g.win);
+  g.o_opt = take(4 * g.win * g.win * g.nslot);
+  g.o_sp = take(4 * (g.Ly + g.k - 1) * g.Lh);
   g.lds = o;
+  // tap slots hold element offsets in 16 bits
+  if (g.kk * g.Cp + g.Cp > 65535 || wplane > 65535) g.lds = 1 << 30;
   return g;
 }
 
@@ -797,7 +967,11 @@ void cnn_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t 
   k_lp_tables<<<grid_for(m->K + 3 * n1, 256), 256, 0, st>>>(m->params, m->K, n1, P32);
   auto launch = [&](auto kern) {
     VMC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, g.lds));
-    kern<<<(unsigned)B, NT, g.lds, st>>>(g, P32, s, B, H->J, H->h, H->bonds, H->n_bonds, eloc);
+    // persistent work-groups: as many as are resident at once
+    int per_cu = 0;
+    VMC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, g.lds));
+    const int64_t grid = std::min<int64_t>(B, (int64_t)std::max(1, per_cu) * cu_count(ctx));
+    if (grid > 0) kern<<<(unsigned)grid, NT, g.lds, st>>>(g, P32, s, B, H->J, H->h, H->bonds, H->n_bonds, eloc);
   };
   if (m->prec == VMC_BF16)
     g.Cp == 16 ? launch(k_cnn_eloc_lp<VMC_BF16, 16>) : launch(k_cnn_eloc_lp<VMC_BF16, 0>);

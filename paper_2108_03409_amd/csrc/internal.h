@@ -76,10 +76,13 @@ struct vmc_ctx {
   // the context's stream inside one call; created on first use
   hipStream_t aux = nullptr;
   hipEvent_t ev_main = nullptr, ev_aux = nullptr;
+  int n_cu = 0;  // compute units of the device (queried on first use)
 };
 
 // The context's auxiliary stream and events (created on first use).
 hipStream_t aux_stream(vmc_ctx* ctx);
+// Compute units of the context's device.
+int cu_count(vmc_ctx* ctx);
 
 template <class F>
 int guard(vmc_ctx* ctx, F&& f) {
