@@ -131,6 +131,22 @@ __device__ __forceinline__ float2 fclog1p(float2 u) {
   return make_float2(0.5f * log1p_fast(fmaf(u.x, u.x + 2.f, u.y * u.y)), atan2_fast(u.y, 1.f + u.x));
 }
 
+// tanh z = (sinh 2x + i sin 2y) / (cosh 2x + cos 2y) with the hardware
+// exponential, reciprocal, sine and cosine (about 2^-21 relative away from the
+// poles): y is reduced modulo pi (tanh has period i pi) and x clamped to
+// [-10, 10], where tanh x is +-1 to float32 precision.  For the float32 chains,
+// whose tanh values feed only acceptance ratios.
+__device__ __forceinline__ float2 fctanh_fast(float2 z) {
+  const float x = fminf(fmaxf(z.x, -10.f), 10.f);
+  const float y = fmaf(-PI_F, rintf(z.y * 0.318309886183790672f), z.y);
+  const float e = __expf(2.f * x), ie = __builtin_amdgcn_rcpf(e);
+  float sn, cs;
+  __sincosf(2.f * y, &sn, &cs);
+  const float sh = 0.5f * (e - ie), ch = 0.5f * (e + ie);
+  const float inv = __builtin_amdgcn_rcpf(ch + cs);
+  return make_float2(sh * inv, sn * inv);
+}
+
 // tanh z and the principal log cosh z from one exponential and one sine /
 // cosine pair: with w = e^{-2 z'}, z' = +-z and Re z' >= 0,
 //   tanh z' = (1 - w) / (1 + w),  log cosh z = z' - log 2 + log(1 + w)
@@ -881,6 +897,473 @@ mh_geom make_mh_geom(const vmc_model* m) {
   return g;
 }
 
+// ---------------------------------------------------------------------------
+// Metropolis chains for the CNN in float32, 16 chains per work-group (the
+// Philox stream of the float64 sampler: chain ch proposes the same sites and
+// draws the same uniforms).  The chains are the rows of the matrix-core
+// products: per step each chain proposes a flip at its own site, the layer-1
+// changes dA of the 16 chains form the A operand (rows), W2 the B operand, and
+// for every window offset e one float32 product gives dZ of 16 chains x 16
+// channels, as in the local-energy kernel.  The per-chain state (z1, tanh z1,
+// Im a1 on the principal branch, z2, tanh z2; position-major, channel fastest)
+// lives in global memory: 16 chains do not fit in LDS.  Accepted moves update
+// z1 and z2 additively with the same float32 dZ and re-evaluate tanh; log psi
+// of a recorded sample is re-summed from z2.  The state is rebuilt from the
+// bits at the start of every call.  Used for C <= 16 and k <= 4.
+struct mb_geom {
+  int Lx, Ly, N, W, C, k, kk, win;
+  int Cp, Cn, sDA;  // channels rounded up to 8 / 16; dA row stride (floats)
+  int o_wre, o_wim, o_are, o_aim, o_cd, o_sd, o_pyx, o_wyx, o_eh, o_opt, o_bits, o_site, o_u, o_sg, o_acc, o_pm,
+      o_pe, o_l1, lds;
+};
+
+constexpr int MB_NT = 512;  // two waves per SIMD: the window offsets' dZ stay in registers until the decision
+constexpr int MB_NW = MB_NT / 64;
+constexpr int MB_CH = 16;    // chains per work-group
+constexpr int MB_MAXE = 6;   // window offsets per wave besides the shared offset 0: (2k - 1)^2 - 1 <= 48
+constexpr int MB_DA = MB_CH * 256 / MB_NT;  // layer-1 changes per thread: k^2 Cp <= 256
+
+__global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2* __restrict__ P32, int n_chains,
+                                                        uint64_t* __restrict__ bits, uint2 key, uint64_t t0, int init,
+                                                        int64_t therm_steps, int64_t n_record, int sweep,
+                                                        uint64_t* __restrict__ s_out, double2* __restrict__ logpsi_out,
+                                                        unsigned long long* __restrict__ acc, float2* __restrict__ z1g,
+                                                        float2* __restrict__ t1g, float* __restrict__ a1ig,
+                                                        float2* __restrict__ z2g, float2* __restrict__ t2g) {
+  extern __shared__ __align__(16) char smem[];
+  float* wre = (float*)(smem + g.o_wre);  // W2 operand planes [t][ci][c] (c fastest, Cn wide)
+  float* wim = (float*)(smem + g.o_wim);
+  float* are = (float*)(smem + g.o_are);  // dA operand planes [chain][w][ci]
+  float* aim = (float*)(smem + g.o_aim);
+  float2* cD = (float2*)(smem + g.o_cd);
+  float2* sD = (float2*)(smem + g.o_sd);
+  int* pyx = (int*)(smem + g.o_pyx);
+  int* wyx = (int*)(smem + g.o_wyx);
+  int4* eh = (int4*)(smem + g.o_eh);
+  unsigned* opt = (unsigned*)(smem + g.o_opt);
+  uint64_t* cb = (uint64_t*)(smem + g.o_bits);  // [MB_CH][W]
+  int* site_s = (int*)(smem + g.o_site);
+  double* u_s = (double*)(smem + g.o_u);
+  float* sg_s = (float*)(smem + g.o_sg);
+  int* acc_s = (int*)(smem + g.o_acc);
+  float2* pm = (float2*)(smem + g.o_pm);  // [MB_NW][16]
+  int* pe = (int*)(smem + g.o_pe);
+  int* l1tab = (int*)(smem + g.o_l1);     // [MB_DA][MB_NT]
+
+  static_assert(MB_NW == 8, "window offset 0 is shared by eight waves");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int C = g.C, N = g.N, kk = g.kk, k = g.k, Cp = g.Cp, Cn = g.Cn, W = g.W;
+  const int64_t CN = (int64_t)C * N;
+  const int nwin = g.win * g.win;
+  const int ch0 = blockIdx.x * MB_CH;
+  const int nch = min(MB_CH, n_chains - ch0);
+  const float2* W1f = P32;
+  const float2* b1f = P32 + C * kk;
+  const float2* W2f = b1f + C;
+  const float2* b2f = W2f + C * C * kk;
+  const float2* tabs = b2f + C;
+
+  // ---- set-up: tables, W2 operand planes, cosh / sinh tables, the bits of the chains
+  for (int p = tid; p < N; p += MB_NT) pyx[p] = ((p / g.Lx) << 16) | (p % g.Lx);
+  for (int w = tid; w < kk; w += MB_NT) wyx[w] = ((w / k) << 16) | (w % k);
+  for (int q = tid; q < nwin * kk; q += MB_NT) {
+    const int e = q / kk, ti = q % kk, ey = e / g.win, ex = e % g.win;
+    const int ty0 = max(0, ey - k + 1), ty1 = min(k - 1, ey);
+    const int tx0 = max(0, ex - k + 1), tx1 = min(k - 1, ex);
+    const int ntx = tx1 - tx0 + 1, nt = (ty1 - ty0 + 1) * ntx;
+    unsigned v = 0;
+    if (ti < nt) {
+      const int ty = ty0 + ti / ntx, tx = tx0 + ti % ntx;
+      v = ((unsigned)(((ey - ty) * k + (ex - tx)) * Cp) << 16) | (unsigned)((ty * k + tx) * Cp * Cn);
+    }
+    opt[q] = v;
+    if (ti == 0) eh[e] = make_int4(ey, ex, __mul24(ey, g.Lx) + ex, nt);
+  }
+  for (int e = tid; e < kk * Cp * Cn; e += MB_NT) {
+    const int t = e / (Cp * Cn), r = e % (Cp * Cn), ci = r / Cn, c = r % Cn;
+    const float2 v = (c < C && ci < C) ? W2f[(c * C + ci) * kk + t] : make_float2(0.f, 0.f);
+    wre[e] = v.x;
+    wim[e] = v.y;
+  }
+  for (int e = tid; e < C * kk; e += MB_NT) {
+    cD[e] = tabs[e];
+    sD[e] = tabs[C * kk + e];
+  }
+  // (chain row, w, ci) of the layer-1 change q = tid + j MB_NT; row 255: none
+  for (int q = tid; q < MB_DA * MB_NT; q += MB_NT) {
+    const int P1 = kk * Cp, r = q / P1, pr = q % P1;
+    l1tab[q] = q < MB_CH * P1 ? (r << 16) | ((pr / Cp) << 8) | (pr % Cp) : (255 << 16);
+  }
+  for (int q = tid; q < MB_CH * W; q += MB_NT) {
+    const int r = q / W, w = q % W;
+    uint64_t word = 0;
+    if (r < nch) {
+      if (init) {
+        const uint4 y = philox(make_uint4((uint32_t)(ch0 + r), (uint32_t)(w >> 1), 0u, 2u), key);
+        word = (w & 1) ? ((uint64_t)y.z | ((uint64_t)y.w << 32)) : ((uint64_t)y.x | ((uint64_t)y.y << 32));
+        const int rem = N - 64 * w;
+        if (rem < 64) word &= (1ull << rem) - 1ull;
+      } else {
+        word = bits[(int64_t)(ch0 + r) * W + w];
+      }
+    }
+    cb[q] = word;
+  }
+  __syncthreads();
+
+  // ---- the state of the chains from their bits (a1 is kept in t2 until z2 is formed)
+  for (int r = 0; r < nch; ++r) {
+    const int64_t base = (int64_t)(ch0 + r) * CN;
+    const uint64_t* br = cb + r * W;
+    for (int e = tid; e < (int)CN; e += MB_NT) {
+      const int p = e / C, c = e % C;
+      const int v = pyx[p], y = v >> 16, x = v & 0xffff;
+      float2 z = b1f[c];
+      for (int wy = 0; wy < k; ++wy) {
+        const int yy = y + wy - (y + wy >= g.Ly ? g.Ly : 0);
+        for (int wx = 0; wx < k; ++wx) {
+          const int xx = x + wx - (x + wx >= g.Lx ? g.Lx : 0);
+          const int q = __mul24(yy, g.Lx) + xx;
+          const float sg = ((br[q >> 6] >> (q & 63)) & 1ull) ? 1.f : -1.f;
+          const float2 wv = W1f[c * kk + wy * k + wx];
+          z.x = fmaf(sg, wv.x, z.x);
+          z.y = fmaf(sg, wv.y, z.y);
+        }
+      }
+      float2 tz, a;
+      fctanh_logcosh_pv(z, tz, a);
+      z1g[base + e] = z;
+      t1g[base + e] = tz;
+      a1ig[base + e] = a.y;
+      t2g[base + e] = a;
+    }
+    __syncthreads();
+    for (int e = tid; e < (int)CN; e += MB_NT) {
+      const int p = e / C, c = e % C;
+      const int v = pyx[p], y = v >> 16, x = v & 0xffff;
+      float2 z = b2f[c];
+      for (int t = 0; t < kk; ++t) {
+        const int vw = wyx[t];
+        const int yy = y + (vw >> 16) - (y + (vw >> 16) >= g.Ly ? g.Ly : 0);
+        const int xx = x + (vw & 0xffff) - (x + (vw & 0xffff) >= g.Lx ? g.Lx : 0);
+        const float2* a1p = t2g + base + (int64_t)(__mul24(yy, g.Lx) + xx) * C;
+        for (int ci = 0; ci < C; ++ci) z = fcadd(z, fcmul(W2f[(c * C + ci) * kk + t], a1p[ci]));
+      }
+      z2g[base + e] = z;
+    }
+    __syncthreads();
+    for (int e = tid; e < (int)CN; e += MB_NT) t2g[base + e] = fctanh(z2g[base + e]);
+  }
+  __syncthreads();
+
+  unsigned long long n_acc = 0;  // thread r < nch: accepted moves of chain ch0 + r
+  const int64_t total = therm_steps + n_record * sweep;
+  // Global-memory phases gather all their loads first and then compute and
+  // store: loads and stores share one in-order counter, so a load issued after
+  // a store would wait for it.
+  // element q = tid + j MB_NT of the [chain][w][ci] layer-1 changes: its state index (-1: none)
+  auto l1_index = [&](int j, int& r, int& w, int& ci) {
+    const int v = l1tab[j * MB_NT + tid];
+    r = v >> 16;
+    w = (v >> 8) & 0xff;
+    ci = v & 0xff;
+    if (r >= nch || ci >= C) return -1;
+    const int site = site_s[r], vs = pyx[site], vw = wyx[w];
+    const int sy = vs >> 16, sx = vs & 0xffff, wy = vw >> 16, wx = vw & 0xffff;
+    const int p = site - __mul24(wy, g.Lx) - wx + (sy < wy ? N : 0) + (sx < wx ? g.Lx : 0);
+    return (ch0 + r) * (int)CN + p * C + ci;
+  };
+  for (int64_t step = 0; step < total; ++step) {
+    const uint64_t t = t0 + (uint64_t)step;
+    if (tid < nch) {
+      const uint4 x = philox(make_uint4((uint32_t)(ch0 + tid), (uint32_t)t, (uint32_t)(t >> 32), 0u), key);
+      const int site = (int)to_index(x.x, (uint32_t)N);
+      site_s[tid] = site;
+      u_s[tid] = to_uniform(x.y, x.z);
+      sg_s[tid] = ((cb[tid * W + (site >> 6)] >> (site & 63)) & 1ull) ? 1.f : -1.f;
+    }
+    __syncthreads();
+    // ---- dA[chain][w][ci] at the layer-1 positions site - w
+    {
+      float2 tv[MB_DA];
+      float av[MB_DA];
+#pragma unroll
+      for (int j = 0; j < MB_DA; ++j) {
+        int r, w, ci;
+        const int idx = l1_index(j, r, w, ci);
+        tv[j] = idx >= 0 ? t1g[idx] : make_float2(0.f, 0.f);
+        av[j] = idx >= 0 ? a1ig[idx] : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < MB_DA; ++j) {
+        int r, w, ci;
+        const int idx = l1_index(j, r, w, ci);
+        if (r >= MB_CH) continue;
+        float2 d = make_float2(0.f, 0.f);
+        if (idx >= 0) {
+          const float2 ts = fcmul(tv[j], sD[ci * kk + w]);
+          const float2 c1 = cD[ci * kk + w];
+          const float sg = sg_s[r];
+          d = fclog1p(make_float2(c1.x - sg * ts.x, c1.y - sg * ts.y));
+          const float sum = av[j] + d.y;
+          d.y += sum > PI_F ? -TWO_PI_F : (sum <= -PI_F ? TWO_PI_F : 0.f);
+        }
+        are[r * g.sDA + w * Cp + ci] = d.x;
+        aim[r * g.sDA + w * Cp + ci] = d.y;
+      }
+    }
+    __syncthreads();
+
+    // ---- window offsets: dZ of 16 chains x 16 channels, the factors of the lane's chains
+    // rows 4 lk + i of the product are chains; the lane's channel is li.  State element of
+    // chain row i, channel li, at position site - e (fewer than 2^31 elements per array):
+    //   rb[i] - (ey Lx + ex) C + (N C if sy < ey) + (Lx C if sx < ex),  rb[i] = chain CN + site C + li
+    // Rows past the group's chains (a partial last group) and padded channels take no part.
+    int rb[4], rsy[4], rsx[4];
+    unsigned rok = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int site = site_s[4 * lk + i], v = pyx[site];
+      rsy[i] = v >> 16;
+      rsx[i] = v & 0xffff;
+      rb[i] = (ch0 + 4 * lk + i) * (int)CN + __mul24(site, C) + li;
+      if (li < C && 4 * lk + i < nch) rok |= 1u << i;
+    }
+    // offset 0 is shared: this wave takes row i = wave & 3 in the lanes lk >> 1 == wave >> 2
+    const unsigned rok0 = (lk >> 1) == (wave >> 2) ? rok & (1u << (wave & 3)) : 0u;
+    float2 P[4];
+    int E[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      P[i] = make_float2(1.f, 0.f);
+      E[i] = 0;
+    }
+    floatx4 zr[MB_MAXE + 1], zi[MB_MAXE + 1];  // dZ kept for the update: slot 0 is offset 0
+    const float* a_re = are + li * g.sDA;
+    const float* a_im = aim + li * g.sDA;
+    const float* b_re = wre + li;
+    const float* b_im = wim + li;
+    auto product = [&](int e, floatx4& re, floatx4& im) {
+      const int nt = __builtin_amdgcn_readfirstlane(eh[e].w);
+      const unsigned* op = opt + e * kk;
+      re = floatx4{0.f, 0.f, 0.f, 0.f};
+      im = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int ti = 0; ti < nt; ++ti) {
+        const unsigned v = op[ti];
+        const int ao = (int)(v >> 16), bo = (int)(v & 0xffffu);
+        for (int c4 = 0; c4 < Cp; c4 += 4) {
+          const int ci = c4 + lk;
+          const float ar = a_re[ao + ci], ai = a_im[ao + ci];
+          const float br = b_re[bo + ci * Cn], bi = b_im[bo + ci * Cn];
+          re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re, 0, 0, 0);
+          re = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, re, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, im, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, im, 0, 0, 0);
+        }
+      }
+    };
+    // state element of row i at the position of window offset e
+    auto widx = [&](int e, int i) {
+      const int4 hd = eh[e];
+      const int ey = __builtin_amdgcn_readfirstlane(hd.x), ex = __builtin_amdgcn_readfirstlane(hd.y);
+      const int eo = __builtin_amdgcn_readfirstlane(hd.z) * C;
+      return rb[i] - eo + (rsy[i] < ey ? N * C : 0) + (rsx[i] < ex ? g.Lx * C : 0);
+    };
+    int nf = 0;
+    // slot j (window offset e, rows ok): tanh z2 loaded before the product so that the loads
+    // overlap it; the factors use the hardware exponential, sine and reciprocal (they feed
+    // only the ratio)
+    auto window = [&](int j, int e, unsigned ok) {
+      float2 tz[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) tz[i] = (ok >> i) & 1u ? t2g[widx(e, i)] : make_float2(0.f, 0.f);
+      product(e, zr[j], zi[j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float2 f = window_factor<VMC_BF16>(make_float2(zr[j][i], zi[j][i]), tz[i]);
+        P[i] = (ok >> i) & 1u ? fcmul(P[i], f) : P[i];
+      }
+      if (++nf == 2) {
+        nf = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) renorm(P[i], E[i]);
+      }
+    };
+    window(0, 0, rok0);
+#pragma unroll
+    for (int j = 1; j <= MB_MAXE; ++j) {
+      const int e = 1 + wave + (j - 1) * MB_NW;
+      if (e < nwin) window(j, e, rok);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      renorm(P[i], E[i]);
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        const float2 q = make_float2(__shfl_xor(P[i].x, o, 64), __shfl_xor(P[i].y, o, 64));
+        E[i] += __shfl_xor(E[i], o, 64);
+        P[i] = fcmul(P[i], q);
+      }
+      renorm(P[i], E[i]);
+    }
+    if (li == 0)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        pm[wave * 16 + 4 * lk + i] = P[i];
+        pe[wave * 16 + 4 * lk + i] = E[i];
+      }
+    __syncthreads();
+    // ---- accept or reject (float64 log ratio)
+    if (tid < MB_CH) {
+      int a = 0;
+      if (tid < nch) {
+        double2 m = make_double2(1.0, 0.0);
+        int ex = 0;
+        for (int w = 0; w < MB_NW; ++w) {
+          const float2 q = pm[w * 16 + tid];
+          m = cmul(m, make_double2(q.x, q.y));
+          ex += pe[w * 16 + tid];
+        }
+        const double lr = log(m.x * m.x + m.y * m.y) + 2.0 * ex * 0.69314718055994530942;
+        a = (lr >= 0.0) || (u_s[tid] < exp(lr));
+        if (a) {
+          ++n_acc;
+          const int site = site_s[tid];
+          cb[tid * W + (site >> 6)] ^= 1ull << (site & 63);
+        }
+      }
+      acc_s[tid] = a;
+    }
+    __syncthreads();
+    // ---- accepted moves: z2 += dZ and tanh z2 at the window positions (each wave its
+    // offsets), z1 -= 2 sigma W1, tanh z1 and Im a1 += Im dA at the layer-1 positions
+    {
+      unsigned racc = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) racc |= acc_s[4 * lk + i] ? 1u << i : 0u;
+      // two halves of the slots (registers): gather z2, then add and store
+#pragma unroll
+      for (int h = 0; h <= MB_MAXE; h += 4) {
+        float2 zv[4][4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int j = h + jj;
+          if (j > MB_MAXE) break;
+          const int e = j == 0 ? 0 : 1 + wave + (j - 1) * MB_NW;
+          const unsigned ok = (j == 0 ? rok0 : (e < nwin ? rok : 0u)) & racc;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) zv[jj][i] = (ok >> i) & 1u ? z2g[widx(e, i)] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int j = h + jj;
+          if (j > MB_MAXE) break;
+          const int e = j == 0 ? 0 : 1 + wave + (j - 1) * MB_NW;
+          const unsigned ok = (j == 0 ? rok0 : (e < nwin ? rok : 0u)) & racc;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (!((ok >> i) & 1u)) continue;
+            const int idx = widx(e, i);
+            const float2 zn = make_float2(zv[jj][i].x + zr[j][i], zv[jj][i].y + zi[j][i]);
+            z2g[idx] = zn;
+            t2g[idx] = fctanh_fast(zn);
+          }
+        }
+      }
+    }
+    {
+      float2 z1v[MB_DA];
+      float av[MB_DA];
+#pragma unroll
+      for (int j = 0; j < MB_DA; ++j) {
+        int r, w, ci;
+        int idx = l1_index(j, r, w, ci);
+        if (idx >= 0 && !acc_s[r]) idx = -1;
+        z1v[j] = idx >= 0 ? z1g[idx] : make_float2(0.f, 0.f);
+        av[j] = idx >= 0 ? a1ig[idx] : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < MB_DA; ++j) {
+        int r, w, ci;
+        const int idx = l1_index(j, r, w, ci);
+        if (idx < 0 || !acc_s[r]) continue;
+        const float2 wv = W1f[ci * kk + w];
+        const float sg = sg_s[r];
+        const float2 zn = make_float2(z1v[j].x - 2.f * sg * wv.x, z1v[j].y - 2.f * sg * wv.y);
+        z1g[idx] = zn;
+        t1g[idx] = fctanh_fast(zn);
+        a1ig[idx] = av[j] + aim[r * g.sDA + w * Cp + ci];
+      }
+    }
+    __syncthreads();
+    // ---- record
+    if (step >= therm_steps && ((step - therm_steps + 1) % sweep) == 0) {
+      const int64_t kr = (step - therm_steps + 1) / sweep - 1;
+      for (int q = tid; q < nch * W; q += MB_NT) {
+        const int r = q / W, w = q % W;
+        s_out[(kr * n_chains + ch0 + r) * W + w] = cb[q];
+      }
+      if (logpsi_out)
+        for (int r = wave; r < nch; r += MB_NW) {
+          const int64_t base = (int64_t)(ch0 + r) * CN;
+          double2 lp = make_double2(0.0, 0.0);
+          for (int64_t e = lane; e < CN; e += 64) {
+            const float2 l = fclogcosh(z2g[base + e]);
+            lp.x += l.x;
+            lp.y += l.y;
+          }
+          lp = wave_sum(lp);
+          if (lane == 0) logpsi_out[kr * n_chains + ch0 + r] = lp;
+        }
+    }
+  }
+  for (int q = tid; q < nch * W; q += MB_NT) bits[(int64_t)ch0 * W + q] = cb[q];
+  if (tid < nch) acc[ch0 + tid] = n_acc;
+}
+
+mb_geom make_mb_geom(const vmc_model* m) {
+  mb_geom g{};
+  g.Lx = m->Lx;
+  g.Ly = m->Ly;
+  g.N = m->N;
+  g.W = m->W;
+  g.C = m->C;
+  g.k = m->k;
+  g.kk = m->k * m->k;
+  g.win = 2 * m->k - 1;
+  g.Cp = (m->C + 7) / 8 * 8;
+  g.Cn = 16;
+  g.sDA = g.kk * g.Cp + 4;
+  int o = 0;
+  auto take = [&](int bytes) {
+    const int r = o;
+    o = (o + bytes + 15) & ~15;
+    return r;
+  };
+  g.o_wre = take(4 * g.kk * g.Cp * g.Cn);
+  g.o_wim = take(4 * g.kk * g.Cp * g.Cn);
+  g.o_are = take(4 * MB_CH * g.sDA);
+  g.o_aim = take(4 * MB_CH * g.sDA);
+  g.o_cd = take(8 * g.C * g.kk);
+  g.o_sd = take(8 * g.C * g.kk);
+  g.o_pyx = take(4 * g.N);
+  g.o_wyx = take(4 * g.kk);
+  g.o_eh = take(16 * g.win * g.win);
+  g.o_opt = take(4 * g.win * g.win * g.kk);
+  g.o_bits = take(8 * MB_CH * g.W);
+  g.o_site = take(4 * MB_CH);
+  g.o_u = take(8 * MB_CH);
+  g.o_sg = take(4 * MB_CH);
+  g.o_acc = take(4 * MB_CH);
+  g.o_pm = take(8 * MB_NW * 16);
+  g.o_pe = take(4 * MB_NW * 16);
+  g.o_l1 = take(4 * MB_DA * MB_NT);
+  g.lds = o;
+  return g;
+}
+
 int align16(int x) { return (x + 15) & ~15; }
 
 lp_geom make_geom(const vmc_model* m, int prec) {
@@ -984,25 +1467,44 @@ void cnn_lowp_sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, 
   vmc_model* m = S->model;
   VMC_REQUIRE(S->opts.proposal == VMC_PROP_FLIP, "the CNN sampler uses single-spin flips");
   VMC_REQUIRE(m->Lx >= 2 * m->k - 1 && m->Ly >= 2 * m->k - 1, "the CNN sampler needs Lx, Ly >= 2 kernel - 1");
-  const mh_geom g = make_mh_geom(m);
-  VMC_REQUIRE(g.nout <= MH_MAXOUT * MH_NT, "CNN window too large for the sampler");
-  if (g.lds > 160 * 1024)
-    throw vmc_error{VMC_ERR_UNSUPPORTED, "CNN too large for the float32 sampler (LDS)"};
   vmc_ctx* ctx = m->ctx;
   hipStream_t st = ctx->stream;
   const int n1 = m->C * m->k * m->k;
   const size_t tb = sizeof(float2) * (size_t)(m->K + 3 * n1);
-  const size_t ab = sizeof(float2) * (size_t)S->opts.n_chains * m->C * m->N;
-  ws_reserve(ctx, ws_round(tb) + ws_round(ab));
-  float2* P32 = (float2*)ws_take(ctx, tb);
-  float2* a1 = (float2*)ws_take(ctx, ab);
-  k_lp_tables<<<grid_for(m->K + 3 * n1, 256), 256, 0, st>>>(m->params, m->K, n1, P32);
-  VMC_HIP(hipFuncSetAttribute((const void*)k_cnn_mh_lp, hipFuncAttributeMaxDynamicSharedMemorySize, g.lds));
   const int64_t therm = S->thermalized ? 0 : (int64_t)S->opts.therm_sweeps * S->opts.sweep_steps;
   const uint2 key = make_uint2((uint32_t)S->opts.seed, (uint32_t)(S->opts.seed >> 32));
-  k_cnn_mh_lp<<<S->opts.n_chains, MH_NT, g.lds, st>>>(g, P32, S->opts.n_chains, S->bits, key, S->t, !S->bits_valid,
-                                                      therm, n_per_chain, S->opts.sweep_steps, s_out, logpsi_out,
-                                                      S->acc, a1);
+  const int nc = S->opts.n_chains;
+  const mb_geom gb = make_mb_geom(m);
+  if (m->C <= 16 && m->k <= 4 && gb.lds <= 160 * 1024 && (int64_t)nc * m->C * m->N < ((int64_t)1 << 31)) {
+    // 16 chains per work-group, state in global memory
+    const size_t cn = (size_t)nc * m->C * m->N;
+    const size_t b2 = ws_round(sizeof(float2) * cn), b1 = ws_round(sizeof(float) * cn);
+    ws_reserve(ctx, ws_round(tb) + 4 * b2 + b1);
+    float2* P32 = (float2*)ws_take(ctx, tb);
+    float2* z1 = (float2*)ws_take(ctx, b2);
+    float2* t1 = (float2*)ws_take(ctx, b2);
+    float2* z2 = (float2*)ws_take(ctx, b2);
+    float2* t2 = (float2*)ws_take(ctx, b2);
+    float* a1i = (float*)ws_take(ctx, b1);
+    k_lp_tables<<<grid_for(m->K + 3 * n1, 256), 256, 0, st>>>(m->params, m->K, n1, P32);
+    VMC_HIP(hipFuncSetAttribute((const void*)k_cnn_mh_batch, hipFuncAttributeMaxDynamicSharedMemorySize, gb.lds));
+    k_cnn_mh_batch<<<(nc + MB_CH - 1) / MB_CH, MB_NT, gb.lds, st>>>(
+        gb, P32, nc, S->bits, key, S->t, !S->bits_valid, therm, n_per_chain, S->opts.sweep_steps, s_out, logpsi_out,
+        S->acc, z1, t1, a1i, z2, t2);
+  } else {
+    const mh_geom g = make_mh_geom(m);
+    VMC_REQUIRE(g.nout <= MH_MAXOUT * MH_NT, "CNN window too large for the sampler");
+    if (g.lds > 160 * 1024)
+      throw vmc_error{VMC_ERR_UNSUPPORTED, "CNN too large for the float32 sampler (LDS)"};
+    const size_t ab = sizeof(float2) * (size_t)nc * m->C * m->N;
+    ws_reserve(ctx, ws_round(tb) + ws_round(ab));
+    float2* P32 = (float2*)ws_take(ctx, tb);
+    float2* a1 = (float2*)ws_take(ctx, ab);
+    k_lp_tables<<<grid_for(m->K + 3 * n1, 256), 256, 0, st>>>(m->params, m->K, n1, P32);
+    VMC_HIP(hipFuncSetAttribute((const void*)k_cnn_mh_lp, hipFuncAttributeMaxDynamicSharedMemorySize, g.lds));
+    k_cnn_mh_lp<<<nc, MH_NT, g.lds, st>>>(g, P32, nc, S->bits, key, S->t, !S->bits_valid, therm, n_per_chain,
+                                          S->opts.sweep_steps, s_out, logpsi_out, S->acc, a1);
+  }
   VMC_HIP(hipGetLastError());
   S->t += (uint64_t)(therm + n_per_chain * S->opts.sweep_steps);
   S->thermalized = 1;
