@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "internal.h"
 
@@ -904,37 +905,44 @@ mh_geom make_mh_geom(const vmc_model* m) {
 // products: per step each chain proposes a flip at its own site, the layer-1
 // changes dA of the 16 chains form the A operand (rows), W2 the B operand, and
 // for every window offset e one float32 product gives dZ of 16 chains x 16
-// channels, as in the local-energy kernel.  The per-chain state (z1, tanh z1,
-// Im a1 on the principal branch, z2, tanh z2; position-major, channel fastest)
-// lives in global memory: 16 chains do not fit in LDS.  Accepted moves update
-// z1 and z2 additively with the same float32 dZ and re-evaluate tanh; log psi
-// of a recorded sample is re-summed from z2.  The state is rebuilt from the
-// bits at the start of every call.  Used for C <= 16 and k <= 4.
-struct mb_geom {
-  int Lx, Ly, N, W, C, k, kk, win;
-  int Cp, Cn, sDA;  // channels rounded up to 8 / 16; dA row stride (floats)
-  int o_wre, o_wim, o_are, o_aim, o_cd, o_sd, o_pyx, o_wyx, o_eh, o_opt, o_bits, o_site, o_u, o_sg, o_acc, o_pm,
-      o_pe, o_l1, lds;
-};
-
-constexpr int MB_NT = 512;  // two waves per SIMD: the window offsets' dZ stay in registers until the decision
+// channels, as in the local-energy kernel.  The per-chain state (z1, Im a1 on
+// the principal branch, z2; position-major, channel fastest) lives in global
+// memory: 16 chains do not fit in LDS.  tanh z1 and tanh z2 are evaluated where
+// they are used; an accepted move stores z1 - 2 sigma W1 and z2 + dZ (float32,
+// additive), so rounding grows only additively; log psi of a recorded sample is
+// re-summed from z2.  The state is rebuilt from the bits at the start of every
+// call.  Used for C <= 16 and k <= 4.
+constexpr int MB_NT = 512;  // two waves per SIMD: the window offsets' new z2 stay in registers until the decision
 constexpr int MB_NW = MB_NT / 64;
 constexpr int MB_CH = 16;    // chains per work-group
 constexpr int MB_MAXE = 6;   // window offsets per wave besides the shared offset 0: (2k - 1)^2 - 1 <= 48
 constexpr int MB_DA = MB_CH * 256 / MB_NT;  // layer-1 changes per thread: k^2 Cp <= 256
 
+struct mb_geom {
+  int Lx, Ly, N, W, C, k, kk, win;
+  int Cp, Cn, sDA;  // channels rounded up to 8 / 16; dA row stride (floats)
+  int o_wre, o_wim, o_wsum, o_are, o_aim, o_asum, o_cd, o_sd, o_pyx, o_wyx, o_eh, o_opt, o_bits, o_site, o_u, o_sg,
+      o_acc, o_pm, o_pe, o_l1, lds;
+  // window offsets 1 .. (2k - 1)^2 - 1 of each wave (-1: none), balanced by their taps
+  short eslot[MB_NW][MB_MAXE];
+};
+
+// KS = Cp / 4: the matrix-core k steps per tap; lane lk takes channels KS lk .. KS lk + KS - 1
+template <int KS>
 __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2* __restrict__ P32, int n_chains,
                                                         uint64_t* __restrict__ bits, uint2 key, uint64_t t0, int init,
                                                         int64_t therm_steps, int64_t n_record, int sweep,
                                                         uint64_t* __restrict__ s_out, double2* __restrict__ logpsi_out,
                                                         unsigned long long* __restrict__ acc, float2* __restrict__ z1g,
-                                                        float2* __restrict__ t1g, float* __restrict__ a1ig,
-                                                        float2* __restrict__ z2g, float2* __restrict__ t2g) {
+                                                        float* __restrict__ a1ig, float2* __restrict__ z2g,
+                                                        float2* __restrict__ a1t) {
   extern __shared__ __align__(16) char smem[];
-  float* wre = (float*)(smem + g.o_wre);  // W2 operand planes [t][ci][c] (c fastest, Cn wide)
+  float* wre = (float*)(smem + g.o_wre);  // W2 operand planes [t][c][ci]: Re, Im, Re + Im
   float* wim = (float*)(smem + g.o_wim);
-  float* are = (float*)(smem + g.o_are);  // dA operand planes [chain][w][ci]
+  float* wsum = (float*)(smem + g.o_wsum);
+  float* are = (float*)(smem + g.o_are);  // dA operand planes [chain][w][ci]: Re, Im, Re + Im
   float* aim = (float*)(smem + g.o_aim);
+  float* asum = (float*)(smem + g.o_asum);
   float2* cD = (float2*)(smem + g.o_cd);
   float2* sD = (float2*)(smem + g.o_sd);
   int* pyx = (int*)(smem + g.o_pyx);
@@ -976,16 +984,17 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
     unsigned v = 0;
     if (ti < nt) {
       const int ty = ty0 + ti / ntx, tx = tx0 + ti % ntx;
-      v = ((unsigned)(((ey - ty) * k + (ex - tx)) * Cp) << 16) | (unsigned)((ty * k + tx) * Cp * Cn);
+      v = ((unsigned)(((ey - ty) * k + (ex - tx)) * Cp) << 16) | (unsigned)((ty * k + tx) * Cn * Cp);
     }
     opt[q] = v;
     if (ti == 0) eh[e] = make_int4(ey, ex, __mul24(ey, g.Lx) + ex, nt);
   }
-  for (int e = tid; e < kk * Cp * Cn; e += MB_NT) {
-    const int t = e / (Cp * Cn), r = e % (Cp * Cn), ci = r / Cn, c = r % Cn;
+  for (int e = tid; e < kk * Cn * Cp; e += MB_NT) {
+    const int t = e / (Cn * Cp), r = e % (Cn * Cp), c = r / Cp, ci = r % Cp;
     const float2 v = (c < C && ci < C) ? W2f[(c * C + ci) * kk + t] : make_float2(0.f, 0.f);
     wre[e] = v.x;
     wim[e] = v.y;
+    wsum[e] = v.x + v.y;
   }
   for (int e = tid; e < C * kk; e += MB_NT) {
     cD[e] = tabs[e];
@@ -1013,7 +1022,7 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
   }
   __syncthreads();
 
-  // ---- the state of the chains from their bits (a1 is kept in t2 until z2 is formed)
+  // ---- the state of the chains from their bits (a1 itself is kept in a1t while z2 is formed)
   for (int r = 0; r < nch; ++r) {
     const int64_t base = (int64_t)(ch0 + r) * CN;
     const uint64_t* br = cb + r * W;
@@ -1035,9 +1044,8 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
       float2 tz, a;
       fctanh_logcosh_pv(z, tz, a);
       z1g[base + e] = z;
-      t1g[base + e] = tz;
       a1ig[base + e] = a.y;
-      t2g[base + e] = a;
+      a1t[base + e] = a;
     }
     __syncthreads();
     for (int e = tid; e < (int)CN; e += MB_NT) {
@@ -1048,21 +1056,19 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
         const int vw = wyx[t];
         const int yy = y + (vw >> 16) - (y + (vw >> 16) >= g.Ly ? g.Ly : 0);
         const int xx = x + (vw & 0xffff) - (x + (vw & 0xffff) >= g.Lx ? g.Lx : 0);
-        const float2* a1p = t2g + base + (int64_t)(__mul24(yy, g.Lx) + xx) * C;
+        const float2* a1p = a1t + base + (int64_t)(__mul24(yy, g.Lx) + xx) * C;
         for (int ci = 0; ci < C; ++ci) z = fcadd(z, fcmul(W2f[(c * C + ci) * kk + t], a1p[ci]));
       }
       z2g[base + e] = z;
     }
     __syncthreads();
-    for (int e = tid; e < (int)CN; e += MB_NT) t2g[base + e] = fctanh(z2g[base + e]);
   }
-  __syncthreads();
 
   unsigned long long n_acc = 0;  // thread r < nch: accepted moves of chain ch0 + r
   const int64_t total = therm_steps + n_record * sweep;
-  // Global-memory phases gather all their loads first and then compute and
-  // store: loads and stores share one in-order counter, so a load issued after
-  // a store would wait for it.
+  // Global-memory phases issue all their loads before any store: loads and
+  // stores share one in-order counter, so a load issued after a store would wait
+  // for it.
   // element q = tid + j MB_NT of the [chain][w][ci] layer-1 changes: its state index (-1: none)
   auto l1_index = [&](int j, int& r, int& w, int& ci) {
     const int v = l1tab[j * MB_NT + tid];
@@ -1074,6 +1080,29 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
     const int sy = vs >> 16, sx = vs & 0xffff, wy = vw >> 16, wx = vw & 0xffff;
     const int p = site - __mul24(wy, g.Lx) - wx + (sy < wy ? N : 0) + (sx < wx ? g.Lx : 0);
     return (ch0 + r) * (int)CN + p * C + ci;
+  };
+  // three real products per complex term: with A = sum Re Re', B = sum Im Im',
+  // S = sum (Re + Im)(Re' + Im'):  Re dZ = A - B,  Im dZ = S - A - B
+  typedef float vks __attribute__((ext_vector_type(KS)));
+  const int ak = li * g.sDA + KS * lk, bk = li * Cp + KS * lk;
+  auto product = [&](int e, floatx4& re, floatx4& im) {
+    const int nt = __builtin_amdgcn_readfirstlane(eh[e].w);
+    const unsigned* op = opt + e * kk;
+    floatx4 A = {0.f, 0.f, 0.f, 0.f}, Bq = A, S = A;
+    for (int ti = 0; ti < nt; ++ti) {
+      const unsigned v = op[ti];
+      const int ao = ak + (int)(v >> 16), bo = bk + (int)(v & 0xffffu);
+      const vks xr = *(const vks*)(are + ao), xi = *(const vks*)(aim + ao), xs = *(const vks*)(asum + ao);
+      const vks yr = *(const vks*)(wre + bo), yi = *(const vks*)(wim + bo), ys = *(const vks*)(wsum + bo);
+#pragma unroll
+      for (int q = 0; q < KS; ++q) {
+        A = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[q], yr[q], A, 0, 0, 0);
+        Bq = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[q], yi[q], Bq, 0, 0, 0);
+        S = __builtin_amdgcn_mfma_f32_16x16x4f32(xs[q], ys[q], S, 0, 0, 0);
+      }
+    }
+    re = A - Bq;
+    im = S - A - Bq;
   };
   for (int64_t step = 0; step < total; ++step) {
     const uint64_t t = t0 + (uint64_t)step;
@@ -1087,13 +1116,13 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
     __syncthreads();
     // ---- dA[chain][w][ci] at the layer-1 positions site - w
     {
-      float2 tv[MB_DA];
+      float2 zv[MB_DA];
       float av[MB_DA];
 #pragma unroll
       for (int j = 0; j < MB_DA; ++j) {
         int r, w, ci;
         const int idx = l1_index(j, r, w, ci);
-        tv[j] = idx >= 0 ? t1g[idx] : make_float2(0.f, 0.f);
+        zv[j] = idx >= 0 ? z1g[idx] : make_float2(0.f, 0.f);
         av[j] = idx >= 0 ? a1ig[idx] : 0.f;
       }
 #pragma unroll
@@ -1103,7 +1132,7 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
         if (r >= MB_CH) continue;
         float2 d = make_float2(0.f, 0.f);
         if (idx >= 0) {
-          const float2 ts = fcmul(tv[j], sD[ci * kk + w]);
+          const float2 ts = fcmul(fctanh_fast(zv[j]), sD[ci * kk + w]);
           const float2 c1 = cD[ci * kk + w];
           const float sg = sg_s[r];
           d = fclog1p(make_float2(c1.x - sg * ts.x, c1.y - sg * ts.y));
@@ -1112,6 +1141,7 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
         }
         are[r * g.sDA + w * Cp + ci] = d.x;
         aim[r * g.sDA + w * Cp + ci] = d.y;
+        asum[r * g.sDA + w * Cp + ci] = d.x + d.y;
       }
     }
     __syncthreads();
@@ -1133,6 +1163,13 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
     }
     // offset 0 is shared: this wave takes row i = wave & 3 in the lanes lk >> 1 == wave >> 2
     const unsigned rok0 = (lk >> 1) == (wave >> 2) ? rok & (1u << (wave & 3)) : 0u;
+    auto widx = [&](int e, int i) {
+      const int4 hd = eh[e];
+      const int ey = __builtin_amdgcn_readfirstlane(hd.x), ex = __builtin_amdgcn_readfirstlane(hd.y);
+      const int eo = __builtin_amdgcn_readfirstlane(hd.z) * C;
+      return rb[i] - eo + (rsy[i] < ey ? N * C : 0) + (rsx[i] < ex ? g.Lx * C : 0);
+    };
+    auto slot_e = [&](int j) { return j == 0 ? 0 : (int)g.eslot[wave][j - 1]; };
     float2 P[4];
     int E[4];
 #pragma unroll
@@ -1140,49 +1177,24 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
       P[i] = make_float2(1.f, 0.f);
       E[i] = 0;
     }
-    floatx4 zr[MB_MAXE + 1], zi[MB_MAXE + 1];  // dZ kept for the update: slot 0 is offset 0
-    const float* a_re = are + li * g.sDA;
-    const float* a_im = aim + li * g.sDA;
-    const float* b_re = wre + li;
-    const float* b_im = wim + li;
-    auto product = [&](int e, floatx4& re, floatx4& im) {
-      const int nt = __builtin_amdgcn_readfirstlane(eh[e].w);
-      const unsigned* op = opt + e * kk;
-      re = floatx4{0.f, 0.f, 0.f, 0.f};
-      im = floatx4{0.f, 0.f, 0.f, 0.f};
-      for (int ti = 0; ti < nt; ++ti) {
-        const unsigned v = op[ti];
-        const int ao = (int)(v >> 16), bo = (int)(v & 0xffffu);
-        for (int c4 = 0; c4 < Cp; c4 += 4) {
-          const int ci = c4 + lk;
-          const float ar = a_re[ao + ci], ai = a_im[ao + ci];
-          const float br = b_re[bo + ci * Cn], bi = b_im[bo + ci * Cn];
-          re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re, 0, 0, 0);
-          re = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, re, 0, 0, 0);
-          im = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, im, 0, 0, 0);
-          im = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, im, 0, 0, 0);
-        }
-      }
-    };
-    // state element of row i at the position of window offset e
-    auto widx = [&](int e, int i) {
-      const int4 hd = eh[e];
-      const int ey = __builtin_amdgcn_readfirstlane(hd.x), ex = __builtin_amdgcn_readfirstlane(hd.y);
-      const int eo = __builtin_amdgcn_readfirstlane(hd.z) * C;
-      return rb[i] - eo + (rsy[i] < ey ? N * C : 0) + (rsx[i] < ex ? g.Lx * C : 0);
-    };
+    float2 zn[MB_MAXE + 1][4];  // z2 + dZ of the window positions, stored if the move is accepted
     int nf = 0;
-    // slot j (window offset e, rows ok): tanh z2 loaded before the product so that the loads
-    // overlap it; the factors use the hardware exponential, sine and reciprocal (they feed
-    // only the ratio)
-    auto window = [&](int j, int e, unsigned ok) {
-      float2 tz[4];
+    // slot j: z2 loaded before the product so that the loads overlap it; tanh z2 and the
+    // factors use the hardware exponential, sine and reciprocal (they feed only the ratio)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) tz[i] = (ok >> i) & 1u ? t2g[widx(e, i)] : make_float2(0.f, 0.f);
-      product(e, zr[j], zi[j]);
+    for (int j = 0; j <= MB_MAXE; ++j) {
+      const int e = slot_e(j);
+      const unsigned ok = e < 0 ? 0u : (j == 0 ? rok0 : rok);
+      if (e < 0) continue;
+      float2 z2v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) z2v[i] = (ok >> i) & 1u ? z2g[widx(e, i)] : make_float2(0.f, 0.f);
+      floatx4 re, im;
+      product(e, re, im);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float2 f = window_factor<VMC_BF16>(make_float2(zr[j][i], zi[j][i]), tz[i]);
+        zn[j][i] = make_float2(z2v[i].x + re[i], z2v[i].y + im[i]);
+        const float2 f = window_factor<VMC_BF16>(make_float2(re[i], im[i]), fctanh_fast(z2v[i]));
         P[i] = (ok >> i) & 1u ? fcmul(P[i], f) : P[i];
       }
       if (++nf == 2) {
@@ -1190,12 +1202,6 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
 #pragma unroll
         for (int i = 0; i < 4; ++i) renorm(P[i], E[i]);
       }
-    };
-    window(0, 0, rok0);
-#pragma unroll
-    for (int j = 1; j <= MB_MAXE; ++j) {
-      const int e = 1 + wave + (j - 1) * MB_NW;
-      if (e < nwin) window(j, e, rok);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -1237,42 +1243,8 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
       acc_s[tid] = a;
     }
     __syncthreads();
-    // ---- accepted moves: z2 += dZ and tanh z2 at the window positions (each wave its
-    // offsets), z1 -= 2 sigma W1, tanh z1 and Im a1 += Im dA at the layer-1 positions
-    {
-      unsigned racc = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) racc |= acc_s[4 * lk + i] ? 1u << i : 0u;
-      // two halves of the slots (registers): gather z2, then add and store
-#pragma unroll
-      for (int h = 0; h <= MB_MAXE; h += 4) {
-        float2 zv[4][4];
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int j = h + jj;
-          if (j > MB_MAXE) break;
-          const int e = j == 0 ? 0 : 1 + wave + (j - 1) * MB_NW;
-          const unsigned ok = (j == 0 ? rok0 : (e < nwin ? rok : 0u)) & racc;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) zv[jj][i] = (ok >> i) & 1u ? z2g[widx(e, i)] : make_float2(0.f, 0.f);
-        }
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int j = h + jj;
-          if (j > MB_MAXE) break;
-          const int e = j == 0 ? 0 : 1 + wave + (j - 1) * MB_NW;
-          const unsigned ok = (j == 0 ? rok0 : (e < nwin ? rok : 0u)) & racc;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            if (!((ok >> i) & 1u)) continue;
-            const int idx = widx(e, i);
-            const float2 zn = make_float2(zv[jj][i].x + zr[j][i], zv[jj][i].y + zi[j][i]);
-            z2g[idx] = zn;
-            t2g[idx] = fctanh_fast(zn);
-          }
-        }
-      }
-    }
+    // ---- accepted moves: z1 -= 2 sigma W1 and Im a1 += Im dA at the layer-1 positions
+    // (loads first), z2 + dZ at the window positions (each wave its offsets)
     {
       float2 z1v[MB_DA];
       float av[MB_DA];
@@ -1284,6 +1256,18 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
         z1v[j] = idx >= 0 ? z1g[idx] : make_float2(0.f, 0.f);
         av[j] = idx >= 0 ? a1ig[idx] : 0.f;
       }
+      unsigned racc = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) racc |= acc_s[4 * lk + i] ? 1u << i : 0u;
+#pragma unroll
+      for (int j = 0; j <= MB_MAXE; ++j) {
+        const int e = slot_e(j);
+        if (e < 0) continue;
+        const unsigned ok = (j == 0 ? rok0 : rok) & racc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if ((ok >> i) & 1u) z2g[widx(e, i)] = zn[j][i];
+      }
 #pragma unroll
       for (int j = 0; j < MB_DA; ++j) {
         int r, w, ci;
@@ -1291,9 +1275,7 @@ __global__ __launch_bounds__(MB_NT) void k_cnn_mh_batch(mb_geom g, const float2*
         if (idx < 0 || !acc_s[r]) continue;
         const float2 wv = W1f[ci * kk + w];
         const float sg = sg_s[r];
-        const float2 zn = make_float2(z1v[j].x - 2.f * sg * wv.x, z1v[j].y - 2.f * sg * wv.y);
-        z1g[idx] = zn;
-        t1g[idx] = fctanh_fast(zn);
+        z1g[idx] = make_float2(z1v[j].x - 2.f * sg * wv.x, z1v[j].y - 2.f * sg * wv.y);
         a1ig[idx] = av[j] + aim[r * g.sDA + w * Cp + ci];
       }
     }
@@ -1344,8 +1326,10 @@ mb_geom make_mb_geom(const vmc_model* m) {
   };
   g.o_wre = take(4 * g.kk * g.Cp * g.Cn);
   g.o_wim = take(4 * g.kk * g.Cp * g.Cn);
+  g.o_wsum = take(4 * g.kk * g.Cp * g.Cn);
   g.o_are = take(4 * MB_CH * g.sDA);
   g.o_aim = take(4 * MB_CH * g.sDA);
+  g.o_asum = take(4 * MB_CH * g.sDA);
   g.o_cd = take(8 * g.C * g.kk);
   g.o_sd = take(8 * g.C * g.kk);
   g.o_pyx = take(4 * g.N);
@@ -1361,6 +1345,26 @@ mb_geom make_mb_geom(const vmc_model* m) {
   g.o_pe = take(4 * MB_NW * 16);
   g.o_l1 = take(4 * MB_DA * MB_NT);
   g.lds = o;
+  // window offsets 1 .. nwin - 1 to the waves, MB_MAXE at most each, by longest
+  // processing time on their tap counts (the matrix-core work of an offset)
+  for (int w = 0; w < MB_NW; ++w)
+    for (int j = 0; j < MB_MAXE; ++j) g.eslot[w][j] = -1;
+  std::vector<int> es;
+  for (int e = 1; e < g.win * g.win; ++e) es.push_back(e);
+  auto taps = [&](int e) {
+    const int ey = e / g.win, ex = e % g.win;
+    return (std::min(g.k - 1, ey) - std::max(0, ey - g.k + 1) + 1) * (std::min(g.k - 1, ex) - std::max(0, ex - g.k + 1) + 1);
+  };
+  std::stable_sort(es.begin(), es.end(), [&](int a, int b) { return taps(a) > taps(b); });
+  int load[MB_NW] = {}, cnt[MB_NW] = {};
+  for (int e : es) {
+    int best = -1;
+    for (int w = 0; w < MB_NW; ++w)
+      if (cnt[w] < MB_MAXE && (best < 0 || load[w] < load[best])) best = w;
+    if (best < 0) throw vmc_error{VMC_ERR_UNSUPPORTED, "CNN window too large for the batched sampler"};
+    g.eslot[best][cnt[best]++] = (short)e;
+    load[best] += taps(e);
+  }
   return g;
 }
 
@@ -1479,18 +1483,20 @@ void cnn_lowp_sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, 
     // 16 chains per work-group, state in global memory
     const size_t cn = (size_t)nc * m->C * m->N;
     const size_t b2 = ws_round(sizeof(float2) * cn), b1 = ws_round(sizeof(float) * cn);
-    ws_reserve(ctx, ws_round(tb) + 4 * b2 + b1);
+    ws_reserve(ctx, ws_round(tb) + 3 * b2 + b1);
     float2* P32 = (float2*)ws_take(ctx, tb);
     float2* z1 = (float2*)ws_take(ctx, b2);
-    float2* t1 = (float2*)ws_take(ctx, b2);
     float2* z2 = (float2*)ws_take(ctx, b2);
-    float2* t2 = (float2*)ws_take(ctx, b2);
+    float2* a1t = (float2*)ws_take(ctx, b2);
     float* a1i = (float*)ws_take(ctx, b1);
     k_lp_tables<<<grid_for(m->K + 3 * n1, 256), 256, 0, st>>>(m->params, m->K, n1, P32);
-    VMC_HIP(hipFuncSetAttribute((const void*)k_cnn_mh_batch, hipFuncAttributeMaxDynamicSharedMemorySize, gb.lds));
-    k_cnn_mh_batch<<<(nc + MB_CH - 1) / MB_CH, MB_NT, gb.lds, st>>>(
-        gb, P32, nc, S->bits, key, S->t, !S->bits_valid, therm, n_per_chain, S->opts.sweep_steps, s_out, logpsi_out,
-        S->acc, z1, t1, a1i, z2, t2);
+    auto launch = [&](auto kern) {
+      VMC_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, gb.lds));
+      kern<<<(nc + MB_CH - 1) / MB_CH, MB_NT, gb.lds, st>>>(gb, P32, nc, S->bits, key, S->t, !S->bits_valid, therm,
+                                                            n_per_chain, S->opts.sweep_steps, s_out, logpsi_out, S->acc,
+                                                            z1, a1i, z2, a1t);
+    };
+    gb.Cp == 16 ? launch(k_cnn_mh_batch<4>) : launch(k_cnn_mh_batch<2>);
   } else {
     const mh_geom g = make_mh_geom(m);
     VMC_REQUIRE(g.nout <= MH_MAXOUT * MH_NT, "CNN window too large for the sampler");
