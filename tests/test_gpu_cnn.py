@@ -95,20 +95,22 @@ def test_sampler_replay(ctx):
     assert 0 < acc <= 1
 
 
-def test_lowp_sampler_histogram(ctx):
+@pytest.mark.parametrize("nc,per", [(1024, 400), (37, 4000)])
+def test_lowp_sampler_histogram(ctx, nc, per):
     # float32 chains (VMC_F32 / VMC_BF16 models): the visit histogram on the
-    # 3 x 3 torus matches |psi|^2 of the float64 oracle
+    # 3 x 3 torus matches |psi|^2 of the float64 oracle (37 chains: a partial
+    # last group of 16)
     from scipy import stats
     from gpu_common import host_bits
-    flush("cnn float32 sampler histogram")
+    flush(f"cnn float32 sampler histogram, {nc} chains")
     Lx, Ly, C, k = 3, 3, 2, 2
     m, p = _cnn(ctx, Lx, Ly, C, k, 0.4, seed=31)
     m.set_precision(V.VMC_F32)
     H = V.Hamiltonian.tfim(ctx, Lx, Ly, True, 1.0, 3.0)
-    S = V.Sampler(ctx, m, H, proposal=V.PROP_FLIP, n_chains=1024, therm_sweeps=20, seed=5)
-    s, _, acc = S.sample(1024 * 400)
+    S = V.Sampler(ctx, m, H, proposal=V.PROP_FLIP, n_chains=nc, therm_sweeps=20, seed=5)
+    s, _, acc = S.sample(nc * per)
     assert 0 < acc < 1
-    dec = host_bits(s).reshape(400, 1024)[::4].reshape(-1).astype(np.int64)
+    dec = host_bits(s).reshape(per, nc)[::4].reshape(-1).astype(np.int64)
     cd = np.bincount(dec, minlength=2 ** 9)
     _, prob, _ = oeloc.exact_probabilities(lambda b: ocnn.log_psi(p, b, Lx, Ly, C, k), 9)
     res = stats.chisquare(cd, prob * cd.sum())
@@ -116,16 +118,18 @@ def test_lowp_sampler_histogram(ctx):
     assert res.pvalue > 1e-4, res
 
 
-@pytest.mark.parametrize("Lx,Ly,C,k,std", [(8, 8, 3, 3, 0.3), (16, 16, 16, 4, 0.05), (9, 7, 17, 2, 0.1)])
-def test_lowp_sampler_log_psi(ctx, Lx, Ly, C, k, std):
+@pytest.mark.parametrize("Lx,Ly,C,k,std,nc", [(8, 8, 3, 3, 0.3, 32), (16, 16, 16, 4, 0.05, 32), (9, 7, 17, 2, 0.1, 32),
+                                             (6, 6, 5, 3, 0.2, 21), (7, 7, 16, 4, 0.1, 16)])
+def test_lowp_sampler_log_psi(ctx, Lx, Ly, C, k, std, nc):
     # the chain's running log psi (float32 window products, float64 sum) stays
-    # on the oracle's log psi of the emitted configurations
+    # on the oracle's log psi of the emitted configurations; C <= 16 and k <= 4
+    # run 16 chains per work-group (nc = 21: a partial last group), C = 17 one
+    # chain per work-group
     from gpu_common import host_bits
-    flush(f"cnn float32 sampler log psi {Lx}x{Ly} C={C} k={k}")
+    flush(f"cnn float32 sampler log psi {Lx}x{Ly} C={C} k={k} chains={nc}")
     m, p = _cnn(ctx, Lx, Ly, C, k, std, seed=41 + C)
     m.set_precision(V.VMC_BF16)
     H = V.Hamiltonian.tfim(ctx, Lx, Ly, True, 1.0, 3.0)
-    nc = 32
     S = V.Sampler(ctx, m, H, proposal=V.PROP_FLIP, n_chains=nc, therm_sweeps=4, seed=9)
     for call in range(2):
         s, lp, acc = S.sample(nc * 3)
