@@ -49,7 +49,7 @@ template <int Q>
 __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   __shared__ uint64_t cb[64];  // chain configuration, W <= 64 words
   // theta_j of the chain in lane-private LDS slots [q][lane]: registers hold
-  // only t_j = tanh theta_j
+  // only t_j = tanh theta_j (theta in registers measured slower)
   __shared__ double2 ths[Q * 64];
   const int c = blockIdx.x;
   if (c >= a.n_chains) return;
@@ -88,6 +88,8 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   // theta_j = b_j + sum_i W_ji sigma_i for the lane's hidden units (or the
   // value kept from the previous launch of this call)
   double2 tt[Q];
+  auto theta = [&](int q) -> double2& { return ths[q * 64 + lane]; };
+#pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int j = lane + 64 * q;
     double2 acc = j < Nh ? a.params[N + j] : make_double2(0.0, 0.0);
@@ -103,10 +105,10 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
         }
       }
     }
-    ths[q * 64 + lane] = acc;
+    theta(q) = acc;
   }
 #pragma unroll
-  for (int q = 0; q < Q; ++q) tt[q] = ctanh(ths[q * 64 + lane]);
+  for (int q = 0; q < Q; ++q) tt[q] = ctanh(theta(q));
 
   unsigned long long accepted = 0;
   const int64_t total = a.therm_steps + a.n_record * a.sweep;
@@ -115,12 +117,26 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   // step ahead (local-move kernels with up to 512 hidden units, where the
   // extra registers fit).
   constexpr bool PF = Q <= 8;
-  uint4 xn = philox(make_uint4((uint32_t)c, (uint32_t)a.t0, (uint32_t)(a.t0 >> 32), 0u), a.key);
+  // The counters of 64 consecutive steps are drawn together, one per lane, into
+  // a table of moves and log u (the same Philox values as one per step; the
+  // test u < exp(r) is taken as log u < r, which decides alike away from
+  // |r - log u| at the rounding level).
+  __shared__ int mv_s[64];
+  __shared__ double uv_s[64];
+  auto draw64 = [&](int64_t s0) {
+    const uint64_t tl = a.t0 + (uint64_t)(s0 + lane);
+    const uint4 y = philox(make_uint4((uint32_t)c, (uint32_t)tl, (uint32_t)(tl >> 32), 0u), a.key);
+    __syncthreads();
+    mv_s[lane] = (int)to_index(y.x, (uint32_t)a.n_moves);
+    uv_s[lane] = log(to_uniform(y.y, y.z));
+    __syncthreads();
+  };
+  draw64(0);
   double2 Tn[PF ? Q : 1], Dn[PF ? Q : 1];
   double2 aln = make_double2(0.0, 0.0), lcn = aln;  // alpha and LC of that move
   int2 bdn = make_int2(0, 0);                       // its bond (exchange moves)
   if (PF) {
-    const int mn = (int)to_index(xn.x, (uint32_t)a.n_moves);
+    const int mn = mv_s[0];
     aln = a.alpha[mn];
     lcn = a.LC[mn];
     if (a.proposal == VMC_PROP_EXCHANGE) bdn = a.bonds[mn];
@@ -132,10 +148,8 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
     }
   }
   for (int64_t step = 0; step < total; ++step) {
-    const uint64_t t = a.t0 + (uint64_t)step;
-    const uint4 x = xn;
-    const int m = (int)to_index(x.x, (uint32_t)a.n_moves);
-    const double u = to_uniform(x.y, x.z);
+    const int m = mv_s[step & 63];
+    const double lu = uv_s[step & 63];
     double2 Tc[PF ? Q : 1], Dc[PF ? Q : 1];
     const double2 alc = aln, lcc = lcn;
     const int2 bdc = bdn;
@@ -147,9 +161,9 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
       }
     }
     if (step + 1 < total) {
-      xn = philox(make_uint4((uint32_t)c, (uint32_t)(t + 1), (uint32_t)((t + 1) >> 32), 0u), a.key);
+      if (((step + 1) & 63) == 0) draw64(step + 1);
       if (PF) {
-        const int mn = (int)to_index(xn.x, (uint32_t)a.n_moves);
+        const int mn = mv_s[(step + 1) & 63];
         aln = a.alpha[mn];
         lcn = a.LC[mn];
         if (a.proposal == VMC_PROP_EXCHANGE) bdn = a.bonds[mn];
@@ -175,20 +189,26 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
     } else {
       const double sg = ((cb[site >> 6] >> (site & 63)) & 1ull) ? 1.0 : -1.0;
       double prod = 1.0;
+      // per hidden unit the factor f = 1 - sigma t_j T_jm and |f|^2, kept for the update
+      double2 fq[Q];
+      double nq[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int j = lane + 64 * q;
+        fq[q] = make_double2(1.0, 0.0);
+        nq[q] = 1.0;
         if (j < Nh) {
           const double2 p = cmul(tt[q], PF ? Tc[PF ? q : 0] : a.T[(int64_t)m * Nh + j]);
-          const double fx = 1.0 - sg * p.x, fy = -sg * p.y;
-          prod *= fx * fx + fy * fy;
+          fq[q] = make_double2(1.0 - sg * p.x, -sg * p.y);
+          nq[q] = fq[q].x * fq[q].x + fq[q].y * fq[q].y;
+          prod *= nq[q];
         }
       }
       double L = wave_sum(log(prod));
       L = __shfl(L, 0, 64);  // one value for the whole wave: a uniform decision
       const double2 al = PF ? alc : a.alpha[m], lc = PF ? lcc : a.LC[m];
       const double r = 2.0 * (-2.0 * sg * al.x + lc.x) + L;
-      const bool acc = (r >= 0.0) || (u < exp(r));
+      const bool acc = (r >= 0.0) || (lu < r);
       if (acc) {
         ++accepted;
 #pragma unroll
@@ -197,13 +217,12 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
           if (j < Nh) {
             const double2 d = PF ? Dc[PF ? q : 0] : a.D[(int64_t)m * Nh + j];
             const double2 Tm = PF ? Tc[PF ? q : 0] : a.T[(int64_t)m * Nh + j];
-            double2 thv = ths[q * 64 + lane];
-            thv.x -= 2.0 * sg * d.x;
-            thv.y -= 2.0 * sg * d.y;
-            ths[q * 64 + lane] = thv;
-            const double2 p = cmul(tt[q], Tm);
-            tt[q] = cdiv(make_double2(tt[q].x - sg * Tm.x, tt[q].y - sg * Tm.y),
-                         make_double2(1.0 - sg * p.x, -sg * p.y));
+            theta(q).x -= 2.0 * sg * d.x;
+            theta(q).y -= 2.0 * sg * d.y;
+            // t' = (t - sigma T) / f = (t - sigma T) conj(f) / |f|^2
+            const double2 nu = make_double2(tt[q].x - sg * Tm.x, tt[q].y - sg * Tm.y);
+            const double inv = 1.0 / nq[q];
+            tt[q] = make_double2((nu.x * fq[q].x + nu.y * fq[q].y) * inv, (nu.y * fq[q].x - nu.x * fq[q].y) * inv);
           }
         }
         __syncthreads();
@@ -230,7 +249,7 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
       for (int q = 0; q < Q; ++q) {
         const int j = lane + 64 * q;
         if (j < Nh) {
-          const double2 thv = ths[q * 64 + lane];
+          const double2 thv = theta(q);
           lp = cadd(lp, clogcosh(thv));
           tt[q] = ctanh(thv);
         }
@@ -241,9 +260,10 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   }
   for (int w = lane; w < W; w += 64) a.bits[(int64_t)c * W + w] = cb[w];
   if (a.theta_store)
+#pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int j = lane + 64 * q;
-      if (j < Nh) a.theta_store[(int64_t)c * Nh + j] = ths[q * 64 + lane];
+      if (j < Nh) a.theta_store[(int64_t)c * Nh + j] = theta(q);
     }
   if (lane == 0) a.acc[c] += accepted;
 }
