@@ -29,7 +29,8 @@ def _hermitian(K, seed, spread=6.0, cplx=True):
     return X.conj().T @ X
 
 
-@pytest.mark.parametrize("K,cplx", [(1, True), (2, True), (7, True), (64, False), (333, True), (1000, True)])
+@pytest.mark.parametrize("K,cplx", [(1, True), (2, True), (7, True), (64, False), (333, True), (1000, True),
+                                    (2048, True)])
 def test_eigh_matches_numpy(ctx, K, cplx):
     flush(f"eigh K={K}")
     A = _hermitian(K, seed=K, cplx=cplx)
