@@ -164,19 +164,18 @@ __device__ __forceinline__ void fctanh_logcosh_pv(float2 z, float2& t, float2& a
   a = make_float2(z.x - 0.69314718f + l.x, remainderf(z.y + l.y, TWO_PI_F));
 }
 
-// cosh dz + tz sinh dz
+// cosh dz + tz sinh dz, with the hardware exponential, sine, cosine and
+// reciprocal (measured on this chip: exp within 4 ulp on [-4, 4], sin and cos
+// within 4.5 x 2^-24 absolute on [-pi, pi], the reciprocal within 1 ulp); in
+// float32 Im dz is reduced to [-pi, pi] first (the float32 error bound of a
+// factor allows 16 x 2^-24).
 template <int PREC>
 __device__ __forceinline__ float2 window_factor(float2 dz, float2 tz) {
-  float ea, sb, cb, ia;
-  if constexpr (PREC == VMC_BF16) {
-    ea = __expf(dz.x);
-    __sincosf(dz.y, &sb, &cb);
-    ia = __builtin_amdgcn_rcpf(ea);  // hardware reciprocal (1 ulp), well inside the bfloat16 error
-  } else {
-    ea = expf(dz.x);
-    sincosf(dz.y, &sb, &cb);
-    ia = 1.f / ea;
-  }
+  float sb, cb;
+  const float ea = __expf(dz.x);
+  const float y = PREC == VMC_F32 ? fmaf(-TWO_PI_F, rintf(dz.y * 0.159154943091895336f), dz.y) : dz.y;
+  __sincosf(y, &sb, &cb);
+  const float ia = __builtin_amdgcn_rcpf(ea);
   const float ch = 0.5f * (ea + ia), sh = 0.5f * (ea - ia);
   const float2 cz = make_float2(ch * cb, sh * sb), sz = make_float2(sh * cb, ch * sb);
   return fcadd(cz, fcmul(tz, sz));
