@@ -25,10 +25,8 @@
 // A non-positive pivot sets the fail index; every later kernel then exits at
 // once.  The upper triangle of S~ is never written.
 //
-// Triangular solves: one launch per block.  Launch b updates the remaining
-// right-hand side with block b's solution (64 rows or columns per group, a
-// quad or a wave per 16 terms); the group that holds the next block's entries,
-// final after its update, forms that block's solution from L_bb^{-1}.
+// Triangular solves: one launch per direction, one group per 64-row block,
+// blocks handed over through ready flags in the order of the solve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -299,129 +297,197 @@ __device__ __forceinline__ double2 quad_sum(double2 v) {
   return cadd(v, shfl_xor2(v, 2));
 }
 
-// y_0 = Linv_0 rhs_0 (one group; thread (r, q) = (tid / 4, tid % 4) sums m = q, q + 4, ...)
-__global__ __launch_bounds__(256) void k_fwd_first(const double2* __restrict__ Linv, const double2* __restrict__ rhs,
-                                                   double2* __restrict__ y, int nb) {
-  const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
-  double2 s = make_double2(0.0, 0.0);
-  for (int m = q; m <= r && m < nb; m += 4) s = cadd(s, cmul(Linv[r * CB + m], rhs[m]));
-  s = quad_sum(s);
-  if (q == 0 && r < nb) y[r] = s;
+// ---------------------------------------------------------------- solves --
+// Each triangular solve is one launch with one group per 64-row block.  A group
+// takes a ticket (an atomic counter) when it starts and solves the block with
+// that rank in the order of the solve, so every block it waits for belongs to a
+// group that started earlier: the waits end whatever the number of groups the
+// device holds at once.  A block's solution is published by its group with a
+// release store of a per-block ready flag; wave 0 of a consumer polls the flags
+// (64 at a time, relaxed), then takes an acquire fence before it reads the
+// solutions.  Off-diagonal products are accumulated in registers over all
+// earlier blocks and reduced once, so the critical path per block is one flag
+// hand-over, one 64-term update and the 64 x 64 product with L_bb^{-1}.
+//
+// sync layout (ints, zeroed before the forward solve): [0] forward ticket,
+// [1, nblk] forward flags, [nblk + 1] backward ticket, [nblk + 2, 2 nblk + 1]
+// backward flags, [2 nblk + 2] set when a wait exceeded its poll limit.
+constexpr int kPollLimit = 1 << 22;  // polls (a global load and a short sleep each) before a wait gives up
+
+__global__ void k_zero_ints(int* __restrict__ p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
-// Forward update of block b (y_b in y): rhs[R] -= sum_m L[R][kb0 + m] y_b[m] for
-// R >= kb0 + 64, 64 rows per group, thread (r, q) summing m = q, q + 4, ...
-// (each quad reads 64 contiguous bytes of its row per step).  Group 0 holds the
-// rows of block b + 1, which are then final: it also forms
-// y_{b+1} = Linv_{b+1} rhs_{b+1}.
-__global__ __launch_bounds__(256) void k_fwd_update(const double2* __restrict__ A, int64_t K, int64_t kb0,
-                                                    const double2* __restrict__ Linv_next, int nb_next,
-                                                    double2* __restrict__ rhs, double2* __restrict__ y) {
-  __shared__ double2 yb[CB];
+// Wave 0 of a group: wait until the flags of blocks j, j + d, j + 2d, ... up to
+// (not including) `end` are set, at least block j; returns the first block
+// past the leading run of set flags (d = +1 forward, -1 backward).
+__device__ __forceinline__ int wait_ready(const int* __restrict__ flag, int j, int end, int d, int* __restrict__ err) {
+  const int lane = threadIdx.x & 63;
+  const int jl = j + d * lane;
+  for (int polls = 0;; ++polls) {
+    const bool in = d > 0 ? jl < end : jl > end;
+    const int f = in ? __hip_atomic_load(flag + jl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    const unsigned long long m = __ballot(f != 0);
+    const int n = ~m == 0ull ? 64 : __builtin_ctzll(~m);
+    if (n > 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      return j + d * n;
+    }
+    if (polls >= kPollLimit) {  // never reached when every group runs to its end
+      if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return j + d;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// L y = rhs.  Group rank b: thread (r, q) = (tid / 4, tid % 4) accumulates
+// sum_j L[R][64 j + m] y_j[m] over m = q, q + 4, ... for row R = 64 b + r
+// (each quad reads 64 contiguous bytes of its row per load), then
+// y_b = L_bb^{-1} (rhs_b - sum).  The row entries of the next two blocks are in
+// flight while a block is applied (three register buffers in turn); L_bb^{-1}
+// waits in LDS, so that two groups fit on a compute unit and every group of the
+// launch is resident at once.
+__global__ __launch_bounds__(256, 2) void k_fwd_chain(const double2* __restrict__ A, int64_t K, int nblk,
+                                                      const double2* __restrict__ Linv, const double2* __restrict__ rhs,
+                                                      double2* __restrict__ y, int* __restrict__ sync) {
+  __shared__ int tk;
+  __shared__ double2 li[CB * (CB + 1)];  // L_bb^{-1}, row stride 65
+  __shared__ double2 yb[2][CB];
   __shared__ double2 rs[CB];
+  __shared__ double2 ys[CB];
   const int tid = threadIdx.x;
   const int r = tid >> 2, q = tid & 3;
-  // group 0: this thread's entries of Linv_{b+1} (m = q + 4 t <= r), loaded
-  // first so that they arrive while the rows are updated
-  double2 lv[CB / 4];
-  if (blockIdx.x == 0) {
+  if (tid == 0) tk = atomicAdd(sync, 1);
+  __syncthreads();
+  const int b = tk;
+  int* flag = sync + 1;
+  const int64_t R = (int64_t)b * CB + r;
+  const bool row_ok = R < K;
+  const int nb = (int)std::min<int64_t>(CB, K - (int64_t)b * CB);
+  const double2 zero = make_double2(0.0, 0.0);
+  const double2* Ar = A + (row_ok ? R : 0) * K + q;
+  auto load_blk = [&](int j, double2(&v)[CB / 4]) {
 #pragma unroll
-    for (int t = 0; t < CB / 4; ++t) {
-      const int m = q + 4 * t;
-      lv[t] = (m <= r && m < nb_next) ? Linv_next[r * CB + m] : make_double2(0.0, 0.0);
+    for (int t = 0; t < CB / 4; ++t) v[t] = row_ok ? Ar[(int64_t)j * CB + 4 * t] : zero;
+  };
+  double2 A0[CB / 4], A1[CB / 4], A2[CB / 4];
+  if (b > 0) load_blk(0, A0);
+  if (b > 1) load_blk(1, A1);
+  const double2 rv = (row_ok && q == 0) ? rhs[R] : zero;
+  for (int i = tid; i < CB * CB; i += 256) li[(i >> 6) * (CB + 1) + (i & 63)] = Linv[(size_t)b * CB * CB + i];
+  double2 acc = zero;
+  int ready = 0;  // wave 0: blocks [0, ready) are published
+  // apply block j (entries in cur); the entries of block j + 2 go to pre
+  auto step = [&](int j, double2(&cur)[CB / 4], double2(&pre)[CB / 4]) {
+    if (tid < 64) {
+      if (j >= ready) ready = wait_ready(flag, j, b, 1, sync + 2 * nblk + 2);
+      yb[j & 1][tid] = y[(int64_t)j * CB + tid];  // block j < b is a full block
     }
+    __syncthreads();
+    if (j + 2 < b) load_blk(j + 2, pre);
+#pragma unroll
+    for (int t = 0; t < CB / 4; ++t) acc = cadd(acc, cmul(cur[t], yb[j & 1][4 * t + q]));
+  };
+  for (int j = 0; j < b; j += 3) {
+    step(j, A0, A2);
+    if (j + 1 < b) step(j + 1, A1, A0);
+    if (j + 2 < b) step(j + 2, A2, A1);
   }
-  // the row entries and the right-hand side do not depend on y_b: their loads
-  // are issued before y_b is published through LDS
-  const int64_t R = kb0 + CB + (int64_t)blockIdx.x * CB + r;
-  double2 av[CB / 4];
-#pragma unroll
-  for (int j = 0; j < CB / 4; ++j) av[j] = R < K ? A[R * K + kb0 + 4 * j + q] : make_double2(0.0, 0.0);
-  const double2 rv = (R < K && q == 0) ? rhs[R] : make_double2(0.0, 0.0);
-  if (tid < CB) yb[tid] = y[kb0 + tid];
-  __syncthreads();
-  double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int j = 0; j < CB / 4; ++j) acc = cadd(acc, cmul(av[j], yb[4 * j + q]));
   acc = quad_sum(acc);
-  double2 nv = make_double2(0.0, 0.0);
-  if (R < K && q == 0) {
-    nv = csub(rv, acc);
-    rhs[R] = nv;
-  }
-  if (blockIdx.x != 0) return;  // uniform over the group
-  if (q == 0) rs[r] = nv;
-  __syncthreads();
-  double2 s = make_double2(0.0, 0.0);
+  if (q == 0) rs[r] = row_ok ? csub(rv, acc) : zero;
+  __syncthreads();  // also orders the LDS copy of L_bb^{-1} before its reads
+  double2 s = zero;
 #pragma unroll
-  for (int t = 0; t < CB / 4; ++t) s = cadd(s, cmul(lv[t], rs[q + 4 * t]));
+  for (int t = 0; t < CB / 4; ++t) {
+    const int m = q + 4 * t;
+    if (m <= r && m < nb) s = cadd(s, cmul(li[r * (CB + 1) + m], rs[m]));
+  }
   s = quad_sum(s);
-  if (q == 0 && r < nb_next) y[kb0 + CB + r] = s;
+  if (q == 0) ys[r] = s;
+  __syncthreads();
+  if (tid < 64) {
+    if (tid < nb) y[(int64_t)b * CB + tid] = ys[tid];
+    __hip_atomic_store(flag + b, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
-// x_b = Linv_b^H v_b for the last block b (one group): (Linv^H)[r][m] = conj(Linv[m][r]), m >= r
-__global__ __launch_bounds__(256) void k_bwd_first(const double2* __restrict__ Linv, const double2* __restrict__ v,
-                                                   double2* __restrict__ x, int nb) {
-  const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
-  double2 s = make_double2(0.0, 0.0);
-  for (int m = r + q; m < nb; m += 4) s = cadd(s, cmul(cconj(Linv[m * CB + r]), v[m]));
-  s = quad_sum(s);
-  if (q == 0 && r < nb) x[r] = s;
-}
-
-// Backward update of block b (x_b in x): v[c] -= sum_m conj(L[kb0 + m][c]) x_b[m]
-// for c < kb0, 64 columns per group, wave q summing m = 16 q .. 16 q + 15 (each
-// step reads 64 consecutive columns of one row).  The last group holds the
-// columns of block b - 1, which are then final: it also forms
-// x_{b-1} = Linv_{b-1}^H v_{b-1}.
-__global__ __launch_bounds__(256) void k_bwd_update(const double2* __restrict__ A, int64_t K, int64_t kb0, int nb,
-                                                    const double2* __restrict__ Linv_prev, double2* __restrict__ v,
-                                                    double2* __restrict__ x) {
-  __shared__ double2 xb[CB];
+// L^H x = y.  Group rank t solves block b = nblk - 1 - t: thread (w, c) =
+// (tid / 64, tid % 64) accumulates sum_j sum_m conj(L[64 j + m][64 b + c]) x_j[m]
+// over m = 16 w .. 16 w + 15 for j > b (each load reads 64 consecutive columns
+// of one row), then x_b = L_bb^{-H} (y_b - sum).  Buffers as in the forward
+// solve; here every step reads 64 rows not read before, so the two-block
+// prefetch also covers their address-translation misses.
+__global__ __launch_bounds__(256, 2) void k_bwd_chain(const double2* __restrict__ A, int64_t K, int nblk,
+                                                      const double2* __restrict__ Linv, const double2* __restrict__ y,
+                                                      double2* __restrict__ x, int* __restrict__ sync) {
+  __shared__ int tk;
+  __shared__ double2 li[CB * (CB + 1)];  // L_bb^{-1}, row stride 65
+  __shared__ double2 xb[2][CB];
   __shared__ double2 part[4][CB];
   __shared__ double2 vs[CB];
   const int tid = threadIdx.x;
-  const int wv = tid >> 6, ln = tid & 63;
-  // last group: wave w holds conj(Linv_{b-1}[m][ln]) for the rows m = w + 4 t
-  // (each load one contiguous row; entries above the diagonal are stored as
-  // zeros), loaded first so that they arrive while the columns are updated
-  double2 lv[CB / 4];
-  if (blockIdx.x == gridDim.x - 1) {
+  const int w = tid >> 6, c = tid & 63;
+  if (tid == 0) tk = atomicAdd(sync + nblk + 1, 1);
+  __syncthreads();
+  const int b = nblk - 1 - tk;
+  int* flag = sync + nblk + 2;
+  const int nb = (int)std::min<int64_t>(CB, K - (int64_t)b * CB);
+  const double2 zero = make_double2(0.0, 0.0);
+  auto nb_of = [&](int j) { return (int)std::min<int64_t>(CB, K - (int64_t)j * CB); };
+  // column 64 b + c exists for every block b < nblk - 1, the only ones that load
+  // (row addresses are wave-uniform: scalar bases plus the lane's column offset)
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  auto load_blk = [&](int j, double2(&v)[CB / 4]) {
+    const int nbj = nb_of(j);
 #pragma unroll
-    for (int t = 0; t < CB / 4; ++t) lv[t] = cconj(Linv_prev[(wv + 4 * t) * CB + ln]);
+    for (int i = 0; i < CB / 4; ++i) {
+      const int m = wu * (CB / 4) + i;
+      const double2* row = A + ((int64_t)j * CB + m) * K + (int64_t)b * CB;
+      v[i] = m < nbj ? cconj(row[c]) : zero;
+    }
+  };
+  double2 A0[CB / 4], A1[CB / 4], A2[CB / 4];
+  if (b < nblk - 1) load_blk(nblk - 1, A0);
+  if (b < nblk - 2) load_blk(nblk - 2, A1);
+  const double2 yv = tid < nb ? y[(int64_t)b * CB + tid] : zero;
+  for (int i = tid; i < CB * CB; i += 256) li[(i >> 6) * (CB + 1) + (i & 63)] = Linv[(size_t)b * CB * CB + i];
+  double2 acc = zero;
+  int ready = nblk - 1;  // wave 0: blocks (ready, nblk) are published
+  // apply block j (entries in cur); the entries of block j - 2 go to pre
+  auto step = [&](int j, double2(&cur)[CB / 4], double2(&pre)[CB / 4]) {
+    if (tid < 64) {
+      if (j <= ready) ready = wait_ready(flag, j, b, -1, sync + 2 * nblk + 2);
+      xb[j & 1][tid] = tid < nb_of(j) ? x[(int64_t)j * CB + tid] : zero;
+    }
+    __syncthreads();
+    if (j - 2 > b) load_blk(j - 2, pre);
+#pragma unroll
+    for (int i = 0; i < CB / 4; ++i) acc = cadd(acc, cmul(cur[i], xb[j & 1][w * (CB / 4) + i]));
+  };
+  for (int j = nblk - 1; j > b; j -= 3) {
+    step(j, A0, A2);
+    if (j - 1 > b) step(j - 1, A1, A0);
+    if (j - 2 > b) step(j - 2, A2, A1);
   }
-  // the column entries and v do not depend on x_b: their loads are issued
-  // before x_b is published through LDS
-  const int cl = tid & 63, q = tid >> 6;
-  const int64_t c = (int64_t)blockIdx.x * CB + cl;  // < kb0: the grid covers kb0 / 64 column blocks
-  double2 av[CB / 4];
+  part[w][c] = acc;
+  __syncthreads();  // also orders the LDS copy of L_bb^{-1} before its reads
+  if (tid < 64)
+    vs[tid] = tid < nb ? csub(yv, cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]))) : zero;
+  __syncthreads();
+  // x_b[c] = sum_{m >= c} conj(L_bb^{-1}[m][c]) v_b[m], wave w over m = w + 4 t
+  double2 s = zero;
 #pragma unroll
-  for (int j = 0; j < CB / 4; ++j) {
-    const int m = q * (CB / 4) + j;
-    av[j] = m < nb ? cconj(A[(kb0 + m) * K + c]) : make_double2(0.0, 0.0);
+  for (int t = 0; t < CB / 4; ++t) {
+    const int m = w + 4 * t;
+    if (m >= c && m < nb) s = cadd(s, cmul(cconj(li[m * (CB + 1) + c]), vs[m]));
   }
-  const double2 vc = tid < CB ? v[c] : make_double2(0.0, 0.0);
-  if (tid < CB) xb[tid] = tid < nb ? x[kb0 + tid] : make_double2(0.0, 0.0);
+  part[w][c] = s;  // every read of part above finished before the last barrier
   __syncthreads();
-  double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int j = 0; j < CB / 4; ++j) acc = cadd(acc, cmul(av[j], xb[q * (CB / 4) + j]));
-  part[q][cl] = acc;
-  __syncthreads();
-  if (tid < CB) {
-    const double2 nv = csub(vc, cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid])));
-    v[c] = nv;
-    vs[tid] = nv;
+  if (tid < 64) {
+    if (tid < nb) x[(int64_t)b * CB + tid] = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
+    __hip_atomic_store(flag + b, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (blockIdx.x != gridDim.x - 1) return;  // uniform over the group
-  __syncthreads();
-  // x_{b-1}[ln] = sum_m conj(Linv_{b-1}[m][ln]) v_{b-1}[m], wave w over m = w + 4 t
-  double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int t = 0; t < CB / 4; ++t) s = cadd(s, cmul(lv[t], vs[wv + 4 * t]));
-  part[wv][ln] = s;  // the column update's reads of part finished before the barrier above
-  __syncthreads();
-  if (tid < CB) x[kb0 - CB + tid] = cadd(cadd(part[0][tid], part[1][tid]), cadd(part[2][tid], part[3][tid]));
 }
 
 }  // namespace
@@ -505,26 +571,17 @@ void chol_factor(vmc_ctx* ctx, double2* S, int64_t K, double2* Linv, long long* 
   VMC_HIP(hipGetLastError());
 }
 
-// rhs is consumed; y and x are K-vectors; x receives the solution
-void chol_solve(vmc_ctx* ctx, const double2* S, int64_t K, const double2* Linv, double2* rhs, double2* y, double2* x) {
+size_t chol_sync_bytes(int64_t K) { return sizeof(int) * (size_t)(2 * ((K + CB - 1) / CB) + 3); }
+int chol_sync_err_index(int64_t K) { return (int)(2 * ((K + CB - 1) / CB) + 2); }
+
+// y and x are K-vectors; x receives the solution, rhs is left unchanged;
+// sync holds chol_sync_bytes(K) (its error word is set if a wait gave up)
+void chol_solve(vmc_ctx* ctx, const double2* S, int64_t K, const double2* Linv, const double2* rhs, double2* y,
+                double2* x, int* sync) {
   hipStream_t st = ctx->stream;
   const int nblk = (int)((K + CB - 1) / CB);
-  auto nb_of = [&](int b) { return (int)std::min<int64_t>(CB, K - (int64_t)b * CB); };
-  // L y = rhs: y_0 first; launch b updates the rows below block b and forms y_{b+1}
-  k_fwd_first<<<1, 256, 0, st>>>(Linv, rhs, y, nb_of(0));
-  for (int b = 0; b + 1 < nblk; ++b) {
-    const int64_t kb0 = (int64_t)b * CB;
-    const int64_t rows = K - kb0 - CB;
-    k_fwd_update<<<(unsigned)((rows + CB - 1) / CB), 256, 0, st>>>(S, K, kb0, Linv + (size_t)(b + 1) * CB * CB,
-                                                                    nb_of(b + 1), rhs, y);
-  }
-  // L^H x = y (in place in y): x of the last block first; launch b updates the
-  // columns left of block b and forms x_{b-1}
-  const int64_t kl = (int64_t)(nblk - 1) * CB;
-  k_bwd_first<<<1, 256, 0, st>>>(Linv + (size_t)(nblk - 1) * CB * CB, y + kl, x + kl, nb_of(nblk - 1));
-  for (int b = nblk - 1; b >= 1; --b) {
-    const int64_t kb0 = (int64_t)b * CB;
-    k_bwd_update<<<(unsigned)b, 256, 0, st>>>(S, K, kb0, nb_of(b), Linv + (size_t)(b - 1) * CB * CB, y, x);
-  }
+  k_zero_ints<<<1, 256, 0, st>>>(sync, 2 * nblk + 3);
+  k_fwd_chain<<<(unsigned)nblk, 256, 0, st>>>(S, K, nblk, Linv, rhs, y, sync);
+  k_bwd_chain<<<(unsigned)nblk, 256, 0, st>>>(S, K, nblk, Linv, y, x, sync);
   VMC_HIP(hipGetLastError());
 }

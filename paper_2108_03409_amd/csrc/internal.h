@@ -461,7 +461,10 @@ void herk_mfma_f32(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode
 size_t chol_linv_bytes(int64_t K);
 int chol_block();
 void chol_factor(vmc_ctx* ctx, double2* S, int64_t K, double2* Linv, long long* fail, double* pivmin);
-void chol_solve(vmc_ctx* ctx, const double2* S, int64_t K, const double2* Linv, double2* rhs, double2* y, double2* x);
+size_t chol_sync_bytes(int64_t K);
+int chol_sync_err_index(int64_t K);
+void chol_solve(vmc_ctx* ctx, const double2* S, int64_t K, const double2* Linv, const double2* rhs, double2* y,
+                double2* x, int* sync);
 // herk16.hip
 size_t herk16_ws_bytes(int64_t N, int64_t K);
 void herk_split16(vmc_ctx* ctx, const float2* X, int64_t N, int64_t K, int mode, double nu, double eps, double2* S,

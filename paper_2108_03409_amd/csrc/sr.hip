@@ -732,7 +732,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   size_t total = eig_extra + (split16 ? herk16_ws_bytes(Nx, K) : 0) + ws_round(hws) + ws_round(64) + ws_round(sizeof(double2) * npart * K) + ws_round(sizeof(double2) * K) * 7 +
                  ws_round(chol_linv_bytes(K)) +
                  ws_round(xsz) + ws_round(sizeof(double2) * (size_t)K * K) + ws_round(sizeof(double) * nblk) +
-                 ws_round(sizeof(long long)) + ws_round(sizeof(double) * 4);
+                 ws_round(sizeof(long long)) + ws_round(sizeof(double) * 4) + ws_round(chol_sync_bytes(K));
   ws_reserve(ctx, total);
   double* stats = (double*)ws_take(ctx, 64);
   double2* partial = (double2*)ws_take(ctx, sizeof(double2) * npart * K);
@@ -749,6 +749,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   double* pivmin = (double*)ws_take(ctx, sizeof(double) * nblk);
   long long* fail = (long long*)ws_take(ctx, sizeof(long long));
   double* norms = (double*)ws_take(ctx, sizeof(double) * 4);
+  int* tsync = (int*)ws_take(ctx, chol_sync_bytes(K));
   void* h16ws = split16 ? ws_take(ctx, herk16_ws_bytes(Nx, K)) : nullptr;
   void* hws_p = hws ? ws_take(ctx, hws) : nullptr;
   void* eig_ws = eig ? ws_take(ctx, eig_ws_bytes(K)) : nullptr;
@@ -923,8 +924,7 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
 
   ph.reset(new phase_scope(ctx, "sr.trsv"));
   k_rhs<<<grid_for(K, 256), 256, 0, st>>>(F, K, o->gamma_re, o->gamma_im, o->mode, rhs);
-  VMC_HIP(hipMemcpyAsync(res, rhs, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
-  chol_solve(ctx, S, K, Linv, res, yv, sol);
+  chol_solve(ctx, S, K, Linv, rhs, yv, sol, tsync);
   VMC_HIP(hipGetLastError());
   ph.reset();
   ph.reset(new phase_scope(ctx, "sr.resid"));
@@ -935,9 +935,13 @@ void sr_solve_impl(vmc_ctx* ctx, const void* O, int dtype, const double2* eloc, 
   VMC_HIP(hipMemcpyAsync(x, sol, sizeof(double2) * K, hipMemcpyDeviceToDevice, st));
   VMC_HIP(hipGetLastError());
   ph.reset();
-  double* hn = (double*)pinned_host(ctx, sizeof(double) * 2);
+  double* hn = (double*)pinned_host(ctx, sizeof(double) * 3);
   VMC_HIP(hipMemcpyAsync(hn, norms, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+  VMC_HIP(hipMemcpyAsync(hn + 2, tsync + chol_sync_err_index(K), sizeof(int), hipMemcpyDeviceToHost, st));
   VMC_HIP(hipStreamSynchronize(st));
+  int wait_err;
+  std::memcpy(&wait_err, hn + 2, sizeof(int));
+  if (wait_err) throw vmc_error{VMC_ERR_HIP, "triangular solve: a block hand-over exceeded its poll limit"};
   info->residual = hn[1] > 0 ? std::sqrt(hn[0] / hn[1]) : std::sqrt(hn[0]);
 }
 
