@@ -345,8 +345,7 @@ __global__ __launch_bounds__(NT) void k_ar_eloc_tri(const uint64_t* __restrict__
         if (grp == r) p0g = p0s[r];
       if (grp < cm)
         for (int i = p0g + gl; i < N; i += 16) acc += buf[grp * N + i];
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+      acc = row16_sum(acc);
       const double r = grp < cm ? mel * exp(0.5 * acc) : 0.0;
 #pragma unroll
       for (int mm = 0; mm < AR_CM; ++mm) e += lane_bcast(r, 16 * mm);

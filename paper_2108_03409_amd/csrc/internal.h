@@ -386,6 +386,37 @@ __device__ __forceinline__ double2 wave_sum(double2 v) {
   return v;
 }
 
+// Cross-lane sums without an LDS round trip, for reductions on the dependent
+// path of a sequential loop: DPP moves inside each row of 16 lanes, then
+// v_readlane across the four rows.  Every lane of the wavefront must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+// Sum over each row of 16 lanes (lanes 16 r .. 16 r + 15), the same bits in
+// all 16: partner lanes add the same two values, and addition commutes.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]: lane ^ 1
+  v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]: lane ^ 2
+  v += dpp_f64<0x141>(v);  // row_half_mirror: the two quads of each half row
+  v += dpp_f64<0x140>(v);  // row_mirror: the two halves of the row
+  return v;
+}
+// Sum over the wavefront, returned wave-uniform to every lane.
+__device__ __forceinline__ double wave_sum_uniform(double v) {
+  v = row16_sum(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 }  // namespace dev
 
 // -------------------------------------------------- cross-file launchers --

@@ -185,8 +185,7 @@ __global__ __launch_bounds__(64) void k_made_sample(const double* __restrict__ W
       const int k = lane + 64 * q;
       if (k < H) part += w2c[q] * fmax(a[q], 0.0);
     }
-    double l = wave_sum(part);
-    l = __shfl(l, 0, 64) + b2[d];
+    const double l = wave_sum_uniform(part) + b2[d];
     const double p = 1.0 / (1.0 + exp(-l));
     const uint32_t xr = (d & 3) == 0 ? x4.x : (d & 3) == 1 ? x4.y : (d & 3) == 2 ? x4.z : x4.w;
     const bool up = (double)xr * 0x1.0p-32 < p;

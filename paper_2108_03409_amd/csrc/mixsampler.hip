@@ -162,11 +162,7 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
           if (deg_[u] <= d) part += a.W2m[(int64_t)d * H + u] * fmax(as_[cl * Hs + u], 0.0);
         }
       }
-      part += __shfl_xor(part, 8, 16);
-      part += __shfl_xor(part, 4, 16);
-      part += __shfl_xor(part, 2, 16);
-      part += __shfl_xor(part, 1, 16);
-      part = __shfl(part, 0, 16);  // one value per chain: a uniform decision
+      part = row16_sum(part);  // the same value in the chain's 16 lanes: a uniform decision
       const double l = Ls_[cl * MP + i] + part;
       const double e = exp(-fabs(l));  // p = sigmoid(l) and softplus(l) from one exponential
       bool up;

@@ -204,8 +204,7 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
           prod *= nq[q];
         }
       }
-      double L = wave_sum(log(prod));
-      L = __shfl(L, 0, 64);  // one value for the whole wave: a uniform decision
+      const double L = wave_sum_uniform(log(prod));  // one value for the whole wave: a uniform decision
       const double2 al = PF ? alc : a.alpha[m], lc = PF ? lcc : a.LC[m];
       const double r = 2.0 * (-2.0 * sg * al.x + lc.x) + L;
       const bool acc = (r >= 0.0) || (lu < r);
