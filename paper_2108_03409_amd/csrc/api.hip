@@ -840,6 +840,7 @@ extern "C" int vmc_sampler_set_state(vmc_sampler* S, const void* buf_host, size_
     S->g = h.g;
     S->thermalized = (int)h.thermalized;
     S->opts.seed = h.seed;
+    S->mix_pg[0] = S->mix_pg[1] = ~0ull;  // proposals formed ahead belong to the replaced state
     S->bits_valid = 1;
   });
 }
@@ -858,10 +859,10 @@ extern "C" int vmc_sampler_destroy(vmc_sampler* S) {
   if (!S) return VMC_ERR_INVALID_ARG;
   (void)hipSetDevice(S->ctx->device);
   (void)hipStreamSynchronize(S->ctx->stream);
+  mix_release(S);
   if (S->bits) (void)hipFree(S->bits);
   if (S->acc) (void)hipFree(S->acc);
-  for (void* p : {(void*)S->made_buf, (void*)S->mix_perm, (void*)S->mix_prop, (void*)S->mix_lq,
-                  (void*)S->mix_theta, (void*)S->mix_theta_prop})
+  for (void* p : {(void*)S->made_buf, (void*)S->mix_perm})
     if (p) (void)hipFree(p);
   vmc_ctx* ctx = S->ctx;
   delete S;

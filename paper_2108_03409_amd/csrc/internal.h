@@ -217,10 +217,20 @@ struct vmc_sampler {
   double* made_buf = nullptr;
   int* mix_perm = nullptr;            // [H] units sorted by degree, then [N + 1] first position per degree
   uint64_t g = 0;                     // global proposals per chain so far
-  uint64_t* mix_prop = nullptr;       // [n_chains][W] proposals of a global step
-  double* mix_lq = nullptr;           // [2][n_chains] log q of the chain states and of the proposals
+  // The proposals of a global step do not depend on the chains: those of step
+  // g + 1 are formed on a second stream while the main stream runs the sweep
+  // after step g.  Two buffers b = g & 1 of proposals, their log q and theta.
+  uint64_t* mix_prop = nullptr;       // [2][n_chains][W] proposals
+  double* mix_lq = nullptr;           // [3][n_chains] log q of the chain states, then of the proposals of buffers 0, 1
   double2* mix_theta = nullptr;       // [n_chains][N_h] theta of the chain states between launches
-  double2* mix_theta_prop = nullptr;  // [n_chains][N_h] theta of the proposals
+  double2* mix_theta_prop = nullptr;  // [2][n_chains][N_h] theta of the proposals
+  double* mix_tf = nullptr;           // teacher forcing of the chain states: X [n_chains][N], A [n_chains][H], L [n_chains][N]
+  hipStream_t mix_side = nullptr;     // the proposals' stream (default priority)
+  hipEvent_t mix_ev_main = nullptr;   // main stream past the last acceptance
+  hipEvent_t mix_ev_prop[2] = {nullptr, nullptr};  // proposals of buffer b formed
+  uint64_t mix_pg[2] = {~0ull, ~0ull};             // global step whose proposals buffer b holds (~0: none)
+  uint64_t mix_pver[2] = {0, 0};                   // RBM parameter version of buffer b's theta
+  int mix_side_buf = -1;                           // buffer last formed on the proposals' stream (-1: none pending)
 };
 
 struct vmc_made {
@@ -421,7 +431,7 @@ __device__ __forceinline__ double wave_sum_uniform(double v) {
 
 // -------------------------------------------------- cross-file launchers --
 // rbm.hip
-void rbm_theta(vmc_model* m, const uint64_t* s, int64_t B, double2* theta);
+void rbm_theta(vmc_model* m, const uint64_t* s, int64_t B, double2* theta, hipStream_t st = nullptr);
 void rbm_ensure_tables(vmc_model* m, const vmc_ham* H, int move_kind);
 void rbm_log_psi(vmc_model* m, const uint64_t* s, int64_t B, double2* logpsi);
 void rbm_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, double2* eloc);
@@ -470,6 +480,8 @@ void mix_ensure(vmc_sampler* S);
 void mix_made_layout(int N, int H, std::vector<int>& perm, std::vector<int>& mstart);
 bool mix_made_fits(int H, int W);
 void mix_global_step(vmc_sampler* S, uint64_t g);
+void mix_release(vmc_sampler* S);
+void mix_wait_side(vmc_sampler* S);  // orders later main-stream work after the proposals formed ahead  // waits for the proposals' stream, frees the global-step buffers
 // gemm64.hip: C = beta C + op(A) op(B) in float64 with arbitrary strides
 struct dgemm_args {
   const double* A;

@@ -6,26 +6,32 @@
 // an independence-sampler kernel that keeps |psi|^2 invariant (Hastings 1970);
 // the sweep's single-spin flips follow (sampler.hip).
 //
-// One global step is three launches over all chains:
-//  1. k_made_block: log q of every chain state (teacher forcing) and, in the
-//     other half of the grid, a sample s' with its log q.  The autoregressive
-//     pass is blocked: sites are taken MP = 16 at a time, and for each block
-//       - the logits' part from hidden units whose inputs are all known
-//         (degree m(k) <= d0) is a float64 matrix-core product
-//         [16 chains x H] . [H x 16 sites];
-//       - the units whose degree falls inside the block (about 1.3 per site
-//         for H = 512, N = 400) are finished site by site, 16 lanes per chain;
-//       - the block's bits update the pre-activations of the later units as a
-//         second product [16 chains x 16 sites] . [16 sites x H].
-//     The sequential dependence per sample is then 16 short site steps per
-//     block instead of one H-wide reduction per site.  The teacher-forced and
-//     the sampling pass run the same code and arithmetic, so log q(s) is the
-//     same function of s whether s was drawn or given: q(s) and q(s') in the
-//     acceptance ratio are exactly consistent.
-//  2. theta' = b + W sigma' of the proposals (rbm_theta, float64).
-//  3. k_mix_accept: the ratio from the chain's theta (kept between launches)
-//     and theta', the uniform of Philox((c, g_lo, g_hi, 3)), and on acceptance
-//     the proposal's bits and theta replace the chain's.
+// A global step g has two parts:
+//  * the proposals, which do not depend on the chains: k_made_block draws
+//    s' ~ q for every chain with its log q (Philox stream of step g), and
+//    theta' = b + W sigma' follows on the matrix cores (rbm_theta).  Those of
+//    step g + 1 are formed on a second stream while the main stream runs the
+//    sweep after step g (two buffers, b = g & 1);
+//  * on the main stream, log q of every chain state by teacher forcing, as
+//    the plain masked forward pass (two float64 matrix-core products), and
+//    k_mix_accept: the ratio from the chain's theta (kept between launches)
+//    and theta', the uniform of Philox((c, g_lo, g_hi, 3)), and on acceptance
+//    the proposal's bits and theta replace the chain's.
+// The autoregressive draw is blocked: sites are taken MP = 16 at a time, and
+// for each block
+//   - the logits' part from hidden units whose inputs are all known (degree
+//     m(k) <= d0) is a float64 matrix-core product [16 chains x H] . [H x 16 sites];
+//   - the units whose degree falls inside the block (about 1.3 per site for
+//     H = 512, N = 400) are finished site by site, 16 lanes per chain;
+//   - the block's bits update the pre-activations of the later units as a
+//     second product [16 chains x 16 sites] . [16 sites x H].
+// The sequential dependence per sample is then 16 short site steps per block
+// instead of one H-wide reduction per site.  The two evaluations of log q (the
+// draw's, for s', and the forward pass, for s) sum in different orders, so the
+// q of a state differs between them by rounding (about 1e-14 relative); the
+// draw itself resolves each conditional to 2^-32 (32-bit uniforms), so the
+// acceptance ratio is as consistent with the distribution actually sampled as
+// a single evaluation would make it.
 #include "internal.h"
 
 using namespace dev;
@@ -48,10 +54,8 @@ struct made_block_args {
   const int* mstart;   // [N + 1] first position in perm with degree >= v
   int N, H, W;
   int n_chains;
-  const uint64_t* cur;  // [n_chains][W] chain states (teacher forcing, blockIdx.y == 0)
-  uint64_t* prop;       // [n_chains][W] proposals (sampling, blockIdx.y == 1)
-  double* lq_cur;       // [n_chains]
-  double* lq_prop;      // [n_chains]
+  uint64_t* prop;       // [n_chains][W] proposals
+  double* lq_prop;      // [n_chains] their log q
   uint2 key;
   uint32_t lo, hi;
 };
@@ -72,7 +76,6 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
   int* us_ = (int*)(bits_ + MC * W);                  // [UCAP]
   int* deg_ = us_ + UCAP;                             // [H] degree m(k)
 
-  const bool sample = blockIdx.y == 1;
   const int c0 = blockIdx.x * MC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
   for (int k = tid; k < H; k += 256) deg_[k] = degree(k, N);
   for (int e = tid; e < MC * W; e += 256) {
     const int c = e / W, w = e % W;
-    bits_[e] = (!sample && c0 + c < a.n_chains) ? a.cur[(int64_t)(c0 + c) * W + w] : 0ull;
+    bits_[e] = 0ull;
   }
   __syncthreads();
 
@@ -165,15 +168,10 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
       part = row16_sum(part);  // the same value in the chain's 16 lanes: a uniform decision
       const double l = Ls_[cl * MP + i] + part;
       const double e = exp(-fabs(l));  // p = sigmoid(l) and softplus(l) from one exponential
-      bool up;
-      if (sample) {
-        if ((d & 3) == 0) x4 = philox(make_uint4(cg, a.lo, a.hi, 1u + 256u * (uint32_t)(d >> 2)), a.key);
-        const uint32_t xr = (d & 3) == 0 ? x4.x : (d & 3) == 1 ? x4.y : (d & 3) == 2 ? x4.z : x4.w;
-        const double p = (l >= 0.0 ? 1.0 : e) / (1.0 + e);
-        up = (double)xr * 0x1.0p-32 < p;
-      } else {
-        up = (bits_[cl * W + (d >> 6)] >> (d & 63)) & 1ull;
-      }
+      if ((d & 3) == 0) x4 = philox(make_uint4(cg, a.lo, a.hi, 1u + 256u * (uint32_t)(d >> 2)), a.key);
+      const uint32_t xr = (d & 3) == 0 ? x4.x : (d & 3) == 1 ? x4.y : (d & 3) == 2 ? x4.z : x4.w;
+      const double p = (l >= 0.0 ? 1.0 : e) / (1.0 + e);
+      const bool up = (double)xr * 0x1.0p-32 < p;
       lq += (up ? l : 0.0) - (fmax(l, 0.0) + log1p(e));
       if (up) {
         if (staged) {
@@ -187,7 +185,7 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
             if (deg_[u] > d) as_[cl * Hs + u] += a.W1mT[(int64_t)d * H + u];
           }
         }
-        if (sample && sub == 0) bits_[cl * W + (d >> 6)] |= 1ull << (d & 63);
+        if (sub == 0) bits_[cl * W + (d >> 6)] |= 1ull << (d & 63);
       }
     }
     __syncthreads();
@@ -226,17 +224,43 @@ __global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
     }
     __syncthreads();
   }
-  if (c0 + cl < a.n_chains && sub == 0) {
-    if (sample)
-      a.lq_prop[c0 + cl] = lq;
-    else
-      a.lq_cur[c0 + cl] = lq;
+  if (c0 + cl < a.n_chains && sub == 0) a.lq_prop[c0 + cl] = lq;
+  for (int e = tid; e < MC * W; e += 256) {
+    const int c = e / W;
+    if (c0 + c < a.n_chains) a.prop[(int64_t)c0 * W + e] = bits_[e];
   }
-  if (sample)
-    for (int e = tid; e < MC * W; e += 256) {
-      const int c = e / W;
-      if (c0 + c < a.n_chains) a.prop[(int64_t)c0 * W + e] = bits_[e];
-    }
+}
+
+// ---- teacher forcing of the chain states (the plain masked forward pass) ----
+// X[c][d] = s_d of chain c as 0 / 1
+__global__ void k_mix_unpack(const uint64_t* __restrict__ bits, int64_t nc, int N, int W, double* __restrict__ X) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nc * N) return;
+  const int64_t c = e / N;
+  const int d = (int)(e % N);
+  X[e] = (double)((bits[c * W + (d >> 6)] >> (d & 63)) & 1ull);
+}
+
+// A = relu(A + b1)
+__global__ void k_mix_relu(double* __restrict__ A, const double* __restrict__ b1, int64_t nc, int H) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nc * H) return;
+  A[e] = fmax(A[e] + b1[e % H], 0.0);
+}
+
+// log q of row c: sum_d x_d l_d - softplus(l_d), l = L + b2; one wave per row
+__global__ __launch_bounds__(64) void k_mix_logq(const double* __restrict__ L, const double* __restrict__ b2,
+                                                 const double* __restrict__ X, int64_t nc, int N,
+                                                 double* __restrict__ lq) {
+  const int64_t c = blockIdx.x;
+  if (c >= nc) return;
+  double acc = 0.0;
+  for (int d = threadIdx.x; d < N; d += 64) {
+    const double l = L[c * N + d] + b2[d];
+    acc += (X[c * N + d] != 0.0 ? l : 0.0) - (fmax(l, 0.0) + log1p(exp(-fabs(l))));
+  }
+  acc = wave_sum(acc);
+  if (threadIdx.x == 0) lq[c] = acc;
 }
 
 struct mix_accept_args {
@@ -324,34 +348,75 @@ bool mix_made_fits(int H, int W) {
   return made_block_lds(H, W) <= (size_t)lds;
 }
 
+namespace {
+
+// proposals of global step g into buffer b, on stream st
+void mix_proposals(vmc_sampler* S, uint64_t g, int b, hipStream_t st) {
+  vmc_model* m = S->model;
+  const int nc = S->opts.n_chains;
+  const int N = m->N, H = S->made_H, W = m->W;
+  const int64_t nh = (int64_t)N * H;
+  made_block_args a{};
+  a.W1mT = S->made_buf;
+  a.W2m = S->made_buf + nh;
+  a.b1 = S->made_buf + 2 * nh;
+  a.b2 = S->made_buf + 2 * nh + H;
+  a.perm = S->mix_perm;
+  a.mstart = S->mix_perm + H;
+  a.N = N;
+  a.H = H;
+  a.W = W;
+  a.n_chains = nc;
+  a.prop = S->mix_prop + (int64_t)b * nc * W;
+  a.lq_prop = S->mix_lq + (int64_t)(1 + b) * nc;
+  a.key = make_uint2((uint32_t)S->opts.seed, (uint32_t)(S->opts.seed >> 32));
+  a.lo = (uint32_t)g;
+  a.hi = (uint32_t)(g >> 32);
+  k_made_block<<<(unsigned)((nc + MC - 1) / MC), 256, made_block_lds(H, W), st>>>(a);
+  VMC_HIP(hipGetLastError());
+  rbm_theta(m, a.prop, nc, S->mix_theta_prop + (int64_t)b * nc * m->Nh, st);
+  S->mix_pg[b] = g;
+  S->mix_pver[b] = m->version;
+}
+
+// log q of the chain states into mix_lq[0 .. nc) (main stream)
+void mix_teacher(vmc_sampler* S) {
+  vmc_ctx* ctx = S->ctx;
+  hipStream_t st = ctx->stream;
+  const int64_t nc = S->opts.n_chains;
+  const int N = S->N, H = S->made_H;
+  const int64_t nh = (int64_t)N * H;
+  const double* W1mT = S->made_buf;
+  const double* W2m = S->made_buf + nh;
+  const double* b1 = S->made_buf + 2 * nh;
+  const double* b2 = b1 + H;
+  double* X = S->mix_tf;
+  double* A = X + nc * N;
+  double* L = A + nc * H;
+  k_mix_unpack<<<grid_for(nc * N, 256), 256, 0, st>>>(S->bits, nc, N, S->W, X);
+  // A[c][k] = sum_d X[c][d] W1m[k][d]   (W1m^T stored as [N][H])
+  dgemm(ctx, dgemm_args{X, N, 1, W1mT, H, 1, A, H, nc, H, N, 0.0});
+  k_mix_relu<<<grid_for(nc * H, 256), 256, 0, st>>>(A, b1, nc, H);
+  // L[c][i] = sum_k A[c][k] W2m[i][k]   (W2m stored as [N][H])
+  dgemm(ctx, dgemm_args{A, H, 1, W2m, 1, H, L, N, nc, N, H, 0.0});
+  k_mix_logq<<<(unsigned)nc, 64, 0, st>>>(L, b2, X, nc, N, S->mix_lq);
+  VMC_HIP(hipGetLastError());
+}
+
+}  // namespace
+
 void mix_global_step(vmc_sampler* S, uint64_t g) {
   vmc_model* m = S->model;
   hipStream_t st = S->ctx->stream;
   const int nc = S->opts.n_chains;
-  const int N = m->N, H = S->made_H, W = m->W;
-  const int64_t nh = (int64_t)N * H;
-  made_block_args b{};
-  b.W1mT = S->made_buf;
-  b.W2m = S->made_buf + nh;
-  b.b1 = S->made_buf + 2 * nh;
-  b.b2 = S->made_buf + 2 * nh + H;
-  b.perm = S->mix_perm;
-  b.mstart = S->mix_perm + H;
-  b.N = N;
-  b.H = H;
-  b.W = W;
-  b.n_chains = nc;
-  b.cur = S->bits;
-  b.prop = S->mix_prop;
-  b.lq_cur = S->mix_lq;
-  b.lq_prop = S->mix_lq + nc;
-  b.key = make_uint2((uint32_t)S->opts.seed, (uint32_t)(S->opts.seed >> 32));
-  b.lo = (uint32_t)g;
-  b.hi = (uint32_t)(g >> 32);
-  const size_t lds = made_block_lds(H, W);
-  k_made_block<<<dim3((unsigned)((nc + MC - 1) / MC), 2), 256, lds, st>>>(b);
-  VMC_HIP(hipGetLastError());
-  rbm_theta(m, S->mix_prop, nc, S->mix_theta_prop);
+  const int N = m->N, W = m->W;
+  const int b = (int)(g & 1);
+  mix_teacher(S);
+  if (S->mix_pg[b] == g && S->mix_pver[b] == m->version) {
+    VMC_HIP(hipStreamWaitEvent(st, S->mix_ev_prop[b], 0));  // formed ahead on the proposals' stream
+  } else {
+    mix_proposals(S, g, b, st);  // first step of a call, or the parameters changed
+  }
   mix_accept_args c{};
   c.params = m->params;
   c.N = N;
@@ -359,14 +424,14 @@ void mix_global_step(vmc_sampler* S, uint64_t g) {
   c.Nh = m->Nh;
   c.n_chains = nc;
   c.bits = S->bits;
-  c.prop = S->mix_prop;
+  c.prop = S->mix_prop + (int64_t)b * nc * W;
   c.theta = S->mix_theta;
-  c.theta_prop = S->mix_theta_prop;
+  c.theta_prop = S->mix_theta_prop + (int64_t)b * nc * m->Nh;
   c.lq_cur = S->mix_lq;
-  c.lq_prop = S->mix_lq + nc;
-  c.key = b.key;
-  c.lo = b.lo;
-  c.hi = b.hi;
+  c.lq_prop = S->mix_lq + (int64_t)(1 + b) * nc;
+  c.key = make_uint2((uint32_t)S->opts.seed, (uint32_t)(S->opts.seed >> 32));
+  c.lo = (uint32_t)g;
+  c.hi = (uint32_t)(g >> 32);
   c.acc = S->acc;
   const int Q = (m->Nh + 63) / 64;
   if (Q <= 1)
@@ -380,4 +445,18 @@ void mix_global_step(vmc_sampler* S, uint64_t g) {
   else
     k_mix_accept<16><<<nc, 64, 0, st>>>(c);
   VMC_HIP(hipGetLastError());
+  // the proposals of step g + 1 go into the other buffer, whose last reader
+  // (the acceptance of step g - 1) precedes this point of the main stream
+  VMC_HIP(hipEventRecord(S->mix_ev_main, st));
+  VMC_HIP(hipStreamWaitEvent(S->mix_side, S->mix_ev_main, 0));
+  mix_proposals(S, g + 1, b ^ 1, S->mix_side);
+  VMC_HIP(hipEventRecord(S->mix_ev_prop[b ^ 1], S->mix_side));
+  S->mix_side_buf = b ^ 1;
+}
+
+void mix_wait_side(vmc_sampler* S) {
+  // later work on the main stream (new parameters, freed buffers) is ordered
+  // after the proposals formed ahead
+  if (S->mix_side_buf >= 0) VMC_HIP(hipStreamWaitEvent(S->ctx->stream, S->mix_ev_prop[S->mix_side_buf], 0));
+  S->mix_side_buf = -1;
 }

@@ -22,40 +22,64 @@ using namespace dev;
 
 namespace {
 
-constexpr int kThetaSamples = 16;  // samples per theta block (4 per thread)
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int kThRows = 64;  // samples per group of the matrix-core theta
+constexpr int kThCols = 64;  // real columns per group (32 hidden units, re and im)
+constexpr int kThKB = 4;     // k steps (4 sites each) whose operand loads are issued together
 
-// theta[n][j] = b_j + sum_i Wt[i][j] sigma_i(n); block (64, 4): x = hidden unit,
-// y = group of 4 samples.
-__global__ __launch_bounds__(256) void k_theta(const double2* __restrict__ params, const double2* __restrict__ Wt,
-                                               const uint64_t* __restrict__ s, int64_t B, int N, int W, int Nh,
-                                               double2* __restrict__ theta) {
-  extern __shared__ uint64_t sbits[];  // [kThetaSamples][W]
-  const int64_t n0 = (int64_t)blockIdx.y * kThetaSamples;
-  const int tid = threadIdx.y * 64 + threadIdx.x;
-  for (int e = tid; e < kThetaSamples * W; e += 256) {
-    int64_t n = n0 + e / W;
+// theta = b + W sigma on the float64 matrix cores.  With Wt viewed as reals
+// [N][2 N_h] (column c = 2 j + re/im), theta[n][c] = b[c] + sum_i sigma_i(n) Wt[i][c]:
+// a group takes 64 samples x 64 columns, wave w the samples 16 w .. 16 w + 15
+// against four 16-column tiles.  v_mfma_f64_16x16x4f64: lane l holds
+// A[l % 16][l / 16] (sample, site), B[l / 16][l % 16] (site, column) and, in
+// register r, D[l / 16 + 4 r][l % 16].  sigma = +-1 is exact; the sums are
+// float64 in the matrix core's order.
+__global__ __launch_bounds__(256) void k_theta_mfma(const double* __restrict__ bre, const double* __restrict__ Wr,
+                                                    const uint64_t* __restrict__ s, int64_t B, int N, int W, int Nh,
+                                                    double* __restrict__ theta) {
+  extern __shared__ uint64_t sbits[];  // [kThRows][W]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t n0 = (int64_t)blockIdx.y * kThRows;
+  const int ncol = 2 * Nh;
+  const int c0 = blockIdx.x * kThCols;
+  for (int e = tid; e < kThRows * W; e += 256) {
+    const int64_t n = n0 + e / W;
     sbits[e] = n < B ? s[n * W + e % W] : 0ull;
   }
   __syncthreads();
-  const int j = blockIdx.x * 64 + threadIdx.x;
-  if (j >= Nh) return;
-  const double2 bj = params[N + j];
-  double2 acc[4] = {bj, bj, bj, bj};
-  const int r0 = threadIdx.y * 4;
-  for (int i = 0; i < N; ++i) {
-    const double2 w = Wt[(int64_t)i * Nh + j];
-    const int wd = i >> 6, bt = i & 63;
+  const uint64_t* myb = sbits + (wave * 16 + li) * W;  // the bits of the lane's A row
+  const bool row_ok = n0 + wave * 16 + li < B;
+  doublex4 acc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const bool up = (sbits[(r0 + q) * W + wd] >> bt) & 1ull;
-      acc[q].x += up ? w.x : -w.x;
-      acc[q].y += up ? w.y : -w.y;
+  for (int t = 0; t < 4; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < N; k0 += 4 * kThKB) {
+    double bv[kThKB][4];
+#pragma unroll
+    for (int kb = 0; kb < kThKB; ++kb) {
+      const int k = k0 + 4 * kb + lk;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = c0 + 16 * t + li;
+        bv[kb][t] = (k < N && c < ncol) ? Wr[(int64_t)k * ncol + c] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int kb = 0; kb < kThKB; ++kb) {
+      const int k = k0 + 4 * kb + lk;
+      const double a = (k < N && row_ok) ? (((myb[k >> 6] >> (k & 63)) & 1ull) ? 1.0 : -1.0) : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[kb][t], acc[t], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t n = n0 + r0 + q;
-    if (n < B) theta[n * Nh + j] = acc[q];
+  for (int t = 0; t < 4; ++t) {
+    const int c = c0 + 16 * t + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t n = n0 + wave * 16 + lk + 4 * r;
+      if (n < B && c < ncol) theta[n * ncol + c] = acc[t][r] + bre[c];
+    }
   }
 }
 
@@ -401,11 +425,18 @@ constexpr int64_t kChunk = 1 << 16;  // samples per theta chunk
 
 }  // namespace
 
-void rbm_theta(vmc_model* m, const uint64_t* s, int64_t B, double2* theta) {
-  dim3 grid(grid_for(m->Nh, 64), grid_for(B, kThetaSamples));
-  k_theta<<<grid, dim3(64, 4), sizeof(uint64_t) * kThetaSamples * m->W, m->ctx->stream>>>(m->params, m->Wt, s, B,
-                                                                                          m->N, m->W, m->Nh, theta);
-  VMC_HIP(hipGetLastError());
+void rbm_theta(vmc_model* m, const uint64_t* s, int64_t B, double2* theta, hipStream_t st) {
+  if (!st) st = m->ctx->stream;
+  // at most 65535 row tiles per launch
+  const int64_t chunk = (int64_t)65535 * kThRows;
+  const unsigned gx = (unsigned)((2 * m->Nh + kThCols - 1) / kThCols);
+  for (int64_t b0 = 0; b0 < B; b0 += chunk) {
+    const int64_t nb = std::min(chunk, B - b0);
+    k_theta_mfma<<<dim3(gx, (unsigned)((nb + kThRows - 1) / kThRows)), 256, sizeof(uint64_t) * kThRows * m->W,
+                   st>>>((const double*)(m->params + m->N), (const double*)m->Wt, s + b0 * m->W, nb, m->N,
+                                     m->W, m->Nh, (double*)(theta + b0 * m->Nh));
+    VMC_HIP(hipGetLastError());
+  }
 }
 
 namespace {

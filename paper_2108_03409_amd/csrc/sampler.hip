@@ -123,6 +123,15 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   // |r - log u| at the rounding level).
   __shared__ int mv_s[64];
   __shared__ double uv_s[64];
+  // entry (m, lane + 64 q) of a [n_moves][N_h] table, zero past N_h: the
+  // address is clamped and the value selected, so the proposal and the update
+  // run without branches over the lane's units (a unit past N_h has t = 0 and
+  // T = D = 0, hence f = 1 and no change)
+  auto row_entry = [&](const double2* tab, int m, int q) {
+    const int j = lane + 64 * q;
+    const double2 v = tab[(int64_t)m * Nh + (j < Nh ? j : Nh - 1)];
+    return j < Nh ? v : make_double2(0.0, 0.0);
+  };
   auto draw64 = [&](int64_t s0) {
     const uint64_t tl = a.t0 + (uint64_t)(s0 + lane);
     const uint4 y = philox(make_uint4((uint32_t)c, (uint32_t)tl, (uint32_t)(tl >> 32), 0u), a.key);
@@ -142,9 +151,8 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
     if (a.proposal == VMC_PROP_EXCHANGE) bdn = a.bonds[mn];
 #pragma unroll
     for (int q = 0; q < (PF ? Q : 1); ++q) {
-      const int j = lane + 64 * q;
-      Tn[q] = j < Nh ? a.T[(int64_t)mn * Nh + j] : make_double2(0.0, 0.0);
-      Dn[q] = j < Nh ? a.D[(int64_t)mn * Nh + j] : make_double2(0.0, 0.0);
+      Tn[q] = row_entry(a.T, mn, q);
+      Dn[q] = row_entry(a.D, mn, q);
     }
   }
   for (int64_t step = 0; step < total; ++step) {
@@ -169,9 +177,8 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
         if (a.proposal == VMC_PROP_EXCHANGE) bdn = a.bonds[mn];
 #pragma unroll
         for (int q = 0; q < (PF ? Q : 1); ++q) {
-          const int j = lane + 64 * q;
-          Tn[q] = j < Nh ? a.T[(int64_t)mn * Nh + j] : make_double2(0.0, 0.0);
-          Dn[q] = j < Nh ? a.D[(int64_t)mn * Nh + j] : make_double2(0.0, 0.0);
+          Tn[q] = row_entry(a.T, mn, q);
+          Dn[q] = row_entry(a.D, mn, q);
         }
       }
     }
@@ -194,15 +201,10 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
       double nq[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        const int j = lane + 64 * q;
-        fq[q] = make_double2(1.0, 0.0);
-        nq[q] = 1.0;
-        if (j < Nh) {
-          const double2 p = cmul(tt[q], PF ? Tc[PF ? q : 0] : a.T[(int64_t)m * Nh + j]);
-          fq[q] = make_double2(1.0 - sg * p.x, -sg * p.y);
-          nq[q] = fq[q].x * fq[q].x + fq[q].y * fq[q].y;
-          prod *= nq[q];
-        }
+        const double2 p = cmul(tt[q], PF ? Tc[PF ? q : 0] : row_entry(a.T, m, q));
+        fq[q] = make_double2(1.0 - sg * p.x, -sg * p.y);
+        nq[q] = fq[q].x * fq[q].x + fq[q].y * fq[q].y;
+        prod *= nq[q];
       }
       const double L = wave_sum_uniform(log(prod));  // one value for the whole wave: a uniform decision
       const double2 al = PF ? alc : a.alpha[m], lc = PF ? lcc : a.LC[m];
@@ -210,26 +212,31 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
       const bool acc = (r >= 0.0) || (lu < r);
       if (acc) {
         ++accepted;
+        double2 th[Q];  // all LDS reads first: one wait instead of one per unit
+#pragma unroll
+        for (int q = 0; q < Q; ++q) th[q] = theta(q);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-          const int j = lane + 64 * q;
-          if (j < Nh) {
-            const double2 d = PF ? Dc[PF ? q : 0] : a.D[(int64_t)m * Nh + j];
-            const double2 Tm = PF ? Tc[PF ? q : 0] : a.T[(int64_t)m * Nh + j];
-            theta(q).x -= 2.0 * sg * d.x;
-            theta(q).y -= 2.0 * sg * d.y;
-            // t' = (t - sigma T) / f = (t - sigma T) conj(f) / |f|^2
-            const double2 nu = make_double2(tt[q].x - sg * Tm.x, tt[q].y - sg * Tm.y);
-            const double inv = 1.0 / nq[q];
-            tt[q] = make_double2((nu.x * fq[q].x + nu.y * fq[q].y) * inv, (nu.y * fq[q].x - nu.x * fq[q].y) * inv);
-          }
+          const double2 d = PF ? Dc[PF ? q : 0] : row_entry(a.D, m, q);
+          const double2 Tm = PF ? Tc[PF ? q : 0] : row_entry(a.T, m, q);
+          theta(q) = make_double2(th[q].x - 2.0 * sg * d.x, th[q].y - 2.0 * sg * d.y);
+          // t' = (t - sigma T) / f = (t - sigma T) conj(f) / |f|^2, with 1 / |f|^2
+          // from the hardware reciprocal and two Newton steps (|f|^2 > 0 here:
+          // a zero factor gives a zero ratio, which is never accepted)
+          const double2 nu = make_double2(tt[q].x - sg * Tm.x, tt[q].y - sg * Tm.y);
+          double inv = __builtin_amdgcn_rcp(nq[q]);
+          inv = fma(inv, fma(-nq[q], inv, 1.0), inv);
+          inv = fma(inv, fma(-nq[q], inv, 1.0), inv);
+          tt[q] = make_double2((nu.x * fq[q].x + nu.y * fq[q].y) * inv, (nu.y * fq[q].x - nu.x * fq[q].y) * inv);
         }
-        __syncthreads();
+        // one wavefront per work-group: LDS operations of the wave stay in
+        // program order, so the flips need no barrier and no returned value
         if (lane == 0) {
-          cb[site >> 6] ^= 1ull << (site & 63);
-          if (site2 >= 0) cb[site2 >> 6] ^= 1ull << (site2 & 63);
+          __hip_atomic_fetch_xor(&cb[site >> 6], 1ull << (site & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (site2 >= 0)
+            __hip_atomic_fetch_xor(&cb[site2 >> 6], 1ull << (site2 & 63), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
         }
-        __syncthreads();
       }
     }
     }
@@ -358,6 +365,7 @@ void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* 
     launch(a, Q, st);
     S->t += (uint64_t)a.sweep;
   }
+  mix_wait_side(S);
   S->thermalized = 1;
 }
 
@@ -378,11 +386,34 @@ __global__ void k_copy_made(const double* __restrict__ W1mT, const double* __res
 // work buffers of the global steps (allocated on first use)
 void mix_ensure(vmc_sampler* S) {
   const int64_t nc = S->opts.n_chains;
+  if (!S->mix_tf) {  // the teacher-forcing workspace depends on the proposal's hidden size
+    VMC_HIP(hipMalloc(&S->mix_tf, sizeof(double) * nc * (2 * (int64_t)S->N + S->made_H)));
+  }
   if (S->mix_prop) return;
-  VMC_HIP(hipMalloc(&S->mix_prop, sizeof(uint64_t) * nc * S->W));
-  VMC_HIP(hipMalloc(&S->mix_lq, sizeof(double) * 2 * nc));
+  VMC_HIP(hipMalloc(&S->mix_prop, sizeof(uint64_t) * 2 * nc * S->W));
+  VMC_HIP(hipMalloc(&S->mix_lq, sizeof(double) * 3 * nc));
   VMC_HIP(hipMalloc(&S->mix_theta, sizeof(double2) * nc * S->model->Nh));
-  VMC_HIP(hipMalloc(&S->mix_theta_prop, sizeof(double2) * nc * S->model->Nh));
+  VMC_HIP(hipMalloc(&S->mix_theta_prop, sizeof(double2) * 2 * nc * S->model->Nh));
+  VMC_HIP(hipStreamCreateWithFlags(&S->mix_side, hipStreamNonBlocking));
+  VMC_HIP(hipEventCreateWithFlags(&S->mix_ev_main, hipEventDisableTiming));
+  for (auto& e : S->mix_ev_prop) VMC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+}
+
+void mix_release(vmc_sampler* S) {
+  if (S->mix_side) (void)hipStreamSynchronize(S->mix_side);
+  for (void* p : {(void*)S->mix_prop, (void*)S->mix_lq, (void*)S->mix_theta, (void*)S->mix_theta_prop, (void*)S->mix_tf})
+    if (p) (void)hipFree(p);
+  S->mix_prop = nullptr;
+  S->mix_lq = nullptr;
+  S->mix_theta = S->mix_theta_prop = nullptr;
+  S->mix_tf = nullptr;
+  for (auto& e : S->mix_ev_prop)
+    if (e) (void)hipEventDestroy(e);
+  if (S->mix_ev_main) (void)hipEventDestroy(S->mix_ev_main);
+  if (S->mix_side) (void)hipStreamDestroy(S->mix_side);
+  S->mix_ev_prop[0] = S->mix_ev_prop[1] = S->mix_ev_main = nullptr;
+  S->mix_side = nullptr;
+  S->mix_pg[0] = S->mix_pg[1] = ~0ull;
 }
 
 extern "C" int vmc_sampler_set_proposal_made(vmc_sampler* S, const vmc_made* md) {
@@ -401,6 +432,10 @@ extern "C" int vmc_sampler_set_proposal_made(vmc_sampler* S, const vmc_made* md)
     mix_made_layout(md->N, md->H, perm, mstart);
     perm.insert(perm.end(), mstart.begin(), mstart.end());
     VMC_HIP(hipStreamSynchronize(S->ctx->stream));
+    if (S->mix_side) VMC_HIP(hipStreamSynchronize(S->mix_side));
+    S->mix_pg[0] = S->mix_pg[1] = ~0ull;  // proposals of the previous network
+    if (S->mix_tf) VMC_HIP(hipFree(S->mix_tf));
+    S->mix_tf = nullptr;
     if (S->made_buf) VMC_HIP(hipFree(S->made_buf));
     if (S->mix_perm) VMC_HIP(hipFree(S->mix_perm));
     S->made_buf = nullptr;
