@@ -62,7 +62,10 @@ struct made_block_args {
 
 __device__ __forceinline__ int degree(int k, int N) { return k % (N - 1) + 1; }
 
-__global__ __launch_bounds__(256) void k_made_block(made_block_args a) {
+// At most 128 registers per lane (four waves per SIMD): the kernel then fits
+// beside a local-sweep wave of the RBM sampler (up to 376 registers), whose
+// sweep it overlaps on the proposals' stream.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_made_block(made_block_args a) {
   extern __shared__ double smem[];
   const int N = a.N, H = a.H, W = a.W;
   const int Hs = H + 1;
