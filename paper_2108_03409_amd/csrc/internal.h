@@ -426,6 +426,22 @@ __device__ __forceinline__ double wave_sum_uniform(double v) {
   v = row16_sum(v);
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
+// Product over the wavefront, wave-uniform (multiplication commutes as well).
+__device__ __forceinline__ double wave_prod_uniform(double v) {
+  v *= dpp_f64<0xB1>(v);
+  v *= dpp_f64<0x4E>(v);
+  v *= dpp_f64<0x141>(v);
+  v *= dpp_f64<0x140>(v);
+  return (readlane_f64(v, 0) * readlane_f64(v, 16)) * (readlane_f64(v, 32) * readlane_f64(v, 48));
+}
+__device__ __forceinline__ int wave_isum_uniform(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);
+  return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+         (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
+}
 
 }  // namespace dev
 

@@ -206,10 +206,21 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
         nq[q] = fq[q].x * fq[q].x + fq[q].y * fq[q].y;
         prod *= nq[q];
       }
-      const double L = wave_sum_uniform(log(prod));  // one value for the whole wave: a uniform decision
+      // accept iff L = sum_j log |f_j|^2 > lu - c, c = 2 Re(-2 sigma alpha + LC), without a
+      // logarithm on the chain's path: each lane's product as mantissa in [1/2, 1) and
+      // exponent, the wave's product M 2^E (M >= 2^-64, no underflow), and M 2^E > e^(lu - c)
+      // tested as ldexp(M, E - n) > 2^r with (lu - c) / ln 2 = n + r, n integer, r in [0, 1);
+      // n and 2^r do not depend on the ratio and are formed beside it.  Decides as
+      // lu < c + L except within rounding of a tie.
       const double2 al = PF ? alc : a.alpha[m], lc = PF ? lcc : a.LC[m];
-      const double r = 2.0 * (-2.0 * sg * al.x + lc.x) + L;
-      const bool acc = (r >= 0.0) || (lu < r);
+      const double t2 = fmin(fmax((lu - 2.0 * (-2.0 * sg * al.x + lc.x)) * 1.4426950408889634074, -4096.0), 4096.0);
+      const double n2 = floor(t2);
+      const double p2 = exp2(t2 - n2);
+      int ex;
+      const double mt = frexp(prod, &ex);
+      const double M = wave_prod_uniform(mt);
+      const int E = wave_isum_uniform(ex);
+      const bool acc = ldexp(M, E - (int)n2) > p2;  // one value for the whole wave: a uniform decision
       if (acc) {
         ++accepted;
         double2 th[Q];  // all LDS reads first: one wait instead of one per unit
