@@ -461,12 +461,15 @@ int vmc_made_train(vmc_made* md, const uint64_t* s, int64_t B, int epochs, int b
  * life) is the sample of row c with counter g, accepted iff r >= 0 or
  * u < exp(r),  r = 2 Re(log psi(s') - log psi(s)) + log q(s) - log q(s'),
  * u = ((x1 << 21) | (x2 >> 11)) 2^-53 of x = Philox((c, g_lo, g_hi, 3)).
- * Each global step and each flip leaves |psi|^2 invariant.  The sampler's
- * global passes are blocked over 16 sites at a time on the float64 matrix
- * cores (same logits up to rounding order; log q of the chain state and of
- * the proposal come from the same code and are consistent to the bit).  The
- * MADE must fit that pass: 16 (H + 1) + 1280 doubles, 16 W words and H + 32
- * ints of LDS (H <= 1024 with W <= 64 does).                                 */
+ * Each global step and each flip leaves |psi|^2 invariant.  The sampler
+ * draws the proposals (with their log q and theta) blocked over 16 sites at
+ * a time on the float64 matrix cores, one global step ahead, on a second
+ * stream of default priority that it creates and owns; vmc_sample orders
+ * later work on the context's stream after that stream's work.  log q of
+ * the chain states comes from the plain masked forward pass: the same logits
+ * up to rounding order (about 1e-14 relative, below the 2^-32 resolution of
+ * the draws).  The MADE must fit the blocked pass: 16 (H + 1) + 1280
+ * doubles, 16 W words and H + 32 ints of LDS (H <= 1024 with W <= 64 does). */
 int vmc_made_sample(vmc_made* md, int64_t B, uint64_t seed, uint64_t counter, uint64_t* s_out, double* logq);
 int vmc_made_destroy(vmc_made* md);
 
