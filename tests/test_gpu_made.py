@@ -126,6 +126,33 @@ def test_mixed_chain_replay(ctx, N, H, G, sweep):
     assert torch.equal(s2, s3)
 
 
+def test_mixed_chain_replay_after_new_parameters(ctx):
+    # the proposals of the next global step, with their theta, are formed ahead
+    # of the step; new RBM parameters between two calls must not leave a stale
+    # theta behind: the second call replays the oracle's chains under the new
+    # parameters (an SR loop changes them between every two calls)
+    flush("mixed replay across a parameter change")
+    N, Nh, H, G, nc, per = 10, 10, 16, 1, 19, 3
+    model, Ham, made, S, pr, pm = _mixed_setup(ctx, N, Nh, H, 0.15, G, nc, made_scale=0.5)
+    s1, _, _ = S.sample(nc * per)
+    pr2 = si.rbm_params(N, Nh, std=0.4, is_complex=True, seed=21)
+    model.set_params(dev_c128(pr2))
+    s2, lp2, _ = S.sample(nc * per)
+    ch = omet.Chains(lambda b: orbm.log_psi(pr, b, Nh), N, "made_mix", seed=101, chain_ids=np.arange(nc),
+                     therm_sweeps=2, made=(pm, N, H), global_steps=G)
+    o1, _ = ch.sample(per)
+    ch.f = lambda b: orbm.log_psi(pr2, b, Nh)
+    ch.logpsi = ch.f(ch.states)
+    o2, ol2 = ch.sample(per)
+    for o, s in ((o1, s1), (o2, s2)):
+        s = host_bits(s).reshape(per, nc, -1)
+        for c in range(nc):
+            for k in range(per):
+                assert np.array_equal(s[k, c], si.pack_bits(o[k, c])[0]), (k, c)
+    assert_logpsi_close(lp2.cpu().numpy().reshape(per, nc), ol2, rtol=1e-10)
+    assert ch.near_ties == 0
+
+
 def test_mixed_chain_replay_at_learned_proposal_shape(ctx):
     # the learned-proposal workload's shape: 20 x 20 lattice, RBM alpha = 2, a
     # MADE 400 -> 512 -> 400, 4096 chains with two global steps per sweep;
