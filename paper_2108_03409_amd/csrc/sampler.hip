@@ -45,15 +45,28 @@ struct sampler_args {
   int theta_in;             // 1: start from theta_store instead of rebuilding theta from the spins
 };
 
-template <int Q>
-__global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
-  __shared__ uint64_t cb[64];  // chain configuration, W <= 64 words
+// One chain per work-group of NW waves.  With NW = 2 (chains fewer than the
+// device's SIMDs, so that one wave per chain would leave SIMDs idle) wave w
+// takes the hidden units j = 64 Q w + 64 q + lane; both waves keep their own
+// copy of the configuration and of the step tables and reach the same
+// decisions, exchanging only their partial ratio (mantissa and exponent)
+// through LDS behind one barrier per proposal.
+template <int Q, int NW>
+__global__ __launch_bounds__(64 * NW) void k_metropolis(sampler_args a) {
+  __shared__ uint64_t cbs[NW][64];  // chain configuration, W <= 64 words (one copy per wave)
   // theta_j of the chain in lane-private LDS slots [q][lane]: registers hold
   // only t_j = tanh theta_j (theta in registers measured slower)
-  __shared__ double2 ths[Q * 64];
+  __shared__ double2 thss[NW][Q * 64];
+  __shared__ double pm_s[2][NW];  // partial ratios of the waves (double-buffered by step parity)
+  __shared__ int pe_s[2][NW];
+  __shared__ double2 lp_s[NW];
   const int c = blockIdx.x;
   if (c >= a.n_chains) return;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wv = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  uint64_t* cb = cbs[wv];
+  double2* ths = thss[wv];
+  const int jb = 64 * Q * wv;  // first hidden unit of this wave
   const int N = a.N, W = a.W, Nh = a.Nh;
 
   if (a.init) {
@@ -91,7 +104,7 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   auto theta = [&](int q) -> double2& { return ths[q * 64 + lane]; };
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int j = lane + 64 * q;
+    const int j = jb + lane + 64 * q;
     double2 acc = j < Nh ? a.params[N + j] : make_double2(0.0, 0.0);
     if (j < Nh) {
       if (a.theta_in) {
@@ -121,14 +134,16 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
   // a table of moves and log u (the same Philox values as one per step; the
   // test u < exp(r) is taken as log u < r, which decides alike away from
   // |r - log u| at the rounding level).
-  __shared__ int mv_s[64];
-  __shared__ double uv_s[64];
+  __shared__ int mv_ss[NW][64];
+  __shared__ double uv_ss[NW][64];
+  int* mv_s = mv_ss[wv];
+  double* uv_s = uv_ss[wv];
   // entry (m, lane + 64 q) of a [n_moves][N_h] table, zero past N_h: the
   // address is clamped and the value selected, so the proposal and the update
   // run without branches over the lane's units (a unit past N_h has t = 0 and
   // T = D = 0, hence f = 1 and no change)
   auto row_entry = [&](const double2* tab, int m, int q) {
-    const int j = lane + 64 * q;
+    const int j = jb + lane + 64 * q;
     const double2 v = tab[(int64_t)m * Nh + (j < Nh ? j : Nh - 1)];
     return j < Nh ? v : make_double2(0.0, 0.0);
   };
@@ -218,9 +233,26 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
       const double p2 = exp2(t2 - n2);
       int ex;
       const double mt = frexp(prod, &ex);
-      const double M = wave_prod_uniform(mt);
-      const int E = wave_isum_uniform(ex);
-      const bool acc = ldexp(M, E - (int)n2) > p2;  // one value for the whole wave: a uniform decision
+      double M = wave_prod_uniform(mt);
+      int E = wave_isum_uniform(ex);
+      if constexpr (NW > 1) {  // the other waves' units: every wave forms the same product
+        const int par = (int)(step & 1);
+        if (lane == 0) {
+          pm_s[par][wv] = M;
+          pe_s[par][wv] = E;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        M = pm_s[par][0];
+        E = pe_s[par][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+          M *= pm_s[par][w];
+          E += pe_s[par][w];
+        }
+      }
+      const bool acc = ldexp(M, E - (int)n2) > p2;  // one value for the work-group: a uniform decision
       if (acc) {
         ++accepted;
         double2 th[Q];  // all LDS reads first: one wait instead of one per unit
@@ -255,16 +287,18 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
     if (step >= a.therm_steps && ((step - a.therm_steps + 1) % a.sweep) == 0) {
       const int64_t k = (step - a.therm_steps + 1) / a.sweep - 1;
       const int64_t row = k * a.n_chains + c;
-      for (int w = lane; w < W; w += 64) a.s_out[row * W + w] = cb[w];
+      if (wv == 0)
+        for (int w = lane; w < W; w += 64) a.s_out[row * W + w] = cb[w];
       double2 lp = make_double2(0.0, 0.0);
-      for (int i = lane; i < N; i += 64) {
-        const double2 av = a.params[i];
-        const double sgi = ((cb[i >> 6] >> (i & 63)) & 1ull) ? 1.0 : -1.0;
-        lp = cadd(lp, cscale(av, sgi));
-      }
+      if (wv == 0)
+        for (int i = lane; i < N; i += 64) {
+          const double2 av = a.params[i];
+          const double sgi = ((cb[i >> 6] >> (i & 63)) & 1ull) ? 1.0 : -1.0;
+          lp = cadd(lp, cscale(av, sgi));
+        }
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        const int j = lane + 64 * q;
+        const int j = jb + lane + 64 * q;
         if (j < Nh) {
           const double2 thv = theta(q);
           lp = cadd(lp, clogcosh(thv));
@@ -272,17 +306,26 @@ __global__ __launch_bounds__(64) void k_metropolis(sampler_args a) {
         }
       }
       lp = wave_sum(lp);
-      if (lane == 0 && a.logpsi_out) a.logpsi_out[row] = lp;
+      if constexpr (NW > 1) {  // records are rare: plain barriers around the exchange
+        if (lane == 0) lp_s[wv] = lp;
+        __syncthreads();
+        lp = lp_s[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) lp = cadd(lp, lp_s[w]);
+        __syncthreads();
+      }
+      if (wv == 0 && lane == 0 && a.logpsi_out) a.logpsi_out[row] = lp;
     }
   }
-  for (int w = lane; w < W; w += 64) a.bits[(int64_t)c * W + w] = cb[w];
+  if (wv == 0)
+    for (int w = lane; w < W; w += 64) a.bits[(int64_t)c * W + w] = cb[w];
   if (a.theta_store)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const int j = lane + 64 * q;
+      const int j = jb + lane + 64 * q;
       if (j < Nh) a.theta_store[(int64_t)c * Nh + j] = theta(q);
     }
-  if (lane == 0) a.acc[c] += accepted;
+  if (wv == 0 && lane == 0) a.acc[c] += accepted;
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
@@ -290,20 +333,35 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
   if (e < n) p[e] = 0ull;
 }
 
-void launch(const sampler_args& a, int Q, hipStream_t st) {
+template <int NW>
+void launch_nw(const sampler_args& a, int Q, hipStream_t st) {
+  const dim3 blk(64 * NW);
   if (Q <= 1)
-    k_metropolis<1><<<a.n_chains, 64, 0, st>>>(a);
+    k_metropolis<1, NW><<<a.n_chains, blk, 0, st>>>(a);
   else if (Q <= 2)
-    k_metropolis<2><<<a.n_chains, 64, 0, st>>>(a);
+    k_metropolis<2, NW><<<a.n_chains, blk, 0, st>>>(a);
   else if (Q <= 4)
-    k_metropolis<4><<<a.n_chains, 64, 0, st>>>(a);
+    k_metropolis<4, NW><<<a.n_chains, blk, 0, st>>>(a);
   else if (Q <= 8)
-    k_metropolis<8><<<a.n_chains, 64, 0, st>>>(a);
+    k_metropolis<8, NW><<<a.n_chains, blk, 0, st>>>(a);
   else if (Q <= 16)
-    k_metropolis<16><<<a.n_chains, 64, 0, st>>>(a);
+    k_metropolis<16, NW><<<a.n_chains, blk, 0, st>>>(a);
   else
     throw vmc_error{VMC_ERR_UNSUPPORTED, "sampler supports up to 1024 hidden units"};
   VMC_HIP(hipGetLastError());
+}
+
+// Two waves per chain when the chains leave SIMDs idle (at most one chain per
+// SIMD) and each wave keeps more than two slots of 64 hidden units: measured
+// at 1 024 chains, N_h = 400 (exchanges) 1.38 -> 1.24 ms per 8 sweeps, while
+// at N_h = 256 (flips) the barrier per proposal costs more than the halved
+// per-unit work saves (1.27 -> 1.50 ms per 16 sweeps).
+void launch(vmc_ctx* ctx, const sampler_args& a, hipStream_t st) {
+  const bool two = a.n_chains <= 4 * cu_count(ctx) && a.Nh > 256;
+  if (two)
+    launch_nw<2>(a, (a.Nh + 127) / 128, st);
+  else
+    launch_nw<1>(a, (a.Nh + 63) / 64, st);
 }
 
 }  // namespace
@@ -335,7 +393,6 @@ void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* 
   a.key = make_uint2((uint32_t)S->opts.seed, (uint32_t)(S->opts.seed >> 32));
   a.acc = S->acc;
   a.sweep = S->opts.sweep_steps;
-  const int Q = (m->Nh + 63) / 64;
   k_zero_u64<<<grid_for(3 * (int64_t)nc, 256), 256, 0, st>>>(S->acc, 3 * (int64_t)nc);
   if (S->opts.proposal != VMC_PROP_MADE_MIX) {
     a.t0 = S->t;
@@ -344,7 +401,7 @@ void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* 
     a.n_record = n_per_chain;
     a.s_out = s_out;
     a.logpsi_out = logpsi_out;
-    launch(a, Q, st);
+    launch(S->ctx, a, st);
     S->t += (uint64_t)(a.therm_steps + a.n_record * a.sweep);
     S->thermalized = 1;
     S->bits_valid = 1;
@@ -360,7 +417,7 @@ void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* 
   a.theta_in = 0;
   a.therm_steps = 0;
   a.n_record = 0;
-  launch(a, Q, st);  // initial states (first call) and theta, no proposals
+  launch(S->ctx, a, st);  // initial states (first call) and theta, no proposals
   S->bits_valid = 1;
   a.init = 0;
   a.theta_in = 1;
@@ -373,7 +430,7 @@ void sampler_run(vmc_sampler* S, int64_t n_per_chain, uint64_t* s_out, double2* 
     a.n_record = rec ? 1 : 0;
     a.s_out = rec ? s_out + (sw - n_therm) * (int64_t)nc * m->W : nullptr;
     a.logpsi_out = (rec && logpsi_out) ? logpsi_out + (sw - n_therm) * (int64_t)nc : nullptr;
-    launch(a, Q, st);
+    launch(S->ctx, a, st);
     S->t += (uint64_t)a.sweep;
   }
   mix_wait_side(S);

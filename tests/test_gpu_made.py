@@ -126,6 +126,30 @@ def test_mixed_chain_replay(ctx, N, H, G, sweep):
     assert torch.equal(s2, s3)
 
 
+def test_mixed_chain_replay_two_waves_per_chain(ctx):
+    # N_h > 256 with few chains: the local sweeps run two waves per chain, which
+    # hand theta to the global steps and take it back between the launches
+    flush("mixed replay, two waves per chain")
+    N, Nh, H, G, nc, per = 12, 300, 16, 2, 19, 3
+    pr = si.rbm_params(N, Nh, std=0.1, is_complex=True, seed=8)
+    model = V.Model.rbm(ctx, N, Nh, True)
+    model.set_params(dev_c128(pr))
+    Ham = V.Hamiltonian.tfim(ctx, N, 1, True, 1.0, 1.0)
+    made, pm = _made(ctx, N, H, 0.5, seed=9)
+    S = V.Sampler(ctx, model, Ham, proposal=V.PROP_MADE_MIX, n_chains=nc, therm_sweeps=2, global_steps=G, seed=101)
+    S.set_proposal_made(made)
+    s, lp, _ = S.sample(nc * per)
+    s = host_bits(s).reshape(per, nc, -1)
+    ch = omet.Chains(lambda b: orbm.log_psi(pr, b, Nh), N, "made_mix", seed=101, chain_ids=np.arange(nc),
+                     therm_sweeps=2, made=(pm, N, H), global_steps=G)
+    os_, ol = ch.sample(per)
+    for c in range(nc):
+        for k in range(per):
+            assert np.array_equal(s[k, c], si.pack_bits(os_[k, c])[0]), (k, c)
+    assert_logpsi_close(lp.cpu().numpy().reshape(per, nc), ol, rtol=1e-10)
+    assert 0 < ch.acc_global < ch.n_global and ch.near_ties == 0
+
+
 def test_mixed_chain_replay_after_new_parameters(ctx):
     # the proposals of the next global step, with their theta, are formed ahead
     # of the step; new RBM parameters between two calls must not leave a stale

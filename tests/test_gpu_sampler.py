@@ -38,6 +38,9 @@ def _setup(ctx, kind, Lx, Ly, Nh, std, cplx, seed):
     ("tfim", 10, 1, 10, 0.5, True, 16, 32, list(range(16))),
     ("heisenberg", 10, 10, 400, 0.01, True, 1024, 2, [0, 1, 517, 1023]),
     ("tfim", 64, 1, 256, 0.05, True, 1024, 2, [0, 3, 999]),
+    # N_h > 256 with at most one chain per SIMD: two waves per chain; 300 units
+    # leave the second wave's last slot partly empty
+    ("tfim", 12, 1, 300, 0.1, True, 16, 8, list(range(16))),
 ])
 def test_replay_matches_oracle(ctx, kind, Lx, Ly, Nh, std, cplx, n_chains, per_chain, ids):
     flush(f"replay {kind} {Lx}x{Ly} chains={n_chains}")
