@@ -224,7 +224,7 @@ struct vmc_sampler {
   double* mix_lq = nullptr;           // [3][n_chains] log q of the chain states, then of the proposals of buffers 0, 1
   double2* mix_theta = nullptr;       // [n_chains][N_h] theta of the chain states between launches
   double2* mix_theta_prop = nullptr;  // [2][n_chains][N_h] theta of the proposals
-  double* mix_tf = nullptr;           // teacher forcing of the chain states: X [n_chains][N], A [n_chains][H], L [n_chains][N]
+  double* mix_tf = nullptr;           // teacher forcing of the chain states: A [n_chains][H], L [n_chains][N]
   hipStream_t mix_side = nullptr;     // the proposals' stream (default priority)
   hipEvent_t mix_ev_main = nullptr;   // main stream past the last acceptance
   hipEvent_t mix_ev_prop[2] = {nullptr, nullptr};  // proposals of buffer b formed

@@ -235,32 +235,70 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 }
 
 // ---- teacher forcing of the chain states (the plain masked forward pass) ----
-// X[c][d] = s_d of chain c as 0 / 1
-__global__ void k_mix_unpack(const uint64_t* __restrict__ bits, int64_t nc, int N, int W, double* __restrict__ X) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= nc * N) return;
-  const int64_t c = e / N;
-  const int d = (int)(e % N);
-  X[e] = (double)((bits[c * W + (d >> 6)] >> (d & 63)) & 1ull);
+// A[c][k] = relu(b1[k] + sum_d s_d(c) W1m[k][d]) on the float64 matrix cores,
+// the inputs 0 / 1 taken from the bits in LDS: 64 chains x 64 units per group,
+// wave w the chains 16 w .. 16 w + 15 against four 16-unit tiles
+// (v_mfma_f64_16x16x4f64: lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and,
+// in register r, D[l / 16 + 4 r][l % 16]).
+constexpr int TF_KB = 4;  // k steps (4 sites each) whose operand loads are issued together
+__global__ __launch_bounds__(256) void k_mix_hidden(const uint64_t* __restrict__ bits, int64_t nc, int N, int W,
+                                                    int H, const double* __restrict__ W1mT,
+                                                    const double* __restrict__ b1, double* __restrict__ A) {
+  extern __shared__ uint64_t sbits[];  // [64][W]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t c0 = (int64_t)blockIdx.y * 64;
+  const int k0c = blockIdx.x * 64;
+  for (int e = tid; e < 64 * W; e += 256) {
+    const int64_t c = c0 + e / W;
+    sbits[e] = c < nc ? bits[c * W + e % W] : 0ull;
+  }
+  __syncthreads();
+  const uint64_t* myb = sbits + (wave * 16 + li) * W;
+  doublex4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+  for (int d0 = 0; d0 < N; d0 += 4 * TF_KB) {
+    double bv[TF_KB][4];
+#pragma unroll
+    for (int kb = 0; kb < TF_KB; ++kb) {
+      const int d = d0 + 4 * kb + lk;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = k0c + 16 * t + li;
+        bv[kb][t] = (d < N && k < H) ? W1mT[(int64_t)d * H + k] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int kb = 0; kb < TF_KB; ++kb) {
+      const int d = d0 + 4 * kb + lk;
+      const double x = d < N ? (double)((myb[d >> 6] >> (d & 63)) & 1ull) : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, bv[kb][t], acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int k = k0c + 16 * t + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t c = c0 + wave * 16 + lk + 4 * r;
+      if (c < nc && k < H) A[c * H + k] = fmax(acc[t][r] + b1[k], 0.0);
+    }
+  }
 }
 
-// A = relu(A + b1)
-__global__ void k_mix_relu(double* __restrict__ A, const double* __restrict__ b1, int64_t nc, int H) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= nc * H) return;
-  A[e] = fmax(A[e] + b1[e % H], 0.0);
-}
-
-// log q of row c: sum_d x_d l_d - softplus(l_d), l = L + b2; one wave per row
+// log q of chain c: sum_d s_d l_d - softplus(l_d), l = L + b2; one wave per chain
 __global__ __launch_bounds__(64) void k_mix_logq(const double* __restrict__ L, const double* __restrict__ b2,
-                                                 const double* __restrict__ X, int64_t nc, int N,
+                                                 const uint64_t* __restrict__ bits, int64_t nc, int N, int W,
                                                  double* __restrict__ lq) {
   const int64_t c = blockIdx.x;
   if (c >= nc) return;
+  const uint64_t* sc = bits + c * W;
   double acc = 0.0;
   for (int d = threadIdx.x; d < N; d += 64) {
     const double l = L[c * N + d] + b2[d];
-    acc += (X[c * N + d] != 0.0 ? l : 0.0) - (fmax(l, 0.0) + log1p(exp(-fabs(l))));
+    acc += (get_bit(sc, d) ? l : 0.0) - (fmax(l, 0.0) + log1p(exp(-fabs(l))));
   }
   acc = wave_sum(acc);
   if (threadIdx.x == 0) lq[c] = acc;
@@ -393,16 +431,15 @@ void mix_teacher(vmc_sampler* S) {
   const double* W2m = S->made_buf + nh;
   const double* b1 = S->made_buf + 2 * nh;
   const double* b2 = b1 + H;
-  double* X = S->mix_tf;
-  double* A = X + nc * N;
+  VMC_REQUIRE((nc + 63) / 64 <= 65535, "too many chains for the teacher-forcing grid");
+  double* A = S->mix_tf;
   double* L = A + nc * H;
-  k_mix_unpack<<<grid_for(nc * N, 256), 256, 0, st>>>(S->bits, nc, N, S->W, X);
-  // A[c][k] = sum_d X[c][d] W1m[k][d]   (W1m^T stored as [N][H])
-  dgemm(ctx, dgemm_args{X, N, 1, W1mT, H, 1, A, H, nc, H, N, 0.0});
-  k_mix_relu<<<grid_for(nc * H, 256), 256, 0, st>>>(A, b1, nc, H);
+  // A = relu(b1 + s W1m^T), with W1m^T stored as [N][H]
+  k_mix_hidden<<<dim3((unsigned)((H + 63) / 64), (unsigned)((nc + 63) / 64)), 256, sizeof(uint64_t) * 64 * S->W, st>>>(
+      S->bits, nc, N, S->W, H, W1mT, b1, A);
   // L[c][i] = sum_k A[c][k] W2m[i][k]   (W2m stored as [N][H])
   dgemm(ctx, dgemm_args{A, H, 1, W2m, 1, H, L, N, nc, N, H, 0.0});
-  k_mix_logq<<<(unsigned)nc, 64, 0, st>>>(L, b2, X, nc, N, S->mix_lq);
+  k_mix_logq<<<(unsigned)nc, 64, 0, st>>>(L, b2, S->bits, nc, N, S->W, S->mix_lq);
   VMC_HIP(hipGetLastError());
 }
 

@@ -455,7 +455,7 @@ __global__ void k_copy_made(const double* __restrict__ W1mT, const double* __res
 void mix_ensure(vmc_sampler* S) {
   const int64_t nc = S->opts.n_chains;
   if (!S->mix_tf) {  // the teacher-forcing workspace depends on the proposal's hidden size
-    VMC_HIP(hipMalloc(&S->mix_tf, sizeof(double) * nc * (2 * (int64_t)S->N + S->made_H)));
+    VMC_HIP(hipMalloc(&S->mix_tf, sizeof(double) * nc * ((int64_t)S->N + S->made_H)));
   }
   if (S->mix_prop) return;
   VMC_HIP(hipMalloc(&S->mix_prop, sizeof(uint64_t) * 2 * nc * S->W));
