@@ -3,7 +3,9 @@
 //   A(m, k) = A[m * sam + k * sak],  B(k, n) = B[k * sbk + n * sbn].
 // 64 x 64 output tile per 256-thread group (2 x 2 waves of 32 x 32, each
 // 2 x 2 blocks of v_mfma_f64_16x16x4), the reduction staged 16 deep through
-// LDS.  Loads are coalesced along whichever stride of each operand is 1.
+// two LDS buffers: the next stage's global loads are issued into registers
+// before the current stage is used.  Loads are coalesced along whichever
+// stride of each operand is 1.
 // Split-K (nsplit > 1): grid z reduces over its own range of k and writes its
 // own C slice (C + z cz); the caller adds the slices.
 #include <hip/hip_runtime.h>
@@ -15,8 +17,8 @@ namespace {
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_dgemm(dgemm_args g) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
+  __shared__ double As[2][16][65];
+  __shared__ double Bs[2][16][65];
   const int64_t m0 = (int64_t)blockIdx.y * 64, n0 = (int64_t)blockIdx.x * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -31,46 +33,55 @@ __global__ __launch_bounds__(256) void k_dgemm(dgemm_args g) {
   const int64_t kz0 = (int64_t)blockIdx.z * g.kchunk;
   const int64_t kz1 = g.kchunk ? min(g.K, kz0 + g.kchunk) : g.K;
   double* const Cz = g.C + (int64_t)blockIdx.z * g.cz;
-  for (int64_t k0 = kz0; k0 < kz1; k0 += 16) {
+  // the stage at k0: element q = tid + 256 j of the 64 x 16 A and 16 x 64 B tiles
+  // (along whichever stride of the operand is 1), read into registers; the next
+  // stage's loads are in flight while the current one is used from LDS
+  double ra[4], rb[4];
+  auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int q = tid + 256 * j;
-      int mm, kk;
-      if (a_k_fast) {
-        mm = q >> 4;
-        kk = q & 15;
-      } else {
-        mm = q & 63;
-        kk = q >> 6;
-      }
+      const int mm = a_k_fast ? q >> 4 : q & 63, kk = a_k_fast ? q & 15 : q >> 6;
       const int64_t m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < g.M && k < kz1) ? g.A[m * g.sam + k * g.sak] : 0.0;
-      int nn, kb;
-      if (b_n_fast) {
-        nn = q & 63;
-        kb = q >> 6;
-      } else {
-        nn = q >> 4;
-        kb = q & 15;
-      }
+      ra[j] = (m < g.M && k < kz1) ? g.A[m * g.sam + k * g.sak] : 0.0;
+      const int nn = b_n_fast ? q & 63 : q >> 4, kb = b_n_fast ? q >> 6 : q & 15;
       const int64_t n = n0 + nn, kq = k0 + kb;
-      Bs[kb][nn] = (n < g.N && kq < kz1) ? g.B[kq * g.sbk + n * g.sbn] : 0.0;
+      rb[j] = (n < g.N && kq < kz1) ? g.B[kq * g.sbk + n * g.sbn] : 0.0;
     }
-    __syncthreads();
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = tid + 256 * j;
+      As[buf][a_k_fast ? q & 15 : q >> 6][a_k_fast ? q >> 4 : q & 63] = ra[j];
+      Bs[buf][b_n_fast ? q >> 6 : q & 15][b_n_fast ? q & 63 : q >> 4] = rb[j];
+    }
+  };
+  if (kz0 < kz1) {
+    gload(kz0);
+    sstore(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kz0; k0 < kz1; k0 += 16) {
+    const bool more = k0 + 16 < kz1;
+    if (more) gload(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int kk = ks * 4 + lk;
       double fa[2], fb[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) fa[i] = As[kk][wr * 32 + i * 16 + li];
+      for (int i = 0; i < 2; ++i) fa[i] = As[buf][kk][wr * 32 + i * 16 + li];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) fb[j] = Bs[kk][wc * 32 + j * 16 + li];
+      for (int j = 0; j < 2; ++j) fb[j] = Bs[buf][kk][wc * 32 + j * 16 + li];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
+    if (more) sstore(buf ^ 1);  // the other buffer: its last readers passed the previous barrier
     __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
