@@ -535,8 +535,12 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
             }
             re -= ii;
           } else {
+            // three real products per complex term (Gauss): P = sum Ar Br, Q = sum Ai Bi,
+            // R = sum (Ar + Ai)(Br + Bi); Re dZ = P - Q, Im dZ = R - P - Q (the rounding
+            // bound of Im at most doubles)
             const T* b_re = wre + cb * 16 + li;
             const T* b_im = wim + cb * 16 + li;
+            floatx4 pp = {0.f, 0.f, 0.f, 0.f}, qq = pp, rr = pp;
             for (int ti = 0; ti < nt; ++ti) {
               const unsigned v = op[ti];
               const int ao = (int)(v >> 16), bo = (int)(v & 0xffffu);
@@ -545,12 +549,13 @@ __global__ __launch_bounds__(NT) void k_cnn_eloc_lp(lp_geom g, const float2* __r
                 const int ci = c4 + lk;
                 const float ar = a_re[ao + ci], ai = a_im[ao + ci];
                 const float br = b_re[bo + ci * g.Cn], bi = b_im[bo + ci * g.Cn];
-                re = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, re, 0, 0, 0);
-                re = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, bi, re, 0, 0, 0);
-                im = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bi, im, 0, 0, 0);
-                im = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, br, im, 0, 0, 0);
+                pp = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, br, pp, 0, 0, 0);
+                qq = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bi, qq, 0, 0, 0);
+                rr = __builtin_amdgcn_mfma_f32_16x16x4f32(ar + ai, br + bi, rr, 0, 0, 0);
               }
             }
+            re = pp - qq;
+            im = rr - pp - qq;
           }
           // the lane holds dZ of flips rb*16 + 4 lk + r, channel cb*16 + li; position
           // f - e on the torus: f - (ey Lx + ex), plus N if fy < ey, plus Lx if fx < ex

@@ -148,7 +148,7 @@ def _windows(N, Lx, Ly, k, size):
     return m
 
 
-def _cnn_eloc_bound(p, sb, Lx, Ly, C, k, h, u, cf):
+def _cnn_eloc_bound(p, sb, Lx, Ly, C, k, h, u, cf, g3=1):
     W1, b1, W2, b2 = ocnn.split(p, C, k)
     N = Lx * Ly
     flips = np.repeat(sb[None], N, axis=0)
@@ -168,7 +168,9 @@ def _cnn_eloc_bound(p, sb, Lx, Ly, C, k, h, u, cf):
     e_z2 = _corr((1 + u) * e_a1 + (u + C * k * k * E) * np.abs(a1), aW2, k) + 8 * E * np.abs(b2)[None, :, None, None]
     t2 = np.abs(np.tanh(z2))
     e_t2 = (1 + t2 ** 2) * e_z2 + 8 * E * t2
-    e_dZ = _corr((1 + u) * e_dA + (u + C * k * k * E) * dA, aW2, k)
+    # g3 = 2: the window products take three real products per complex term, whose
+    # accumulated rounding in Im is at most twice the four-product bound
+    e_dZ = _corr((1 + u) * e_dA + (u + g3 * C * k * k * E) * dA, aW2, k)
     fac = np.abs(np.cosh(z2p) / np.cosh(z2))
     term = np.abs(np.tanh(z2p)) * e_dZ + np.abs(np.sinh(z2p - z2)) / fac * e_t2 + cf * E
     delta = np.sum(term * _windows(N, Lx, Ly, k, 2 * k - 1)[:, None], axis=(1, 2, 3))
@@ -190,12 +192,12 @@ def test_cnn_local_energy_precision(ctx, Lx, Ly, C, k, std, B):
     s = dev_bits(si.pack_bits(bits))
     f = lambda b: ocnn.log_psi(p, b, Lx, Ly, C, k)
     ref = oeloc.local_energy(f, "tfim", bits, Lx, Ly, True, 1.0, 3.0)
-    for prec, u, cf in [(V.VMC_F32, 0.0, 16), (V.VMC_BF16, 2.0 ** -9, 64)]:
+    for prec, u, cf, g3 in [(V.VMC_F32, 0.0, 16, 2), (V.VMC_BF16, 2.0 ** -9, 64, 1)]:
         m.set_precision(prec)
         got = m.local_energy(H, s).cpu().numpy()
         errs = []
         for n, sb in enumerate(bits):
-            bnd = _cnn_eloc_bound(p, sb, Lx, Ly, C, k, 3.0, u, cf)
+            bnd = _cnn_eloc_bound(p, sb, Lx, Ly, C, k, 3.0, u, cf, g3)
             errs.append((abs(got[n] - ref[n]), bnd))
             assert abs(got[n] - ref[n]) <= bnd + 1e-12, (prec, n, abs(got[n] - ref[n]), bnd)
         rel = max(e / abs(r) for (e, _), r in zip(errs, ref))
