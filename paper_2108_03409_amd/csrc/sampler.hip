@@ -1,8 +1,9 @@
 // Metropolis sampler (Sec. 2.1 and Sec. 4.2 "Sampler"): all chains advance in
-// sync, one wavefront per chain, the chain's hidden units spread over the 64
-// lanes (theta_j and t_j = tanh theta_j live in registers).  A proposal costs
-// N_h/64 complex multiply-adds per lane plus one wave reduction, using the
-// move identity of rbm.hip:
+// sync, one wavefront per chain (two when the chains leave SIMDs idle), the
+// chain's hidden units spread over the lanes (t_j = tanh theta_j in registers,
+// theta_j in lane-private LDS slots).  A proposal costs N_h/64 complex
+// multiply-adds per lane plus one wave reduction, using the move identity of
+// rbm.hip:
 //   2 Re(log psi(s') - log psi(s)) = 2 Re(-2 sigma_m alpha_m + LC_m)
 //                                    + sum_j log|1 - sigma_m t_j T_jm|^2.
 // On acceptance theta_j -= 2 sigma_m D_jm and t_j follows the tanh addition
@@ -10,9 +11,10 @@
 // at the start of every call and t from theta at every recorded sample.
 //
 // VMC_PROP_MADE_MIX: each sweep starts with global Metropolis-Hastings steps
-// made by all chains together (mixsampler.hip); the sweep's single-spin flips
-// then run here, one launch per sweep, with each chain's theta kept in device
-// memory between the launches.
+// made by all chains together (mixsampler.hip; the proposals of the next step
+// are formed on a second stream during the sweep); the sweep's single-spin
+// flips then run here, one launch per sweep, with each chain's theta kept in
+// device memory between the launches.
 #include "internal.h"
 
 using namespace dev;
@@ -132,8 +134,8 @@ __global__ __launch_bounds__(64 * NW) void k_metropolis(sampler_args a) {
   constexpr bool PF = Q <= 8;
   // The counters of 64 consecutive steps are drawn together, one per lane, into
   // a table of moves and log u (the same Philox values as one per step; the
-  // test u < exp(r) is taken as log u < r, which decides alike away from
-  // |r - log u| at the rounding level).
+  // test u < exp(r) is decided from log u, below, alike away from |r - log u|
+  // at the rounding level).
   __shared__ int mv_ss[NW][64];
   __shared__ double uv_ss[NW][64];
   int* mv_s = mv_ss[wv];
