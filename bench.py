@@ -205,9 +205,12 @@ def eloc_result(V, torch, workload, prec, steps, warmup):
     get_samples = lambda: sampler.sample(ns)[0]
     set_prec(V, model, prec)
 
+    last = {}
+
     def step():
         s = get_samples()
         model.local_energy(H, s, out=el)
+        last["s"] = s
 
     for _ in range(warmup):
         step()
@@ -231,6 +234,17 @@ def eloc_result(V, torch, workload, prec, steps, warmup):
         "eloc_kernel_per_s": round(ns / (eloc_ms * 1e-3), 1),
         "mean_energy": float(el.real.mean().item()),
     }
+    if prec != "f64":
+        # the error of this precision against the float64 path (itself pinned to
+        # the oracle at 1e-10) on the first 4 096 samples of the last step
+        nref = min(ns, 4096)
+        set_prec(V, model, "f64")
+        ref = model.local_energy(H, last["s"][:nref])
+        set_prec(V, model, prec)
+        got = el[:nref]
+        rel = ((got - ref).abs() / ref.abs().clamp_min(1e-300)).max().item()
+        out["error_vs_f64"] = {"samples": nref, "max_rel_eloc": float(rel),
+                               "rel_mean_energy": float(abs((got.mean() - ref.mean()) / ref.mean()).item())}
     achieved = ns * work / (eloc_ms * 1e-3) / 1e12
     effective = None
     if cfg["net"] == "cnn" and prec == "f32":
@@ -633,6 +647,8 @@ def other_workloads(V, torch):
         r = eloc_result(V, torch, wl, prec, steps, warm)
         res[name] = {"local_energies_per_s": r["value"], "eloc_kernel_per_s": r["eloc_kernel_per_s"],
                      "ms_per_step": r["ms_per_step"], "phases_ms": r["phases_ms"], "roofline": r["roofline"]}
+        if "error_vs_f64" in r:
+            res[name]["error_vs_f64"] = r["error_vs_f64"]
         torch.cuda.empty_cache()
     m = made_result(V, torch, "tfim2d_20x20_rbm_a2_made", 1, 64, 100, 1e-3)
     res["tfim2d_20x20_rbm_a2_made"] = {

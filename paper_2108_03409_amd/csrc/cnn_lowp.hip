@@ -171,10 +171,13 @@ __device__ __forceinline__ void fctanh_logcosh_pv(float2 z, float2& t, float2& a
 // factor allows 16 x 2^-24).
 template <int PREC>
 __device__ __forceinline__ float2 window_factor(float2 dz, float2 tz) {
-  float sb, cb;
   const float ea = __expf(dz.x);
   const float y = PREC == VMC_F32 ? fmaf(-TWO_PI_F, rintf(dz.y * 0.159154943091895336f), dz.y) : dz.y;
-  __sincosf(y, &sb, &cb);
+  // cos y as 1 - 2 sin^2(y / 2): near y = 0, where the window changes lie, the
+  // hardware cosine's error is a fraction of an ulp of 1 with a consistent
+  // sign, which the product over a window's factors accumulates
+  const float sb = __sinf(y), sh2 = __sinf(0.5f * y);
+  const float cb = fmaf(-2.f * sh2, sh2, 1.f);
   const float ia = __builtin_amdgcn_rcpf(ea);
   const float ch = 0.5f * (ea + ia), sh = 0.5f * (ea - ia);
   const float2 cz = make_float2(ch * cb, sh * sb), sz = make_float2(sh * cb, ch * sb);
