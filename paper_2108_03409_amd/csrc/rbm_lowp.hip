@@ -118,9 +118,10 @@ __global__ __launch_bounds__(64) void k_logpsi_lowp(const float2* __restrict__ a
   if (lane == 0) logpsi[n] = acc;
 }
 
+// T [Nhp][n_moves], the rows past N_h (up to Nhp, a multiple of 16) zero
 __global__ __launch_bounds__(64) void k_tables_lowp(const float2* __restrict__ Wt32, const float2* __restrict__ ab32,
                                                     const int2* __restrict__ bonds, int move_kind, int n_moves, int N,
-                                                    int Nh, float2* __restrict__ T, float2* __restrict__ LC,
+                                                    int Nh, int Nhp, float2* __restrict__ T, float2* __restrict__ LC,
                                                     float2* __restrict__ alpha) {
   const int m = blockIdx.x;
   if (m >= n_moves) return;
@@ -145,6 +146,7 @@ __global__ __launch_bounds__(64) void k_tables_lowp(const float2* __restrict__ W
     lc.x += l.x;
     lc.y += l.y;
   }
+  for (int j = Nh + lane; j < Nhp; j += 64) T[(int64_t)j * n_moves + m] = make_float2(0.f, 0.f);
   lc = wave_sum(lc);
   if (lane == 0) {
     LC[m] = make_float2((float)lc.x, (float)lc.y);
@@ -157,16 +159,22 @@ __global__ __launch_bounds__(64) void k_eloc_lowp(const float2* __restrict__ the
                                                   int64_t B, int N, int W, int Nh, int ham_kind, double J, double h,
                                                   const int2* __restrict__ bonds, int n_bonds,
                                                   const float2* __restrict__ T, const float2* __restrict__ LC,
-                                                  const float2* __restrict__ alpha, int n_moves,
+                                                  const float2* __restrict__ alpha, int n_moves, int Nhp,
                                                   double2* __restrict__ eloc) {
+  // sigma t_j for both spins: tpm[0][j] = -t_j, tpm[1][j] = t_j, zero past N_h
+  // (up to Nhp, a multiple of 16, where the table rows are zero as well)
   extern __shared__ float2 lds32[];
-  float2* t = lds32;                   // [Nh]
-  int* moves = (int*)(lds32 + Nh);     // [n_moves]
+  float2* tpm = lds32;                   // [2][Nhp]
+  int* moves = (int*)(lds32 + 2 * Nhp);  // [n_moves]
   const int64_t n = blockIdx.x;
   if (n >= B) return;
   const int lane = threadIdx.x;
   const uint64_t* sn = s + n * W;
-  for (int j = lane; j < Nh; j += 64) t[j] = fctanh(theta[n * Nh + j]);
+  for (int j = lane; j < Nhp; j += 64) {
+    const float2 tj = j < Nh ? fctanh(theta[n * Nh + j]) : make_float2(0.f, 0.f);
+    tpm[j] = make_float2(-tj.x, -tj.y);
+    tpm[Nhp + j] = tj;
+  }
   int n_al = 0;
   for (int b = lane; b < n_bonds; b += 64) n_al += get_bit(sn, bonds[b].x) == get_bit(sn, bonds[b].y);
 #pragma unroll
@@ -201,20 +209,22 @@ __global__ __launch_bounds__(64) void k_eloc_lowp(const float2* __restrict__ the
     if (q < n_slots) {
       const int m = moves[q];
       const int site = ham_kind == HAM_TFIM ? m : bonds[m].x;
-      const float sg = get_bit(sn, site) ? 1.f : -1.f;
+      const int up = get_bit(sn, site);
+      const float sg = up ? 1.f : -1.f;
+      const float2* st = tpm + (up ? Nhp : 0);  // sigma t of this slot's spin
+      const float2* Tm = T + m;                 // column m; rows n_moves apart (fewer than 2^31 entries)
       float2 P = make_float2(1.f, 0.f);
       int e2 = 0;
-      for (int j0 = 0; j0 < Nh; j0 += 16) {
-        const int j1 = min(Nh, j0 + 16);
-        for (int jb = j0; jb < j1; jb += 8) {
+      for (int j0 = 0; j0 < Nhp; j0 += 16) {
+#pragma unroll
+        for (int jb = j0; jb < j0 + 16; jb += 8) {
           float2 Tv[8];  // eight table loads in flight before their products
 #pragma unroll
-          for (int u = 0; u < 8; ++u) Tv[u] = jb + u < j1 ? T[(int64_t)(jb + u) * n_moves + m] : make_float2(0.f, 0.f);
+          for (int u = 0; u < 8; ++u) Tv[u] = Tm[(jb + u) * n_moves];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            if (jb + u >= j1) break;
-            const float2 tt = fcmul(t[jb + u], Tv[u]);
-            P = fcmul(P, make_float2(1.f - sg * tt.x, -sg * tt.y));
+            const float2 tt = fcmul(st[jb + u], Tv[u]);  // sigma t_j T_jm
+            P = fcmul(P, make_float2(1.f - tt.x, -tt.y));
           }
         }
         int e;
@@ -237,6 +247,8 @@ __global__ __launch_bounds__(64) void k_eloc_lowp(const float2* __restrict__ the
 }
 
 constexpr int64_t kChunk = 1 << 16;
+
+int nh_pad(int Nh) { return (Nh + 15) / 16 * 16; }
 
 void ensure_params(vmc_model* m) {
   if (m->Wt32 && m->lowp_version == m->version && m->lowp_prec == m->prec) return;
@@ -303,7 +315,7 @@ void rbm_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t 
     if (tb.LC) VMC_HIP(hipFree(tb.LC));
     if (tb.alpha) VMC_HIP(hipFree(tb.alpha));
     tb.T = tb.LC = tb.alpha = nullptr;
-    VMC_HIP(hipMalloc(&tb.T, sizeof(float2) * (size_t)m->Nh * std::max(1, n_moves)));
+    VMC_HIP(hipMalloc(&tb.T, sizeof(float2) * (size_t)nh_pad(m->Nh) * std::max(1, n_moves)));
     VMC_HIP(hipMalloc(&tb.LC, sizeof(float2) * std::max(1, n_moves)));
     VMC_HIP(hipMalloc(&tb.alpha, sizeof(float2) * std::max(1, n_moves)));
     tb.version = 0;
@@ -311,7 +323,7 @@ void rbm_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t 
   if (tb.version != m->version || tb.prec != m->prec || tb.n_moves != n_moves || (move_kind == 1 && tb.ham_uid != H->uid)) {
     if (n_moves > 0)
       k_tables_lowp<<<n_moves, 64, 0, ctx->stream>>>(m->Wt32, m->ab32, H->bonds, move_kind, n_moves, m->N, m->Nh,
-                                                     tb.T, tb.LC, tb.alpha);
+                                                     nh_pad(m->Nh), tb.T, tb.LC, tb.alpha);
     VMC_HIP(hipGetLastError());
     tb.version = m->version;
     tb.prec = m->prec;
@@ -321,13 +333,15 @@ void rbm_lowp_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t 
   const int64_t chunk = std::min<int64_t>(B, kChunk);
   ws_reserve(ctx, ws_round(sizeof(float2) * chunk * m->Nh));
   float2* th = (float2*)ws_take(ctx, sizeof(float2) * chunk * m->Nh);
-  const size_t lds = sizeof(float2) * m->Nh + sizeof(int) * std::max(1, n_moves);
+  const int Nhp = nh_pad(m->Nh);
+  const size_t lds = sizeof(float2) * 2 * Nhp + sizeof(int) * std::max(1, n_moves);
   VMC_REQUIRE(lds <= 64 * 1024, "model too large for the local-energy kernel's LDS budget");
+  VMC_REQUIRE((int64_t)Nhp * std::max(1, n_moves) < ((int64_t)1 << 31), "move table too large");
   for (int64_t b0 = 0; b0 < B; b0 += chunk) {
     const int64_t nb = std::min(chunk, B - b0);
     theta_lowp(m, s + b0 * m->W, nb, th);
     k_eloc_lowp<<<(unsigned)nb, 64, lds, ctx->stream>>>(th, s + b0 * m->W, nb, m->N, m->W, m->Nh, H->kind, H->J,
-                                                       H->h, H->bonds, H->n_bonds, tb.T, tb.LC, tb.alpha, n_moves,
+                                                       H->h, H->bonds, H->n_bonds, tb.T, tb.LC, tb.alpha, n_moves, Nhp,
                                                        eloc + b0);
     VMC_HIP(hipGetLastError());
   }
