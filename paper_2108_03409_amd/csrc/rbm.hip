@@ -23,6 +23,8 @@ using namespace dev;
 namespace {
 
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+int nh_pad16(int Nh) { return (Nh + 15) / 16 * 16; }
 constexpr int kThRows = 64;  // samples per group of the matrix-core theta
 constexpr int kThCols = 64;  // real columns per group (32 hidden units, re and im)
 constexpr int kThKB = 4;     // k steps (4 sites each) whose operand loads are issued together
@@ -103,8 +105,9 @@ __global__ __launch_bounds__(64) void k_logpsi(const double2* __restrict__ param
 }
 
 // Move tables: one wave per move m.
+// T and D [N_h][n_moves]; T holds zero rows past N_h up to Nhp (a multiple of 16)
 __global__ __launch_bounds__(64) void k_tables(const double2* __restrict__ params, const int2* __restrict__ bonds,
-                                               int move_kind, int n_moves, int N, int Nh, double2* __restrict__ T,
+                                               int move_kind, int n_moves, int N, int Nh, int Nhp, double2* __restrict__ T,
                                                double2* __restrict__ D, double2* __restrict__ LC,
                                                double2* __restrict__ alpha) {
   const int m = blockIdx.x;
@@ -127,6 +130,7 @@ __global__ __launch_bounds__(64) void k_tables(const double2* __restrict__ param
     T[(int64_t)j * n_moves + m] = ctanh(d2);
     lc = cadd(lc, clogcosh(d2));
   }
+  for (int j = Nh + lane; j < Nhp; j += 64) T[(int64_t)j * n_moves + m] = make_double2(0.0, 0.0);
   lc = wave_sum(lc);
   if (lane == 0) {
     LC[m] = lc;
@@ -255,17 +259,23 @@ __global__ __launch_bounds__(64) void k_eloc_compact(const double2* __restrict__
                                              int64_t B, int N, int W, int Nh, int ham_kind, double J, double h,
                                              const int2* __restrict__ bonds, int n_bonds,
                                              const double2* __restrict__ T, const double2* __restrict__ LC,
-                                             const double2* __restrict__ alpha, int n_moves,
+                                             const double2* __restrict__ alpha, int n_moves, int Nhp,
                                              double2* __restrict__ eloc) {
+  // sigma t_j for both spins: tpm[0][j] = -t_j, tpm[1][j] = t_j, zero past N_h up
+  // to Nhp (a multiple of 16, where the table rows are zero as well)
   extern __shared__ double2 lds[];
-  double2* t = lds;                              // [Nh]
-  int* moves = (int*)(lds + Nh);                 // [n_moves]
+  double2* tpm = lds;                            // [2][Nhp]
+  int* moves = (int*)(lds + 2 * Nhp);            // [n_moves]
   const int64_t n = blockIdx.x;
   if (n >= B) return;
   const int lane = threadIdx.x;
   const uint64_t* sn = s + n * W;
 
-  for (int j = lane; j < Nh; j += 64) t[j] = ctanh(theta[n * Nh + j]);
+  for (int j = lane; j < Nhp; j += 64) {
+    const double2 tj = j < Nh ? ctanh(theta[n * Nh + j]) : make_double2(0.0, 0.0);
+    tpm[j] = make_double2(-tj.x, -tj.y);
+    tpm[Nhp + j] = tj;
+  }
 
   // diagonal element: coupling * (n_aligned - n_anti), exact integer count
   int n_al = 0;
@@ -312,22 +322,22 @@ __global__ __launch_bounds__(64) void k_eloc_compact(const double2* __restrict__
     if (q < n_slots) {
       const int m = moves[q];
       const int site = ham_kind == HAM_TFIM ? m : bonds[m].x;
-      const double sg = get_bit(sn, site) ? 1.0 : -1.0;
+      const int up = get_bit(sn, site);
+      const double sg = up ? 1.0 : -1.0;
+      const double2* st = tpm + (up ? Nhp : 0);  // sigma t of this slot's spin
       double2 P = make_double2(1.0, 0.0);
       int e2 = 0;
-      const double2* Tm = T + m;
-      for (int j0 = 0; j0 < Nh; j0 += 32) {
-        const int j1 = min(Nh, j0 + 32);
-        for (int jb = j0; jb < j1; jb += 8) {
+      const double2* Tm = T + m;  // column m; rows n_moves apart (fewer than 2^31 entries)
+      for (int j0 = 0; j0 < Nhp; j0 += 16) {
+#pragma unroll
+        for (int jb = j0; jb < j0 + 16; jb += 8) {
           double2 Tv[8];  // eight table loads in flight before their products
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
-            Tv[u] = jb + u < j1 ? Tm[(int64_t)(jb + u) * n_moves] : make_double2(0.0, 0.0);
+          for (int u = 0; u < 8; ++u) Tv[u] = Tm[(jb + u) * n_moves];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            if (jb + u >= j1) break;
-            const double2 tt = cmul(t[jb + u], Tv[u]);
-            P = cmul(P, make_double2(1.0 - sg * tt.x, -sg * tt.y));
+            const double2 tt = cmul(st[jb + u], Tv[u]);  // sigma t_j T_jm
+            P = cmul(P, make_double2(1.0 - tt.x, -tt.y));
           }
         }
         // keep |P| near 1: exact power-of-two rescaling
@@ -465,7 +475,7 @@ void rbm_ensure_tables(vmc_model* m, const vmc_ham* H, int move_kind) {
     if (tb.Dt) VMC_HIP(hipFree(tb.Dt));
     tb.T = tb.D = tb.LC = tb.alpha = tb.Tt = tb.Dt = nullptr;
     size_t tsz = sizeof(double2) * (size_t)m->Nh * std::max(1, n_moves);
-    VMC_HIP(hipMalloc(&tb.T, tsz));
+    VMC_HIP(hipMalloc(&tb.T, sizeof(double2) * (size_t)nh_pad16(m->Nh) * std::max(1, n_moves)));
     VMC_HIP(hipMalloc(&tb.D, tsz));
     VMC_HIP(hipMalloc(&tb.Tt, tsz));
     VMC_HIP(hipMalloc(&tb.Dt, tsz));
@@ -476,8 +486,8 @@ void rbm_ensure_tables(vmc_model* m, const vmc_ham* H, int move_kind) {
   tb.n_moves = n_moves;
   tb.ham_uid = H->uid;
   if (n_moves > 0) {
-    k_tables<<<n_moves, 64, 0, m->ctx->stream>>>(m->params, H->bonds, move_kind, n_moves, m->N, m->Nh, tb.T, tb.D,
-                                                 tb.LC, tb.alpha);
+    k_tables<<<n_moves, 64, 0, m->ctx->stream>>>(m->params, H->bonds, move_kind, n_moves, m->N, m->Nh,
+                                                 nh_pad16(m->Nh), tb.T, tb.D, tb.LC, tb.alpha);
     const int64_t n = (int64_t)m->Nh * n_moves;
     k_transpose2<<<grid_for(n, 256), 256, 0, m->ctx->stream>>>(tb.T, tb.D, m->Nh, n_moves, tb.Tt, tb.Dt);
     VMC_HIP(hipGetLastError());
@@ -511,15 +521,17 @@ void rbm_local_energy(vmc_model* m, vmc_ham* H, const uint64_t* s, int64_t B, do
   // sample per wavefront over its compacted list of anti-aligned bonds
   const int S = m->Nh <= 1024 ? 4 : 2;
   const size_t lds = sizeof(double2) * (size_t)S * m->Nh;
-  const size_t lds1 = sizeof(double2) * m->Nh + sizeof(int) * std::max(1, tb.n_moves);
-  VMC_REQUIRE(lds1 <= 64 * 1024, "model too large for the local-energy kernel's LDS budget");
+  const int Nhp = nh_pad16(m->Nh);
+  const size_t lds1 = sizeof(double2) * 2 * Nhp + sizeof(int) * std::max(1, tb.n_moves);
+  VMC_REQUIRE((move_kind == 1 ? lds1 : lds) <= 64 * 1024, "model too large for the local-energy kernel's LDS budget");
+  VMC_REQUIRE((int64_t)Nhp * std::max(1, tb.n_moves) < ((int64_t)1 << 31), "move table too large");
   for (int64_t b0 = 0; b0 < B; b0 += chunk) {
     const int64_t nb = std::min(chunk, B - b0);
     rbm_theta(m, s + b0 * m->W, nb, theta);
     if (move_kind == 1) {
       k_eloc_compact<<<(unsigned)nb, 64, lds1, ctx->stream>>>(theta, s + b0 * m->W, nb, m->N, m->W, m->Nh, H->kind,
                                                               H->J, H->h, H->bonds, H->n_bonds, tb.T, tb.LC, tb.alpha,
-                                                              tb.n_moves, eloc + b0);
+                                                              tb.n_moves, Nhp, eloc + b0);
       VMC_HIP(hipGetLastError());
       continue;
     }
