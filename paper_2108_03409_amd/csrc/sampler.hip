@@ -52,9 +52,11 @@ struct sampler_args {
 // takes the hidden units j = 64 Q w + 64 q + lane; both waves keep their own
 // copy of the configuration and of the step tables and reach the same
 // decisions, exchanging only their partial ratio (mantissa and exponent)
-// through LDS behind one barrier per proposal.
+// through LDS behind one barrier per proposal.  Up to four slots of hidden
+// units the kernel is held to 256 registers, so that two waves share a SIMD
+// (1 024 chains of two waves fill 2 048 wave slots on 1 024 SIMDs).
 template <int Q, int NW>
-__global__ __launch_bounds__(64 * NW) void k_metropolis(sampler_args a) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(Q <= 4 ? 2 : 1))) void k_metropolis(sampler_args a) {
   __shared__ uint64_t cbs[NW][64];  // chain configuration, W <= 64 words (one copy per wave)
   // theta_j of the chain in lane-private LDS slots [q][lane]: registers hold
   // only t_j = tanh theta_j (theta in registers measured slower)
@@ -158,33 +160,33 @@ __global__ __launch_bounds__(64 * NW) void k_metropolis(sampler_args a) {
     __syncthreads();
   };
   draw64(0);
-  double2 Tn[PF ? Q : 1], Dn[PF ? Q : 1];
-  double2 aln = make_double2(0.0, 0.0), lcn = aln;  // alpha and LC of that move
-  int2 bdn = make_int2(0, 0);                       // its bond (exchange moves)
+  // Two sets of prefetch registers, A and B, alternate between the current
+  // step's rows and the next step's (the loop runs two steps per trip), so
+  // that no step copies its prefetched rows from one set to the other.
+  constexpr int QP = PF ? Q : 1;
+  double2 TA[QP], DA[QP], TB[QP], DB[QP];
+  double2 alA = make_double2(0.0, 0.0), lcA = alA;  // alpha and LC of the move
+  int2 bdA = make_int2(0, 0);                       // its bond (exchange moves)
+  double2 alB = alA, lcB = alA;
+  int2 bdB = bdA;
   if (PF) {
     const int mn = mv_s[0];
-    aln = a.alpha[mn];
-    lcn = a.LC[mn];
-    if (a.proposal == VMC_PROP_EXCHANGE) bdn = a.bonds[mn];
+    alA = a.alpha[mn];
+    lcA = a.LC[mn];
+    if (a.proposal == VMC_PROP_EXCHANGE) bdA = a.bonds[mn];
 #pragma unroll
-    for (int q = 0; q < (PF ? Q : 1); ++q) {
-      Tn[q] = row_entry(a.T, mn, q);
-      Dn[q] = row_entry(a.D, mn, q);
+    for (int q = 0; q < QP; ++q) {
+      TA[q] = row_entry(a.T, mn, q);
+      DA[q] = row_entry(a.D, mn, q);
     }
   }
-  for (int64_t step = 0; step < total; ++step) {
+  // one proposal: the current move's prefetched rows in (Tc, Dc, alc, lcc,
+  // bdc), the next move's loaded into (Tn, Dn, aln, lcn, bdn)
+  auto one_step = [&](const int64_t step, const double2 (&Tc)[QP], const double2 (&Dc)[QP], const double2 alc,
+                      const double2 lcc, const int2 bdc, double2 (&Tn)[QP], double2 (&Dn)[QP], double2& aln,
+                      double2& lcn, int2& bdn) __attribute__((always_inline)) {
     const int m = mv_s[step & 63];
     const double lu = uv_s[step & 63];
-    double2 Tc[PF ? Q : 1], Dc[PF ? Q : 1];
-    const double2 alc = aln, lcc = lcn;
-    const int2 bdc = bdn;
-    if (PF) {
-#pragma unroll
-      for (int q = 0; q < (PF ? Q : 1); ++q) {
-        Tc[q] = Tn[q];
-        Dc[q] = Dn[q];
-      }
-    }
     if (step + 1 < total) {
       if (((step + 1) & 63) == 0) draw64(step + 1);
       if (PF) {
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(64 * NW) void k_metropolis(sampler_args a) {
         lcn = a.LC[mn];
         if (a.proposal == VMC_PROP_EXCHANGE) bdn = a.bonds[mn];
 #pragma unroll
-        for (int q = 0; q < (PF ? Q : 1); ++q) {
+        for (int q = 0; q < QP; ++q) {
           Tn[q] = row_entry(a.T, mn, q);
           Dn[q] = row_entry(a.D, mn, q);
         }
@@ -318,6 +320,14 @@ __global__ __launch_bounds__(64 * NW) void k_metropolis(sampler_args a) {
       }
       if (wv == 0 && lane == 0 && a.logpsi_out) a.logpsi_out[row] = lp;
     }
+  };
+  if constexpr (PF) {
+    for (int64_t step = 0; step < total; step += 2) {
+      one_step(step, TA, DA, alA, lcA, bdA, TB, DB, alB, lcB, bdB);
+      if (step + 1 < total) one_step(step + 1, TB, DB, alB, lcB, bdB, TA, DA, alA, lcA, bdA);
+    }
+  } else {
+    for (int64_t step = 0; step < total; ++step) one_step(step, TA, DA, alA, lcA, bdA, TB, DB, alB, lcB, bdB);
   }
   if (wv == 0)
     for (int w = lane; w < W; w += 64) a.bits[(int64_t)c * W + w] = cb[w];
