@@ -180,11 +180,23 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(Q <= 4 
       DA[q] = row_entry(a.D, mn, q);
     }
   }
-  // one proposal: the current move's prefetched rows in (Tc, Dc, alc, lcc,
-  // bdc), the next move's loaded into (Tn, Dn, aln, lcn, bdn)
-  auto one_step = [&](const int64_t step, const double2 (&Tc)[QP], const double2 (&Dc)[QP], const double2 alc,
-                      const double2 lcc, const int2 bdc, double2 (&Tn)[QP], double2 (&Dn)[QP], double2& aln,
-                      double2& lcn, int2& bdn) __attribute__((always_inline)) {
+  constexpr int NSTEP = PF ? 2 : 1;  // proposals per trip of the loop (one without prefetch)
+  for (int64_t s0 = 0; s0 < total; s0 += NSTEP) {
+#pragma unroll
+  for (int h = 0; h < NSTEP; ++h) {
+    const int64_t step = s0 + h;
+    if (h > 0 && step >= total) break;
+    // the current move's prefetched rows in (Tc, Dc, alc, lcc, bdc), the
+    // next move's loaded into (Tn, Dn, aln, lcn, bdn)
+    const double2(&Tc)[QP] = h ? TB : TA;
+    const double2(&Dc)[QP] = h ? DB : DA;
+    const double2 alc = h ? alB : alA, lcc = h ? lcB : lcA;
+    const int2 bdc = h ? bdB : bdA;
+    double2(&Tn)[QP] = h ? TA : TB;
+    double2(&Dn)[QP] = h ? DA : DB;
+    double2& aln = h ? alA : alB;
+    double2& lcn = h ? lcA : lcB;
+    int2& bdn = h ? bdA : bdB;
     const int m = mv_s[step & 63];
     const double lu = uv_s[step & 63];
     if (step + 1 < total) {
@@ -320,14 +332,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(Q <= 4 
       }
       if (wv == 0 && lane == 0 && a.logpsi_out) a.logpsi_out[row] = lp;
     }
-  };
-  if constexpr (PF) {
-    for (int64_t step = 0; step < total; step += 2) {
-      one_step(step, TA, DA, alA, lcA, bdA, TB, DB, alB, lcB, bdB);
-      if (step + 1 < total) one_step(step + 1, TB, DB, alB, lcB, bdB, TA, DA, alA, lcA, bdA);
-    }
-  } else {
-    for (int64_t step = 0; step < total; ++step) one_step(step, TA, DA, alA, lcA, bdA, TB, DB, alB, lcB, bdB);
+  }
   }
   if (wv == 0)
     for (int w = lane; w < W; w += 64) a.bits[(int64_t)c * W + w] = cb[w];
